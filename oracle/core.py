@@ -1,0 +1,215 @@
+"""ctypes front end of the C oracle (csrc/oracle.c) — test infrastructure only.
+
+Every function takes plain numpy arrays and returns numpy arrays over the
+pattern S = {(i, j) : (L + D + L^T)_ij != 0} in S's CSR layout (both
+triangles, sorted columns), in the factor ordering.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "csrc", "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ORC_ERRORS = {1: "pattern", 2: "singular D block", 3: "allocation"}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc, single-threaded, -O2, no fast-math."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        lib.orc_pattern.argtypes = [i32, _P, _P, _P, _P, _P, ctypes.POINTER(i64)]
+        lib.orc_selinv.argtypes = [i32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        lib.orc_linv.argtypes = [i32, _P, _P, _P, i32, f64, i64, _P, _P, _P, ctypes.POINTER(i64)]
+        lib.orc_ninv_product.argtypes = [i32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        lib.orc_mix.argtypes = [i32, _P, _P, _P, _P, f64, _P]
+        lib.orc_mix.restype = None
+        lib.orc_spai.argtypes = [i32, _P, _P, _P, _P, _P, _P, i32, _P]
+        lib.orc_lowrank.argtypes = [i32, i32, _P, _P, _P, _P, _P, _P]
+        lib.orc_lowrank.restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data
+
+
+def _check(rc):
+    if rc != 0:
+        raise ValueError(f"oracle error: {ORC_ERRORS.get(rc, rc)}")
+
+
+@dataclass
+class Pattern:
+    """S in CSR form (both triangles)."""
+    n: int
+    rowptr: np.ndarray  # int64 [n+1]
+    col: np.ndarray     # int32 [nnzS]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def rows(self) -> np.ndarray:
+        return np.repeat(np.arange(self.n, dtype=np.int64), np.diff(self.rowptr))
+
+    def diag_positions(self) -> np.ndarray:
+        r = self.rows()
+        return np.nonzero(r == self.col)[0]
+
+    def to_csr(self, vals) -> sp.csr_matrix:
+        return sp.csr_matrix((np.asarray(vals, dtype=np.float64), self.col, self.rowptr),
+                             shape=(self.n, self.n))
+
+    def gather(self, M) -> np.ndarray:
+        """Values of a (dense or sparse) matrix at the positions of S."""
+        if sp.issparse(M):
+            M = sp.csr_matrix(M)
+            return np.asarray(M[self.rows(), self.col]).ravel()
+        return np.asarray(M)[self.rows(), self.col]
+
+
+def _f(F, name):
+    return np.ascontiguousarray(getattr(F, name))
+
+
+def pattern(F) -> Pattern:
+    """S = pattern(L + D + L^T) with the 2x2 union rule (Section 1)."""
+    lib = _load()
+    n = F.n
+    Lp, Li, piv = _f(F, "L_rowptr"), _f(F, "L_col"), _f(F, "piv")
+    rowptr = np.zeros(n + 1, np.int64)
+    nnz = ctypes.c_int64()
+    _check(lib.orc_pattern(n, _p(Lp), _p(Li), _p(piv), _p(rowptr), None, ctypes.byref(nnz)))
+    col = np.zeros(max(1, nnz.value), np.int32)
+    _check(lib.orc_pattern(n, _p(Lp), _p(Li), _p(piv), _p(rowptr), _p(col), ctypes.byref(nnz)))
+    return Pattern(n, rowptr, col[:nnz.value])
+
+
+def selinv(F, S: Pattern) -> np.ndarray:
+    """Takahashi/SelInv recursion on S (Section 2.1)."""
+    lib = _load()
+    Z = np.zeros(max(1, S.nnz))
+    _check(lib.orc_selinv(F.n, _p(_f(F, "L_rowptr")), _p(_f(F, "L_col")), _p(_f(F, "L_val")),
+                          _p(_f(F, "d_diag")), _p(_f(F, "d_sub")), _p(_f(F, "piv")),
+                          _p(S.rowptr), _p(S.col), _p(Z)))
+    return Z[:S.nnz]
+
+
+def linv(F, p: int, delta: float):
+    """Columns of the truncated, delta-sparsified Neumann series of L^-1 (Section 2.2).
+
+    Returns CSC arrays (colptr int64, rows int32, vals float64), rows sorted.
+    """
+    lib = _load()
+    n = F.n
+    need = ctypes.c_int64()
+    args = (n, _p(_f(F, "L_rowptr")), _p(_f(F, "L_col")), _p(_f(F, "L_val")), int(p), float(delta))
+    _check(lib.orc_linv(*args, 0, None, None, None, ctypes.byref(need)))
+    cap = max(1, need.value)
+    Vp = np.zeros(n + 1, np.int64)
+    Vi = np.zeros(cap, np.int32)
+    Vx = np.zeros(cap)
+    _check(lib.orc_linv(*args, cap, _p(Vp), _p(Vi), _p(Vx), ctypes.byref(need)))
+    return Vp, Vi[:need.value], Vx[:need.value]
+
+
+def ninv(F, S: Pattern, p: int, delta: float, linv_cols=None) -> np.ndarray:
+    """NInv on S: (L^inv)^T D^-1 L^inv evaluated at the positions of S (Section 2.2)."""
+    lib = _load()
+    Vp, Vi, Vx = linv(F, p, delta) if linv_cols is None else linv_cols
+    N = np.zeros(max(1, S.nnz))
+    Vi = np.ascontiguousarray(Vi) if len(Vi) else np.zeros(1, np.int32)
+    Vx = np.ascontiguousarray(Vx) if len(Vx) else np.zeros(1)
+    _check(lib.orc_ninv_product(F.n, _p(Vp), _p(Vi), _p(Vx), _p(_f(F, "d_diag")),
+                                _p(_f(F, "d_sub")), _p(_f(F, "piv")), _p(S.rowptr), _p(S.col),
+                                _p(N)))
+    return N[:S.nnz]
+
+
+def mix(S: Pattern, Z: np.ndarray, N: np.ndarray, eps: float) -> np.ndarray:
+    """Mix (Section 2.3): Z where |Z_ij| > eps sqrt(|Z_ii Z_jj|), else N."""
+    lib = _load()
+    M = np.zeros(max(1, S.nnz))
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    N = np.ascontiguousarray(N, dtype=np.float64)
+    lib.orc_mix(S.n, _p(S.rowptr), _p(S.col), _p(Z), _p(N), float(eps), _p(M))
+    return M[:S.nnz]
+
+
+def spai(Ahat, S: Pattern, M: np.ndarray, iters: int) -> np.ndarray:
+    """Mix-SPAI (Section 2.4): per-column CG refinement on S, then (X + X^T)/2.
+
+    ``Ahat`` = P^T A P in the factor ordering (both triangles).
+    """
+    lib = _load()
+    Ahat = sp.csr_matrix(Ahat)
+    Ahat.sort_indices()
+    Ap = np.ascontiguousarray(Ahat.indptr, dtype=np.int64)
+    Aj = np.ascontiguousarray(Ahat.indices, dtype=np.int32)
+    Ax = np.ascontiguousarray(Ahat.data, dtype=np.float64)
+    R = np.zeros(max(1, S.nnz))
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    _check(lib.orc_spai(S.n, _p(Ap), _p(Aj), _p(Ax), _p(S.rowptr), _p(S.col), _p(M), int(iters),
+                        _p(R)))
+    return R[:S.nnz]
+
+
+def lowrank(S: Pattern, V: np.ndarray, lam: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Rank-k correction on S (Section 2.5): X_ij + sum_m lam_m V_im V_jm."""
+    lib = _load()
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    out = np.zeros(max(1, S.nnz))
+    lib.orc_lowrank(S.n, V.shape[1], _p(V), _p(lam), _p(S.rowptr), _p(S.col), _p(X), _p(out))
+    return out[:S.nnz]
+
+
+def diag(S: Pattern, X: np.ndarray) -> np.ndarray:
+    return np.asarray(X)[S.diag_positions()]
+
+
+def err1(d: np.ndarray, dhat: np.ndarray) -> float:
+    """Relative diagonal 1-norm error ||d - dhat||_1 / ||d||_1 (Section 2.6)."""
+    return float(np.abs(d - dhat).sum() / np.abs(d).sum())
+
+
+def entry_error(S: Pattern, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """Per-entry error |x_ij - y_ij| / sqrt(|y_ii y_jj|) on S (Y is the reference)."""
+    dy = diag(S, Y)
+    r = S.rows()
+    return np.abs(np.asarray(X) - np.asarray(Y)) / np.sqrt(np.abs(dy[r] * dy[S.col]))
+
+
+def permuted(A, perm) -> sp.csr_matrix:
+    """P^T A P = A[perm][:, perm] in the factor ordering."""
+    A = sp.csr_matrix(A)
+    B = A[perm][:, perm].tocsr()
+    B.sort_indices()
+    return B
