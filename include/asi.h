@@ -1,0 +1,186 @@
+/*
+ * asi.h — approximate selected inversion from an incomplete LDL^T factor on
+ * one AMD MI355X (gfx950). C ABI of libasi.so.
+ *
+ * Problem (Section 1 and Section 2.1 of the paper): given a symmetric
+ * permutation P and factors with P^T A P ~ L D L^T, where L is unit lower
+ * triangular with identity diagonal blocks and D is block diagonal with 1x1
+ * and 2x2 blocks, compute entries of the inverse on the selected pattern
+ *     S = {(i, j) : (L + D + L^T)_ij != 0}.
+ * Everything is in the factor ordering (row/column k of the outputs is
+ * unknown perm[k] of A).
+ *
+ * Conventions shared by all calls
+ *  - Index types: row pointers int64, column indices int32, 0-based; columns
+ *    sorted and unique within each row.
+ *  - L is passed as its strictly lower part in CSR (the unit diagonal is
+ *    implicit). A 2x2 block {j, j+1} must not store L(j+1, j). If the two
+ *    columns of a 2x2 block hold different row sets, S uses their union and
+ *    the missing L entries count as zero.
+ *  - D is passed as d_diag[n] (D_jj), d_sub[n] (D_{j+1,j} where j starts a
+ *    2x2 block, ignored elsewhere) and piv[n] (int8: 0 = 1x1 block, 1 = first
+ *    and 2 = second index of a 2x2 block).
+ *  - Values on S travel as one float64 array in S's CSR layout (both
+ *    triangles, |S| entries) as returned by asi_get_pattern.
+ *  - Host pointers are marked _h; every other pointer is device memory on the
+ *    handle's device. The caller owns every buffer, including the workspace;
+ *    the library never allocates device memory.
+ *  - Numeric calls are enqueued asynchronously on the handle's stream and
+ *    return after argument checks. Errors found on the device (a singular D
+ *    block, a non-finite value, an exhausted pool) are latched in the
+ *    workspace and returned by asi_sync.
+ *  - A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef ASI_H
+#define ASI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct asi_handle_s *asi_handle;
+
+typedef enum {
+    ASI_OK = 0,
+    ASI_E_ARG = 1,         /* bad argument (null pointer, size, range) */
+    ASI_E_PATTERN = 2,     /* L or piv violates the conventions above */
+    ASI_E_SINGULAR_D = 3,  /* a D block is singular (device-detected) */
+    ASI_E_NONFINITE = 4,   /* a non-finite value was produced (device-detected) */
+    ASI_E_STATE = 5,       /* call order violated (e.g. numeric call before analyze) */
+    ASI_E_WORKSPACE = 6,   /* workspace too small or a device pool exhausted */
+    ASI_E_HIP = 7,         /* a HIP runtime call failed */
+    ASI_E_UNSUPPORTED = 8  /* the pattern exceeds a documented kernel limit */
+} asi_status;
+
+typedef enum { ASI_FP64 = 0, ASI_MIXED = 1 } asi_precision;
+
+/* Summary of the symbolic analysis (filled by asi_get_info). */
+typedef struct {
+    int32_t n;
+    int32_t n_blocks;        /* D blocks */
+    int32_t n_levels;        /* levels of the SelInv dependency DAG */
+    int32_t max_cols;        /* max |R_J| over blocks */
+    int64_t nnz_L;           /* stored L entries (input) */
+    int64_t nnz_S;           /* |S|, both triangles */
+    int64_t gather_pairs;    /* sum over J of the Z entries scanned by the sweep */
+    int64_t gather_hits;     /* sum over J of the pairs (r, l) in R_J x R_J found in S */
+    size_t workspace_min;    /* bytes without the NInv pool */
+    size_t workspace_default;/* bytes with a default-sized NInv pool */
+} asi_info;
+
+/* Create a handle bound to HIP device `device` and stream `stream` (a
+ * hipStream_t; NULL selects the null stream). device = -1 creates a
+ * host-only handle that can run asi_analyze and asi_get_info but no device
+ * call (those return ASI_E_STATE). */
+asi_status asi_create(asi_handle *h, int device, void *stream);
+asi_status asi_destroy(asi_handle h);
+/* Rebind the stream used by subsequent numeric calls. */
+asi_status asi_set_stream(asi_handle h, void *stream);
+/* Message of the last failing call on this handle (valid until the next call). */
+const char *asi_last_error(asi_handle h);
+
+/*
+ * Symbolic analysis of the pattern of L (Section 1: S is induced by the
+ * pattern of L + D + L^T; Section 2.1: inverse information flows from the
+ * last block to the first, so block J can run once every block holding a
+ * row of R_J is done). Host pointers. Builds S, the dependency levels and
+ * the index maps; reports |S| and the workspace size.
+ * Errors: ASI_E_ARG, ASI_E_PATTERN, ASI_E_UNSUPPORTED (|R_J| above 2048).
+ */
+asi_status asi_analyze(asi_handle h, int32_t n, const int64_t *L_rowptr_h, const int32_t *L_col_h,
+                       const int8_t *piv_h, int64_t *nnzS_out, size_t *workspace_bytes_out);
+
+/* Hand the library a device workspace of `bytes` (at least workspace_min;
+ * whatever exceeds it becomes the NInv pool) and upload the analysis into it
+ * (synchronous). The workspace must stay alive while the handle uses it. */
+asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes);
+
+asi_status asi_get_info(asi_handle h, asi_info *info);
+
+/* Copy S's CSR pattern (device buffers of n+1 and |S| entries) and, if
+ * level_d is not NULL, each unknown's DAG level (n entries). */
+asi_status asi_get_pattern(asi_handle h, int64_t *S_rowptr_d, int32_t *S_col_d, int32_t *level_d);
+
+/*
+ * SelInv (Section 2.1, recursion for G21 and G11): for every block J from
+ * the last to the first, Z(R_J, J) = -Zhat(R_J, R_J) L(R_J, J) and
+ * Z(J, J) = D_J^-1 - L(R_J, J)^T Z(R_J, J), where Zhat is Z restricted to S
+ * (entries outside S are discarded). L_val: values in the order of the
+ * L_col array given to asi_analyze. Z_S: |S| float64 outputs.
+ * ASI_MIXED keeps the off-diagonal working values, the gathers and their
+ * accumulation in float32, and the D-block inverses and Z(J, J) in float64.
+ */
+asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
+                      asi_precision prec, double *Z_S);
+
+/*
+ * NInv (Section 2.2): L^inv = sum_{m=0}^{p} T_m with T_0 = I and
+ * T_m = drop_delta(E T_{m-1}), E = I - L, dropping |t| < delta in each new
+ * term; N = (L^inv)^T D^-1 L^inv evaluated on S. Columns of L^inv are kept in
+ * the workspace pool (ASI_E_WORKSPACE at asi_sync if it runs out).
+ */
+asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
+                    int32_t p, double delta, asi_precision prec, double *N_S);
+
+/*
+ * Mix (Section 2.3): M_ij = Z_ij where |Z_ij| > eps sqrt(|Z_ii Z_jj|), else
+ * N_ij. M_S may alias Z_S or N_S.
+ */
+asi_status asi_mix(asi_handle h, const double *Z_S, const double *N_S, double eps, double *M_S);
+
+/*
+ * SPAI refinement (Section 2.4): for each column j, cg_iters steps of
+ * Jacobi-preconditioned CG on the normal equations of min ||Ah m - e_j||_2
+ * with supp(m) in column j of S, starting from M(:, j); Ah = P^T A P from the
+ * original-order CSR of A (both triangles) and perm; then R = (M' + M'^T)/2.
+ * Column j of S may hold at most 512 entries.
+ */
+asi_status asi_spai(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                    const int32_t *perm, const double *M_S, int32_t cg_iters, double *R_S);
+
+/*
+ * Rank-k correction on S (Section 2.5, corrected inverse; Section 2.6,
+ * corrected diagonal): out_ij = in_ij + sum_m lambda_m V_im V_jm with V an
+ * n x k row-major float64 matrix in the factor ordering. 1 <= k <= 64.
+ * out_S may alias in_S.
+ */
+asi_status asi_lowrank(asi_handle h, int32_t k, const double *V, const double *lambda,
+                       const double *in_S, double *out_S);
+
+/* Diagonal of a matrix on S: d[i] = X(i, i). */
+asi_status asi_diag(asi_handle h, const double *X_S, double *d);
+
+/* Wait for the handle's stream; return the first device-side error latched
+ * since the previous asi_sync (and clear it). */
+asi_status asi_sync(asi_handle h);
+
+/*
+ * Device-side tracing. asi_profile(h, 1) clears the counters and brackets
+ * every subsequent kernel launch of the numeric calls with HIP events on the
+ * handle's stream; asi_profile(h, 0) stops. asi_profile_read waits for the
+ * stream and returns, for one kernel class, the number of launches, their
+ * summed device time and their summed algorithmic bytes (0 where the class
+ * has no byte model).
+ */
+typedef enum {
+    ASI_K_DINV = 0,          /* D-block inverses */
+    ASI_K_SELINV = 1,        /* SelInv level launches, wavefront-per-block kernel */
+    ASI_K_SELINV_BIG = 2,    /* SelInv level launches, workgroup-per-block kernel */
+    ASI_K_NINV = 3,          /* the NInv sequence (series columns and product on S) */
+    ASI_K_MIX = 4,           /* Mix selection (with its diagonal copy) */
+    ASI_K_SPAI = 5,          /* SPAI refinement and symmetrisation */
+    ASI_K_LOWRANK = 6,       /* rank-k correction on S */
+    ASI_K_COUNT = 7
+} asi_kernel_class;
+asi_status asi_profile(asi_handle h, int enable);
+asi_status asi_profile_read(asi_handle h, int32_t kernel_class, int64_t *launches, double *total_ms,
+                            double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASI_H */

@@ -1,0 +1,243 @@
+"""Python binding of libasi (include/asi.h): argument marshalling only.
+
+Every numeric step runs in the library's HIP kernels; PyTorch supplies device
+memory (the workspace and the input/output tensors) and the stream. The
+binding loads the in-tree ``libasi.so`` and fails loudly when it is missing;
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libasi.so")
+
+STATUS = {0: "ASI_OK", 1: "ASI_E_ARG", 2: "ASI_E_PATTERN", 3: "ASI_E_SINGULAR_D",
+          4: "ASI_E_NONFINITE", 5: "ASI_E_STATE", 6: "ASI_E_WORKSPACE", 7: "ASI_E_HIP",
+          8: "ASI_E_UNSUPPORTED"}
+PRECISION = {"fp64": 0, "mixed": 1}
+
+# every symbol the header declares
+EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi_analyze",
+           "asi_set_workspace", "asi_get_info", "asi_get_pattern", "asi_selinv", "asi_ninv",
+           "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
+           "asi_profile_read"]
+KERNEL_CLASSES = {"dinv": 0, "selinv": 1, "selinv_big": 2, "ninv": 3, "mix": 4, "spai": 5,
+                  "lowrank": 6}
+
+
+class AsiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_blocks", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("max_cols", ctypes.c_int32), ("nnz_L", ctypes.c_int64), ("nnz_S", ctypes.c_int64),
+                ("gather_pairs", ctypes.c_int64), ("gather_hits", ctypes.c_int64),
+                ("workspace_min", ctypes.c_size_t), ("workspace_default", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library():
+    """Load the in-tree libasi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first (__graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "asi_create": [ctypes.POINTER(P), ctypes.c_int, P],
+        "asi_destroy": [P],
+        "asi_set_stream": [P, P],
+        "asi_analyze": [P, i32, P, P, P, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)],
+        "asi_set_workspace": [P, P, ctypes.c_size_t],
+        "asi_get_info": [P, ctypes.POINTER(Info)],
+        "asi_get_pattern": [P, P, P, P],
+        "asi_selinv": [P, P, P, P, ctypes.c_int, P],
+        "asi_ninv": [P, P, P, P, i32, f64, ctypes.c_int, P],
+        "asi_mix": [P, P, P, f64, P],
+        "asi_spai": [P, P, P, P, P, P, i32, P],
+        "asi_lowrank": [P, i32, P, P, P, P],
+        "asi_diag": [P, P, P],
+        "asi_sync": [P],
+        "asi_profile": [P, ctypes.c_int],
+        "asi_profile_read": [P, i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(f64)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.asi_last_error.argtypes = [P]
+    lib.asi_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One handle of the library bound to a CUDA/HIP device of torch."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        self.h = ctypes.c_void_p()
+        self._check(self.lib.asi_create(ctypes.byref(self.h), device, None))
+        self.ws = None
+        self.n = 0
+        self.nnz_S = 0
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.lib.asi_destroy(self.h)
+        except Exception:
+            pass
+
+    # -- plumbing ------------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            msg = self.lib.asi_last_error(self.h) if self.h else b""
+            raise AsiError(rc, (msg or b"").decode())
+
+    def _stream(self):
+        s = self.torch.cuda.current_stream(self.device)
+        self._check(self.lib.asi_set_stream(self.h, ctypes.c_void_p(s.cuda_stream)))
+
+    def _f64(self, x, n=None):
+        t = self.torch.as_tensor(x, dtype=self.torch.float64, device=self.device).contiguous()
+        if n is not None and t.numel() != n:
+            raise ValueError(f"expected {n} entries, got {t.numel()}")
+        return t
+
+    # -- symbolic ------------------------------------------------------------
+    def analyze(self, n, L_rowptr, L_col, piv, workspace_bytes=None):
+        """asi_analyze + asi_set_workspace (the workspace is a torch uint8 tensor)."""
+        rp = np.ascontiguousarray(L_rowptr, dtype=np.int64)
+        cl = np.ascontiguousarray(L_col, dtype=np.int32)
+        pv = np.ascontiguousarray(piv, dtype=np.int8)
+        if len(cl) == 0:
+            cl = np.zeros(1, np.int32)
+        nnz = ctypes.c_int64()
+        wsb = ctypes.c_size_t()
+        self._check(self.lib.asi_analyze(self.h, int(n), rp.ctypes.data, cl.ctypes.data, pv.ctypes.data,
+                                         ctypes.byref(nnz), ctypes.byref(wsb)))
+        self.n = int(n)
+        self.nnz_S = int(nnz.value)
+        self.set_workspace(workspace_bytes or wsb.value)
+        return self.nnz_S
+
+    def set_workspace(self, nbytes):
+        self.ws = self.torch.empty(int(nbytes) + 256, dtype=self.torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) & ~255
+        self._stream()
+        self._check(self.lib.asi_set_workspace(self.h, ctypes.c_void_p(aligned), int(nbytes)))
+
+    def info(self):
+        inf = Info()
+        self._check(self.lib.asi_get_info(self.h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def pattern(self, with_level=False):
+        t = self.torch
+        rp = t.empty(self.n + 1, dtype=t.int64, device=self.device)
+        cl = t.empty(self.nnz_S, dtype=t.int32, device=self.device)
+        lv = t.empty(self.n, dtype=t.int32, device=self.device) if with_level else None
+        self._stream()
+        self._check(self.lib.asi_get_pattern(self.h, _ptr(rp), _ptr(cl), _ptr(lv) if lv is not None else None))
+        return (rp, cl, lv) if with_level else (rp, cl)
+
+    # -- numeric -------------------------------------------------------------
+    def _out(self, out):
+        if out is None:
+            return self.torch.empty(self.nnz_S, dtype=self.torch.float64, device=self.device)
+        assert out.dtype == self.torch.float64 and out.numel() == self.nnz_S and out.is_contiguous()
+        return out
+
+    def selinv(self, L_val, d_diag, d_sub, precision="fp64", out=None):
+        out = self._out(out)
+        self._stream()
+        self._check(self.lib.asi_selinv(self.h, _ptr(L_val), _ptr(d_diag), _ptr(d_sub),
+                                        PRECISION[precision], _ptr(out)))
+        return out
+
+    def ninv(self, L_val, d_diag, d_sub, p=3, delta=0.1, precision="fp64", out=None):
+        out = self._out(out)
+        self._stream()
+        self._check(self.lib.asi_ninv(self.h, _ptr(L_val), _ptr(d_diag), _ptr(d_sub), int(p),
+                                      float(delta), PRECISION[precision], _ptr(out)))
+        return out
+
+    def mix(self, Z, N, eps=1e-2, out=None):
+        out = self._out(out)
+        self._stream()
+        self._check(self.lib.asi_mix(self.h, _ptr(Z), _ptr(N), float(eps), _ptr(out)))
+        return out
+
+    def spai(self, A_rowptr, A_col, A_val, perm, M, cg_iters=10, out=None):
+        out = self._out(out)
+        self._stream()
+        self._check(self.lib.asi_spai(self.h, _ptr(A_rowptr), _ptr(A_col), _ptr(A_val), _ptr(perm),
+                                      _ptr(M), int(cg_iters), _ptr(out)))
+        return out
+
+    def lowrank(self, V, lam, X, out=None):
+        out = self._out(out)
+        self._stream()
+        k = int(V.shape[1])
+        self._check(self.lib.asi_lowrank(self.h, k, _ptr(V), _ptr(lam), _ptr(X), _ptr(out)))
+        return out
+
+    def diag(self, X, out=None):
+        t = self.torch
+        if out is None:
+            out = t.empty(self.n, dtype=t.float64, device=self.device)
+        self._stream()
+        self._check(self.lib.asi_diag(self.h, _ptr(X), _ptr(out)))
+        return out
+
+    def sync(self):
+        self._stream()
+        self._check(self.lib.asi_sync(self.h))
+
+    def profile(self, enable=True):
+        self._stream()
+        self._check(self.lib.asi_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{class: (launches, total_ms, algorithmic_bytes)} for every kernel class."""
+        out = {}
+        for name, k in KERNEL_CLASSES.items():
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            b = ctypes.c_double()
+            self._check(self.lib.asi_profile_read(self.h, k, ctypes.byref(n), ctypes.byref(ms),
+                                                  ctypes.byref(b)))
+            out[name] = (n.value, ms.value, b.value)
+        return out
+
+
+def upload_factors(F, device="cuda:0"):
+    """Device copies of the numeric factor arrays (L values, D) as torch tensors."""
+    import torch
+    dev = torch.device(device)
+    return (torch.as_tensor(F.L_val, dtype=torch.float64, device=dev),
+            torch.as_tensor(F.d_diag, dtype=torch.float64, device=dev),
+            torch.as_tensor(F.d_sub, dtype=torch.float64, device=dev))

@@ -1,0 +1,229 @@
+// Symbolic analysis of the factor pattern (host side of libasi).
+//
+// S is the pattern of L + D + L^T (Section 1). Column J of L (both columns of
+// a 2x2 block, union of their rows) gives R_J, the rows below the block; the
+// upper part of row `last(J)` of S is exactly R_J, so S's CSR doubles as the
+// column layout of the lower triangle of Z that the SelInv gathers read.
+// Block J depends on every block that holds a row of R_J (its Z(R_J, R_J)
+// entries, Section 2.1), which gives the level schedule.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "asi_internal.h"
+
+namespace asi {
+
+namespace {
+enum { OK = 0, E_ARG = 1, E_PATTERN = 2, E_UNSUPPORTED = 8 };
+}
+
+int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, Analysis &A,
+            std::string &msg) {
+    A = Analysis();
+    if (n <= 0) {
+        msg = "n must be positive";
+        return E_ARG;
+    }
+    A.n = n;
+    A.piv.assign(piv, piv + n);
+    if (Lp[0] != 0) {
+        msg = "L_rowptr[0] must be 0";
+        return E_PATTERN;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        int8_t p = piv[i];
+        if (p < 0 || p > 2) {
+            msg = "piv values must be 0, 1 or 2";
+            return E_PATTERN;
+        }
+        if (p == 1 && (i + 1 >= n || piv[i + 1] != 2)) {
+            msg = "piv: a 1 must be followed by a 2";
+            return E_PATTERN;
+        }
+        if (p == 2 && (i == 0 || piv[i - 1] != 1)) {
+            msg = "piv: a 2 must follow a 1";
+            return E_PATTERN;
+        }
+        if (Lp[i + 1] < Lp[i]) {
+            msg = "L_rowptr must be nondecreasing";
+            return E_PATTERN;
+        }
+        for (int64_t q = Lp[i]; q < Lp[i + 1]; ++q) {
+            int32_t c = Li[q];
+            if (c < 0 || c >= i) {
+                msg = "L must be strictly lower triangular with in-range columns";
+                return E_PATTERN;
+            }
+            if (q > Lp[i] && c <= Li[q - 1]) {
+                msg = "L columns must be sorted and unique within each row";
+                return E_PATTERN;
+            }
+            if (p == 2 && c == i - 1) {
+                msg = "L must not store the (j+1, j) entry of a 2x2 block";
+                return E_PATTERN;
+            }
+        }
+    }
+    A.nnzL = Lp[n];
+
+    // column lists of L (CSC) with the source index of every entry
+    std::vector<int64_t> cp(n + 1, 0);
+    for (int64_t q = 0; q < A.nnzL; ++q) cp[Li[q] + 1]++;
+    for (int32_t j = 0; j < n; ++j) cp[j + 1] += cp[j];
+    std::vector<int32_t> crow(A.nnzL);
+    std::vector<int64_t> csrc(A.nnzL);
+    {
+        std::vector<int64_t> f(cp.begin(), cp.end() - 1);
+        for (int32_t r = 0; r < n; ++r)
+            for (int64_t q = Lp[r]; q < Lp[r + 1]; ++q) {
+                int64_t d = f[Li[q]]++;
+                crow[d] = r;  // rows ascending since r ascends
+                csrc[d] = q;
+            }
+    }
+
+    // upper part of every row: row j holds {j+1 if j starts a 2x2} + R_J,
+    // row j+1 of a 2x2 holds R_J; R_J = union of the block's column rows
+    std::vector<int64_t> up(n + 1, 0);
+    std::vector<int32_t> ucol;
+    ucol.reserve(A.nnzL + n);
+    std::vector<int32_t> RJ;
+    for (int32_t j = 0; j < n;) {
+        if (piv[j] == 1) {
+            RJ.clear();
+            std::set_union(crow.begin() + cp[j], crow.begin() + cp[j + 1], crow.begin() + cp[j + 1],
+                           crow.begin() + cp[j + 2], std::back_inserter(RJ));
+            // row j: (j, j+1) then R_J
+            up[j + 1] = up[j] + 1 + (int64_t)RJ.size();
+            ucol.push_back(j + 1);
+            ucol.insert(ucol.end(), RJ.begin(), RJ.end());
+            up[j + 2] = up[j + 1] + (int64_t)RJ.size();
+            ucol.insert(ucol.end(), RJ.begin(), RJ.end());
+            j += 2;
+        } else {
+            up[j + 1] = up[j] + (cp[j + 1] - cp[j]);
+            ucol.insert(ucol.end(), crow.begin() + cp[j], crow.begin() + cp[j + 1]);
+            j += 1;
+        }
+    }
+
+    // lower part of row r = transpose of the upper parts; build row lengths
+    std::vector<int64_t> lowcnt(n + 1, 0);
+    for (int32_t j = 0; j < n; ++j)
+        for (int64_t q = up[j]; q < up[j + 1]; ++q) lowcnt[ucol[q] + 1]++;
+    A.rowptr.assign(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) A.rowptr[i + 1] = A.rowptr[i] + lowcnt[i + 1] + 1 + (up[i + 1] - up[i]);
+    A.nnzS = A.rowptr[n];
+    A.col.resize(A.nnzS);
+    A.srow.resize(A.nnzS);
+    A.diagpos.resize(n);
+    A.mirror.assign(A.nnzS, -1);
+    A.lsrc.assign(A.nnzS, -1);
+    for (int32_t i = 0; i < n; ++i) {
+        A.diagpos[i] = A.rowptr[i] + lowcnt[i + 1];
+        A.col[A.diagpos[i]] = i;
+        A.mirror[A.diagpos[i]] = A.diagpos[i];
+        int64_t q0 = A.diagpos[i] + 1;
+        for (int64_t q = up[i]; q < up[i + 1]; ++q) A.col[q0 + (q - up[i])] = ucol[q];
+        for (int64_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) A.srow[p] = i;
+    }
+    {
+        // lower entries: (r, j) for every upper (j, r); rows j ascending keep them sorted
+        std::vector<int64_t> f(n);
+        for (int32_t i = 0; i < n; ++i) f[i] = A.rowptr[i];
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = A.diagpos[j] + 1; p < A.rowptr[j + 1]; ++p) {
+                int32_t r = A.col[p];
+                int64_t d = f[r]++;
+                A.col[d] = j;
+                A.mirror[d] = p;
+                A.mirror[p] = d;
+            }
+    }
+    // L source of each upper position (j, r): L(r, j), found by a merge of
+    // the (sorted) upper row j with the (sorted) column j of L
+    for (int32_t j = 0; j < n; ++j) {
+        int64_t p = A.diagpos[j] + 1, pe = A.rowptr[j + 1];
+        int64_t q = cp[j], qe = cp[j + 1];
+        while (p < pe && q < qe) {
+            if (A.col[p] == crow[q]) {
+                A.lsrc[p] = csrc[q];
+                ++p;
+                ++q;
+            } else if (A.col[p] < crow[q]) {
+                ++p;
+            } else {
+                ++q;
+            }
+        }
+    }
+
+    // blocks, levels and work counts
+    A.level.assign(n, 0);
+    std::vector<int32_t> blocks;
+    for (int32_t j = 0; j < n; j += (piv[j] == 1 ? 2 : 1)) blocks.push_back(j);
+    A.n_blocks = (int32_t)blocks.size();
+    std::vector<int32_t> bcols(n, 0);
+    std::vector<int64_t> bhits(n, 0);
+    std::vector<int32_t> mark(n, -1);
+    int32_t maxlev = -1;
+    for (auto it = blocks.rbegin(); it != blocks.rend(); ++it) {
+        int32_t j = *it;
+        int32_t last = piv[j] == 1 ? j + 1 : j;
+        int64_t u0 = A.diagpos[last] + 1, u1 = A.rowptr[last + 1];
+        int32_t lev = 0;
+        for (int64_t p = u0; p < u1; ++p) {
+            lev = std::max(lev, A.level[A.col[p]] + 1);
+            mark[A.col[p]] = j;
+        }
+        A.level[j] = lev;
+        if (last != j) A.level[last] = lev;
+        maxlev = std::max(maxlev, lev);
+        int32_t c = (int32_t)(u1 - u0);
+        bcols[j] = c;
+        A.max_cols = std::max(A.max_cols, c);
+        for (int64_t p = u0; p < u1; ++p) {
+            int32_t l = A.col[p];
+            int64_t s0 = A.diagpos[l] + 1, s1 = A.rowptr[l + 1];
+            A.gather_pairs += s1 - s0;
+            for (int64_t s = s0; s < s1; ++s) bhits[j] += (mark[A.col[s]] == j);
+        }
+        A.gather_hits += bhits[j];
+    }
+    A.n_levels = maxlev + 1;
+    if (A.max_cols > kBigCols) {
+        msg = "a block has more than 2048 rows below it (|R_J| limit)";
+        return E_UNSUPPORTED;
+    }
+    // level-major schedules (blocks in increasing start index within a level)
+    std::vector<int32_t> cs(A.n_levels + 1, 0), cb(A.n_levels + 1, 0);
+    for (int32_t j : blocks) (bcols[j] <= kSmallCols ? cs : cb)[A.level[j] + 1]++;
+    for (int32_t l = 0; l < A.n_levels; ++l) {
+        cs[l + 1] += cs[l];
+        cb[l + 1] += cb[l];
+    }
+    A.lvl_small = cs;
+    A.lvl_big = cb;
+    A.sched_small.resize(cs[A.n_levels]);
+    A.sched_big.resize(cb[A.n_levels]);
+    for (int m = 0; m < 2; ++m) {
+        A.lvl_bytes_small[m].assign(A.n_levels, 0.0);
+        A.lvl_bytes_big[m].assign(A.n_levels, 0.0);
+    }
+    for (int32_t j : blocks) {
+        const bool small = bcols[j] <= kSmallCols;
+        if (small)
+            A.sched_small[cs[A.level[j]]++] = j;
+        else
+            A.sched_big[cb[A.level[j]]++] = j;
+        const int ncols = piv[j] == 1 ? 2 : 1;
+        for (int m = 0; m < 2; ++m) {
+            double b = selinv_block_bytes(bcols[j], ncols, bhits[j], m == 0);
+            (small ? A.lvl_bytes_small[m] : A.lvl_bytes_big[m])[A.level[j]] += b;
+        }
+    }
+    return OK;
+}
+
+}  // namespace asi

@@ -1,0 +1,591 @@
+// C ABI of libasi: handle, workspace layout, argument checks and launch
+// sequences. Declared in include/asi.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "asi.h"
+#include "asi_internal.h"
+#include "kernels.h"
+
+struct asi_handle_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool analyzed = false;
+    bool ws_ready = false;
+    asi::Analysis A;
+    size_t ws_min = 0;
+    size_t ws_default = 0;
+    // device workspace
+    unsigned char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t *rowptr = nullptr;
+    int32_t *col = nullptr;
+    int32_t *srow = nullptr;
+    int64_t *diagpos = nullptr;
+    int64_t *mirror = nullptr;
+    int64_t *lsrc = nullptr;
+    int8_t *piv = nullptr;
+    int32_t *level = nullptr;
+    int32_t *sched_small = nullptr;
+    int32_t *sched_big = nullptr;
+    double *dinv = nullptr;
+    float *zw32 = nullptr;
+    double *zdiag = nullptr;
+    int32_t *status = nullptr;
+    int64_t *cstart = nullptr;
+    int32_t *clen = nullptr;
+    int32_t *ovf = nullptr;
+    int32_t *ovf2 = nullptr;
+    int32_t *counters = nullptr;  // [0] ovf count, [1] ovf2 count
+    unsigned long long *pool_top = nullptr;
+    int32_t *iperm = nullptr;
+    double *cn2 = nullptr;
+    double *X = nullptr;
+    int32_t *prow = nullptr;
+    void *plinv = nullptr;
+    void *pw = nullptr;
+    int64_t pool_cap = 0;  // entries (sized for float64 values)
+    // tracing
+    bool prof = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int kind;
+        double bytes;
+    };
+    std::vector<hipEvent_t> ev_free;
+    std::vector<Rec> pending;
+    int64_t prof_n[ASI_K_COUNT] = {};
+    double prof_ms[ASI_K_COUNT] = {};
+    double prof_bytes[ASI_K_COUNT] = {};
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+asi_status fail(asi_handle h, asi_status s, const std::string &m) {
+    if (h) h->err = m;
+    return s;
+}
+
+asi_status hip_fail(asi_handle h, hipError_t e, const char *what) {
+    return fail(h, ASI_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace layout: fixed regions followed by the NInv pool.
+struct Layout {
+    size_t off[32];
+    int k = 0;
+    size_t cur = 0;
+    size_t add(size_t bytes) {
+        size_t o = cur;
+        cur = align256(cur + std::max<size_t>(bytes, 1));
+        off[k++] = o;
+        return o;
+    }
+};
+
+Layout make_layout(const asi::Analysis &A) {
+    const size_t n = (size_t)A.n, s = (size_t)A.nnzS;
+    Layout L;
+    L.add((n + 1) * 8);                 // 0 rowptr
+    L.add(s * 4);                       // 1 col
+    L.add(s * 4);                       // 2 srow
+    L.add(n * 8);                       // 3 diagpos
+    L.add(s * 8);                       // 4 mirror
+    L.add(s * 8);                       // 5 lsrc
+    L.add(n);                           // 6 piv
+    L.add(n * 4);                       // 7 level
+    L.add(A.sched_small.size() * 4);    // 8
+    L.add(A.sched_big.size() * 4);      // 9
+    L.add(3 * n * 8);                   // 10 dinv
+    L.add(s * 4);                       // 11 zw32
+    L.add(n * 8);                       // 12 zdiag
+    L.add(256);                         // 13 status + counters + pool_top
+    L.add(n * 8);                       // 14 cstart
+    L.add(n * 4);                       // 15 clen
+    L.add(n * 4);                       // 16 ovf
+    L.add(n * 4);                       // 17 ovf2
+    L.add(n * 4);                       // 18 iperm
+    L.add(n * 8);                       // 19 cn2
+    L.add(s * 8);                       // 20 X
+    return L;
+}
+
+constexpr size_t kPoolEntryBytes = 4 + 8 + 8;
+
+template <typename T>
+T *at(unsigned char *base, size_t off) {
+    return reinterpret_cast<T *>(base + off);
+}
+
+hipEvent_t take_event(asi_handle h) {
+    if (!h->ev_free.empty()) {
+        hipEvent_t e = h->ev_free.back();
+        h->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets a launch sequence with events when tracing is on.
+struct Trace {
+    asi_handle h;
+    int kind;
+    double bytes;
+    hipEvent_t a = nullptr;
+    Trace(asi_handle hh, int k, double b) : h(hh), kind(k), bytes(b) {
+        if (h->prof) {
+            a = take_event(h);
+            if (a) (void)hipEventRecord(a, h->stream);
+        }
+    }
+    ~Trace() {
+        if (!a) return;
+        hipEvent_t b = take_event(h);
+        if (!b) {
+            h->ev_free.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, h->stream);
+        h->pending.push_back({a, b, kind, bytes});
+    }
+};
+
+asi_status need_ready(asi_handle h) {
+    if (!h) return ASI_E_ARG;
+    if (!h->analyzed) return fail(h, ASI_E_STATE, "asi_analyze has not run");
+    if (!h->ws_ready) return fail(h, ASI_E_STATE, "asi_set_workspace has not run");
+    return ASI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+asi_status asi_create(asi_handle *h, int device, void *stream) {
+    if (!h) return ASI_E_ARG;
+    int count = 0;
+    if (device != -1 && (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count))
+        return ASI_E_ARG;
+    auto *p = new asi_handle_s();
+    p->device = device;
+    p->stream = reinterpret_cast<hipStream_t>(stream);
+    *h = p;
+    return ASI_OK;
+}
+
+asi_status asi_destroy(asi_handle h) {
+    if (!h) return ASI_OK;
+    if (h->device >= 0) {
+        DeviceGuard g(h->device);
+        (void)hipStreamSynchronize(h->stream);
+        for (auto &r : h->pending) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : h->ev_free) (void)hipEventDestroy(e);
+    }
+    delete h;
+    return ASI_OK;
+}
+
+asi_status asi_set_stream(asi_handle h, void *stream) {
+    if (!h) return ASI_E_ARG;
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    return ASI_OK;
+}
+
+const char *asi_last_error(asi_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+asi_status asi_analyze(asi_handle h, int32_t n, const int64_t *L_rowptr_h, const int32_t *L_col_h,
+                       const int8_t *piv_h, int64_t *nnzS_out, size_t *workspace_bytes_out) {
+    if (!h) return ASI_E_ARG;
+    h->err.clear();
+    h->analyzed = false;
+    h->ws_ready = false;
+    if (n <= 0 || !L_rowptr_h || !piv_h || (!L_col_h && n > 0 && L_rowptr_h[n] > 0))
+        return fail(h, ASI_E_ARG, "null or empty analysis input");
+    std::string msg;
+    int rc = asi::analyze(n, L_rowptr_h, L_col_h, piv_h, h->A, msg);
+    if (rc != 0) return fail(h, (asi_status)rc, msg);
+    Layout L = make_layout(h->A);
+    h->ws_min = L.cur;
+    int64_t pool = 8 * (int64_t)n + 2 * h->A.nnzL + 4096;
+    h->ws_default = L.cur + (size_t)pool * kPoolEntryBytes + 3 * 256;
+    h->analyzed = true;
+    if (nnzS_out) *nnzS_out = h->A.nnzS;
+    if (workspace_bytes_out) *workspace_bytes_out = h->ws_default;
+    return ASI_OK;
+}
+
+asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
+    if (!h) return ASI_E_ARG;
+    if (h->device < 0) return fail(h, ASI_E_STATE, "host-only handle (device -1) has no workspace");
+    if (!h->analyzed) return fail(h, ASI_E_STATE, "asi_analyze has not run");
+    if (!dev_ws) return fail(h, ASI_E_ARG, "null workspace");
+    if ((reinterpret_cast<uintptr_t>(dev_ws) & 255) != 0) return fail(h, ASI_E_ARG, "workspace must be 256-byte aligned");
+    if (bytes < h->ws_min + 3 * 256 + 64 * kPoolEntryBytes)
+        return fail(h, ASI_E_WORKSPACE, "workspace smaller than workspace_min");
+    DeviceGuard g(h->device);
+    const asi::Analysis &A = h->A;
+    Layout L = make_layout(A);
+    unsigned char *b = static_cast<unsigned char *>(dev_ws);
+    h->ws = b;
+    h->ws_bytes = bytes;
+    h->rowptr = at<int64_t>(b, L.off[0]);
+    h->col = at<int32_t>(b, L.off[1]);
+    h->srow = at<int32_t>(b, L.off[2]);
+    h->diagpos = at<int64_t>(b, L.off[3]);
+    h->mirror = at<int64_t>(b, L.off[4]);
+    h->lsrc = at<int64_t>(b, L.off[5]);
+    h->piv = at<int8_t>(b, L.off[6]);
+    h->level = at<int32_t>(b, L.off[7]);
+    h->sched_small = at<int32_t>(b, L.off[8]);
+    h->sched_big = at<int32_t>(b, L.off[9]);
+    h->dinv = at<double>(b, L.off[10]);
+    h->zw32 = at<float>(b, L.off[11]);
+    h->zdiag = at<double>(b, L.off[12]);
+    h->status = at<int32_t>(b, L.off[13]);
+    h->counters = h->status + 4;
+    h->pool_top = reinterpret_cast<unsigned long long *>(h->status + 8);
+    h->cstart = at<int64_t>(b, L.off[14]);
+    h->clen = at<int32_t>(b, L.off[15]);
+    h->ovf = at<int32_t>(b, L.off[16]);
+    h->ovf2 = at<int32_t>(b, L.off[17]);
+    h->iperm = at<int32_t>(b, L.off[18]);
+    h->cn2 = at<double>(b, L.off[19]);
+    h->X = at<double>(b, L.off[20]);
+    // pool: rows | linv | w, each region 256-aligned
+    size_t rest = bytes - L.cur - 3 * 256;
+    int64_t cap = (int64_t)(rest / kPoolEntryBytes);
+    size_t o = L.cur;
+    h->prow = at<int32_t>(b, o);
+    o = align256(o + (size_t)cap * 4);
+    h->plinv = b + o;
+    o = align256(o + (size_t)cap * 8);
+    h->pw = b + o;
+    h->pool_cap = cap;
+
+    struct Up {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    } ups[] = {
+        {h->rowptr, A.rowptr.data(), A.rowptr.size() * 8},
+        {h->col, A.col.data(), A.col.size() * 4},
+        {h->srow, A.srow.data(), A.srow.size() * 4},
+        {h->diagpos, A.diagpos.data(), A.diagpos.size() * 8},
+        {h->mirror, A.mirror.data(), A.mirror.size() * 8},
+        {h->lsrc, A.lsrc.data(), A.lsrc.size() * 8},
+        {h->piv, A.piv.data(), A.piv.size()},
+        {h->level, A.level.data(), A.level.size() * 4},
+        {h->sched_small, A.sched_small.data(), A.sched_small.size() * 4},
+        {h->sched_big, A.sched_big.data(), A.sched_big.size() * 4},
+    };
+    for (auto &u : ups) {
+        if (u.bytes == 0) continue;
+        hipError_t e = hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "upload analysis");
+    }
+    hipError_t e = asi::launch_fill_i32(h->status, 64, 0, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "clear status");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "upload analysis");
+    e = asi::set_big_lds_limits();
+    if (e != hipSuccess) return hip_fail(h, e, "set LDS limits");
+    h->ws_ready = true;
+    return ASI_OK;
+}
+
+asi_status asi_get_info(asi_handle h, asi_info *info) {
+    if (!h || !info) return ASI_E_ARG;
+    if (!h->analyzed) return fail(h, ASI_E_STATE, "asi_analyze has not run");
+    const asi::Analysis &A = h->A;
+    info->n = A.n;
+    info->n_blocks = A.n_blocks;
+    info->n_levels = A.n_levels;
+    info->max_cols = A.max_cols;
+    info->nnz_L = A.nnzL;
+    info->nnz_S = A.nnzS;
+    info->gather_pairs = A.gather_pairs;
+    info->gather_hits = A.gather_hits;
+    info->workspace_min = h->ws_min + 3 * 256 + 64 * kPoolEntryBytes;
+    info->workspace_default = h->ws_default;
+    return ASI_OK;
+}
+
+asi_status asi_get_pattern(asi_handle h, int64_t *S_rowptr_d, int32_t *S_col_d, int32_t *level_d) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!S_rowptr_d || !S_col_d) return fail(h, ASI_E_ARG, "null output");
+    DeviceGuard g(h->device);
+    const asi::Analysis &A = h->A;
+    hipError_t e = hipMemcpyAsync(S_rowptr_d, h->rowptr, (A.n + 1) * 8, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S_col_d, h->col, A.nnzS * 4, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess && level_d)
+        e = hipMemcpyAsync(level_d, h->level, A.n * 4, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "copy pattern");
+    return ASI_OK;
+}
+
+asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
+                      asi_precision prec, double *Z_S) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if ((!L_val && h->A.nnzL > 0) || !d_diag || !d_sub || !Z_S) return fail(h, ASI_E_ARG, "null pointer");
+    if (prec != ASI_FP64 && prec != ASI_MIXED) return fail(h, ASI_E_ARG, "unknown precision");
+    DeviceGuard g(h->device);
+    const asi::Analysis &A = h->A;
+    hipError_t e;
+    {
+        Trace t(h, ASI_K_DINV, 0.0);
+        e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "dinv");
+    const bool fp64 = prec == ASI_FP64;
+    const int m = fp64 ? 0 : 1;
+    asi::SelinvParams P{};
+    P.rowptr = h->rowptr;
+    P.col = h->col;
+    P.diagpos = h->diagpos;
+    P.mirror = h->mirror;
+    P.lsrc = h->lsrc;
+    P.piv = h->piv;
+    P.Lval = L_val;
+    P.dinv = h->dinv;
+    P.Zw = fp64 ? static_cast<void *>(Z_S) : static_cast<void *>(h->zw32);
+    P.out = Z_S;
+    P.same = fp64 ? 1 : 0;
+    P.status = h->status;
+    for (int32_t l = 0; l < A.n_levels; ++l) {
+        P.blocks = h->sched_small + A.lvl_small[l];
+        P.nblk = A.lvl_small[l + 1] - A.lvl_small[l];
+        if (P.nblk > 0) {
+            Trace t(h, ASI_K_SELINV, A.lvl_bytes_small[m][l]);
+            e = asi::launch_selinv_level(P, false, fp64, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "selinv level");
+        }
+        P.blocks = h->sched_big + A.lvl_big[l];
+        P.nblk = A.lvl_big[l + 1] - A.lvl_big[l];
+        if (P.nblk > 0) {
+            Trace t(h, ASI_K_SELINV_BIG, A.lvl_bytes_big[m][l]);
+            e = asi::launch_selinv_level(P, true, fp64, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "selinv level (large blocks)");
+        }
+    }
+    return ASI_OK;
+}
+
+asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub, int32_t p,
+                    double delta, asi_precision prec, double *N_S) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if ((!L_val && h->A.nnzL > 0) || !d_diag || !d_sub || !N_S) return fail(h, ASI_E_ARG, "null pointer");
+    if (p < 0 || p > 64) return fail(h, ASI_E_ARG, "p must be in [0, 64]");
+    if (!(delta >= 0.0)) return fail(h, ASI_E_ARG, "delta must be >= 0");
+    if (prec != ASI_FP64 && prec != ASI_MIXED) return fail(h, ASI_E_ARG, "unknown precision");
+    DeviceGuard g(h->device);
+    const asi::Analysis &A = h->A;
+    hipError_t e;
+    {
+        Trace t(h, ASI_K_DINV, 0.0);
+        e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "dinv");
+    asi::NinvParams P{};
+    P.n = A.n;
+    P.rowptr = h->rowptr;
+    P.col = h->col;
+    P.diagpos = h->diagpos;
+    P.mirror = h->mirror;
+    P.lsrc = h->lsrc;
+    P.piv = h->piv;
+    P.Lval = L_val;
+    P.dinv = h->dinv;
+    P.p = p;
+    P.delta = delta;
+    P.prow = h->prow;
+    P.plinv = h->plinv;
+    P.pw = h->pw;
+    P.pool_cap = h->pool_cap;
+    P.pool_top = h->pool_top;
+    P.cstart = h->cstart;
+    P.clen = h->clen;
+    P.ovf_list = h->ovf;
+    P.ovf_count = h->counters;
+    P.ovf2_list = h->ovf2;
+    P.ovf2_count = h->counters + 1;
+    P.out = N_S;
+    P.status = h->status;
+    {
+        Trace t(h, ASI_K_NINV, 0.0);
+        e = asi::launch_ninv(P, prec == ASI_FP64, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "ninv");
+    return ASI_OK;
+}
+
+asi_status asi_mix(asi_handle h, const double *Z_S, const double *N_S, double eps, double *M_S) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!Z_S || !N_S || !M_S) return fail(h, ASI_E_ARG, "null pointer");
+    if (!(eps >= 0.0)) return fail(h, ASI_E_ARG, "eps must be >= 0");
+    DeviceGuard g(h->device);
+    // bytes: Z, N and M values (24 B), row and column index (8 B) per entry; the
+    // diagonal copy reads and writes 8 B per row twice
+    Trace t(h, ASI_K_MIX, 32.0 * h->A.nnzS + 24.0 * h->A.n);
+    hipError_t e = asi::launch_zdiag(h->A.n, h->diagpos, Z_S, h->zdiag, h->stream);
+    if (e == hipSuccess)
+        e = asi::launch_mix(h->A.nnzS, h->srow, h->col, h->zdiag, Z_S, N_S, eps, M_S, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "mix");
+    return ASI_OK;
+}
+
+asi_status asi_spai(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                    const int32_t *perm, const double *M_S, int32_t cg_iters, double *R_S) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!A_rowptr || !A_col || !A_val || !perm || !M_S || !R_S) return fail(h, ASI_E_ARG, "null pointer");
+    if (cg_iters < 0) return fail(h, ASI_E_ARG, "cg_iters must be >= 0");
+    int64_t maxrow = 0;
+    for (int32_t i = 0; i < h->A.n; ++i) maxrow = std::max(maxrow, h->A.rowptr[i + 1] - h->A.rowptr[i]);
+    if (maxrow > asi::kSpaiMaxCols) return fail(h, ASI_E_UNSUPPORTED, "a column of S has more than 512 entries");
+    DeviceGuard g(h->device);
+    asi::SpaiParams P{};
+    P.n = h->A.n;
+    P.rowptr = h->rowptr;
+    P.col = h->col;
+    P.mirror = h->mirror;
+    P.A_rowptr = A_rowptr;
+    P.A_col = A_col;
+    P.A_val = A_val;
+    P.perm = perm;
+    P.iperm = h->iperm;
+    P.colnorm2 = h->cn2;
+    P.M = M_S;
+    P.X = h->X;
+    P.R = R_S;
+    P.iters = cg_iters;
+    P.status = h->status;
+    Trace t(h, ASI_K_SPAI, 0.0);
+    hipError_t e = asi::launch_spai(P, h->stream);
+    if (e == hipSuccess) e = asi::launch_symmetrize(h->A.nnzS, h->mirror, h->X, R_S, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "spai");
+    return ASI_OK;
+}
+
+asi_status asi_lowrank(asi_handle h, int32_t k, const double *V, const double *lambda, const double *in_S,
+                       double *out_S) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (k < 1 || k > asi::kMaxRank) return fail(h, ASI_E_ARG, "k must be in [1, 64]");
+    if (!V || !lambda || !in_S || !out_S) return fail(h, ASI_E_ARG, "null pointer");
+    DeviceGuard g(h->device);
+    // bytes per entry: column index, input and output values (20 B); V once
+    Trace t(h, ASI_K_LOWRANK, 20.0 * h->A.nnzS + 8.0 * h->A.n * (k + 2));
+    hipError_t e = asi::launch_lowrank(h->A.n, k, h->rowptr, h->col, V, lambda, in_S, out_S, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "lowrank");
+    return ASI_OK;
+}
+
+asi_status asi_diag(asi_handle h, const double *X_S, double *d) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!X_S || !d) return fail(h, ASI_E_ARG, "null pointer");
+    DeviceGuard g(h->device);
+    hipError_t e = asi::launch_zdiag(h->A.n, h->diagpos, X_S, d, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "diag");
+    return ASI_OK;
+}
+
+asi_status asi_sync(asi_handle h) {
+    if (!h) return ASI_E_ARG;
+    if (h->device < 0) return ASI_OK;
+    DeviceGuard g(h->device);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+    if (!h->ws_ready) return ASI_OK;
+    int32_t st = 0;
+    e = hipMemcpy(&st, h->status, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "read status");
+    if (st != 0) {
+        e = asi::launch_fill_i32(h->status, 1, 0, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "clear status");
+        const char *what = st == asi::ST_SINGULAR   ? "singular D block"
+                           : st == asi::ST_NONFINITE ? "non-finite value produced"
+                           : st == asi::ST_POOL      ? "NInv pool exhausted: enlarge the workspace"
+                                                     : "a column exceeds a kernel limit";
+        return fail(h, (asi_status)st, what);
+    }
+    return ASI_OK;
+}
+
+asi_status asi_profile(asi_handle h, int enable) {
+    if (!h) return ASI_E_ARG;
+    if (h->device < 0) return fail(h, ASI_E_STATE, "host-only handle");
+    DeviceGuard g(h->device);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+    for (auto &r : h->pending) {
+        h->ev_free.push_back(r.a);
+        h->ev_free.push_back(r.b);
+    }
+    h->pending.clear();
+    for (int k = 0; k < ASI_K_COUNT; ++k) {
+        h->prof_n[k] = 0;
+        h->prof_ms[k] = 0.0;
+        h->prof_bytes[k] = 0.0;
+    }
+    h->prof = enable != 0;
+    return ASI_OK;
+}
+
+asi_status asi_profile_read(asi_handle h, int32_t kernel_class, int64_t *launches, double *total_ms,
+                            double *bytes) {
+    if (!h) return ASI_E_ARG;
+    if (kernel_class < 0 || kernel_class >= ASI_K_COUNT) return fail(h, ASI_E_ARG, "unknown kernel class");
+    if (h->device >= 0 && !h->pending.empty()) {
+        DeviceGuard g(h->device);
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+        for (auto &r : h->pending) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, r.a, r.b);
+            if (e != hipSuccess) return hip_fail(h, e, "event elapsed time");
+            h->prof_n[r.kind] += 1;
+            h->prof_ms[r.kind] += ms;
+            h->prof_bytes[r.kind] += r.bytes;
+            h->ev_free.push_back(r.a);
+            h->ev_free.push_back(r.b);
+        }
+        h->pending.clear();
+    }
+    if (launches) *launches = h->prof_n[kernel_class];
+    if (total_ms) *total_ms = h->prof_ms[kernel_class];
+    if (bytes) *bytes = h->prof_bytes[kernel_class];
+    return ASI_OK;
+}
+
+}  // extern "C"

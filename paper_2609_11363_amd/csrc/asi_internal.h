@@ -1,0 +1,57 @@
+// Internal declarations shared by the host analysis, the C ABI layer and the
+// HIP kernels of libasi. Not part of the public interface (include/asi.h).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace asi {
+
+// Kernel limits (the analysis refuses patterns above them).
+constexpr int kSmallCols = 128;   // |R_J| handled by one wavefront per block
+constexpr int kBigCols = 2048;    // |R_J| handled by one 256-thread workgroup per block
+constexpr int kSpaiMaxCols = 512; // entries per column of S for the SPAI kernel
+constexpr int kMaxRank = 64;      // rank of the low-rank correction
+
+// Host-side result of the symbolic analysis. Positions index S's CSR arrays.
+struct Analysis {
+    int32_t n = 0;
+    int64_t nnzL = 0;
+    int64_t nnzS = 0;
+    std::vector<int64_t> rowptr;   // n+1
+    std::vector<int32_t> col;      // nnzS
+    std::vector<int32_t> srow;     // nnzS: row of each position
+    std::vector<int64_t> diagpos;  // n: position of (i, i)
+    std::vector<int64_t> mirror;   // nnzS: position of (j, i) for (i, j)
+    std::vector<int64_t> lsrc;     // nnzS: for an upper position (j, r) the index of L(r, j)
+                                   //       in the input L arrays, -1 when L(r, j) is not stored
+    std::vector<int8_t> piv;       // n
+    std::vector<int32_t> level;    // n: DAG level of each unknown's block
+    int32_t n_blocks = 0;
+    int32_t n_levels = 0;
+    int32_t max_cols = 0;
+    // level-major schedules of block starts, split by column count
+    std::vector<int32_t> sched_small, sched_big;
+    std::vector<int32_t> lvl_small, lvl_big;  // n_levels+1 offsets into the schedules
+    int64_t gather_pairs = 0;
+    int64_t gather_hits = 0;
+    // algorithmic bytes of each level's launches, [0] float64 mode, [1] mixed
+    std::vector<double> lvl_bytes_small[2], lvl_bytes_big[2];
+};
+
+// Algorithmic bytes of one SelInv block: L(R_J, J) read as index + value
+// (12 B each), the h gathered Zhat entries (4 B index + w B value), the
+// float64 outputs in both triangles (16 B per entry), the float32 working
+// copy in mixed mode (4 B per entry) and Z(J, J).
+inline double selinv_block_bytes(int64_t c, int ncols, int64_t hits, bool fp64) {
+    const double w = fp64 ? 8.0 : 4.0;
+    return 12.0 * c * ncols + (4.0 + w) * hits + (fp64 ? 16.0 : 20.0) * c * ncols + 8.0 * ncols * ncols;
+}
+
+// Builds the analysis; returns 0 or an asi_status code with a message.
+int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, Analysis &out,
+            std::string &msg);
+
+}  // namespace asi

@@ -1,0 +1,98 @@
+// Kernel launch interface of libasi (host <-> device code of the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "asi_internal.h"
+
+namespace asi {
+
+// Device-side status codes latched into the workspace status word.
+enum : int32_t { ST_SINGULAR = 3, ST_NONFINITE = 4, ST_POOL = 6, ST_LIMIT = 8 };
+
+struct SelinvParams {
+    const int32_t *blocks;  // block starts of this launch
+    int32_t nblk;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const int64_t *diagpos;
+    const int64_t *mirror;
+    const int64_t *lsrc;
+    const int8_t *piv;
+    const double *Lval;
+    const double *dinv;
+    void *Zw;     // working off-diagonal values (double or float), S positions
+    double *out;  // float64 result on S
+    int same;     // Zw aliases out (float64 mode)
+    int32_t *status;
+};
+
+hipError_t launch_dinv(int32_t n, const int8_t *piv, const double *dd, const double *ds, double *dinv,
+                       int32_t *status, hipStream_t st);
+hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipStream_t st);
+hipError_t set_big_lds_limits();
+size_t selinv_big_lds_bytes(bool fp64);
+
+// NInv: columns of L^inv into a pool, then (L^inv)^T D^-1 L^inv on S.
+struct NinvParams {
+    int32_t n;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const int64_t *diagpos;
+    const int64_t *mirror;
+    const int64_t *lsrc;
+    const int8_t *piv;
+    const double *Lval;
+    const double *dinv;
+    int32_t p;
+    double delta;
+    // pool of L^inv columns: rows (int32), linv and w = D^-1 linv (float or double)
+    int32_t *prow;
+    void *plinv;
+    void *pw;
+    int64_t pool_cap;
+    unsigned long long *pool_top;  // allocation counter
+    int64_t *cstart;               // n
+    int32_t *clen;                 // n (-1: pending in the large-column pass)
+    int32_t *ovf_list;             // n
+    int32_t *ovf_count;            // 1
+    int32_t *ovf2_list;            // n (product pass overflow)
+    int32_t *ovf2_count;           // 1
+    double *out;                   // N on S (float64)
+    int32_t *status;
+};
+
+hipError_t launch_ninv(const NinvParams &P, bool fp64, hipStream_t st);
+
+hipError_t launch_zdiag(int32_t n, const int64_t *diagpos, const double *X, double *d, hipStream_t st);
+hipError_t launch_mix(int64_t nnz, const int32_t *srow, const int32_t *col, const double *zdiag,
+                      const double *Z, const double *N, double eps, double *M, hipStream_t st);
+hipError_t launch_lowrank(int32_t n, int32_t k, const int64_t *rowptr, const int32_t *col,
+                          const double *V, const double *lam, const double *in, double *out,
+                          hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st);
+
+struct SpaiParams {
+    int32_t n;
+    const int64_t *rowptr;  // S
+    const int32_t *col;
+    const int64_t *mirror;
+    const int64_t *A_rowptr;  // A in original order
+    const int32_t *A_col;
+    const double *A_val;
+    const int32_t *perm;
+    int32_t *iperm;  // workspace, n
+    double *colnorm2;  // workspace, n (||Ah(:, i)||^2 in factor order)
+    const double *M;
+    double *X;  // workspace, nnzS (column j of M' stored in row j)
+    double *R;
+    int32_t iters;
+    int32_t *status;
+};
+
+hipError_t launch_spai(const SpaiParams &P, hipStream_t st);
+hipError_t launch_symmetrize(int64_t nnz, const int64_t *mirror, const double *X, double *R, hipStream_t st);
+
+}  // namespace asi
