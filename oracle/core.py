@@ -201,10 +201,20 @@ def err1(d: np.ndarray, dhat: np.ndarray) -> float:
 
 
 def entry_error(S: Pattern, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
-    """Per-entry error |x_ij - y_ij| / sqrt(|y_ii y_jj|) on S (Y is the reference)."""
+    """Per-entry error |x_ij - y_ij| / sqrt(|y_ii y_jj|) on S (Y is the reference).
+
+    For indefinite inputs a diagonal entry of the inverse can vanish; the
+    scale is then max(sqrt(|y_ii y_jj|), |y_ij|), and 1 where both are zero
+    (the error becomes absolute). For SPD inputs |y_ij| <= sqrt(y_ii y_jj), so
+    the scale is the plain one.
+    """
+    X = np.asarray(X)
+    Y = np.asarray(Y)
     dy = diag(S, Y)
     r = S.rows()
-    return np.abs(np.asarray(X) - np.asarray(Y)) / np.sqrt(np.abs(dy[r] * dy[S.col]))
+    scale = np.maximum(np.sqrt(np.abs(dy[r] * dy[S.col])), np.abs(Y))
+    scale = np.where(scale > 0, scale, 1.0)
+    return np.abs(X - Y) / scale
 
 
 def permuted(A, perm) -> sp.csr_matrix:

@@ -127,8 +127,12 @@ class Solver:
         return t
 
     # -- symbolic ------------------------------------------------------------
-    def analyze(self, n, L_rowptr, L_col, piv, workspace_bytes=None):
-        """asi_analyze + asi_set_workspace (the workspace is a torch uint8 tensor)."""
+    def analyze(self, n, L_rowptr, L_col, piv, workspace_bytes=None, pool_entries=None):
+        """asi_analyze + asi_set_workspace (the workspace is a torch uint8 tensor).
+
+        ``pool_entries`` sizes the NInv pool (columns of L^inv, 20 bytes per
+        entry); by default the library's suggestion is used.
+        """
         rp = np.ascontiguousarray(L_rowptr, dtype=np.int64)
         cl = np.ascontiguousarray(L_col, dtype=np.int32)
         pv = np.ascontiguousarray(piv, dtype=np.int8)
@@ -140,6 +144,8 @@ class Solver:
                                          ctypes.byref(nnz), ctypes.byref(wsb)))
         self.n = int(n)
         self.nnz_S = int(nnz.value)
+        if workspace_bytes is None and pool_entries is not None:
+            workspace_bytes = self.info()["workspace_min"] + 20 * int(pool_entries) + 1024
         self.set_workspace(workspace_bytes or wsb.value)
         return self.nnz_S
 

@@ -80,7 +80,7 @@ def torch_mod():
 def _run(torch_mod, F, p, delta, eps, precision):
     from paper_2609_11363_amd import Solver, upload_factors
     s = Solver(0)
-    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv, pool_entries=F.n * min(F.n, 1024))
     Lv, dd, ds = upload_factors(F)
     Z = s.selinv(Lv, dd, ds, precision=precision)
     N = s.ninv(Lv, dd, ds, p=p, delta=delta, precision=precision)
