@@ -173,7 +173,8 @@ typedef enum {
     ASI_K_MIX = 4,           /* Mix selection (with its diagonal copy) */
     ASI_K_SPAI = 5,          /* SPAI refinement and symmetrisation */
     ASI_K_LOWRANK = 6,       /* rank-k correction on S */
-    ASI_K_COUNT = 7
+    ASI_K_GATHER = 7,        /* L values gathered into the column layout, once per call */
+    ASI_K_COUNT = 8
 } asi_kernel_class;
 asi_status asi_profile(asi_handle h, int enable);
 asi_status asi_profile_read(asi_handle h, int32_t kernel_class, int64_t *launches, double *total_ms,

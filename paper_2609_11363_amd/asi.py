@@ -26,7 +26,7 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
            "asi_profile_read"]
 KERNEL_CLASSES = {"dinv": 0, "selinv": 1, "selinv_big": 2, "ninv": 3, "mix": 4, "spai": 5,
-                  "lowrank": 6}
+                  "lowrank": 6, "gather_l": 7}
 
 
 class AsiError(RuntimeError):

@@ -7,6 +7,7 @@
 // Block J depends on every block that holds a row of R_J (its Z(R_J, R_J)
 // entries, Section 2.1), which gives the level schedule.
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <numeric>
 
@@ -119,7 +120,6 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
     A.srow.resize(A.nnzS);
     A.diagpos.resize(n);
     A.mirror.assign(A.nnzS, -1);
-    A.lsrc.assign(A.nnzS, -1);
     for (int32_t i = 0; i < n; ++i) {
         A.diagpos[i] = A.rowptr[i] + lowcnt[i + 1];
         A.col[A.diagpos[i]] = i;
@@ -141,23 +141,37 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
                 A.mirror[p] = d;
             }
     }
-    // L source of each upper position (j, r): L(r, j), found by a merge of
-    // the (sorted) upper row j with the (sorted) column j of L
+    // u-space: the upper part of each row, with the L source of every entry
+    // (a merge of the sorted upper row j with the sorted column j of L)
+    A.ustart.assign(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) A.ustart[i + 1] = A.ustart[i] + (A.rowptr[i + 1] - A.diagpos[i] - 1);
+    A.nnzU = A.ustart[n];
+    A.ucol.resize(A.nnzU);
+    A.lsrc_u.assign(A.nnzU, -1);
+    A.mirror_u.resize(A.nnzU);
+    A.useg_u.resize(A.nnzU);
     for (int32_t j = 0; j < n; ++j) {
-        int64_t p = A.diagpos[j] + 1, pe = A.rowptr[j + 1];
+        const int64_t p0 = A.diagpos[j] + 1, u0 = A.ustart[j];
+        for (int64_t u = u0; u < A.ustart[j + 1]; ++u) {
+            int64_t p = p0 + (u - u0);
+            A.ucol[u] = A.col[p];
+            A.mirror_u[u] = A.mirror[p];
+        }
+        int64_t p = u0, pe = A.ustart[j + 1];
         int64_t q = cp[j], qe = cp[j + 1];
         while (p < pe && q < qe) {
-            if (A.col[p] == crow[q]) {
-                A.lsrc[p] = csrc[q];
+            if (A.ucol[p] == crow[q]) {
+                A.lsrc_u[p] = csrc[q];
                 ++p;
                 ++q;
-            } else if (A.col[p] < crow[q]) {
+            } else if (A.ucol[p] < crow[q]) {
                 ++p;
             } else {
                 ++q;
             }
         }
     }
+    for (int64_t u = 0; u < A.nnzU; ++u) A.useg_u[u] = A.ustart[A.ucol[u]];
 
     // blocks, levels and work counts
     A.level.assign(n, 0);
@@ -195,6 +209,41 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
     if (A.max_cols > kBigCols) {
         msg = "a block has more than 2048 rows below it (|R_J| limit)";
         return E_UNSUPPORTED;
+    }
+    // hit lists, blocks in increasing start index
+    {
+        int64_t words = 0;
+        for (int32_t j : blocks) words += bhits[j] * (bcols[j] <= kSmallCols ? 1 : 2);
+        A.hits.resize(words);
+        A.hit_ptr.assign(n + 1, 0);
+        std::vector<int32_t> pos(n, -1);
+        int64_t w = 0;
+        for (int32_t j : blocks) {
+            const int32_t last = piv[j] == 1 ? j + 1 : j;
+            const int64_t ub = A.ustart[last], ue = A.ustart[last + 1];
+            const int32_t c = (int32_t)(ue - ub);
+            const bool small = c <= kSmallCols;
+            A.hit_ptr[j] = w;
+            for (int32_t t = 0; t < c; ++t) pos[A.ucol[ub + t]] = t;
+            for (int32_t b = 0; b < c; ++b) {
+                const int32_t l = A.ucol[ub + b];
+                const int64_t s0 = A.ustart[l], s1 = A.ustart[l + 1];
+                for (int64_t q = s0; q < s1; ++q) {
+                    const int32_t a = pos[A.ucol[q]];
+                    if (a < 0) continue;
+                    const uint32_t off = (uint32_t)(q - s0);
+                    if (small) {
+                        A.hits[w++] = (uint32_t)a | ((uint32_t)b << 7) | (off << 14);
+                    } else {
+                        A.hits[w++] = (uint32_t)a | ((uint32_t)b << 16);
+                        A.hits[w++] = off;
+                    }
+                }
+            }
+            for (int32_t t = 0; t < c; ++t) pos[A.ucol[ub + t]] = -1;
+            A.hit_ptr[j + 1] = w;
+            if (last != j) A.hit_ptr[last + 1] = w;
+        }
     }
     // level-major schedules (blocks in increasing start index within a level)
     std::vector<int32_t> cs(A.n_levels + 1, 0), cb(A.n_levels + 1, 0);

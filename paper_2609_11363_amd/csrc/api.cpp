@@ -28,13 +28,21 @@ struct asi_handle_s {
     int32_t *srow = nullptr;
     int64_t *diagpos = nullptr;
     int64_t *mirror = nullptr;
-    int64_t *lsrc = nullptr;
+    int64_t *ustart = nullptr;
+    int32_t *ucol = nullptr;
+    int64_t *lsrc_u = nullptr;
+    int64_t *mirror_u = nullptr;
+    int64_t *useg = nullptr;
+    int64_t *hit_ptr = nullptr;
+    uint32_t *hits = nullptr;
+    void *Lu = nullptr;
+    void *Zu = nullptr;
+    double *zd = nullptr;
     int8_t *piv = nullptr;
     int32_t *level = nullptr;
     int32_t *sched_small = nullptr;
     int32_t *sched_big = nullptr;
     double *dinv = nullptr;
-    float *zw32 = nullptr;
     double *zdiag = nullptr;
     int32_t *status = nullptr;
     int64_t *cstart = nullptr;
@@ -103,21 +111,21 @@ struct Layout {
 };
 
 Layout make_layout(const asi::Analysis &A) {
-    const size_t n = (size_t)A.n, s = (size_t)A.nnzS;
+    const size_t n = (size_t)A.n, s = (size_t)A.nnzS, u = (size_t)A.nnzU;
     Layout L;
     L.add((n + 1) * 8);                 // 0 rowptr
     L.add(s * 4);                       // 1 col
     L.add(s * 4);                       // 2 srow
     L.add(n * 8);                       // 3 diagpos
     L.add(s * 8);                       // 4 mirror
-    L.add(s * 8);                       // 5 lsrc
+    L.add((n + 1) * 8);                 // 5 ustart
     L.add(n);                           // 6 piv
     L.add(n * 4);                       // 7 level
     L.add(A.sched_small.size() * 4);    // 8
     L.add(A.sched_big.size() * 4);      // 9
     L.add(3 * n * 8);                   // 10 dinv
-    L.add(s * 4);                       // 11 zw32
-    L.add(n * 8);                       // 12 zdiag
+    L.add(u * 4);                       // 11 ucol
+    L.add(n * 8);                       // 12 zdiag (Mix)
     L.add(256);                         // 13 status + counters + pool_top
     L.add(n * 8);                       // 14 cstart
     L.add(n * 4);                       // 15 clen
@@ -126,6 +134,14 @@ Layout make_layout(const asi::Analysis &A) {
     L.add(n * 4);                       // 18 iperm
     L.add(n * 8);                       // 19 cn2
     L.add(s * 8);                       // 20 X
+    L.add(u * 8);                       // 21 lsrc_u
+    L.add(u * 8);                       // 22 mirror_u
+    L.add(u * 8);                       // 23 useg
+    L.add((n + 1) * 8);                 // 24 hit_ptr
+    L.add(u * 8);                       // 25 Lu
+    L.add(u * 8);                       // 26 Zu
+    L.add(n * 8);                       // 27 zd (SelInv diagonal)
+    L.add(A.hits.size() * 4);           // 28 hits
     return L;
 }
 
@@ -257,13 +273,13 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->srow = at<int32_t>(b, L.off[2]);
     h->diagpos = at<int64_t>(b, L.off[3]);
     h->mirror = at<int64_t>(b, L.off[4]);
-    h->lsrc = at<int64_t>(b, L.off[5]);
+    h->ustart = at<int64_t>(b, L.off[5]);
     h->piv = at<int8_t>(b, L.off[6]);
     h->level = at<int32_t>(b, L.off[7]);
     h->sched_small = at<int32_t>(b, L.off[8]);
     h->sched_big = at<int32_t>(b, L.off[9]);
     h->dinv = at<double>(b, L.off[10]);
-    h->zw32 = at<float>(b, L.off[11]);
+    h->ucol = at<int32_t>(b, L.off[11]);
     h->zdiag = at<double>(b, L.off[12]);
     h->status = at<int32_t>(b, L.off[13]);
     h->counters = h->status + 4;
@@ -275,6 +291,14 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->iperm = at<int32_t>(b, L.off[18]);
     h->cn2 = at<double>(b, L.off[19]);
     h->X = at<double>(b, L.off[20]);
+    h->lsrc_u = at<int64_t>(b, L.off[21]);
+    h->mirror_u = at<int64_t>(b, L.off[22]);
+    h->useg = at<int64_t>(b, L.off[23]);
+    h->hit_ptr = at<int64_t>(b, L.off[24]);
+    h->Lu = b + L.off[25];
+    h->Zu = b + L.off[26];
+    h->zd = at<double>(b, L.off[27]);
+    h->hits = at<uint32_t>(b, L.off[28]);
     // pool: rows | linv | w, each region 256-aligned
     size_t rest = bytes - L.cur - 3 * 256;
     int64_t cap = (int64_t)(rest / kPoolEntryBytes);
@@ -296,7 +320,13 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
         {h->srow, A.srow.data(), A.srow.size() * 4},
         {h->diagpos, A.diagpos.data(), A.diagpos.size() * 8},
         {h->mirror, A.mirror.data(), A.mirror.size() * 8},
-        {h->lsrc, A.lsrc.data(), A.lsrc.size() * 8},
+        {h->ustart, A.ustart.data(), A.ustart.size() * 8},
+        {h->ucol, A.ucol.data(), A.ucol.size() * 4},
+        {h->lsrc_u, A.lsrc_u.data(), A.lsrc_u.size() * 8},
+        {h->mirror_u, A.mirror_u.data(), A.mirror_u.size() * 8},
+        {h->useg, A.useg_u.data(), A.useg_u.size() * 8},
+        {h->hit_ptr, A.hit_ptr.data(), A.hit_ptr.size() * 8},
+        {h->hits, A.hits.data(), A.hits.size() * 4},
         {h->piv, A.piv.data(), A.piv.size()},
         {h->level, A.level.data(), A.level.size() * 4},
         {h->sched_small, A.sched_small.data(), A.sched_small.size() * 4},
@@ -365,32 +395,39 @@ asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, c
     if (e != hipSuccess) return hip_fail(h, e, "dinv");
     const bool fp64 = prec == ASI_FP64;
     const int m = fp64 ? 0 : 1;
+    {
+        Trace t(h, ASI_K_GATHER, 24.0 * A.nnzU);
+        e = asi::launch_gather_lu(A.nnzU, h->lsrc_u, L_val, h->Lu, fp64, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "gather L");
     asi::SelinvParams P{};
-    P.rowptr = h->rowptr;
-    P.col = h->col;
+    P.ustart = h->ustart;
+    P.ucol = h->ucol;
+    P.useg = h->useg;
+    P.hit_ptr = h->hit_ptr;
+    P.hits = h->hits;
+    P.mirror_u = h->mirror_u;
     P.diagpos = h->diagpos;
-    P.mirror = h->mirror;
-    P.lsrc = h->lsrc;
     P.piv = h->piv;
-    P.Lval = L_val;
+    P.Lu = h->Lu;
     P.dinv = h->dinv;
-    P.Zw = fp64 ? static_cast<void *>(Z_S) : static_cast<void *>(h->zw32);
+    P.Zu = h->Zu;
+    P.zdiag = h->zd;
     P.out = Z_S;
-    P.same = fp64 ? 1 : 0;
     P.status = h->status;
     for (int32_t l = 0; l < A.n_levels; ++l) {
         P.blocks = h->sched_small + A.lvl_small[l];
         P.nblk = A.lvl_small[l + 1] - A.lvl_small[l];
         if (P.nblk > 0) {
             Trace t(h, ASI_K_SELINV, A.lvl_bytes_small[m][l]);
-            e = asi::launch_selinv_level(P, false, fp64, h->stream);
+            e = asi::launch_selinv_level(P, false, fp64, h->stream, asi::small_group_size(P.nblk));
             if (e != hipSuccess) return hip_fail(h, e, "selinv level");
         }
         P.blocks = h->sched_big + A.lvl_big[l];
         P.nblk = A.lvl_big[l + 1] - A.lvl_big[l];
         if (P.nblk > 0) {
             Trace t(h, ASI_K_SELINV_BIG, A.lvl_bytes_big[m][l]);
-            e = asi::launch_selinv_level(P, true, fp64, h->stream);
+            e = asi::launch_selinv_level(P, true, fp64, h->stream, 256);
             if (e != hipSuccess) return hip_fail(h, e, "selinv level (large blocks)");
         }
     }
@@ -413,15 +450,22 @@ asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, con
         e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
     }
     if (e != hipSuccess) return hip_fail(h, e, "dinv");
+    const bool fp64 = prec == ASI_FP64;
+    {
+        Trace t(h, ASI_K_GATHER, 24.0 * A.nnzU);
+        e = asi::launch_gather_lu(A.nnzU, h->lsrc_u, L_val, h->Lu, fp64, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "gather L");
     asi::NinvParams P{};
     P.n = A.n;
     P.rowptr = h->rowptr;
     P.col = h->col;
     P.diagpos = h->diagpos;
     P.mirror = h->mirror;
-    P.lsrc = h->lsrc;
+    P.ustart = h->ustart;
+    P.ucol = h->ucol;
     P.piv = h->piv;
-    P.Lval = L_val;
+    P.Lu = h->Lu;
     P.dinv = h->dinv;
     P.p = p;
     P.delta = delta;
@@ -440,7 +484,7 @@ asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, con
     P.status = h->status;
     {
         Trace t(h, ASI_K_NINV, 0.0);
-        e = asi::launch_ninv(P, prec == ASI_FP64, h->stream);
+        e = asi::launch_ninv(P, fp64, h->stream);
     }
     if (e != hipSuccess) return hip_fail(h, e, "ninv");
     return ASI_OK;

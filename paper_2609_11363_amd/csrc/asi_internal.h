@@ -25,8 +25,22 @@ struct Analysis {
     std::vector<int32_t> srow;     // nnzS: row of each position
     std::vector<int64_t> diagpos;  // n: position of (i, i)
     std::vector<int64_t> mirror;   // nnzS: position of (j, i) for (i, j)
-    std::vector<int64_t> lsrc;     // nnzS: for an upper position (j, r) the index of L(r, j)
-                                   //       in the input L arrays, -1 when L(r, j) is not stored
+    // Upper triangle of S by rows ("u-space", the columns of L): the u-range of
+    // row j is [ustart[j], ustart[j+1]) and holds R_J (after (j, j+1) when j
+    // starts a 2x2 block).
+    int64_t nnzU = 0;
+    std::vector<int64_t> ustart;   // n+1
+    std::vector<int32_t> ucol;     // nnzU: column r of the upper entry (j, r)
+    std::vector<int64_t> lsrc_u;   // nnzU: index of L(r, j) in the input L arrays, -1 if absent
+    std::vector<int64_t> mirror_u; // nnzU: S position of the lower entry (r, j)
+    std::vector<int64_t> useg_u;   // nnzU: ustart[r], start of row r's u-range (gather segment)
+    // Hit lists of the SelInv gathers: for block J, every pair (r, l) in
+    // R_J x R_J with r > l and (r, l) in S, as (a, b, off) with r = R_J[a],
+    // l = R_J[b] and Z(r, l) at u-index ustart[l] + off, sorted by b then off.
+    // Blocks with |R_J| <= kSmallCols use one word per hit,
+    // a | b << 7 | off << 14; larger blocks use two, a | b << 16 and off.
+    std::vector<int64_t> hit_ptr;  // n+1: words of block J are [hit_ptr[J], hit_ptr[J+1])
+    std::vector<uint32_t> hits;
     std::vector<int8_t> piv;       // n
     std::vector<int32_t> level;    // n: DAG level of each unknown's block
     int32_t n_blocks = 0;
@@ -48,6 +62,18 @@ struct Analysis {
 inline double selinv_block_bytes(int64_t c, int ncols, int64_t hits, bool fp64) {
     const double w = fp64 ? 8.0 : 4.0;
     return 12.0 * c * ncols + (4.0 + w) * hits + (fp64 ? 16.0 : 20.0) * c * ncols + 8.0 * ncols * ncols;
+}
+
+// Threads per block for a level of nblk blocks with |R_J| <= kSmallCols:
+// enough lanes per block that the level keeps about 6144 wavefronts (256 CUs,
+// 24 resident wavefronts each) busy, from one wavefront up to a 512-thread
+// workgroup per block.
+inline int small_group_size(int64_t nblk) {
+    const int64_t waves = 6144;
+    if (nblk * 2 > waves) return 64;
+    if (nblk * 4 > waves) return 128;
+    if (nblk * 8 > waves) return 256;
+    return 512;
 }
 
 // Builds the analysis; returns 0 or an asi_status code with a message.

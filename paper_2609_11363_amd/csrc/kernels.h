@@ -15,23 +15,29 @@ enum : int32_t { ST_SINGULAR = 3, ST_NONFINITE = 4, ST_POOL = 6, ST_LIMIT = 8 };
 struct SelinvParams {
     const int32_t *blocks;  // block starts of this launch
     int32_t nblk;
-    const int64_t *rowptr;
-    const int32_t *col;
-    const int64_t *diagpos;
-    const int64_t *mirror;
-    const int64_t *lsrc;
-    const int8_t *piv;
-    const double *Lval;
-    const double *dinv;
-    void *Zw;     // working off-diagonal values (double or float), S positions
-    double *out;  // float64 result on S
-    int same;     // Zw aliases out (float64 mode)
+    const int64_t *ustart;   // n+1
+    const int32_t *ucol;     // nnzU
+    const int64_t *useg;     // nnzU
+    const int64_t *hit_ptr;  // n+1
+    const uint32_t *hits;    // hit records (see the analysis)
+    const int64_t *mirror_u; // nnzU
+    const int64_t *diagpos;  // n
+    const int8_t *piv;       // n
+    const void *Lu;          // nnzU, L values in u-space (double or float)
+    const double *dinv;      // 3n
+    void *Zu;                // nnzU, working off-diagonal Z in u-space (double or float)
+    double *zdiag;           // n, float64 diagonal of Z
+    double *out;             // |S|, float64 result
     int32_t *status;
 };
 
 hipError_t launch_dinv(int32_t n, const int8_t *piv, const double *dd, const double *ds, double *dinv,
                        int32_t *status, hipStream_t st);
-hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipStream_t st);
+// group: threads per block for |R_J| <= kSmallCols (64 = one wavefront per
+// block, four blocks per workgroup; 128, 256 or 512 = one workgroup per block)
+hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipStream_t st, int group);
+hipError_t launch_gather_lu(int64_t nnzU, const int64_t *lsrc_u, const double *Lval, void *Lu, bool fp64,
+                            hipStream_t st);
 hipError_t set_big_lds_limits();
 size_t selinv_big_lds_bytes(bool fp64);
 
@@ -42,9 +48,10 @@ struct NinvParams {
     const int32_t *col;
     const int64_t *diagpos;
     const int64_t *mirror;
-    const int64_t *lsrc;
+    const int64_t *ustart;
+    const int32_t *ucol;
     const int8_t *piv;
-    const double *Lval;
+    const void *Lu;  // u-space L values (double or float)
     const double *dinv;
     int32_t p;
     double delta;

@@ -1,14 +1,17 @@
 // HIP kernels of libasi for gfx950 (CDNA4, 64-wide wavefronts).
 //
-// Data layout in HBM (all indexed by positions of S's CSR, both triangles):
-//   col[p], srow[p]     column / row of position p
-//   diagpos[i]          position of (i, i)
-//   mirror[p]           position of the transposed entry
-//   lsrc[p]             for an upper position (j, r): index of L(r, j) in the
-//                       caller's L arrays, -1 if not stored
-// The upper part of row `last(J)` is R_J, so Z's lower triangle by columns is
-// read straight from the output array: a gather of column l of Z is a
-// contiguous, coalesced read of row l's upper segment.
+// Data layout in HBM. Results live on S's CSR (both triangles; positions p).
+// The sweep works in "u-space", the upper triangle of S stored by rows, which
+// is the lower triangle of Z stored by columns (the layout of L's columns):
+//   ustart[j]           first u-index of row j (its entries are R_J, preceded
+//                       by (j, j+1) when j starts a 2x2 block)
+//   ucol[u]             column r of the upper entry u = (j, r)
+//   useg[u]             start of row r's u-range (the gather segment of r)
+//   hit_ptr, hits       per block, the pairs (r, l) in R_J x R_J found in S,
+//                       precomputed as (a, b, offset in l's u-range)
+//   mirror_u[u]         S position of the lower entry (r, j)
+//   Lu[u], Zu[u]        L(r, j) and Z(r, j) in the working precision
+// A gather of column l of Z is a contiguous, coalesced read of l's u-range.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -57,6 +60,27 @@ __device__ inline int seg_of(const int32_t *off, int c, int32_t t) {
             hi = mid - 1;
     }
     return lo;
+}
+
+// Sum of v over the lanes of this wavefront that carry the same key k as the
+// calling lane and sit at or after it; keys must be nondecreasing across
+// lanes. The first lane of each key run receives the run's total.
+template <typename V>
+__device__ inline V seg_suffix_sum(V v, int32_t k) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        V vo = __shfl_down(v, o, 64);
+        int32_t ko = __shfl_down(k, o, 64);
+        if (lane + o < 64 && ko == k) v += vo;
+    }
+    return v;
+}
+
+__device__ inline bool run_head(int32_t k) {
+    const int lane = lane_id();
+    int32_t kp = __shfl_up(k, 1, 64);
+    return lane == 0 || kp != k;
 }
 
 // index of r in sorted R[lo..hi], or -1
@@ -109,21 +133,23 @@ __global__ void k_dinv(int32_t n, const int8_t *__restrict__ piv, const double *
 // ---------------------------------------------------------------------------
 // SelInv block: Z(R_J, J) = -Zhat(R_J, R_J) L(R_J, J),
 //               Z(J, J)   = D_J^-1 - L(R_J, J)^T Z(R_J, J).
-// The pairs (r, l) in R_J x R_J with r > l and (r, l) in S are found by
-// scanning row l's upper segment (contiguous) for every l in R_J and looking
-// each column up in R_J (binary search in LDS). Each hit feeds two outputs:
-// y_r += z L_lJ (scatter half, LDS atomic) and y_l += z L_rJ (LDS atomic).
+// Zhat(R_J, R_J) restricted to S is read through the block's precomputed hit
+// list: each hit (a, b, off) is the entry Z(r, l) with r = R_J[a] > l = R_J[b],
+// stored at u-index ustart[l] + off, and feeds two outputs,
+// y_a += z L(l, J) (scatter half, LDS atomics on distinct targets) and
+// y_b += z L(r, J) (dot half: hits are sorted by b, so a segmented wavefront
+// sum leaves one atomic per run). Each lane keeps kUnroll hits in flight.
 // T is the working precision of the off-diagonal values and their
 // accumulation; D^-1 and Z(J, J) stay in float64.
+constexpr int kUnroll = 4;
+
 template <typename T>
 struct SelinvLds {
-    int32_t *R;
     T *l0, *l1, *y0, *y1;
-    int32_t *off;  // c + 1
-    int64_t *seg;  // c
+    int64_t *seg;  // c: u-range start of R_J[b]
 };
 
-template <typename T, int G>
+template <int G>
 __device__ inline void group_sync() {
     if constexpr (G == 64)
         wave_sync();
@@ -131,82 +157,118 @@ __device__ inline void group_sync() {
         __syncthreads();
 }
 
-template <typename T, int G>
+template <typename T, int G, int NT, bool WIDE>
 __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T> &S, int tid,
-                             double *red /* G == 256: 4 waves x 4 partial sums */) {
+                             double *red /* G > 64: (G / 64) waves x 4 partial sums */) {
     const bool two = P.piv[j] == 1;
     const int32_t last = two ? j + 1 : j;
-    const int64_t u0 = P.diagpos[last] + 1;
-    const int32_t c = (int32_t)(P.rowptr[last + 1] - u0);
-    const int64_t u0j = two ? P.diagpos[j] + 2 : u0;  // L(R_J, j) in row j
-    T *Zw = reinterpret_cast<T *>(P.Zw);
+    const int64_t ub = P.ustart[last];
+    const int32_t c = (int32_t)(P.ustart[last + 1] - ub);
+    const int64_t ubj = two ? P.ustart[j] + 1 : ub;  // L(R_J, j) in row j's u-range
+    const T *Lu = reinterpret_cast<const T *>(P.Lu);
+    T *Zu = reinterpret_cast<T *>(P.Zu);
+    const int64_t pdl = P.diagpos[last] + 1;  // S position of row last's first upper entry
+    const int64_t pdj = two ? P.diagpos[j] + 2 : pdl;
+    const int64_t h0 = P.hit_ptr[j];
+    const int32_t nwords = (int32_t)(P.hit_ptr[last + 1] - h0);
+    const int32_t total = WIDE ? nwords / 2 : nwords;
 
-    // stage R_J, L(R_J, J), the gather segments and the diagonal terms
-    for (int t = tid; t < c; t += G) {
-        int32_t r = P.col[u0 + t];
-        S.R[t] = r;
-        int64_t s0 = P.lsrc[u0j + t];
-        T v0 = s0 >= 0 ? (T)P.Lval[s0] : T(0);
-        S.l0[t] = v0;
-        T v1 = T(0);
-        if (two) {
-            int64_t s1 = P.lsrc[u0 + t];
-            v1 = s1 >= 0 ? (T)P.Lval[s1] : T(0);
-            S.l1[t] = v1;
+    // stage L(R_J, J), the gather segments and the diagonal terms; the
+    // mirror positions of the outputs stay in registers
+    int64_t mir0[NT], mir1[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const int t = tid + k * G;
+        mir0[k] = mir1[k] = -1;
+        if (t < c) {
+            int32_t r = P.ucol[ub + t];
+            int64_t sg = P.useg[ub + t];
+            T v0 = Lu[ubj + t];
+            T v1 = two ? Lu[ub + t] : T(0);
+            mir0[k] = P.mirror_u[ubj + t];
+            if (two) mir1[k] = P.mirror_u[ub + t];
+            S.seg[t] = sg;
+            S.l0[t] = v0;
+            if (two) S.l1[t] = v1;
+            T zll = (T)P.zdiag[r];
+            S.y0[t] = -zll * v0;
+            if (two) S.y1[t] = -zll * v1;
         }
-        int64_t d = P.diagpos[r];
-        S.seg[t] = d + 1;
-        S.off[t + 1] = (int32_t)(P.rowptr[r + 1] - d - 1);
-        T zll = (T)P.out[d];
-        S.y0[t] = -zll * v0;
-        if (two) S.y1[t] = -zll * v1;
     }
-    group_sync<T, G>();
-    // exclusive offsets of the segment lengths (one wavefront scans)
-    if (tid < 64) {
-        int32_t carry = 0;
-        for (int base = 0; base < c; base += 64) {
-            int t = base + tid;
-            int32_t v = t < c ? S.off[t + 1] : 0;
-            int32_t s = wave_incl_scan(v) + carry;
-            if (t < c) S.off[t + 1] = s;
-            carry = __shfl(s, 63, 64);
+    group_sync<G>();
+    const uint32_t *H = P.hits + h0;
+    // loop bound uniform across the group so every lane joins the shuffles
+    for (int32_t base0 = 0; base0 < total; base0 += G * kUnroll) {
+        const int32_t base = base0 + tid;
+        int32_t a[kUnroll], b[kUnroll];
+        uint32_t w0[kUnroll], w1[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int32_t t = base + u * G;
+            b[u] = -1;
+            if (t < total) {
+                if (WIDE) {
+                    w0[u] = H[2 * t];
+                    w1[u] = H[2 * t + 1];
+                } else {
+                    w0[u] = H[t];
+                }
+            }
         }
-        if (tid == 0) S.off[0] = 0;
-    }
-    group_sync<T, G>();
-    const int32_t total = c > 0 ? S.off[c] : 0;
-    for (int32_t t = tid; t < total; t += G) {
-        int b = seg_of(S.off, c, t);
-        int64_t p = S.seg[b] + (t - S.off[b]);
-        int32_t r = P.col[p];
-        int a = find_sorted(S.R, b + 1, c - 1, r);
-        if (a >= 0) {
-            T z = Zw[p];
-            atomicAdd(&S.y0[a], -z * S.l0[b]);
-            atomicAdd(&S.y0[b], -z * S.l0[a]);
-            if (two) {
-                atomicAdd(&S.y1[a], -z * S.l1[b]);
-                atomicAdd(&S.y1[b], -z * S.l1[a]);
+        T z[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int32_t t = base + u * G;
+            if (t < total) {
+                int64_t off;
+                if (WIDE) {
+                    a[u] = (int32_t)(w0[u] & 0xffffu);
+                    b[u] = (int32_t)(w0[u] >> 16);
+                    off = (int64_t)w1[u];
+                } else {
+                    a[u] = (int32_t)(w0[u] & 0x7fu);
+                    b[u] = (int32_t)((w0[u] >> 7) & 0x7fu);
+                    off = (int64_t)(w0[u] >> 14);
+                }
+                z[u] = Zu[S.seg[b[u]] + off];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            T dot0 = T(0), dot1 = T(0);
+            if (b[u] >= 0) {
+                atomicAdd(&S.y0[a[u]], -z[u] * S.l0[b[u]]);
+                dot0 = -z[u] * S.l0[a[u]];
+                if (two) {
+                    atomicAdd(&S.y1[a[u]], -z[u] * S.l1[b[u]]);
+                    dot1 = -z[u] * S.l1[a[u]];
+                }
+            }
+            dot0 = seg_suffix_sum(dot0, b[u]);
+            if (two) dot1 = seg_suffix_sum(dot1, b[u]);
+            if (b[u] >= 0 && run_head(b[u])) {
+                atomicAdd(&S.y0[b[u]], dot0);
+                if (two) atomicAdd(&S.y1[b[u]], dot1);
             }
         }
     }
-    group_sync<T, G>();
+    group_sync<G>();
     double d00 = 0.0, d11 = 0.0, d10 = 0.0, d01 = 0.0;
-    for (int t = tid; t < c; t += G) {
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const int t = tid + k * G;
+        if (t >= c) continue;
         T y0 = S.y0[t];
-        int64_t pu = u0j + t;
-        if (!P.same) Zw[pu] = y0;
-        P.out[pu] = (double)y0;
-        P.out[P.mirror[pu]] = (double)y0;
+        Zu[ubj + t] = y0;
+        P.out[pdj + t] = (double)y0;
+        P.out[mir0[k]] = (double)y0;
         double l0 = (double)S.l0[t];
         d00 += l0 * (double)y0;
         if (two) {
             T y1 = S.y1[t];
-            int64_t pu1 = u0 + t;
-            if (!P.same) Zw[pu1] = y1;
-            P.out[pu1] = (double)y1;
-            P.out[P.mirror[pu1]] = (double)y1;
+            Zu[ub + t] = y1;
+            P.out[pdl + t] = (double)y1;
+            P.out[mir1[k]] = (double)y1;
             double l1 = (double)S.l1[t];
             d11 += l1 * (double)y1;
             d10 += l1 * (double)y0;
@@ -214,9 +276,11 @@ __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T
         }
     }
     d00 = wave_sum(d00);
-    d11 = wave_sum(d11);
-    d10 = wave_sum(d10);
-    d01 = wave_sum(d01);
+    if (two) {
+        d11 = wave_sum(d11);
+        d10 = wave_sum(d10);
+        d01 = wave_sum(d01);
+    }
     if constexpr (G > 64) {
         const int w = tid >> 6;
         if ((tid & 63) == 0) {
@@ -227,26 +291,27 @@ __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T
         }
         __syncthreads();
         d00 = d11 = d10 = d01 = 0.0;
-        for (int q = 0; q < G / 64; ++q) {
-            d00 += red[4 * q + 0];
-            d11 += red[4 * q + 1];
-            d10 += red[4 * q + 2];
-            d01 += red[4 * q + 3];
+        for (int q2 = 0; q2 < G / 64; ++q2) {
+            d00 += red[4 * q2 + 0];
+            d11 += red[4 * q2 + 1];
+            d10 += red[4 * q2 + 2];
+            d01 += red[4 * q2 + 3];
         }
     }
     if (tid == 0) {
         const double *iv = P.dinv + 3 * (int64_t)j;
         double zjj = iv[0] - d00;
         P.out[P.diagpos[j]] = zjj;
+        P.zdiag[j] = zjj;
         bool bad = !isfinite(zjj);
         if (two) {
             double z11 = iv[2] - d11;
             double off = iv[1] - 0.5 * (d10 + d01);
             P.out[P.diagpos[last]] = z11;
-            int64_t pjl = P.diagpos[j] + 1;  // (j, j+1), an upper position read by gathers
-            P.out[pjl] = off;
+            P.zdiag[last] = z11;
+            P.out[P.diagpos[j] + 1] = off;
             P.out[P.diagpos[last] - 1] = off;
-            if (!P.same) Zw[pjl] = (T)off;
+            Zu[P.ustart[j]] = (T)off;  // (j, j+1), read by later gathers
             bad = bad || !isfinite(z11) || !isfinite(off);
         }
         if (bad) latch(P.status, 4);
@@ -255,42 +320,61 @@ __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T
 
 template <typename T, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_selinv_small(SelinvParams P) {
-    __shared__ int32_t sR[WAVES][kSmallCols];
     __shared__ T sL0[WAVES][kSmallCols], sL1[WAVES][kSmallCols];
     __shared__ T sY0[WAVES][kSmallCols], sY1[WAVES][kSmallCols];
-    __shared__ int32_t sOff[WAVES][kSmallCols + 1];
     __shared__ int64_t sSeg[WAVES][kSmallCols];
     const int w = threadIdx.x >> 6;
     const int32_t bi = blockIdx.x * WAVES + w;
     if (bi >= P.nblk) return;  // the whole wavefront leaves; no workgroup barrier follows
-    SelinvLds<T> S{sR[w], sL0[w], sL1[w], sY0[w], sY1[w], sOff[w], sSeg[w]};
-    selinv_block<T, 64>(P, P.blocks[bi], S, lane_id(), nullptr);
+    SelinvLds<T> S{sL0[w], sL1[w], sY0[w], sY1[w], sSeg[w]};
+    selinv_block<T, 64, kSmallCols / 64, false>(P, P.blocks[bi], S, lane_id(), nullptr);
+}
+
+// one workgroup of G threads per block (|R_J| <= kSmallCols), for levels with
+// few blocks
+template <typename T, int G>
+__global__ __launch_bounds__(G) void k_selinv_group(SelinvParams P) {
+    __shared__ T sL0[kSmallCols], sL1[kSmallCols];
+    __shared__ T sY0[kSmallCols], sY1[kSmallCols];
+    __shared__ int64_t sSeg[kSmallCols];
+    __shared__ double red[4 * (G / 64)];
+    const int32_t bi = blockIdx.x;
+    if (bi >= P.nblk) return;
+    SelinvLds<T> S{sL0, sL1, sY0, sY1, sSeg};
+    selinv_block<T, G, (kSmallCols + G - 1) / G, false>(P, P.blocks[bi], S, threadIdx.x, red);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_selinv_big(SelinvParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
-    // layout: seg (int64, C) | l0, l1, y0, y1 (T, C each) | R (int32, C) | off (int32, C+1) | red
+    // layout: red (16 doubles) | seg (int64, C) | l0, l1, y0, y1 (T, C each)
     const int C = kBigCols;
-    int64_t *seg = reinterpret_cast<int64_t *>(smem);
+    double *red = reinterpret_cast<double *>(smem);
+    int64_t *seg = reinterpret_cast<int64_t *>(red + 16);
     T *l0 = reinterpret_cast<T *>(seg + C);
     T *l1 = l0 + C;
     T *y0 = l1 + C;
     T *y1 = y0 + C;
-    int32_t *R = reinterpret_cast<int32_t *>(y1 + C);
-    int32_t *off = R + C;
-    double *red = reinterpret_cast<double *>(off + C + 2);
     const int32_t bi = blockIdx.x;
     if (bi >= P.nblk) return;
-    SelinvLds<T> S{R, l0, l1, y0, y1, off, seg};
-    selinv_block<T, 256>(P, P.blocks[bi], S, threadIdx.x, red);
+    SelinvLds<T> S{l0, l1, y0, y1, seg};
+    selinv_block<T, 256, kBigCols / 256, true>(P, P.blocks[bi], S, threadIdx.x, red);
+}
+
+template <typename T>
+__global__ void k_gather_lu(int64_t nnzU, const int64_t *__restrict__ lsrc_u, const double *__restrict__ Lval,
+                            T *__restrict__ Lu) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nnzU) return;
+    int64_t s = lsrc_u[u];
+    Lu[u] = s >= 0 ? (T)Lval[s] : T(0);
 }
 
 }  // namespace dev
 
 size_t selinv_big_lds_bytes(bool fp64) {
     const size_t C = kBigCols, w = fp64 ? 8 : 4;
-    return C * 8 + 4 * C * w + C * 4 + (C + 2) * 4 + 16 * 8 + 16;
+    return 16 * 8 + C * 8 + 4 * C * w;
 }
 
 hipError_t launch_dinv(int32_t n, const int8_t *piv, const double *dd, const double *ds, double *dinv,
@@ -300,15 +384,32 @@ hipError_t launch_dinv(int32_t n, const int8_t *piv, const double *dd, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipStream_t st) {
+template <typename T>
+static void launch_small_family(const SelinvParams &P, int group, hipStream_t st) {
+    constexpr int W = 4;
+    switch (group) {
+        case 64:
+            hipLaunchKernelGGL((dev::k_selinv_small<T, W>), dim3((P.nblk + W - 1) / W), dim3(64 * W), 0, st, P);
+            break;
+        case 128:
+            hipLaunchKernelGGL((dev::k_selinv_group<T, 128>), dim3(P.nblk), dim3(128), 0, st, P);
+            break;
+        case 256:
+            hipLaunchKernelGGL((dev::k_selinv_group<T, 256>), dim3(P.nblk), dim3(256), 0, st, P);
+            break;
+        default:
+            hipLaunchKernelGGL((dev::k_selinv_group<T, 512>), dim3(P.nblk), dim3(512), 0, st, P);
+            break;
+    }
+}
+
+hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipStream_t st, int group) {
     if (P.nblk <= 0) return hipSuccess;
     if (!big) {
-        constexpr int W = 4;
-        dim3 g((P.nblk + W - 1) / W);
         if (fp64)
-            hipLaunchKernelGGL((dev::k_selinv_small<double, W>), g, dim3(64 * W), 0, st, P);
+            launch_small_family<double>(P, group, st);
         else
-            hipLaunchKernelGGL((dev::k_selinv_small<float, W>), g, dim3(64 * W), 0, st, P);
+            launch_small_family<float>(P, group, st);
     } else {
         size_t lds = selinv_big_lds_bytes(fp64);
         if (fp64)
@@ -316,6 +417,19 @@ hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipSt
         else
             hipLaunchKernelGGL((dev::k_selinv_big<float>), dim3(P.nblk), dim3(256), lds, st, P);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_lu(int64_t nnzU, const int64_t *lsrc_u, const double *Lval, void *Lu, bool fp64,
+                            hipStream_t st) {
+    if (nnzU <= 0) return hipSuccess;
+    dim3 g((unsigned)((nnzU + 255) / 256));
+    if (fp64)
+        hipLaunchKernelGGL(dev::k_gather_lu<double>, g, dim3(256), 0, st, nnzU, lsrc_u, Lval,
+                           reinterpret_cast<double *>(Lu));
+    else
+        hipLaunchKernelGGL(dev::k_gather_lu<float>, g, dim3(256), 0, st, nnzU, lsrc_u, Lval,
+                           reinterpret_cast<float *>(Lu));
     return hipGetLastError();
 }
 

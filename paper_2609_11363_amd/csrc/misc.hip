@@ -82,8 +82,10 @@ __global__ void k_colnorm2(int32_t n, const int32_t *__restrict__ perm, const in
 }
 
 constexpr int kSpaiH = 4096;
+static_assert(kSpaiH == 1 << 12, "sslot assumes 2^12 slots");
 
-__device__ inline uint32_t sslot(int32_t r) { return ((uint32_t)r * 2654435761u) & (uint32_t)(kSpaiH - 1); }
+// Fibonacci hashing on the top bits of the product (kSpaiH = 2^12)
+__device__ inline uint32_t sslot(int32_t r) { return ((uint32_t)r * 2654435761u) >> (32 - 12); }
 
 __device__ inline int sinsert(int32_t *keys, int32_t r) {
     uint32_t s = sslot(r);

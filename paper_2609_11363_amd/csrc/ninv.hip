@@ -12,6 +12,7 @@
 // column j holds w_j in an LDS hash and streams the columns i of its row.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -32,7 +33,11 @@ __device__ inline void gsync() {
     }
 }
 
-__device__ inline uint32_t hslot(int32_t r, int H) { return ((uint32_t)r * 2654435761u) & (uint32_t)(H - 1); }
+// Fibonacci hashing: the top log2(H) bits of r * 2^32/phi (the low bits of the
+// product only depend on the low bits of r, which cluster for grid orderings)
+__device__ inline uint32_t hslot(int32_t r, int H) {
+    return ((uint32_t)r * 2654435761u) >> (32 - (31 - __builtin_clz((unsigned)H)));
+}
 
 // insert-or-find r in an LDS open-addressing table; -1 when full
 __device__ inline int hinsert(int32_t *keys, int H, int32_t r) {
@@ -58,6 +63,19 @@ __device__ inline int hfind(const int32_t *keys, int H, int32_t r) {
         s = (s + 1) & (uint32_t)(H - 1);
     }
     return -1;
+}
+
+// largest b in [0, c) with off[b] <= t
+__device__ inline int seg_of_n(const int32_t *off, int c, int32_t t) {
+    int lo = 0, hi = c - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
 // group-wide exclusive prefix of per-thread counts; returns this thread's
@@ -89,55 +107,95 @@ __device__ inline int32_t group_excl_scan(int32_t v, int32_t *scratch, int32_t *
 
 template <typename T>
 struct LinvLds {
-    int32_t *key;
-    T *cur, *nxt, *ser;
-    int32_t *lk;   // compact list of the current term: rows
-    T *lv;         //   and values
-    int32_t *off;  // segment offsets (H + 1)
+    int32_t *key;  // H
+    T *nxt, *ser;  // H: the term being accumulated, the series
+    int32_t *tl;   // H: slots touched by the current column
+    int32_t *lk;   // H: rows of the current term (compact)
+    T *lv;         // H: values of the current term
+    int32_t *off;  // H + 1: flattened offsets of the L columns to scatter
+    int64_t *seg;  // H: u-range starts of those columns
     int32_t *scr;  // scan scratch
-    int32_t *flag; // [0] overflow, [2] column fits the pool
-    int64_t *base; // pool offset of the column
+    int32_t *flag; // [0] overflow, [1] current term size, [2] column fits the pool, [3] touched count
+    int64_t *base; // [0] pool offset of the column, [1] next free entry of this group's
+                   // pool chunk, [2] end of the chunk
 };
 
-// builds column j of L^inv; returns false if the table overflowed
-template <typename T, int G>
-__device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S, int H, int tid) {
+// Pool entries are handed out in chunks per group so the global counter is
+// touched once per chunk rather than once per column.
+constexpr int64_t kPoolChunk = 512;
+
+// insert-or-find r; a newly claimed slot is appended to the touched list
+__device__ inline int hinsert_t(int32_t *keys, int H, int32_t r, int32_t *tl, int32_t *ntouched) {
+    uint32_t s = hslot(r, H);
+    for (int probe = 0; probe < H; ++probe) {
+        int32_t k = keys[s];
+        if (k == r) return (int)s;
+        if (k == -1) {
+            int32_t old = atomicCAS(&keys[s], -1, r);
+            if (old == -1) {
+                tl[atomicAdd(ntouched, 1)] = (int32_t)s;
+                return (int)s;
+            }
+            if (old == r) return (int)s;
+        }
+        s = (s + 1) & (uint32_t)(H - 1);
+    }
+    return -1;
+}
+
+template <typename T, int G, int H>
+__device__ void linv_init(const LinvLds<T> &S, int tid) {
     for (int s = tid; s < H; s += G) {
         S.key[s] = -1;
-        S.cur[s] = T(0);
         S.nxt[s] = T(0);
         S.ser[s] = T(0);
     }
     if (tid == 0) {
-        S.flag[0] = 0;
-        S.flag[1] = 0;
+        S.flag[3] = 0;
+        S.base[1] = 0;  // empty chunk
+        S.base[2] = 0;
     }
     gsync<G>();
+}
+
+// resets the slots the last column touched
+template <typename T, int G, int H>
+__device__ void linv_reset(const LinvLds<T> &S, int tid) {
+    const int32_t nt = S.flag[3];
+    for (int i = tid; i < nt; i += G) {
+        int s = S.tl[i];
+        S.key[s] = -1;
+        S.nxt[s] = T(0);
+        S.ser[s] = T(0);
+    }
+    gsync<G>();
+    if (tid == 0) S.flag[3] = 0;
+    gsync<G>();
+}
+
+// builds column j of L^inv; returns false if the table overflowed
+template <typename T, int G, int H>
+__device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S, int tid) {
+    const T *Lu = reinterpret_cast<const T *>(P.Lu);
     if (tid == 0) {
-        int s = hinsert(S.key, H, j);
-        S.cur[s] = T(1);
+        S.flag[0] = 0;
+        int s = hinsert_t(S.key, H, j, S.tl, &S.flag[3]);
         S.ser[s] = T(1);
+        S.lk[0] = j;
+        S.lv[0] = T(1);
+        S.flag[1] = 1;
     }
     gsync<G>();
     const T delta = (T)P.delta;
     for (int m = 1; m <= P.p; ++m) {
-        // compact the support of t^{m-1}
-        int32_t mine = 0;
-        for (int s = tid; s < H; s += G) mine += (S.key[s] >= 0 && S.cur[s] != T(0));
-        int32_t nl;
-        int32_t pos = group_excl_scan<G>(mine, S.scr, &nl);
-        for (int s = tid; s < H; s += G)
-            if (S.key[s] >= 0 && S.cur[s] != T(0)) {
-                S.lk[pos] = S.key[s];
-                S.lv[pos] = S.cur[s];
-                ++pos;
-            }
-        gsync<G>();
+        const int32_t nl = S.flag[1];
         if (nl == 0) break;
-        // segment lengths of the L columns to scatter
+        // columns of L (u-ranges) to scatter: E t = -sum_k t_k L(:, k)
         for (int b = tid; b < nl; b += G) {
             int32_t k = S.lk[b];
-            S.off[b + 1] = (int32_t)(P.rowptr[k + 1] - P.diagpos[k] - 1);
+            int64_t u0 = P.ustart[k];
+            S.seg[b] = u0;
+            S.off[b + 1] = (int32_t)(P.ustart[k + 1] - u0);
         }
         gsync<G>();
         if (tid < 64) {
@@ -158,47 +216,83 @@ __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S,
         }
         gsync<G>();
         const int32_t total = S.off[nl];
-        for (int32_t t = tid; t < total; t += G) {
-            int lo = 0, hi = nl - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (S.off[mid] <= t)
-                    lo = mid;
-                else
-                    hi = mid - 1;
+        for (int32_t t0 = tid; t0 < total; t0 += 2 * G) {
+            int64_t q[2];
+            int b[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                int32_t t = t0 + u * G;
+                b[u] = -1;
+                if (t < total) {
+                    b[u] = seg_of_n(S.off, nl, t);
+                    q[u] = S.seg[b[u]] + (t - S.off[b[u]]);
+                }
             }
-            int32_t k = S.lk[lo];
-            int64_t q = P.diagpos[k] + 1 + (t - S.off[lo]);
-            int64_t src = P.lsrc[q];
-            if (src < 0) continue;  // structural zero of a 2x2 union or the (k, k+1) slot
-            T val = -S.lv[lo] * (T)P.Lval[src];
-            int s = hinsert(S.key, H, P.col[q]);
-            if (s < 0) {
-                S.flag[0] = 1;
-                continue;
+            int32_t r[2];
+            T l[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (b[u] >= 0) {
+                    r[u] = P.ucol[q[u]];
+                    l[u] = Lu[q[u]];
+                }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (b[u] < 0 || l[u] == T(0)) continue;  // padding of a 2x2 union or (k, k+1)
+                int s = hinsert_t(S.key, H, r[u], S.tl, &S.flag[3]);
+                if (s < 0) {
+                    S.flag[0] = 1;
+                    continue;
+                }
+                atomicAdd(&S.nxt[s], -S.lv[b[u]] * l[u]);
             }
-            atomicAdd(&S.nxt[s], val);
         }
         gsync<G>();
         if (S.flag[0]) return false;
-        // drop |t| < delta from the new term and add it to the series
-        for (int s = tid; s < H; s += G) {
-            T v = S.nxt[s];
-            S.nxt[s] = T(0);
-            bool keep = S.key[s] >= 0 && v != T(0) && !(fabs(v) < delta);
-            S.cur[s] = keep ? v : T(0);
-            if (keep) S.ser[s] += v;
+        // drop |t| < delta from the new term, add it to the series and make
+        // it the current term (only touched slots can hold a value)
+        const int32_t nt = S.flag[3];
+        int32_t nn = 0, pos = 0;
+        for (int i0 = 0; i0 < nt; i0 += G) {
+            const int i = i0 + tid;
+            int32_t key = -1;
+            T v = T(0);
+            if (i < nt) {
+                int s = S.tl[i];
+                v = S.nxt[s];
+                S.nxt[s] = T(0);
+                key = S.key[s];
+                bool keep = v != T(0) && !(fabs(v) < delta);
+                if (keep)
+                    S.ser[s] += v;
+                else
+                    key = -1;
+            }
+            int32_t cnt;
+            int32_t p0 = group_excl_scan<G>(key >= 0 ? 1 : 0, S.scr, &cnt);
+            if (key >= 0) {
+                S.lk[nn + p0] = key;
+                S.lv[nn + p0] = v;
+            }
+            nn += cnt;
         }
+        (void)pos;
+        if (tid == 0) S.flag[1] = nn;
         gsync<G>();
     }
     // block partners of 2x2 rows must be present for w = D^-1 L^inv
-    for (int s = tid; s < H; s += G) {
-        int32_t r = S.key[s];
-        if (r >= 0 && S.ser[s] != T(0)) {
-            int8_t pv = P.piv[r];
-            if (pv != 0) {
-                int32_t partner = pv == 1 ? r + 1 : r - 1;
-                if (hinsert(S.key, H, partner) < 0) S.flag[0] = 1;
+    {
+        const int32_t nt = S.flag[3];
+        gsync<G>();
+        for (int i = tid; i < nt; i += G) {
+            int s = S.tl[i];
+            int32_t r = S.key[s];
+            if (S.ser[s] != T(0)) {
+                int8_t pv = P.piv[r];
+                if (pv != 0) {
+                    int32_t partner = pv == 1 ? r + 1 : r - 1;
+                    if (hinsert_t(S.key, H, partner, S.tl, &S.flag[3]) < 0) S.flag[0] = 1;
+                }
             }
         }
     }
@@ -207,27 +301,38 @@ __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S,
 }
 
 // writes the finished column to the pool
-template <typename T, int G>
-__device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, int H, int tid) {
+template <typename T, int G, int H>
+__device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, int tid) {
     auto wanted = [&](int s) -> bool {
         int32_t r = S.key[s];
-        if (r < 0) return false;
         if (S.ser[s] != T(0)) return true;
         int8_t pv = P.piv[r];
         if (pv == 0) return false;
         int ps = hfind(S.key, H, pv == 1 ? r + 1 : r - 1);
         return ps >= 0 && S.ser[ps] != T(0);
     };
+    const int32_t nt = S.flag[3];
     int32_t mine = 0;
-    for (int s = tid; s < H; s += G) mine += wanted(s);
+    for (int i = tid; i < nt; i += G) mine += wanted(S.tl[i]);
     int32_t cnt;
     int32_t pos = group_excl_scan<G>(mine, S.scr, &cnt);
     if (tid == 0) {
-        unsigned long long base = atomicAdd(P.pool_top, (unsigned long long)cnt);
-        bool fits = (int64_t)(base + cnt) <= P.pool_cap;
+        int64_t base = S.base[1];
+        if (base + cnt > S.base[2]) {
+            // chunk size: at most kPoolChunk and at most half the pool split
+            // over all groups, so small pools are not exhausted by reservations
+            const int64_t groups = (int64_t)gridDim.x * (blockDim.x / G);
+            int64_t want = P.pool_cap / (2 * groups);
+            want = want < kPoolChunk ? want : kPoolChunk;
+            want = want > cnt ? want : (int64_t)cnt;
+            base = (int64_t)atomicAdd(P.pool_top, (unsigned long long)want);
+            S.base[2] = base + want;
+        }
+        S.base[1] = base + cnt;
+        bool fits = base + cnt <= P.pool_cap;
         if (!fits) latch2(P.status, ST_POOL);
         S.flag[2] = fits ? 1 : 0;
-        S.base[0] = (int64_t)base;
+        S.base[0] = base;
     }
     gsync<G>();
     const bool fits = S.flag[2] != 0;
@@ -235,7 +340,8 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
     if (fits) {
         T *plinv = reinterpret_cast<T *>(P.plinv);
         T *pw = reinterpret_cast<T *>(P.pw);
-        for (int s = tid; s < H; s += G) {
+        for (int i = tid; i < nt; i += G) {
+            const int s = S.tl[i];
             if (!wanted(s)) continue;
             int32_t r = S.key[s];
             T lv = S.ser[s];
@@ -263,59 +369,69 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
         P.cstart[j] = base;
         P.clen[j] = fits ? cnt : 0;
     }
+    gsync<G>();
 }
 
-constexpr int kLinvH = 512;
+constexpr int kLinvH = 256;
 constexpr int kLinvHBig = 2048;
+constexpr int kLinvGrid = 2048;  // workgroups of the persistent column kernel
 
 template <typename T, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_linv_small(NinvParams P) {
     __shared__ int32_t key[WAVES][kLinvH];
-    __shared__ T cur[WAVES][kLinvH], nxt[WAVES][kLinvH], ser[WAVES][kLinvH];
+    __shared__ T nxt[WAVES][kLinvH], ser[WAVES][kLinvH];
+    __shared__ int32_t tl[WAVES][kLinvH];
     __shared__ int32_t lk[WAVES][kLinvH];
     __shared__ T lv[WAVES][kLinvH];
     __shared__ int32_t off[WAVES][kLinvH + 1];
+    __shared__ int64_t seg[WAVES][kLinvH];
     __shared__ int32_t scr[WAVES][8];
     __shared__ int32_t flag[WAVES][8];
-    __shared__ int64_t basev[WAVES];
+    __shared__ int64_t basev[WAVES][3];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int32_t j = blockIdx.x * WAVES + w;
-    if (j >= P.n) return;
-    LinvLds<T> S{key[w], cur[w], nxt[w], ser[w], lk[w], lv[w], off[w], scr[w], flag[w], &basev[w]};
-    if (linv_column<T, 64>(P, j, S, kLinvH, lane)) {
-        linv_emit<T, 64>(P, j, S, kLinvH, lane);
-    } else if (lane == 0) {
-        P.clen[j] = -1;
-        int32_t slot = atomicAdd(P.ovf_count, 1);
-        P.ovf_list[slot] = j;
+    LinvLds<T> S{key[w], nxt[w], ser[w], tl[w], lk[w], lv[w], off[w], seg[w], scr[w], flag[w], basev[w]};
+    linv_init<T, 64, kLinvH>(S, lane);
+    const int32_t stride = gridDim.x * WAVES;
+    for (int32_t j = blockIdx.x * WAVES + w; j < P.n; j += stride) {
+        if (linv_column<T, 64, kLinvH>(P, j, S, lane)) {
+            linv_emit<T, 64, kLinvH>(P, j, S, lane);
+        } else if (lane == 0) {
+            P.clen[j] = -1;
+            int32_t slot = atomicAdd(P.ovf_count, 1);
+            P.ovf_list[slot] = j;
+        }
+        linv_reset<T, 64, kLinvH>(S, lane);
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_linv_big(NinvParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int H = kLinvHBig;
+    constexpr int H = kLinvHBig;
     int64_t *basev = reinterpret_cast<int64_t *>(smem);
-    T *cur = reinterpret_cast<T *>(smem + 16);
-    T *nxt = cur + H;
+    int64_t *seg = basev + 4;
+    T *nxt = reinterpret_cast<T *>(seg + H);
     T *ser = nxt + H;
     T *lv = ser + H;
     int32_t *key = reinterpret_cast<int32_t *>(lv + H);
-    int32_t *lk = key + H;
+    int32_t *tl = key + H;
+    int32_t *lk = tl + H;
     int32_t *off = lk + H;
     int32_t *scr = off + H + 1;
     int32_t *flag = scr + 8;
-    LinvLds<T> S{key, cur, nxt, ser, lk, lv, off, scr, flag, basev};
+    LinvLds<T> S{key, nxt, ser, tl, lk, lv, off, seg, scr, flag, basev};
     const int32_t cnt = *P.ovf_count;
+    if (cnt == 0) return;
+    linv_init<T, 256, H>(S, threadIdx.x);
     for (int32_t idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
         int32_t j = P.ovf_list[idx];
-        if (linv_column<T, 256>(P, j, S, H, threadIdx.x)) {
-            linv_emit<T, 256>(P, j, S, H, threadIdx.x);
+        if (linv_column<T, 256, H>(P, j, S, threadIdx.x)) {
+            linv_emit<T, 256, H>(P, j, S, threadIdx.x);
         } else if (threadIdx.x == 0) {
             P.clen[j] = 0;
             latch2(P.status, ST_LIMIT);
         }
-        __syncthreads();
+        linv_reset<T, 256, H>(S, threadIdx.x);
     }
 }
 
@@ -369,18 +485,37 @@ __device__ void nprod_column(const NinvParams &P, int32_t j, const ProdLds<T> &S
     }
     gsync<G>();
     const int32_t total = S.off[ct];
-    for (int32_t t = tid; t < total; t += G) {
-        int lo = 0, hi = ct - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (S.off[mid] <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
+    // uniform trip count: every lane joins the segmented sums
+    for (int32_t t0 = 0; t0 < total; t0 += G) {
+        const int32_t t = t0 + tid;
+        int lo = -1;
+        T v = T(0);
+        if (t < total) {
+            lo = 0;
+            int hi = ct - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (S.off[mid] <= t)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            int64_t q = S.start[lo] + (t - S.off[lo]);
+            int32_t row = P.prow[q];
+            T lvv = plinv[q];
+            int s = hfind(S.key, H, row);
+            if (s >= 0) v = lvv * S.w[s];
         }
-        int64_t q = S.start[lo] + (t - S.off[lo]);
-        int s = hfind(S.key, H, P.prow[q]);
-        if (s >= 0) atomicAdd(&S.acc[lo], plinv[q] * S.w[s]);
+        // one target per segment: sum the run within the wavefront first
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            T vo = __shfl_down(v, o, 64);
+            int ko = __shfl_down(lo, o, 64);
+            if (lane + o < 64 && ko == lo) v += vo;
+        }
+        int kp = __shfl_up(lo, 1, 64);
+        if (lo >= 0 && (lane == 0 || kp != lo)) atomicAdd(&S.acc[lo], v);
     }
     gsync<G>();
     for (int t = tid; t < ct; t += G) {
@@ -390,7 +525,7 @@ __device__ void nprod_column(const NinvParams &P, int32_t j, const ProdLds<T> &S
     }
 }
 
-constexpr int kProdH = 512;
+constexpr int kProdH = 64;
 constexpr int kProdCt = 160;
 constexpr int kProdHBig = 4096;
 constexpr int kProdCtBig = kBigCols + 2;
@@ -449,7 +584,8 @@ __global__ void k_ninv_reset(NinvParams P) {
 
 template <typename T>
 size_t linv_big_lds() {
-    return 16 + 4 * (size_t)kLinvHBig * sizeof(T) + (3 * (size_t)kLinvHBig + 1 + 8 + 8) * 4 + 64;
+    return 32 + 8 * (size_t)kLinvHBig + 3 * (size_t)kLinvHBig * sizeof(T) +
+           (4 * (size_t)kLinvHBig + 1 + 8 + 8) * 4 + 64;
 }
 template <typename T>
 size_t nprod_big_lds() {
@@ -460,12 +596,13 @@ size_t nprod_big_lds() {
 template <typename T>
 hipError_t run_ninv(const NinvParams &P, hipStream_t st) {
     hipLaunchKernelGGL(k_ninv_reset, dim3(1), dim3(64), 0, st, P);
-    constexpr int W = 2;
-    hipLaunchKernelGGL((k_linv_small<T, W>), dim3((P.n + W - 1) / W), dim3(64 * W), 0, st, P);
+    constexpr int W = 4;
+    const int grid = (int)std::min<int64_t>((P.n + W - 1) / W, kLinvGrid);
+    hipLaunchKernelGGL((k_linv_small<T, W>), dim3(grid), dim3(64 * W), 0, st, P);
     size_t l1 = linv_big_lds<T>();
     hipFuncSetAttribute((const void *)k_linv_big<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
     hipLaunchKernelGGL((k_linv_big<T>), dim3(256), dim3(256), l1, st, P);
-    constexpr int W2 = 4;
+    constexpr int W2 = 8;
     hipLaunchKernelGGL((k_nprod_small<T, W2>), dim3((P.n + W2 - 1) / W2), dim3(64 * W2), 0, st, P);
     size_t l2 = nprod_big_lds<T>();
     hipFuncSetAttribute((const void *)k_nprod_big<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);

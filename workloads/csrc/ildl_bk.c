@@ -37,8 +37,9 @@ typedef struct {
     int32_t cnt;
 } htab;
 
+/* Fibonacci hashing: the top log2(cap) bits of k * 2^32/phi */
 static inline uint32_t hslot(int32_t k, int32_t cap) {
-    return ((uint32_t)k * 2654435761u) & (uint32_t)(cap - 1);
+    return ((uint32_t)k * 2654435761u) >> (32 - __builtin_ctz((unsigned)cap));
 }
 
 static int ht_init(htab *h, int32_t want) {
