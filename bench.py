@@ -106,6 +106,38 @@ def main():
     Z32 = Z.cpu().numpy()
     log(f"mixed step {ms_step_mixed:.3f} ms")
 
+    # the two SelInv schedules, and the whole step replayed from a HIP graph
+    sweeps = {}
+    for mode in ("levels", "dataflow"):
+        try:
+            s.set_sweep(mode)
+            s.selinv(Lv, dd, ds, out=Z)
+            s.sync()
+            sweeps[mode] = timed(lambda: s.selinv(Lv, dd, ds, out=Z), args.steps) * 1e3
+            s.sync()
+        except Exception as exc:  # noqa: BLE001 - reported, not fatal
+            sweeps[mode] = f"unavailable: {exc}"
+    log(f"selinv sweeps: {sweeps}")
+    ms_graph = None
+    try:
+        s.set_sweep("levels")
+        step()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(args.warmup):
+            graph.replay()
+        ms_graph = timed(graph.replay, args.steps) * 1e3
+        s.sync()
+        gZ = Z.cpu().numpy()
+        graph_ok = bool(np.array_equal(gZ, Z64)) or float(np.max(np.abs(gZ - Z64))) < 1e-12
+        log(f"graph step {ms_graph:.3f} ms (matches eager: {graph_ok})")
+        del graph
+    except Exception as exc:  # noqa: BLE001
+        log(f"graph capture unavailable: {exc}")
+    s.set_sweep("auto")
+
     # live per-launch timing of the dominant kernel (HIP events on the stream)
     s.profile(True)
     for _ in range(3):
@@ -145,6 +177,8 @@ def main():
             "selinv_mixed": {"ms": ms_selinv_mixed, "entries_per_s": nnzS / (ms_selinv_mixed * 1e-3)},
             "mix_pipeline_mixed": {"ms": ms_step_mixed, "entries_per_s": nnzS / (ms_step_mixed * 1e-3)},
         },
+        "selinv_sweeps_ms": sweeps,
+        "graph_step_ms": ms_graph,
         "profile_ms_per_step": {k: v[1] / 3 for k, v in prof.items() if v[0]},
         "roofline": {"kernel": "k_selinv_small (SelInv level, wavefront per block)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

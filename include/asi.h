@@ -52,7 +52,8 @@ typedef enum {
     ASI_E_STATE = 5,       /* call order violated (e.g. numeric call before analyze) */
     ASI_E_WORKSPACE = 6,   /* workspace too small or a device pool exhausted */
     ASI_E_HIP = 7,         /* a HIP runtime call failed */
-    ASI_E_UNSUPPORTED = 8  /* the pattern exceeds a documented kernel limit */
+    ASI_E_UNSUPPORTED = 8, /* the pattern exceeds a documented kernel limit */
+    ASI_E_TIMEOUT = 9      /* a dataflow wait exceeded its poll limit (results invalid) */
 } asi_status;
 
 typedef enum { ASI_FP64 = 0, ASI_MIXED = 1 } asi_precision;
@@ -117,6 +118,18 @@ asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, c
                       asi_precision prec, double *Z_S);
 
 /*
+ * How asi_selinv schedules the blocks. ASI_SWEEP_LEVELS launches one kernel
+ * per level of the dependency DAG. ASI_SWEEP_DATAFLOW runs the whole sweep as
+ * one cooperative launch in which each block waits only for the blocks it
+ * depends on (requires every |R_J| <= 128 and cooperative-launch support;
+ * otherwise asi_selinv returns ASI_E_UNSUPPORTED). ASI_SWEEP_AUTO (default)
+ * currently selects the level schedule, the faster of the two on MI355X for
+ * the tested patterns.
+ */
+typedef enum { ASI_SWEEP_AUTO = 0, ASI_SWEEP_LEVELS = 1, ASI_SWEEP_DATAFLOW = 2 } asi_sweep;
+asi_status asi_set_sweep(asi_handle h, asi_sweep mode);
+
+/*
  * NInv (Section 2.2): L^inv = sum_{m=0}^{p} T_m with T_0 = I and
  * T_m = drop_delta(E T_{m-1}), E = I - L, dropping |t| < delta in each new
  * term; N = (L^inv)^T D^-1 L^inv evaluated on S. Columns of L^inv are kept in
@@ -174,7 +187,8 @@ typedef enum {
     ASI_K_SPAI = 5,          /* SPAI refinement and symmetrisation */
     ASI_K_LOWRANK = 6,       /* rank-k correction on S */
     ASI_K_GATHER = 7,        /* L values gathered into the column layout, once per call */
-    ASI_K_COUNT = 8
+    ASI_K_SELINV_FLOW = 8,   /* the dataflow SelInv sweep (one launch per call) */
+    ASI_K_COUNT = 9
 } asi_kernel_class;
 asi_status asi_profile(asi_handle h, int enable);
 asi_status asi_profile_read(asi_handle h, int32_t kernel_class, int64_t *launches, double *total_ms,

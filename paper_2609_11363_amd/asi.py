@@ -17,16 +17,17 @@ LIB_PATH = os.path.join(_HERE, "libasi.so")
 
 STATUS = {0: "ASI_OK", 1: "ASI_E_ARG", 2: "ASI_E_PATTERN", 3: "ASI_E_SINGULAR_D",
           4: "ASI_E_NONFINITE", 5: "ASI_E_STATE", 6: "ASI_E_WORKSPACE", 7: "ASI_E_HIP",
-          8: "ASI_E_UNSUPPORTED"}
+          8: "ASI_E_UNSUPPORTED", 9: "ASI_E_TIMEOUT"}
+SWEEP = {"auto": 0, "levels": 1, "dataflow": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 
 # every symbol the header declares
 EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi_analyze",
            "asi_set_workspace", "asi_get_info", "asi_get_pattern", "asi_selinv", "asi_ninv",
            "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
-           "asi_profile_read"]
+           "asi_profile_read", "asi_set_sweep"]
 KERNEL_CLASSES = {"dinv": 0, "selinv": 1, "selinv_big": 2, "ninv": 3, "mix": 4, "spai": 5,
-                  "lowrank": 6, "gather_l": 7}
+                  "lowrank": 6, "gather_l": 7, "selinv_flow": 8}
 
 
 class AsiError(RuntimeError):
@@ -73,6 +74,7 @@ def load_library():
         "asi_diag": [P, P, P],
         "asi_sync": [P],
         "asi_profile": [P, ctypes.c_int],
+        "asi_set_sweep": [P, ctypes.c_int],
         "asi_profile_read": [P, i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(f64)],
     }
     for name, args in sig.items():
@@ -222,6 +224,10 @@ class Solver:
     def sync(self):
         self._stream()
         self._check(self.lib.asi_sync(self.h))
+
+    def set_sweep(self, mode="auto"):
+        """SelInv schedule: "auto", "levels" (one launch per DAG level) or "dataflow"."""
+        self._check(self.lib.asi_set_sweep(self.h, SWEEP[mode]))
 
     def profile(self, enable=True):
         self._stream()

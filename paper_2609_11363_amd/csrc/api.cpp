@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -38,6 +39,9 @@ struct asi_handle_s {
     void *Lu = nullptr;
     void *Zu = nullptr;
     double *zd = nullptr;
+    int32_t *done = nullptr;
+    int32_t epoch = 0;
+    int sweep = ASI_SWEEP_AUTO;
     int8_t *piv = nullptr;
     int32_t *level = nullptr;
     int32_t *sched_small = nullptr;
@@ -142,6 +146,7 @@ Layout make_layout(const asi::Analysis &A) {
     L.add(u * 8);                       // 26 Zu
     L.add(n * 8);                       // 27 zd (SelInv diagonal)
     L.add(A.hits.size() * 4);           // 28 hits
+    L.add(n * 4);                       // 29 done flags of the dataflow sweep
     return L;
 }
 
@@ -299,6 +304,8 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->Zu = b + L.off[26];
     h->zd = at<double>(b, L.off[27]);
     h->hits = at<uint32_t>(b, L.off[28]);
+    h->done = at<int32_t>(b, L.off[29]);
+    h->epoch = 0;
     // pool: rows | linv | w, each region 256-aligned
     size_t rest = bytes - L.cur - 3 * 256;
     int64_t cap = (int64_t)(rest / kPoolEntryBytes);
@@ -338,10 +345,12 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
         if (e != hipSuccess) return hip_fail(h, e, "upload analysis");
     }
     hipError_t e = asi::launch_fill_i32(h->status, 64, 0, h->stream);
+    if (e == hipSuccess) e = asi::launch_fill_i32(h->done, A.n, 0, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "clear status");
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "upload analysis");
     e = asi::set_big_lds_limits();
+    if (e == hipSuccess) e = asi::set_ninv_lds_limits();
     if (e != hipSuccess) return hip_fail(h, e, "set LDS limits");
     h->ws_ready = true;
     return ASI_OK;
@@ -415,6 +424,24 @@ asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, c
     P.zdiag = h->zd;
     P.out = Z_S;
     P.status = h->status;
+    const bool flow_ok = A.sched_big.empty() && A.n_blocks > 0;
+    int grid = 0;
+    // AUTO runs the level schedule: on MI355X it measured faster than the
+    // dataflow sweep for the workloads here (per-block flag latency outweighs
+    // the saved launch boundaries)
+    if (h->sweep == ASI_SWEEP_DATAFLOW && flow_ok) grid = asi::flow_grid(fp64);
+    if (h->sweep == ASI_SWEEP_DATAFLOW && grid <= 0)
+        return fail(h, ASI_E_UNSUPPORTED, "dataflow sweep needs |R_J| <= 128 and cooperative launch");
+    if (grid > 0) {
+        double bytes = 0.0;
+        for (int32_t l = 0; l < A.n_levels; ++l) bytes += A.lvl_bytes_small[m][l];
+        h->epoch = h->epoch == INT32_MAX ? 1 : h->epoch + 1;
+        Trace t(h, ASI_K_SELINV_FLOW, bytes);
+        e = asi::launch_selinv_flow(P, h->sched_small, A.n_blocks, h->done, h->epoch, 1 << 21, fp64, grid,
+                                    h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "selinv dataflow launch");
+        return ASI_OK;
+    }
     for (int32_t l = 0; l < A.n_levels; ++l) {
         P.blocks = h->sched_small + A.lvl_small[l];
         P.nblk = A.lvl_small[l + 1] - A.lvl_small[l];
@@ -431,6 +458,14 @@ asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, c
             if (e != hipSuccess) return hip_fail(h, e, "selinv level (large blocks)");
         }
     }
+    return ASI_OK;
+}
+
+asi_status asi_set_sweep(asi_handle h, asi_sweep mode) {
+    if (!h) return ASI_E_ARG;
+    if (mode != ASI_SWEEP_AUTO && mode != ASI_SWEEP_LEVELS && mode != ASI_SWEEP_DATAFLOW)
+        return fail(h, ASI_E_ARG, "unknown sweep mode");
+    h->sweep = mode;
     return ASI_OK;
 }
 
@@ -580,6 +615,7 @@ asi_status asi_sync(asi_handle h) {
         const char *what = st == asi::ST_SINGULAR   ? "singular D block"
                            : st == asi::ST_NONFINITE ? "non-finite value produced"
                            : st == asi::ST_POOL      ? "NInv pool exhausted: enlarge the workspace"
+                           : st == asi::ST_TIMEOUT   ? "dataflow wait exceeded its poll limit"
                                                      : "a column exceeds a kernel limit";
         return fail(h, (asi_status)st, what);
     }

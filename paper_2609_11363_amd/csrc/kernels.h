@@ -10,7 +10,7 @@
 namespace asi {
 
 // Device-side status codes latched into the workspace status word.
-enum : int32_t { ST_SINGULAR = 3, ST_NONFINITE = 4, ST_POOL = 6, ST_LIMIT = 8 };
+enum : int32_t { ST_SINGULAR = 3, ST_NONFINITE = 4, ST_POOL = 6, ST_LIMIT = 8, ST_TIMEOUT = 9 };
 
 struct SelinvParams {
     const int32_t *blocks;  // block starts of this launch
@@ -36,6 +36,10 @@ hipError_t launch_dinv(int32_t n, const int8_t *piv, const double *dd, const dou
 // group: threads per block for |R_J| <= kSmallCols (64 = one wavefront per
 // block, four blocks per workgroup; 128, 256 or 512 = one workgroup per block)
 hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipStream_t st, int group);
+// Dataflow sweep over all blocks in one cooperative launch (|R_J| <= kSmallCols).
+int flow_grid(bool fp64);
+hipError_t launch_selinv_flow(const SelinvParams &P, const int32_t *order, int32_t nblocks, int32_t *done,
+                              int32_t epoch, int32_t spin_limit, bool fp64, int grid, hipStream_t st);
 hipError_t launch_gather_lu(int64_t nnzU, const int64_t *lsrc_u, const double *Lval, void *Lu, bool fp64,
                             hipStream_t st);
 hipError_t set_big_lds_limits();
@@ -72,6 +76,7 @@ struct NinvParams {
 };
 
 hipError_t launch_ninv(const NinvParams &P, bool fp64, hipStream_t st);
+hipError_t set_ninv_lds_limits();
 
 hipError_t launch_zdiag(int32_t n, const int64_t *diagpos, const double *X, double *d, hipStream_t st);
 hipError_t launch_mix(int64_t nnz, const int32_t *srow, const int32_t *col, const double *zdiag,

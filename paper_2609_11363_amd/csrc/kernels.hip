@@ -149,6 +149,26 @@ struct SelinvLds {
     int64_t *seg;  // c: u-range start of R_J[b]
 };
 
+// Accesses to the data that crosses blocks inside one launch (Z columns in
+// u-space and the diagonal). In the dataflow sweep (CO = true) they are
+// agent-coherent loads and stores, so a block's results are visible to other
+// compute units once its stores have completed; no cache maintenance is needed.
+template <bool CO, typename V>
+__device__ inline V co_load(const V *p) {
+    if constexpr (CO)
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *p;
+}
+
+template <bool CO, typename V>
+__device__ inline void co_store(V *p, V v) {
+    if constexpr (CO)
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+
 template <int G>
 __device__ inline void group_sync() {
     if constexpr (G == 64)
@@ -157,9 +177,38 @@ __device__ inline void group_sync() {
         __syncthreads();
 }
 
-template <typename T, int G, int NT, bool WIDE>
+// Static part of a block's staging (data that no block of the sweep writes):
+// L(R_J, J), the gather segments, the rows of R_J and the mirror positions.
+template <typename T, int G, int NT>
+__device__ inline void stage_static(const SelinvParams &P, int32_t j, const SelinvLds<T> &S, int tid,
+                                    int32_t (&rr)[NT], int64_t (&mir0)[NT], int64_t (&mir1)[NT]) {
+    const bool two = P.piv[j] == 1;
+    const int32_t last = two ? j + 1 : j;
+    const int64_t ub = P.ustart[last];
+    const int32_t c = (int32_t)(P.ustart[last + 1] - ub);
+    const int64_t ubj = two ? P.ustart[j] + 1 : ub;
+    const T *Lu = reinterpret_cast<const T *>(P.Lu);
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const int t = tid + k * G;
+        rr[k] = -1;
+        mir0[k] = mir1[k] = -1;
+        if (t < c) {
+            rr[k] = P.ucol[ub + t];
+            S.seg[t] = P.useg[ub + t];
+            S.l0[t] = Lu[ubj + t];
+            if (two) S.l1[t] = Lu[ub + t];
+            mir0[k] = P.mirror_u[ubj + t];
+            if (two) mir1[k] = P.mirror_u[ub + t];
+        }
+    }
+}
+
+template <typename T, int G, int NT, bool WIDE, bool CO = false, bool PRE = false>
 __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T> &S, int tid,
-                             double *red /* G > 64: (G / 64) waves x 4 partial sums */) {
+                             double *red /* G > 64: (G / 64) waves x 4 partial sums */,
+                             const int32_t *pre_r = nullptr, const int64_t *pre_m0 = nullptr,
+                             const int64_t *pre_m1 = nullptr) {
     const bool two = P.piv[j] == 1;
     const int32_t last = two ? j + 1 : j;
     const int64_t ub = P.ustart[last];
@@ -179,6 +228,16 @@ __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
         const int t = tid + k * G;
+        if constexpr (PRE) {
+            mir0[k] = pre_m0[k];
+            mir1[k] = pre_m1[k];
+            if (t < c) {
+                T zll = (T)co_load<CO>(&P.zdiag[pre_r[k]]);
+                S.y0[t] = -zll * S.l0[t];
+                if (two) S.y1[t] = -zll * S.l1[t];
+            }
+            continue;
+        }
         mir0[k] = mir1[k] = -1;
         if (t < c) {
             int32_t r = P.ucol[ub + t];
@@ -190,7 +249,7 @@ __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T
             S.seg[t] = sg;
             S.l0[t] = v0;
             if (two) S.l1[t] = v1;
-            T zll = (T)P.zdiag[r];
+            T zll = (T)co_load<CO>(&P.zdiag[r]);
             S.y0[t] = -zll * v0;
             if (two) S.y1[t] = -zll * v1;
         }
@@ -230,7 +289,7 @@ __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T
                     b[u] = (int32_t)((w0[u] >> 7) & 0x7fu);
                     off = (int64_t)(w0[u] >> 14);
                 }
-                z[u] = Zu[S.seg[b[u]] + off];
+                z[u] = co_load<CO>(&Zu[S.seg[b[u]] + off]);
             }
         }
 #pragma unroll
@@ -259,14 +318,14 @@ __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T
         const int t = tid + k * G;
         if (t >= c) continue;
         T y0 = S.y0[t];
-        Zu[ubj + t] = y0;
+        co_store<CO>(&Zu[ubj + t], y0);
         P.out[pdj + t] = (double)y0;
         P.out[mir0[k]] = (double)y0;
         double l0 = (double)S.l0[t];
         d00 += l0 * (double)y0;
         if (two) {
             T y1 = S.y1[t];
-            Zu[ub + t] = y1;
+            co_store<CO>(&Zu[ub + t], y1);
             P.out[pdl + t] = (double)y1;
             P.out[mir1[k]] = (double)y1;
             double l1 = (double)S.l1[t];
@@ -302,16 +361,16 @@ __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T
         const double *iv = P.dinv + 3 * (int64_t)j;
         double zjj = iv[0] - d00;
         P.out[P.diagpos[j]] = zjj;
-        P.zdiag[j] = zjj;
+        co_store<CO>(&P.zdiag[j], zjj);
         bool bad = !isfinite(zjj);
         if (two) {
             double z11 = iv[2] - d11;
             double off = iv[1] - 0.5 * (d10 + d01);
             P.out[P.diagpos[last]] = z11;
-            P.zdiag[last] = z11;
+            co_store<CO>(&P.zdiag[last], z11);
             P.out[P.diagpos[j] + 1] = off;
             P.out[P.diagpos[last] - 1] = off;
-            Zu[P.ustart[j]] = (T)off;  // (j, j+1), read by later gathers
+            co_store<CO>(&Zu[P.ustart[j]], (T)off);  // (j, j+1), read by later gathers
             bad = bad || !isfinite(z11) || !isfinite(off);
         }
         if (bad) latch(P.status, 4);
@@ -359,6 +418,60 @@ __global__ __launch_bounds__(256) void k_selinv_big(SelinvParams P) {
     if (bi >= P.nblk) return;
     SelinvLds<T> S{l0, l1, y0, y1, seg};
     selinv_block<T, 256, kBigCols / 256, true>(P, P.blocks[bi], S, threadIdx.x, red);
+}
+
+// ---------------------------------------------------------------------------
+// Dataflow sweep: one cooperative launch, one wavefront per block. Blocks are
+// taken in a topological order (level-major), wavefront w handling positions
+// w, w + W, w + 2W, ... Before a block starts, its wavefront waits until every
+// block that holds a row of R_J has published its column (flag == epoch);
+// after finishing it publishes its own. Z columns and the diagonal are read
+// and written with agent-coherent accesses and the flag is stored only after
+// the block's stores have completed, so no L2 writeback or invalidation is
+// issued per block. All wavefronts are co-resident (cooperative launch), so
+// the earliest unfinished block can always proceed.
+// The wait is bounded: after spin_limit polls the status word is latched and
+// the block runs anyway, so the launch always drains.
+template <typename T, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_selinv_flow(SelinvParams P, const int32_t *__restrict__ order,
+                                                            int32_t nblocks, int32_t *done, int32_t epoch,
+                                                            int32_t spin_limit) {
+    __shared__ T sL0[WAVES][kSmallCols], sL1[WAVES][kSmallCols];
+    __shared__ T sY0[WAVES][kSmallCols], sY1[WAVES][kSmallCols];
+    __shared__ int64_t sSeg[WAVES][kSmallCols];
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    SelinvLds<T> S{sL0[w], sL1[w], sY0[w], sY1[w], sSeg[w]};
+    const int32_t stride = gridDim.x * WAVES;
+    for (int32_t i = blockIdx.x * WAVES + w; i < nblocks; i += stride) {
+        const int32_t j = order[i];
+        const int32_t last = P.piv[j] == 1 ? j + 1 : j;
+        // stage what no block writes before waiting for the dependencies
+        constexpr int NT = kSmallCols / 64;
+        int32_t rr[NT];
+        int64_t m0[NT], m1[NT];
+        stage_static<T, 64, NT>(P, j, S, lane, rr, m0, m1);
+        const int32_t r0 = rr[0], r1 = rr[1];
+        for (int32_t poll = 0;; ++poll) {
+            bool ok = true;
+            if (r0 >= 0) ok = __hip_atomic_load(&done[r0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+            if (r1 >= 0 && ok)
+                ok = __hip_atomic_load(&done[r1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+            if (__all(ok)) break;
+            if (poll >= spin_limit) {
+                if (lane == 0) latch(P.status, ST_TIMEOUT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        wave_sync();
+        selinv_block<T, 64, NT, false, true, true>(P, j, S, lane, nullptr, rr, m0, m1);
+        // the block's agent-coherent stores are complete before its flag is set
+        __builtin_amdgcn_s_waitcnt(0);
+        if (lane == 0) {
+            __hip_atomic_store(&done[j], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (last != j) __hip_atomic_store(&done[last], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 template <typename T>
@@ -431,6 +544,28 @@ hipError_t launch_gather_lu(int64_t nnzU, const int64_t *lsrc_u, const double *L
         hipLaunchKernelGGL(dev::k_gather_lu<float>, g, dim3(256), 0, st, nnzU, lsrc_u, Lval,
                            reinterpret_cast<float *>(Lu));
     return hipGetLastError();
+}
+
+// Largest co-resident grid of the dataflow kernel (0 if unavailable).
+int flow_grid(bool fp64) {
+    constexpr int W = 4;
+    int dev = 0, cus = 0, per = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, dev::k_selinv_flow<double, W>, 64 * W, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, dev::k_selinv_flow<float, W>, 64 * W, 0);
+    if (e != hipSuccess) return 0;
+    return per * cus;
+}
+
+hipError_t launch_selinv_flow(const SelinvParams &P, const int32_t *order, int32_t nblocks, int32_t *done,
+                              int32_t epoch, int32_t spin_limit, bool fp64, int grid, hipStream_t st) {
+    constexpr int W = 4;
+    SelinvParams p = P;
+    void *args[] = {&p, (void *)&order, &nblocks, &done, &epoch, &spin_limit};
+    const void *fn = fp64 ? (const void *)dev::k_selinv_flow<double, W> : (const void *)dev::k_selinv_flow<float, W>;
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(64 * W), args, 0, st);
 }
 
 hipError_t set_big_lds_limits() {

@@ -600,17 +600,27 @@ hipError_t run_ninv(const NinvParams &P, hipStream_t st) {
     const int grid = (int)std::min<int64_t>((P.n + W - 1) / W, kLinvGrid);
     hipLaunchKernelGGL((k_linv_small<T, W>), dim3(grid), dim3(64 * W), 0, st, P);
     size_t l1 = linv_big_lds<T>();
-    hipFuncSetAttribute((const void *)k_linv_big<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
     hipLaunchKernelGGL((k_linv_big<T>), dim3(256), dim3(256), l1, st, P);
     constexpr int W2 = 8;
     hipLaunchKernelGGL((k_nprod_small<T, W2>), dim3((P.n + W2 - 1) / W2), dim3(64 * W2), 0, st, P);
     size_t l2 = nprod_big_lds<T>();
-    hipFuncSetAttribute((const void *)k_nprod_big<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
     hipLaunchKernelGGL((k_nprod_big<T>), dim3(256), dim3(256), l2, st, P);
     return hipGetLastError();
 }
 
 }  // namespace dev
+
+hipError_t set_ninv_lds_limits() {
+    const void *fns[] = {(const void *)dev::k_linv_big<double>, (const void *)dev::k_linv_big<float>,
+                         (const void *)dev::k_nprod_big<double>, (const void *)dev::k_nprod_big<float>};
+    const size_t bytes[] = {dev::linv_big_lds<double>(), dev::linv_big_lds<float>(),
+                            dev::nprod_big_lds<double>(), dev::nprod_big_lds<float>()};
+    for (int i = 0; i < 4; ++i) {
+        hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes[i]);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_ninv(const NinvParams &P, bool fp64, hipStream_t st) {
     return fp64 ? dev::run_ninv<double>(P, st) : dev::run_ninv<float>(P, st);

@@ -157,3 +157,26 @@ def test_small_pool_is_reported(torch_mod):
     with pytest.raises(AsiError) as ei:
         s.sync()
     assert ei.value.code == 6
+
+
+@pytest.mark.parametrize("name", ["lap32_tau0", "kkt_tau0", "diff16_tau1e-3", "rand3000_tau1e-2"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sweep_schedules_agree(torch_mod, name, precision):
+    """Level-by-level and dataflow sweeps both match the oracle."""
+    from paper_2609_11363_amd import Solver, upload_factors
+    print(f"[sweeps] case={name} precision={precision}", flush=True)
+    F = _case(name)
+    S = oc.pattern(F)
+    Zo = oc.selinv(F, S)
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    Lv, dd, ds = upload_factors(F)
+    for mode in ("levels", "dataflow"):
+        s.set_sweep(mode)
+        for rep in range(2):  # the second call reuses the flags with a new epoch
+            Z = s.selinv(Lv, dd, ds, precision=precision)
+            s.sync()
+            e = oc.entry_error(S, Z.cpu().numpy(), Zo).max()
+            print(f"  {mode} call {rep}: e_Z={e:.2e}")
+            assert e <= tol
