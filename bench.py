@@ -39,6 +39,10 @@ def main():
     ap.add_argument("--grid", type=int, default=64)
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweeps", default="levels,dataflow",
+                    help="SelInv schedules to time separately (comma list of levels, dataflow)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -108,7 +112,7 @@ def main():
 
     # the two SelInv schedules, and the whole step replayed from a HIP graph
     sweeps = {}
-    for mode in ("levels", "dataflow"):
+    for mode in [m for m in args.sweeps.split(",") if m]:
         try:
             s.set_sweep(mode)
             s.selinv(Lv, dd, ds, out=Z)
@@ -137,6 +141,16 @@ def main():
     except Exception as exc:  # noqa: BLE001
         log(f"graph capture unavailable: {exc}")
     s.set_sweep("auto")
+
+    if args.copy_calibration:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE read for it give
+        # the counters' scale (256 MiB read + 256 MiB written per launch)
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # live per-launch timing of the dominant kernel (HIP events on the stream)
     s.profile(True)
