@@ -1,0 +1,85 @@
+"""GPU parity of Mix-SPAI (Section 2.4) and the rank-k correction on S
+(Section 2.5, diagonal of Section 2.6) against the CPU oracle."""
+import numpy as np
+import pytest
+
+from oracle import core as oc
+from workloads import (diffusion3d_7pt, ildl_bk, laplace2d, nested_multicolor_grid, rcm,
+                       shifted_laplace2d_indefinite)
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+def _spai_case(name):
+    if name == "lap32_tau1e-2":
+        A = laplace2d(32, 32, 0.01)
+        return A, ildl_bk(A, rcm(A), 1e-2)
+    if name == "indef24_tau1e-2":
+        A, _ = shifted_laplace2d_indefinite(24, 4)
+        return A, ildl_bk(A, nested_multicolor_grid((24, 24)), 1e-2)
+    if name == "diff12_tau1e-3":
+        A = diffusion3d_7pt(12, 1.0, 2)
+        return A, ildl_bk(A, nested_multicolor_grid((12, 12, 12)), 1e-3)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["lap32_tau1e-2", "indef24_tau1e-2", "diff12_tau1e-3"])
+@pytest.mark.parametrize("iters", [1, 10])
+def test_spai_parity(name, iters):
+    import torch
+    from paper_2609_11363_amd import Solver, upload_factors
+    print(f"[spai] case={name} iters={iters}", flush=True)
+    A, F = _spai_case(name)
+    S = oc.pattern(F)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    Lv, dd, ds = upload_factors(F)
+    Z = s.selinv(Lv, dd, ds)
+    N = s.ninv(Lv, dd, ds, p=3, delta=0.1)
+    M = s.mix(Z, N, 1e-2)
+    dev = torch.device("cuda", 0)
+    Ar = torch.as_tensor(A.indptr.astype(np.int64), device=dev)
+    Ac = torch.as_tensor(A.indices.astype(np.int32), device=dev)
+    Av = torch.as_tensor(A.data.astype(np.float64), device=dev)
+    perm = torch.as_tensor(F.perm.astype(np.int32), device=dev)
+    R = s.spai(Ar, Ac, Av, perm, M, cg_iters=iters)
+    s.sync()
+    # the oracle refines the same starting values (the device's Mix output)
+    Ro = oc.spai(oc.permuted(A, F.perm), S, M.cpu().numpy(), iters)
+    e = oc.entry_error(S, R.cpu().numpy(), Ro)
+    print(f"  n={F.n} |S|={S.nnz} e_R max={e.max():.2e}")
+    assert e.max() <= FP64_TOL
+    Rm = S.to_csr(R.cpu().numpy())
+    assert abs(Rm - Rm.T).max() == 0.0
+
+
+@pytest.mark.parametrize("k", [1, 5, 16, 33, 64])
+def test_lowrank_parity(k):
+    import torch
+    from paper_2609_11363_amd import Solver, upload_factors
+    print(f"[lowrank] k={k}", flush=True)
+    A = laplace2d(20, 20, 0.1)
+    F = ildl_bk(A, rcm(A), 1e-2)
+    S = oc.pattern(F)
+    rng = np.random.default_rng(k)
+    V = rng.standard_normal((F.n, k))
+    lam = rng.standard_normal(k)
+    X = rng.standard_normal(S.nnz)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    dev = torch.device("cuda", 0)
+    Vt = torch.as_tensor(V, device=dev)
+    lt = torch.as_tensor(lam, device=dev)
+    Xt = torch.as_tensor(X, device=dev)
+    out = s.lowrank(Vt, lt, Xt)
+    d = s.diag(out)
+    inplace = Xt.clone()
+    s.lowrank(Vt, lt, inplace, out=inplace)  # out may alias in
+    s.sync()
+    ref = oc.lowrank(S, V, lam, X)
+    scale = np.abs(ref).max()
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-13 * scale
+    assert np.abs(inplace.cpu().numpy() - ref).max() <= 1e-13 * scale
+    np.testing.assert_allclose(d.cpu().numpy(), oc.diag(S, ref), rtol=1e-13, atol=1e-13 * scale)
