@@ -163,6 +163,43 @@ asi_status asi_spai(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col,
 asi_status asi_lowrank(asi_handle h, int32_t k, const double *V, const double *lambda,
                        const double *in_S, double *out_S);
 
+/*
+ * Learned per-entry correction of the Mix result (not part of the paper: a
+ * 16 -> 64 -> 64 -> 1 ReLU network with bfloat16 weights and activations and
+ * float32 accumulation, M'_ij = M_ij + y_ij s_ij, s_ij = sqrt(|M_ii M_jj|)).
+ *
+ * asi_mlp_features: the 16 features of every entry of S from Z (SelInv), N
+ * (NInv), M (Mix with threshold eps), L and D: F is |S| x 16 bfloat16 (raw
+ * 16-bit words, row-major), scale receives s_ij (float32, |S|).
+ * Feature order: M/s, (Z-N)/s, [Mix took Z], [i == j], log|D^-1_ii|,
+ * log|D^-1_jj|, log row norms of L at i and j, log column norms of L at i and
+ * j, |L(max, min)|, log(1 + |N|/s), log(1 + |Z|/s), level(i)/max level,
+ * level(j)/max level, log(1 + |R| of column min(i, j)).
+ */
+#define ASI_MLP_FEATURES 16
+#define ASI_MLP_PARAMS 5313        /* float32 masters: W1[64][16], b1, W2[64][64], b2, w3, b3 */
+#define ASI_MLP_PACKED_BYTES 12944 /* bfloat16 W1 (padded to [64][32]), W2, w3; float32 b1, b2, b3 */
+asi_status asi_mlp_features(asi_handle h, const double *Z_S, const double *N_S, const double *M_S, double eps,
+                            const double *L_val, const double *d_diag, const double *d_sub, uint16_t *F,
+                            float *scale);
+/* The following calls need a device handle but no analysis. */
+/* Round the float32 masters (ASI_MLP_PARAMS) into the packed inference weights. */
+asi_status asi_mlp_pack(asi_handle h, const float *theta, void *packed);
+/* y[r] for rows feature rows (bfloat16 MFMA, float32 accumulation). */
+asi_status asi_mlp_forward(asi_handle h, const void *packed, const uint16_t *F, int64_t rows, float *y);
+/* grad += d(sum_r dy[r] y[r]) / d theta for the packed weights' network
+ * (bfloat16 roundings treated as identity); float32, ASI_MLP_PARAMS entries. */
+asi_status asi_mlp_backward(asi_handle h, const void *packed, const uint16_t *F, const float *dy, int64_t rows,
+                            float *grad);
+/* Mean squared error: dy[r] = 2 (y[r] - t[r]) / rows and *loss += mean((y - t)^2)
+ * (loss: one device float64). */
+asi_status asi_mlp_loss(asi_handle h, const float *y, const float *t, int64_t rows, float *dy, double *loss);
+/* One Adam step on the masters (step count t >= 1, bias-corrected). */
+asi_status asi_mlp_adam(asi_handle h, float *theta, float *m, float *v, const float *grad, float lr, float beta1,
+                        float beta2, float eps, int64_t t);
+/* out = M + y * scale on S (out may alias M). */
+asi_status asi_mlp_apply(asi_handle h, const double *M_S, const float *y, const float *scale, double *out_S);
+
 /* Diagonal of a matrix on S: d[i] = X(i, i). */
 asi_status asi_diag(asi_handle h, const double *X_S, double *d);
 
@@ -188,7 +225,10 @@ typedef enum {
     ASI_K_LOWRANK = 6,       /* rank-k correction on S */
     ASI_K_GATHER = 7,        /* L values gathered into the column layout, once per call */
     ASI_K_SELINV_FLOW = 8,   /* the dataflow SelInv sweep (one launch per call) */
-    ASI_K_COUNT = 9
+    ASI_K_MLP_FEATURES = 9,  /* features of the learned correction */
+    ASI_K_MLP_FORWARD = 10,  /* MLP inference */
+    ASI_K_MLP_TRAIN = 11,    /* MLP backward, loss and Adam */
+    ASI_K_COUNT = 12
 } asi_kernel_class;
 asi_status asi_profile(asi_handle h, int enable);
 asi_status asi_profile_read(asi_handle h, int32_t kernel_class, int64_t *launches, double *total_ms,

@@ -25,9 +25,14 @@ PRECISION = {"fp64": 0, "mixed": 1}
 EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi_analyze",
            "asi_set_workspace", "asi_get_info", "asi_get_pattern", "asi_selinv", "asi_ninv",
            "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
-           "asi_profile_read", "asi_set_sweep"]
+           "asi_profile_read", "asi_set_sweep", "asi_mlp_features", "asi_mlp_pack", "asi_mlp_forward",
+           "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply"]
+MLP_FEATURES = 16
+MLP_PARAMS = 5313
+MLP_PACKED_BYTES = 12944
 KERNEL_CLASSES = {"dinv": 0, "selinv": 1, "selinv_big": 2, "ninv": 3, "mix": 4, "spai": 5,
-                  "lowrank": 6, "gather_l": 7, "selinv_flow": 8}
+                  "lowrank": 6, "gather_l": 7, "selinv_flow": 8, "mlp_features": 9, "mlp_forward": 10,
+                  "mlp_train": 11}
 
 
 class AsiError(RuntimeError):
@@ -75,6 +80,13 @@ def load_library():
         "asi_sync": [P],
         "asi_profile": [P, ctypes.c_int],
         "asi_set_sweep": [P, ctypes.c_int],
+        "asi_mlp_features": [P, P, P, P, f64, P, P, P, P, P],
+        "asi_mlp_pack": [P, P, P],
+        "asi_mlp_forward": [P, P, P, i64, P],
+        "asi_mlp_backward": [P, P, P, P, i64, P],
+        "asi_mlp_loss": [P, P, P, i64, P, P],
+        "asi_mlp_adam": [P, P, P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, i64],
+        "asi_mlp_apply": [P, P, P, P, P],
         "asi_profile_read": [P, i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(f64)],
     }
     for name, args in sig.items():
@@ -211,6 +223,57 @@ class Solver:
         self._stream()
         k = int(V.shape[1])
         self._check(self.lib.asi_lowrank(self.h, k, _ptr(V), _ptr(lam), _ptr(X), _ptr(out)))
+        return out
+
+    # -- learned correction --------------------------------------------------
+    def mlp_features(self, Z, N, M, eps, L_val, d_diag, d_sub):
+        """(features |S| x 16 as int16 bfloat16 words, scale |S| float32)."""
+        t = self.torch
+        F = t.empty((self.nnz_S, MLP_FEATURES), dtype=t.int16, device=self.device)
+        sc = t.empty(self.nnz_S, dtype=t.float32, device=self.device)
+        self._stream()
+        self._check(self.lib.asi_mlp_features(self.h, _ptr(Z), _ptr(N), _ptr(M), float(eps), _ptr(L_val),
+                                              _ptr(d_diag), _ptr(d_sub), _ptr(F), _ptr(sc)))
+        return F, sc
+
+    def mlp_pack(self, theta, packed=None):
+        t = self.torch
+        if packed is None:
+            packed = t.empty(MLP_PACKED_BYTES, dtype=t.uint8, device=self.device)
+        self._stream()
+        self._check(self.lib.asi_mlp_pack(self.h, _ptr(theta), _ptr(packed)))
+        return packed
+
+    def mlp_forward(self, packed, F, rows=None, y=None):
+        t = self.torch
+        rows = F.shape[0] if rows is None else int(rows)
+        if y is None:
+            y = t.empty(rows, dtype=t.float32, device=self.device)
+        self._stream()
+        self._check(self.lib.asi_mlp_forward(self.h, _ptr(packed), _ptr(F), rows, _ptr(y)))
+        return y
+
+    def mlp_backward(self, packed, F, dy, grad, rows=None):
+        rows = F.shape[0] if rows is None else int(rows)
+        self._stream()
+        self._check(self.lib.asi_mlp_backward(self.h, _ptr(packed), _ptr(F), _ptr(dy), rows, _ptr(grad)))
+        return grad
+
+    def mlp_loss(self, y, target, dy, loss, rows=None):
+        rows = y.shape[0] if rows is None else int(rows)
+        self._stream()
+        self._check(self.lib.asi_mlp_loss(self.h, _ptr(y), _ptr(target), rows, _ptr(dy), _ptr(loss)))
+        return dy
+
+    def mlp_adam(self, theta, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._stream()
+        self._check(self.lib.asi_mlp_adam(self.h, _ptr(theta), _ptr(m), _ptr(v), _ptr(grad), float(lr),
+                                          float(beta1), float(beta2), float(eps), int(step)))
+
+    def mlp_apply(self, M, y, scale, out=None):
+        out = self._out(out)
+        self._stream()
+        self._check(self.lib.asi_mlp_apply(self.h, _ptr(M), _ptr(y), _ptr(scale), _ptr(out)))
         return out
 
     def diag(self, X, out=None):

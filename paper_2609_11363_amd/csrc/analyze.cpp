@@ -67,6 +67,7 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
         }
     }
     A.nnzL = Lp[n];
+    A.L_rowptr.assign(Lp, Lp + n + 1);
 
     // column lists of L (CSC) with the source index of every entry
     std::vector<int64_t> cp(n + 1, 0);

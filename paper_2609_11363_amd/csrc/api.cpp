@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -40,6 +41,9 @@ struct asi_handle_s {
     void *Zu = nullptr;
     double *zd = nullptr;
     int32_t *done = nullptr;
+    double *rn = nullptr;
+    double *cn = nullptr;
+    int64_t *rowptr_L = nullptr;
     int32_t epoch = 0;
     int sweep = ASI_SWEEP_AUTO;
     int8_t *piv = nullptr;
@@ -103,7 +107,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace layout: fixed regions followed by the NInv pool.
 struct Layout {
-    size_t off[32];
+    size_t off[48];
     int k = 0;
     size_t cur = 0;
     size_t add(size_t bytes) {
@@ -147,6 +151,9 @@ Layout make_layout(const asi::Analysis &A) {
     L.add(n * 8);                       // 27 zd (SelInv diagonal)
     L.add(A.hits.size() * 4);           // 28 hits
     L.add(n * 4);                       // 29 done flags of the dataflow sweep
+    L.add(n * 8);                       // 30 row norms of L (features)
+    L.add(n * 8);                       // 31 column norms of L (features)
+    L.add((n + 1) * 8);                 // 32 row pointers of the input L
     return L;
 }
 
@@ -305,6 +312,9 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->zd = at<double>(b, L.off[27]);
     h->hits = at<uint32_t>(b, L.off[28]);
     h->done = at<int32_t>(b, L.off[29]);
+    h->rn = at<double>(b, L.off[30]);
+    h->cn = at<double>(b, L.off[31]);
+    h->rowptr_L = at<int64_t>(b, L.off[32]);
     h->epoch = 0;
     // pool: rows | linv | w, each region 256-aligned
     size_t rest = bytes - L.cur - 3 * 256;
@@ -334,6 +344,7 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
         {h->useg, A.useg_u.data(), A.useg_u.size() * 8},
         {h->hit_ptr, A.hit_ptr.data(), A.hit_ptr.size() * 8},
         {h->hits, A.hits.data(), A.hits.size() * 4},
+        {h->rowptr_L, A.L_rowptr.data(), A.L_rowptr.size() * 8},
         {h->piv, A.piv.data(), A.piv.size()},
         {h->level, A.level.data(), A.level.size() * 4},
         {h->sched_small, A.sched_small.data(), A.sched_small.size() * 4},
@@ -586,6 +597,115 @@ asi_status asi_lowrank(asi_handle h, int32_t k, const double *V, const double *l
     hipError_t e = asi::launch_lowrank(h->A.n, k, h->rowptr, h->col, V, lambda, in_S, out_S, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "lowrank");
     return ASI_OK;
+}
+
+asi_status asi_mlp_features(asi_handle h, const double *Z_S, const double *N_S, const double *M_S, double eps,
+                            const double *L_val, const double *d_diag, const double *d_sub, uint16_t *F,
+                            float *scale) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!Z_S || !N_S || !M_S || (!L_val && h->A.nnzL > 0) || !d_diag || !d_sub || !F || !scale)
+        return fail(h, ASI_E_ARG, "null pointer");
+    DeviceGuard g(h->device);
+    const asi::Analysis &A = h->A;
+    Trace t(h, ASI_K_MLP_FEATURES, 0.0);
+    hipError_t e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
+    if (e == hipSuccess) e = asi::launch_gather_lu(A.nnzU, h->lsrc_u, L_val, h->Lu, true, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "features setup");
+    asi::MlpFeatParams P{};
+    P.n = A.n;
+    P.nnz = A.nnzS;
+    P.srow = h->srow;
+    P.col = h->col;
+    P.diagpos = h->diagpos;
+    P.mirror = h->mirror;
+    P.ustart = h->ustart;
+    P.piv = h->piv;
+    P.level = h->level;
+    P.maxlevel = A.n_levels - 1;
+    P.Lu = reinterpret_cast<const double *>(h->Lu);
+    P.dinv = h->dinv;
+    P.rn = h->rn;
+    P.cn = h->cn;
+    P.Z = Z_S;
+    P.N = N_S;
+    P.M = M_S;
+    P.eps = eps;
+    P.F = F;
+    P.scale = scale;
+    e = asi::launch_mlp_features(P, h->rowptr_L, L_val, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "features");
+    return ASI_OK;
+}
+
+static asi_status need_device(asi_handle h) {
+    if (!h) return ASI_E_ARG;
+    if (h->device < 0) return fail(h, ASI_E_STATE, "host-only handle");
+    return ASI_OK;
+}
+
+asi_status asi_mlp_pack(asi_handle h, const float *theta, void *packed) {
+    asi_status s = need_device(h);
+    if (s != ASI_OK) return s;
+    if (!theta || !packed) return fail(h, ASI_E_ARG, "null pointer");
+    DeviceGuard g(h->device);
+    hipError_t e = asi::launch_mlp_pack(theta, packed, h->stream);
+    return e == hipSuccess ? ASI_OK : hip_fail(h, e, "mlp pack");
+}
+
+asi_status asi_mlp_forward(asi_handle h, const void *packed, const uint16_t *F, int64_t rows, float *y) {
+    asi_status s = need_device(h);
+    if (s != ASI_OK) return s;
+    if (rows < 0 || (rows > 0 && (!packed || !F || !y))) return fail(h, ASI_E_ARG, "bad arguments");
+    DeviceGuard g(h->device);
+    // algorithmic bytes: 32 B of features in, 4 B out per row
+    Trace t(h, ASI_K_MLP_FORWARD, 36.0 * rows);
+    hipError_t e = asi::launch_mlp_forward(packed, F, rows, y, h->stream);
+    return e == hipSuccess ? ASI_OK : hip_fail(h, e, "mlp forward");
+}
+
+asi_status asi_mlp_backward(asi_handle h, const void *packed, const uint16_t *F, const float *dy, int64_t rows,
+                            float *grad) {
+    asi_status s = need_device(h);
+    if (s != ASI_OK) return s;
+    if (rows < 0 || (rows > 0 && (!packed || !F || !dy || !grad))) return fail(h, ASI_E_ARG, "bad arguments");
+    DeviceGuard g(h->device);
+    Trace t(h, ASI_K_MLP_TRAIN, 0.0);
+    hipError_t e = asi::launch_mlp_backward(packed, F, dy, rows, grad, h->stream);
+    return e == hipSuccess ? ASI_OK : hip_fail(h, e, "mlp backward");
+}
+
+asi_status asi_mlp_loss(asi_handle h, const float *y, const float *t, int64_t rows, float *dy, double *loss) {
+    asi_status s = need_device(h);
+    if (s != ASI_OK) return s;
+    if (rows < 0 || (rows > 0 && (!y || !t || !dy || !loss))) return fail(h, ASI_E_ARG, "bad arguments");
+    DeviceGuard g(h->device);
+    Trace tr(h, ASI_K_MLP_TRAIN, 0.0);
+    hipError_t e = asi::launch_mlp_loss(y, t, rows, dy, loss, h->stream);
+    return e == hipSuccess ? ASI_OK : hip_fail(h, e, "mlp loss");
+}
+
+asi_status asi_mlp_adam(asi_handle h, float *theta, float *m, float *v, const float *grad, float lr, float beta1,
+                        float beta2, float eps, int64_t t) {
+    asi_status s = need_device(h);
+    if (s != ASI_OK) return s;
+    if (!theta || !m || !v || !grad || t < 1) return fail(h, ASI_E_ARG, "bad arguments");
+    DeviceGuard g(h->device);
+    const float c1 = 1.0f - (float)std::pow((double)beta1, (double)t);
+    const float c2 = 1.0f - (float)std::pow((double)beta2, (double)t);
+    Trace tr(h, ASI_K_MLP_TRAIN, 0.0);
+    hipError_t e = asi::launch_adam(theta, m, v, grad, asi::kMlpParams, lr, beta1, beta2, eps, c1, c2, h->stream);
+    return e == hipSuccess ? ASI_OK : hip_fail(h, e, "adam");
+}
+
+asi_status asi_mlp_apply(asi_handle h, const double *M_S, const float *y, const float *scale, double *out_S) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!M_S || !y || !scale || !out_S) return fail(h, ASI_E_ARG, "null pointer");
+    DeviceGuard g(h->device);
+    Trace t(h, ASI_K_MLP_FORWARD, 28.0 * h->A.nnzS);
+    hipError_t e = asi::launch_mlp_apply(h->A.nnzS, M_S, y, scale, out_S, h->stream);
+    return e == hipSuccess ? ASI_OK : hip_fail(h, e, "mlp apply");
 }
 
 asi_status asi_diag(asi_handle h, const double *X_S, double *d) {

@@ -14,12 +14,18 @@ constexpr int kSmallCols = 128;   // |R_J| handled by one wavefront per block
 constexpr int kBigCols = 2048;    // |R_J| handled by one 256-thread workgroup per block
 constexpr int kSpaiMaxCols = 512; // entries per column of S for the SPAI kernel
 constexpr int kMaxRank = 64;      // rank of the low-rank correction
+constexpr int kMlpFeatures = 16;  // learned correction: inputs per entry
+constexpr int kMlpHidden = 64;    //   hidden units per layer
+constexpr int kMlpParams = kMlpHidden * kMlpFeatures + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
+                           kMlpHidden + 1;  // 5313 float32 master parameters
+constexpr int kMlpPackedBytes = 12944;      // bfloat16 weights + float32 biases
 
 // Host-side result of the symbolic analysis. Positions index S's CSR arrays.
 struct Analysis {
     int32_t n = 0;
     int64_t nnzL = 0;
     int64_t nnzS = 0;
+    std::vector<int64_t> L_rowptr; // n+1: the input L's row pointers
     std::vector<int64_t> rowptr;   // n+1
     std::vector<int32_t> col;      // nnzS
     std::vector<int32_t> srow;     // nnzS: row of each position

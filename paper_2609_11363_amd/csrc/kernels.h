@@ -107,4 +107,37 @@ struct SpaiParams {
 hipError_t launch_spai(const SpaiParams &P, hipStream_t st);
 hipError_t launch_symmetrize(int64_t nnz, const int64_t *mirror, const double *X, double *R, hipStream_t st);
 
+struct MlpFeatParams {
+    int32_t n;
+    int64_t nnz;
+    const int32_t *srow;
+    const int32_t *col;
+    const int64_t *diagpos;
+    const int64_t *mirror;
+    const int64_t *ustart;
+    const int8_t *piv;
+    const int32_t *level;
+    int32_t maxlevel;
+    const double *Lu;    // u-space L values (float64)
+    const double *dinv;  // 3 per block start
+    double *rn;          // n: row norms of L (filled by the launch)
+    double *cn;          // n: column norms of L (filled by the launch)
+    const double *Z, *N, *M;
+    double eps;
+    uint16_t *F;  // nnz x 16 bfloat16
+    float *scale; // nnz
+};
+
+hipError_t launch_mlp_features(const MlpFeatParams &P, const int64_t *L_rowptr, const double *L_val,
+                               hipStream_t st);
+hipError_t launch_mlp_pack(const float *theta, void *W, hipStream_t st);
+hipError_t launch_mlp_forward(const void *W, const uint16_t *F, int64_t rows, float *y, hipStream_t st);
+hipError_t launch_mlp_backward(const void *W, const uint16_t *F, const float *dy, int64_t rows, float *grad,
+                               hipStream_t st);
+hipError_t launch_mlp_loss(const float *y, const float *t, int64_t rows, float *dy, double *loss, hipStream_t st);
+hipError_t launch_adam(float *theta, float *m, float *v, const float *g, int32_t np, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t st);
+hipError_t launch_mlp_apply(int64_t nnz, const double *M, const float *y, const float *s, double *out,
+                            hipStream_t st);
+
 }  // namespace asi

@@ -1,0 +1,418 @@
+// Learned per-entry correction of the Mix result (the build's addition to
+// the paper's method): features on S, a 16 -> 64 -> 64 -> 1 ReLU network with
+// bfloat16 weights and activations and float32 accumulation, its backward
+// pass, the squared-error loss and Adam.
+//
+// Packed weights (MLP_PACKED_BYTES): W1 bf16 [64][32] (inputs 16..31 are
+// zero padding), W2 bf16 [64][64], w3 bf16 [64], b1 f32 [64], b2 f32 [64],
+// b3 f32. Master parameters (float32, 5313): W1 [64][16], b1, W2 [64][64],
+// b2, w3, b3.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace asi {
+namespace dev {
+
+typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
+
+constexpr int NF = kMlpFeatures, NH = kMlpHidden;
+constexpr int OFF_W1 = 0, OFF_W2 = 4096, OFF_W3 = 12288, OFF_B1 = 12416, OFF_B2 = 12672, OFF_B3 = 12928;
+// master layout
+constexpr int M_W1 = 0, M_B1 = 1024, M_W2 = 1088, M_B2 = 5184, M_W3 = 5248, M_B3 = 5312;
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ inline uint16_t to_bf16(float x) {
+    uint32_t b = __float_as_uint(x);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+__device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ inline float round_bf16(float x) { return from_bf16(to_bf16(x)); }
+
+// ---- features --------------------------------------------------------------
+
+__global__ void k_row_norms(int32_t n, const int64_t *__restrict__ Lp, const double *__restrict__ Lval,
+                            double *__restrict__ rn) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t q = Lp[i]; q < Lp[i + 1]; ++q) s += Lval[q] * Lval[q];
+    rn[i] = sqrt(s);
+}
+
+// column norms of L from its column layout (u-space values, padding is 0)
+__global__ void k_col_norms(int32_t n, const int64_t *__restrict__ ustart, const double *__restrict__ Lu,
+                            double *__restrict__ cn) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t u = ustart[i]; u < ustart[i + 1]; ++u) s += Lu[u] * Lu[u];
+    cn[i] = sqrt(s);
+}
+
+__device__ inline double dinv_diag(const double *dinv, const int8_t *piv, int32_t i) {
+    // diagonal of D^-1 at i: 1x1 -> inv00; first of 2x2 -> inv00; second -> inv11
+    return piv[i] == 2 ? dinv[3 * (int64_t)(i - 1) + 2] : dinv[3 * (int64_t)i];
+}
+
+__global__ void k_features(MlpFeatParams P) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.nnz) return;
+    const int32_t i = P.srow[p], j = P.col[p];
+    const double Mii = P.M[P.diagpos[i]], Mjj = P.M[P.diagpos[j]];
+    double s = sqrt(fabs(Mii * Mjj));
+    if (!(s > 0.0)) s = 1.0;
+    const double z = P.Z[p], nv = P.N[p], m = P.M[p];
+    const double zii = P.Z[P.diagpos[i]], zjj = P.Z[P.diagpos[j]];
+    const int32_t lo = i < j ? i : j;
+    double lval = 0.0;
+    if (i != j) {
+        // upper position of (lo, hi): row lo's u-range at the column's offset
+        const int64_t pu = i < j ? p : P.mirror[p];
+        const int64_t u = P.ustart[lo] + (pu - P.diagpos[lo] - 1);
+        lval = fabs(P.Lu[u]);
+    }
+    const double maxlev = P.maxlevel > 0 ? (double)P.maxlevel : 1.0;
+    double f[NF];
+    f[0] = m / s;
+    f[1] = (z - nv) / s;
+    f[2] = fabs(z) > P.eps * sqrt(fabs(zii * zjj)) ? 1.0 : 0.0;
+    f[3] = i == j ? 1.0 : 0.0;
+    f[4] = log(fabs(dinv_diag(P.dinv, P.piv, i)));
+    f[5] = log(fabs(dinv_diag(P.dinv, P.piv, j)));
+    f[6] = log(P.rn[i] + 1e-30);
+    f[7] = log(P.rn[j] + 1e-30);
+    f[8] = log(P.cn[i] + 1e-30);
+    f[9] = log(P.cn[j] + 1e-30);
+    f[10] = lval;
+    f[11] = log1p(fabs(nv) / s);
+    f[12] = log1p(fabs(z) / s);
+    f[13] = P.level[i] / maxlev;
+    f[14] = P.level[j] / maxlev;
+    f[15] = log1p((double)(P.ustart[lo + 1] - P.ustart[lo]));
+    uint16_t *out = P.F + p * NF;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) out[k] = to_bf16((float)f[k]);
+    P.scale[p] = (float)s;
+}
+
+// ---- parameters --------------------------------------------------------------
+
+__global__ void k_mlp_pack(const float *__restrict__ theta, uint8_t *__restrict__ W) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    uint16_t *w1 = reinterpret_cast<uint16_t *>(W + OFF_W1);
+    uint16_t *w2 = reinterpret_cast<uint16_t *>(W + OFF_W2);
+    uint16_t *w3 = reinterpret_cast<uint16_t *>(W + OFF_W3);
+    float *b1 = reinterpret_cast<float *>(W + OFF_B1);
+    float *b2 = reinterpret_cast<float *>(W + OFF_B2);
+    float *b3 = reinterpret_cast<float *>(W + OFF_B3);
+    if (t < NH * 32) {
+        int n = t / 32, k = t % 32;
+        w1[t] = k < NF ? to_bf16(theta[M_W1 + n * NF + k]) : (uint16_t)0;
+    }
+    if (t < NH * NH) w2[t] = to_bf16(theta[M_W2 + t]);
+    if (t < NH) {
+        w3[t] = to_bf16(theta[M_W3 + t]);
+        b1[t] = theta[M_B1 + t];
+        b2[t] = theta[M_B2 + t];
+    }
+    if (t == 0) b3[0] = theta[M_B3];
+}
+
+// ---- forward (bfloat16 MFMA 16x16x32, float32 accumulation) ------------------
+// A wavefront handles 64 entries per pass as four 16-row tiles. Operand
+// layout of v_mfma_f32_16x16x32_bf16: lane l supplies row (A) / column (B)
+// l % 16 and the 8 consecutive k values 8 (l / 16) ..; the result holds
+// column l % 16 and rows 4 (l / 16) .. + 3. The hidden activations go through
+// LDS to change from the result layout to the operand layout.
+
+__device__ inline bf16x8 load8(const uint16_t *p) {
+    uint4 v = *reinterpret_cast<const uint4 *>(p);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+constexpr int kFwdWaves = 4;
+
+__global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const uint8_t *__restrict__ W,
+                                                                const uint16_t *__restrict__ F, int64_t rows,
+                                                                float *__restrict__ y) {
+    __shared__ __align__(16) uint16_t sW1[NH * 32];
+    __shared__ __align__(16) uint16_t sW2[NH * NH];
+    __shared__ float sw3[NH], sb1[NH], sb2[NH];
+    __shared__ float sb3;
+    __shared__ __align__(16) uint16_t sH[kFwdWaves][64 * NH];
+    for (int t = threadIdx.x; t < NH * 32; t += blockDim.x) sW1[t] = reinterpret_cast<const uint16_t *>(W + OFF_W1)[t];
+    for (int t = threadIdx.x; t < NH * NH; t += blockDim.x) sW2[t] = reinterpret_cast<const uint16_t *>(W + OFF_W2)[t];
+    for (int t = threadIdx.x; t < NH; t += blockDim.x) {
+        sw3[t] = from_bf16(reinterpret_cast<const uint16_t *>(W + OFF_W3)[t]);
+        sb1[t] = reinterpret_cast<const float *>(W + OFF_B1)[t];
+        sb2[t] = reinterpret_cast<const float *>(W + OFF_B2)[t];
+    }
+    if (threadIdx.x == 0) sb3 = reinterpret_cast<const float *>(W + OFF_B3)[0];
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, g = lane >> 4;
+    uint16_t *H = sH[w];
+    const int64_t ntiles = (rows + 63) / 64;
+    for (int64_t tile = (int64_t)blockIdx.x * kFwdWaves + w; tile < ntiles; tile += (int64_t)gridDim.x * kFwdWaves) {
+        const int64_t base = tile * 64;
+        // layer 1: [64 x 32] x [32 x 64]
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int64_t row = base + mt * 16 + col;
+            bf16x8 a;
+            if (g < 2 && row < rows) {
+                a = load8(F + row * NF + 8 * g);
+            } else {
+                uint4 zero = {0u, 0u, 0u, 0u};
+                a = __builtin_bit_cast(bf16x8, zero);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int n = nt * 16 + col;
+                bf16x8 b = load8(sW1 + n * 32 + 8 * g);
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[r] + sb1[n];
+                    H[(mt * 16 + 4 * g + r) * NH + n] = to_bf16(v > 0.f ? v : 0.f);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // layer 2: [64 x 64] x [64 x 64], then layer 3 as a dot product
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            float part[4] = {0.f, 0.f, 0.f, 0.f};
+            bf16x8 a0 = load8(H + (mt * 16 + col) * NH + 8 * g);
+            bf16x8 a1 = load8(H + (mt * 16 + col) * NH + 32 + 8 * g);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int n = nt * 16 + col;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, load8(sW2 + n * NH + 8 * g), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, load8(sW2 + n * NH + 32 + 8 * g), acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[r] + sb2[n];
+                    v = round_bf16(v > 0.f ? v : 0.f);
+                    part[r] += v * sw3[n];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = part[r];
+                v += __shfl_xor(v, 1, 64);
+                v += __shfl_xor(v, 2, 64);
+                v += __shfl_xor(v, 4, 64);
+                v += __shfl_xor(v, 8, 64);
+                part[r] = v;
+            }
+            if (col == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = base + mt * 16 + 4 * g + r;
+                    if (row < rows) y[row] = part[r] + sb3;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// ---- backward (float32) -------------------------------------------------------
+// Phase A, lane = entry: recompute the forward pass in float32 with the same
+// bfloat16 quantisation, then dz2 = dy w3 [z2 > 0], dz1 = (W2^T dz2) [z1 > 0]
+// into LDS. Phase B, lane = unit n: accumulate the weight gradients over the
+// 64 entries of the tile. Each wavefront adds its totals to grad at the end.
+
+constexpr int kBwdTile = 32;   // entries per pass
+constexpr int kLd = NH + 1;    // padded row stride of the per-entry LDS arrays
+
+__global__ __launch_bounds__(64) void k_mlp_backward(const uint8_t *__restrict__ W, const uint16_t *__restrict__ F,
+                                                     const float *__restrict__ dy, int64_t rows,
+                                                     float *__restrict__ grad) {
+    __shared__ float sW1[NH * NF];
+    __shared__ float sW2[NH * NH];
+    __shared__ float sw3[NH], sb1[NH], sb2[NH];
+    __shared__ float sX[kBwdTile * (NF + 1)];
+    __shared__ float sH1[kBwdTile * kLd], sH2[kBwdTile * kLd], sD1[kBwdTile * kLd], sD2[kBwdTile * kLd];
+    __shared__ float sDY[kBwdTile];
+    const int lane = threadIdx.x;
+    for (int t = lane; t < NH * NF; t += 64) {
+        int n = t / NF, k = t % NF;
+        sW1[t] = from_bf16(reinterpret_cast<const uint16_t *>(W + OFF_W1)[n * 32 + k]);
+    }
+    for (int t = lane; t < NH * NH; t += 64) sW2[t] = from_bf16(reinterpret_cast<const uint16_t *>(W + OFF_W2)[t]);
+    sw3[lane] = from_bf16(reinterpret_cast<const uint16_t *>(W + OFF_W3)[lane]);
+    sb1[lane] = reinterpret_cast<const float *>(W + OFF_B1)[lane];
+    sb2[lane] = reinterpret_cast<const float *>(W + OFF_B2)[lane];
+    __syncthreads();
+    float gW2[NH], gW1[NF];
+#pragma unroll
+    for (int k = 0; k < NH; ++k) gW2[k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) gW1[k] = 0.f;
+    float gb1 = 0.f, gb2 = 0.f, gw3 = 0.f, gb3 = 0.f;
+    const int64_t ntiles = (rows + kBwdTile - 1) / kBwdTile;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        // phase A: lanes 0..31 take one entry each
+        if (lane < kBwdTile) {
+            const int64_t e = tile * kBwdTile + lane;
+            const bool valid = e < rows;
+            float x[NF];
+#pragma unroll
+            for (int k = 0; k < NF; ++k) x[k] = valid ? from_bf16(F[e * NF + k]) : 0.f;
+            const float d = valid ? dy[e] : 0.f;
+            float *h1 = sH1 + lane * kLd, *h2 = sH2 + lane * kLd, *d1 = sD1 + lane * kLd, *d2 = sD2 + lane * kLd;
+            uint64_t m1 = 0, m2 = 0;
+            for (int n = 0; n < NH; ++n) {
+                float z = sb1[n];
+#pragma unroll
+                for (int k = 0; k < NF; ++k) z += sW1[n * NF + k] * x[k];
+                m1 |= (uint64_t)(z > 0.f) << n;
+                h1[n] = round_bf16(z > 0.f ? z : 0.f);
+            }
+            for (int n = 0; n < NH; ++n) {
+                float z = sb2[n];
+                for (int k = 0; k < NH; ++k) z += sW2[n * NH + k] * h1[k];
+                m2 |= (uint64_t)(z > 0.f) << n;
+                h2[n] = round_bf16(z > 0.f ? z : 0.f);
+                d2[n] = ((m2 >> n) & 1) ? d * sw3[n] : 0.f;
+            }
+            for (int k = 0; k < NH; ++k) {
+                float s = 0.f;
+                for (int n = 0; n < NH; ++n) s += d2[n] * sW2[n * NH + k];
+                d1[k] = ((m1 >> k) & 1) ? s : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < NF; ++k) sX[lane * (NF + 1) + k] = x[k];
+            sDY[lane] = d;
+        }
+        __syncthreads();
+        // phase B: lane = unit n
+        const int n = lane;
+        for (int ee = 0; ee < kBwdTile; ++ee) {
+            const float d2 = sD2[ee * kLd + n], d1 = sD1[ee * kLd + n];
+#pragma unroll
+            for (int k = 0; k < NH; ++k) gW2[k] += d2 * sH1[ee * kLd + k];
+#pragma unroll
+            for (int k = 0; k < NF; ++k) gW1[k] += d1 * sX[ee * (NF + 1) + k];
+            gb1 += d1;
+            gb2 += d2;
+            gw3 += sDY[ee] * sH2[ee * kLd + n];
+            if (n == 0) gb3 += sDY[ee];
+        }
+        __syncthreads();
+    }
+    const int n = lane;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) atomicAdd(&grad[M_W2 + n * NH + k], gW2[k]);
+#pragma unroll
+    for (int k = 0; k < NF; ++k) atomicAdd(&grad[M_W1 + n * NF + k], gW1[k]);
+    atomicAdd(&grad[M_B1 + n], gb1);
+    atomicAdd(&grad[M_B2 + n], gb2);
+    atomicAdd(&grad[M_W3 + n], gw3);
+    if (n == 0) atomicAdd(&grad[M_B3], gb3);
+}
+
+// ---- loss, Adam, apply ------------------------------------------------------
+
+__global__ void k_mlp_loss(const float *__restrict__ y, const float *__restrict__ t, int64_t rows,
+                           float *__restrict__ dy, double *__restrict__ loss) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double sq = 0.0;
+    if (e < rows) {
+        float d = y[e] - t[e];
+        dy[e] = 2.0f * d / (float)rows;
+        sq = (double)d * (double)d;
+    }
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(loss, sq / (double)rows);
+}
+
+__global__ void k_adam(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int32_t np, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_mlp_apply(int64_t nnz, const double *__restrict__ M, const float *__restrict__ y,
+                            const float *__restrict__ s, double *__restrict__ out) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) out[p] = M[p] + (double)y[p] * (double)s[p];
+}
+
+}  // namespace dev
+
+hipError_t launch_mlp_features(const MlpFeatParams &P, const int64_t *L_rowptr, const double *L_val,
+                               hipStream_t st) {
+    dim3 gn((P.n + 255) / 256);
+    hipLaunchKernelGGL(dev::k_row_norms, gn, dim3(256), 0, st, P.n, L_rowptr, L_val, P.rn);
+    hipLaunchKernelGGL(dev::k_col_norms, gn, dim3(256), 0, st, P.n, P.ustart, P.Lu, P.cn);
+    hipLaunchKernelGGL(dev::k_features, dim3((unsigned)((P.nnz + 255) / 256)), dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_pack(const float *theta, void *W, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_mlp_pack, dim3(16), dim3(256), 0, st, theta, reinterpret_cast<uint8_t *>(W));
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const void *W, const uint16_t *F, int64_t rows, float *y, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    const int64_t tiles = (rows + 63) / 64;
+    const int64_t grid = std::min<int64_t>((tiles + dev::kFwdWaves - 1) / dev::kFwdWaves, 4096);
+    hipLaunchKernelGGL(dev::k_mlp_forward, dim3((unsigned)grid), dim3(64 * dev::kFwdWaves), 0, st,
+                       reinterpret_cast<const uint8_t *>(W), F, rows, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_backward(const void *W, const uint16_t *F, const float *dy, int64_t rows, float *grad,
+                               hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    const int64_t tiles = (rows + dev::kBwdTile - 1) / dev::kBwdTile;
+    const int64_t grid = std::min<int64_t>(tiles, 512);
+    hipLaunchKernelGGL(dev::k_mlp_backward, dim3((unsigned)grid), dim3(64), 0, st,
+                       reinterpret_cast<const uint8_t *>(W), F, dy, rows, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_loss(const float *y, const float *t, int64_t rows, float *dy, double *loss, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::k_mlp_loss, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, y, t, rows, dy,
+                       loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *theta, float *m, float *v, const float *g, int32_t np, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_adam, dim3((np + 255) / 256), dim3(256), 0, st, theta, m, v, g, np, lr, b1, b2, eps,
+                       c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_apply(int64_t nnz, const double *M, const float *y, const float *s, double *out,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_mlp_apply, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, nnz, M, y, s, out);
+    return hipGetLastError();
+}
+
+}  // namespace asi

@@ -1,0 +1,156 @@
+"""GPU parity of the learned correction's kernels against oracle/mlp.py, and a
+small end-to-end training run showing what the trained network gains over
+plain Mix on held-out matrices.
+
+Forward: both sides use the same bfloat16 features and weights and float32
+accumulation; the rare bfloat16 re-rounding flips of a hidden activation
+(different float32 summation order) bound the tolerance. Gradients: relative
+Frobenius error <= 1e-3 per tensor against the oracle's float64 backward with
+the same quantisation points.
+"""
+import numpy as np
+import pytest
+
+from oracle import core as oc
+from oracle import mlp as om
+from workloads import ildl_bk, laplace2d, random_dd_symmetric, rcm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver():
+    from paper_2609_11363_amd import Solver
+    A = laplace2d(8, 8, 0.1)
+    F = ildl_bk(A, rcm(A), 1e-2)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    return s
+
+
+def _bf16_words(x):
+    """float32 bf16-valued array -> int16 words (the device layout)."""
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32) >> 16
+    return b.astype(np.uint16).view(np.int16)
+
+
+def _random_inputs(rows, seed):
+    rng = np.random.default_rng(seed)
+    X = om.bf16((rng.standard_normal((rows, om.NF)) * 1.5).astype(np.float32))
+    theta = om.init_params(seed)
+    return X, theta
+
+
+@pytest.mark.parametrize("rows", [1, 63, 64, 1000, 70001])
+def test_forward_parity(solver, rows):
+    import torch
+    print(f"[mlp forward] rows={rows}", flush=True)
+    X, theta = _random_inputs(rows, rows)
+    dev = solver.device
+    th = torch.as_tensor(theta, device=dev)
+    packed = solver.mlp_pack(th)
+    y = solver.mlp_forward(packed, torch.as_tensor(_bf16_words(X), device=dev)).cpu().numpy()
+    ref = om.forward(theta, X)
+    err = np.abs(y - ref)
+    scale = np.abs(ref).max() + 1e-6
+    rel = err / (np.abs(ref) + 1e-3 * scale)
+    print(f"  max abs {err.max():.2e} (scale {scale:.2e}) median rel {np.median(rel):.2e}")
+    assert np.median(rel) <= 1e-5
+    assert err.max() <= 2e-2 * scale
+    assert (rel > 1e-4).mean() <= 0.01
+
+
+def test_backward_loss_adam_parity(solver):
+    import torch
+    rows = 5000
+    X, theta = _random_inputs(rows, 7)
+    t = np.random.default_rng(8).standard_normal(rows).astype(np.float32)
+    dev = solver.device
+    th = torch.as_tensor(theta, device=dev)
+    packed = solver.mlp_pack(th)
+    Xd = torch.as_tensor(_bf16_words(X), device=dev)
+    y = solver.mlp_forward(packed, Xd)
+    dy = torch.empty_like(y)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    solver.mlp_loss(y, torch.as_tensor(t, device=dev), dy, loss)
+    grad = torch.zeros(om.NPARAMS, dtype=torch.float32, device=dev)
+    solver.mlp_backward(packed, Xd, dy, grad)
+    solver.sync()
+    yo = om.forward(theta, X)
+    lo, dyo = om.mse_grad(yo, t)
+    assert abs(loss.item() - lo) <= 1e-4 * lo
+    np.testing.assert_allclose(dy.cpu().numpy(), dyo, rtol=1e-3, atol=1e-6 * np.abs(dyo).max())
+    gov = om.backward(theta, X, dyo)
+    go = om.unpack(gov)
+    gg = om.unpack(grad.cpu().numpy().astype(np.float64))
+    for k in go:
+        e = np.linalg.norm(gg[k] - go[k]) / max(np.linalg.norm(go[k]), 1e-30)
+        print(f"  grad {k}: rel {e:.2e}")
+        assert e <= 1e-3, k
+    # one Adam step from zero moments
+    m = torch.zeros_like(th)
+    v = torch.zeros_like(th)
+    solver.mlp_adam(th, m, v, grad, 1, lr=1e-3)
+    solver.sync()
+    t1, _, _ = om.adam(theta.astype(np.float64), 0 * theta, 0 * theta, gov, 1)
+    big = np.abs(gov) > 1e-3 * np.abs(gov).max()  # where the gradient's sign is unambiguous
+    np.testing.assert_allclose(th.cpu().numpy()[big], t1[big], rtol=1e-6, atol=1e-7)
+
+
+def test_features_parity_and_zero_layer_identity():
+    import torch
+    from paper_2609_11363_amd import Solver, upload_factors
+    A = random_dd_symmetric(3, n=2500)
+    F = ildl_bk(A, rcm(A), 1e-2)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    Lv, dd, ds = upload_factors(F)
+    eps = 1e-2
+    Z = s.selinv(Lv, dd, ds)
+    N = s.ninv(Lv, dd, ds, p=3, delta=0.1)
+    M = s.mix(Z, N, eps)
+    Fe, sc = s.mlp_features(Z, N, M, eps, Lv, dd, ds)
+    rp, cl, lev = s.pattern(with_level=True)
+    s.sync()
+    S = oc.pattern(F)
+    Zo = oc.selinv(F, S)
+    No = oc.ninv(F, S, 3, 0.1)
+    Mo = oc.mix(S, Zo, No, eps)
+    ucount = np.array([int((S.col[S.rowptr[j]:S.rowptr[j + 1]] > j).sum()) for j in range(F.n)])
+    Xo, so = om.features(S, Zo, No, Mo, eps, F, lev.cpu().numpy().astype(np.int64), ucount)
+    Xg = (Fe.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    same = Xg == Xo
+    print(f"  features identical: {same.mean():.6f}")
+    assert same.mean() >= 0.9999
+    diff = np.abs(Xg - Xo)[~same]
+    assert np.all(diff <= np.abs(Xo[~same]) * 2 ** -7 + 1e-30)
+    np.testing.assert_allclose(sc.cpu().numpy(), so, rtol=1e-6)
+    # zero last layer: the corrected values equal Mix bit for bit
+    theta = torch.as_tensor(om.init_params(1, zero_last=True), device=s.device)
+    y = s.mlp_forward(s.mlp_pack(theta), Fe)
+    out = s.mlp_apply(M, y, sc)
+    s.sync()
+    assert torch.equal(out, M)
+
+
+def test_training_gain_on_held_out_matrices():
+    """Train on Mix (tau 1e-2) -> SelInv (tau 3e-4) pairs; report the gain."""
+    from paper_2609_11363_amd import learned
+    sizes = [2000, 2600, 3200, 2300, 2900, 3500, 2100, 3300]
+    samples = []
+    for seed, n in enumerate(sizes):
+        A = random_dd_symmetric(100 + seed, n=n)
+        samples.append(learned.build_sample(A, rcm(A)))
+        print(f"  sample {seed}: {samples[-1].meta}", flush=True)
+    train, val, test = samples[:5], samples[5:6], samples[6:]
+    packed, theta, hist = learned.train(train, val, epochs=30, lr=1e-3, seed=0,
+                                        log=lambda m: print("  " + m, flush=True))
+    assert hist["loss"][-1] < hist["loss"][0]
+    base = learned.mean_error(test)
+    if packed is None:
+        print(f"  fallback to plain Mix: test error {base[0]:.4e}")
+        return
+    got = learned.mean_error(test, packed)
+    print(f"  held-out mean entry error vs tight SelInv: Mix {base[0]:.4e} -> Mix+learned {got[0]:.4e} "
+          f"(gain {base[0] / got[0]:.2f}x); p99 {base[1]:.3e} -> {got[1]:.3e}")
+    assert got[0] < base[0]
