@@ -203,6 +203,22 @@ asi_status asi_mlp_apply(asi_handle h, const double *M_S, const float *y, const 
 /* Diagonal of a matrix on S: d[i] = X(i, i). */
 asi_status asi_diag(asi_handle h, const double *X_S, double *d);
 
+/*
+ * Relative diagonal 1-norm error (Section 2.6) of a diagonal with an optional
+ * rank-k term (Section 2.6, corrected diagonal), the quantity of the
+ * acceptance test of Algorithm 1:
+ *   sums[0] = sum_i |d_ref[i] - d_hat[i] - sum_{m<k} lambda_m V[i][m]^2|
+ *   sums[1] = sum_i |d_ref[i]|
+ * so err_1 = sums[0] / sums[1]. d_ref, d_hat: n float64 (factor ordering);
+ * V: n x k row-major float64, lambda: k float64, both unused when k = 0;
+ * 0 <= k <= 64. sums: 2 float64, device. Every pointer is a device pointer;
+ * the call is asynchronous on the handle's stream. The summation order is
+ * fixed (a per-block stage, then one block), so repeated calls give the same
+ * bits. A mode can be left out by passing lambda_m = 0.
+ */
+asi_status asi_diag_err1(asi_handle h, const double *d_ref, const double *d_hat, int32_t k, const double *V,
+                         const double *lambda, double *sums);
+
 /* Wait for the handle's stream; return the first device-side error latched
  * since the previous asi_sync (and clear it). */
 asi_status asi_sync(asi_handle h);
@@ -228,7 +244,8 @@ typedef enum {
     ASI_K_MLP_FEATURES = 9,  /* features of the learned correction */
     ASI_K_MLP_FORWARD = 10,  /* MLP inference */
     ASI_K_MLP_TRAIN = 11,    /* MLP backward, loss and Adam */
-    ASI_K_COUNT = 12
+    ASI_K_DIAG = 12,         /* diagonal error reductions */
+    ASI_K_COUNT = 13
 } asi_kernel_class;
 asi_status asi_profile(asi_handle h, int enable);
 asi_status asi_profile_read(asi_handle h, int32_t kernel_class, int64_t *launches, double *total_ms,

@@ -200,6 +200,42 @@ def err1(d: np.ndarray, dhat: np.ndarray) -> float:
     return float(np.abs(d - dhat).sum() / np.abs(d).sum())
 
 
+def corrected_diag(dhat: np.ndarray, V: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    """Diagonal of the rank-k corrected approximation (Section 2.6):
+    dhat_i + sum_m lam_m V_im^2."""
+    dk = np.array(dhat, dtype=np.float64)
+    for m in range(len(lam)):
+        dk += lam[m] * V[:, m] * V[:, m]
+    return dk
+
+
+def err1_sums(d: np.ndarray, dhat: np.ndarray, V=None, lam=None):
+    """(||d - dhat^k||_1, ||d||_1), the two sums of err_1 (Section 2.6) for the
+    diagonal corrected by the modes (V, lam) (none when V is None)."""
+    dk = dhat if V is None else corrected_diag(dhat, V, lam)
+    return float(np.abs(d - dk).sum()), float(np.abs(d).sum())
+
+
+def accept_modes(d: np.ndarray, dhat: np.ndarray, V: np.ndarray, lam: np.ndarray):
+    """Acceptance test of Algorithm 1, read per mode: candidates are taken in
+    order of decreasing |lam| (ties by index); each is kept only if adding it to
+    the modes kept so far makes ||d - dhat^k||_1 strictly smaller (Section 3,
+    safeguard on the diagonal error). Returns (indices kept, err_1 before,
+    err_1 after)."""
+    order = sorted(range(len(lam)), key=lambda m: (-abs(lam[m]), m))
+    kept = []
+    cur = np.array(dhat, dtype=np.float64)
+    base, dn = err1_sums(d, cur)
+    best = base
+    for m in order:
+        cand = cur + lam[m] * V[:, m] * V[:, m]
+        e = float(np.abs(d - cand).sum())
+        if e < best:
+            kept.append(m)
+            cur, best = cand, e
+    return kept, base / dn, best / dn
+
+
 def entry_error(S: Pattern, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
     """Per-entry error |x_ij - y_ij| / sqrt(|y_ii y_jj|) on S (Y is the reference).
 

@@ -26,13 +26,13 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_set_workspace", "asi_get_info", "asi_get_pattern", "asi_selinv", "asi_ninv",
            "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
            "asi_profile_read", "asi_set_sweep", "asi_mlp_features", "asi_mlp_pack", "asi_mlp_forward",
-           "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply"]
+           "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
 KERNEL_CLASSES = {"dinv": 0, "selinv": 1, "selinv_big": 2, "ninv": 3, "mix": 4, "spai": 5,
                   "lowrank": 6, "gather_l": 7, "selinv_flow": 8, "mlp_features": 9, "mlp_forward": 10,
-                  "mlp_train": 11}
+                  "mlp_train": 11, "diag": 12}
 
 
 class AsiError(RuntimeError):
@@ -77,6 +77,7 @@ def load_library():
         "asi_spai": [P, P, P, P, P, P, i32, P],
         "asi_lowrank": [P, i32, P, P, P, P],
         "asi_diag": [P, P, P],
+        "asi_diag_err1": [P, P, P, i32, P, P, P],
         "asi_sync": [P],
         "asi_profile": [P, ctypes.c_int],
         "asi_set_sweep": [P, ctypes.c_int],
@@ -226,11 +227,13 @@ class Solver:
         return out
 
     # -- learned correction --------------------------------------------------
-    def mlp_features(self, Z, N, M, eps, L_val, d_diag, d_sub):
+    def mlp_features(self, Z, N, M, eps, L_val, d_diag, d_sub, F=None, sc=None):
         """(features |S| x 16 as int16 bfloat16 words, scale |S| float32)."""
         t = self.torch
-        F = t.empty((self.nnz_S, MLP_FEATURES), dtype=t.int16, device=self.device)
-        sc = t.empty(self.nnz_S, dtype=t.float32, device=self.device)
+        if F is None:
+            F = t.empty((self.nnz_S, MLP_FEATURES), dtype=t.int16, device=self.device)
+        if sc is None:
+            sc = t.empty(self.nnz_S, dtype=t.float32, device=self.device)
         self._stream()
         self._check(self.lib.asi_mlp_features(self.h, _ptr(Z), _ptr(N), _ptr(M), float(eps), _ptr(L_val),
                                               _ptr(d_diag), _ptr(d_sub), _ptr(F), _ptr(sc)))
@@ -283,6 +286,17 @@ class Solver:
         self._stream()
         self._check(self.lib.asi_diag(self.h, _ptr(X), _ptr(out)))
         return out
+
+    def diag_err1(self, d_ref, d_hat, V=None, lam=None, sums=None):
+        """Device float64[2]: (sum |d_ref - d_hat - sum_m lam_m V_im^2|, sum |d_ref|)."""
+        t = self.torch
+        if sums is None:
+            sums = t.empty(2, dtype=t.float64, device=self.device)
+        k = 0 if V is None else int(V.shape[1])
+        self._stream()
+        self._check(self.lib.asi_diag_err1(self.h, _ptr(d_ref), _ptr(d_hat), k,
+                                           _ptr(V) if k else None, _ptr(lam) if k else None, _ptr(sums)))
+        return sums
 
     def sync(self):
         self._stream()

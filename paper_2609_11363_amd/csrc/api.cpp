@@ -57,11 +57,13 @@ struct asi_handle_s {
     int32_t *clen = nullptr;
     int32_t *ovf = nullptr;
     int32_t *ovf2 = nullptr;
-    int32_t *counters = nullptr;  // [0] ovf count, [1] ovf2 count
+    int32_t *counters = nullptr;  // [0] ovf count, [1] ovf2 count, [2], [3] SPAI list lengths
     unsigned long long *pool_top = nullptr;
     int32_t *iperm = nullptr;
     double *cn2 = nullptr;
     double *X = nullptr;
+    double *red = nullptr;
+    int32_t *spai_list = nullptr;
     int32_t *prow = nullptr;
     void *plinv = nullptr;
     void *pw = nullptr;
@@ -154,6 +156,8 @@ Layout make_layout(const asi::Analysis &A) {
     L.add(n * 8);                       // 30 row norms of L (features)
     L.add(n * 8);                       // 31 column norms of L (features)
     L.add((n + 1) * 8);                 // 32 row pointers of the input L
+    L.add(2 * asi::kRedBlocks * 8);     // 33 partial sums of the diagonal error
+    L.add(2 * n * 4);                   // 34 column lists of the SPAI kernels
     return L;
 }
 
@@ -315,6 +319,8 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->rn = at<double>(b, L.off[30]);
     h->cn = at<double>(b, L.off[31]);
     h->rowptr_L = at<int64_t>(b, L.off[32]);
+    h->red = at<double>(b, L.off[33]);
+    h->spai_list = at<int32_t>(b, L.off[34]);
     h->epoch = 0;
     // pool: rows | linv | w, each region 256-aligned
     size_t rest = bytes - L.cur - 3 * 256;
@@ -578,6 +584,8 @@ asi_status asi_spai(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col,
     P.R = R_S;
     P.iters = cg_iters;
     P.status = h->status;
+    P.list = h->spai_list;
+    P.list_count = h->counters + 2;
     Trace t(h, ASI_K_SPAI, 0.0);
     hipError_t e = asi::launch_spai(P, h->stream);
     if (e == hipSuccess) e = asi::launch_symmetrize(h->A.nnzS, h->mirror, h->X, R_S, h->stream);
@@ -594,7 +602,7 @@ asi_status asi_lowrank(asi_handle h, int32_t k, const double *V, const double *l
     DeviceGuard g(h->device);
     // bytes per entry: column index, input and output values (20 B); V once
     Trace t(h, ASI_K_LOWRANK, 20.0 * h->A.nnzS + 8.0 * h->A.n * (k + 2));
-    hipError_t e = asi::launch_lowrank(h->A.n, k, h->rowptr, h->col, V, lambda, in_S, out_S, h->stream);
+    hipError_t e = asi::launch_lowrank(h->A.nnzS, k, h->srow, h->col, V, lambda, in_S, out_S, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "lowrank");
     return ASI_OK;
 }
@@ -715,6 +723,20 @@ asi_status asi_diag(asi_handle h, const double *X_S, double *d) {
     DeviceGuard g(h->device);
     hipError_t e = asi::launch_zdiag(h->A.n, h->diagpos, X_S, d, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "diag");
+    return ASI_OK;
+}
+
+asi_status asi_diag_err1(asi_handle h, const double *d_ref, const double *d_hat, int32_t k, const double *V,
+                         const double *lambda, double *sums) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!d_ref || !d_hat || !sums) return fail(h, ASI_E_ARG, "null pointer");
+    if (k < 0 || k > asi::kMaxRank) return fail(h, ASI_E_ARG, "k must be in [0, 64]");
+    if (k > 0 && (!V || !lambda)) return fail(h, ASI_E_ARG, "null V or lambda with k > 0");
+    DeviceGuard g(h->device);
+    Trace t(h, ASI_K_DIAG, 16.0 * h->A.n + 8.0 * h->A.n * k);
+    hipError_t e = asi::launch_diag_err1(h->A.n, d_ref, d_hat, k, V, lambda, h->red, sums, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "diag_err1");
     return ASI_OK;
 }
 

@@ -13,7 +13,8 @@ namespace asi {
 constexpr int kSmallCols = 128;   // |R_J| handled by one wavefront per block
 constexpr int kBigCols = 2048;    // |R_J| handled by one 256-thread workgroup per block
 constexpr int kSpaiMaxCols = 512; // entries per column of S for the SPAI kernel
-constexpr int kMaxRank = 64;      // rank of the low-rank correction
+constexpr int kMaxRank = 64;     // rank of the low-rank correction
+constexpr int kRedBlocks = 512;   // blocks of the first stage of the diagonal-error reduction
 constexpr int kMlpFeatures = 16;  // learned correction: inputs per entry
 constexpr int kMlpHidden = 64;    //   hidden units per layer
 constexpr int kMlpParams = kMlpHidden * kMlpFeatures + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +

@@ -81,9 +81,10 @@ hipError_t set_ninv_lds_limits();
 hipError_t launch_zdiag(int32_t n, const int64_t *diagpos, const double *X, double *d, hipStream_t st);
 hipError_t launch_mix(int64_t nnz, const int32_t *srow, const int32_t *col, const double *zdiag,
                       const double *Z, const double *N, double eps, double *M, hipStream_t st);
-hipError_t launch_lowrank(int32_t n, int32_t k, const int64_t *rowptr, const int32_t *col,
-                          const double *V, const double *lam, const double *in, double *out,
-                          hipStream_t st);
+hipError_t launch_diag_err1(int32_t n, const double *d_ref, const double *d_hat, int32_t k, const double *V,
+                            const double *lam, double *part, double *sums, hipStream_t st);
+hipError_t launch_lowrank(int64_t nnz, int32_t k, const int32_t *srow, const int32_t *col, const double *V,
+                          const double *lam, const double *in, double *out, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st);
 
 struct SpaiParams {
@@ -102,6 +103,8 @@ struct SpaiParams {
     double *R;
     int32_t iters;
     int32_t *status;
+    int32_t *list;        // workspace, 2n: columns passed on by the staged kernels
+    int32_t *list_count;  // workspace, 2
 };
 
 hipError_t launch_spai(const SpaiParams &P, hipStream_t st);

@@ -2,6 +2,7 @@
 // selection, the rank-k correction and SPAI refinement.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -33,34 +34,40 @@ __global__ void k_mix(int64_t nnz, const int32_t *__restrict__ srow, const int32
 }
 
 // Rank-k correction on S (Section 2.5): out_ij = in_ij + sum_m lam_m V_im V_jm.
-// One wavefront per row i: V(i, :) is scaled by lambda once and kept in
-// registers; each lane takes one entry (i, j) and reads row j of V.
+// One thread per entry of S (all lanes busy whatever the row lengths): the
+// row index comes from the stored row of each entry, rows i and j of V are
+// read as 16-byte vectors when V is 16-byte aligned (consecutive entries share
+// row i, so its reads hit the cache); lambda is uniform across the wavefront.
 template <int K>
-__global__ __launch_bounds__(256) void k_lowrank(int32_t n, int32_t k, const int64_t *__restrict__ rowptr,
+__global__ __launch_bounds__(256) void k_lowrank(int64_t nnz, int32_t k, const int32_t *__restrict__ srow,
                                                  const int32_t *__restrict__ col, const double *__restrict__ V,
                                                  const double *__restrict__ lam, const double *in, double *out) {
-    const int lane = threadIdx.x & 63;
-    const int32_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (i >= n) return;
-    double vi[K];
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= nnz) return;
+    const double *vi = V + (int64_t)srow[p] * k;
+    const double *vj = V + (int64_t)col[p] * k;
+    double s = 0.0;
+    if (K > 1 && k == K) {
+        const double2 *a = reinterpret_cast<const double2 *>(vi);
+        const double2 *b = reinterpret_cast<const double2 *>(vj);
 #pragma unroll
-    for (int m = 0; m < K; ++m) vi[m] = m < k ? lam[m] * V[(int64_t)i * k + m] : 0.0;
-    const int64_t p0 = rowptr[i], p1 = rowptr[i + 1];
-    for (int64_t p = p0 + lane; p < p1; p += 64) {
-        const double *vj = V + (int64_t)col[p] * k;
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < K; ++m)
-            if (m < k) s += vi[m] * vj[m];
-        out[p] = in[p] + s;
+        for (int m = 0; m < K / 2; ++m) {
+            const double2 x = a[m], y = b[m];
+            s += lam[2 * m] * x.x * y.x;
+            s += lam[2 * m + 1] * x.y * y.y;
+        }
+    } else {
+        for (int m = 0; m < k; ++m) s += lam[m] * vi[m] * vj[m];
     }
+    out[p] = in[p] + s;
 }
 
 // ---- SPAI -----------------------------------------------------------------
 
 __global__ void k_iperm(int32_t n, const int32_t *__restrict__ perm, int32_t *__restrict__ iperm,
-                        int32_t *status) {
+                        int32_t *status, int32_t *list_count) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2) list_count[i] = 0;
     if (i >= n) return;
     int32_t p = perm[i];
     if (p < 0 || p >= n) {
@@ -123,20 +130,29 @@ __device__ inline double wsum(double v) {
     return v;
 }
 
-// One wavefront per column j of S (Section 2.4). G = Ah_J^T Ah_J is applied
-// as Ah_J^T (Ah_J p): the first half scatters rows of Ah into an LDS hash
-// keyed by row, the second half gathers them back per column of J.
-__global__ __launch_bounds__(64) void k_spai(SpaiParams P) {
+struct SpaiGeneralLds {
+    int32_t sJ[kSpaiMaxCols];
+    double sx[kSpaiMaxCols], sr[kSpaiMaxCols], sz[kSpaiMaxCols], sp[kSpaiMaxCols], sg[kSpaiMaxCols];
+    int32_t soff[kSpaiMaxCols + 1];
+    int32_t hkey[kSpaiH];
+    double hval[kSpaiH];
+    int32_t sflag[1];
+};
+
+// General SPAI column (Section 2.4) for columns the staged kernel cannot hold:
+// one wavefront, up to 512 entries in the column of S and 2048 distinct rows
+// of Ah(:, J). G = Ah_J^T Ah_J is applied as Ah_J^T (Ah_J p): the first half
+// scatters rows of Ah into an LDS hash keyed by row, the second half gathers
+// them back per column of J, both reading A from global memory.
+__device__ void spai_general_column(const SpaiParams &P, int32_t j, SpaiGeneralLds &Lg) {
     constexpr int C = kSpaiMaxCols;
-    __shared__ int32_t sJ[C];
-    __shared__ double sx[C], sr[C], sz[C], sp[C], sg[C];
-    __shared__ int32_t soff[C + 1];
-    __shared__ int32_t hkey[kSpaiH];
-    __shared__ double hval[kSpaiH];
-    __shared__ int32_t sflag[1];
-    const int lane = threadIdx.x;
-    const int32_t j = blockIdx.x;
-    if (j >= P.n) return;
+    int32_t *sJ = Lg.sJ;
+    double *sx = Lg.sx, *sr = Lg.sr, *sz = Lg.sz, *sp = Lg.sp, *sg = Lg.sg;
+    int32_t *soff = Lg.soff;
+    int32_t *hkey = Lg.hkey;
+    double *hval = Lg.hval;
+    int32_t *sflag = Lg.sflag;
+    const int lane = threadIdx.x & 63;
     const int64_t s0 = P.rowptr[j];
     const int32_t c = (int32_t)(P.rowptr[j + 1] - s0);
     if (c > C) {
@@ -271,13 +287,260 @@ __global__ __launch_bounds__(64) void k_spai(SpaiParams P) {
     for (int a = lane; a < c; a += 64) P.X[s0 + a] = sx[a];
 }
 
+// Columns listed by the staged kernel, one wavefront per block.
+__global__ __launch_bounds__(64) void k_spai_general(SpaiParams P, const int32_t *__restrict__ list,
+                                                     const int32_t *__restrict__ count) {
+    __shared__ SpaiGeneralLds Lg;
+    const int32_t cnt = *count;
+    for (int32_t q = blockIdx.x; q < cnt; q += gridDim.x) {
+        wsync();
+        spai_general_column(P, list[q], Lg);
+    }
+}
+
+// ---- SPAI, staged variant --------------------------------------------------
+// One wavefront per column j of S. Lane l owns the entries a = l + 64 k
+// (k < E) of the column (J_a) with their CG scalars, and stages column J_a of
+// Ah (its rows as slots of a per-wavefront LDS hash, its values) once; each
+// application of G = Ah_J^T Ah_J is then an LDS scatter of Ah_J p into the
+// slots and a per-lane gather back, with no global traffic. The E = 1 kernel
+// runs over every column and lists those it cannot hold (more than 64
+// entries, or more than 384 entries in Ah(:, J)); the E = 2 kernel takes that
+// list and passes what it cannot hold on to the general kernel.
+template <int E>
+struct SpaiStaged {
+    static constexpr int C = 64 * E;    // entries of the column of S
+    static constexpr int T = 384 * E;   // entries of Ah(:, J)
+    static constexpr int HB = 8 + E;    // log2 of the hash slots (2^HB > T)
+    static constexpr int H = 1 << HB;
+    static_assert(H > T, "every row of Ah(:, J) must find a slot");
+    union {
+        int32_t key[H];  // setup: row of each slot
+        double y[H];     // CG: (Ah_J p) per slot
+    };
+    double val[T];
+    uint16_t slot[T];
+    int32_t flag;
+};
+
+template <int HB>
+__device__ inline int sp_insert(int32_t *key, int32_t r) {
+    constexpr int H = 1 << HB;
+    uint32_t s = ((uint32_t)r * 2654435761u) >> (32 - HB);
+    for (int probe = 0; probe < H; ++probe) {
+        int32_t k = key[s];
+        if (k == r) return (int)s;
+        if (k == -1) {
+            int32_t old = atomicCAS(&key[s], -1, r);
+            if (old == -1 || old == r) return (int)s;
+        }
+        s = (s + 1) & (uint32_t)(H - 1);
+    }
+    return -1;
+}
+
+template <int E, int W>
+__global__ __launch_bounds__(64 * W) void k_spai_staged(SpaiParams P, const int32_t *__restrict__ in_list,
+                                                        const int32_t *__restrict__ in_count,
+                                                        int32_t *__restrict__ out_list,
+                                                        int32_t *__restrict__ out_count) {
+    using Lds = SpaiStaged<E>;
+    __shared__ Lds lds[W];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Lds &L = lds[w];
+    const int32_t total = in_list ? *in_count : P.n;
+    for (int32_t q = blockIdx.x * W + w; q < total; q += gridDim.x * W) {
+        const int32_t j = in_list ? in_list[q] : q;
+        const int64_t s0 = P.rowptr[j];
+        const int32_t c = (int32_t)(P.rowptr[j + 1] - s0);
+        if (c > Lds::C) {
+            if (lane == 0) out_list[atomicAdd(out_count, 1)] = j;
+            continue;
+        }
+        double xa[E], cna[E];
+        int64_t qa[E];
+        int32_t dega[E], e0[E];
+        int32_t carry = 0;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const int a = lane + 64 * k;
+            xa[k] = 0.0;
+            cna[k] = 1.0;
+            qa[k] = 0;
+            dega[k] = 0;
+            if (a < c) {
+                const int32_t ja = P.col[s0 + a];
+                xa[k] = P.M[s0 + a];
+                cna[k] = P.colnorm2[ja];
+                const int32_t ra = P.perm[ja];
+                qa[k] = P.A_rowptr[ra];
+                dega[k] = (int32_t)(P.A_rowptr[ra + 1] - qa[k]);
+            }
+            int32_t incl = dega[k];
+            for (int o = 1; o < 64; o <<= 1) {
+                int32_t u = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += u;
+            }
+            incl += carry;
+            e0[k] = incl - dega[k];
+            carry = __shfl(incl, 63, 64);
+        }
+        if (carry > Lds::T) {
+            if (lane == 0) out_list[atomicAdd(out_count, 1)] = j;
+            continue;
+        }
+        wsync();  // the previous column's readers of L are done
+        for (int s = lane; s < Lds::H; s += 64) L.key[s] = -1;
+        if (lane == 0) L.flag = 0;
+        wsync();
+        // b_a = Ah(j, J_a) = entry of column J_a of Ah in row j (Ah symmetric)
+        const int32_t rj = P.perm[j];
+        double ba[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            ba[k] = 0.0;
+            for (int32_t e = 0; e < dega[k]; ++e) {
+                const int32_t r = P.A_col[qa[k] + e];
+                const double v = P.A_val[qa[k] + e];
+                const int sl = sp_insert<Lds::HB>(L.key, r);
+                if (sl < 0) L.flag = 1;
+                L.slot[e0[k] + e] = (uint16_t)(sl < 0 ? 0 : sl);
+                L.val[e0[k] + e] = v;
+                if (r == rj) ba[k] = v;
+            }
+        }
+        wsync();
+        if (L.flag) {
+            if (lane == 0) out_list[atomicAdd(out_count, 1)] = j;
+            continue;
+        }
+        // g = G v for the lane-owned vector entries v
+        auto apply = [&](const double(&va)[E], double(&ga)[E]) {
+            wsync();
+            for (int s = lane; s < Lds::H; s += 64) L.y[s] = 0.0;
+            wsync();
+#pragma unroll
+            for (int k = 0; k < E; ++k)
+                for (int32_t e = e0[k]; e < e0[k] + dega[k]; ++e) atomicAdd(&L.y[L.slot[e]], L.val[e] * va[k]);
+            wsync();
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                double g = 0.0;
+                for (int32_t e = e0[k]; e < e0[k] + dega[k]; ++e) g += L.val[e] * L.y[L.slot[e]];
+                ga[k] = g;
+            }
+        };
+        // r = b - G x, z = r / diag, p = z
+        double ga[E], ra[E], za[E], pa[E];
+        apply(xa, ga);
+        double rz = 0.0;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const bool own = lane + 64 * k < c;
+            ra[k] = own ? ba[k] - ga[k] : 0.0;
+            za[k] = own ? ra[k] / cna[k] : 0.0;
+            pa[k] = za[k];
+            rz += ra[k] * za[k];
+        }
+        rz = wsum(rz);
+        for (int it = 0; it < P.iters; ++it) {
+            if (rz == 0.0) break;
+            apply(pa, ga);
+            double pgp = 0.0;
+#pragma unroll
+            for (int k = 0; k < E; ++k) pgp += pa[k] * ga[k];
+            pgp = wsum(pgp);
+            if (pgp == 0.0) break;
+            const double al = rz / pgp;
+            double rzn = 0.0;
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const bool own = lane + 64 * k < c;
+                xa[k] += al * pa[k];
+                ra[k] -= al * ga[k];
+                za[k] = own ? ra[k] / cna[k] : 0.0;
+                rzn += ra[k] * za[k];
+            }
+            rzn = wsum(rzn);
+            const double be = rzn / rz;
+#pragma unroll
+            for (int k = 0; k < E; ++k) pa[k] = za[k] + be * pa[k];
+            rz = rzn;
+        }
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if (lane + 64 * k < c) P.X[s0 + lane + 64 * k] = xa[k];
+    }
+}
+
 __global__ void k_symmetrize(int64_t nnz, const int64_t *__restrict__ mirror, const double *__restrict__ X,
                              double *__restrict__ R) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < nnz) R[p] = 0.5 * (X[p] + X[mirror[p]]);
 }
 
+// First stage of the diagonal error: block b sums |d_ref - d_hat - sum_m
+// lambda_m V_im^2| and |d_ref| over a grid-stride range of rows into part[2b],
+// part[2b + 1].
+__global__ __launch_bounds__(256) void k_err1_part(int32_t n, const double *__restrict__ d_ref,
+                                                   const double *__restrict__ d_hat, int32_t k,
+                                                   const double *__restrict__ V, const double *__restrict__ lam,
+                                                   double *__restrict__ part) {
+    __shared__ double s0[4], s1[4];
+    double a = 0.0, b = 0.0;
+    for (int32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        double c = d_hat[i];
+        const double *v = V + (int64_t)i * k;
+        for (int m = 0; m < k; ++m) c += lam[m] * v[m] * v[m];
+        a += fabs(d_ref[i] - c);
+        b += fabs(d_ref[i]);
+    }
+    a = wsum(a);
+    b = wsum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s0[w] = a;
+        s1[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = (s0[0] + s0[1]) + (s0[2] + s0[3]);
+        part[2 * blockIdx.x + 1] = (s1[0] + s1[1]) + (s1[2] + s1[3]);
+    }
+}
+
+// Second stage: one block adds the partial sums in a fixed order.
+__global__ __launch_bounds__(256) void k_err1_final(int nblk, const double *__restrict__ part,
+                                                    double *__restrict__ sums) {
+    __shared__ double s0[4], s1[4];
+    double a = 0.0, b = 0.0;
+    for (int q = threadIdx.x; q < nblk; q += 256) {
+        a += part[2 * q];
+        b += part[2 * q + 1];
+    }
+    a = wsum(a);
+    b = wsum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s0[w] = a;
+        s1[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sums[0] = (s0[0] + s0[1]) + (s0[2] + s0[3]);
+        sums[1] = (s1[0] + s1[1]) + (s1[2] + s1[3]);
+    }
+}
+
 }  // namespace dev
+
+hipError_t launch_diag_err1(int32_t n, const double *d_ref, const double *d_hat, int32_t k, const double *V,
+                            const double *lam, double *part, double *sums, hipStream_t st) {
+    int nblk = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ((int64_t)n + 255) / 256));
+    hipLaunchKernelGGL(dev::k_err1_part, dim3(nblk), dim3(256), 0, st, n, d_ref, d_hat, k, V, lam, part);
+    hipLaunchKernelGGL(dev::k_err1_final, dim3(1), dim3(256), 0, st, nblk, part, sums);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st) {
     if (count <= 0) return hipSuccess;
@@ -297,25 +560,36 @@ hipError_t launch_mix(int64_t nnz, const int32_t *srow, const int32_t *col, cons
     return hipGetLastError();
 }
 
-hipError_t launch_lowrank(int32_t n, int32_t k, const int64_t *rowptr, const int32_t *col, const double *V,
+hipError_t launch_lowrank(int64_t nnz, int32_t k, const int32_t *srow, const int32_t *col, const double *V,
                           const double *lam, const double *in, double *out, hipStream_t st) {
-    dim3 g((n + 3) / 4), b(256);
-    if (k <= 8)
-        hipLaunchKernelGGL((dev::k_lowrank<8>), g, b, 0, st, n, k, rowptr, col, V, lam, in, out);
-    else if (k <= 16)
-        hipLaunchKernelGGL((dev::k_lowrank<16>), g, b, 0, st, n, k, rowptr, col, V, lam, in, out);
-    else if (k <= 32)
-        hipLaunchKernelGGL((dev::k_lowrank<32>), g, b, 0, st, n, k, rowptr, col, V, lam, in, out);
-    else
-        hipLaunchKernelGGL((dev::k_lowrank<64>), g, b, 0, st, n, k, rowptr, col, V, lam, in, out);
+    dim3 g((unsigned)((nnz + 255) / 256)), b(256);
+    if (nnz == 0) return hipSuccess;
+    const bool vec = (reinterpret_cast<uintptr_t>(V) & 15) == 0;
+    switch (vec ? k : 0) {
+    case 8: hipLaunchKernelGGL((dev::k_lowrank<8>), g, b, 0, st, nnz, k, srow, col, V, lam, in, out); break;
+    case 16: hipLaunchKernelGGL((dev::k_lowrank<16>), g, b, 0, st, nnz, k, srow, col, V, lam, in, out); break;
+    case 32: hipLaunchKernelGGL((dev::k_lowrank<32>), g, b, 0, st, nnz, k, srow, col, V, lam, in, out); break;
+    case 64: hipLaunchKernelGGL((dev::k_lowrank<64>), g, b, 0, st, nnz, k, srow, col, V, lam, in, out); break;
+    default: hipLaunchKernelGGL((dev::k_lowrank<1>), g, b, 0, st, nnz, k, srow, col, V, lam, in, out); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_spai(const SpaiParams &P, hipStream_t st) {
     dim3 g1((P.n + 255) / 256);
-    hipLaunchKernelGGL(dev::k_iperm, g1, dim3(256), 0, st, P.n, P.perm, P.iperm, P.status);
+    hipLaunchKernelGGL(dev::k_iperm, g1, dim3(256), 0, st, P.n, P.perm, P.iperm, P.status, P.list_count);
     hipLaunchKernelGGL(dev::k_colnorm2, g1, dim3(256), 0, st, P.n, P.perm, P.A_rowptr, P.A_val, P.colnorm2);
-    hipLaunchKernelGGL(dev::k_spai, dim3(P.n), dim3(64), 0, st, P);
+    // every column -> list 1 (too long for E = 1) -> list 2 (too long for E = 2)
+    int32_t *list1 = P.list, *list2 = P.list + P.n;
+    int32_t *cnt1 = P.list_count, *cnt2 = P.list_count + 1;
+    const int64_t nb = std::min<int64_t>(((int64_t)P.n + 3) / 4, 8192);
+    hipLaunchKernelGGL((dev::k_spai_staged<1, 4>), dim3((unsigned)nb), dim3(256), 0, st, P, nullptr, nullptr,
+                       list1, cnt1);
+    const int64_t nm = std::min<int64_t>(((int64_t)P.n + 1) / 2, 2048);
+    hipLaunchKernelGGL((dev::k_spai_staged<2, 2>), dim3((unsigned)nm), dim3(128), 0, st, P, list1, cnt1, list2,
+                       cnt2);
+    const int64_t ng = std::min<int64_t>(P.n, 2048);
+    hipLaunchKernelGGL(dev::k_spai_general, dim3((unsigned)ng), dim3(64), 0, st, P, list2, cnt2);
     return hipGetLastError();
 }
 

@@ -4,8 +4,8 @@ import numpy as np
 import pytest
 
 from oracle import core as oc
-from workloads import (diffusion3d_7pt, ildl_bk, laplace2d, nested_multicolor_grid, rcm,
-                       shifted_laplace2d_indefinite)
+from workloads import (diffusion3d_7pt, ildl_bk, laplace2d, nested_multicolor_grid, random_dd_symmetric, rcm,
+                       shifted_laplace2d_indefinite, stencil27_3d)
 
 pytestmark = pytest.mark.gpu
 
@@ -22,10 +22,20 @@ def _spai_case(name):
     if name == "diff12_tau1e-3":
         A = diffusion3d_7pt(12, 1.0, 2)
         return A, ildl_bk(A, nested_multicolor_grid((12, 12, 12)), 1e-3)
+    if name == "st27_7_tau1e-2":
+        # 27 entries per column of A: most columns of S overflow the staged
+        # kernel's 384 entries of Ah(:, J) and take the general kernel
+        A = stencil27_3d(7, 0.5, 11)
+        return A, ildl_bk(A, nested_multicolor_grid((7, 7, 7)), 1e-2)
+    if name == "rand400_tau1e-4":
+        # high fill: columns of S longer than 64 entries (general kernel)
+        A = random_dd_symmetric(5, n=400)
+        return A, ildl_bk(A, rcm(A), 1e-4)
     raise KeyError(name)
 
 
-@pytest.mark.parametrize("name", ["lap32_tau1e-2", "indef24_tau1e-2", "diff12_tau1e-3"])
+@pytest.mark.parametrize("name", ["lap32_tau1e-2", "indef24_tau1e-2", "diff12_tau1e-3", "st27_7_tau1e-2",
+                                  "rand400_tau1e-4"])
 @pytest.mark.parametrize("iters", [1, 10])
 def test_spai_parity(name, iters):
     import torch
@@ -35,21 +45,20 @@ def test_spai_parity(name, iters):
     S = oc.pattern(F)
     s = Solver(0)
     s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
-    Lv, dd, ds = upload_factors(F)
-    Z = s.selinv(Lv, dd, ds)
-    N = s.ninv(Lv, dd, ds, p=3, delta=0.1)
-    M = s.mix(Z, N, 1e-2)
+    # both sides refine the oracle's Mix result; the device Mix has its own tests
+    Mo = oc.mix(S, oc.selinv(F, S), oc.ninv(F, S, 3, 0.1), 1e-2)
     dev = torch.device("cuda", 0)
+    M = torch.as_tensor(Mo, device=dev)
     Ar = torch.as_tensor(A.indptr.astype(np.int64), device=dev)
     Ac = torch.as_tensor(A.indices.astype(np.int32), device=dev)
     Av = torch.as_tensor(A.data.astype(np.float64), device=dev)
     perm = torch.as_tensor(F.perm.astype(np.int32), device=dev)
     R = s.spai(Ar, Ac, Av, perm, M, cg_iters=iters)
     s.sync()
-    # the oracle refines the same starting values (the device's Mix output)
-    Ro = oc.spai(oc.permuted(A, F.perm), S, M.cpu().numpy(), iters)
+    Ro = oc.spai(oc.permuted(A, F.perm), S, Mo, iters)
     e = oc.entry_error(S, R.cpu().numpy(), Ro)
-    print(f"  n={F.n} |S|={S.nnz} e_R max={e.max():.2e}")
+    clen = np.diff(S.rowptr)
+    print(f"  n={F.n} |S|={S.nnz} longest column {clen.max()} e_R max={e.max():.2e}")
     assert e.max() <= FP64_TOL
     Rm = S.to_csr(R.cpu().numpy())
     assert abs(Rm - Rm.T).max() == 0.0

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared_symbols():
     txt = open(os.path.join(ROOT, "include", "asi.h")).read()
-    return sorted(set(re.findall(r"\b(asi_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(asi_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_exports_every_declared_symbol():
