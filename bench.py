@@ -111,15 +111,10 @@ def run_diffusion(args):
     # learned correction: trained on small grids of the same family before the
     # timed region (Mix at this tau as input, SelInv at tau/10 as target)
     learned_info, packed = train_learned(args, tau, p, delta, eps)
-    Fe = torch.empty((nnzS, 16), dtype=torch.int16, device=dev)
-    sc = torch.empty(nnzS, dtype=torch.float32, device=dev)
-    yv = torch.empty(nnzS, dtype=torch.float32, device=dev)
     ML = torch.empty_like(Z)
 
     def correct():
-        s.mlp_features(Z, Nn, M, eps, Lv, dd, ds, F=Fe, sc=sc)
-        s.mlp_forward(packed, Fe, y=yv)
-        s.mlp_apply(M, yv, sc, out=ML)
+        s.mlp_correct(packed, Z, Nn, M, eps, Lv, dd, ds, out=ML)
 
     def full_step(prec="fp64"):
         step(prec)
@@ -224,7 +219,7 @@ def run_diffusion(args):
         "data": "synthetic",
         "config": {"workload": f"3D 7-point lognormal(0,1) diffusion {N}^3, nested multicolor order, "
                                f"ILDL tau={tau}; step = SelInv + NInv(p=3, delta=0.1) + Mix(eps=1e-2)"
-                               + (" + learned correction (features, bf16 MLP, apply)" if packed is not None
+                               + (" + learned correction (fused features, bf16 MLP, apply)" if packed is not None
                                   else " (learned correction fell back to plain Mix)"),
                    "n": F.n, "nnz_A": int(A.nnz), "nnz_L": F.nnzL, "nnz_S": nnzS,
                    "levels": info["n_levels"], "max_cols": info["max_cols"],

@@ -171,8 +171,8 @@ asi_status asi_lowrank(asi_handle h, int32_t k, const double *V, const double *l
  * asi_mlp_features: the 16 features of every entry of S from Z (SelInv), N
  * (NInv), M (Mix with threshold eps), L and D: F is |S| x 16 bfloat16 (raw
  * 16-bit words, row-major), scale receives s_ij (float32, |S|).
- * Feature order: M/s, (Z-N)/s, [Mix took Z], [i == j], log|D^-1_ii|,
- * log|D^-1_jj|, log row norms of L at i and j, log column norms of L at i and
+ * Feature order: M/s, (Z-N)/s, [Mix took Z], [i == j], log(|D^-1_ii| + 1e-30),
+ * log(|D^-1_jj| + 1e-30), log row norms of L at i and j, log column norms of L at i and
  * j, |L(max, min)|, log(1 + |N|/s), log(1 + |Z|/s), level(i)/max level,
  * level(j)/max level, log(1 + |R| of column min(i, j)).
  */
@@ -199,6 +199,17 @@ asi_status asi_mlp_adam(asi_handle h, float *theta, float *m, float *v, const fl
                         float beta2, float eps, int64_t t);
 /* out = M + y * scale on S (out may alias M). */
 asi_status asi_mlp_apply(asi_handle h, const double *M_S, const float *y, const float *scale, double *out_S);
+/*
+ * The whole correction in one pass: features of every entry of S (as
+ * asi_mlp_features), the network (as asi_mlp_forward) and out = M + y s (as
+ * asi_mlp_apply), with nothing but out written to memory; the result equals
+ * that of the three calls bit for bit. W: packed weights (asi_mlp_pack).
+ * Arguments as for asi_mlp_features; out_S: |S| float64, device, may alias
+ * M_S. Needs an analysis.
+ */
+asi_status asi_mlp_correct(asi_handle h, const void *W, const double *Z_S, const double *N_S, const double *M_S,
+                           double eps, const double *L_val, const double *d_diag, const double *d_sub,
+                           double *out_S);
 
 /* Diagonal of a matrix on S: d[i] = X(i, i). */
 asi_status asi_diag(asi_handle h, const double *X_S, double *d);

@@ -200,6 +200,28 @@ def err1(d: np.ndarray, dhat: np.ndarray) -> float:
     return float(np.abs(d - dhat).sum() / np.abs(d).sum())
 
 
+def dag_levels(F, S: Pattern) -> np.ndarray:
+    """Level of every unknown in the SelInv dependency DAG (Section 2.1; the
+    schedule reading for an incomplete pattern): the blocks J of D (1x1, or
+    the two columns of a 2x2 pivot) are visited last to first, R_J is the set
+    of rows of S below J outside J, level(J) = 0 when R_J is empty and
+    1 + max level over R_J otherwise; both columns of a 2x2 block carry the
+    block's level."""
+    n = F.n
+    piv = np.asarray(F.piv)
+    lev = np.zeros(n, dtype=np.int64)
+    j = n - 1
+    while j >= 0:
+        j0 = j - 1 if piv[j] == 2 else j
+        R = set()
+        for c in range(j0, j + 1):
+            cols = S.col[S.rowptr[c]:S.rowptr[c + 1]]
+            R.update(int(r) for r in cols if r > j)
+        lev[j0:j + 1] = 1 + max(lev[r] for r in R) if R else 0
+        j = j0 - 1
+    return lev
+
+
 def corrected_diag(dhat: np.ndarray, V: np.ndarray, lam: np.ndarray) -> np.ndarray:
     """Diagonal of the rank-k corrected approximation (Section 2.6):
     dhat_i + sum_m lam_m V_im^2."""

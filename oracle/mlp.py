@@ -11,7 +11,8 @@ Features (16 per entry (i, j) of S), in this order:
   1  (Z_ij - N_ij) / s_ij
   2  1 if |Z_ij| > eps sqrt(|Z_ii Z_jj|) (Mix took the SelInv value) else 0
   3  1 if i == j else 0
-  4  log |(D^-1)_ii|          5  log |(D^-1)_jj|
+  4  log(|(D^-1)_ii| + 1e-30)   5  same for j   (with 2x2 pivots a diagonal
+     entry of D^-1 can vanish; the offset keeps the feature finite)
   6  log(||L(i, :)||_2 + 1e-30)   7  same for row j   (strict lower part of L)
   8  log(||L(:, i)||_2 + 1e-30)   9  same for column j
   10 |L(max(i,j), min(i,j))| (the first Neumann term at the entry; 0 if not stored)
@@ -91,9 +92,11 @@ def features(S, Z, N, M, eps, F, level, ucount):
     j = 0
     while j < n:
         if F.piv[j] == 1:
-            B = np.array([[F.d_diag[j], F.d_sub[j]], [F.d_sub[j], F.d_diag[j + 1]]])
-            Bi = np.linalg.inv(B)
-            dinv[j], dinv[j + 1] = Bi[0, 0], Bi[1, 1]
+            # [[a, c], [c, d]]^-1 = [[d, -c], [-c, a]] / (a d - c^2): exact zeros
+            # where a or d is zero
+            ba, bc, bd = F.d_diag[j], F.d_sub[j], F.d_diag[j + 1]
+            det = ba * bd - bc * bc
+            dinv[j], dinv[j + 1] = bd / det, ba / det
             j += 2
         else:
             dinv[j] = 1.0 / F.d_diag[j]
@@ -109,8 +112,8 @@ def features(S, Z, N, M, eps, F, level, ucount):
     f[:, 1] = (Z - N) / s
     f[:, 2] = (np.abs(Z) > eps * np.sqrt(np.abs(zd[r] * zd[c]))).astype(float)
     f[:, 3] = (r == c).astype(float)
-    f[:, 4] = np.log(np.abs(dinv[r]))
-    f[:, 5] = np.log(np.abs(dinv[c]))
+    f[:, 4] = np.log(np.abs(dinv[r]) + 1e-30)
+    f[:, 5] = np.log(np.abs(dinv[c]) + 1e-30)
     f[:, 6] = np.log(rn[r] + 1e-30)
     f[:, 7] = np.log(rn[c] + 1e-30)
     f[:, 8] = np.log(cn[r] + 1e-30)

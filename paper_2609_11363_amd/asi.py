@@ -26,7 +26,7 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_set_workspace", "asi_get_info", "asi_get_pattern", "asi_selinv", "asi_ninv",
            "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
            "asi_profile_read", "asi_set_sweep", "asi_mlp_features", "asi_mlp_pack", "asi_mlp_forward",
-           "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1"]
+           "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -88,6 +88,7 @@ def load_library():
         "asi_mlp_loss": [P, P, P, i64, P, P],
         "asi_mlp_adam": [P, P, P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, i64],
         "asi_mlp_apply": [P, P, P, P, P],
+        "asi_mlp_correct": [P, P, P, P, P, f64, P, P, P, P],
         "asi_profile_read": [P, i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(f64)],
     }
     for name, args in sig.items():
@@ -277,6 +278,14 @@ class Solver:
         out = self._out(out)
         self._stream()
         self._check(self.lib.asi_mlp_apply(self.h, _ptr(M), _ptr(y), _ptr(scale), _ptr(out)))
+        return out
+
+    def mlp_correct(self, packed, Z, N, M, eps, L_val, d_diag, d_sub, out=None):
+        """M + y s on S from features, network and correction in one pass."""
+        out = self._out(out)
+        self._stream()
+        self._check(self.lib.asi_mlp_correct(self.h, _ptr(packed), _ptr(Z), _ptr(N), _ptr(M), float(eps),
+                                             _ptr(L_val), _ptr(d_diag), _ptr(d_sub), _ptr(out)))
         return out
 
     def diag(self, X, out=None):

@@ -41,8 +41,7 @@ struct asi_handle_s {
     void *Zu = nullptr;
     double *zd = nullptr;
     int32_t *done = nullptr;
-    double *rn = nullptr;
-    double *cn = nullptr;
+    unsigned char *node = nullptr;
     int64_t *rowptr_L = nullptr;
     int32_t epoch = 0;
     int sweep = ASI_SWEEP_AUTO;
@@ -153,11 +152,10 @@ Layout make_layout(const asi::Analysis &A) {
     L.add(n * 8);                       // 27 zd (SelInv diagonal)
     L.add(A.hits.size() * 4);           // 28 hits
     L.add(n * 4);                       // 29 done flags of the dataflow sweep
-    L.add(n * 8);                       // 30 row norms of L (features)
-    L.add(n * 8);                       // 31 column norms of L (features)
-    L.add((n + 1) * 8);                 // 32 row pointers of the input L
-    L.add(2 * asi::kRedBlocks * 8);     // 33 partial sums of the diagonal error
-    L.add(2 * n * 4);                   // 34 column lists of the SPAI kernels
+    L.add(n * 32);                      // 30 per-node feature records (learned correction)
+    L.add((n + 1) * 8);                 // 31 row pointers of the input L
+    L.add(2 * asi::kRedBlocks * 8);     // 32 partial sums of the diagonal error
+    L.add(2 * n * 4);                   // 33 column lists of the SPAI kernels
     return L;
 }
 
@@ -316,11 +314,10 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->zd = at<double>(b, L.off[27]);
     h->hits = at<uint32_t>(b, L.off[28]);
     h->done = at<int32_t>(b, L.off[29]);
-    h->rn = at<double>(b, L.off[30]);
-    h->cn = at<double>(b, L.off[31]);
-    h->rowptr_L = at<int64_t>(b, L.off[32]);
-    h->red = at<double>(b, L.off[33]);
-    h->spai_list = at<int32_t>(b, L.off[34]);
+    h->node = b + L.off[30];
+    h->rowptr_L = at<int64_t>(b, L.off[31]);
+    h->red = at<double>(b, L.off[32]);
+    h->spai_list = at<int32_t>(b, L.off[33]);
     h->epoch = 0;
     // pool: rows | linv | w, each region 256-aligned
     size_t rest = bytes - L.cur - 3 * 256;
@@ -607,20 +604,15 @@ asi_status asi_lowrank(asi_handle h, int32_t k, const double *V, const double *l
     return ASI_OK;
 }
 
-asi_status asi_mlp_features(asi_handle h, const double *Z_S, const double *N_S, const double *M_S, double eps,
-                            const double *L_val, const double *d_diag, const double *d_sub, uint16_t *F,
-                            float *scale) {
-    asi_status s = need_ready(h);
-    if (s != ASI_OK) return s;
-    if (!Z_S || !N_S || !M_S || (!L_val && h->A.nnzL > 0) || !d_diag || !d_sub || !F || !scale)
-        return fail(h, ASI_E_ARG, "null pointer");
-    DeviceGuard g(h->device);
+// Common set-up of the learned-correction calls: D-block inverses, L in its
+// column layout, the per-node records; fills P.
+static asi_status mlp_setup(asi_handle h, const double *Z_S, const double *N_S, const double *M_S, double eps,
+                            const double *L_val, const double *d_diag, const double *d_sub, asi::MlpFeatParams &P) {
     const asi::Analysis &A = h->A;
-    Trace t(h, ASI_K_MLP_FEATURES, 0.0);
     hipError_t e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
     if (e == hipSuccess) e = asi::launch_gather_lu(A.nnzU, h->lsrc_u, L_val, h->Lu, true, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "features setup");
-    asi::MlpFeatParams P{};
+    P = asi::MlpFeatParams{};
     P.n = A.n;
     P.nnz = A.nnzS;
     P.srow = h->srow;
@@ -633,16 +625,51 @@ asi_status asi_mlp_features(asi_handle h, const double *Z_S, const double *N_S, 
     P.maxlevel = A.n_levels - 1;
     P.Lu = reinterpret_cast<const double *>(h->Lu);
     P.dinv = h->dinv;
-    P.rn = h->rn;
-    P.cn = h->cn;
+    P.node = h->node;
     P.Z = Z_S;
     P.N = N_S;
     P.M = M_S;
     P.eps = eps;
+    e = asi::launch_node_feats(P, h->rowptr_L, L_val, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "node features");
+    return ASI_OK;
+}
+
+asi_status asi_mlp_features(asi_handle h, const double *Z_S, const double *N_S, const double *M_S, double eps,
+                            const double *L_val, const double *d_diag, const double *d_sub, uint16_t *F,
+                            float *scale) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!Z_S || !N_S || !M_S || (!L_val && h->A.nnzL > 0) || !d_diag || !d_sub || !F || !scale)
+        return fail(h, ASI_E_ARG, "null pointer");
+    DeviceGuard g(h->device);
+    Trace t(h, ASI_K_MLP_FEATURES, 0.0);
+    asi::MlpFeatParams P;
+    s = mlp_setup(h, Z_S, N_S, M_S, eps, L_val, d_diag, d_sub, P);
+    if (s != ASI_OK) return s;
     P.F = F;
     P.scale = scale;
-    e = asi::launch_mlp_features(P, h->rowptr_L, L_val, h->stream);
+    hipError_t e = asi::launch_mlp_features(P, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "features");
+    return ASI_OK;
+}
+
+asi_status asi_mlp_correct(asi_handle h, const void *W, const double *Z_S, const double *N_S, const double *M_S,
+                           double eps, const double *L_val, const double *d_diag, const double *d_sub,
+                           double *out_S) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!W || !Z_S || !N_S || !M_S || (!L_val && h->A.nnzL > 0) || !d_diag || !d_sub || !out_S)
+        return fail(h, ASI_E_ARG, "null pointer");
+    DeviceGuard g(h->device);
+    // algorithmic bytes: row and column index, Z, N, M in and the result out
+    // per entry; two node records of 32 B per entry come from the cache
+    Trace t(h, ASI_K_MLP_FORWARD, 40.0 * h->A.nnzS + 32.0 * h->A.n);
+    asi::MlpFeatParams P;
+    s = mlp_setup(h, Z_S, N_S, M_S, eps, L_val, d_diag, d_sub, P);
+    if (s != ASI_OK) return s;
+    hipError_t e = asi::launch_mlp_correct(P, W, out_S, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "mlp correct");
     return ASI_OK;
 }
 

@@ -123,16 +123,17 @@ struct MlpFeatParams {
     int32_t maxlevel;
     const double *Lu;    // u-space L values (float64)
     const double *dinv;  // 3 per block start
-    double *rn;          // n: row norms of L (filled by the launch)
-    double *cn;          // n: column norms of L (filled by the launch)
+    void *node;          // n per-node feature records of 32 bytes (workspace)
     const double *Z, *N, *M;
     double eps;
     uint16_t *F;  // nnz x 16 bfloat16
     float *scale; // nnz
 };
 
-hipError_t launch_mlp_features(const MlpFeatParams &P, const int64_t *L_rowptr, const double *L_val,
-                               hipStream_t st);
+hipError_t launch_node_feats(const MlpFeatParams &P, const int64_t *L_rowptr, const double *L_val,
+                             hipStream_t st);
+hipError_t launch_mlp_features(const MlpFeatParams &P, hipStream_t st);
+hipError_t launch_mlp_correct(const MlpFeatParams &P, const void *W, double *out, hipStream_t st);
 hipError_t launch_mlp_pack(const float *theta, void *W, hipStream_t st);
 hipError_t launch_mlp_forward(const void *W, const uint16_t *F, int64_t rows, float *y, hipStream_t st);
 hipError_t launch_mlp_backward(const void *W, const uint16_t *F, const float *dy, int64_t rows, float *grad,

@@ -25,80 +25,112 @@ constexpr int OFF_W1 = 0, OFF_W2 = 4096, OFF_W3 = 12288, OFF_B1 = 12416, OFF_B2 
 // master layout
 constexpr int M_W1 = 0, M_B1 = 1024, M_W2 = 1088, M_B2 = 5184, M_W3 = 5248, M_B3 = 5312;
 
-// float -> bfloat16 bits, round to nearest even (finite inputs)
-__device__ inline uint16_t to_bf16(float x) {
-    uint32_t b = __float_as_uint(x);
-    b += 0x7FFFu + ((b >> 16) & 1u);
-    return (uint16_t)(b >> 16);
-}
+// float -> bfloat16 bits, round to nearest even (the gfx950 conversion
+// instruction; bit-identical to the integer rounding b + 0x7FFF + lsb on
+// finite values, denormals and ties included)
+__device__ inline uint16_t to_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// A float64 value rounded to float32 and then to bfloat16, two separate
+// roundings to nearest even as the features are defined. The second step is
+// integer arithmetic: a compiler may otherwise fuse the float64 -> float32 ->
+// bfloat16 chain into a single rounding from float64, which differs whenever
+// the float32 value lies exactly halfway between two bfloat16 values.
+__device__ inline uint16_t feat_bf16(double x) {
+    const uint32_t b = __float_as_uint((float)x);
+    if ((b & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((b >> 16) | 0x40u);  // NaN stays NaN
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
 __device__ inline float round_bf16(float x) { return from_bf16(to_bf16(x)); }
 
 // ---- features --------------------------------------------------------------
-
-__global__ void k_row_norms(int32_t n, const int64_t *__restrict__ Lp, const double *__restrict__ Lval,
-                            double *__restrict__ rn) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int64_t q = Lp[i]; q < Lp[i + 1]; ++q) s += Lval[q] * Lval[q];
-    rn[i] = sqrt(s);
-}
-
-// column norms of L from its column layout (u-space values, padding is 0)
-__global__ void k_col_norms(int32_t n, const int64_t *__restrict__ ustart, const double *__restrict__ Lu,
-                            double *__restrict__ cn) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int64_t u = ustart[i]; u < ustart[i + 1]; ++u) s += Lu[u] * Lu[u];
-    cn[i] = sqrt(s);
-}
+// Per-node record, computed once per call: the diagonals of M and Z, and the
+// node's bfloat16 features (log(|D^-1_ii| + 1e-30), log(||L(i,:)||_2 + 1e-30),
+// log(||L(:,i)||_2 + 1e-30), level(i) / max level, log(1 + |R_i|)).
+struct NodeRec {
+    double m, z;
+    uint16_t f[6];
+    uint32_t pad;
+};
+static_assert(sizeof(NodeRec) == 32, "node records are 32 bytes");
 
 __device__ inline double dinv_diag(const double *dinv, const int8_t *piv, int32_t i) {
     // diagonal of D^-1 at i: 1x1 -> inv00; first of 2x2 -> inv00; second -> inv11
     return piv[i] == 2 ? dinv[3 * (int64_t)(i - 1) + 2] : dinv[3 * (int64_t)i];
 }
 
-__global__ void k_features(MlpFeatParams P) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P.nnz) return;
+__global__ void k_node_feats(MlpFeatParams P, const int64_t *__restrict__ Lp, const double *__restrict__ Lval) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    double rs = 0.0, cs = 0.0;
+    for (int64_t q = Lp[i]; q < Lp[i + 1]; ++q) rs += Lval[q] * Lval[q];
+    // column i of L from its column layout (u-space values, padding is 0)
+    for (int64_t u = P.ustart[i]; u < P.ustart[i + 1]; ++u) cs += P.Lu[u] * P.Lu[u];
+    const double maxlev = P.maxlevel > 0 ? (double)P.maxlevel : 1.0;
+    NodeRec r;
+    r.m = P.M[P.diagpos[i]];
+    r.z = P.Z[P.diagpos[i]];
+    r.f[0] = feat_bf16(log(fabs(dinv_diag(P.dinv, P.piv, i)) + 1e-30));
+    r.f[1] = feat_bf16(log(sqrt(rs) + 1e-30));
+    r.f[2] = feat_bf16(log(sqrt(cs) + 1e-30));
+    r.f[3] = feat_bf16(P.level[i] / maxlev);
+    r.f[4] = feat_bf16(log1p((double)(P.ustart[i + 1] - P.ustart[i])));
+    r.f[5] = 0;
+    r.pad = 0;
+    reinterpret_cast<NodeRec *>(P.node)[i] = r;
+}
+
+constexpr uint16_t kBf16One = 0x3F80;
+
+// The 16 features of entry p (order as in the header) and its M value and
+// scale s = sqrt(|M_ii M_jj|) (1 where that is 0).
+__device__ inline void entry_features(const MlpFeatParams &P, int64_t p, uint16_t (&f)[NF], double &m,
+                                      double &s) {
+    const NodeRec *node = reinterpret_cast<const NodeRec *>(P.node);
     const int32_t i = P.srow[p], j = P.col[p];
-    const double Mii = P.M[P.diagpos[i]], Mjj = P.M[P.diagpos[j]];
-    double s = sqrt(fabs(Mii * Mjj));
+    const NodeRec ni = node[i], nj = node[j];
+    s = sqrt(fabs(ni.m * nj.m));
     if (!(s > 0.0)) s = 1.0;
-    const double z = P.Z[p], nv = P.N[p], m = P.M[p];
-    const double zii = P.Z[P.diagpos[i]], zjj = P.Z[P.diagpos[j]];
-    const int32_t lo = i < j ? i : j;
+    const double z = P.Z[p], nv = P.N[p];
+    m = P.M[p];
     double lval = 0.0;
     if (i != j) {
         // upper position of (lo, hi): row lo's u-range at the column's offset
+        const int32_t lo = i < j ? i : j;
         const int64_t pu = i < j ? p : P.mirror[p];
         const int64_t u = P.ustart[lo] + (pu - P.diagpos[lo] - 1);
         lval = fabs(P.Lu[u]);
     }
-    const double maxlev = P.maxlevel > 0 ? (double)P.maxlevel : 1.0;
-    double f[NF];
-    f[0] = m / s;
-    f[1] = (z - nv) / s;
-    f[2] = fabs(z) > P.eps * sqrt(fabs(zii * zjj)) ? 1.0 : 0.0;
-    f[3] = i == j ? 1.0 : 0.0;
-    f[4] = log(fabs(dinv_diag(P.dinv, P.piv, i)));
-    f[5] = log(fabs(dinv_diag(P.dinv, P.piv, j)));
-    f[6] = log(P.rn[i] + 1e-30);
-    f[7] = log(P.rn[j] + 1e-30);
-    f[8] = log(P.cn[i] + 1e-30);
-    f[9] = log(P.cn[j] + 1e-30);
-    f[10] = lval;
-    f[11] = log1p(fabs(nv) / s);
-    f[12] = log1p(fabs(z) / s);
-    f[13] = P.level[i] / maxlev;
-    f[14] = P.level[j] / maxlev;
-    f[15] = log1p((double)(P.ustart[lo + 1] - P.ustart[lo]));
-    uint16_t *out = P.F + p * NF;
-#pragma unroll
-    for (int k = 0; k < NF; ++k) out[k] = to_bf16((float)f[k]);
-    P.scale[p] = (float)s;
+    f[0] = feat_bf16(m / s);
+    f[1] = feat_bf16((z - nv) / s);
+    f[2] = fabs(z) > P.eps * sqrt(fabs(ni.z * nj.z)) ? kBf16One : (uint16_t)0;
+    f[3] = i == j ? kBf16One : (uint16_t)0;
+    f[4] = ni.f[0];
+    f[5] = nj.f[0];
+    f[6] = ni.f[1];
+    f[7] = nj.f[1];
+    f[8] = ni.f[2];
+    f[9] = nj.f[2];
+    f[10] = feat_bf16(lval);
+    f[11] = feat_bf16(log1p(fabs(nv) / s));
+    f[12] = feat_bf16(log1p(fabs(z) / s));
+    f[13] = ni.f[3];
+    f[14] = nj.f[3];
+    f[15] = i < j ? ni.f[4] : nj.f[4];
+}
+
+__global__ void k_features(MlpFeatParams P) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.nnz) return;
+    uint16_t f[NF];
+    double m, sc;
+    entry_features(P, p, f, m, sc);
+    uint4 *out = reinterpret_cast<uint4 *>(P.F + p * NF);
+    out[0] = make_uint4(f[0] | (uint32_t)f[1] << 16, f[2] | (uint32_t)f[3] << 16, f[4] | (uint32_t)f[5] << 16,
+                        f[6] | (uint32_t)f[7] << 16);
+    out[1] = make_uint4(f[8] | (uint32_t)f[9] << 16, f[10] | (uint32_t)f[11] << 16,
+                        f[12] | (uint32_t)f[13] << 16, f[14] | (uint32_t)f[15] << 16);
+    P.scale[p] = (float)sc;
 }
 
 // ---- parameters --------------------------------------------------------------
@@ -125,15 +157,105 @@ __global__ void k_mlp_pack(const float *__restrict__ theta, uint8_t *__restrict_
 }
 
 // ---- forward (bfloat16 MFMA 16x16x32, float32 accumulation) ------------------
-// A wavefront handles 64 entries per pass as four 16-row tiles. Operand
+// A wavefront handles 64 entries per tile as four 16-row blocks. Operand
 // layout of v_mfma_f32_16x16x32_bf16: lane l supplies row (A) / column (B)
 // l % 16 and the 8 consecutive k values 8 (l / 16) ..; the result holds
-// column l % 16 and rows 4 (l / 16) .. + 3. The hidden activations go through
-// LDS to change from the result layout to the operand layout.
+// column l % 16 and rows 4 (l / 16) .. + 3. The weight fragments stay in
+// registers for the whole launch; the tile's features and the hidden
+// activations of one 16-row block go through LDS to reach the operand layout.
 
 __device__ inline bf16x8 load8(const uint16_t *p) {
     uint4 v = *reinterpret_cast<const uint4 *>(p);
     return __builtin_bit_cast(bf16x8, v);
+}
+
+struct MlpRegs {
+    bf16x8 w1[4];     // layer 1, unit nt * 16 + l % 16, inputs 8 (l / 16) ..
+    bf16x8 w2[4][2];  // layer 2, same unit, inputs 8 (l / 16) .. and 32 + 8 (l / 16) ..
+    float b1[4], b2[4], w3[4];
+    float b3;
+};
+
+__device__ inline void load_mlp_regs(const uint8_t *W, int col, int g, MlpRegs &R) {
+    const uint16_t *w1 = reinterpret_cast<const uint16_t *>(W + OFF_W1);
+    const uint16_t *w2 = reinterpret_cast<const uint16_t *>(W + OFF_W2);
+    const uint16_t *w3 = reinterpret_cast<const uint16_t *>(W + OFF_W3);
+    const float *b1 = reinterpret_cast<const float *>(W + OFF_B1);
+    const float *b2 = reinterpret_cast<const float *>(W + OFF_B2);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int n = nt * 16 + col;
+        R.w1[nt] = load8(w1 + n * 32 + 8 * g);
+        R.w2[nt][0] = load8(w2 + n * NH + 8 * g);
+        R.w2[nt][1] = load8(w2 + n * NH + 32 + 8 * g);
+        R.b1[nt] = b1[n];
+        R.b2[nt] = b2[n];
+        R.w3[nt] = from_bf16(w3[n]);
+    }
+    R.b3 = reinterpret_cast<const float *>(W + OFF_B3)[0];
+}
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// y for the 64 feature rows in Fs (LDS, row-major 64 x 16 bfloat16) into ys
+// (LDS, 64 floats); H is LDS scratch of 16 x 64 bfloat16.
+__device__ inline void mlp_tile(const MlpRegs &R, const uint16_t *Fs, uint16_t *H, float *ys, int col, int g) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        // layer 1: [16 x 32] x [32 x 64] (inputs 16..31 are zero)
+        bf16x8 a;
+        if (g < 2) {
+            a = load8(Fs + (mt * 16 + col) * NF + 8 * g);
+        } else {
+            uint4 zero = {0u, 0u, 0u, 0u};
+            a = __builtin_bit_cast(bf16x8, zero);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, R.w1[nt], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = acc[r] + R.b1[nt];
+                H[(4 * g + r) * NH + nt * 16 + col] = to_bf16(v > 0.f ? v : 0.f);
+            }
+        }
+        wave_sync();
+        // layer 2: [16 x 64] x [64 x 64], then layer 3 as a dot product
+        float part[4] = {0.f, 0.f, 0.f, 0.f};
+        const bf16x8 a0 = load8(H + col * NH + 8 * g);
+        const bf16x8 a1 = load8(H + col * NH + 32 + 8 * g);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, R.w2[nt][0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, R.w2[nt][1], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = acc[r] + R.b2[nt];
+                v = round_bf16(v > 0.f ? v : 0.f);
+                part[r] += v * R.w3[nt];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float v = part[r];
+            v += __shfl_xor(v, 1, 64);
+            v += __shfl_xor(v, 2, 64);
+            v += __shfl_xor(v, 4, 64);
+            v += __shfl_xor(v, 8, 64);
+            part[r] = v;
+        }
+        if (col == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ys[mt * 16 + 4 * g + r] = part[r] + R.b3;
+        }
+        wave_sync();  // H is rewritten by the next block
+    }
 }
 
 constexpr int kFwdWaves = 4;
@@ -141,92 +263,58 @@ constexpr int kFwdWaves = 4;
 __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const uint8_t *__restrict__ W,
                                                                 const uint16_t *__restrict__ F, int64_t rows,
                                                                 float *__restrict__ y) {
-    __shared__ __align__(16) uint16_t sW1[NH * 32];
-    __shared__ __align__(16) uint16_t sW2[NH * NH];
-    __shared__ float sw3[NH], sb1[NH], sb2[NH];
-    __shared__ float sb3;
-    __shared__ __align__(16) uint16_t sH[kFwdWaves][64 * NH];
-    for (int t = threadIdx.x; t < NH * 32; t += blockDim.x) sW1[t] = reinterpret_cast<const uint16_t *>(W + OFF_W1)[t];
-    for (int t = threadIdx.x; t < NH * NH; t += blockDim.x) sW2[t] = reinterpret_cast<const uint16_t *>(W + OFF_W2)[t];
-    for (int t = threadIdx.x; t < NH; t += blockDim.x) {
-        sw3[t] = from_bf16(reinterpret_cast<const uint16_t *>(W + OFF_W3)[t]);
-        sb1[t] = reinterpret_cast<const float *>(W + OFF_B1)[t];
-        sb2[t] = reinterpret_cast<const float *>(W + OFF_B2)[t];
-    }
-    if (threadIdx.x == 0) sb3 = reinterpret_cast<const float *>(W + OFF_B3)[0];
-    __syncthreads();
+    __shared__ __align__(16) uint16_t sF[kFwdWaves][64 * NF];
+    __shared__ __align__(16) uint16_t sH[kFwdWaves][16 * NH];
+    __shared__ float sy[kFwdWaves][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
-    uint16_t *H = sH[w];
+    MlpRegs R;
+    load_mlp_regs(W, col, g, R);
     const int64_t ntiles = (rows + 63) / 64;
     for (int64_t tile = (int64_t)blockIdx.x * kFwdWaves + w; tile < ntiles; tile += (int64_t)gridDim.x * kFwdWaves) {
-        const int64_t base = tile * 64;
-        // layer 1: [64 x 32] x [32 x 64]
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const int64_t row = base + mt * 16 + col;
-            bf16x8 a;
-            if (g < 2 && row < rows) {
-                a = load8(F + row * NF + 8 * g);
-            } else {
-                uint4 zero = {0u, 0u, 0u, 0u};
-                a = __builtin_bit_cast(bf16x8, zero);
-            }
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int n = nt * 16 + col;
-                bf16x8 b = load8(sW1 + n * 32 + 8 * g);
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float v = acc[r] + sb1[n];
-                    H[(mt * 16 + 4 * g + r) * NH + n] = to_bf16(v > 0.f ? v : 0.f);
-                }
-            }
+        const int64_t row = tile * 64 + lane;
+        uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+        if (row < rows) {
+            v0 = reinterpret_cast<const uint4 *>(F + row * NF)[0];
+            v1 = reinterpret_cast<const uint4 *>(F + row * NF)[1];
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // layer 2: [64 x 64] x [64 x 64], then layer 3 as a dot product
+        reinterpret_cast<uint4 *>(sF[w] + lane * NF)[0] = v0;
+        reinterpret_cast<uint4 *>(sF[w] + lane * NF)[1] = v1;
+        wave_sync();
+        mlp_tile(R, sF[w], sH[w], sy[w], col, g);
+        if (row < rows) y[row] = sy[w][lane];
+    }
+}
+
+// Features, network and correction in one pass: out = M + y s on S.
+__global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_correct(MlpFeatParams P, const uint8_t *__restrict__ W,
+                                                                double *out) {
+    __shared__ __align__(16) uint16_t sF[kFwdWaves][64 * NF];
+    __shared__ __align__(16) uint16_t sH[kFwdWaves][16 * NH];
+    __shared__ float sy[kFwdWaves][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, g = lane >> 4;
+    MlpRegs R;
+    load_mlp_regs(W, col, g, R);
+    const int64_t ntiles = (P.nnz + 63) / 64;
+    for (int64_t tile = (int64_t)blockIdx.x * kFwdWaves + w; tile < ntiles; tile += (int64_t)gridDim.x * kFwdWaves) {
+        const int64_t p = tile * 64 + lane;
+        uint16_t f[NF];
+        double m = 0.0, sc = 1.0;
+        if (p < P.nnz) {
+            entry_features(P, p, f, m, sc);
+        } else {
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            float part[4] = {0.f, 0.f, 0.f, 0.f};
-            bf16x8 a0 = load8(H + (mt * 16 + col) * NH + 8 * g);
-            bf16x8 a1 = load8(H + (mt * 16 + col) * NH + 32 + 8 * g);
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int n = nt * 16 + col;
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, load8(sW2 + n * NH + 8 * g), acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, load8(sW2 + n * NH + 32 + 8 * g), acc, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float v = acc[r] + sb2[n];
-                    v = round_bf16(v > 0.f ? v : 0.f);
-                    part[r] += v * sw3[n];
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float v = part[r];
-                v += __shfl_xor(v, 1, 64);
-                v += __shfl_xor(v, 2, 64);
-                v += __shfl_xor(v, 4, 64);
-                v += __shfl_xor(v, 8, 64);
-                part[r] = v;
-            }
-            if (col == 0) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t row = base + mt * 16 + 4 * g + r;
-                    if (row < rows) y[row] = part[r] + sb3;
-                }
-            }
+            for (int k = 0; k < NF; ++k) f[k] = 0;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint4 *dst = reinterpret_cast<uint4 *>(sF[w] + lane * NF);
+        dst[0] = make_uint4(f[0] | (uint32_t)f[1] << 16, f[2] | (uint32_t)f[3] << 16, f[4] | (uint32_t)f[5] << 16,
+                            f[6] | (uint32_t)f[7] << 16);
+        dst[1] = make_uint4(f[8] | (uint32_t)f[9] << 16, f[10] | (uint32_t)f[11] << 16,
+                            f[12] | (uint32_t)f[13] << 16, f[14] | (uint32_t)f[15] << 16);
+        wave_sync();
+        mlp_tile(R, sF[w], sH[w], sy[w], col, g);
+        if (p < P.nnz) out[p] = m + (double)sy[w][lane] * (double)(float)sc;
     }
 }
 
@@ -362,12 +450,24 @@ __global__ void k_mlp_apply(int64_t nnz, const double *__restrict__ M, const flo
 
 }  // namespace dev
 
-hipError_t launch_mlp_features(const MlpFeatParams &P, const int64_t *L_rowptr, const double *L_val,
-                               hipStream_t st) {
-    dim3 gn((P.n + 255) / 256);
-    hipLaunchKernelGGL(dev::k_row_norms, gn, dim3(256), 0, st, P.n, L_rowptr, L_val, P.rn);
-    hipLaunchKernelGGL(dev::k_col_norms, gn, dim3(256), 0, st, P.n, P.ustart, P.Lu, P.cn);
-    hipLaunchKernelGGL(dev::k_features, dim3((unsigned)((P.nnz + 255) / 256)), dim3(256), 0, st, P);
+hipError_t launch_node_feats(const MlpFeatParams &P, const int64_t *L_rowptr, const double *L_val,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_node_feats, dim3((P.n + 255) / 256), dim3(256), 0, st, P, L_rowptr, L_val);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_features(const MlpFeatParams &P, hipStream_t st) {
+    if (P.nnz > 0)
+        hipLaunchKernelGGL(dev::k_features, dim3((unsigned)((P.nnz + 255) / 256)), dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_correct(const MlpFeatParams &P, const void *W, double *out, hipStream_t st) {
+    if (P.nnz <= 0) return hipSuccess;
+    const int64_t tiles = (P.nnz + 63) / 64;
+    const int64_t grid = std::min<int64_t>((tiles + dev::kFwdWaves - 1) / dev::kFwdWaves, 8192);
+    hipLaunchKernelGGL(dev::k_mlp_correct, dim3((unsigned)grid), dim3(64 * dev::kFwdWaves), 0, st, P,
+                       reinterpret_cast<const uint8_t *>(W), out);
     return hipGetLastError();
 }
 
@@ -379,7 +479,7 @@ hipError_t launch_mlp_pack(const float *theta, void *W, hipStream_t st) {
 hipError_t launch_mlp_forward(const void *W, const uint16_t *F, int64_t rows, float *y, hipStream_t st) {
     if (rows <= 0) return hipSuccess;
     const int64_t tiles = (rows + 63) / 64;
-    const int64_t grid = std::min<int64_t>((tiles + dev::kFwdWaves - 1) / dev::kFwdWaves, 4096);
+    const int64_t grid = std::min<int64_t>((tiles + dev::kFwdWaves - 1) / dev::kFwdWaves, 8192);
     hipLaunchKernelGGL(dev::k_mlp_forward, dim3((unsigned)grid), dim3(64 * dev::kFwdWaves), 0, st,
                        reinterpret_cast<const uint8_t *>(W), F, rows, y);
     return hipGetLastError();

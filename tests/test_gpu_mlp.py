@@ -110,14 +110,13 @@ def test_features_parity_and_zero_layer_identity():
     N = s.ninv(Lv, dd, ds, p=3, delta=0.1)
     M = s.mix(Z, N, eps)
     Fe, sc = s.mlp_features(Z, N, M, eps, Lv, dd, ds)
-    rp, cl, lev = s.pattern(with_level=True)
     s.sync()
     S = oc.pattern(F)
     Zo = oc.selinv(F, S)
     No = oc.ninv(F, S, 3, 0.1)
     Mo = oc.mix(S, Zo, No, eps)
     ucount = np.array([int((S.col[S.rowptr[j]:S.rowptr[j + 1]] > j).sum()) for j in range(F.n)])
-    Xo, so = om.features(S, Zo, No, Mo, eps, F, lev.cpu().numpy().astype(np.int64), ucount)
+    Xo, so = om.features(S, Zo, No, Mo, eps, F, oc.dag_levels(F, S), ucount)
     Xg = (Fe.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
     same = Xg == Xo
     print(f"  features identical: {same.mean():.6f}")
@@ -154,3 +153,65 @@ def test_training_gain_on_held_out_matrices():
     print(f"  held-out mean entry error vs tight SelInv: Mix {base[0]:.4e} -> Mix+learned {got[0]:.4e} "
           f"(gain {base[0] / got[0]:.2f}x); p99 {base[1]:.3e} -> {got[1]:.3e}")
     assert got[0] < base[0]
+
+
+@pytest.mark.parametrize("case", ["rand2500", "kkt"])
+def test_fused_correction_matches_three_calls_and_oracle(case):
+    """asi_mlp_correct equals features -> forward -> apply bit for bit, and the
+    oracle's features -> network -> M + y s within the forward tolerance."""
+    import torch
+    from paper_2609_11363_amd import Solver, upload_factors
+    from workloads import kkt_matrix
+    print(f"[mlp correct] case={case}", flush=True)
+    if case == "rand2500":
+        A = random_dd_symmetric(4, n=2500)
+        F = ildl_bk(A, rcm(A), 1e-2)
+    else:
+        A = kkt_matrix(60, 40, 3)
+        F = ildl_bk(A, None, 1e-2)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    Lv, dd, ds = upload_factors(F)
+    eps = 1e-2
+    Z = s.selinv(Lv, dd, ds)
+    N = s.ninv(Lv, dd, ds, p=3, delta=0.1)
+    M = s.mix(Z, N, eps)
+    theta_h = om.init_params(11)
+    theta_h[5248:5313] *= 0.01  # a correction of the size the trained network makes
+    theta = torch.as_tensor(theta_h, device=s.device)
+    packed = s.mlp_pack(theta)
+    Fe, sc = s.mlp_features(Z, N, M, eps, Lv, dd, ds)
+    y = s.mlp_forward(packed, Fe)
+    out3 = s.mlp_apply(M, y, sc)
+    outF = s.mlp_correct(packed, Z, N, M, eps, Lv, dd, ds)
+    Ma = M.clone()
+    s.mlp_correct(packed, Z, N, Ma, eps, Lv, dd, ds, out=Ma)  # out may alias M
+    s.sync()
+    diff = (out3 != outF).nonzero().flatten()
+    if diff.numel():
+        d = (out3 - outF).abs()
+        k = int(diff[0])
+        print(f"  fused vs three calls: {diff.numel()} of {out3.numel()} differ, max {d.max().item():.3e}; "
+              f"first at {k}: {out3[k].item()!r} vs {outF[k].item()!r}, M {M[k].item()!r}, y {y[k].item()!r}, "
+              f"s {sc[k].item()!r}")
+    assert torch.equal(out3, outF)
+    assert torch.equal(outF, Ma)
+    # oracle: its own SelInv, NInv, Mix and features, then the network
+    S = oc.pattern(F)
+    Zo = oc.selinv(F, S)
+    No = oc.ninv(F, S, 3, 0.1)
+    Mo = oc.mix(S, Zo, No, eps)
+    ucount = np.array([int((S.col[S.rowptr[j]:S.rowptr[j + 1]] > j).sum()) for j in range(F.n)])
+    Xo, so = om.features(S, Zo, No, Mo, eps, F, oc.dag_levels(F, S), ucount)
+    yo = om.forward(theta_h, Xo)
+    want = Mo + yo.astype(np.float64) * so.astype(np.float64)
+    got = outF.cpu().numpy()
+    # scale of the correction: |y| s; compare the corrections themselves
+    d_got, d_want = got - Mo, want - Mo
+    err = np.abs(d_got - d_want)
+    scale = np.abs(d_want).max() + 1e-300
+    rel = err / (np.abs(d_want) + 1e-3 * scale)
+    print(f"  |S|={S.nnz} max |correction| {scale:.3e} max abs err {err.max():.2e} median rel {np.median(rel):.2e}")
+    assert np.median(rel) <= 1e-5
+    assert err.max() <= 2e-2 * scale
+    assert (rel > 1e-4).mean() <= 0.01

@@ -87,7 +87,7 @@ def test_features_match_per_entry_brute_force():
         sij = np.sqrt(abs(M[dpos[i]] * M[dpos[j]])) or 1.0
         want = [M[q] / sij, (Z[q] - N[q]) / sij,
                 float(abs(Z[q]) > eps * np.sqrt(abs(Z[dpos[i]] * Z[dpos[j]]))), float(i == j),
-                np.log(abs(Dinv[i, i])), np.log(abs(Dinv[j, j])),
+                np.log(abs(Dinv[i, i]) + 1e-30), np.log(abs(Dinv[j, j]) + 1e-30),
                 np.log(np.linalg.norm(Lm[i]) + 1e-30), np.log(np.linalg.norm(Lm[j]) + 1e-30),
                 np.log(np.linalg.norm(Lm[:, i]) + 1e-30), np.log(np.linalg.norm(Lm[:, j]) + 1e-30),
                 abs(Lm[max(i, j), min(i, j)]), np.log1p(abs(N[q]) / sij), np.log1p(abs(Z[q]) / sij),
@@ -95,3 +95,35 @@ def test_features_match_per_entry_brute_force():
         np.testing.assert_array_equal(X[q], om.bf16(np.array(want, np.float32)))
         assert s[q] == np.float32(sij)
     del Ld
+
+
+def test_dag_levels_chain_and_brute_force():
+    from workloads import kkt_matrix
+    # tridiagonal in natural order, no drops: column j depends on j + 1 only
+    A = laplace2d(12, 1, 0.5)
+    F = ildl_bk(A, np.arange(12), 0.0)
+    S = oc.pattern(F)
+    np.testing.assert_array_equal(oc.dag_levels(F, S), np.arange(11, -1, -1))
+    # 1x1 pivots only: the per-column recursion written out directly
+    A = laplace2d(9, 9, 0.05)
+    F = ildl_bk(A, rcm(A), 5e-2)
+    S = oc.pattern(F)
+    assert int(np.sum(F.piv != 0)) == 0
+    want = np.zeros(F.n, np.int64)
+    for j in range(F.n - 1, -1, -1):
+        R = [c for c in S.col[S.rowptr[j]:S.rowptr[j + 1]] if c > j]
+        want[j] = 0 if not R else 1 + max(want[r] for r in R)
+    np.testing.assert_array_equal(oc.dag_levels(F, S), want)
+    # 2x2 pivots: both columns of a block share its level, which exceeds the
+    # level of every row below the block
+    A = kkt_matrix(30, 20, 1)
+    F = ildl_bk(A, None, 1e-2)
+    S = oc.pattern(F)
+    lev = oc.dag_levels(F, S)
+    first = np.nonzero(F.piv == 1)[0]
+    assert len(first) > 0
+    for j0 in first:
+        assert lev[j0] == lev[j0 + 1]
+        R = [c for c in np.concatenate([S.col[S.rowptr[j0]:S.rowptr[j0 + 1]],
+                                        S.col[S.rowptr[j0 + 1]:S.rowptr[j0 + 2]]]) if c > j0 + 1]
+        assert all(lev[j0] > lev[r] for r in R)
