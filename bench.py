@@ -23,6 +23,7 @@ the library's stream, and the CPU oracle timed on the host.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -32,6 +33,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# L2 <-> memory traffic of the float64 SelInv level kernels on the default
+# workload (64^3, tau = 1e-3), from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
+# scaled by a 256 MiB copy (3.396 GB read + 0.371 GB written per sweep of 140
+# launches). It holds only for the kernel sources it was measured on; any
+# other sources report null.
+SELINV_TRAFFIC = {"sources_sha256": "246134584951bf5db6dced2841f7886b8fbb4dcd4eb3c31e5290124428bde267",
+                  "bytes_per_launch": (3.396e9 + 0.371e9) / 140,
+                  "profile": "profiles/selinv_ninv_mix_learned_diffusion64.md"}
+
+
+def selinv_sources_sha256():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h", "asi_internal.h"):
+        with open(os.path.join(ROOT, "paper_2609_11363_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(msg):
@@ -203,6 +221,9 @@ def run_diffusion(args):
     avg_ms = tot_ms / max(launches, 1)
     achieved = (tot_bytes / launches) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     log("profile: " + ", ".join(f"{k}: {v[0]} launches {v[1]:.3f} ms" for k, v in prof.items() if v[0]))
+    traffic = None
+    if N == 64 and tau == 1e-3 and selinv_sources_sha256() == SELINV_TRAFFIC["sources_sha256"]:
+        traffic = SELINV_TRAFFIC["bytes_per_launch"]
 
     result = {
         "metric": "selected entries of A^-1 per sec (SelInv, Mix, Mix+learned) at stated rel error",
@@ -239,9 +260,11 @@ def run_diffusion(args):
         "selinv_sweeps_ms": sweeps,
         "graph_step_ms": ms_graph,
         "profile_ms_per_step": {k: v[1] / 3 for k, v in prof.items() if v[0]},
-        "roofline": {"kernel": "k_selinv_small (SelInv level, wavefront per block)",
+        "roofline": {"kernel": "SelInv level kernels, float64 (k_selinv_small / k_selinv_group)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (L2 <-> memory, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                     "traffic_source": SELINV_TRAFFIC["profile"] if traffic else None,
                      "launches_per_step": launches // 3, "avg_launch_ms": avg_ms,
                      "alg_bytes_per_launch": tot_bytes / max(launches, 1),
                      "dominant_class_by_time": dom},

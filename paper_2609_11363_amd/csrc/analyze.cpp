@@ -273,6 +273,27 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
             (small ? A.lvl_bytes_small[m] : A.lvl_bytes_big[m])[A.level[j]] += b;
         }
     }
+    for (int k = 0; k < 2; ++k) {
+        const std::vector<int32_t> &sched = k == 0 ? A.sched_small : A.sched_big;
+        std::vector<BlockMeta> &meta = k == 0 ? A.meta_small : A.meta_big;
+        meta.resize(sched.size());
+        for (size_t s = 0; s < sched.size(); ++s) {
+            const int32_t j = sched[s];
+            const bool two = piv[j] == 1;
+            const int32_t last = two ? j + 1 : j;
+            BlockMeta m{};
+            m.ub = A.ustart[last];
+            m.ubj = two ? A.ustart[j] + 1 : m.ub;
+            m.h0 = A.hit_ptr[j];
+            m.pdl = A.diagpos[last] + 1;
+            m.pdj = two ? A.diagpos[j] + 2 : m.pdl;
+            m.j = j;
+            m.c = (int32_t)(A.ustart[last + 1] - m.ub);
+            m.nwords = (int32_t)(A.hit_ptr[last + 1] - m.h0);
+            m.two = two ? 1 : 0;
+            meta[s] = m;
+        }
+    }
     return OK;
 }
 

@@ -47,8 +47,8 @@ struct asi_handle_s {
     int sweep = ASI_SWEEP_AUTO;
     int8_t *piv = nullptr;
     int32_t *level = nullptr;
-    int32_t *sched_small = nullptr;
-    int32_t *sched_big = nullptr;
+    asi::BlockMeta *meta_small = nullptr;
+    asi::BlockMeta *meta_big = nullptr;
     double *dinv = nullptr;
     double *zdiag = nullptr;
     int32_t *status = nullptr;
@@ -130,8 +130,8 @@ Layout make_layout(const asi::Analysis &A) {
     L.add((n + 1) * 8);                 // 5 ustart
     L.add(n);                           // 6 piv
     L.add(n * 4);                       // 7 level
-    L.add(A.sched_small.size() * 4);    // 8
-    L.add(A.sched_big.size() * 4);      // 9
+    L.add(A.meta_small.size() * 64);    // 8 block records, wavefront-per-block schedule
+    L.add(A.meta_big.size() * 64);      // 9 block records, workgroup-per-block schedule
     L.add(3 * n * 8);                   // 10 dinv
     L.add(u * 4);                       // 11 ucol
     L.add(n * 8);                       // 12 zdiag (Mix)
@@ -290,8 +290,8 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->ustart = at<int64_t>(b, L.off[5]);
     h->piv = at<int8_t>(b, L.off[6]);
     h->level = at<int32_t>(b, L.off[7]);
-    h->sched_small = at<int32_t>(b, L.off[8]);
-    h->sched_big = at<int32_t>(b, L.off[9]);
+    h->meta_small = at<asi::BlockMeta>(b, L.off[8]);
+    h->meta_big = at<asi::BlockMeta>(b, L.off[9]);
     h->dinv = at<double>(b, L.off[10]);
     h->ucol = at<int32_t>(b, L.off[11]);
     h->zdiag = at<double>(b, L.off[12]);
@@ -350,8 +350,8 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
         {h->rowptr_L, A.L_rowptr.data(), A.L_rowptr.size() * 8},
         {h->piv, A.piv.data(), A.piv.size()},
         {h->level, A.level.data(), A.level.size() * 4},
-        {h->sched_small, A.sched_small.data(), A.sched_small.size() * 4},
-        {h->sched_big, A.sched_big.data(), A.sched_big.size() * 4},
+        {h->meta_small, A.meta_small.data(), A.meta_small.size() * 64},
+        {h->meta_big, A.meta_big.data(), A.meta_big.size() * 64},
     };
     for (auto &u : ups) {
         if (u.bytes == 0) continue;
@@ -451,20 +451,21 @@ asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, c
         for (int32_t l = 0; l < A.n_levels; ++l) bytes += A.lvl_bytes_small[m][l];
         h->epoch = h->epoch == INT32_MAX ? 1 : h->epoch + 1;
         Trace t(h, ASI_K_SELINV_FLOW, bytes);
-        e = asi::launch_selinv_flow(P, h->sched_small, A.n_blocks, h->done, h->epoch, 1 << 21, fp64, grid,
+        P.meta = h->meta_small;
+        e = asi::launch_selinv_flow(P, A.n_blocks, h->done, h->epoch, 1 << 21, fp64, grid,
                                     h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "selinv dataflow launch");
         return ASI_OK;
     }
     for (int32_t l = 0; l < A.n_levels; ++l) {
-        P.blocks = h->sched_small + A.lvl_small[l];
+        P.meta = h->meta_small + A.lvl_small[l];
         P.nblk = A.lvl_small[l + 1] - A.lvl_small[l];
         if (P.nblk > 0) {
             Trace t(h, ASI_K_SELINV, A.lvl_bytes_small[m][l]);
             e = asi::launch_selinv_level(P, false, fp64, h->stream, asi::small_group_size(P.nblk));
             if (e != hipSuccess) return hip_fail(h, e, "selinv level");
         }
-        P.blocks = h->sched_big + A.lvl_big[l];
+        P.meta = h->meta_big + A.lvl_big[l];
         P.nblk = A.lvl_big[l + 1] - A.lvl_big[l];
         if (P.nblk > 0) {
             Trace t(h, ASI_K_SELINV_BIG, A.lvl_bytes_big[m][l]);

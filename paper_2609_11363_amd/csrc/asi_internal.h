@@ -9,6 +9,22 @@
 
 namespace asi {
 
+// Per-slot record of a SelInv block, one per entry of a schedule, so that a
+// wavefront finds everything it needs to start in one load.
+struct BlockMeta {
+    int64_t ub;      // u-start of the R_J entries of column last (the block's last column)
+    int64_t ubj;     // u-start of L(R_J, j) (ub for a 1x1 block)
+    int64_t h0;      // first hit word of the block
+    int64_t pdl;     // S position of row last's first upper entry (diagpos[last] + 1)
+    int64_t pdj;     // the same for row j (diagpos[j] + 2 for a 2x2 block, else pdl)
+    int32_t j;       // first column of the block
+    int32_t c;       // |R_J|
+    int32_t nwords;  // hit words of the block
+    int32_t two;     // 1 for a 2x2 block
+    int64_t pad;
+};
+static_assert(sizeof(BlockMeta) == 64, "block records are 64 bytes");
+
 // Kernel limits (the analysis refuses patterns above them).
 constexpr int kSmallCols = 128;   // |R_J| handled by one wavefront per block
 constexpr int kBigCols = 2048;    // |R_J| handled by one 256-thread workgroup per block
@@ -55,6 +71,7 @@ struct Analysis {
     int32_t max_cols = 0;
     // level-major schedules of block starts, split by column count
     std::vector<int32_t> sched_small, sched_big;
+    std::vector<BlockMeta> meta_small, meta_big;  // records of the schedules' slots
     std::vector<int32_t> lvl_small, lvl_big;  // n_levels+1 offsets into the schedules
     int64_t gather_pairs = 0;
     int64_t gather_hits = 0;

@@ -13,7 +13,7 @@ namespace asi {
 enum : int32_t { ST_SINGULAR = 3, ST_NONFINITE = 4, ST_POOL = 6, ST_LIMIT = 8, ST_TIMEOUT = 9 };
 
 struct SelinvParams {
-    const int32_t *blocks;  // block starts of this launch
+    const BlockMeta *meta;  // records of this launch's blocks
     int32_t nblk;
     const int64_t *ustart;   // n+1
     const int32_t *ucol;     // nnzU
@@ -38,8 +38,8 @@ hipError_t launch_dinv(int32_t n, const int8_t *piv, const double *dd, const dou
 hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipStream_t st, int group);
 // Dataflow sweep over all blocks in one cooperative launch (|R_J| <= kSmallCols).
 int flow_grid(bool fp64);
-hipError_t launch_selinv_flow(const SelinvParams &P, const int32_t *order, int32_t nblocks, int32_t *done,
-                              int32_t epoch, int32_t spin_limit, bool fp64, int grid, hipStream_t st);
+hipError_t launch_selinv_flow(const SelinvParams &P, int32_t nblocks, int32_t *done, int32_t epoch,
+                              int32_t spin_limit, bool fp64, int grid, hipStream_t st);
 hipError_t launch_gather_lu(int64_t nnzU, const int64_t *lsrc_u, const double *Lval, void *Lu, bool fp64,
                             hipStream_t st);
 hipError_t set_big_lds_limits();

@@ -180,104 +180,110 @@ __device__ inline void group_sync() {
 // Static part of a block's staging (data that no block of the sweep writes):
 // L(R_J, J), the gather segments, the rows of R_J and the mirror positions.
 template <typename T, int G, int NT>
-__device__ inline void stage_static(const SelinvParams &P, int32_t j, const SelinvLds<T> &S, int tid,
+__device__ inline void stage_static(const SelinvParams &P, const BlockMeta &M, const SelinvLds<T> &S, int tid,
                                     int32_t (&rr)[NT], int64_t (&mir0)[NT], int64_t (&mir1)[NT]) {
-    const bool two = P.piv[j] == 1;
-    const int32_t last = two ? j + 1 : j;
-    const int64_t ub = P.ustart[last];
-    const int32_t c = (int32_t)(P.ustart[last + 1] - ub);
-    const int64_t ubj = two ? P.ustart[j] + 1 : ub;
+    const bool two = M.two != 0;
     const T *Lu = reinterpret_cast<const T *>(P.Lu);
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
         const int t = tid + k * G;
         rr[k] = -1;
         mir0[k] = mir1[k] = -1;
-        if (t < c) {
-            rr[k] = P.ucol[ub + t];
-            S.seg[t] = P.useg[ub + t];
-            S.l0[t] = Lu[ubj + t];
-            if (two) S.l1[t] = Lu[ub + t];
-            mir0[k] = P.mirror_u[ubj + t];
-            if (two) mir1[k] = P.mirror_u[ub + t];
+        if (t < M.c) {
+            rr[k] = P.ucol[M.ub + t];
+            S.seg[t] = P.useg[M.ub + t];
+            S.l0[t] = Lu[M.ubj + t];
+            if (two) S.l1[t] = Lu[M.ub + t];
+            mir0[k] = P.mirror_u[M.ubj + t];
+            if (two) mir1[k] = P.mirror_u[M.ub + t];
         }
     }
 }
 
+// The hit words of one pass (kUnroll per lane); words past the end are 0.
+template <bool WIDE, int G>
+__device__ inline void load_hit_words(const uint32_t *H, int32_t base, int32_t total, uint32_t (&w0)[kUnroll],
+                                      uint32_t (&w1)[kUnroll]) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const int32_t t = base + u * G;
+        w0[u] = 0u;
+        w1[u] = 0u;
+        if (t < total) {
+            if (WIDE) {
+                w0[u] = H[2 * t];
+                w1[u] = H[2 * t + 1];
+            } else {
+                w0[u] = H[t];
+            }
+        }
+    }
+}
+
+// The dependent global loads of a block are kept to three rounds: the block
+// record; then the staging, the first hit words and (once the rows are known)
+// the diagonal entries Z(r, r), all in flight together; then the Z gathers of
+// each pass, with the next pass's hit words loaded behind them. The diagonal
+// term -Z(r, r) L(r, J) is added after the hits.
 template <typename T, int G, int NT, bool WIDE, bool CO = false, bool PRE = false>
-__device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T> &S, int tid,
+__device__ void selinv_block(const SelinvParams &P, const BlockMeta &M, const SelinvLds<T> &S, int tid,
                              double *red /* G > 64: (G / 64) waves x 4 partial sums */,
                              const int32_t *pre_r = nullptr, const int64_t *pre_m0 = nullptr,
                              const int64_t *pre_m1 = nullptr) {
-    const bool two = P.piv[j] == 1;
+    const bool two = M.two != 0;
+    const int32_t j = M.j;
     const int32_t last = two ? j + 1 : j;
-    const int64_t ub = P.ustart[last];
-    const int32_t c = (int32_t)(P.ustart[last + 1] - ub);
-    const int64_t ubj = two ? P.ustart[j] + 1 : ub;  // L(R_J, j) in row j's u-range
+    const int32_t c = M.c;
+    const int64_t ub = M.ub, ubj = M.ubj;
     const T *Lu = reinterpret_cast<const T *>(P.Lu);
     T *Zu = reinterpret_cast<T *>(P.Zu);
-    const int64_t pdl = P.diagpos[last] + 1;  // S position of row last's first upper entry
-    const int64_t pdj = two ? P.diagpos[j] + 2 : pdl;
-    const int64_t h0 = P.hit_ptr[j];
-    const int32_t nwords = (int32_t)(P.hit_ptr[last + 1] - h0);
-    const int32_t total = WIDE ? nwords / 2 : nwords;
+    const int32_t total = WIDE ? M.nwords / 2 : M.nwords;
+    const uint32_t *H = P.hits + M.h0;
+    constexpr int kStep = G * kUnroll;
 
-    // stage L(R_J, J), the gather segments and the diagonal terms; the
-    // mirror positions of the outputs stay in registers
+    uint32_t w0[kUnroll], w1[kUnroll];
+    load_hit_words<WIDE, G>(H, tid, total, w0, w1);
+    // stage L(R_J, J) and the gather segments; rows, mirror positions and
+    // the diagonal entries Z(r, r) stay in registers
+    int32_t rr[NT];
     int64_t mir0[NT], mir1[NT];
+    T zrr[NT];
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
         const int t = tid + k * G;
         if constexpr (PRE) {
+            rr[k] = pre_r[k];
             mir0[k] = pre_m0[k];
             mir1[k] = pre_m1[k];
+        } else {
+            rr[k] = -1;
+            mir0[k] = mir1[k] = -1;
             if (t < c) {
-                T zll = (T)co_load<CO>(&P.zdiag[pre_r[k]]);
-                S.y0[t] = -zll * S.l0[t];
-                if (two) S.y1[t] = -zll * S.l1[t];
+                rr[k] = P.ucol[ub + t];
+                S.seg[t] = P.useg[ub + t];
+                S.l0[t] = Lu[ubj + t];
+                if (two) S.l1[t] = Lu[ub + t];
+                mir0[k] = P.mirror_u[ubj + t];
+                if (two) mir1[k] = P.mirror_u[ub + t];
             }
-            continue;
         }
-        mir0[k] = mir1[k] = -1;
+        zrr[k] = T(0);
         if (t < c) {
-            int32_t r = P.ucol[ub + t];
-            int64_t sg = P.useg[ub + t];
-            T v0 = Lu[ubj + t];
-            T v1 = two ? Lu[ub + t] : T(0);
-            mir0[k] = P.mirror_u[ubj + t];
-            if (two) mir1[k] = P.mirror_u[ub + t];
-            S.seg[t] = sg;
-            S.l0[t] = v0;
-            if (two) S.l1[t] = v1;
-            T zll = (T)co_load<CO>(&P.zdiag[r]);
-            S.y0[t] = -zll * v0;
-            if (two) S.y1[t] = -zll * v1;
+            zrr[k] = (T)co_load<CO>(&P.zdiag[rr[k]]);
+            S.y0[t] = T(0);
+            if (two) S.y1[t] = T(0);
         }
     }
     group_sync<G>();
-    const uint32_t *H = P.hits + h0;
     // loop bound uniform across the group so every lane joins the shuffles
-    for (int32_t base0 = 0; base0 < total; base0 += G * kUnroll) {
-        const int32_t base = base0 + tid;
+    for (int32_t base0 = 0; base0 < total; base0 += kStep) {
         int32_t a[kUnroll], b[kUnroll];
-        uint32_t w0[kUnroll], w1[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int32_t t = base + u * G;
-            b[u] = -1;
-            if (t < total) {
-                if (WIDE) {
-                    w0[u] = H[2 * t];
-                    w1[u] = H[2 * t + 1];
-                } else {
-                    w0[u] = H[t];
-                }
-            }
-        }
         T z[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int32_t t = base + u * G;
+            const int32_t t = base0 + tid + u * G;
+            b[u] = -1;
+            a[u] = 0;
             if (t < total) {
                 int64_t off;
                 if (WIDE) {
@@ -292,6 +298,7 @@ __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T
                 z[u] = co_load<CO>(&Zu[S.seg[b[u]] + off]);
             }
         }
+        if (base0 + kStep < total) load_hit_words<WIDE, G>(H, base0 + kStep + tid, total, w0, w1);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             T dot0 = T(0), dot1 = T(0);
@@ -317,18 +324,20 @@ __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T
     for (int k = 0; k < NT; ++k) {
         const int t = tid + k * G;
         if (t >= c) continue;
-        T y0 = S.y0[t];
+        const T l0t = S.l0[t];
+        const T y0 = S.y0[t] - zrr[k] * l0t;
         co_store<CO>(&Zu[ubj + t], y0);
-        P.out[pdj + t] = (double)y0;
+        P.out[M.pdj + t] = (double)y0;
         P.out[mir0[k]] = (double)y0;
-        double l0 = (double)S.l0[t];
+        double l0 = (double)l0t;
         d00 += l0 * (double)y0;
         if (two) {
-            T y1 = S.y1[t];
+            const T l1t = S.l1[t];
+            const T y1 = S.y1[t] - zrr[k] * l1t;
             co_store<CO>(&Zu[ub + t], y1);
-            P.out[pdl + t] = (double)y1;
+            P.out[M.pdl + t] = (double)y1;
             P.out[mir1[k]] = (double)y1;
-            double l1 = (double)S.l1[t];
+            double l1 = (double)l1t;
             d11 += l1 * (double)y1;
             d10 += l1 * (double)y0;
             d01 += l0 * (double)y1;
@@ -359,18 +368,20 @@ __device__ void selinv_block(const SelinvParams &P, int32_t j, const SelinvLds<T
     }
     if (tid == 0) {
         const double *iv = P.dinv + 3 * (int64_t)j;
+        const int64_t dj = two ? M.pdj - 2 : M.pdl - 1;  // diagpos[j]
+        const int64_t dl = M.pdl - 1;                     // diagpos[last]
         double zjj = iv[0] - d00;
-        P.out[P.diagpos[j]] = zjj;
+        P.out[dj] = zjj;
         co_store<CO>(&P.zdiag[j], zjj);
         bool bad = !isfinite(zjj);
         if (two) {
             double z11 = iv[2] - d11;
             double off = iv[1] - 0.5 * (d10 + d01);
-            P.out[P.diagpos[last]] = z11;
+            P.out[dl] = z11;
             co_store<CO>(&P.zdiag[last], z11);
-            P.out[P.diagpos[j] + 1] = off;
-            P.out[P.diagpos[last] - 1] = off;
-            co_store<CO>(&Zu[P.ustart[j]], (T)off);  // (j, j+1), read by later gathers
+            P.out[dj + 1] = off;
+            P.out[dl - 1] = off;
+            co_store<CO>(&Zu[ubj - 1], (T)off);  // (j, j+1) at ustart[j], read by later gathers
             bad = bad || !isfinite(z11) || !isfinite(off);
         }
         if (bad) latch(P.status, 4);
@@ -382,11 +393,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_selinv_small(SelinvParams P) {
     __shared__ T sL0[WAVES][kSmallCols], sL1[WAVES][kSmallCols];
     __shared__ T sY0[WAVES][kSmallCols], sY1[WAVES][kSmallCols];
     __shared__ int64_t sSeg[WAVES][kSmallCols];
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t bi = blockIdx.x * WAVES + w;
     if (bi >= P.nblk) return;  // the whole wavefront leaves; no workgroup barrier follows
     SelinvLds<T> S{sL0[w], sL1[w], sY0[w], sY1[w], sSeg[w]};
-    selinv_block<T, 64, kSmallCols / 64, false>(P, P.blocks[bi], S, lane_id(), nullptr);
+    const BlockMeta M = P.meta[bi];
+    selinv_block<T, 64, kSmallCols / 64, false>(P, M, S, lane_id(), nullptr);
 }
 
 // one workgroup of G threads per block (|R_J| <= kSmallCols), for levels with
@@ -400,7 +412,8 @@ __global__ __launch_bounds__(G) void k_selinv_group(SelinvParams P) {
     const int32_t bi = blockIdx.x;
     if (bi >= P.nblk) return;
     SelinvLds<T> S{sL0, sL1, sY0, sY1, sSeg};
-    selinv_block<T, G, (kSmallCols + G - 1) / G, false>(P, P.blocks[bi], S, threadIdx.x, red);
+    const BlockMeta M = P.meta[bi];
+    selinv_block<T, G, (kSmallCols + G - 1) / G, false>(P, M, S, threadIdx.x, red);
 }
 
 template <typename T>
@@ -417,7 +430,8 @@ __global__ __launch_bounds__(256) void k_selinv_big(SelinvParams P) {
     const int32_t bi = blockIdx.x;
     if (bi >= P.nblk) return;
     SelinvLds<T> S{l0, l1, y0, y1, seg};
-    selinv_block<T, 256, kBigCols / 256, true>(P, P.blocks[bi], S, threadIdx.x, red);
+    const BlockMeta M = P.meta[bi];
+    selinv_block<T, 256, kBigCols / 256, true>(P, M, S, threadIdx.x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -433,23 +447,23 @@ __global__ __launch_bounds__(256) void k_selinv_big(SelinvParams P) {
 // The wait is bounded: after spin_limit polls the status word is latched and
 // the block runs anyway, so the launch always drains.
 template <typename T, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_selinv_flow(SelinvParams P, const int32_t *__restrict__ order,
-                                                            int32_t nblocks, int32_t *done, int32_t epoch,
-                                                            int32_t spin_limit) {
+__global__ __launch_bounds__(64 * WAVES) void k_selinv_flow(SelinvParams P, int32_t nblocks, int32_t *done,
+                                                            int32_t epoch, int32_t spin_limit) {
     __shared__ T sL0[WAVES][kSmallCols], sL1[WAVES][kSmallCols];
     __shared__ T sY0[WAVES][kSmallCols], sY1[WAVES][kSmallCols];
     __shared__ int64_t sSeg[WAVES][kSmallCols];
-    const int w = threadIdx.x >> 6, lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
     SelinvLds<T> S{sL0[w], sL1[w], sY0[w], sY1[w], sSeg[w]};
     const int32_t stride = gridDim.x * WAVES;
     for (int32_t i = blockIdx.x * WAVES + w; i < nblocks; i += stride) {
-        const int32_t j = order[i];
-        const int32_t last = P.piv[j] == 1 ? j + 1 : j;
+        const BlockMeta M = P.meta[i];
+        const int32_t j = M.j;
+        const int32_t last = M.two ? j + 1 : j;
         // stage what no block writes before waiting for the dependencies
         constexpr int NT = kSmallCols / 64;
         int32_t rr[NT];
         int64_t m0[NT], m1[NT];
-        stage_static<T, 64, NT>(P, j, S, lane, rr, m0, m1);
+        stage_static<T, 64, NT>(P, M, S, lane, rr, m0, m1);
         const int32_t r0 = rr[0], r1 = rr[1];
         for (int32_t poll = 0;; ++poll) {
             bool ok = true;
@@ -464,7 +478,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_selinv_flow(SelinvParams P, cons
             __builtin_amdgcn_s_sleep(2);
         }
         wave_sync();
-        selinv_block<T, 64, NT, false, true, true>(P, j, S, lane, nullptr, rr, m0, m1);
+        selinv_block<T, 64, NT, false, true, true>(P, M, S, lane, nullptr, rr, m0, m1);
         // the block's agent-coherent stores are complete before its flag is set
         __builtin_amdgcn_s_waitcnt(0);
         if (lane == 0) {
@@ -559,11 +573,11 @@ int flow_grid(bool fp64) {
     return per * cus;
 }
 
-hipError_t launch_selinv_flow(const SelinvParams &P, const int32_t *order, int32_t nblocks, int32_t *done,
-                              int32_t epoch, int32_t spin_limit, bool fp64, int grid, hipStream_t st) {
+hipError_t launch_selinv_flow(const SelinvParams &P, int32_t nblocks, int32_t *done, int32_t epoch,
+                              int32_t spin_limit, bool fp64, int grid, hipStream_t st) {
     constexpr int W = 4;
     SelinvParams p = P;
-    void *args[] = {&p, (void *)&order, &nblocks, &done, &epoch, &spin_limit};
+    void *args[] = {&p, &nblocks, &done, &epoch, &spin_limit};
     const void *fn = fp64 ? (const void *)dev::k_selinv_flow<double, W> : (const void *)dev::k_selinv_flow<float, W>;
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(64 * W), args, 0, st);
 }
