@@ -61,8 +61,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="diffusion64", choices=["diffusion64", "indefinite512"])
-    ap.add_argument("--grid", type=int, default=None, help="grid size (default 64, resp. 512)")
+    ap.add_argument("--workload", default="diffusion64", choices=["diffusion64", "indefinite512", "stencil27_128"])
+    ap.add_argument("--grid", type=int, default=None, help="grid size (default 64, 512, 128 per workload)")
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--learned-epochs", type=int, default=30)
@@ -78,6 +78,9 @@ def main():
 
     if args.workload == "indefinite512":
         run_indefinite(args)
+        return
+    if args.workload == "stencil27_128":
+        run_stencil27(args)
         return
     run_diffusion(args)
 
@@ -294,31 +297,41 @@ def run_diffusion(args):
     print(json.dumps(result), flush=True)
 
 
-def train_learned(args, tau, p, delta, eps):
+def train_learned(args, tau, p, delta, eps, family="diffusion7"):
     """Train the learned correction on small grids of the workload's family
-    (3D 7-point lognormal diffusion, nested multicolor order): inputs are Mix
-    at tau, targets SelInv at tau/10; the held-out grid reports the gain."""
+    (nested multicolor order): inputs are Mix at tau, targets SelInv at
+    tau/10; the held-out grid reports the gain."""
     from paper_2609_11363_amd import learned
-    from workloads import diffusion3d_7pt, nested_multicolor_grid
+    from workloads import diffusion3d_7pt, nested_multicolor_grid, stencil27_3d
+
+    if family == "diffusion7":
+        gen = lambda Ng, sd: diffusion3d_7pt(Ng, 1.0, sd)  # noqa: E731
+        specs = [(16, 11), (16, 12), (20, 13), (20, 14), (24, 15)]
+        val_spec, test_spec = (20, 16), (24, 17)
+        desc = ("3D 7-point lognormal(0,1) diffusion: 16^3 x2, 20^3 x2, 24^3 (seeds 11-15); validation "
+                "20^3 (seed 16); held-out test 24^3 (seed 17)")
+    else:
+        gen = lambda Ng, sd: stencil27_3d(Ng, 0.5, sd)  # noqa: E731
+        specs = [(12, 21), (14, 22), (14, 23), (16, 24), (18, 25)]
+        val_spec, test_spec = (16, 26), (20, 27)
+        desc = ("3D 27-point lognormal(0,0.5) stencil: 12^3, 14^3 x2, 16^3, 18^3 (seeds 21-25); "
+                "validation 16^3 (seed 26); held-out test 20^3 (seed 27)")
 
     def sample(Ng, seed):
-        Ag = diffusion3d_7pt(Ng, 1.0, seed)
-        return learned.build_sample(Ag, nested_multicolor_grid((Ng, Ng, Ng)), tau_loose=tau,
+        return learned.build_sample(gen(Ng, seed), nested_multicolor_grid((Ng, Ng, Ng)), tau_loose=tau,
                                     tau_tight=tau / 10, p=p, delta=delta, eps=eps)
 
     t0 = time.time()
-    train = [sample(Ng, sd) for Ng, sd in [(16, 11), (16, 12), (20, 13), (20, 14), (24, 15)]]
-    val = [sample(20, 16)]
-    test = [sample(24, 17)]
+    train = [sample(Ng, sd) for Ng, sd in specs]
+    val = [sample(*val_spec)]
+    test = [sample(*test_spec)]
     t_data = time.time() - t0
     t0 = time.time()
     packed, _, hist = learned.train(train, val, epochs=args.learned_epochs, lr=1e-3, seed=0)
     t_train = time.time() - t0
     base = learned.mean_error(test)
     got = learned.mean_error(test, packed) if packed is not None else base
-    info = {"train_grids": "16^3 x2, 20^3 x2, 24^3 (seeds 11-15); validation 20^3 (seed 16); "
-                           "held-out test 24^3 (seed 17)",
-            "tau_loose": tau, "tau_tight": tau / 10, "epochs": args.learned_epochs,
+    info = {"train_grids": desc, "tau_loose": tau, "tau_tight": tau / 10, "epochs": args.learned_epochs,
             "train_rows": int(sum(len(x.target) for x in train)),
             "data_s": t_data, "train_s": t_train, "fallback_to_mix": packed is None,
             "val_mean_entry_error": {"mix": hist["base_val"], "best": min(hist["val"] + [hist["base_val"]])},
@@ -330,6 +343,139 @@ def train_learned(args, tau, p, delta, eps):
     for x in train + val + test:
         del x.solver
     return info, packed
+
+
+def run_stencil27(args):
+    """3D 27-point lognormal(0, 0.5) stencil, 128^3: float64 SelInv, the
+    mixed-precision Mix pipeline and Mix + learned correction. Parity at this
+    size: NInv against the oracle on every entry, SelInv through its defining
+    recursion on sampled blocks, Mix through its selection rule."""
+    import numpy as np
+    import torch
+
+    from paper_2609_11363_amd import Solver, upload_factors
+    from workloads import ildl_bk, nested_multicolor_grid, stencil27_3d
+
+    N, tau = args.grid or 128, args.tau
+    p, delta, eps = 3, 0.1, 1e-2
+    t0 = time.time()
+    A = stencil27_3d(N, 0.5, 5)
+    log(f"generated n={A.shape[0]} nnz(A)={A.nnz}; host ILDL (tau={tau}) starts")
+    F = ildl_bk(A, nested_multicolor_grid((N, N, N)), tau, progress=True)
+    t_fact = time.time() - t0
+    log(f"workload nnz(L)={F.nnzL} |S|={F.nnzS} ildl {t_fact:.1f}s")
+    learned_info, packed = train_learned(args, tau, p, delta, eps, family="stencil27")
+
+    dev = torch.device("cuda", 0)
+    s = Solver(0)
+    t0 = time.time()
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    t_sym = time.time() - t0
+    info = s.info()
+    log(f"analysis {t_sym:.1f}s levels={info['n_levels']} max|R_J|={info['max_cols']} "
+        f"workspace {s.ws.numel() / 1e9:.1f} GB")
+    Lv, dd, ds = upload_factors(F)
+    nnzS = s.nnz_S
+    Z = torch.empty(nnzS, dtype=torch.float64, device=dev)
+    Nn, M, ML = (torch.empty_like(Z) for _ in range(3))
+
+    def mix_pipeline(prec):
+        s.selinv(Lv, dd, ds, precision=prec, out=Z)
+        s.ninv(Lv, dd, ds, p=p, delta=delta, precision=prec, out=Nn)
+        s.mix(Z, Nn, eps, out=M)
+
+    def learned_pipeline(prec):
+        mix_pipeline(prec)
+        if packed is not None:
+            s.mlp_correct(packed, Z, Nn, M, eps, Lv, dd, ds, out=ML)
+
+    for _ in range(args.warmup):
+        learned_pipeline("mixed")
+    s.sync()
+    ms = {"selinv_fp64": timed(lambda: s.selinv(Lv, dd, ds, out=Z), args.steps) * 1e3,
+          "selinv_mixed": timed(lambda: s.selinv(Lv, dd, ds, precision="mixed", out=Z), args.steps) * 1e3,
+          "mix_pipeline_fp64": timed(lambda: mix_pipeline("fp64"), args.steps) * 1e3,
+          "mix_pipeline_mixed": timed(lambda: mix_pipeline("mixed"), args.steps) * 1e3,
+          "mix_learned_pipeline_mixed": timed(lambda: learned_pipeline("mixed"), args.steps) * 1e3}
+    s.sync()
+    log("times: " + ", ".join(f"{k} {v:.2f} ms" for k, v in ms.items()))
+    Zm, Mm = Z.cpu().numpy(), M.cpu().numpy()          # mixed-precision results of the last pipeline
+    MLm = ML.cpu().numpy() if packed is not None else None
+    mix_pipeline("fp64")
+    s.sync()
+    Z64, N64, M64 = Z.cpu().numpy(), Nn.cpu().numpy(), M.cpu().numpy()
+
+    s.profile(True)
+    s.selinv(Lv, dd, ds, out=Z)
+    prof = s.profile_read()
+    s.profile(False)
+    s.sync()
+    launches, tot_ms, tot_bytes = prof["selinv"]
+    avg_ms = tot_ms / max(launches, 1)
+    achieved = (tot_bytes / launches) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+
+    step_ms = ms["mix_learned_pipeline_mixed"]
+    result = {
+        "metric": "selected entries of A^-1 per sec (SelInv, Mix, Mix+learned) at stated rel error",
+        "value": nnzS / (step_ms * 1e-3),
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (mixed: float32 off-diagonal bulk, float64 D blocks and diagonals)",
+        "data": "synthetic",
+        "config": {"workload": f"3D 27-point lognormal(0,0.5) stencil {N}^3, nested multicolor order, ILDL "
+                               f"tau={tau}; step = mixed-precision SelInv + NInv(p=3, delta=0.1) + Mix(eps=1e-2)"
+                               + (" + learned correction" if packed is not None else " (learned fell back to Mix)"),
+                   "n": F.n, "nnz_A": int(A.nnz), "nnz_L": F.nnzL, "nnz_S": nnzS,
+                   "levels": info["n_levels"], "max_cols": info["max_cols"], "parallelism": "single GPU"},
+        "methods": {k: {"ms": v, "entries_per_s": nnzS / (v * 1e-3)} for k, v in ms.items()},
+        "learned": learned_info,
+        "roofline": {"kernel": "SelInv level kernels, float64 (k_selinv_small / k_selinv_group)",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches_per_step": launches,
+                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": tot_bytes / max(launches, 1)},
+        "host": {"ildl_s": t_fact, "analysis_s": t_sym},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import core as oc
+        t0 = time.time()
+        S = oc.pattern(F)
+        log(f"oracle pattern {time.time() - t0:.1f}s; oracle NInv on the whole workload starts")
+        t0 = time.perf_counter()
+        No = oc.ninv(F, S, p, delta)
+        t_ninv = time.perf_counter() - t0
+        log(f"oracle NInv {t_ninv:.1f}s")
+        e_ninv = oc.entry_error(S, N64, No)
+        # Mix: the selection rule applied to the device's SelInv and the oracle's NInv
+        e_mix = oc.entry_error(S, M64, oc.mix(S, Z64, No, eps))
+        # SelInv: the defining recursion on sampled blocks (float64 and mixed results)
+        rng = np.random.default_rng(11)
+        firsts = np.nonzero(F.piv != 2)[0]
+        blocks = np.sort(rng.choice(firsts, size=min(256, len(firsts)), replace=False))
+        t0 = time.perf_counter()
+        e_sel = oc.selinv_block_check(F, S, Z64, blocks)
+        e_sel_m = oc.selinv_block_check(F, S, Zm, blocks)
+        log(f"SelInv recursion on {len(blocks)} sampled blocks {time.perf_counter() - t0:.1f}s: "
+            f"float64 {e_sel.max():.2e}, mixed {e_sel_m.max():.2e}; NInv {e_ninv.max():.2e}; Mix {e_mix.max():.2e}")
+        result["cpu_baseline"] = {"value": nnzS / t_ninv, "unit": "entries/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"oracle NInv (p=3, delta=0.1) on the whole {N}^3 workload, "
+                                            f"{t_ninv:.1f} s (the oracle SelInv is not run at this size)"}
+        result["rel_error_vs_oracle"] = {
+            "ninv_fp64_max_all_entries": float(e_ninv.max()),
+            "mix_fp64_max_selection_rule": float(e_mix.max()),
+            "selinv_fp64_max_recursion_256_blocks": float(e_sel.max()),
+            "selinv_mixed_max_recursion_256_blocks": float(e_sel_m.max()),
+            "mixed_vs_fp64_selinv_max": float(oc.entry_error(S, Zm, Z64).max()),
+            "mixed_vs_fp64_mix_max": float(oc.entry_error(S, Mm, M64).max())}
+        if MLm is not None:
+            result["rel_error_vs_oracle"]["learned_correction_vs_mix_mean"] = float(
+                oc.entry_error(S, MLm, Mm).mean())
+    print(json.dumps(result), flush=True)
 
 
 def run_indefinite(args):

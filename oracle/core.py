@@ -200,6 +200,74 @@ def err1(d: np.ndarray, dhat: np.ndarray) -> float:
     return float(np.abs(d - dhat).sum() / np.abs(d).sum())
 
 
+def selinv_block_check(F, S: Pattern, Z: np.ndarray, blocks) -> np.ndarray:
+    """Largest entry error, per block J in `blocks` (first columns), between a
+    result Z on S and the SelInv recursion of Section 2.1 evaluated from Z's
+    own entries on S: Z(R_J, J) = -Zhat(R_J, R_J) L(R_J, J) with Zhat = Z on S
+    and 0 off S, and Z_JJ = D_J^-1 - L(R_J, J)^T Z(R_J, J) (2x2 off-diagonal:
+    the mean of its two expressions). A Z that satisfies this at every block
+    is the SelInv result; checking a sample of blocks is a property test that
+    holds at any size."""
+    Lc = F.L_csr().tocsc()
+    Lc.sort_indices()
+    Z = np.asarray(Z)
+    dpos = S.diag_positions()
+
+    def zval(rows, cols):
+        # Z at (rows[k], cols[k]) when stored in S, else 0
+        out = np.zeros(len(rows))
+        for k, (r, c) in enumerate(zip(rows, cols)):
+            seg = S.col[S.rowptr[r]:S.rowptr[r + 1]]
+            q = np.searchsorted(seg, c)
+            if q < len(seg) and seg[q] == c:
+                out[k] = Z[S.rowptr[r] + q]
+        return out
+
+    errs = []
+    for j in blocks:
+        j = int(j)
+        J = [j, j + 1] if F.piv[j] == 1 else [j]
+        last = J[-1]
+        R = sorted(set(int(r) for c in J for r in Lc.indices[Lc.indptr[c]:Lc.indptr[c + 1]] if r > last))
+        c = len(R)
+        LRJ = np.zeros((c, len(J)))
+        for b, col in enumerate(J):
+            rows = Lc.indices[Lc.indptr[col]:Lc.indptr[col + 1]]
+            vals = Lc.data[Lc.indptr[col]:Lc.indptr[col + 1]]
+            for r, v in zip(rows, vals):
+                if r > last:
+                    LRJ[R.index(int(r)), b] = v
+        if c:
+            rr, ll = np.meshgrid(R, R, indexing="ij")
+            Zh = zval(rr.ravel(), ll.ravel()).reshape(c, c)
+        else:
+            Zh = np.zeros((0, 0))
+        y = -Zh @ LRJ
+        if len(J) == 1:
+            Dinv = np.array([[1.0 / F.d_diag[j]]])
+        else:
+            a, b2, d = F.d_diag[j], F.d_sub[j], F.d_diag[j + 1]
+            Dinv = np.array([[d, -b2], [-b2, a]]) / (a * d - b2 * b2)
+        ZJJ = Dinv - LRJ.T @ y
+        if len(J) == 2:
+            ZJJ[0, 1] = ZJJ[1, 0] = 0.5 * (ZJJ[0, 1] + ZJJ[1, 0])
+        got_y = np.stack([zval(R, [col] * c) for col in J], axis=1) if c else np.zeros((0, len(J)))
+        got_J = np.array([[zval([a1], [b1])[0] for b1 in J] for a1 in J])
+        def zd(i):
+            return abs(Z[dpos[i]])
+        e = 0.0
+        for k, r in enumerate(R):
+            for b, col in enumerate(J):
+                sc = max(np.sqrt(zd(r) * zd(col)), abs(y[k, b]))
+                e = max(e, abs(got_y[k, b] - y[k, b]) / (sc if sc > 0 else 1.0))
+        for a1 in range(len(J)):
+            for b1 in range(len(J)):
+                sc = max(np.sqrt(zd(J[a1]) * zd(J[b1])), abs(ZJJ[a1, b1]))
+                e = max(e, abs(got_J[a1, b1] - ZJJ[a1, b1]) / (sc if sc > 0 else 1.0))
+        errs.append(e)
+    return np.array(errs)
+
+
 def dag_levels(F, S: Pattern) -> np.ndarray:
     """Level of every unknown in the SelInv dependency DAG (Section 2.1; the
     schedule reading for an incomplete pattern): the blocks J of D (1x1, or

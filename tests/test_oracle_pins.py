@@ -349,3 +349,20 @@ def test_selinv_2x2_incomplete_matches_dense_masked_recursion(seed):
     mask = od.pattern_mask(F)
     Zd = od.masked_selinv(od.dense_L(F), od.dense_D(F.d_diag, F.d_sub, F.piv), F.piv, mask)
     np.testing.assert_allclose(oc.selinv(F, S), S.gather(Zd), rtol=1e-11, atol=1e-13)
+
+
+def test_selinv_block_check_accepts_selinv_and_flags_a_planted_error():
+    """The sampled-block property checker (used where the full oracle is too
+    slow) returns rounding-level errors on the oracle's SelInv, with 1x1 and
+    2x2 blocks, and flags one perturbed entry in the blocks that read it."""
+    from workloads import kkt_matrix
+    for A, q in [(laplace2d(20, 20, 0.05), "rcm"), (kkt_matrix(40, 25, 2), None)]:
+        F = ildl_bk(A, rcm(A) if q == "rcm" else None, 1e-2)
+        S = oc.pattern(F)
+        Z = oc.selinv(F, S)
+        blocks = [j for j in range(F.n) if F.piv[j] != 2]
+        assert oc.selinv_block_check(F, S, Z, blocks).max() <= 1e-13
+        Zb = Z.copy()
+        p = S.rowptr[10] + 1  # an off-diagonal entry of row 10
+        Zb[p] *= 1.0 + 1e-6
+        assert oc.selinv_block_check(F, S, Zb, blocks).max() >= 1e-8

@@ -27,6 +27,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -225,6 +226,10 @@ void ildl_free(ildl_result *r) {
  * 1 = Bunch-Kaufman. Returns 0 on success, -1 on allocation failure,
  * -2 on a singular 2x2 block.
  */
+/* Progress lines on stderr every `every` pivots (0: none), for long runs. */
+static int32_t progress_every = 0;
+void ildl_set_progress(int32_t every) { progress_every = every > 0 ? every : 0; }
+
 int ildl_bk(int32_t n, const int64_t *rowptr, const int32_t *col, const double *val, double tau,
             int pivoting, ildl_result *res) {
     memset(res, 0, sizeof(*res));
@@ -279,7 +284,13 @@ int ildl_bk(int32_t n, const int64_t *rowptr, const int32_t *col, const double *
     const double tiny = 1e-14 * amax, repl = 1e-8 * amax;
 
     int32_t k = 0;
+    int32_t next_report = progress_every;
     while (k < n) {
+        if (progress_every > 0 && k >= next_report) {
+            fprintf(stderr, "[ildl] %d of %d pivots, %lld entries of L so far\n", k, n, (long long)L.n);
+            fflush(stderr);
+            next_report += progress_every;
+        }
         int32_t p = order[k];
         int32_t cp = gather_col(&tab[p], elim, idp, vp);
         int two = 0;

@@ -61,6 +61,8 @@ def _load():
         lib.ildl_bk.restype = ctypes.c_int
         lib.ildl_bk.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Res)]
+        lib.ildl_set_progress.restype = None
+        lib.ildl_set_progress.argtypes = [ctypes.c_int32]
         lib.ildl_free.restype = None
         lib.ildl_free.argtypes = [ctypes.POINTER(_Res)]
         _lib = lib
@@ -108,11 +110,12 @@ class IldlFactors:
                              shape=(n, n))
 
 
-def ildl_bk(A, q=None, tau: float = 1e-3, pivoting: bool = True) -> IldlFactors:
+def ildl_bk(A, q=None, tau: float = 1e-3, pivoting: bool = True, progress: bool = False) -> IldlFactors:
     """Threshold ILDL with Bunch-Kaufman pivots of A ordered by q.
 
     ``q`` is a fill-reducing ordering (identity if None); the returned
-    ``perm`` composes q with the pivoting swaps.
+    ``perm`` composes q with the pivoting swaps. ``progress`` prints a line
+    to stderr every 5 % of the pivots.
     """
     A = sp.csr_matrix(A)
     n = A.shape[0]
@@ -125,6 +128,7 @@ def ildl_bk(A, q=None, tau: float = 1e-3, pivoting: bool = True) -> IldlFactors:
     col = np.ascontiguousarray(B.indices, dtype=np.int32)
     val = np.ascontiguousarray(B.data, dtype=np.float64)
     lib = _load()
+    lib.ildl_set_progress(max(1, n // 20) if progress else 0)
     res = _Res()
     rc = lib.ildl_bk(n, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, float(tau),
                      1 if pivoting else 0, ctypes.byref(res))
