@@ -175,6 +175,8 @@ asi_status asi_lowrank(asi_handle h, int32_t k, const double *V, const double *l
  * log(|D^-1_jj| + 1e-30), log row norms of L at i and j, log column norms of L at i and
  * j, |L(max, min)|, log(1 + |N|/s), log(1 + |Z|/s), level(i)/max level,
  * level(j)/max level, log(1 + |R| of column min(i, j)).
+ * The learned-correction calls that take an analysis need |S| < 2^31
+ * (ASI_E_UNSUPPORTED otherwise).
  */
 #define ASI_MLP_FEATURES 16
 #define ASI_MLP_PARAMS 5313        /* float32 masters: W1[64][16], b1, W2[64][64], b2, w3, b3 */

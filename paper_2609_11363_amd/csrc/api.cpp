@@ -610,6 +610,7 @@ asi_status asi_lowrank(asi_handle h, int32_t k, const double *V, const double *l
 static asi_status mlp_setup(asi_handle h, const double *Z_S, const double *N_S, const double *M_S, double eps,
                             const double *L_val, const double *d_diag, const double *d_sub, asi::MlpFeatParams &P) {
     const asi::Analysis &A = h->A;
+    if (A.nnzS > (int64_t)INT32_MAX) return fail(h, ASI_E_UNSUPPORTED, "the learned correction needs |S| < 2^31");
     hipError_t e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
     if (e == hipSuccess) e = asi::launch_gather_lu(A.nnzU, h->lsrc_u, L_val, h->Lu, true, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "features setup");

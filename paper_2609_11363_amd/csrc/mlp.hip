@@ -44,13 +44,14 @@ __device__ inline uint16_t feat_bf16(double x) {
 __device__ inline float round_bf16(float x) { return from_bf16(to_bf16(x)); }
 
 // ---- features --------------------------------------------------------------
-// Per-node record, computed once per call: the diagonals of M and Z, and the
+// Per-node record, computed once per call: the diagonals of M and Z, the
 // node's bfloat16 features (log(|D^-1_ii| + 1e-30), log(||L(i,:)||_2 + 1e-30),
-// log(||L(:,i)||_2 + 1e-30), level(i) / max level, log(1 + |R_i|)).
+// log(||L(:,i)||_2 + 1e-30), level(i) / max level, log(1 + |R_i|)) and the
+// offset from S positions of row i's upper part to its u-range (|S| < 2^31).
 struct NodeRec {
     double m, z;
     uint16_t f[6];
-    uint32_t pad;
+    int32_t uoff;  // ustart[i] - diagpos[i] - 1: u-index of S position q > diagpos[i] in row i is uoff + q
 };
 static_assert(sizeof(NodeRec) == 32, "node records are 32 bytes");
 
@@ -76,7 +77,7 @@ __global__ void k_node_feats(MlpFeatParams P, const int64_t *__restrict__ Lp, co
     r.f[3] = feat_bf16(P.level[i] / maxlev);
     r.f[4] = feat_bf16(log1p((double)(P.ustart[i + 1] - P.ustart[i])));
     r.f[5] = 0;
-    r.pad = 0;
+    r.uoff = (int32_t)(P.ustart[i] - P.diagpos[i] - 1);
     reinterpret_cast<NodeRec *>(P.node)[i] = r;
 }
 
@@ -95,10 +96,8 @@ __device__ inline void entry_features(const MlpFeatParams &P, int64_t p, uint16_
     m = P.M[p];
     double lval = 0.0;
     if (i != j) {
-        // upper position of (lo, hi): row lo's u-range at the column's offset
-        const int32_t lo = i < j ? i : j;
-        const int64_t pu = i < j ? p : P.mirror[p];
-        const int64_t u = P.ustart[lo] + (pu - P.diagpos[lo] - 1);
+        // L(max, min) sits in row min's u-range at the upper position of the entry
+        const int64_t u = i < j ? (int64_t)ni.uoff + p : (int64_t)nj.uoff + P.mirror[p];
         lval = fabs(P.Lu[u]);
     }
     f[0] = feat_bf16(m / s);

@@ -173,8 +173,9 @@ __device__ void linv_reset(const LinvLds<T> &S, int tid) {
     gsync<G>();
 }
 
-// builds column j of L^inv; returns false if the table overflowed
-template <typename T, int G, int H>
+// builds column j of L^inv; returns false if the table (H slots) or the
+// current-term arrays (TC entries) overflowed
+template <typename T, int G, int H, int TC>
 __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S, int tid) {
     const T *Lu = reinterpret_cast<const T *>(P.Lu);
     if (tid == 0) {
@@ -270,15 +271,19 @@ __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S,
             }
             int32_t cnt;
             int32_t p0 = group_excl_scan<G>(key >= 0 ? 1 : 0, S.scr, &cnt);
-            if (key >= 0) {
+            if (key >= 0 && nn + p0 < TC) {
                 S.lk[nn + p0] = key;
                 S.lv[nn + p0] = v;
             }
             nn += cnt;
         }
         (void)pos;
-        if (tid == 0) S.flag[1] = nn;
+        if (tid == 0) {
+            S.flag[1] = nn;
+            if (nn > TC) S.flag[0] = 1;
+        }
         gsync<G>();
+        if (S.flag[0]) return false;
     }
     // block partners of 2x2 rows must be present for w = D^-1 L^inv
     {
@@ -373,6 +378,7 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
 }
 
 constexpr int kLinvH = 256;
+constexpr int kLinvTerm = 64;    // kept entries of one term (the series columns are short)
 constexpr int kLinvHBig = 2048;
 constexpr int kLinvGrid = 2048;  // workgroups of the persistent column kernel
 
@@ -381,10 +387,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_linv_small(NinvParams P) {
     __shared__ int32_t key[WAVES][kLinvH];
     __shared__ T nxt[WAVES][kLinvH], ser[WAVES][kLinvH];
     __shared__ int32_t tl[WAVES][kLinvH];
-    __shared__ int32_t lk[WAVES][kLinvH];
-    __shared__ T lv[WAVES][kLinvH];
-    __shared__ int32_t off[WAVES][kLinvH + 1];
-    __shared__ int64_t seg[WAVES][kLinvH];
+    __shared__ int32_t lk[WAVES][kLinvTerm];
+    __shared__ T lv[WAVES][kLinvTerm];
+    __shared__ int32_t off[WAVES][kLinvTerm + 1];
+    __shared__ int64_t seg[WAVES][kLinvTerm];
     __shared__ int32_t scr[WAVES][8];
     __shared__ int32_t flag[WAVES][8];
     __shared__ int64_t basev[WAVES][3];
@@ -393,7 +399,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_linv_small(NinvParams P) {
     linv_init<T, 64, kLinvH>(S, lane);
     const int32_t stride = gridDim.x * WAVES;
     for (int32_t j = blockIdx.x * WAVES + w; j < P.n; j += stride) {
-        if (linv_column<T, 64, kLinvH>(P, j, S, lane)) {
+        if (linv_column<T, 64, kLinvH, kLinvTerm>(P, j, S, lane)) {
             linv_emit<T, 64, kLinvH>(P, j, S, lane);
         } else if (lane == 0) {
             P.clen[j] = -1;
@@ -425,7 +431,7 @@ __global__ __launch_bounds__(256) void k_linv_big(NinvParams P) {
     linv_init<T, 256, H>(S, threadIdx.x);
     for (int32_t idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
         int32_t j = P.ovf_list[idx];
-        if (linv_column<T, 256, H>(P, j, S, threadIdx.x)) {
+        if (linv_column<T, 256, H, H>(P, j, S, threadIdx.x)) {
             linv_emit<T, 256, H>(P, j, S, threadIdx.x);
         } else if (threadIdx.x == 0) {
             P.clen[j] = 0;
@@ -593,11 +599,29 @@ size_t nprod_big_lds() {
            (size_t)kProdHBig * 4 + ((size_t)kProdCtBig + 1) * 4 + 64;
 }
 
+// Workgroups of the persistent column kernel: as many as can be resident at
+// once (so the grid-stride loop ends evenly), at most kLinvGrid.
+template <typename T, int W>
+int linv_grid(int64_t n) {
+    static int resident = 0;  // per element type; the same value on every device of one type
+    if (resident == 0) {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_linv_small<T, W>, 64 * W, 0) != hipSuccess ||
+            per <= 0)
+            per = 2;
+        resident = cus * per;
+    }
+    return (int)std::min<int64_t>(std::min<int64_t>((n + W - 1) / W, kLinvGrid), resident);
+}
+
 template <typename T>
 hipError_t run_ninv(const NinvParams &P, hipStream_t st) {
     hipLaunchKernelGGL(k_ninv_reset, dim3(1), dim3(64), 0, st, P);
     constexpr int W = 4;
-    const int grid = (int)std::min<int64_t>((P.n + W - 1) / W, kLinvGrid);
+    const int grid = linv_grid<T, W>(P.n);
     hipLaunchKernelGGL((k_linv_small<T, W>), dim3(grid), dim3(64 * W), 0, st, P);
     size_t l1 = linv_big_lds<T>();
     hipLaunchKernelGGL((k_linv_big<T>), dim3(256), dim3(256), l1, st, P);
