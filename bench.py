@@ -125,8 +125,9 @@ def run_diffusion(args):
     M = torch.empty_like(Z)
 
     def step(prec="fp64"):
-        s.selinv(Lv, dd, ds, precision=prec, out=Z)
-        s.ninv(Lv, dd, ds, p=p, delta=delta, precision=prec, out=Nn)
+        s.load_factor(Lv, dd, ds)
+        s.selinv(precision=prec, out=Z)
+        s.ninv(p=p, delta=delta, precision=prec, out=Nn)
         s.mix(Z, Nn, eps, out=M)
 
     # learned correction: trained on small grids of the same family before the
@@ -135,7 +136,7 @@ def run_diffusion(args):
     ML = torch.empty_like(Z)
 
     def correct():
-        s.mlp_correct(packed, Z, Nn, M, eps, Lv, dd, ds, out=ML)
+        s.mlp_correct(packed, Z, Nn, M, eps, out=ML)
 
     def full_step(prec="fp64"):
         step(prec)

@@ -106,11 +106,26 @@ asi_status asi_get_info(asi_handle h, asi_info *info);
 asi_status asi_get_pattern(asi_handle h, int64_t *S_rowptr_d, int32_t *S_col_d, int32_t *level_d);
 
 /*
+ * The factor values of one step (Section 1: L and D of P^T A P ~ L D L^T):
+ * L_val in the order of the L_col array given to asi_analyze, d_diag (n),
+ * d_sub (n, the (j+1, j) entry at the first column of each 2x2 block), all
+ * device float64. The library inverts the D blocks and gathers L into its
+ * column layout once; asi_selinv, asi_ninv, asi_mlp_features and
+ * asi_mlp_correct then take NULL for all three factor pointers to use it
+ * (a call that passes the pointers works on those instead and leaves no
+ * factor loaded). The caller may reuse its buffers after the stream has
+ * passed this call.
+ */
+asi_status asi_load_factor(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub);
+
+/*
  * SelInv (Section 2.1, recursion for G21 and G11): for every block J from
  * the last to the first, Z(R_J, J) = -Zhat(R_J, R_J) L(R_J, J) and
  * Z(J, J) = D_J^-1 - L(R_J, J)^T Z(R_J, J), where Zhat is Z restricted to S
  * (entries outside S are discarded). L_val: values in the order of the
- * L_col array given to asi_analyze. Z_S: |S| float64 outputs.
+ * L_col array given to asi_analyze (or L_val, d_diag and d_sub all NULL:
+ * the factor of asi_load_factor; ASI_E_STATE if none is loaded).
+ * Z_S: |S| float64 outputs.
  * ASI_MIXED keeps the off-diagonal working values, the gathers and their
  * accumulation in float32, and the D-block inverses and Z(J, J) in float64.
  */
@@ -133,7 +148,8 @@ asi_status asi_set_sweep(asi_handle h, asi_sweep mode);
  * NInv (Section 2.2): L^inv = sum_{m=0}^{p} T_m with T_0 = I and
  * T_m = drop_delta(E T_{m-1}), E = I - L, dropping |t| < delta in each new
  * term; N = (L^inv)^T D^-1 L^inv evaluated on S. Columns of L^inv are kept in
- * the workspace pool (ASI_E_WORKSPACE at asi_sync if it runs out).
+ * the workspace pool (ASI_E_WORKSPACE at asi_sync if it runs out). Factor
+ * pointers as for asi_selinv.
  */
 asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
                     int32_t p, double delta, asi_precision prec, double *N_S);
@@ -252,7 +268,7 @@ typedef enum {
     ASI_K_MIX = 4,           /* Mix selection (with its diagonal copy) */
     ASI_K_SPAI = 5,          /* SPAI refinement and symmetrisation */
     ASI_K_LOWRANK = 6,       /* rank-k correction on S */
-    ASI_K_GATHER = 7,        /* L values gathered into the column layout, once per call */
+    ASI_K_GATHER = 7,        /* L values into the column layout (gather, or float32 copy of the loaded factor) */
     ASI_K_SELINV_FLOW = 8,   /* the dataflow SelInv sweep (one launch per call) */
     ASI_K_MLP_FEATURES = 9,  /* features of the learned correction */
     ASI_K_MLP_FORWARD = 10,  /* MLP inference */

@@ -26,7 +26,7 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_set_workspace", "asi_get_info", "asi_get_pattern", "asi_selinv", "asi_ninv",
            "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
            "asi_profile_read", "asi_set_sweep", "asi_mlp_features", "asi_mlp_pack", "asi_mlp_forward",
-           "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct"]
+           "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -71,6 +71,7 @@ def load_library():
         "asi_set_workspace": [P, P, ctypes.c_size_t],
         "asi_get_info": [P, ctypes.POINTER(Info)],
         "asi_get_pattern": [P, P, P, P],
+        "asi_load_factor": [P, P, P, P],
         "asi_selinv": [P, P, P, P, ctypes.c_int, P],
         "asi_ninv": [P, P, P, P, i32, f64, ctypes.c_int, P],
         "asi_mix": [P, P, P, f64, P],
@@ -102,7 +103,7 @@ def load_library():
 
 
 def _ptr(t):
-    return ctypes.c_void_p(t.data_ptr())
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
 class Solver:
@@ -193,14 +194,19 @@ class Solver:
         assert out.dtype == self.torch.float64 and out.numel() == self.nnz_S and out.is_contiguous()
         return out
 
-    def selinv(self, L_val, d_diag, d_sub, precision="fp64", out=None):
+    def load_factor(self, L_val, d_diag, d_sub):
+        """asi_load_factor: later calls may pass None for the three factor arrays."""
+        self._stream()
+        self._check(self.lib.asi_load_factor(self.h, _ptr(L_val), _ptr(d_diag), _ptr(d_sub)))
+
+    def selinv(self, L_val=None, d_diag=None, d_sub=None, precision="fp64", out=None):
         out = self._out(out)
         self._stream()
         self._check(self.lib.asi_selinv(self.h, _ptr(L_val), _ptr(d_diag), _ptr(d_sub),
                                         PRECISION[precision], _ptr(out)))
         return out
 
-    def ninv(self, L_val, d_diag, d_sub, p=3, delta=0.1, precision="fp64", out=None):
+    def ninv(self, L_val=None, d_diag=None, d_sub=None, p=3, delta=0.1, precision="fp64", out=None):
         out = self._out(out)
         self._stream()
         self._check(self.lib.asi_ninv(self.h, _ptr(L_val), _ptr(d_diag), _ptr(d_sub), int(p),
@@ -228,7 +234,7 @@ class Solver:
         return out
 
     # -- learned correction --------------------------------------------------
-    def mlp_features(self, Z, N, M, eps, L_val, d_diag, d_sub, F=None, sc=None):
+    def mlp_features(self, Z, N, M, eps, L_val=None, d_diag=None, d_sub=None, F=None, sc=None):
         """(features |S| x 16 as int16 bfloat16 words, scale |S| float32)."""
         t = self.torch
         if F is None:
@@ -280,7 +286,7 @@ class Solver:
         self._check(self.lib.asi_mlp_apply(self.h, _ptr(M), _ptr(y), _ptr(scale), _ptr(out)))
         return out
 
-    def mlp_correct(self, packed, Z, N, M, eps, L_val, d_diag, d_sub, out=None):
+    def mlp_correct(self, packed, Z, N, M, eps, L_val=None, d_diag=None, d_sub=None, out=None):
         """M + y s on S from features, network and correction in one pass."""
         out = self._out(out)
         self._stream()

@@ -42,7 +42,11 @@ struct asi_handle_s {
     double *zd = nullptr;
     int32_t *done = nullptr;
     unsigned char *node = nullptr;
-    int64_t *rowptr_L = nullptr;
+    double *rn = nullptr;         // ||L(i, :)||_2 of the factor in Lu (set with it)
+    int64_t *rowptr_L = nullptr;  // the input L's row pointers
+    float *Lf = nullptr;          // float32 copy of the loaded factor's L (mixed precision)
+    bool factor_loaded = false;   // Lu (float64) and dinv hold the factor of asi_load_factor
+    bool lf_loaded = false;       // Lf holds the float32 copy of that factor's L
     int32_t epoch = 0;
     int sweep = ASI_SWEEP_AUTO;
     int8_t *piv = nullptr;
@@ -153,9 +157,11 @@ Layout make_layout(const asi::Analysis &A) {
     L.add(A.hits.size() * 4);           // 28 hits
     L.add(n * 4);                       // 29 done flags of the dataflow sweep
     L.add(n * 32);                      // 30 per-node feature records (learned correction)
-    L.add((n + 1) * 8);                 // 31 row pointers of the input L
-    L.add(2 * asi::kRedBlocks * 8);     // 32 partial sums of the diagonal error
-    L.add(2 * n * 4);                   // 33 column lists of the SPAI kernels
+    L.add(2 * asi::kRedBlocks * 8);     // 31 partial sums of the diagonal error
+    L.add(2 * n * 4);                   // 32 column lists of the SPAI kernels
+    L.add(u * 4);                       // 33 L in u-space, float32 (mixed precision)
+    L.add(n * 8);                       // 34 row norms of L (learned-correction features)
+    L.add((n + 1) * 8);                 // 35 row pointers of the input L
     return L;
 }
 
@@ -315,9 +321,13 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->hits = at<uint32_t>(b, L.off[28]);
     h->done = at<int32_t>(b, L.off[29]);
     h->node = b + L.off[30];
-    h->rowptr_L = at<int64_t>(b, L.off[31]);
-    h->red = at<double>(b, L.off[32]);
-    h->spai_list = at<int32_t>(b, L.off[33]);
+    h->red = at<double>(b, L.off[31]);
+    h->spai_list = at<int32_t>(b, L.off[32]);
+    h->Lf = at<float>(b, L.off[33]);
+    h->rn = at<double>(b, L.off[34]);
+    h->rowptr_L = at<int64_t>(b, L.off[35]);
+    h->factor_loaded = false;
+    h->lf_loaded = false;
     h->epoch = 0;
     // pool: rows | linv | w, each region 256-aligned
     size_t rest = bytes - L.cur - 3 * 256;
@@ -347,11 +357,11 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
         {h->useg, A.useg_u.data(), A.useg_u.size() * 8},
         {h->hit_ptr, A.hit_ptr.data(), A.hit_ptr.size() * 8},
         {h->hits, A.hits.data(), A.hits.size() * 4},
-        {h->rowptr_L, A.L_rowptr.data(), A.L_rowptr.size() * 8},
         {h->piv, A.piv.data(), A.piv.size()},
         {h->level, A.level.data(), A.level.size() * 4},
         {h->meta_small, A.meta_small.data(), A.meta_small.size() * 64},
         {h->meta_big, A.meta_big.data(), A.meta_big.size() * 64},
+        {h->rowptr_L, A.L_rowptr.data(), A.L_rowptr.size() * 8},
     };
     for (auto &u : ups) {
         if (u.bytes == 0) continue;
@@ -402,27 +412,70 @@ asi_status asi_get_pattern(asi_handle h, int64_t *S_rowptr_d, int32_t *S_col_d, 
     return ASI_OK;
 }
 
+// The factor of one call in the workspace: D-block inverses in dinv and L in
+// u-space in the call's precision (Lu float64, Lf float32), from the given
+// arrays, or (all three NULL) from the factor of asi_load_factor. Sets *Lu to
+// the u-space values the call's kernels read.
+static asi_status prepare_factor(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
+                                 bool fp64, const void **Lu) {
+    const asi::Analysis &A = h->A;
+    hipError_t e;
+    if (L_val || d_diag || d_sub) {
+        if ((!L_val && A.nnzL > 0) || !d_diag || !d_sub)
+            return fail(h, ASI_E_ARG, "null factor pointer (give L_val, d_diag and d_sub, or none of them)");
+        h->factor_loaded = false;  // dinv (and Lu or Lf) now hold this call's factor
+        h->lf_loaded = false;
+        {
+            Trace t(h, ASI_K_DINV, 0.0);
+            e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "dinv");
+        {
+            Trace t(h, ASI_K_GATHER, 24.0 * A.nnzU);
+            e = asi::launch_gather_lu(A.nnzU, h->lsrc_u, L_val, fp64 ? h->Lu : (void *)h->Lf, fp64, h->stream);
+            // the row norms of L (learned-correction features) come with the float64 copy
+            if (e == hipSuccess && fp64) e = asi::launch_row_norms(A.n, h->rowptr_L, L_val, h->rn, h->stream);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "gather L");
+    } else {
+        if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor given and none loaded (asi_load_factor)");
+        if (!fp64 && !h->lf_loaded) {
+            Trace t(h, ASI_K_GATHER, 12.0 * A.nnzU);
+            e = asi::launch_lu_to_float(A.nnzU, reinterpret_cast<const double *>(h->Lu), h->Lf, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "L to float32");
+            h->lf_loaded = true;
+        }
+    }
+    *Lu = fp64 ? h->Lu : (const void *)h->Lf;
+    return ASI_OK;
+}
+
+asi_status asi_load_factor(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if ((!L_val && h->A.nnzL > 0) || !d_diag || !d_sub) return fail(h, ASI_E_ARG, "null pointer");
+    DeviceGuard g(h->device);
+    const void *Lu = nullptr;
+    s = prepare_factor(h, L_val, d_diag, d_sub, true, &Lu);
+    if (s != ASI_OK) return s;
+    h->factor_loaded = true;
+    return ASI_OK;
+}
+
 asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
                       asi_precision prec, double *Z_S) {
     asi_status s = need_ready(h);
     if (s != ASI_OK) return s;
-    if ((!L_val && h->A.nnzL > 0) || !d_diag || !d_sub || !Z_S) return fail(h, ASI_E_ARG, "null pointer");
+    if (!Z_S) return fail(h, ASI_E_ARG, "null pointer");
     if (prec != ASI_FP64 && prec != ASI_MIXED) return fail(h, ASI_E_ARG, "unknown precision");
     DeviceGuard g(h->device);
     const asi::Analysis &A = h->A;
     hipError_t e;
-    {
-        Trace t(h, ASI_K_DINV, 0.0);
-        e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
-    }
-    if (e != hipSuccess) return hip_fail(h, e, "dinv");
     const bool fp64 = prec == ASI_FP64;
     const int m = fp64 ? 0 : 1;
-    {
-        Trace t(h, ASI_K_GATHER, 24.0 * A.nnzU);
-        e = asi::launch_gather_lu(A.nnzU, h->lsrc_u, L_val, h->Lu, fp64, h->stream);
-    }
-    if (e != hipSuccess) return hip_fail(h, e, "gather L");
+    const void *Lu = nullptr;
+    s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu);
+    if (s != ASI_OK) return s;
     asi::SelinvParams P{};
     P.ustart = h->ustart;
     P.ucol = h->ucol;
@@ -432,7 +485,7 @@ asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, c
     P.mirror_u = h->mirror_u;
     P.diagpos = h->diagpos;
     P.piv = h->piv;
-    P.Lu = h->Lu;
+    P.Lu = Lu;
     P.dinv = h->dinv;
     P.Zu = h->Zu;
     P.zdiag = h->zd;
@@ -488,24 +541,17 @@ asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, con
                     double delta, asi_precision prec, double *N_S) {
     asi_status s = need_ready(h);
     if (s != ASI_OK) return s;
-    if ((!L_val && h->A.nnzL > 0) || !d_diag || !d_sub || !N_S) return fail(h, ASI_E_ARG, "null pointer");
+    if (!N_S) return fail(h, ASI_E_ARG, "null pointer");
     if (p < 0 || p > 64) return fail(h, ASI_E_ARG, "p must be in [0, 64]");
     if (!(delta >= 0.0)) return fail(h, ASI_E_ARG, "delta must be >= 0");
     if (prec != ASI_FP64 && prec != ASI_MIXED) return fail(h, ASI_E_ARG, "unknown precision");
     DeviceGuard g(h->device);
     const asi::Analysis &A = h->A;
     hipError_t e;
-    {
-        Trace t(h, ASI_K_DINV, 0.0);
-        e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
-    }
-    if (e != hipSuccess) return hip_fail(h, e, "dinv");
     const bool fp64 = prec == ASI_FP64;
-    {
-        Trace t(h, ASI_K_GATHER, 24.0 * A.nnzU);
-        e = asi::launch_gather_lu(A.nnzU, h->lsrc_u, L_val, h->Lu, fp64, h->stream);
-    }
-    if (e != hipSuccess) return hip_fail(h, e, "gather L");
+    const void *Lu = nullptr;
+    s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu);
+    if (s != ASI_OK) return s;
     asi::NinvParams P{};
     P.n = A.n;
     P.rowptr = h->rowptr;
@@ -515,7 +561,7 @@ asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, con
     P.ustart = h->ustart;
     P.ucol = h->ucol;
     P.piv = h->piv;
-    P.Lu = h->Lu;
+    P.Lu = Lu;
     P.dinv = h->dinv;
     P.p = p;
     P.delta = delta;
@@ -611,9 +657,10 @@ static asi_status mlp_setup(asi_handle h, const double *Z_S, const double *N_S, 
                             const double *L_val, const double *d_diag, const double *d_sub, asi::MlpFeatParams &P) {
     const asi::Analysis &A = h->A;
     if (A.nnzS > (int64_t)INT32_MAX) return fail(h, ASI_E_UNSUPPORTED, "the learned correction needs |S| < 2^31");
-    hipError_t e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
-    if (e == hipSuccess) e = asi::launch_gather_lu(A.nnzU, h->lsrc_u, L_val, h->Lu, true, h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "features setup");
+    const void *Lu = nullptr;
+    asi_status s = prepare_factor(h, L_val, d_diag, d_sub, true, &Lu);
+    if (s != ASI_OK) return s;
+    hipError_t e;
     P = asi::MlpFeatParams{};
     P.n = A.n;
     P.nnz = A.nnzS;
@@ -625,14 +672,18 @@ static asi_status mlp_setup(asi_handle h, const double *Z_S, const double *N_S, 
     P.piv = h->piv;
     P.level = h->level;
     P.maxlevel = A.n_levels - 1;
-    P.Lu = reinterpret_cast<const double *>(h->Lu);
+    P.Lu = reinterpret_cast<const double *>(Lu);
     P.dinv = h->dinv;
     P.node = h->node;
+    P.rn = h->rn;
     P.Z = Z_S;
     P.N = N_S;
     P.M = M_S;
     P.eps = eps;
-    e = asi::launch_node_feats(P, h->rowptr_L, L_val, h->stream);
+    {
+        Trace t(h, ASI_K_MLP_FEATURES, 0.0);
+        e = asi::launch_node_feats(P, h->stream);
+    }
     if (e != hipSuccess) return hip_fail(h, e, "node features");
     return ASI_OK;
 }
@@ -642,15 +693,14 @@ asi_status asi_mlp_features(asi_handle h, const double *Z_S, const double *N_S, 
                             float *scale) {
     asi_status s = need_ready(h);
     if (s != ASI_OK) return s;
-    if (!Z_S || !N_S || !M_S || (!L_val && h->A.nnzL > 0) || !d_diag || !d_sub || !F || !scale)
-        return fail(h, ASI_E_ARG, "null pointer");
+    if (!Z_S || !N_S || !M_S || !F || !scale) return fail(h, ASI_E_ARG, "null pointer");
     DeviceGuard g(h->device);
-    Trace t(h, ASI_K_MLP_FEATURES, 0.0);
     asi::MlpFeatParams P;
     s = mlp_setup(h, Z_S, N_S, M_S, eps, L_val, d_diag, d_sub, P);
     if (s != ASI_OK) return s;
     P.F = F;
     P.scale = scale;
+    Trace t(h, ASI_K_MLP_FEATURES, 0.0);
     hipError_t e = asi::launch_mlp_features(P, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "features");
     return ASI_OK;
@@ -661,15 +711,14 @@ asi_status asi_mlp_correct(asi_handle h, const void *W, const double *Z_S, const
                            double *out_S) {
     asi_status s = need_ready(h);
     if (s != ASI_OK) return s;
-    if (!W || !Z_S || !N_S || !M_S || (!L_val && h->A.nnzL > 0) || !d_diag || !d_sub || !out_S)
-        return fail(h, ASI_E_ARG, "null pointer");
+    if (!W || !Z_S || !N_S || !M_S || !out_S) return fail(h, ASI_E_ARG, "null pointer");
     DeviceGuard g(h->device);
-    // algorithmic bytes: row and column index, Z, N, M in and the result out
-    // per entry; two node records of 32 B per entry come from the cache
-    Trace t(h, ASI_K_MLP_FORWARD, 40.0 * h->A.nnzS + 32.0 * h->A.n);
     asi::MlpFeatParams P;
     s = mlp_setup(h, Z_S, N_S, M_S, eps, L_val, d_diag, d_sub, P);
     if (s != ASI_OK) return s;
+    // algorithmic bytes: row and column index, Z, N, M in and the result out
+    // per entry; two node records of 32 B per entry come from the cache
+    Trace t(h, ASI_K_MLP_FORWARD, 40.0 * h->A.nnzS + 32.0 * h->A.n);
     hipError_t e = asi::launch_mlp_correct(P, W, out_S, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "mlp correct");
     return ASI_OK;

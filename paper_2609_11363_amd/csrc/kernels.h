@@ -40,6 +40,7 @@ hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipSt
 int flow_grid(bool fp64);
 hipError_t launch_selinv_flow(const SelinvParams &P, int32_t nblocks, int32_t *done, int32_t epoch,
                               int32_t spin_limit, bool fp64, int grid, hipStream_t st);
+hipError_t launch_lu_to_float(int64_t nnzU, const double *Lu, float *Lf, hipStream_t st);
 hipError_t launch_gather_lu(int64_t nnzU, const int64_t *lsrc_u, const double *Lval, void *Lu, bool fp64,
                             hipStream_t st);
 hipError_t set_big_lds_limits();
@@ -124,14 +125,15 @@ struct MlpFeatParams {
     const double *Lu;    // u-space L values (float64)
     const double *dinv;  // 3 per block start
     void *node;          // n per-node feature records of 32 bytes (workspace)
+    const double *rn;    // n: ||L(i, :)||_2
     const double *Z, *N, *M;
     double eps;
     uint16_t *F;  // nnz x 16 bfloat16
     float *scale; // nnz
 };
 
-hipError_t launch_node_feats(const MlpFeatParams &P, const int64_t *L_rowptr, const double *L_val,
-                             hipStream_t st);
+hipError_t launch_node_feats(const MlpFeatParams &P, hipStream_t st);
+hipError_t launch_row_norms(int32_t n, const int64_t *Lp, const double *Lval, double *rn, hipStream_t st);
 hipError_t launch_mlp_features(const MlpFeatParams &P, hipStream_t st);
 hipError_t launch_mlp_correct(const MlpFeatParams &P, const void *W, double *out, hipStream_t st);
 hipError_t launch_mlp_pack(const float *theta, void *W, hipStream_t st);

@@ -497,7 +497,18 @@ __global__ void k_gather_lu(int64_t nnzU, const int64_t *__restrict__ lsrc_u, co
     Lu[u] = s >= 0 ? (T)Lval[s] : T(0);
 }
 
+__global__ void k_lu_to_float(int64_t nnzU, const double *__restrict__ Lu, float *__restrict__ Lf) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < nnzU) Lf[u] = (float)Lu[u];
+}
+
 }  // namespace dev
+
+hipError_t launch_lu_to_float(int64_t nnzU, const double *Lu, float *Lf, hipStream_t st) {
+    if (nnzU <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::k_lu_to_float, dim3((unsigned)((nnzU + 255) / 256)), dim3(256), 0, st, nnzU, Lu, Lf);
+    return hipGetLastError();
+}
 
 size_t selinv_big_lds_bytes(bool fp64) {
     const size_t C = kBigCols, w = fp64 ? 8 : 4;

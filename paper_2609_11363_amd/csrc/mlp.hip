@@ -60,11 +60,20 @@ __device__ inline double dinv_diag(const double *dinv, const int8_t *piv, int32_
     return piv[i] == 2 ? dinv[3 * (int64_t)(i - 1) + 2] : dinv[3 * (int64_t)i];
 }
 
-__global__ void k_node_feats(MlpFeatParams P, const int64_t *__restrict__ Lp, const double *__restrict__ Lval) {
+// ||L(i, :)||_2 from the caller's CSR values (row order)
+__global__ void k_row_norms(int32_t n, const int64_t *__restrict__ Lp, const double *__restrict__ Lval,
+                            double *__restrict__ rn) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t q = Lp[i]; q < Lp[i + 1]; ++q) s += Lval[q] * Lval[q];
+    rn[i] = sqrt(s);
+}
+
+__global__ void k_node_feats(MlpFeatParams P) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
-    double rs = 0.0, cs = 0.0;
-    for (int64_t q = Lp[i]; q < Lp[i + 1]; ++q) rs += Lval[q] * Lval[q];
+    double cs = 0.0;
     // column i of L from its column layout (u-space values, padding is 0)
     for (int64_t u = P.ustart[i]; u < P.ustart[i + 1]; ++u) cs += P.Lu[u] * P.Lu[u];
     const double maxlev = P.maxlevel > 0 ? (double)P.maxlevel : 1.0;
@@ -72,7 +81,7 @@ __global__ void k_node_feats(MlpFeatParams P, const int64_t *__restrict__ Lp, co
     r.m = P.M[P.diagpos[i]];
     r.z = P.Z[P.diagpos[i]];
     r.f[0] = feat_bf16(log(fabs(dinv_diag(P.dinv, P.piv, i)) + 1e-30));
-    r.f[1] = feat_bf16(log(sqrt(rs) + 1e-30));
+    r.f[1] = feat_bf16(log(P.rn[i] + 1e-30));
     r.f[2] = feat_bf16(log(sqrt(cs) + 1e-30));
     r.f[3] = feat_bf16(P.level[i] / maxlev);
     r.f[4] = feat_bf16(log1p((double)(P.ustart[i + 1] - P.ustart[i])));
@@ -449,9 +458,13 @@ __global__ void k_mlp_apply(int64_t nnz, const double *__restrict__ M, const flo
 
 }  // namespace dev
 
-hipError_t launch_node_feats(const MlpFeatParams &P, const int64_t *L_rowptr, const double *L_val,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(dev::k_node_feats, dim3((P.n + 255) / 256), dim3(256), 0, st, P, L_rowptr, L_val);
+hipError_t launch_row_norms(int32_t n, const int64_t *Lp, const double *Lval, double *rn, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_row_norms, dim3((n + 255) / 256), dim3(256), 0, st, n, Lp, Lval, rn);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_feats(const MlpFeatParams &P, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_node_feats, dim3((P.n + 255) / 256), dim3(256), 0, st, P);
     return hipGetLastError();
 }
 

@@ -1,0 +1,64 @@
+"""asi_load_factor: the calls that reuse the loaded factor agree with the
+calls that pass the factor arrays, in float64 and mixed precision, with and
+without 2x2 pivots; a call with explicit arrays leaves no factor loaded.
+
+SelInv and NInv are compared at rounding level: blocks handled by several
+wavefronts add into shared LDS accumulators in run-dependent order. The
+learned-correction kernels have no such sums; given the same Z, N and M they
+are compared bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import core as oc
+from oracle import mlp as om
+from workloads import diffusion3d_7pt, ildl_bk, kkt_matrix, nested_multicolor_grid
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    if name == "diff12":
+        A = diffusion3d_7pt(12, 1.0, 2)
+        return ildl_bk(A, nested_multicolor_grid((12, 12, 12)), 1e-3)
+    A = kkt_matrix(60, 40, 3)
+    return ildl_bk(A, None, 1e-2)
+
+
+@pytest.mark.parametrize("name", ["diff12", "kkt"])
+def test_loaded_factor_matches_explicit_arrays(name):
+    import torch
+    from paper_2609_11363_amd import Solver, upload_factors
+    from paper_2609_11363_amd.asi import AsiError
+    print(f"[load_factor] case={name}", flush=True)
+    F = _case(name)
+    S = oc.pattern(F)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    Lv, dd, ds = upload_factors(F)
+    with pytest.raises(AsiError):
+        s.selinv()  # nothing loaded yet
+    packed = s.mlp_pack(torch.as_tensor(om.init_params(3), device=s.device))
+    tol = {"fp64": 1e-12, "mixed": 1e-4}  # the mixed mode's stated bound
+    for prec in ("fp64", "mixed"):
+        Ze = s.selinv(Lv, dd, ds, precision=prec)
+        Ne = s.ninv(Lv, dd, ds, p=3, delta=0.1, precision=prec)
+        M = s.mix(Ze, Ne, 1e-2)
+        Fe, sce = s.mlp_features(Ze, Ne, M, 1e-2, Lv, dd, ds)
+        Ce = s.mlp_correct(packed, Ze, Ne, M, 1e-2, Lv, dd, ds)
+        s.load_factor(Lv, dd, ds)
+        Zl = s.selinv(precision=prec)
+        Nl = s.ninv(p=3, delta=0.1, precision=prec)
+        Fl, scl = s.mlp_features(Ze, Ne, M, 1e-2)
+        Cl = s.mlp_correct(packed, Ze, Ne, M, 1e-2)
+        s.sync()
+        ez = oc.entry_error(S, Zl.cpu().numpy(), Ze.cpu().numpy()).max()
+        en = oc.entry_error(S, Nl.cpu().numpy(), Ne.cpu().numpy()).max()
+        print(f"  {prec}: loaded vs explicit SelInv {ez:.1e}, NInv {en:.1e}")
+        assert ez <= tol[prec] and en <= tol[prec]
+        assert torch.equal(Fe, Fl) and torch.equal(sce, scl) and torch.equal(Ce, Cl)
+    # an explicit call replaces the loaded factor's D-block inverses: nothing is loaded afterwards
+    s.selinv(Lv, dd, ds)
+    with pytest.raises(AsiError):
+        s.ninv()
+    s.sync()
+    assert np.isfinite(Ze.cpu().numpy()).all()
