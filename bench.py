@@ -126,8 +126,7 @@ def run_diffusion(args):
 
     def step(prec="fp64"):
         s.load_factor(Lv, dd, ds)
-        s.selinv(precision=prec, out=Z)
-        s.ninv(p=p, delta=delta, precision=prec, out=Nn)
+        s.selinv_ninv(p=p, delta=delta, precision=prec, Z=Z, N=Nn)
         s.mix(Z, Nn, eps, out=M)
 
     # learned correction: trained on small grids of the same family before the
@@ -184,13 +183,22 @@ def run_diffusion(args):
             sweeps[mode] = f"unavailable: {exc}"
     log(f"selinv sweeps: {sweeps}")
     ms_graph = None
+
+    def step_one_stream():
+        # the same work on one stream: a captured fork/join replays slower than
+        # the two calls in sequence
+        s.load_factor(Lv, dd, ds)
+        s.selinv(out=Z)
+        s.ninv(p=p, delta=delta, out=Nn)
+        s.mix(Z, Nn, eps, out=M)
+
     try:
         s.set_sweep("levels")
-        step()
+        step_one_stream()
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            step()
+            step_one_stream()
         for _ in range(args.warmup):
             graph.replay()
         ms_graph = timed(graph.replay, args.steps) * 1e3

@@ -155,6 +155,18 @@ asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, con
                     int32_t p, double delta, asi_precision prec, double *N_S);
 
 /*
+ * SelInv and NInv of the same factor in one call (together they are the
+ * inputs of Mix, Section 2.3): NInv runs on a second stream of the handle
+ * (created on first use, default priority) concurrently with the SelInv
+ * sweep on the handle's stream, and the handle's stream waits for it before
+ * its next work, so later calls and asi_sync see both results. Arguments and
+ * results as for asi_selinv and asi_ninv. With ASI_SWEEP_DATAFLOW the two
+ * run one after the other (that sweep needs every workgroup resident).
+ */
+asi_status asi_selinv_ninv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
+                           int32_t p, double delta, asi_precision prec, double *Z_S, double *N_S);
+
+/*
  * Mix (Section 2.3): M_ij = Z_ij where |Z_ij| > eps sqrt(|Z_ii Z_jj|), else
  * N_ij. M_S may alias Z_S or N_S.
  */

@@ -26,7 +26,7 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_set_workspace", "asi_get_info", "asi_get_pattern", "asi_selinv", "asi_ninv",
            "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
            "asi_profile_read", "asi_set_sweep", "asi_mlp_features", "asi_mlp_pack", "asi_mlp_forward",
-           "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor"]
+           "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor", "asi_selinv_ninv"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -72,6 +72,7 @@ def load_library():
         "asi_get_info": [P, ctypes.POINTER(Info)],
         "asi_get_pattern": [P, P, P, P],
         "asi_load_factor": [P, P, P, P],
+        "asi_selinv_ninv": [P, P, P, P, i32, f64, ctypes.c_int, P, P],
         "asi_selinv": [P, P, P, P, ctypes.c_int, P],
         "asi_ninv": [P, P, P, P, i32, f64, ctypes.c_int, P],
         "asi_mix": [P, P, P, f64, P],
@@ -205,6 +206,16 @@ class Solver:
         self._check(self.lib.asi_selinv(self.h, _ptr(L_val), _ptr(d_diag), _ptr(d_sub),
                                         PRECISION[precision], _ptr(out)))
         return out
+
+    def selinv_ninv(self, L_val=None, d_diag=None, d_sub=None, p=3, delta=0.1, precision="fp64",
+                    Z=None, N=None):
+        """SelInv and NInv concurrently (NInv on the handle's second stream); returns (Z, N)."""
+        Z = self._out(Z)
+        N = self._out(N)
+        self._stream()
+        self._check(self.lib.asi_selinv_ninv(self.h, _ptr(L_val), _ptr(d_diag), _ptr(d_sub), int(p),
+                                             float(delta), PRECISION[precision], _ptr(Z), _ptr(N)))
+        return Z, N
 
     def ninv(self, L_val=None, d_diag=None, d_sub=None, p=3, delta=0.1, precision="fp64", out=None):
         out = self._out(out)

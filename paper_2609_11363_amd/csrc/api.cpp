@@ -16,6 +16,8 @@
 struct asi_handle_s {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t aux = nullptr;      // second stream of asi_selinv_ninv (created on first use)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::string err;
     bool analyzed = false;
     bool ws_ready = false;
@@ -188,11 +190,13 @@ struct Trace {
     asi_handle h;
     int kind;
     double bytes;
+    hipStream_t st;
     hipEvent_t a = nullptr;
-    Trace(asi_handle hh, int k, double b) : h(hh), kind(k), bytes(b) {
+    Trace(asi_handle hh, int k, double b, hipStream_t s = nullptr)
+        : h(hh), kind(k), bytes(b), st(s ? s : hh->stream) {
         if (h->prof) {
             a = take_event(h);
-            if (a) (void)hipEventRecord(a, h->stream);
+            if (a) (void)hipEventRecord(a, st);
         }
     }
     ~Trace() {
@@ -202,7 +206,7 @@ struct Trace {
             h->ev_free.push_back(a);
             return;
         }
-        (void)hipEventRecord(b, h->stream);
+        (void)hipEventRecord(b, st);
         h->pending.push_back({a, b, kind, bytes});
     }
 };
@@ -240,6 +244,12 @@ asi_status asi_destroy(asi_handle h) {
             (void)hipEventDestroy(r.b);
         }
         for (auto e : h->ev_free) (void)hipEventDestroy(e);
+        if (h->aux) {
+            (void)hipStreamSynchronize(h->aux);
+            (void)hipStreamDestroy(h->aux);
+        }
+        if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+        if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     }
     delete h;
     return ASI_OK;
@@ -462,20 +472,11 @@ asi_status asi_load_factor(asi_handle h, const double *L_val, const double *d_di
     return ASI_OK;
 }
 
-asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
-                      asi_precision prec, double *Z_S) {
-    asi_status s = need_ready(h);
-    if (s != ASI_OK) return s;
-    if (!Z_S) return fail(h, ASI_E_ARG, "null pointer");
-    if (prec != ASI_FP64 && prec != ASI_MIXED) return fail(h, ASI_E_ARG, "unknown precision");
-    DeviceGuard g(h->device);
+// The SelInv sweep on stream st, reading L in u-space from Lu.
+static asi_status selinv_launch(asi_handle h, const void *Lu, bool fp64, double *Z_S, hipStream_t st) {
     const asi::Analysis &A = h->A;
-    hipError_t e;
-    const bool fp64 = prec == ASI_FP64;
     const int m = fp64 ? 0 : 1;
-    const void *Lu = nullptr;
-    s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu);
-    if (s != ASI_OK) return s;
+    hipError_t e;
     asi::SelinvParams P{};
     P.ustart = h->ustart;
     P.ucol = h->ucol;
@@ -503,10 +504,9 @@ asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, c
         double bytes = 0.0;
         for (int32_t l = 0; l < A.n_levels; ++l) bytes += A.lvl_bytes_small[m][l];
         h->epoch = h->epoch == INT32_MAX ? 1 : h->epoch + 1;
-        Trace t(h, ASI_K_SELINV_FLOW, bytes);
+        Trace t(h, ASI_K_SELINV_FLOW, bytes, st);
         P.meta = h->meta_small;
-        e = asi::launch_selinv_flow(P, A.n_blocks, h->done, h->epoch, 1 << 21, fp64, grid,
-                                    h->stream);
+        e = asi::launch_selinv_flow(P, A.n_blocks, h->done, h->epoch, 1 << 21, fp64, grid, st);
         if (e != hipSuccess) return hip_fail(h, e, "selinv dataflow launch");
         return ASI_OK;
     }
@@ -514,19 +514,33 @@ asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, c
         P.meta = h->meta_small + A.lvl_small[l];
         P.nblk = A.lvl_small[l + 1] - A.lvl_small[l];
         if (P.nblk > 0) {
-            Trace t(h, ASI_K_SELINV, A.lvl_bytes_small[m][l]);
-            e = asi::launch_selinv_level(P, false, fp64, h->stream, asi::small_group_size(P.nblk));
+            Trace t(h, ASI_K_SELINV, A.lvl_bytes_small[m][l], st);
+            e = asi::launch_selinv_level(P, false, fp64, st, asi::small_group_size(P.nblk));
             if (e != hipSuccess) return hip_fail(h, e, "selinv level");
         }
         P.meta = h->meta_big + A.lvl_big[l];
         P.nblk = A.lvl_big[l + 1] - A.lvl_big[l];
         if (P.nblk > 0) {
-            Trace t(h, ASI_K_SELINV_BIG, A.lvl_bytes_big[m][l]);
-            e = asi::launch_selinv_level(P, true, fp64, h->stream, 256);
+            Trace t(h, ASI_K_SELINV_BIG, A.lvl_bytes_big[m][l], st);
+            e = asi::launch_selinv_level(P, true, fp64, st, 256);
             if (e != hipSuccess) return hip_fail(h, e, "selinv level (large blocks)");
         }
     }
     return ASI_OK;
+}
+
+asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
+                      asi_precision prec, double *Z_S) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!Z_S) return fail(h, ASI_E_ARG, "null pointer");
+    if (prec != ASI_FP64 && prec != ASI_MIXED) return fail(h, ASI_E_ARG, "unknown precision");
+    DeviceGuard g(h->device);
+    const bool fp64 = prec == ASI_FP64;
+    const void *Lu = nullptr;
+    s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu);
+    if (s != ASI_OK) return s;
+    return selinv_launch(h, Lu, fp64, Z_S, h->stream);
 }
 
 asi_status asi_set_sweep(asi_handle h, asi_sweep mode) {
@@ -537,21 +551,11 @@ asi_status asi_set_sweep(asi_handle h, asi_sweep mode) {
     return ASI_OK;
 }
 
-asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub, int32_t p,
-                    double delta, asi_precision prec, double *N_S) {
-    asi_status s = need_ready(h);
-    if (s != ASI_OK) return s;
-    if (!N_S) return fail(h, ASI_E_ARG, "null pointer");
-    if (p < 0 || p > 64) return fail(h, ASI_E_ARG, "p must be in [0, 64]");
-    if (!(delta >= 0.0)) return fail(h, ASI_E_ARG, "delta must be >= 0");
-    if (prec != ASI_FP64 && prec != ASI_MIXED) return fail(h, ASI_E_ARG, "unknown precision");
-    DeviceGuard g(h->device);
+// NInv on stream st, reading L in u-space from Lu; linv_grid > 0 caps the
+// workgroups of the persistent series kernel (0: as many as are resident).
+static asi_status ninv_launch(asi_handle h, const void *Lu, bool fp64, int32_t p, double delta, double *N_S,
+                              hipStream_t st, int linv_grid) {
     const asi::Analysis &A = h->A;
-    hipError_t e;
-    const bool fp64 = prec == ASI_FP64;
-    const void *Lu = nullptr;
-    s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu);
-    if (s != ASI_OK) return s;
     asi::NinvParams P{};
     P.n = A.n;
     P.rowptr = h->rowptr;
@@ -578,12 +582,68 @@ asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, con
     P.ovf2_count = h->counters + 1;
     P.out = N_S;
     P.status = h->status;
+    hipError_t e;
     {
-        Trace t(h, ASI_K_NINV, 0.0);
-        e = asi::launch_ninv(P, fp64, h->stream);
+        Trace t(h, ASI_K_NINV, 0.0, st);
+        e = asi::launch_ninv(P, fp64, st, linv_grid);
     }
     if (e != hipSuccess) return hip_fail(h, e, "ninv");
     return ASI_OK;
+}
+
+asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub, int32_t p,
+                    double delta, asi_precision prec, double *N_S) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!N_S) return fail(h, ASI_E_ARG, "null pointer");
+    if (p < 0 || p > 64) return fail(h, ASI_E_ARG, "p must be in [0, 64]");
+    if (!(delta >= 0.0)) return fail(h, ASI_E_ARG, "delta must be >= 0");
+    if (prec != ASI_FP64 && prec != ASI_MIXED) return fail(h, ASI_E_ARG, "unknown precision");
+    DeviceGuard g(h->device);
+    const bool fp64 = prec == ASI_FP64;
+    const void *Lu = nullptr;
+    s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu);
+    if (s != ASI_OK) return s;
+    return ninv_launch(h, Lu, fp64, p, delta, N_S, h->stream, 0);
+}
+
+asi_status asi_selinv_ninv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
+                           int32_t p, double delta, asi_precision prec, double *Z_S, double *N_S) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!Z_S || !N_S) return fail(h, ASI_E_ARG, "null pointer");
+    if (p < 0 || p > 64) return fail(h, ASI_E_ARG, "p must be in [0, 64]");
+    if (!(delta >= 0.0)) return fail(h, ASI_E_ARG, "delta must be >= 0");
+    if (prec != ASI_FP64 && prec != ASI_MIXED) return fail(h, ASI_E_ARG, "unknown precision");
+    DeviceGuard g(h->device);
+    const bool fp64 = prec == ASI_FP64;
+    const void *Lu = nullptr;
+    s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu);
+    if (s != ASI_OK) return s;
+    // the dataflow sweep needs every workgroup resident: no concurrent work beside it
+    if (h->sweep == ASI_SWEEP_DATAFLOW) {
+        s = ninv_launch(h, Lu, fp64, p, delta, N_S, h->stream, 0);
+        if (s != ASI_OK) return s;
+        return selinv_launch(h, Lu, fp64, Z_S, h->stream);
+    }
+    hipError_t e = hipSuccess;
+    if (!h->aux) {
+        e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(h, e, "second stream");
+    }
+    e = hipEventRecord(h->ev_fork, h->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->aux, h->ev_fork, 0);
+    if (e != hipSuccess) return hip_fail(h, e, "fork");
+    // NInv's persistent kernel takes half the resident workgroups, leaving
+    // compute units to the latency-bound SelInv levels running beside it
+    s = ninv_launch(h, Lu, fp64, p, delta, N_S, h->aux, -2);
+    if (s == ASI_OK) s = selinv_launch(h, Lu, fp64, Z_S, h->stream);
+    e = hipEventRecord(h->ev_join, h->aux);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->ev_join, 0);
+    if (e != hipSuccess) return hip_fail(h, e, "join");
+    return s;
 }
 
 asi_status asi_mix(asi_handle h, const double *Z_S, const double *N_S, double eps, double *M_S) {

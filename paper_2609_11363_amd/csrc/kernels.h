@@ -76,7 +76,9 @@ struct NinvParams {
     int32_t *status;
 };
 
-hipError_t launch_ninv(const NinvParams &P, bool fp64, hipStream_t st);
+// linv_grid: 0 = as many workgroups of the series kernel as are resident,
+// -k = 1/k of that, k > 0 = at most k
+hipError_t launch_ninv(const NinvParams &P, bool fp64, hipStream_t st, int linv_grid = 0);
 hipError_t set_ninv_lds_limits();
 
 hipError_t launch_zdiag(int32_t n, const int64_t *diagpos, const double *X, double *d, hipStream_t st);

@@ -602,7 +602,7 @@ size_t nprod_big_lds() {
 // Workgroups of the persistent column kernel: as many as can be resident at
 // once (so the grid-stride loop ends evenly), at most kLinvGrid.
 template <typename T, int W>
-int linv_grid(int64_t n) {
+int linv_grid(int64_t n, int cap) {
     static int resident = 0;  // per element type; the same value on every device of one type
     if (resident == 0) {
         int dev = 0, cus = 0, per = 0;
@@ -614,14 +614,17 @@ int linv_grid(int64_t n) {
             per = 2;
         resident = cus * per;
     }
-    return (int)std::min<int64_t>(std::min<int64_t>((n + W - 1) / W, kLinvGrid), resident);
+    int64_t g = std::min<int64_t>(std::min<int64_t>((n + W - 1) / W, kLinvGrid), resident);
+    if (cap < 0) g = std::max<int64_t>(1, g / (-cap));
+    if (cap > 0) g = std::min<int64_t>(g, cap);
+    return (int)g;
 }
 
 template <typename T>
-hipError_t run_ninv(const NinvParams &P, hipStream_t st) {
+hipError_t run_ninv(const NinvParams &P, hipStream_t st, int cap) {
     hipLaunchKernelGGL(k_ninv_reset, dim3(1), dim3(64), 0, st, P);
     constexpr int W = 4;
-    const int grid = linv_grid<T, W>(P.n);
+    const int grid = linv_grid<T, W>(P.n, cap);
     hipLaunchKernelGGL((k_linv_small<T, W>), dim3(grid), dim3(64 * W), 0, st, P);
     size_t l1 = linv_big_lds<T>();
     hipLaunchKernelGGL((k_linv_big<T>), dim3(256), dim3(256), l1, st, P);
@@ -646,8 +649,8 @@ hipError_t set_ninv_lds_limits() {
     return hipSuccess;
 }
 
-hipError_t launch_ninv(const NinvParams &P, bool fp64, hipStream_t st) {
-    return fp64 ? dev::run_ninv<double>(P, st) : dev::run_ninv<float>(P, st);
+hipError_t launch_ninv(const NinvParams &P, bool fp64, hipStream_t st, int linv_grid) {
+    return fp64 ? dev::run_ninv<double>(P, st, linv_grid) : dev::run_ninv<float>(P, st, linv_grid);
 }
 
 }  // namespace asi

@@ -62,3 +62,45 @@ def test_loaded_factor_matches_explicit_arrays(name):
         s.ninv()
     s.sync()
     assert np.isfinite(Ze.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("name", ["diff12", "kkt"])
+def test_selinv_ninv_concurrent_matches_separate_calls(name):
+    """asi_selinv_ninv (NInv on the handle's second stream beside the SelInv
+    sweep) gives what asi_selinv and asi_ninv give, and the oracle's values."""
+    from paper_2609_11363_amd import Solver, upload_factors
+    print(f"[selinv_ninv] case={name}", flush=True)
+    F = _case(name)
+    S = oc.pattern(F)
+    Zo = oc.selinv(F, S)
+    No = oc.ninv(F, S, 3, 0.1)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    Lv, dd, ds = upload_factors(F)
+    tol = {"fp64": 1e-12, "mixed": 1e-4}
+    s.load_factor(Lv, dd, ds)
+    for prec in ("fp64", "mixed"):
+        Z1 = s.selinv(precision=prec)
+        N1 = s.ninv(p=3, delta=0.1, precision=prec)
+        runs = [s.selinv_ninv(p=3, delta=0.1, precision=prec) for _ in range(3)]
+        s.sync()
+        for Z2, N2 in runs:
+            ez = oc.entry_error(S, Z2.cpu().numpy(), Z1.cpu().numpy()).max()
+            en = oc.entry_error(S, N2.cpu().numpy(), N1.cpu().numpy()).max()
+            assert ez <= tol[prec] and en <= tol[prec], (prec, ez, en)
+        if prec == "fp64":
+            Z2, N2 = runs[-1]
+            eo = max(oc.entry_error(S, Z2.cpu().numpy(), Zo).max(), oc.entry_error(S, N2.cpu().numpy(), No).max())
+            print(f"  concurrent float64 vs oracle {eo:.1e}")
+            assert eo <= 1e-10
+    # explicit factor arrays, and the sequential path of the dataflow sweep
+    Z3, N3 = s.selinv_ninv(Lv, dd, ds, p=3, delta=0.1)
+    s.set_sweep("dataflow")
+    try:
+        Z4, N4 = s.selinv_ninv(Lv, dd, ds, p=3, delta=0.1)
+    finally:
+        s.set_sweep("auto")
+    s.sync()
+    for Z, N in ((Z3, N3), (Z4, N4)):
+        assert oc.entry_error(S, Z.cpu().numpy(), Zo).max() <= 1e-10
+        assert oc.entry_error(S, N.cpu().numpy(), No).max() <= 1e-10
