@@ -104,3 +104,44 @@ def test_selinv_ninv_concurrent_matches_separate_calls(name):
     for Z, N in ((Z3, N3), (Z4, N4)):
         assert oc.entry_error(S, Z.cpu().numpy(), Zo).max() <= 1e-10
         assert oc.entry_error(S, N.cpu().numpy(), No).max() <= 1e-10
+
+
+def test_selinv_ninv_graph_replays_match_eager():
+    """The concurrent call captured in a HIP graph (its fork and join become
+    graph edges): every replay, with eager work in between, gives the eager
+    results."""
+    import torch
+    from paper_2609_11363_amd import Solver, upload_factors
+    print("[selinv_ninv graph]", flush=True)
+    F = _case("diff12")
+    S = oc.pattern(F)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    Lv, dd, ds = upload_factors(F)
+    dev = torch.device("cuda", 0)
+    Z = torch.empty(s.nnz_S, dtype=torch.float64, device=dev)
+    N = torch.empty_like(Z)
+
+    def step():
+        s.load_factor(Lv, dd, ds)
+        s.selinv_ninv(p=3, delta=0.1, Z=Z, N=N)
+
+    step()
+    s.sync()
+    Ze, Ne = Z.clone(), N.clone()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for k in range(3):
+        Z.zero_()
+        N.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        ez = oc.entry_error(S, Z.cpu().numpy(), Ze.cpu().numpy()).max()
+        en = oc.entry_error(S, N.cpu().numpy(), Ne.cpu().numpy()).max()
+        print(f"  replay {k}: SelInv {ez:.1e} NInv {en:.1e}")
+        assert ez <= 1e-12 and en <= 1e-12
+        s.selinv(Lv, dd, ds)  # eager work between replays
+        s.sync()
+    del g
