@@ -61,7 +61,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="diffusion64", choices=["diffusion64", "indefinite512", "stencil27_128"])
+    ap.add_argument("--workload", default="diffusion64",
+                    choices=["diffusion64", "indefinite512", "stencil27_128", "stencil27_equal_error"])
     ap.add_argument("--grid", type=int, default=None, help="grid size (default 64, 512, 128 per workload)")
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -81,6 +82,9 @@ def main():
         return
     if args.workload == "stencil27_128":
         run_stencil27(args)
+        return
+    if args.workload == "stencil27_equal_error":
+        run_equal_error(args)
         return
     run_diffusion(args)
 
@@ -484,6 +488,181 @@ def run_stencil27(args):
         if MLm is not None:
             result["rel_error_vs_oracle"]["learned_correction_vs_mix_mean"] = float(
                 oc.entry_error(S, MLm, Mm).mean())
+    print(json.dumps(result), flush=True)
+
+
+def reference_columns(A, cols, tol=1e-12, max_iter=20000):
+    """Columns `cols` of A^-1 (original ordering) by Jacobi-preconditioned CG in
+    float64 on the GPU, to a relative residual of tol per column (the accuracy
+    reference of the equal-error comparison; torch's sparse product is used
+    here as measurement plumbing, outside the method's path)."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", 0)
+    At = torch.sparse_csr_tensor(torch.as_tensor(A.indptr, dtype=torch.int64),
+                                 torch.as_tensor(A.indices, dtype=torch.int64),
+                                 torch.as_tensor(A.data, dtype=torch.float64), size=A.shape).to(dev)
+    n, k = A.shape[0], len(cols)
+    dinv = torch.as_tensor(1.0 / A.diagonal(), device=dev)[:, None]
+    B = torch.zeros(n, k, dtype=torch.float64, device=dev)
+    B[torch.as_tensor(cols, device=dev), torch.arange(k, device=dev)] = 1.0
+    X = torch.zeros_like(B)
+    R = B.clone()
+    Zp = dinv * R
+    P = Zp.clone()
+    rz = (R * Zp).sum(0)
+    bn = B.norm(dim=0)
+    it = 0
+    for it in range(1, max_iter + 1):
+        AP = At @ P
+        alpha = rz / (P * AP).sum(0)
+        X += alpha * P
+        R -= alpha * AP
+        if it % 25 == 0 and bool(((R.norm(dim=0) / bn) <= tol).all()):
+            break
+        Zp = dinv * R
+        rz_new = (R * Zp).sum(0)
+        P = Zp + (rz_new / rz) * P
+        rz = rz_new
+    res = float((R.norm(dim=0) / bn).max())
+    return X.cpu().numpy(), it, res
+
+
+def run_equal_error(args):
+    """Equal-error comparison on the 27-point lognormal(0, 0.5) stencil (64^3
+    by default): float64 SelInv at tau = 1e-3, 3e-4, 1e-4 against Mix and
+    Mix + learned (mixed precision) at tau = 1e-3. Accuracy against 256
+    sampled columns of A^-1: err_1 on their diagonals (Section 2.6) and the
+    column-relative error |x_ij - y_ij| / |y_jj| on the entries of the
+    tau = 1e-3 pattern in those columns."""
+    import numpy as np
+    import torch
+
+    from paper_2609_11363_amd import Solver, upload_factors
+    from workloads import ildl_bk, nested_multicolor_grid, stencil27_3d
+
+    N = args.grid or 64
+    taus = [1e-3, 3e-4, 1e-4]
+    p, delta, eps = 3, 0.1, 1e-2
+    A = stencil27_3d(N, 0.5, 5)
+    n = A.shape[0]
+    q = nested_multicolor_grid((N, N, N))
+    rng = np.random.default_rng(3)
+    cols = np.sort(rng.choice(n, size=256, replace=False))
+    learned_info, packed = train_learned(args, taus[0], p, delta, eps, family="stencil27")
+    t0 = time.time()
+    Xref, iters, res = reference_columns(A, cols)
+    log(f"reference: 256 columns of A^-1 by CG, {iters} iterations, residual {res:.1e}, {time.time() - t0:.1f}s")
+    yjj = Xref[cols, np.arange(len(cols))]
+    dev = torch.device("cuda", 0)
+    methods = {}
+    loose_entries = None  # (factor rows, sample index) of the tau = 1e-3 pattern in the sampled columns
+
+    def sample_values(s, perm, values):
+        """values on S at (i, cols[k]) for every entry of S in the sampled columns."""
+        rp, cl = (x.cpu().numpy() for x in s.pattern())
+        iperm = np.empty(n, np.int64)
+        iperm[perm] = np.arange(n)
+        fc = iperm[cols]
+        out = {}
+        v = values.cpu().numpy()
+        for k, f in enumerate(fc):
+            lo, hi = rp[f], rp[f + 1]
+            for fi, x in zip(cl[lo:hi], v[lo:hi]):  # row f of S = column f (symmetric)
+                out[(int(perm[fi]), k)] = x
+        return out
+
+    def errors(vals):
+        keys = loose_entries
+        d = np.array([vals.get((int(cols[k]), k), 0.0) for k in range(len(cols))])
+        err1 = float(np.abs(d - yjj).sum() / np.abs(yjj).sum())
+        e = np.array([abs(vals.get(key, 0.0) - Xref[key[0], key[1]]) / abs(yjj[key[1]]) for key in keys])
+        return err1, float(e.mean()), float(np.quantile(e, 0.99))
+
+    for tau in taus:
+        t0 = time.time()
+        F = ildl_bk(A, q, tau, progress=True)
+        t_fact = time.time() - t0
+        s = Solver(0)
+        s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+        Lv, dd, ds = upload_factors(F)
+        Z = torch.empty(s.nnz_S, dtype=torch.float64, device=dev)
+        s.load_factor(Lv, dd, ds)
+        for _ in range(args.warmup):
+            s.selinv(Lv, dd, ds, out=Z)
+        ms_sel = timed(lambda: s.selinv(Lv, dd, ds, out=Z), args.steps) * 1e3
+        s.sync()
+        zv = sample_values(s, F.perm, Z)
+        if loose_entries is None:
+            loose_entries = sorted(zv.keys())
+        e1, em, e99 = errors(zv)
+        methods[f"selinv_fp64_tau{tau:g}"] = {"tau": tau, "nnz_S": s.nnz_S, "ms": ms_sel,
+                                             "entries_per_s": s.nnz_S / (ms_sel * 1e-3), "err1_diag": e1,
+                                             "mean_entry_err": em, "p99_entry_err": e99, "ildl_s": t_fact}
+        log(f"SelInv fp64 tau={tau:g}: |S|={s.nnz_S} {ms_sel:.2f} ms err_1 {e1:.3e} mean entry {em:.3e}")
+        if tau == taus[0]:
+            Nn, M, ML = (torch.empty_like(Z) for _ in range(3))
+
+            def mix_mixed():
+                s.load_factor(Lv, dd, ds)
+                s.selinv_ninv(p=p, delta=delta, precision="mixed", Z=Z, N=Nn)
+                s.mix(Z, Nn, eps, out=M)
+
+            def mix_learned_mixed():
+                mix_mixed()
+                if packed is not None:
+                    s.mlp_correct(packed, Z, Nn, M, eps, out=ML)
+
+            for _ in range(args.warmup):
+                mix_learned_mixed()
+            ms_mix = timed(mix_mixed, args.steps) * 1e3
+            ms_ml = timed(mix_learned_mixed, args.steps) * 1e3
+            s.sync()
+            for name, ms, vals in (("mix_mixed", ms_mix, M), ("mix_learned_mixed", ms_ml,
+                                                               ML if packed is not None else M)):
+                e1, em, e99 = errors(sample_values(s, F.perm, vals))
+                methods[f"{name}_tau{tau:g}"] = {"tau": tau, "nnz_S": s.nnz_S, "ms": ms,
+                                                 "entries_per_s": s.nnz_S / (ms * 1e-3), "err1_diag": e1,
+                                                 "mean_entry_err": em, "p99_entry_err": e99}
+                log(f"{name} tau={tau:g}: {ms:.2f} ms err_1 {e1:.3e} mean entry {em:.3e}")
+        del s, Lv, dd, ds, Z
+        torch.cuda.empty_cache()
+
+    # float64 SelInv time at the learned form's error (log-log interpolation in tau's sweep)
+    def at_equal(metric):
+        target = methods[f"mix_learned_mixed_tau{taus[0]:g}"][metric]
+        sel = [methods[f"selinv_fp64_tau{t:g}"] for t in taus]
+        for a, b in zip(sel, sel[1:]):
+            if (a[metric] - target) * (b[metric] - target) <= 0 and a[metric] != b[metric]:
+                w = (np.log(target) - np.log(a[metric])) / (np.log(b[metric]) - np.log(a[metric]))
+                return float(np.exp(np.log(a["ms"]) + w * (np.log(b["ms"]) - np.log(a["ms"]))))
+        return None
+
+    ml = methods[f"mix_learned_mixed_tau{taus[0]:g}"]
+    eq = {m: at_equal(m) for m in ("err1_diag", "mean_entry_err")}
+    result = {
+        "metric": "selected entries of A^-1 per sec (SelInv, Mix, Mix+learned) at stated rel error",
+        "value": ml["entries_per_s"],
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ml["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (mixed) for Mix / Mix+learned; f64 for the SelInv sweep",
+        "data": "synthetic",
+        "config": {"workload": f"equal-error comparison, 3D 27-point lognormal(0,0.5) stencil {N}^3, nested "
+                               f"multicolor order: float64 SelInv at tau in {taus} vs mixed Mix and Mix+learned at "
+                               f"tau={taus[0]}; errors against 256 CG columns of A^-1", "n": n,
+                   "parallelism": "single GPU"},
+        "methods": methods,
+        "learned": learned_info,
+        "reference": {"columns": 256, "cg_iterations": iters, "max_rel_residual": res},
+        "selinv_fp64_ms_at_mix_learned_error": eq,
+        "speedup_at_equal_error": {m: (v / ml["ms"] if v else None) for m, v in eq.items()},
+    }
     print(json.dumps(result), flush=True)
 
 
