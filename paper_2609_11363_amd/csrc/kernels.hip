@@ -243,6 +243,17 @@ __device__ void selinv_block(const SelinvParams &P, const BlockMeta &M, const Se
 
     uint32_t w0[kUnroll], w1[kUnroll];
     load_hit_words<WIDE, G>(H, tid, total, w0, w1);
+    // the block's D^-1 entries, needed last, are loaded first so that their
+    // latency overlaps the staging instead of ending the block
+    double iv0 = 0.0, iv1 = 0.0, iv2 = 0.0;
+    if (tid == 0) {
+        const double *iv = P.dinv + 3 * (int64_t)j;
+        iv0 = iv[0];
+        if (two) {
+            iv1 = iv[1];
+            iv2 = iv[2];
+        }
+    }
     // stage L(R_J, J) and the gather segments; rows, mirror positions and
     // the diagonal entries Z(r, r) stay in registers
     int32_t rr[NT];
@@ -367,16 +378,15 @@ __device__ void selinv_block(const SelinvParams &P, const BlockMeta &M, const Se
         }
     }
     if (tid == 0) {
-        const double *iv = P.dinv + 3 * (int64_t)j;
         const int64_t dj = two ? M.pdj - 2 : M.pdl - 1;  // diagpos[j]
         const int64_t dl = M.pdl - 1;                     // diagpos[last]
-        double zjj = iv[0] - d00;
+        double zjj = iv0 - d00;
         P.out[dj] = zjj;
         co_store<CO>(&P.zdiag[j], zjj);
         bool bad = !isfinite(zjj);
         if (two) {
-            double z11 = iv[2] - d11;
-            double off = iv[1] - 0.5 * (d10 + d01);
+            double z11 = iv2 - d11;
+            double off = iv1 - 0.5 * (d10 + d01);
             P.out[dl] = z11;
             co_store<CO>(&P.zdiag[last], z11);
             P.out[dj + 1] = off;
