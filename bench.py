@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 
 # L2 <-> memory traffic of the float64 SelInv level kernels on the default
 # workload (64^3, tau = 1e-3), from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
-# scaled by a 256 MiB copy (3.396 GB read + 0.371 GB written per sweep of 140
+# scaled by a 256 MiB copy (3.397 GB read + 0.370 GB written per sweep of 140
 # launches). It holds only for the kernel sources it was measured on; any
 # other sources report null.
-SELINV_TRAFFIC = {"sources_sha256": "246134584951bf5db6dced2841f7886b8fbb4dcd4eb3c31e5290124428bde267",
-                  "bytes_per_launch": (3.396e9 + 0.371e9) / 140,
+SELINV_TRAFFIC = {"sources_sha256": "ddea18aca98255aa4da1fd1f5afab0270697b96a828e79f1cfbf1458eaacda7c",
+                  "bytes_per_launch": (3.397e9 + 0.370e9) / 140,
                   "profile": "profiles/selinv_ninv_mix_learned_diffusion64.md"}
 
 
