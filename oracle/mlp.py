@@ -1,7 +1,7 @@
 """Learned per-entry correction — CPU reference (test infrastructure only).
 
-The paper has no learned component; this is the build target's addition. A
-small MLP predicts a correction of the Mix value of every entry of S from
+The paper has no learned component; this correction is an addition to the
+method. A small MLP predicts a correction of the Mix value of every entry of S from
 local features, as a stand-in for tightening the drop tolerance:
 
     M'_ij = M_ij + y_ij * s_ij,   s_ij = sqrt(|M_ii M_jj|)   (1 where that is 0)

@@ -1,5 +1,5 @@
-// Learned per-entry correction of the Mix result (the build's addition to
-// the paper's method): features on S, a 16 -> 64 -> 64 -> 1 ReLU network with
+// Learned per-entry correction of the Mix result (an addition to the paper's
+// method): features on S, a 16 -> 64 -> 64 -> 1 ReLU network with
 // bfloat16 weights and activations and float32 accumulation, its backward
 // pass, the squared-error loss and Adam.
 //
