@@ -261,12 +261,15 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
         A.lvl_bytes_small[m].assign(A.n_levels, 0.0);
         A.lvl_bytes_big[m].assign(A.n_levels, 0.0);
     }
+    A.lvl_maxc_big.assign(A.n_levels, 0);
     for (int32_t j : blocks) {
         const bool small = bcols[j] <= kSmallCols;
-        if (small)
+        if (small) {
             A.sched_small[cs[A.level[j]]++] = j;
-        else
+        } else {
             A.sched_big[cb[A.level[j]]++] = j;
+            A.lvl_maxc_big[A.level[j]] = std::max(A.lvl_maxc_big[A.level[j]], bcols[j]);
+        }
         const int ncols = piv[j] == 1 ? 2 : 1;
         for (int m = 0; m < 2; ++m) {
             double b = selinv_block_bytes(bcols[j], ncols, bhits[j], m == 0);

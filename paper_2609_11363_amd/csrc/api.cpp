@@ -522,7 +522,7 @@ static asi_status selinv_launch(asi_handle h, const void *Lu, bool fp64, double 
         P.nblk = A.lvl_big[l + 1] - A.lvl_big[l];
         if (P.nblk > 0) {
             Trace t(h, ASI_K_SELINV_BIG, A.lvl_bytes_big[m][l], st);
-            e = asi::launch_selinv_level(P, true, fp64, st, 256);
+            e = asi::launch_selinv_level(P, true, fp64, st, A.lvl_maxc_big[l]);
             if (e != hipSuccess) return hip_fail(h, e, "selinv level (large blocks)");
         }
     }

@@ -73,6 +73,7 @@ struct Analysis {
     std::vector<int32_t> sched_small, sched_big;
     std::vector<BlockMeta> meta_small, meta_big;  // records of the schedules' slots
     std::vector<int32_t> lvl_small, lvl_big;  // n_levels+1 offsets into the schedules
+    std::vector<int32_t> lvl_maxc_big;        // per level: largest |R_J| of its large blocks
     int64_t gather_pairs = 0;
     int64_t gather_hits = 0;
     // algorithmic bytes of each level's launches, [0] float64 mode, [1] mixed

@@ -35,6 +35,8 @@ hipError_t launch_dinv(int32_t n, const int8_t *piv, const double *dd, const dou
                        int32_t *status, hipStream_t st);
 // group: threads per block for |R_J| <= kSmallCols (64 = one wavefront per
 // block, four blocks per workgroup; 128, 256 or 512 = one workgroup per block)
+// group: for |R_J| <= kSmallCols, threads per block; for the large blocks,
+// the launch's largest |R_J| (sizes the dynamic LDS)
 hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipStream_t st, int group);
 // Dataflow sweep over all blocks in one cooperative launch (|R_J| <= kSmallCols).
 int flow_grid(bool fp64);
@@ -44,7 +46,7 @@ hipError_t launch_lu_to_float(int64_t nnzU, const double *Lu, float *Lf, hipStre
 hipError_t launch_gather_lu(int64_t nnzU, const int64_t *lsrc_u, const double *Lval, void *Lu, bool fp64,
                             hipStream_t st);
 hipError_t set_big_lds_limits();
-size_t selinv_big_lds_bytes(bool fp64);
+size_t selinv_big_lds_bytes(bool fp64, int G, int32_t C);
 
 // NInv: columns of L^inv into a pool, then (L^inv)^T D^-1 L^inv on S.
 struct NinvParams {

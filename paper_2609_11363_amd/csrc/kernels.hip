@@ -14,6 +14,7 @@
 // A gather of column l of Z is a contiguous, coalesced read of l's u-range.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -426,13 +427,14 @@ __global__ __launch_bounds__(G) void k_selinv_group(SelinvParams P) {
     selinv_block<T, G, (kSmallCols + G - 1) / G, false>(P, M, S, threadIdx.x, red);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_selinv_big(SelinvParams P) {
+// one workgroup of G threads per block with |R_J| > kSmallCols; the dynamic
+// LDS holds C = the largest |R_J| of the launch (at most kBigCols):
+// red (4 G/64 doubles) | seg (int64, C) | l0, l1, y0, y1 (T, C each)
+template <typename T, int G>
+__global__ __launch_bounds__(G) void k_selinv_big(SelinvParams P, int32_t C) {
     extern __shared__ __align__(16) unsigned char smem[];
-    // layout: red (16 doubles) | seg (int64, C) | l0, l1, y0, y1 (T, C each)
-    const int C = kBigCols;
     double *red = reinterpret_cast<double *>(smem);
-    int64_t *seg = reinterpret_cast<int64_t *>(red + 16);
+    int64_t *seg = reinterpret_cast<int64_t *>(red + 4 * (G / 64));
     T *l0 = reinterpret_cast<T *>(seg + C);
     T *l1 = l0 + C;
     T *y0 = l1 + C;
@@ -441,7 +443,7 @@ __global__ __launch_bounds__(256) void k_selinv_big(SelinvParams P) {
     if (bi >= P.nblk) return;
     SelinvLds<T> S{l0, l1, y0, y1, seg};
     const BlockMeta M = P.meta[bi];
-    selinv_block<T, 256, kBigCols / 256, true>(P, M, S, threadIdx.x, red);
+    selinv_block<T, G, kBigCols / G, true>(P, M, S, threadIdx.x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -520,9 +522,9 @@ hipError_t launch_lu_to_float(int64_t nnzU, const double *Lu, float *Lf, hipStre
     return hipGetLastError();
 }
 
-size_t selinv_big_lds_bytes(bool fp64) {
-    const size_t C = kBigCols, w = fp64 ? 8 : 4;
-    return 16 * 8 + C * 8 + 4 * C * w;
+size_t selinv_big_lds_bytes(bool fp64, int G, int32_t C) {
+    const size_t w = fp64 ? 8 : 4;
+    return (size_t)4 * (G / 64) * 8 + (size_t)C * 8 + 4 * (size_t)C * w;
 }
 
 hipError_t launch_dinv(int32_t n, const int8_t *piv, const double *dd, const double *ds, double *dinv,
@@ -559,11 +561,22 @@ hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipSt
         else
             launch_small_family<float>(P, group, st);
     } else {
-        size_t lds = selinv_big_lds_bytes(fp64);
-        if (fp64)
-            hipLaunchKernelGGL((dev::k_selinv_big<double>), dim3(P.nblk), dim3(256), lds, st, P);
-        else
-            hipLaunchKernelGGL((dev::k_selinv_big<float>), dim3(P.nblk), dim3(256), lds, st, P);
+        // group = the level's largest |R_J|; few blocks: 1024 threads per block
+        // (fewer passes over each block's hits), many: 256 (more blocks per CU)
+        const int32_t C = std::min<int32_t>(kBigCols, (group + 63) & ~63);
+        const bool wide = P.nblk <= 1024;
+        const size_t lds = selinv_big_lds_bytes(fp64, wide ? 1024 : 256, C);
+        if (fp64) {
+            if (wide)
+                hipLaunchKernelGGL((dev::k_selinv_big<double, 1024>), dim3(P.nblk), dim3(1024), lds, st, P, C);
+            else
+                hipLaunchKernelGGL((dev::k_selinv_big<double, 256>), dim3(P.nblk), dim3(256), lds, st, P, C);
+        } else {
+            if (wide)
+                hipLaunchKernelGGL((dev::k_selinv_big<float, 1024>), dim3(P.nblk), dim3(1024), lds, st, P, C);
+            else
+                hipLaunchKernelGGL((dev::k_selinv_big<float, 256>), dim3(P.nblk), dim3(256), lds, st, P, C);
+        }
     }
     return hipGetLastError();
 }
@@ -604,13 +617,15 @@ hipError_t launch_selinv_flow(const SelinvParams &P, int32_t nblocks, int32_t *d
 }
 
 hipError_t set_big_lds_limits() {
-    hipError_t e = hipFuncSetAttribute((const void *)dev::k_selinv_big<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)selinv_big_lds_bytes(true));
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)dev::k_selinv_big<float>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)selinv_big_lds_bytes(false));
+    const void *fns[] = {(const void *)dev::k_selinv_big<double, 256>, (const void *)dev::k_selinv_big<double, 1024>,
+                         (const void *)dev::k_selinv_big<float, 256>, (const void *)dev::k_selinv_big<float, 1024>};
+    const size_t bytes[] = {selinv_big_lds_bytes(true, 256, kBigCols), selinv_big_lds_bytes(true, 1024, kBigCols),
+                            selinv_big_lds_bytes(false, 256, kBigCols), selinv_big_lds_bytes(false, 1024, kBigCols)};
+    for (int i = 0; i < 4; ++i) {
+        hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes[i]);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace asi
