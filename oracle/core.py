@@ -306,6 +306,15 @@ def err1_sums(d: np.ndarray, dhat: np.ndarray, V=None, lam=None):
     return float(np.abs(d - dk).sum()), float(np.abs(d).sum())
 
 
+def trace_sums(S, X: np.ndarray, V=None, lam=None):
+    """(tr, ||diag||_1) of the approximation X on S, corrected by the modes
+    (V, lam) when given: the trace estimate of the covariance A^-1 as the sum
+    of the approximate diagonal (Section 3.5)."""
+    d = diag(S, X)
+    dk = d if V is None else corrected_diag(d, V, lam)
+    return float(dk.sum()), float(np.abs(dk).sum())
+
+
 def accept_modes(d: np.ndarray, dhat: np.ndarray, V: np.ndarray, lam: np.ndarray):
     """Acceptance test of Algorithm 1, read per mode: candidates are taken in
     order of decreasing |lam| (ties by index); each is kept only if adding it to

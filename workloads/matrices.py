@@ -234,3 +234,35 @@ def dodd(A) -> float:
     with np.errstate(divide="ignore"):
         r = np.where(off > 0, d / np.where(off > 0, off, 1), np.inf)
     return float(r.min())
+
+
+def covariance_grid(N: int = 200, alpha: float = 3.0, beta: float = 4.0):
+    """Covariance-type matrix on an N-by-N grid (the paper's covariance and
+    uncertainty-quantification example): c_ij = (1 - d(i, j) / alpha)^beta
+    where the Euclidean grid distance d(i, j) <= alpha, 0 otherwise.
+
+    The diagonal is 1. For beta >= 3/2 the truncated power function is a
+    positive definite kernel in two dimensions, so the matrix is SPD; with
+    alpha = 3, beta = 4 it has 25 entries per interior row and is not
+    diagonally dominant (off-diagonal row sums about 1.19). Deterministic.
+    """
+    n = N * N
+    r = int(np.floor(alpha))
+    rows = [np.arange(n)]
+    cols = [np.arange(n)]
+    vals = [np.ones(n)]
+    for dy in range(0, r + 1):
+        for dx in range(-r, r + 1):
+            if dy == 0 and dx <= 0:
+                continue  # each unordered pair once
+            d = float(np.hypot(dx, dy))
+            if d > alpha:
+                continue
+            c = (1.0 - d / alpha) ** beta
+            if c == 0.0:
+                continue
+            p, q, _ = _grid_pairs((N, N), (dx, dy))
+            rows += [p, q]
+            cols += [q, p]
+            vals += [np.full(len(p), c), np.full(len(p), c)]
+    return _csr(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
