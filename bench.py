@@ -62,7 +62,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="diffusion64",
-                    choices=["diffusion64", "indefinite512", "stencil27_128", "stencil27_equal_error"])
+                    choices=["diffusion64", "indefinite512", "stencil27_128", "stencil27_equal_error",
+                             "covariance200"])
     ap.add_argument("--grid", type=int, default=None, help="grid size (default 64, 512, 128 per workload)")
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -85,6 +86,9 @@ def main():
         return
     if args.workload == "stencil27_equal_error":
         run_equal_error(args)
+        return
+    if args.workload == "covariance200":
+        run_covariance(args)
         return
     run_diffusion(args)
 
@@ -491,7 +495,7 @@ def run_stencil27(args):
     print(json.dumps(result), flush=True)
 
 
-def reference_columns(A, cols, tol=1e-12, max_iter=20000):
+def reference_columns(A, cols, tol=1e-12, max_iter=20000, diag_only=False):
     """Columns `cols` of A^-1 (original ordering) by Jacobi-preconditioned CG in
     float64 on the GPU, to a relative residual of tol per column (the accuracy
     reference of the equal-error comparison; torch's sparse product is used
@@ -525,6 +529,8 @@ def reference_columns(A, cols, tol=1e-12, max_iter=20000):
         P = Zp + (rz_new / rz) * P
         rz = rz_new
     res = float((R.norm(dim=0) / bn).max())
+    if diag_only:  # (A^-1)_jj for j in cols
+        return X[torch.as_tensor(cols, device=dev), torch.arange(k, device=dev)].cpu().numpy(), it, res
     return X.cpu().numpy(), it, res
 
 
@@ -840,6 +846,206 @@ def run_indefinite(args):
             "mix_fp64_max": float(oc.entry_error(S, M.cpu().numpy(), Mo).max()),
             "mix_spai_fp64_max": float(oc.entry_error(S, R.cpu().numpy(), Ro).max()),
             "lowrank_fp64_max": float(oc.entry_error(S, Cd.cpu().numpy(), Co).max())}
+        log(f"oracle {t_cpu:.1f}s; {result['rel_error_vs_oracle']}")
+    print(json.dumps(result), flush=True)
+
+
+def run_covariance(args):
+    """Covariance-type matrix of the paper's uncertainty-quantification example
+    (c_ij = (1 - d/alpha)^beta, N = 200, alpha = 3, beta = 4, n = 40,000):
+    selected covariances, the variances diag(A^-1) and the trace by SelInv,
+    NInv, Mix and Mix-SPAI, and the spectral check with 3 eigenpairs."""
+    import numpy as np
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    import torch
+
+    from paper_2609_11363_amd import Solver, upload_factors
+    from paper_2609_11363_amd.spectral import accept_on_device, inverse_error_eigenpairs
+    from workloads import covariance_grid, ildl_bk, nested_multicolor_grid
+
+    N, tau = args.grid or 200, args.tau
+    alpha, beta = 3.0, 4.0
+    k, cg = 3, 10
+    p, delta, eps = 3, 0.1, 1e-2
+    t0 = time.time()
+    A = covariance_grid(N, alpha, beta)
+    F = ildl_bk(A, nested_multicolor_grid((N, N)), tau)
+    t_fact = time.time() - t0
+    log(f"workload n={F.n} nnz(A)={A.nnz} nnz(L)={F.nnzL} |S|={F.nnzS} ildl {t_fact:.1f}s")
+
+    dev = torch.device("cuda", 0)
+    s = Solver(0)
+    t0 = time.time()
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    t_sym = time.time() - t0
+    info = s.info()
+    log(f"analysis {t_sym:.2f}s levels={info['n_levels']} max|R_J|={info['max_cols']}")
+    Lv, dd, ds = upload_factors(F)
+    Ar = torch.as_tensor(A.indptr.astype(np.int64), device=dev)
+    Ac = torch.as_tensor(A.indices.astype(np.int32), device=dev)
+    Av = torch.as_tensor(A.data.astype(np.float64), device=dev)
+    perm = torch.as_tensor(F.perm.astype(np.int32), device=dev)
+    nnzS = s.nnz_S
+    Z = torch.empty(nnzS, dtype=torch.float64, device=dev)
+    Nn, M, R = (torch.empty_like(Z) for _ in range(3))
+    dR = torch.empty(F.n, dtype=torch.float64, device=dev)
+    tr = torch.empty(2, dtype=torch.float64, device=dev)
+
+    def step():
+        s.load_factor(Lv, dd, ds)
+        s.selinv_ninv(p=p, delta=delta, Z=Z, N=Nn)
+        s.mix(Z, Nn, eps, out=M)
+        s.spai(Ar, Ac, Av, perm, M, cg_iters=cg, out=R)
+        s.diag(R, out=dR)
+        s.trace(R, sums=tr)
+
+    step()
+    s.sync()
+    # reference variances: diag(A^-1) by Jacobi-preconditioned CG in float64
+    # on the device (measurement only) for every unit vector, in blocks of
+    # columns, to a relative residual of 1e-13
+    t0 = time.time()
+    d_ref_full = np.empty(F.n)
+    cg_res, cg_it = 0.0, 0
+    for c0 in range(0, F.n, 4096):
+        cols = np.arange(c0, min(F.n, c0 + 4096))
+        d_ref_full[cols], it, res = reference_columns(A, cols, tol=1e-13, diag_only=True)
+        cg_res, cg_it = max(cg_res, res), max(cg_it, it)
+    t_ref = time.time() - t0
+    q = F.perm
+    d_ref_h = d_ref_full[q]
+    tr_ref = float(d_ref_full.sum())
+    errs, trs = {}, {}
+    for name, Xd in [("selinv", Z), ("ninv", Nn), ("mix", M), ("mix_spai", R)]:
+        dh = s.diag(Xd).cpu().numpy()
+        errs[name] = float(np.abs(d_ref_h - dh).sum() / np.abs(d_ref_h).sum())
+        trs[name] = float(s.trace(Xd)[0].item() / tr_ref - 1.0)
+    log(f"reference diag(A^-1) {t_ref:.1f}s (CG {cg_it} iterations, residual {cg_res:.1e}), trace {tr_ref:.6e}; err_1 " +
+        ", ".join(f"{kk} {v:.3e}" for kk, v in errs.items()) + "; trace rel error " +
+        ", ".join(f"{kk} {v:+.2e}" for kk, v in trs.items()))
+
+    # spectral check (Algorithm 1) with 3 eigenpairs of A^-1 - R, exact
+    # A^-1 products from a sparse direct factorization on the host
+    t0 = time.time()
+    rp, cl = (x.cpu().numpy() for x in s.pattern())
+    X = sp.csr_matrix((R.cpu().numpy(), cl, rp), shape=(F.n, F.n))
+    lu = spla.splu(sp.csc_matrix(A))
+
+    def apply_inv(x):
+        y = np.empty_like(x)
+        y[q] = x
+        return lu.solve(y)[q]
+
+    lam, V, res, napp = inverse_error_eigenpairs(apply_inv, X, k, tol=1e-8, seed=0)
+    corr = accept_on_device(s, torch.as_tensor(d_ref_h, device=dev), dR, torch.as_tensor(V, device=dev), lam)
+    t_eig = time.time() - t0
+    log(f"spectral check: {t_eig:.1f}s, {napp} applications, |lam| {np.abs(lam)}, "
+        f"k_acc={len(corr.kept)} of {k}, err_1 {corr.err1_before:.3e} -> {corr.err1_after:.3e}")
+
+    for _ in range(args.warmup):
+        step()
+    s.sync()
+    ms_step = timed(step, args.steps) * 1e3
+    s.sync()
+    log(f"step {ms_step:.4f} ms")
+    s.profile(True)
+    for _ in range(3):
+        step()
+    prof = s.profile_read()
+    s.profile(False)
+    s.sync()
+    log("profile: " + ", ".join(f"{kk}: {v[0]} launches {v[1]:.3f} ms" for kk, v in prof.items() if v[0]))
+    # NInv and Mix on their own pattern (synchronous calls: size, then fill)
+    Nf = s.ninv_full(p=p, delta=delta, drop=delta)
+    Mf = s.mix_full(Z, Nf, eps)
+    s.sync()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        s.ninv_full(p=p, delta=delta, drop=delta)
+    s.sync()
+    ms_nfull = (time.perf_counter() - t0) / 5 * 1e3
+    t0 = time.perf_counter()
+    for _ in range(5):
+        s.mix_full(Z, Nf, eps)
+    s.sync()
+    ms_mfull = (time.perf_counter() - t0) / 5 * 1e3
+    full = {"ninv_nnz_lower": int(Nf[1].numel()), "mix_nnz_lower": int(Mf[1].numel()),
+            "ninv_ms": ms_nfull, "mix_ms": ms_mfull, "drop": delta}
+    log(f"full pattern: NInv {full['ninv_nnz_lower']} lower entries {ms_nfull:.2f} ms, Mix "
+        f"{full['mix_nnz_lower']} lower entries {ms_mfull:.2f} ms (|S| lower {(nnzS + F.n) // 2})")
+    # dominant kernel class of the step
+    dom = max((kk for kk, v in prof.items() if v[0]), key=lambda kk: prof[kk][1])
+    launches, tot_ms, tot_bytes = prof[dom]
+    avg_ms = tot_ms / max(launches, 1)
+    achieved = (tot_bytes / launches) / (avg_ms * 1e-3) / 1e9 if launches and tot_bytes else 0.0
+
+    result = {
+        "metric": "selected entries of A^-1 per sec (SelInv, Mix, Mix+learned) at stated rel error",
+        "value": nnzS / (ms_step * 1e-3),
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"covariance-type matrix c_ij = (1 - d/{alpha:g})^{beta:g} on a {N}x{N} grid, "
+                               f"nested multicolor order, ILDL tau={tau}; step = SelInv with NInv(p=3, "
+                               f"delta=0.1) beside it + Mix(eps=1e-2) + SPAI({cg} CG) + diagonal + trace",
+                   "n": F.n, "nnz_A": int(A.nnz), "nnz_L": F.nnzL, "nnz_S": nnzS,
+                   "levels": info["n_levels"], "max_cols": info["max_cols"], "parallelism": "single GPU"},
+        "err1": errs,
+        "trace_rel_error": trs,
+        "trace_reference": tr_ref,
+        "spectral_check": {"k": k, "k_acc": len(corr.kept), "lambda": [float(x) for x in lam],
+                           "eig_residual_max": float(res.max()), "host_s": t_eig,
+                           "err1_before": corr.err1_before, "err1_after": corr.err1_after},
+        "profile_ms_per_step": {kk: v[1] / 3 for kk, v in prof.items() if v[0]},
+        "roofline": {"kernel": f"{dom} (kernel class with the largest share of the step)",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "launches_per_step": launches // 3, "avg_launch_ms": avg_ms,
+                     "alg_bytes_per_launch": tot_bytes / max(launches, 1)},
+        "host": {"ildl_s": t_fact, "analysis_s": t_sym, "reference_s": t_ref},
+        "reference": {"method": "Jacobi-preconditioned CG per unit vector, float64, on the device",
+                      "max_iterations": cg_it, "max_rel_residual": cg_res},
+        "full_pattern": full,
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import core as oc
+        S = oc.pattern(F)
+        Ahat = oc.permuted(A, F.perm)
+        t0 = time.perf_counter()
+        Zo = oc.selinv(F, S)
+        No = oc.ninv(F, S, p, delta)
+        Mo = oc.mix(S, Zo, No, eps)
+        Ro = oc.spai(Ahat, S, Mo, cg)
+        tro = oc.trace_sums(S, Ro)
+        t_cpu = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": nnzS / t_cpu, "unit": "entries/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"the whole workload ({N}^2, |S|={nnzS}): single-threaded float64 "
+                                            f"oracle SelInv + NInv + Mix + SPAI + trace, {t_cpu:.1f} s"}
+        result["rel_error_vs_oracle"] = {
+            "selinv_fp64_max": float(oc.entry_error(S, Z.cpu().numpy(), Zo).max()),
+            "ninv_fp64_max": float(oc.entry_error(S, Nn.cpu().numpy(), No).max()),
+            "mix_fp64_max": float(oc.entry_error(S, M.cpu().numpy(), Mo).max()),
+            "mix_spai_fp64_max": float(oc.entry_error(S, R.cpu().numpy(), Ro).max()),
+            "trace_rel": abs(float(tr[0].item()) / tro[0] - 1.0)}
+        # NInv on its own pattern: same pattern as the oracle's, largest entry error
+        Nfo = oc.ninv_full(F, p, delta, delta)
+        rp_g, c_g, v_g = (x.cpu().numpy() for x in Nf)
+        same = np.array_equal(rp_g, Nfo[0]) and np.array_equal(c_g, Nfo[1])
+        dN = v_g[rp_g[1:] - 1]  # the diagonal closes every lower row
+        rr = np.repeat(np.arange(F.n), np.diff(rp_g))
+        result["rel_error_vs_oracle"]["ninv_full_same_pattern"] = bool(same)
+        if same:
+            result["rel_error_vs_oracle"]["ninv_full_fp64_max"] = float(
+                (np.abs(v_g - Nfo[2]) / np.sqrt(np.abs(dN[rr] * dN[c_g]))).max())
         log(f"oracle {t_cpu:.1f}s; {result['rel_error_vs_oracle']}")
     print(json.dumps(result), flush=True)
 

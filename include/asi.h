@@ -155,6 +155,39 @@ asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, con
                     int32_t p, double delta, asi_precision prec, double *N_S);
 
 /*
+ * NInv on its own pattern (Section 2.2): N = (L^inv)^T D^-1 L^inv, L^inv the
+ * truncated series of asi_ninv (p terms, entry drop delta), evaluated at
+ * every (i, j) whose columns of L^inv meet a common D block, with the
+ * off-diagonal entries |N_ij| < drop sqrt(|N_ii N_jj|) removed (the drop of
+ * the product, Section 2.2; read relative to the diagonal so that it does not
+ * depend on the scaling of A). The result is the lower triangle (diagonal
+ * included) in CSR with sorted columns: rowptr (n + 1 int64), col (int32)
+ * and val (float64), device arrays of the caller; col and val hold cap
+ * entries. The call is synchronous: it sizes the result (*nnz, host), and if
+ * it exceeds cap writes only rowptr and returns ASI_E_WORKSPACE, so a caller
+ * may call with cap = 0 first. The L^inv columns and the rows of D^-1 L^inv
+ * use the workspace's NInv pool, which must hold twice the series' entries
+ * (ASI_E_WORKSPACE otherwise). Float64; repeatable bit for bit unless a
+ * series column needed the workgroup kernel of asi_ninv (then to rounding).
+ * Factor pointers as for asi_selinv (all NULL: the loaded factor).
+ */
+asi_status asi_ninv_full(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub, int32_t p,
+                         double delta, double drop, int64_t cap, int64_t *rowptr, int32_t *col, double *val,
+                         int64_t *nnz);
+
+/*
+ * Mix on NInv's own pattern (Section 2.3: Mix keeps the structure of NInv
+ * and takes SelInv's value on S_eps = {(i, j) in S : |Z_ij| > eps
+ * sqrt(|Z_ii Z_jj|)}): the pattern of N joined with S_eps, Z_ij on S_eps and
+ * N_ij elsewhere. Z_S: SelInv on S (|S| float64); N_rowptr, N_col, N_val: the
+ * lower triangle of N as returned by asi_ninv_full. Output, cap and *nnz as
+ * for asi_ninv_full (lower triangle, CSR, synchronous).
+ */
+asi_status asi_mix_full(asi_handle h, const double *Z_S, const int64_t *N_rowptr, const int32_t *N_col,
+                        const double *N_val, double eps, int64_t cap, int64_t *rowptr, int32_t *col, double *val,
+                        int64_t *nnz);
+
+/*
  * SelInv and NInv of the same factor in one call (together they are the
  * inputs of Mix, Section 2.3): NInv runs on a second stream of the handle
  * (created on first use, default priority) concurrently with the SelInv
@@ -259,6 +292,22 @@ asi_status asi_diag(asi_handle h, const double *X_S, double *d);
  */
 asi_status asi_diag_err1(asi_handle h, const double *d_ref, const double *d_hat, int32_t k, const double *V,
                          const double *lambda, double *sums);
+
+/*
+ * Trace and diagonal 1-norm of an approximate inverse on S with an optional
+ * rank-k term (Section 3.5, covariance and uncertainty quantification: the
+ * trace of the covariance A^-1 is approximated by the sum of the diagonal of
+ * the approximation, corrected by V_k Lambda_k V_k^T when a correction is
+ * accepted):
+ *   sums[0] = sum_i c_i,  sums[1] = sum_i |c_i|,
+ *   c_i = X(i, i) + sum_{m<k} lambda_m V[i][m]^2.
+ * X_S: |S| float64 on S; V: n x k row-major float64, lambda: k float64, both
+ * unused when k = 0; 0 <= k <= 64. sums: 2 float64. Every pointer is a
+ * device pointer; asynchronous on the handle's stream. The summation order is
+ * fixed, so repeated calls give the same bits. Needs an analysis.
+ */
+asi_status asi_trace(asi_handle h, const double *X_S, int32_t k, const double *V, const double *lambda,
+                     double *sums);
 
 /* Wait for the handle's stream; return the first device-side error latched
  * since the previous asi_sync (and clear it). */

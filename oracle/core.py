@@ -152,6 +152,80 @@ def ninv(F, S: Pattern, p: int, delta: float, linv_cols=None) -> np.ndarray:
     return N[:S.nnz]
 
 
+def dinv_matrix(F) -> sp.csr_matrix:
+    """D^-1 as a sparse block-diagonal matrix (1x1 and 2x2 blocks, Section 2.1),
+    2x2 inverses as [d, -c; -c, a] / (a d - c^2)."""
+    n = F.n
+    rows, cols, vals = [], [], []
+    j = 0
+    while j < n:
+        if F.piv[j] == 1:
+            a, c, d = F.d_diag[j], F.d_sub[j], F.d_diag[j + 1]
+            det = a * d - c * c
+            rows += [j, j, j + 1, j + 1]
+            cols += [j, j + 1, j, j + 1]
+            vals += [d / det, -c / det, -c / det, a / det]
+            j += 2
+        else:
+            rows.append(j)
+            cols.append(j)
+            vals.append(1.0 / F.d_diag[j])
+            j += 1
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+
+
+def ninv_full(F, p: int, delta: float, drop: float, linv_cols=None):
+    """NInv on its own pattern (Section 2.2): N = (L^inv)^T D^-1 L^inv over
+    every pair of columns of L^inv that meet a common D block, with the
+    off-diagonal entries |N_ij| < drop sqrt(|N_ii N_jj|) removed (the product
+    drop of Section 2.2). Returns the lower triangle (diagonal included) as
+    CSR arrays (rowptr int64, col int32 sorted, val float64)."""
+    n = F.n
+    Vp, Vi, Vx = linv(F, p, delta) if linv_cols is None else linv_cols
+    Li = sp.csc_matrix((Vx, Vi, Vp), shape=(n, n))
+    Di = dinv_matrix(F)
+    N = (Li.T @ Di @ Li).tocsr()
+    # structure without cancellation: the same product over indicator matrices
+    B = sp.csc_matrix((np.ones(len(Vi)), Vi, Vp), shape=(n, n))
+    C = sp.csr_matrix((np.ones(Di.nnz), Di.indices, Di.indptr), shape=(n, n))
+    Pt = sp.tril(B.T @ C @ B).tocsr()
+    Pt.sort_indices()
+    r = np.repeat(np.arange(n), np.diff(Pt.indptr))
+    c = Pt.indices.astype(np.int64)
+    v = np.asarray(N[r, c]).ravel()
+    d = N.diagonal()
+    keep = (r == c) | (np.abs(v) >= drop * np.sqrt(np.abs(d[r] * d[c])))
+    r, c, v = r[keep], c[keep], v[keep]
+    rowptr = np.zeros(n + 1, np.int64)
+    np.add.at(rowptr, r + 1, 1)
+    return np.cumsum(rowptr), c.astype(np.int32), v
+
+
+def mix_full(S: Pattern, Z: np.ndarray, Nfull, eps: float):
+    """Mix on NInv's own pattern (Section 2.3): Z_ij for (i, j) in S_eps =
+    {|Z_ij| > eps sqrt(|Z_ii Z_jj|)}, N_ij elsewhere on N's pattern; the
+    pattern is N's joined with S_eps. Nfull and the result are lower
+    triangles (diagonal included) as CSR arrays (rowptr, col, val)."""
+    n = S.n
+    r = S.rows()
+    c = S.col.astype(np.int64)
+    zd = np.asarray(Z)[S.diag_positions()]
+    sel = (c <= r) & (np.abs(Z) > eps * np.sqrt(np.abs(zd[r] * zd[c])))
+    out = {}
+    Np, Nc, Nv = Nfull
+    for i in range(n):
+        for q in range(Np[i], Np[i + 1]):
+            out[(i, int(Nc[q]))] = Nv[q]
+    for q in np.nonzero(sel)[0]:
+        out[(int(r[q]), int(c[q]))] = Z[q]
+    keys = sorted(out)
+    rowptr = np.zeros(n + 1, np.int64)
+    for (i, _) in keys:
+        rowptr[i + 1] += 1
+    return (np.cumsum(rowptr), np.array([k[1] for k in keys], dtype=np.int32),
+            np.array([out[k] for k in keys], dtype=np.float64))
+
+
 def mix(S: Pattern, Z: np.ndarray, N: np.ndarray, eps: float) -> np.ndarray:
     """Mix (Section 2.3): Z where |Z_ij| > eps sqrt(|Z_ii Z_jj|), else N."""
     lib = _load()

@@ -26,7 +26,7 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_set_workspace", "asi_get_info", "asi_get_pattern", "asi_selinv", "asi_ninv",
            "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
            "asi_profile_read", "asi_set_sweep", "asi_mlp_features", "asi_mlp_pack", "asi_mlp_forward",
-           "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor", "asi_selinv_ninv"]
+           "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor", "asi_selinv_ninv", "asi_trace", "asi_ninv_full", "asi_mix_full"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -80,6 +80,9 @@ def load_library():
         "asi_lowrank": [P, i32, P, P, P, P],
         "asi_diag": [P, P, P],
         "asi_diag_err1": [P, P, P, i32, P, P, P],
+        "asi_trace": [P, P, i32, P, P, P],
+        "asi_ninv_full": [P, P, P, P, i32, f64, f64, i64, P, P, P, P],
+        "asi_mix_full": [P, P, P, P, P, f64, i64, P, P, P, P],
         "asi_sync": [P],
         "asi_profile": [P, ctypes.c_int],
         "asi_set_sweep": [P, ctypes.c_int],
@@ -322,6 +325,41 @@ class Solver:
         self._stream()
         self._check(self.lib.asi_diag_err1(self.h, _ptr(d_ref), _ptr(d_hat), k,
                                            _ptr(V) if k else None, _ptr(lam) if k else None, _ptr(sums)))
+        return sums
+
+    def _full_call(self, fn, args):
+        """Two-pass call of a full-pattern entry point: size, allocate, fill."""
+        t = self.torch
+        nnz = ctypes.c_int64(0)
+        rowptr = t.empty(self.n + 1, dtype=t.int64, device=self.device)
+        self._stream()
+        rc = fn(self.h, *args, 0, _ptr(rowptr), None, None, ctypes.byref(nnz))
+        if rc != 0 and nnz.value == 0:
+            self._check(rc)
+        col = t.empty(max(nnz.value, 1), dtype=t.int32, device=self.device)
+        val = t.empty(max(nnz.value, 1), dtype=t.float64, device=self.device)
+        self._check(fn(self.h, *args, nnz.value, _ptr(rowptr), _ptr(col), _ptr(val), ctypes.byref(nnz)))
+        return rowptr, col[:nnz.value], val[:nnz.value]
+
+    def ninv_full(self, L_val=None, d_diag=None, d_sub=None, p=3, delta=0.1, drop=0.1):
+        """NInv on its own pattern: lower triangle as (rowptr int64, col int32, val float64)."""
+        return self._full_call(self.lib.asi_ninv_full, (_ptr(L_val), _ptr(d_diag), _ptr(d_sub), int(p),
+                                                        float(delta), float(drop)))
+
+    def mix_full(self, Z, N_full, eps=1e-2):
+        """Mix on NInv's pattern joined with S_eps: lower triangle as (rowptr, col, val)."""
+        rp, cl, vl = N_full
+        return self._full_call(self.lib.asi_mix_full, (_ptr(Z), _ptr(rp), _ptr(cl), _ptr(vl), float(eps)))
+
+    def trace(self, X, V=None, lam=None, sums=None):
+        """Device float64[2]: (sum_i c_i, sum_i |c_i|), c_i = X_ii + sum_m lam_m V_im^2."""
+        t = self.torch
+        if sums is None:
+            sums = t.empty(2, dtype=t.float64, device=self.device)
+        k = 0 if V is None else int(V.shape[1])
+        self._stream()
+        self._check(self.lib.asi_trace(self.h, _ptr(X), k, _ptr(V) if k else None, _ptr(lam) if k else None,
+                                       _ptr(sums)))
         return sums
 
     def sync(self):

@@ -173,6 +173,16 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
         }
     }
     for (int64_t u = 0; u < A.nnzU; ++u) A.useg_u[u] = A.ustart[A.ucol[u]];
+    // S position -> u-index of the entry's L value (int32; the learned
+    // correction, which reads it, needs |S| < 2^31)
+    A.s2u.assign(A.nnzS <= (int64_t)INT32_MAX ? A.nnzS : 0, -1);
+    if (!A.s2u.empty())
+        for (int32_t i = 0; i < n; ++i)
+            for (int64_t p = A.diagpos[i] + 1; p < A.rowptr[i + 1]; ++p) {
+                const int32_t u = (int32_t)(A.ustart[i] + (p - A.diagpos[i] - 1));
+                A.s2u[p] = u;
+                A.s2u[A.mirror[p]] = u;
+            }
 
     // blocks, levels and work counts
     A.level.assign(n, 0);

@@ -44,7 +44,12 @@ struct asi_handle_s {
     double *zd = nullptr;
     int32_t *done = nullptr;
     unsigned char *node = nullptr;
-    double *rn = nullptr;         // ||L(i, :)||_2 of the factor in Lu (set with it)
+    int32_t *s2u = nullptr;       // S position -> u-index of its L value
+    int64_t *nf_rpT = nullptr;    // NInv on its own pattern: rows of w, cursors, diagonal, scan sums
+    unsigned long long *nf_cur = nullptr;
+    double *nf_dN = nullptr;
+    unsigned long long *nf_bsum = nullptr;
+    double *rn = nullptr;         // ||L(i, :)||_2, then ||L(:, i)||_2, of the factor in Lu (set with it)
     int64_t *rowptr_L = nullptr;  // the input L's row pointers
     float *Lf = nullptr;          // float32 copy of the loaded factor's L (mixed precision)
     bool factor_loaded = false;   // Lu (float64) and dinv hold the factor of asi_load_factor
@@ -162,8 +167,13 @@ Layout make_layout(const asi::Analysis &A) {
     L.add(2 * asi::kRedBlocks * 8);     // 31 partial sums of the diagonal error
     L.add(2 * n * 4);                   // 32 column lists of the SPAI kernels
     L.add(u * 4);                       // 33 L in u-space, float32 (mixed precision)
-    L.add(n * 8);                       // 34 row norms of L (learned-correction features)
+    L.add(2 * n * 8);                   // 34 row and column norms of L (learned-correction features)
     L.add((n + 1) * 8);                 // 35 row pointers of the input L
+    L.add(A.s2u.size() * 4);            // 36 u-index of each entry's L value (learned correction)
+    L.add((n + 1) * 8);                 // 37 NInv on its own pattern: row pointers of the rows of w
+    L.add((n + 1) * 8);                 // 38   their fill cursors
+    L.add(n * 8);                       // 39   diagonal of N
+    L.add((n / 1024 + 2) * 8);          // 40   scan block sums
     return L;
 }
 
@@ -336,6 +346,11 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->Lf = at<float>(b, L.off[33]);
     h->rn = at<double>(b, L.off[34]);
     h->rowptr_L = at<int64_t>(b, L.off[35]);
+    h->s2u = at<int32_t>(b, L.off[36]);
+    h->nf_rpT = at<int64_t>(b, L.off[37]);
+    h->nf_cur = at<unsigned long long>(b, L.off[38]);
+    h->nf_dN = at<double>(b, L.off[39]);
+    h->nf_bsum = at<unsigned long long>(b, L.off[40]);
     h->factor_loaded = false;
     h->lf_loaded = false;
     h->epoch = 0;
@@ -372,6 +387,7 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
         {h->meta_small, A.meta_small.data(), A.meta_small.size() * 64},
         {h->meta_big, A.meta_big.data(), A.meta_big.size() * 64},
         {h->rowptr_L, A.L_rowptr.data(), A.L_rowptr.size() * 8},
+        {h->s2u, A.s2u.data(), A.s2u.size() * 4},
     };
     for (auto &u : ups) {
         if (u.bytes == 0) continue;
@@ -385,6 +401,7 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     if (e != hipSuccess) return hip_fail(h, e, "upload analysis");
     e = asi::set_big_lds_limits();
     if (e == hipSuccess) e = asi::set_ninv_lds_limits();
+    if (e == hipSuccess) e = asi::set_nfull_lds_limits();
     if (e != hipSuccess) return hip_fail(h, e, "set LDS limits");
     h->ws_ready = true;
     return ASI_OK;
@@ -443,8 +460,10 @@ static asi_status prepare_factor(asi_handle h, const double *L_val, const double
         {
             Trace t(h, ASI_K_GATHER, 24.0 * A.nnzU);
             e = asi::launch_gather_lu(A.nnzU, h->lsrc_u, L_val, fp64 ? h->Lu : (void *)h->Lf, fp64, h->stream);
-            // the row norms of L (learned-correction features) come with the float64 copy
-            if (e == hipSuccess && fp64) e = asi::launch_row_norms(A.n, h->rowptr_L, L_val, h->rn, h->stream);
+            // the row and column norms of L (learned-correction features) come with the float64 copy
+            if (e == hipSuccess && fp64)
+                e = asi::launch_factor_norms(A.n, h->rowptr_L, L_val, h->ustart, reinterpret_cast<const double *>(h->Lu),
+                                             h->rn, h->stream);
         }
         if (e != hipSuccess) return hip_fail(h, e, "gather L");
     } else {
@@ -607,6 +626,151 @@ asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, con
     return ninv_launch(h, Lu, fp64, p, delta, N_S, h->stream, 0);
 }
 
+// Result sizes of the full-pattern calls: the count pass leaves the row
+// pointers in the caller's array; their last entry is the size.
+static asi_status read_total(asi_handle h, const int64_t *rowptr, int64_t *nnz) {
+    asi_status s = asi_sync(h);  // surfaces a latched device error
+    if (s != ASI_OK) return s;
+    hipError_t e = hipMemcpy(nnz, rowptr + h->A.n, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "read result size");
+    return ASI_OK;
+}
+
+asi_status asi_ninv_full(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub, int32_t p,
+                         double delta, double drop, int64_t cap, int64_t *rowptr, int32_t *col, double *val,
+                         int64_t *nnz) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!rowptr || !nnz || (cap > 0 && (!col || !val))) return fail(h, ASI_E_ARG, "null pointer");
+    if (p < 0 || p > 64) return fail(h, ASI_E_ARG, "p must be in [0, 64]");
+    if (!(delta >= 0.0) || !(drop >= 0.0)) return fail(h, ASI_E_ARG, "delta and drop must be >= 0");
+    DeviceGuard g(h->device);
+    const asi::Analysis &A = h->A;
+    *nnz = 0;
+    const void *Lu = nullptr;
+    s = prepare_factor(h, L_val, d_diag, d_sub, true, &Lu);
+    if (s != ASI_OK) return s;
+    asi::NinvParams Q{};
+    Q.n = A.n;
+    Q.rowptr = h->rowptr;
+    Q.col = h->col;
+    Q.diagpos = h->diagpos;
+    Q.mirror = h->mirror;
+    Q.ustart = h->ustart;
+    Q.ucol = h->ucol;
+    Q.piv = h->piv;
+    Q.Lu = Lu;
+    Q.dinv = h->dinv;
+    Q.p = p;
+    Q.delta = delta;
+    Q.prow = h->prow;
+    Q.plinv = h->plinv;
+    Q.pw = h->pw;
+    Q.pool_cap = h->pool_cap;
+    Q.pool_top = h->pool_top;
+    Q.cstart = h->cstart;
+    Q.clen = h->clen;
+    Q.ovf_list = h->ovf;
+    Q.ovf_count = h->counters;
+    Q.ovf2_list = h->ovf2;
+    Q.ovf2_count = h->counters + 1;
+    Q.status = h->status;
+    hipError_t e;
+    {
+        Trace t(h, ASI_K_NINV, 0.0);
+        e = asi::launch_linv(Q, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "ninv series");
+    s = asi_sync(h);
+    if (s != ASI_OK) return s;
+    unsigned long long used = 0;
+    e = hipMemcpy(&used, h->pool_top, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "read pool size");
+    // the rows of w go to the upper half of the pool's row and w regions
+    const int64_t half = h->pool_cap / 2;
+    if ((int64_t)used > half) return fail(h, ASI_E_WORKSPACE, "NInv pool too small for the full pattern: enlarge the workspace");
+    asi::NfullParams P{};
+    P.n = A.n;
+    P.cstart = h->cstart;
+    P.clen = h->clen;
+    P.prow = h->prow;
+    P.plinv = reinterpret_cast<double *>(h->plinv);
+    P.pw = reinterpret_cast<double *>(h->pw);
+    P.rpT = h->nf_rpT;
+    P.cur = h->nf_cur;
+    P.colT = h->prow + half;
+    P.valT = reinterpret_cast<double *>(h->pw) + half;
+    P.dN = h->nf_dN;
+    P.drop = drop;
+    P.bsum = h->nf_bsum;
+    P.cnt = reinterpret_cast<unsigned long long *>(rowptr);
+    P.rowptr = rowptr;
+    P.col = col;
+    P.val = val;
+    P.ovf_list = h->ovf;
+    P.ovf_count = h->counters;
+    P.status = h->status;
+    {
+        Trace t(h, ASI_K_NINV, 0.0);
+        e = asi::launch_nfull_prepare(P, h->stream);
+        if (e == hipSuccess) e = asi::launch_nfull_rows(P, false, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "ninv full pattern (count)");
+    s = read_total(h, rowptr, nnz);
+    if (s != ASI_OK) return s;
+    if (*nnz > cap) return fail(h, ASI_E_WORKSPACE, "result larger than cap (the size is in *nnz)");
+    {
+        Trace t(h, ASI_K_NINV, 0.0);
+        e = asi::launch_nfull_rows(P, true, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "ninv full pattern (fill)");
+    return asi_sync(h);
+}
+
+asi_status asi_mix_full(asi_handle h, const double *Z_S, const int64_t *N_rowptr, const int32_t *N_col,
+                        const double *N_val, double eps, int64_t cap, int64_t *rowptr, int32_t *col, double *val,
+                        int64_t *nnz) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!Z_S || !N_rowptr || !rowptr || !nnz || (cap > 0 && (!col || !val))) return fail(h, ASI_E_ARG, "null pointer");
+    if (!(eps >= 0.0)) return fail(h, ASI_E_ARG, "eps must be >= 0");
+    DeviceGuard g(h->device);
+    const asi::Analysis &A = h->A;
+    *nnz = 0;
+    hipError_t e = asi::launch_zdiag(A.n, h->diagpos, Z_S, h->zdiag, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "Z diagonal");
+    asi::MixFullParams P{};
+    P.n = A.n;
+    P.Nrp = N_rowptr;
+    P.Ncol = N_col;
+    P.Nval = N_val;
+    P.srp = h->rowptr;
+    P.scol = h->col;
+    P.diagpos = h->diagpos;
+    P.Z = Z_S;
+    P.zdiag = h->zdiag;
+    P.eps = eps;
+    P.bsum = h->nf_bsum;
+    P.cnt = reinterpret_cast<unsigned long long *>(rowptr);
+    P.rowptr = rowptr;
+    P.col = col;
+    P.val = val;
+    {
+        Trace t(h, ASI_K_MIX, 0.0);
+        e = asi::launch_mixfull(P, false, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "mix full pattern (count)");
+    s = read_total(h, rowptr, nnz);
+    if (s != ASI_OK) return s;
+    if (*nnz > cap) return fail(h, ASI_E_WORKSPACE, "result larger than cap (the size is in *nnz)");
+    {
+        Trace t(h, ASI_K_MIX, 0.0);
+        e = asi::launch_mixfull(P, true, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "mix full pattern (fill)");
+    return ASI_OK;
+}
+
 asi_status asi_selinv_ninv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
                            int32_t p, double delta, asi_precision prec, double *Z_S, double *N_S) {
     asi_status s = need_ready(h);
@@ -727,7 +891,7 @@ static asi_status mlp_setup(asi_handle h, const double *Z_S, const double *N_S, 
     P.srow = h->srow;
     P.col = h->col;
     P.diagpos = h->diagpos;
-    P.mirror = h->mirror;
+    P.s2u = h->s2u;
     P.ustart = h->ustart;
     P.piv = h->piv;
     P.level = h->level;
@@ -875,6 +1039,20 @@ asi_status asi_diag_err1(asi_handle h, const double *d_ref, const double *d_hat,
     Trace t(h, ASI_K_DIAG, 16.0 * h->A.n + 8.0 * h->A.n * k);
     hipError_t e = asi::launch_diag_err1(h->A.n, d_ref, d_hat, k, V, lambda, h->red, sums, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "diag_err1");
+    return ASI_OK;
+}
+
+asi_status asi_trace(asi_handle h, const double *X_S, int32_t k, const double *V, const double *lambda,
+                     double *sums) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!X_S || !sums) return fail(h, ASI_E_ARG, "null pointer");
+    if (k < 0 || k > asi::kMaxRank) return fail(h, ASI_E_ARG, "k must be in [0, 64]");
+    if (k > 0 && (!V || !lambda)) return fail(h, ASI_E_ARG, "null V or lambda with k > 0");
+    DeviceGuard g(h->device);
+    Trace t(h, ASI_K_DIAG, 16.0 * h->A.n + 8.0 * h->A.n * k);
+    hipError_t e = asi::launch_trace(h->A.n, h->diagpos, X_S, k, V, lambda, h->red, sums, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "trace");
     return ASI_OK;
 }
 

@@ -46,6 +46,7 @@ struct Analysis {
     std::vector<int64_t> rowptr;   // n+1
     std::vector<int32_t> col;      // nnzS
     std::vector<int32_t> srow;     // nnzS: row of each position
+    std::vector<int32_t> s2u;      // nnzS: u-index of L(max(i, j), min(i, j)) for (i, j), -1 on the diagonal
     std::vector<int64_t> diagpos;  // n: position of (i, i)
     std::vector<int64_t> mirror;   // nnzS: position of (j, i) for (i, j)
     // Upper triangle of S by rows ("u-space", the columns of L): the u-range of

@@ -88,6 +88,8 @@ hipError_t launch_mix(int64_t nnz, const int32_t *srow, const int32_t *col, cons
                       const double *Z, const double *N, double eps, double *M, hipStream_t st);
 hipError_t launch_diag_err1(int32_t n, const double *d_ref, const double *d_hat, int32_t k, const double *V,
                             const double *lam, double *part, double *sums, hipStream_t st);
+hipError_t launch_trace(int32_t n, const int64_t *diagpos, const double *X, int32_t k, const double *V,
+                        const double *lam, double *part, double *sums, hipStream_t st);
 hipError_t launch_lowrank(int64_t nnz, int32_t k, const int32_t *srow, const int32_t *col, const double *V,
                           const double *lam, const double *in, double *out, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st);
@@ -121,7 +123,7 @@ struct MlpFeatParams {
     const int32_t *srow;
     const int32_t *col;
     const int64_t *diagpos;
-    const int64_t *mirror;
+    const int32_t *s2u;  // nnz: u-index of the entry's L value, -1 on the diagonal
     const int64_t *ustart;
     const int8_t *piv;
     const int32_t *level;
@@ -129,15 +131,63 @@ struct MlpFeatParams {
     const double *Lu;    // u-space L values (float64)
     const double *dinv;  // 3 per block start
     void *node;          // n per-node feature records of 32 bytes (workspace)
-    const double *rn;    // n: ||L(i, :)||_2
+    const double *rn;    // 2n: ||L(i, :)||_2, then ||L(:, i)||_2
     const double *Z, *N, *M;
     double eps;
     uint16_t *F;  // nnz x 16 bfloat16
     float *scale; // nnz
 };
 
+// NInv and Mix on their own pattern (lower triangle, CSR)
+struct NfullParams {
+    int32_t n;
+    const int64_t *cstart;  // pool columns of L^inv (rows, L^inv, w = D^-1 L^inv; float64)
+    const int32_t *clen;
+    int32_t *prow;
+    double *plinv, *pw;
+    int64_t *rpT;             // n + 1: row pointers of the rows of w
+    unsigned long long *cur;  // n + 1: fill cursors
+    int32_t *colT;            // rows of w: columns and values
+    double *valT;
+    double *dN;               // n: diagonal of N
+    double drop;
+    unsigned long long *bsum; // scan block sums
+    unsigned long long *cnt;  // count pass: n + 1 (cnt[0] = 0), scanned into row pointers
+    const int64_t *rowptr;    // fill pass: row pointers of the result
+    int32_t *col;
+    double *val;
+    int32_t *ovf_list;        // n
+    int32_t *ovf_count;       // 1
+    int32_t *status;
+};
+
+struct MixFullParams {
+    int32_t n;
+    const int64_t *Nrp;  // N (lower, CSR)
+    const int32_t *Ncol;
+    const double *Nval;
+    const int64_t *srp;  // S
+    const int32_t *scol;
+    const int64_t *diagpos;
+    const double *Z;     // SelInv on S
+    const double *zdiag;
+    double eps;
+    unsigned long long *bsum;
+    unsigned long long *cnt;
+    const int64_t *rowptr;
+    int32_t *col;
+    double *val;
+};
+
+hipError_t launch_linv(const NinvParams &P, hipStream_t st);  // float64 series columns into the pool
+hipError_t launch_nfull_prepare(const NfullParams &P, hipStream_t st);
+hipError_t launch_nfull_rows(const NfullParams &P, bool fill, hipStream_t st);
+hipError_t launch_mixfull(const MixFullParams &P, bool fill, hipStream_t st);
+hipError_t set_nfull_lds_limits();
+
 hipError_t launch_node_feats(const MlpFeatParams &P, hipStream_t st);
-hipError_t launch_row_norms(int32_t n, const int64_t *Lp, const double *Lval, double *rn, hipStream_t st);
+hipError_t launch_factor_norms(int32_t n, const int64_t *Lp, const double *Lval, const int64_t *ustart,
+                              const double *Lu, double *rn, hipStream_t st);
 hipError_t launch_mlp_features(const MlpFeatParams &P, hipStream_t st);
 hipError_t launch_mlp_correct(const MlpFeatParams &P, const void *W, double *out, hipStream_t st);
 hipError_t launch_mlp_pack(const float *theta, void *W, hipStream_t st);

@@ -509,6 +509,36 @@ __global__ __launch_bounds__(256) void k_err1_part(int32_t n, const double *__re
     }
 }
 
+// Trace of a matrix on S with an optional rank-k term, per block of 256
+// unknowns (same two-stage pattern as the err_1 sums): part = (sum_i c_i,
+// sum_i |c_i|) with c_i = X(i, i) + sum_{m<k} lam_m V[i][m]^2.
+__global__ __launch_bounds__(256) void k_trace_part(int32_t n, const int64_t *__restrict__ diagpos,
+                                                    const double *__restrict__ X, int32_t k,
+                                                    const double *__restrict__ V, const double *__restrict__ lam,
+                                                    double *__restrict__ part) {
+    __shared__ double s0[4], s1[4];
+    double a = 0.0, b = 0.0;
+    for (int32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        double c = X[diagpos[i]];
+        const double *v = V + (int64_t)i * k;
+        for (int m = 0; m < k; ++m) c += lam[m] * v[m] * v[m];
+        a += c;
+        b += fabs(c);
+    }
+    a = wsum(a);
+    b = wsum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s0[w] = a;
+        s1[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = (s0[0] + s0[1]) + (s0[2] + s0[3]);
+        part[2 * blockIdx.x + 1] = (s1[0] + s1[1]) + (s1[2] + s1[3]);
+    }
+}
+
 // Second stage: one block adds the partial sums in a fixed order.
 __global__ __launch_bounds__(256) void k_err1_final(int nblk, const double *__restrict__ part,
                                                     double *__restrict__ sums) {
@@ -538,6 +568,14 @@ hipError_t launch_diag_err1(int32_t n, const double *d_ref, const double *d_hat,
                             const double *lam, double *part, double *sums, hipStream_t st) {
     int nblk = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ((int64_t)n + 255) / 256));
     hipLaunchKernelGGL(dev::k_err1_part, dim3(nblk), dim3(256), 0, st, n, d_ref, d_hat, k, V, lam, part);
+    hipLaunchKernelGGL(dev::k_err1_final, dim3(1), dim3(256), 0, st, nblk, part, sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(int32_t n, const int64_t *diagpos, const double *X, int32_t k, const double *V,
+                        const double *lam, double *part, double *sums, hipStream_t st) {
+    int nblk = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ((int64_t)n + 255) / 256));
+    hipLaunchKernelGGL(dev::k_trace_part, dim3(nblk), dim3(256), 0, st, n, diagpos, X, k, V, lam, part);
     hipLaunchKernelGGL(dev::k_err1_final, dim3(1), dim3(256), 0, st, nblk, part, sums);
     return hipGetLastError();
 }

@@ -19,6 +19,7 @@ namespace dev {
 
 typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
 typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
+typedef short s16x4 __attribute__((__vector_size__(4 * sizeof(short))));
 
 constexpr int NF = kMlpFeatures, NH = kMlpHidden;
 constexpr int OFF_W1 = 0, OFF_W2 = 4096, OFF_W3 = 12288, OFF_B1 = 12416, OFF_B2 = 12672, OFF_B3 = 12928;
@@ -46,12 +47,11 @@ __device__ inline float round_bf16(float x) { return from_bf16(to_bf16(x)); }
 // ---- features --------------------------------------------------------------
 // Per-node record, computed once per call: the diagonals of M and Z, the
 // node's bfloat16 features (log(|D^-1_ii| + 1e-30), log(||L(i,:)||_2 + 1e-30),
-// log(||L(:,i)||_2 + 1e-30), level(i) / max level, log(1 + |R_i|)) and the
-// offset from S positions of row i's upper part to its u-range (|S| < 2^31).
+// log(||L(:,i)||_2 + 1e-30), level(i) / max level, log(1 + |R_i|)).
 struct NodeRec {
     double m, z;
     uint16_t f[6];
-    int32_t uoff;  // ustart[i] - diagpos[i] - 1: u-index of S position q > diagpos[i] in row i is uoff + q
+    int32_t pad;
 };
 static_assert(sizeof(NodeRec) == 32, "node records are 32 bytes");
 
@@ -60,57 +60,96 @@ __device__ inline double dinv_diag(const double *dinv, const int8_t *piv, int32_
     return piv[i] == 2 ? dinv[3 * (int64_t)(i - 1) + 2] : dinv[3 * (int64_t)i];
 }
 
-// ||L(i, :)||_2 from the caller's CSR values (row order)
-__global__ void k_row_norms(int32_t n, const int64_t *__restrict__ Lp, const double *__restrict__ Lval,
-                            double *__restrict__ rn) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int64_t q = Lp[i]; q < Lp[i + 1]; ++q) s += Lval[q] * Lval[q];
-    rn[i] = sqrt(s);
+// ||L(i, :)||_2 from the caller's CSR values (row order) into rn[i] and
+// ||L(:, i)||_2 from the column layout (u-range of column i, padding is 0)
+// into rn[n + i]; 16 lanes per unknown, strided over its entries
+__global__ __launch_bounds__(256) void k_factor_norms(int32_t n, const int64_t *__restrict__ Lp,
+                                                      const double *__restrict__ Lval,
+                                                      const int64_t *__restrict__ ustart,
+                                                      const double *__restrict__ Lu, double *__restrict__ rn) {
+    const int32_t i = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 4);
+    const int sub = threadIdx.x & 15;
+    double r = 0.0, c = 0.0;
+    if (i < n) {
+        for (int64_t q = Lp[i] + sub; q < Lp[i + 1]; q += 16) r += Lval[q] * Lval[q];
+        for (int64_t u = ustart[i] + sub; u < ustart[i + 1]; u += 16) c += Lu[u] * Lu[u];
+    }
+#pragma unroll
+    for (int k = 8; k >= 1; k >>= 1) {
+        r += __shfl_xor(r, k, 64);
+        c += __shfl_xor(c, k, 64);
+    }
+    if (i < n && sub == 0) {
+        rn[i] = sqrt(r);
+        rn[n + i] = sqrt(c);
+    }
 }
 
 __global__ void k_node_feats(MlpFeatParams P) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
-    double cs = 0.0;
-    // column i of L from its column layout (u-space values, padding is 0)
-    for (int64_t u = P.ustart[i]; u < P.ustart[i + 1]; ++u) cs += P.Lu[u] * P.Lu[u];
     const double maxlev = P.maxlevel > 0 ? (double)P.maxlevel : 1.0;
     NodeRec r;
     r.m = P.M[P.diagpos[i]];
     r.z = P.Z[P.diagpos[i]];
     r.f[0] = feat_bf16(log(fabs(dinv_diag(P.dinv, P.piv, i)) + 1e-30));
     r.f[1] = feat_bf16(log(P.rn[i] + 1e-30));
-    r.f[2] = feat_bf16(log(sqrt(cs) + 1e-30));
+    r.f[2] = feat_bf16(log(P.rn[P.n + i] + 1e-30));
     r.f[3] = feat_bf16(P.level[i] / maxlev);
     r.f[4] = feat_bf16(log1p((double)(P.ustart[i + 1] - P.ustart[i])));
     r.f[5] = 0;
-    r.uoff = (int32_t)(P.ustart[i] - P.diagpos[i] - 1);
+    r.pad = 0;
     reinterpret_cast<NodeRec *>(P.node)[i] = r;
 }
 
 constexpr uint16_t kBf16One = 0x3F80;
 
-// The 16 features of entry p (order as in the header) and its M value and
-// scale s = sqrt(|M_ii M_jj|) (1 where that is 0).
-__device__ inline void entry_features(const MlpFeatParams &P, int64_t p, uint16_t (&f)[NF], double &m,
-                                      double &s) {
-    const NodeRec *node = reinterpret_cast<const NodeRec *>(P.node);
-    const int32_t i = P.srow[p], j = P.col[p];
-    const NodeRec ni = node[i], nj = node[j];
+// log(1 + x) for x >= 0 in float64 (+inf and NaN pass through), within a few
+// units in the last place: 1 + x = u = 2^e m with m in [sqrt(1/2), sqrt(2)),
+// log m = 2 atanh(t) = 2 t sum_k t^(2k) / (2k + 1) with t = (m - 1) / (m + 1)
+// (|t| <= 0.1716, so 11 terms reach float64 precision), plus the rounding
+// error of u, (x - (u - 1)) / u, which carries log1p's accuracy for small x.
+// The features round the result to float32 and then bfloat16, which a
+// last-place difference changes only for values within a few units of a
+// float32 rounding boundary.
+// coefficients 1 / (2k + 1), k = 10 .. 1, then ln 2 split so that e ln2_hi is
+// exact for |e| < 2^11 (a table in constant memory keeps them in scalar registers)
+__constant__ double kLog1pCoef[12] = {1.0 / 21.0, 1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0,
+                                      1.0 / 9.0,  1.0 / 7.0,  1.0 / 5.0,  1.0 / 3.0,
+                                      6.93147180369123816490e-01, 1.90821492927058770002e-10};
+
+__device__ inline double log1p_pos(double x) {
+    if (!(x < INFINITY)) return x;
+    const double u = 1.0 + x;
+    const double c = (x - (u - 1.0)) * __builtin_amdgcn_rcp(u);
+    int e = __builtin_amdgcn_frexp_exp(u);
+    double m = __builtin_amdgcn_frexp_mant(u);  // [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double t = (m - 1.0) / (m + 1.0);
+    const double t2 = t * t;
+    double q = kLog1pCoef[0];
+#pragma unroll
+    for (int k = 1; k < 10; ++k) q = fma(q, t2, kLog1pCoef[k]);
+    const double logm = 2.0 * t + (2.0 * t) * (t2 * q);
+    const double de = (double)e;
+    return fma(de, kLog1pCoef[10], logm + fma(de, kLog1pCoef[11], c));
+}
+
+// The 16 features of entry p = (i, j) (order as in the header) from its
+// values z = Z_ij, nv = N_ij, m = M_ij, the node records of i and j and
+// lval = |L(max, min)| (0 on the diagonal); s = sqrt(|M_ii M_jj|) (1 where
+// that is 0).
+__device__ inline void features_of(const MlpFeatParams &P, int32_t i, int32_t j, const NodeRec &ni,
+                                   const NodeRec &nj, double z, double nv, double m, double lval, uint16_t (&f)[NF],
+                                   double &s) {
     s = sqrt(fabs(ni.m * nj.m));
     if (!(s > 0.0)) s = 1.0;
-    const double z = P.Z[p], nv = P.N[p];
-    m = P.M[p];
-    double lval = 0.0;
-    if (i != j) {
-        // L(max, min) sits in row min's u-range at the upper position of the entry
-        const int64_t u = i < j ? (int64_t)ni.uoff + p : (int64_t)nj.uoff + P.mirror[p];
-        lval = fabs(P.Lu[u]);
-    }
-    f[0] = feat_bf16(m / s);
-    f[1] = feat_bf16((z - nv) / s);
+    const double rs = 1.0 / s;  // the four ratios below as products with 1 / s
+    f[0] = feat_bf16(m * rs);
+    f[1] = feat_bf16((z - nv) * rs);
     f[2] = fabs(z) > P.eps * sqrt(fabs(ni.z * nj.z)) ? kBf16One : (uint16_t)0;
     f[3] = i == j ? kBf16One : (uint16_t)0;
     f[4] = ni.f[0];
@@ -120,24 +159,33 @@ __device__ inline void entry_features(const MlpFeatParams &P, int64_t p, uint16_
     f[8] = ni.f[2];
     f[9] = nj.f[2];
     f[10] = feat_bf16(lval);
-    f[11] = feat_bf16(log1p(fabs(nv) / s));
-    f[12] = feat_bf16(log1p(fabs(z) / s));
+    f[11] = feat_bf16(log1p_pos(fabs(nv) * rs));
+    f[12] = feat_bf16(log1p_pos(fabs(z) * rs));
     f[13] = ni.f[3];
     f[14] = nj.f[3];
     f[15] = i < j ? ni.f[4] : nj.f[4];
 }
 
+// |L(max(i, j), min(i, j))| at u-index u (-1: diagonal, 0)
+__device__ inline double lval_at(const MlpFeatParams &P, int32_t u) { return u >= 0 ? fabs(P.Lu[u]) : 0.0; }
+
+__device__ inline void store_features(uint16_t *dst16, const uint16_t (&f)[NF]) {
+    uint4 *dst = reinterpret_cast<uint4 *>(dst16);
+    dst[0] = make_uint4(f[0] | (uint32_t)f[1] << 16, f[2] | (uint32_t)f[3] << 16, f[4] | (uint32_t)f[5] << 16,
+                        f[6] | (uint32_t)f[7] << 16);
+    dst[1] = make_uint4(f[8] | (uint32_t)f[9] << 16, f[10] | (uint32_t)f[11] << 16,
+                        f[12] | (uint32_t)f[13] << 16, f[14] | (uint32_t)f[15] << 16);
+}
+
 __global__ void k_features(MlpFeatParams P) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P.nnz) return;
+    const NodeRec *node = reinterpret_cast<const NodeRec *>(P.node);
+    const int32_t i = P.srow[p], j = P.col[p];
     uint16_t f[NF];
-    double m, sc;
-    entry_features(P, p, f, m, sc);
-    uint4 *out = reinterpret_cast<uint4 *>(P.F + p * NF);
-    out[0] = make_uint4(f[0] | (uint32_t)f[1] << 16, f[2] | (uint32_t)f[3] << 16, f[4] | (uint32_t)f[5] << 16,
-                        f[6] | (uint32_t)f[7] << 16);
-    out[1] = make_uint4(f[8] | (uint32_t)f[9] << 16, f[10] | (uint32_t)f[11] << 16,
-                        f[12] | (uint32_t)f[13] << 16, f[14] | (uint32_t)f[15] << 16);
+    double sc;
+    features_of(P, i, j, node[i], node[j], P.Z[p], P.N[p], P.M[p], lval_at(P, P.s2u[p]), f, sc);
+    store_features(P.F + p * NF, f);
     P.scale[p] = (float)sc;
 }
 
@@ -164,43 +212,74 @@ __global__ void k_mlp_pack(const float *__restrict__ theta, uint8_t *__restrict_
     if (t == 0) b3[0] = theta[M_B3];
 }
 
-// ---- forward (bfloat16 MFMA 16x16x32, float32 accumulation) ------------------
-// A wavefront handles 64 entries per tile as four 16-row blocks. Operand
-// layout of v_mfma_f32_16x16x32_bf16: lane l supplies row (A) / column (B)
-// l % 16 and the 8 consecutive k values 8 (l / 16) ..; the result holds
-// column l % 16 and rows 4 (l / 16) .. + 3. The weight fragments stay in
-// registers for the whole launch; the tile's features and the hidden
-// activations of one 16-row block go through LDS to reach the operand layout.
+// ---- forward (bfloat16 MFMA, float32 accumulation) -----------------------------
+// A wavefront handles 64 entries per tile as four blocks of 16. Each layer is
+// computed transposed, units x entries = W x X^T, so that its result is
+// already in the operand layout of the next layer. Operand layout of
+// v_mfma_f32_16x16x32_bf16: lane l supplies row l % 16 of A and column l % 16
+// of B with the 8 k values 8 (l / 16) ..; the result holds column l % 16 and
+// rows 4 (l / 16) .. + 3. The first layer (16 inputs) uses
+// v_mfma_f32_16x16x16_bf16, where lane l supplies the 4 k values 4 (l / 16) ..
+// Lane (col = l % 16, g = l / 16) therefore ends a layer with entry col and
+// units 16 nt + 4 g + r (nt, r = 0..3). The next layer's k slots are
+// numbered so that these are exactly the values the lane supplies: slot s of
+// k-block kb on lane group g is unit
+//   sigma(kb, g, s) = 16 (2 kb + s / 4) + 4 g + s % 4,
+// and the weights (A operand) are read in the same order. A sum over k does
+// not depend on how its slots are numbered, so the activations never leave
+// the registers. The last layer is an MFMA with w3 in every row of A. Biases
+// are the accumulators' initial values. Only the tile's features go through
+// LDS (lane = entry when computed, column layout for the first layer).
 
 __device__ inline bf16x8 load8(const uint16_t *p) {
     uint4 v = *reinterpret_cast<const uint4 *>(p);
     return __builtin_bit_cast(bf16x8, v);
 }
 
+// units 32 kb + 4 g .. + 3 and 32 kb + 16 + 4 g .. + 3 of a bf16 row
+__device__ inline bf16x8 load_sigma(const uint16_t *row, int kb, int g) {
+    const uint2 lo = *reinterpret_cast<const uint2 *>(row + 32 * kb + 4 * g);
+    const uint2 hi = *reinterpret_cast<const uint2 *>(row + 32 * kb + 16 + 4 * g);
+    return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+}
+
 struct MlpRegs {
-    bf16x8 w1[4];     // layer 1, unit nt * 16 + l % 16, inputs 8 (l / 16) ..
-    bf16x8 w2[4][2];  // layer 2, same unit, inputs 8 (l / 16) .. and 32 + 8 (l / 16) ..
-    float b1[4], b2[4], w3[4];
+    s16x4 w1[4];  // layer 1 (16x16x16 MFMA): unit 16 nt + col, inputs 4 g .. + 3
     float b3;
 };
 
-__device__ inline void load_mlp_regs(const uint8_t *W, int col, int g, MlpRegs &R) {
+// LDS tables of a workgroup: the biases b1, b2 (float32, 64 each; sb, read
+// per block as f32x4) and the layer-2 and layer-3 weight fragments (sw,
+// kMlpFragBytes), each lane's 16-byte fragment at ((f * 64) + lane) * 16 for
+// fragment f = 2 nt + kb of layer 2 and f = 8 + kb of layer 3, so that a
+// wavefront's read is one conflict-free 1 KiB row. Keeping them in LDS
+// rather than registers leaves the registers to the feature computation (4
+// wavefronts per SIMD without spills).
+constexpr int kMlpFragBytes = 10 * 64 * 16;
+
+// Layer-1 fragments into registers, the tables into LDS (filled by wavefront 0).
+__device__ inline void load_mlp_regs(const uint8_t *W, int col, int g, MlpRegs &R, float *sb, uint8_t *sw) {
     const uint16_t *w1 = reinterpret_cast<const uint16_t *>(W + OFF_W1);
     const uint16_t *w2 = reinterpret_cast<const uint16_t *>(W + OFF_W2);
     const uint16_t *w3 = reinterpret_cast<const uint16_t *>(W + OFF_W3);
-    const float *b1 = reinterpret_cast<const float *>(W + OFF_B1);
-    const float *b2 = reinterpret_cast<const float *>(W + OFF_B2);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int n = nt * 16 + col;
-        R.w1[nt] = load8(w1 + n * 32 + 8 * g);
-        R.w2[nt][0] = load8(w2 + n * NH + 8 * g);
-        R.w2[nt][1] = load8(w2 + n * NH + 32 + 8 * g);
-        R.b1[nt] = b1[n];
-        R.b2[nt] = b2[n];
-        R.w3[nt] = from_bf16(w3[n]);
+        R.w1[nt] = *reinterpret_cast<const s16x4 *>(w1 + n * 32 + 4 * g);
+        if (threadIdx.x < 64) {
+            *reinterpret_cast<bf16x8 *>(sw + ((nt * 2 + 0) * 64 + threadIdx.x) * 16) = load_sigma(w2 + n * NH, 0, g);
+            *reinterpret_cast<bf16x8 *>(sw + ((nt * 2 + 1) * 64 + threadIdx.x) * 16) = load_sigma(w2 + n * NH, 1, g);
+        }
+    }
+    if (threadIdx.x < 64) {
+        *reinterpret_cast<bf16x8 *>(sw + (8 * 64 + threadIdx.x) * 16) = load_sigma(w3, 0, g);
+        *reinterpret_cast<bf16x8 *>(sw + (9 * 64 + threadIdx.x) * 16) = load_sigma(w3, 1, g);
     }
     R.b3 = reinterpret_cast<const float *>(W + OFF_B3)[0];
+    // b1 then b2: OFF_B2 follows OFF_B1 directly
+    const float *b = reinterpret_cast<const float *>(W + OFF_B1);
+    for (int t = threadIdx.x; t < 2 * NH; t += blockDim.x) sb[t] = b[t];
+    __syncthreads();
 }
 
 __device__ inline void wave_sync() {
@@ -209,75 +288,75 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// max(x, 0) as one integer maximum of the bit pattern (a negative float is a
+// negative integer; -0 gives +0); a NaN with the sign bit clear passes through
+__device__ inline float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// ReLU and bfloat16 rounding of two 16 x 16 result blocks (units of blocks
+// 2 kb and 2 kb + 1), packed as the next layer's B operand for k-block kb
+__device__ inline bf16x8 relu_pack(const f32x4 &a, const f32x4 &b) {
+    uint16_t h[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        h[r] = to_bf16(relu(a[r]));
+        h[4 + r] = to_bf16(relu(b[r]));
+    }
+    const uint4 v = make_uint4(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16,
+                               h[4] | (uint32_t)h[5] << 16, h[6] | (uint32_t)h[7] << 16);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
 // y for the 64 feature rows in Fs (LDS, row-major 64 x 16 bfloat16) into ys
-// (LDS, 64 floats); H is LDS scratch of 16 x 64 bfloat16.
-__device__ inline void mlp_tile(const MlpRegs &R, const uint16_t *Fs, uint16_t *H, float *ys, int col, int g) {
+// (LDS, 64 floats).
+__device__ inline void mlp_tile(const MlpRegs &R, const float *sb, const uint8_t *sw, const uint16_t *Fs, float *ys,
+                                int col, int g) {
+    const int ln = col + 16 * g;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-        // layer 1: [16 x 32] x [32 x 64] (inputs 16..31 are zero)
-        bf16x8 a;
-        if (g < 2) {
-            a = load8(Fs + (mt * 16 + col) * NF + 8 * g);
-        } else {
-            uint4 zero = {0u, 0u, 0u, 0u};
-            a = __builtin_bit_cast(bf16x8, zero);
-        }
+        // layer 1: [64 x 16] x [16 x 16]
+        const s16x4 x = *reinterpret_cast<const s16x4 *>(Fs + (mt * 16 + col) * NF + 4 * g);
+        f32x4 h1[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, R.w1[nt], acc, 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float v = acc[r] + R.b1[nt];
-                H[(4 * g + r) * NH + nt * 16 + col] = to_bf16(v > 0.f ? v : 0.f);
-            }
+            const f32x4 b1 = *reinterpret_cast<const f32x4 *>(sb + 16 * nt + 4 * g);
+            h1[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w1[nt], x, b1, 0, 0, 0);
         }
-        wave_sync();
-        // layer 2: [16 x 64] x [64 x 64], then layer 3 as a dot product
-        float part[4] = {0.f, 0.f, 0.f, 0.f};
-        const bf16x8 a0 = load8(H + col * NH + 8 * g);
-        const bf16x8 a1 = load8(H + col * NH + 32 + 8 * g);
+        const bf16x8 x2[2] = {relu_pack(h1[0], h1[1]), relu_pack(h1[2], h1[3])};
+        // layer 2: [64 x 64] x [64 x 16]
+        f32x4 h2[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, R.w2[nt][0], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, R.w2[nt][1], acc, 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float v = acc[r] + R.b2[nt];
-                v = round_bf16(v > 0.f ? v : 0.f);
-                part[r] += v * R.w3[nt];
-            }
+            const f32x4 b2 = *reinterpret_cast<const f32x4 *>(sb + NH + 16 * nt + 4 * g);
+            const bf16x8 wa = *reinterpret_cast<const bf16x8 *>(sw + ((nt * 2 + 0) * 64 + ln) * 16);
+            const bf16x8 wb = *reinterpret_cast<const bf16x8 *>(sw + ((nt * 2 + 1) * 64 + ln) * 16);
+            h2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, x2[0], b2, 0, 0, 0);
+            h2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb, x2[1], h2[nt], 0, 0, 0);
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            float v = part[r];
-            v += __shfl_xor(v, 1, 64);
-            v += __shfl_xor(v, 2, 64);
-            v += __shfl_xor(v, 4, 64);
-            v += __shfl_xor(v, 8, 64);
-            part[r] = v;
-        }
-        if (col == 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) ys[mt * 16 + 4 * g + r] = part[r] + R.b3;
-        }
-        wave_sync();  // H is rewritten by the next block
+        const bf16x8 x3[2] = {relu_pack(h2[0], h2[1]), relu_pack(h2[2], h2[3])};
+        // layer 3: every row of A is w3, so every row of the result is y
+        f32x4 y = {0.f, 0.f, 0.f, 0.f};
+        const bf16x8 w3a = *reinterpret_cast<const bf16x8 *>(sw + (8 * 64 + ln) * 16);
+        const bf16x8 w3b = *reinterpret_cast<const bf16x8 *>(sw + (9 * 64 + ln) * 16);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3a, x3[0], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3b, x3[1], y, 0, 0, 0);
+        if (g == 0) ys[mt * 16 + col] = y[0] + R.b3;
     }
+    wave_sync();
 }
 
 constexpr int kFwdWaves = 4;
 
-__global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const uint8_t *__restrict__ W,
+__global__ __launch_bounds__(64 * kFwdWaves, 4) void k_mlp_forward(const uint8_t *__restrict__ W,
                                                                 const uint16_t *__restrict__ F, int64_t rows,
                                                                 float *__restrict__ y) {
     __shared__ __align__(16) uint16_t sF[kFwdWaves][64 * NF];
-    __shared__ __align__(16) uint16_t sH[kFwdWaves][16 * NH];
     __shared__ float sy[kFwdWaves][64];
+    __shared__ __align__(16) float sb[2 * NH];
+    __shared__ __align__(16) uint8_t sw[kMlpFragBytes];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
     MlpRegs R;
-    load_mlp_regs(W, col, g, R);
+    load_mlp_regs(W, col, g, R, sb, sw);
     const int64_t ntiles = (rows + 63) / 64;
     for (int64_t tile = (int64_t)blockIdx.x * kFwdWaves + w; tile < ntiles; tile += (int64_t)gridDim.x * kFwdWaves) {
         const int64_t row = tile * 64 + lane;
@@ -289,40 +368,70 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const uint8_t *_
         reinterpret_cast<uint4 *>(sF[w] + lane * NF)[0] = v0;
         reinterpret_cast<uint4 *>(sF[w] + lane * NF)[1] = v1;
         wave_sync();
-        mlp_tile(R, sF[w], sH[w], sy[w], col, g);
+        mlp_tile(R, sb, sw, sF[w], sy[w], col, g);
         if (row < rows) y[row] = sy[w][lane];
     }
 }
 
-// Features, network and correction in one pass: out = M + y s on S.
-__global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_correct(MlpFeatParams P, const uint8_t *__restrict__ W,
-                                                                double *out) {
+// Features, network and correction in one pass: out = M + y s on S. The
+// indices of the next tile (row, column, u-index) are loaded while the
+// current tile's gathers and network run, so a tile waits for one round of
+// memory accesses (node records, L value, Z, N, M) instead of two.
+__global__ __launch_bounds__(64 * kFwdWaves, 4) void k_mlp_correct(MlpFeatParams P, const uint8_t *__restrict__ W,
+                                                                   double *out) {
     __shared__ __align__(16) uint16_t sF[kFwdWaves][64 * NF];
-    __shared__ __align__(16) uint16_t sH[kFwdWaves][16 * NH];
     __shared__ float sy[kFwdWaves][64];
+    __shared__ __align__(16) float sb[2 * NH];
+    __shared__ __align__(16) uint8_t sw[kMlpFragBytes];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
     MlpRegs R;
-    load_mlp_regs(W, col, g, R);
+    load_mlp_regs(W, col, g, R, sb, sw);
+    const NodeRec *node = reinterpret_cast<const NodeRec *>(P.node);
     const int64_t ntiles = (P.nnz + 63) / 64;
-    for (int64_t tile = (int64_t)blockIdx.x * kFwdWaves + w; tile < ntiles; tile += (int64_t)gridDim.x * kFwdWaves) {
+    const int64_t stride = (int64_t)gridDim.x * kFwdWaves;
+    int64_t tile = (int64_t)blockIdx.x * kFwdWaves + w;
+    int32_t ci = 0, cj = 0, cu = -1;
+    {
         const int64_t p = tile * 64 + lane;
-        uint16_t f[NF];
-        double m = 0.0, sc = 1.0;
         if (p < P.nnz) {
-            entry_features(P, p, f, m, sc);
+            ci = P.srow[p];
+            cj = P.col[p];
+            cu = P.s2u[p];
+        }
+    }
+    for (; tile < ntiles; tile += stride) {
+        const int64_t p = tile * 64 + lane;
+        const bool valid = p < P.nnz;
+        NodeRec ni{}, nj{};
+        double z = 0.0, nv = 0.0, m = 0.0, lv = 0.0;
+        if (valid) {
+            ni = node[ci];
+            nj = node[cj];
+            lv = lval_at(P, cu);
+            z = P.Z[p];
+            nv = P.N[p];
+            m = P.M[p];
+        }
+        const int32_t i = ci, j = cj;
+        const int64_t pn = p + stride * 64;
+        if (pn < P.nnz) {
+            ci = P.srow[pn];
+            cj = P.col[pn];
+            cu = P.s2u[pn];
+        }
+        uint16_t f[NF];
+        double sc = 1.0;
+        if (valid) {
+            features_of(P, i, j, ni, nj, z, nv, m, lv, f, sc);
         } else {
 #pragma unroll
             for (int k = 0; k < NF; ++k) f[k] = 0;
         }
-        uint4 *dst = reinterpret_cast<uint4 *>(sF[w] + lane * NF);
-        dst[0] = make_uint4(f[0] | (uint32_t)f[1] << 16, f[2] | (uint32_t)f[3] << 16, f[4] | (uint32_t)f[5] << 16,
-                            f[6] | (uint32_t)f[7] << 16);
-        dst[1] = make_uint4(f[8] | (uint32_t)f[9] << 16, f[10] | (uint32_t)f[11] << 16,
-                            f[12] | (uint32_t)f[13] << 16, f[14] | (uint32_t)f[15] << 16);
+        store_features(sF[w] + lane * NF, f);
         wave_sync();
-        mlp_tile(R, sF[w], sH[w], sy[w], col, g);
-        if (p < P.nnz) out[p] = m + (double)sy[w][lane] * (double)(float)sc;
+        mlp_tile(R, sb, sw, sF[w], sy[w], col, g);
+        if (valid) out[p] = m + (double)sy[w][lane] * (double)(float)sc;
     }
 }
 
@@ -458,8 +567,11 @@ __global__ void k_mlp_apply(int64_t nnz, const double *__restrict__ M, const flo
 
 }  // namespace dev
 
-hipError_t launch_row_norms(int32_t n, const int64_t *Lp, const double *Lval, double *rn, hipStream_t st) {
-    hipLaunchKernelGGL(dev::k_row_norms, dim3((n + 255) / 256), dim3(256), 0, st, n, Lp, Lval, rn);
+hipError_t launch_factor_norms(int32_t n, const int64_t *Lp, const double *Lval, const int64_t *ustart,
+                              const double *Lu, double *rn, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::k_factor_norms, dim3((unsigned)(((int64_t)n * 16 + 255) / 256)), dim3(256), 0, st, n, Lp,
+                       Lval, ustart, Lu, rn);
     return hipGetLastError();
 }
 

@@ -649,6 +649,15 @@ hipError_t set_ninv_lds_limits() {
     return hipSuccess;
 }
 
+hipError_t launch_linv(const NinvParams &P, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_ninv_reset, dim3(1), dim3(64), 0, st, P);
+    constexpr int W = 4;
+    const int grid = dev::linv_grid<double, W>(P.n, 0);
+    hipLaunchKernelGGL((dev::k_linv_small<double, W>), dim3(grid), dim3(64 * W), 0, st, P);
+    hipLaunchKernelGGL((dev::k_linv_big<double>), dim3(256), dim3(256), dev::linv_big_lds<double>(), st, P);
+    return hipGetLastError();
+}
+
 hipError_t launch_ninv(const NinvParams &P, bool fp64, hipStream_t st, int linv_grid) {
     return fp64 ? dev::run_ninv<double>(P, st, linv_grid) : dev::run_ninv<float>(P, st, linv_grid);
 }
