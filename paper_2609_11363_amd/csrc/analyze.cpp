@@ -272,10 +272,17 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
         A.lvl_bytes_big[m].assign(A.n_levels, 0.0);
     }
     A.lvl_maxc_big.assign(A.n_levels, 0);
+    A.lvl_heavy.assign(A.n_levels, 0);
+    // small blocks with many hits first within their level
+    for (int32_t j : blocks)
+        if (bcols[j] <= kSmallCols && bhits[j] > kHeavyHits) {
+            A.sched_small[cs[A.level[j]]++] = j;
+            A.lvl_heavy[A.level[j]]++;
+        }
     for (int32_t j : blocks) {
         const bool small = bcols[j] <= kSmallCols;
         if (small) {
-            A.sched_small[cs[A.level[j]]++] = j;
+            if (bhits[j] <= kHeavyHits) A.sched_small[cs[A.level[j]]++] = j;
         } else {
             A.sched_big[cb[A.level[j]]++] = j;
             A.lvl_maxc_big[A.level[j]] = std::max(A.lvl_maxc_big[A.level[j]], bcols[j]);

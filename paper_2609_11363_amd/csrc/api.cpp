@@ -532,6 +532,7 @@ static asi_status selinv_launch(asi_handle h, const void *Lu, bool fp64, double 
     for (int32_t l = 0; l < A.n_levels; ++l) {
         P.meta = h->meta_small + A.lvl_small[l];
         P.nblk = A.lvl_small[l + 1] - A.lvl_small[l];
+        P.nheavy = A.lvl_heavy[l];
         if (P.nblk > 0) {
             Trace t(h, ASI_K_SELINV, A.lvl_bytes_small[m][l], st);
             e = asi::launch_selinv_level(P, false, fp64, st, asi::small_group_size(P.nblk));
@@ -539,6 +540,7 @@ static asi_status selinv_launch(asi_handle h, const void *Lu, bool fp64, double 
         }
         P.meta = h->meta_big + A.lvl_big[l];
         P.nblk = A.lvl_big[l + 1] - A.lvl_big[l];
+        P.nheavy = 0;
         if (P.nblk > 0) {
             Trace t(h, ASI_K_SELINV_BIG, A.lvl_bytes_big[m][l], st);
             e = asi::launch_selinv_level(P, true, fp64, st, A.lvl_maxc_big[l]);

@@ -75,6 +75,8 @@ struct Analysis {
     std::vector<BlockMeta> meta_small, meta_big;  // records of the schedules' slots
     std::vector<int32_t> lvl_small, lvl_big;  // n_levels+1 offsets into the schedules
     std::vector<int32_t> lvl_maxc_big;        // per level: largest |R_J| of its large blocks
+    std::vector<int32_t> lvl_heavy;           // per level: small blocks with more than kHeavyHits hits
+                                              // (placed first in the level's small schedule)
     int64_t gather_pairs = 0;
     int64_t gather_hits = 0;
     // algorithmic bytes of each level's launches, [0] float64 mode, [1] mixed
@@ -94,6 +96,11 @@ inline double selinv_block_bytes(int64_t c, int ncols, int64_t hits, bool fp64) 
 // enough lanes per block that the level keeps about 6144 wavefronts (256 CUs,
 // 24 resident wavefronts each) busy, from one wavefront up to a 512-thread
 // workgroup per block.
+// A small block with more hits than this takes more than two passes of a
+// wavefront (4 hits per lane per pass); in a level run one wavefront per
+// block such blocks get a whole 256-thread workgroup instead.
+constexpr int32_t kHeavyHits = 512;
+
 inline int small_group_size(int64_t nblk) {
     const int64_t waves = 6144;
     if (nblk * 2 > waves) return 64;

@@ -15,6 +15,7 @@ enum : int32_t { ST_SINGULAR = 3, ST_NONFINITE = 4, ST_POOL = 6, ST_LIMIT = 8, S
 struct SelinvParams {
     const BlockMeta *meta;  // records of this launch's blocks
     int32_t nblk;
+    int32_t nheavy;          // the first nheavy blocks have more than kHeavyHits hits
     const int64_t *ustart;   // n+1
     const int32_t *ucol;     // nnzU
     const int64_t *useg;     // nnzU

@@ -412,6 +412,32 @@ __global__ __launch_bounds__(64 * WAVES) void k_selinv_small(SelinvParams P) {
     selinv_block<T, 64, kSmallCols / 64, false>(P, M, S, lane_id(), nullptr);
 }
 
+// A level of many blocks whose first P.nheavy blocks have many hits: each of
+// those gets a 256-thread workgroup (a quarter of the passes over its hits),
+// the others a wavefront each, four per workgroup; the level no longer waits
+// on its longest hit lists walked by one wavefront.
+template <typename T>
+__global__ __launch_bounds__(256) void k_selinv_split(SelinvParams P) {
+    constexpr int W = 4;
+    __shared__ T sL0[W][kSmallCols], sL1[W][kSmallCols];
+    __shared__ T sY0[W][kSmallCols], sY1[W][kSmallCols];
+    __shared__ int64_t sSeg[W][kSmallCols];
+    __shared__ double red[4 * W];
+    const int32_t b = blockIdx.x;
+    if (b < P.nheavy) {
+        SelinvLds<T> S{sL0[0], sL1[0], sY0[0], sY1[0], sSeg[0]};
+        const BlockMeta M = P.meta[b];
+        selinv_block<T, 256, (kSmallCols + 255) / 256, false>(P, M, S, threadIdx.x, red);
+        return;
+    }
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int32_t bi = P.nheavy + (b - P.nheavy) * W + w;
+    if (bi >= P.nblk) return;  // the whole wavefront leaves; no workgroup barrier follows
+    SelinvLds<T> S{sL0[w], sL1[w], sY0[w], sY1[w], sSeg[w]};
+    const BlockMeta M = P.meta[bi];
+    selinv_block<T, 64, kSmallCols / 64, false>(P, M, S, lane_id(), nullptr);
+}
+
 // one workgroup of G threads per block (|R_J| <= kSmallCols), for levels with
 // few blocks
 template <typename T, int G>
@@ -539,7 +565,12 @@ static void launch_small_family(const SelinvParams &P, int group, hipStream_t st
     constexpr int W = 4;
     switch (group) {
         case 64:
-            hipLaunchKernelGGL((dev::k_selinv_small<T, W>), dim3((P.nblk + W - 1) / W), dim3(64 * W), 0, st, P);
+            if (P.nheavy > 0)
+                hipLaunchKernelGGL((dev::k_selinv_split<T>), dim3(P.nheavy + (P.nblk - P.nheavy + W - 1) / W),
+                                   dim3(64 * W), 0, st, P);
+            else
+                hipLaunchKernelGGL((dev::k_selinv_small<T, W>), dim3((P.nblk + W - 1) / W), dim3(64 * W), 0, st,
+                                   P);
             break;
         case 128:
             hipLaunchKernelGGL((dev::k_selinv_group<T, 128>), dim3(P.nblk), dim3(128), 0, st, P);
