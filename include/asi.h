@@ -165,9 +165,9 @@ asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, con
  * and val (float64), device arrays of the caller; col and val hold cap
  * entries. The call is synchronous: it sizes the result (*nnz, host), and if
  * it exceeds cap writes only rowptr and returns ASI_E_WORKSPACE, so a caller
- * may call with cap = 0 first. The L^inv columns and the rows of D^-1 L^inv
- * use the workspace's NInv pool, which must hold twice the series' entries
- * (ASI_E_WORKSPACE otherwise). Float64; repeatable bit for bit unless a
+ * may call with cap = 0 first. The L^inv columns and, after them, the rows of
+ * D^-1 L^inv use the workspace's NInv pool, which must hold the series'
+ * entries twice over (ASI_E_WORKSPACE otherwise). Float64; repeatable bit for bit unless a
  * series column needed the workgroup kernel of asi_ninv (then to rounding).
  * Factor pointers as for asi_selinv (all NULL: the loaded factor).
  */

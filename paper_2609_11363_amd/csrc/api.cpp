@@ -685,12 +685,6 @@ asi_status asi_ninv_full(asi_handle h, const double *L_val, const double *d_diag
     if (e != hipSuccess) return hip_fail(h, e, "ninv series");
     s = asi_sync(h);
     if (s != ASI_OK) return s;
-    unsigned long long used = 0;
-    e = hipMemcpy(&used, h->pool_top, 8, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(h, e, "read pool size");
-    // the rows of w go to the upper half of the pool's row and w regions
-    const int64_t half = h->pool_cap / 2;
-    if ((int64_t)used > half) return fail(h, ASI_E_WORKSPACE, "NInv pool too small for the full pattern: enlarge the workspace");
     asi::NfullParams P{};
     P.n = A.n;
     P.cstart = h->cstart;
@@ -700,8 +694,6 @@ asi_status asi_ninv_full(asi_handle h, const double *L_val, const double *d_diag
     P.pw = reinterpret_cast<double *>(h->pw);
     P.rpT = h->nf_rpT;
     P.cur = h->nf_cur;
-    P.colT = h->prow + half;
-    P.valT = reinterpret_cast<double *>(h->pw) + half;
     P.dN = h->nf_dN;
     P.drop = drop;
     P.bsum = h->nf_bsum;
@@ -714,7 +706,24 @@ asi_status asi_ninv_full(asi_handle h, const double *L_val, const double *d_diag
     P.status = h->status;
     {
         Trace t(h, ASI_K_NINV, 0.0);
-        e = asi::launch_nfull_prepare(P, h->stream);
+        e = asi::launch_nfull_count_w(P, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "ninv full pattern (rows of w)");
+    s = asi_sync(h);
+    if (s != ASI_OK) return s;
+    // the rows of w go after the pool's reserved entries of the row and w regions
+    unsigned long long used = 0;
+    int64_t total = 0;
+    e = hipMemcpy(&used, h->pool_top, 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&total, h->nf_rpT + A.n, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "read pool size");
+    if ((int64_t)used + total > h->pool_cap)
+        return fail(h, ASI_E_WORKSPACE, "NInv pool too small for the full pattern: enlarge the workspace");
+    P.colT = h->prow + used;
+    P.valT = reinterpret_cast<double *>(h->pw) + used;
+    {
+        Trace t(h, ASI_K_NINV, 0.0);
+        e = asi::launch_nfull_fill_w(P, h->stream);
         if (e == hipSuccess) e = asi::launch_nfull_rows(P, false, h->stream);
     }
     if (e != hipSuccess) return hip_fail(h, e, "ninv full pattern (count)");

@@ -181,7 +181,8 @@ struct MixFullParams {
 };
 
 hipError_t launch_linv(const NinvParams &P, hipStream_t st);  // float64 series columns into the pool
-hipError_t launch_nfull_prepare(const NfullParams &P, hipStream_t st);
+hipError_t launch_nfull_count_w(const NfullParams &P, hipStream_t st);  // pool sort, rows of w sized
+hipError_t launch_nfull_fill_w(const NfullParams &P, hipStream_t st);   // rows of w filled, diagonal of N
 hipError_t launch_nfull_rows(const NfullParams &P, bool fill, hipStream_t st);
 hipError_t launch_mixfull(const MixFullParams &P, bool fill, hipStream_t st);
 hipError_t set_nfull_lds_limits();

@@ -387,17 +387,24 @@ static hipError_t scan_counts(int64_t n, unsigned long long *a, unsigned long lo
     return hipGetLastError();
 }
 
-hipError_t launch_nfull_prepare(const NfullParams &P, hipStream_t st) {
+hipError_t launch_nfull_count_w(const NfullParams &P, hipStream_t st) {
     const int32_t n = P.n;
     const dim3 g((unsigned)((n + 255) / 256)), b(256);
     const dim3 g1((unsigned)((n + 1 + 255) / 256));
     hipLaunchKernelGGL(dev::k_pool_sort, g, b, 0, st, n, P.cstart, P.clen, P.prow, P.plinv, P.pw);
-    // rows of w: counts, row pointers, cursors, scatter, sort
+    // rows of w: counts and row pointers (rpT[n] = entries of the series)
     hipLaunchKernelGGL(dev::k_zero_u64, g1, b, 0, st, (int64_t)n + 1, reinterpret_cast<unsigned long long *>(P.rpT));
     hipLaunchKernelGGL(dev::k_wt_count, g, b, 0, st, n, P.cstart, P.clen, P.prow,
                        reinterpret_cast<unsigned long long *>(P.rpT));
     hipError_t e = scan_counts(n, reinterpret_cast<unsigned long long *>(P.rpT), P.bsum, st);
     if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_nfull_fill_w(const NfullParams &P, hipStream_t st) {
+    const int32_t n = P.n;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    const dim3 g1((unsigned)((n + 1 + 255) / 256));
     hipLaunchKernelGGL(dev::k_copy_u64, g1, b, 0, st, (int64_t)n + 1,
                        reinterpret_cast<const unsigned long long *>(P.rpT), P.cur);
     hipLaunchKernelGGL(dev::k_wt_fill, g, b, 0, st, n, P.cstart, P.clen, P.prow, P.pw, P.cur, P.colT, P.valT);
