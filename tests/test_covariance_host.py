@@ -30,6 +30,12 @@ def test_covariance_grid_matches_definition(N, alpha, beta):
 
 
 def test_covariance_grid_sizes():
+    import os
+    golden = os.path.join(os.path.dirname(__file__), "golden", "covariance_sizes.txt")
+    for line in open(golden):
+        if line.strip() and not line.startswith("#"):
+            N, n = (int(x) for x in line.split())
+            assert covariance_grid(N, 3.0, 4.0).shape == (n, n)
     A = covariance_grid(200)
     assert A.shape == (40000, 40000)
     counts = np.diff(A.indptr)
