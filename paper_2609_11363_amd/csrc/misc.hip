@@ -23,14 +23,36 @@ __global__ void k_zdiag(int32_t n, const int64_t *__restrict__ diagpos, const do
 
 // Mix (Section 2.3): keep Z where |Z_ij| > eps sqrt(|Z_ii Z_jj|), else N.
 // zdiag is a copy of Z's diagonal taken before this kernel so M may alias Z.
-__global__ void k_mix(int64_t nnz, const int32_t *__restrict__ srow, const int32_t *__restrict__ col,
-                      const double *__restrict__ zdiag, const double *Z, const double *N, double eps,
-                      double *M) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nnz) return;
-    double z = Z[p];
-    double thr = eps * sqrt(fabs(zdiag[srow[p]] * zdiag[col[p]]));
-    M[p] = fabs(z) > thr ? z : N[p];
+__device__ inline double mix_pick(double z, double n, double zi, double zj, double eps) {
+    return fabs(z) > eps * sqrt(fabs(zi * zj)) ? z : n;
+}
+
+__global__ __launch_bounds__(256) void k_mix1(int64_t nnz, const int32_t *__restrict__ srow,
+                                              const int32_t *__restrict__ col, const double *__restrict__ zdiag,
+                                              const double *Z, const double *N, double eps, double *M) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) M[p] = mix_pick(Z[p], N[p], zdiag[srow[p]], zdiag[col[p]], eps);
+}
+
+// two entries per thread with 8- and 16-byte accesses when Z, N and M are
+// 16-byte aligned (the index arrays are workspace regions); an odd tail
+// entry is done alone
+__global__ __launch_bounds__(256) void k_mix(int64_t nnz, const int32_t *__restrict__ srow,
+                                             const int32_t *__restrict__ col, const double *__restrict__ zdiag,
+                                             const double *Z, const double *N, double eps, double *M) {
+    const int64_t p = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (p + 1 < nnz) {
+        const int2 r = *reinterpret_cast<const int2 *>(srow + p);
+        const int2 c = *reinterpret_cast<const int2 *>(col + p);
+        const double2 z = *reinterpret_cast<const double2 *>(Z + p);
+        const double2 n = *reinterpret_cast<const double2 *>(N + p);
+        double2 m;
+        m.x = mix_pick(z.x, n.x, zdiag[r.x], zdiag[c.x], eps);
+        m.y = mix_pick(z.y, n.y, zdiag[r.y], zdiag[c.y], eps);
+        *reinterpret_cast<double2 *>(M + p) = m;
+    } else if (p < nnz) {
+        M[p] = mix_pick(Z[p], N[p], zdiag[srow[p]], zdiag[col[p]], eps);
+    }
 }
 
 // Rank-k correction on S (Section 2.5): out_ij = in_ij + sum_m lam_m V_im V_jm.
@@ -593,8 +615,15 @@ hipError_t launch_zdiag(int32_t n, const int64_t *diagpos, const double *X, doub
 
 hipError_t launch_mix(int64_t nnz, const int32_t *srow, const int32_t *col, const double *zdiag,
                       const double *Z, const double *N, double eps, double *M, hipStream_t st) {
-    hipLaunchKernelGGL(dev::k_mix, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, nnz, srow, col,
-                       zdiag, Z, N, eps, M);
+    if (nnz <= 0) return hipSuccess;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(Z) | reinterpret_cast<uintptr_t>(N) |
+                           reinterpret_cast<uintptr_t>(M)) & 15) == 0;
+    if (aligned)
+        hipLaunchKernelGGL(dev::k_mix, dim3((unsigned)((nnz + 511) / 512)), dim3(256), 0, st, nnz, srow, col, zdiag,
+                           Z, N, eps, M);
+    else
+        hipLaunchKernelGGL(dev::k_mix1, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, nnz, srow, col,
+                           zdiag, Z, N, eps, M);
     return hipGetLastError();
 }
 
