@@ -940,6 +940,18 @@ def run_covariance(args):
     t_eig = time.time() - t0
     log(f"spectral check: {t_eig:.1f}s, {napp} applications, |lam| {np.abs(lam)}, "
         f"k_acc={len(corr.kept)} of {k}, err_1 {corr.err1_before:.3e} -> {corr.err1_after:.3e}")
+    # the same eigen step with E applied on the device: A^-1 x by conjugate
+    # gradients preconditioned with the incomplete factor, X x on S
+    from paper_2609_11363_amd.spectral import device_error_operator
+    s.load_factor(Lv, dd, ds)
+    apply_E, est = device_error_operator(s, Ar, Ac, Av, perm, R, tol=1e-12)
+    t0 = time.time()
+    lam_d, V_d, res_d, napp_d = inverse_error_eigenpairs(None, X, k, tol=1e-8, seed=0, apply_E=apply_E)
+    t_eig_dev = time.time() - t0
+    sub = float(np.linalg.svd(V_d.T @ V, compute_uv=False).min())
+    log(f"spectral check with device solves: {t_eig_dev:.1f}s, {napp_d} applications, "
+        f"{est['cg_steps'] / max(est['applications'], 1):.1f} CG steps each, |lam| {np.abs(lam_d)}, "
+        f"eigenvalues vs host {np.abs(lam_d - lam).max():.1e}, subspace cosine {sub:.9f}")
 
     for _ in range(args.warmup):
         step()
@@ -1003,7 +1015,12 @@ def run_covariance(args):
         "trace_reference": tr_ref,
         "spectral_check": {"k": k, "k_acc": len(corr.kept), "lambda": [float(x) for x in lam],
                            "eig_residual_max": float(res.max()), "host_s": t_eig,
-                           "err1_before": corr.err1_before, "err1_after": corr.err1_after},
+                           "err1_before": corr.err1_before, "err1_after": corr.err1_after,
+                           "device_solves": {"s": t_eig_dev, "applications": napp_d,
+                                             "cg_steps_per_application": est["cg_steps"] / max(est["applications"], 1),
+                                             "max_cg_relres": est["max_relres"],
+                                             "eigenvalue_diff_vs_host": float(np.abs(lam_d - lam).max()),
+                                             "subspace_cosine_vs_host": sub}},
         "profile_ms_per_step": {kk: v[1] / 3 for kk, v in prof.items() if v[0]},
         "roofline": {"kernel": "SPAI (k_spai_staged<1, 4> + k_spai_staged<2, 2> + k_symmetrize, one call)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

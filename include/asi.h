@@ -309,6 +309,42 @@ asi_status asi_diag_err1(asi_handle h, const double *d_ref, const double *d_hat,
 asi_status asi_trace(asi_handle h, const double *X_S, int32_t k, const double *V, const double *lambda,
                      double *sums);
 
+/*
+ * Operator applications of the eigen step of the spectral correction
+ * (Section 2.5: E x = A^-1 x - X x is applied matrix-free, A^-1 x by a Krylov
+ * method preconditioned with the incomplete block factorization; conjugate
+ * gradients in the positive definite case). All vectors are float64 device
+ * arrays of length n in the factor ordering; asynchronous on the handle's
+ * stream unless stated.
+ *
+ * asi_spmv: y = X x for X on S (|S| values, S's CSR order). x and y must
+ * not alias.
+ */
+asi_status asi_spmv(asi_handle h, const double *X_S, const double *x, double *y);
+
+/*
+ * asi_ldl_solve: y = (L D L^T)^-1 x with the factor of asi_load_factor
+ * (ASI_E_STATE if none is loaded): forward substitution with the unit lower
+ * L, the D-block inverses, backward substitution with L^T, level by level of
+ * the SelInv schedule. y may alias x. Needs |S| < 2^31.
+ */
+asi_status asi_ldl_solve(asi_handle h, const double *x, double *y);
+
+/*
+ * asi_pcg: x = Ah^-1 b by conjugate gradients on Ah = P^T A P (A: the
+ * caller's CSR in its own ordering, int64 row pointers, int32 columns,
+ * float64 values; perm: n int32 with Ah(i, j) = A(perm[i], perm[j]))
+ * preconditioned with the loaded factor (L D L^T)^-1, from x = 0, until
+ * ||b - Ah x||_2 <= tol ||b||_2 or maxit steps. For symmetric positive
+ * definite A and a positive D. Synchronous (reads one residual norm per
+ * step); *iters and *relres (host, nullable) receive the steps taken and the
+ * final relative residual. ASI_E_NONFINITE on a breakdown. Uses the
+ * workspace's CG vectors, so calls on one handle must not overlap.
+ */
+asi_status asi_pcg(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                   const int32_t *perm, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,
+                   double *relres);
+
 /* Wait for the handle's stream; return the first device-side error latched
  * since the previous asi_sync (and clear it). */
 asi_status asi_sync(asi_handle h);

@@ -226,6 +226,27 @@ def mix_full(S: Pattern, Z: np.ndarray, Nfull, eps: float):
             np.array([out[k] for k in keys], dtype=np.float64))
 
 
+def spmv(S: Pattern, X: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """y = X x for X on S (Section 2.5: the second term of E x)."""
+    return S.to_csr(X) @ np.asarray(x, dtype=np.float64)
+
+
+def unit_lower(F) -> sp.csr_matrix:
+    """L with its unit diagonal (the factor stores the strictly lower part)."""
+    L = sp.csr_matrix(F.L_csr())
+    return (L + sp.identity(F.n, format="csr")).tocsr()
+
+
+def ldl_solve(F, x: np.ndarray) -> np.ndarray:
+    """y = (L D L^T)^-1 x: the incomplete factorization as a preconditioner
+    (Section 2.5), by two triangular solves around the D-block inverses."""
+    from scipy.sparse.linalg import spsolve_triangular
+    L = unit_lower(F)
+    z = spsolve_triangular(L, np.asarray(x, dtype=np.float64), lower=True, unit_diagonal=True)
+    w = dinv_matrix(F) @ z
+    return spsolve_triangular(sp.csr_matrix(L.T), w, lower=False, unit_diagonal=True)
+
+
 def mix(S: Pattern, Z: np.ndarray, N: np.ndarray, eps: float) -> np.ndarray:
     """Mix (Section 2.3): Z where |Z_ij| > eps sqrt(|Z_ii Z_jj|), else N."""
     lib = _load()

@@ -49,6 +49,7 @@ struct asi_handle_s {
     unsigned long long *nf_cur = nullptr;
     double *nf_dN = nullptr;
     unsigned long long *nf_bsum = nullptr;
+    double *cg = nullptr;  // CG work vectors (4 n), dot partials (1024), scalars (16)
     double *rn = nullptr;         // ||L(i, :)||_2, then ||L(:, i)||_2, of the factor in Lu (set with it)
     int64_t *rowptr_L = nullptr;  // the input L's row pointers
     float *Lf = nullptr;          // float32 copy of the loaded factor's L (mixed precision)
@@ -174,6 +175,7 @@ Layout make_layout(const asi::Analysis &A) {
     L.add((n + 1) * 8);                 // 38   their fill cursors
     L.add(n * 8);                       // 39   diagonal of N
     L.add((n / 1024 + 2) * 8);          // 40   scan block sums
+    L.add((4 * n + 1024 + 16) * 8);     // 41 preconditioned CG: r, z, p, q, dot partials, scalars
     return L;
 }
 
@@ -351,6 +353,7 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->nf_cur = at<unsigned long long>(b, L.off[38]);
     h->nf_dN = at<double>(b, L.off[39]);
     h->nf_bsum = at<unsigned long long>(b, L.off[40]);
+    h->cg = at<double>(b, L.off[41]);
     h->factor_loaded = false;
     h->lf_loaded = false;
     h->epoch = 0;
@@ -1065,6 +1068,120 @@ asi_status asi_trace(asi_handle h, const double *X_S, int32_t k, const double *V
     hipError_t e = asi::launch_trace(h->A.n, h->diagpos, X_S, k, V, lambda, h->red, sums, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "trace");
     return ASI_OK;
+}
+
+static asi::LdlSolveParams ldl_params(asi_handle h) {
+    const asi::Analysis &A = h->A;
+    asi::LdlSolveParams P{};
+    P.n = A.n;
+    P.n_levels = A.n_levels;
+    P.lvl_small = A.lvl_small.data();
+    P.lvl_big = A.lvl_big.data();
+    P.meta_small = h->meta_small;
+    P.meta_big = h->meta_big;
+    P.rowptr = h->rowptr;
+    P.diagpos = h->diagpos;
+    P.col = h->col;
+    P.s2u = h->s2u;
+    P.Lu = reinterpret_cast<const double *>(h->Lu);
+    P.piv = h->piv;
+    P.dinv = h->dinv;
+    return P;
+}
+
+asi_status asi_spmv(asi_handle h, const double *X_S, const double *x, double *y) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!X_S || !x || !y) return fail(h, ASI_E_ARG, "null pointer");
+    if (x == y) return fail(h, ASI_E_ARG, "x and y must not alias");
+    DeviceGuard g(h->device);
+    Trace t(h, ASI_K_DIAG, 12.0 * h->A.nnzS + 16.0 * h->A.n);
+    hipError_t e = asi::launch_spmv_s(h->A.n, h->rowptr, h->col, X_S, x, y, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "spmv");
+    return ASI_OK;
+}
+
+asi_status asi_ldl_solve(asi_handle h, const double *x, double *y) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!x || !y) return fail(h, ASI_E_ARG, "null pointer");
+    if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor loaded (asi_load_factor)");
+    if (h->A.s2u.empty() && h->A.nnzS > 0) return fail(h, ASI_E_UNSUPPORTED, "solves need |S| < 2^31");
+    DeviceGuard g(h->device);
+    Trace t(h, ASI_K_DIAG, 24.0 * h->A.nnzS + 40.0 * h->A.n);
+    hipError_t e = asi::launch_ldl_solve(ldl_params(h), x, y, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "ldl solve");
+    return ASI_OK;
+}
+
+asi_status asi_pcg(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                   const int32_t *perm, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,
+                   double *relres) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!A_rowptr || !A_col || !A_val || !perm || !b || !x) return fail(h, ASI_E_ARG, "null pointer");
+    if (!(tol > 0.0) || maxit < 0) return fail(h, ASI_E_ARG, "tol must be > 0 and maxit >= 0");
+    if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor loaded (asi_load_factor)");
+    if (h->A.s2u.empty() && h->A.nnzS > 0) return fail(h, ASI_E_UNSUPPORTED, "solves need |S| < 2^31");
+    DeviceGuard g(h->device);
+    const int32_t n = h->A.n;
+    const int64_t nn = n;
+    double *r = h->cg, *z = r + nn, *p = z + nn, *q = p + nn, *part = q + nn, *sc = part + 1024;
+    double *rz = sc, *rzn = sc + 1, *pq = sc + 2, *rr = sc + 3, *bb = sc + 4;
+    const asi::LdlSolveParams L = ldl_params(h);
+    hipStream_t st = h->stream;
+    int32_t it = 0;
+    double res = 0.0;
+    hipError_t e;
+    {
+        Trace t(h, ASI_K_DIAG, 0.0);
+        e = asi::launch_iperm(n, perm, h->iperm, h->status, st);
+        if (e == hipSuccess) e = asi::launch_fill_f64(nn, 0.0, x, st);
+        if (e == hipSuccess) e = asi::launch_copy_f64(nn, b, r, st);
+        if (e == hipSuccess) e = asi::launch_dot(nn, b, b, part, bb, st);
+        if (e == hipSuccess) e = asi::launch_ldl_solve(L, r, z, st);
+        if (e == hipSuccess) e = asi::launch_copy_f64(nn, z, p, st);
+        if (e == hipSuccess) e = asi::launch_dot(nn, r, z, part, rz, st);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "pcg setup");
+    double bnorm2 = 0.0;
+    e = hipMemcpyAsync(&bnorm2, bb, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(h, e, "pcg norm");
+    if (bnorm2 == 0.0) {
+        if (iters) *iters = 0;
+        if (relres) *relres = 0.0;
+        return asi_sync(h);
+    }
+    for (it = 1; it <= maxit; ++it) {
+        {
+            Trace t(h, ASI_K_DIAG, 0.0);
+            e = asi::launch_spmv_ahat(n, A_rowptr, A_col, A_val, perm, h->iperm, p, q, st);
+            if (e == hipSuccess) e = asi::launch_dot(nn, p, q, part, pq, st);
+            if (e == hipSuccess) e = asi::launch_axpy_ratio(nn, rz, pq, 1.0, p, x, st);
+            if (e == hipSuccess) e = asi::launch_axpy_ratio(nn, rz, pq, -1.0, q, r, st);
+            if (e == hipSuccess) e = asi::launch_dot(nn, r, r, part, rr, st);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "pcg step");
+        double rnorm2 = 0.0;
+        e = hipMemcpyAsync(&rnorm2, rr, 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(h, e, "pcg residual");
+        res = std::sqrt(rnorm2 / bnorm2);
+        if (!(res == res)) return fail(h, ASI_E_NONFINITE, "pcg breakdown (non-finite residual)");
+        if (res <= tol) break;
+        {
+            Trace t(h, ASI_K_DIAG, 0.0);
+            e = asi::launch_ldl_solve(L, r, z, st);
+            if (e == hipSuccess) e = asi::launch_dot(nn, r, z, part, rzn, st);
+            if (e == hipSuccess) e = asi::launch_xpby_ratio(nn, z, rzn, rz, p, st);
+            if (e == hipSuccess) e = asi::launch_copy_f64(1, rzn, rz, st);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "pcg preconditioner");
+    }
+    if (iters) *iters = std::min(it, maxit);
+    if (relres) *relres = res;
+    return asi_sync(h);
 }
 
 asi_status asi_sync(asi_handle h) {

@@ -187,6 +187,32 @@ hipError_t launch_nfull_rows(const NfullParams &P, bool fill, hipStream_t st);
 hipError_t launch_mixfull(const MixFullParams &P, bool fill, hipStream_t st);
 hipError_t set_nfull_lds_limits();
 
+// Operator applications of the eigen step (y = X x on S, y = Ah x, LDL^T solves)
+struct LdlSolveParams {
+    int32_t n, n_levels;
+    const int32_t *lvl_small, *lvl_big;  // host: per-level offsets into the block records
+    const BlockMeta *meta_small, *meta_big;
+    const int64_t *rowptr, *diagpos;
+    const int32_t *col, *s2u;
+    const double *Lu;  // float64 L in u-space
+    const int8_t *piv;
+    const double *dinv;
+};
+hipError_t launch_spmv_s(int32_t n, const int64_t *rowptr, const int32_t *col, const double *X, const double *x,
+                         double *y, hipStream_t st);
+hipError_t launch_spmv_ahat(int32_t n, const int64_t *Ap, const int32_t *Aj, const double *Av, const int32_t *perm,
+                            const int32_t *iperm, const double *x, double *y, hipStream_t st);
+hipError_t launch_iperm(int32_t n, const int32_t *perm, int32_t *iperm, int32_t *status, hipStream_t st);
+hipError_t launch_ldl_solve(const LdlSolveParams &P, const double *x, double *v, hipStream_t st);
+int dot_blocks(int64_t n);
+hipError_t launch_dot(int64_t n, const double *a, const double *b, double *part, double *out, hipStream_t st);
+hipError_t launch_axpy_ratio(int64_t n, const double *num, const double *den, double sign, const double *x, double *y,
+                             hipStream_t st);
+hipError_t launch_xpby_ratio(int64_t n, const double *z, const double *num, const double *den, double *p,
+                             hipStream_t st);
+hipError_t launch_copy_f64(int64_t n, const double *a, double *b, hipStream_t st);
+hipError_t launch_fill_f64(int64_t n, double v, double *a, hipStream_t st);
+
 hipError_t launch_node_feats(const MlpFeatParams &P, hipStream_t st);
 hipError_t launch_factor_norms(int32_t n, const int64_t *Lp, const double *Lval, const int64_t *ustart,
                               const double *Lu, double *rn, hipStream_t st);

@@ -1,0 +1,248 @@
+// Operator applications for the eigen step of the spectral correction
+// (Section 2.5, Algorithm 1: the eigenpairs of A^-1 - X need products with X
+// and solves with A, preconditioned by the incomplete factor):
+//   y = X x for X on S (both triangles),
+//   y = Ah x for Ah = P^T A P (A in its own ordering, perm),
+//   y = (L D L^T)^-1 x with the loaded factor, by the level schedule of the
+//   SelInv sweep: the rows of a level depend only on rows of other levels,
+//   forward substitution runs the levels last to first, backward first to
+//   last, each row a gather over its part of S (its L values in u-space);
+// and the vector kernels of a preconditioned CG on Ah.
+// Every sum has a fixed order (segment lanes, then a fixed shuffle tree, and
+// fixed-order two-stage reductions), so the results repeat bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace asi {
+namespace dev {
+
+namespace {
+constexpr int kSeg = 16;  // lanes per row
+
+__device__ inline double seg_sum(double v) {
+#pragma unroll
+    for (int o = kSeg / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+}  // namespace
+
+// y = X x on S, kSeg lanes per row
+__global__ __launch_bounds__(256) void k_spmv_s(int32_t n, const int64_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ col, const double *__restrict__ X,
+                                                const double *__restrict__ x, double *__restrict__ y) {
+    const int32_t i = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
+    const int sub = threadIdx.x % kSeg;
+    double s = 0.0;
+    if (i < n)
+        for (int64_t p = rowptr[i] + sub; p < rowptr[i + 1]; p += kSeg) s += X[p] * x[col[p]];
+    s = seg_sum(s);
+    if (i < n && sub == 0) y[i] = s;
+}
+
+// y = Ah x, Ah(i, j) = A(perm[i], perm[j]); iperm maps A's columns back
+__global__ __launch_bounds__(256) void k_spmv_ahat(int32_t n, const int64_t *__restrict__ Ap,
+                                                   const int32_t *__restrict__ Aj, const double *__restrict__ Av,
+                                                   const int32_t *__restrict__ perm,
+                                                   const int32_t *__restrict__ iperm, const double *__restrict__ x,
+                                                   double *__restrict__ y) {
+    const int32_t i = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
+    const int sub = threadIdx.x % kSeg;
+    double s = 0.0;
+    if (i < n) {
+        const int32_t r = perm[i];
+        for (int64_t p = Ap[r] + sub; p < Ap[r + 1]; p += kSeg) s += Av[p] * x[iperm[Aj[p]]];
+    }
+    s = seg_sum(s);
+    if (i < n && sub == 0) y[i] = s;
+}
+
+// One level of the forward (FWD) or backward substitution, in place on v,
+// kSeg lanes per block (both rows of a 2x2 block in turn). Forward: row i
+// subtracts L(i, c) v_c over the lower part of row i of S; backward: row k
+// subtracts L(r, k) v_r over its upper part. The 2x2 partner entry (an
+// explicit zero of L, in the same level) is skipped.
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_ldl_level(const BlockMeta *__restrict__ ma, int32_t na,
+                                                   const BlockMeta *__restrict__ mb, int32_t nb,
+                                                   const int64_t *__restrict__ rowptr,
+                                                   const int64_t *__restrict__ diagpos,
+                                                   const int32_t *__restrict__ col, const int32_t *__restrict__ s2u,
+                                                   const double *__restrict__ Lu, double *__restrict__ v) {
+    const int32_t b = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
+    const int sub = threadIdx.x % kSeg;
+    if (b >= na + nb) return;  // the segment's lanes leave together
+    const BlockMeta &M = b < na ? ma[b] : mb[b - na];
+    const int rows = M.two ? 2 : 1;
+    for (int t = 0; t < rows; ++t) {
+        const int32_t i = M.j + t;
+        const int32_t partner = M.two ? M.j + 1 - t : -1;
+        const int64_t p0 = FWD ? rowptr[i] : diagpos[i] + 1;
+        const int64_t p1 = FWD ? diagpos[i] : rowptr[i + 1];
+        double s = 0.0;
+        for (int64_t p = p0 + sub; p < p1; p += kSeg) {
+            const int32_t c = col[p];
+            if (c != partner) s += Lu[s2u[p]] * v[c];
+        }
+        s = seg_sum(s);
+        if (sub == 0) v[i] -= s;
+    }
+}
+
+// v = D^-1 v (1x1 and 2x2 blocks, inverses from the D-block kernel)
+__global__ void k_ldl_diag(int32_t n, const int8_t *__restrict__ piv, const double *__restrict__ dinv,
+                           double *__restrict__ v) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n || piv[j] == 2) return;  // the second row of a 2x2 block is done with its first
+    const double *iv = dinv + 3 * (int64_t)j;
+    if (piv[j] == 1) {
+        const double a = v[j], b = v[j + 1];
+        v[j] = iv[0] * a + iv[1] * b;
+        v[j + 1] = iv[1] * a + iv[2] * b;
+    } else {
+        v[j] = iv[0] * v[j];
+    }
+}
+
+// fixed-order dot products: per block of 256 entries, then one block
+__global__ __launch_bounds__(256) void k_dot_part(int64_t n, const double *__restrict__ a,
+                                                  const double *__restrict__ b, double *__restrict__ part) {
+    __shared__ double s[4];
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) v += a[i] * b[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+__global__ __launch_bounds__(256) void k_dot_final(int nb, const double *__restrict__ part, double *__restrict__ out) {
+    __shared__ double s[4];
+    double v = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) v += part[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// y += a x (a read from device memory: *a_num / *a_den, times sign)
+__global__ void k_axpy_ratio(int64_t n, const double *__restrict__ num, const double *__restrict__ den, double sign,
+                             const double *__restrict__ x, double *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += sign * (*num / *den) * x[i];
+}
+
+// p = z + (num / den) p
+__global__ void k_xpby_ratio(int64_t n, const double *__restrict__ z, const double *__restrict__ num,
+                             const double *__restrict__ den, double *__restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = z[i] + (*num / *den) * p[i];
+}
+
+__global__ void k_copy_f64(int64_t n, const double *__restrict__ a, double *__restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+__global__ void k_fill_f64(int64_t n, double v, double *__restrict__ a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ void k_iperm_only(int32_t n, const int32_t *__restrict__ perm, int32_t *__restrict__ iperm,
+                             int32_t *status) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t p = perm[i];
+    if (p < 0 || p >= n) {
+        atomicCAS(status, 0, ST_LIMIT);
+        return;
+    }
+    iperm[p] = i;
+}
+
+}  // namespace dev
+
+static dim3 seg_grid(int64_t rows) { return dim3((unsigned)((rows * dev::kSeg + 255) / 256)); }
+static dim3 elem_grid(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+hipError_t launch_spmv_s(int32_t n, const int64_t *rowptr, const int32_t *col, const double *X, const double *x,
+                         double *y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::k_spmv_s, seg_grid(n), dim3(256), 0, st, n, rowptr, col, X, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_ahat(int32_t n, const int64_t *Ap, const int32_t *Aj, const double *Av, const int32_t *perm,
+                            const int32_t *iperm, const double *x, double *y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::k_spmv_ahat, seg_grid(n), dim3(256), 0, st, n, Ap, Aj, Av, perm, iperm, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_iperm(int32_t n, const int32_t *perm, int32_t *iperm, int32_t *status, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::k_iperm_only, elem_grid(n), dim3(256), 0, st, n, perm, iperm, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_ldl_solve(const LdlSolveParams &P, const double *x, double *v, hipStream_t st) {
+    const int32_t n = P.n;
+    if (n <= 0) return hipSuccess;
+    if (x != v) hipLaunchKernelGGL(dev::k_copy_f64, elem_grid(n), dim3(256), 0, st, (int64_t)n, x, v);
+    // forward: levels last to first (a row's lower entries belong to blocks of higher levels)
+    for (int32_t l = P.n_levels - 1; l >= 0; --l) {
+        const int32_t na = P.lvl_small[l + 1] - P.lvl_small[l], nb = P.lvl_big[l + 1] - P.lvl_big[l];
+        if (na + nb == 0) continue;
+        hipLaunchKernelGGL(dev::k_ldl_level<true>, seg_grid(na + nb), dim3(256), 0, st, P.meta_small + P.lvl_small[l],
+                           na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos, P.col, P.s2u, P.Lu, v);
+    }
+    hipLaunchKernelGGL(dev::k_ldl_diag, elem_grid(n), dim3(256), 0, st, n, P.piv, P.dinv, v);
+    for (int32_t l = 0; l < P.n_levels; ++l) {
+        const int32_t na = P.lvl_small[l + 1] - P.lvl_small[l], nb = P.lvl_big[l + 1] - P.lvl_big[l];
+        if (na + nb == 0) continue;
+        hipLaunchKernelGGL(dev::k_ldl_level<false>, seg_grid(na + nb), dim3(256), 0, st,
+                           P.meta_small + P.lvl_small[l], na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos,
+                           P.col, P.s2u, P.Lu, v);
+    }
+    return hipGetLastError();
+}
+
+int dot_blocks(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256)); }
+
+hipError_t launch_dot(int64_t n, const double *a, const double *b, double *part, double *out, hipStream_t st) {
+    const int nb = dot_blocks(n);
+    hipLaunchKernelGGL(dev::k_dot_part, dim3(nb), dim3(256), 0, st, n, a, b, part);
+    hipLaunchKernelGGL(dev::k_dot_final, dim3(1), dim3(256), 0, st, nb, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_ratio(int64_t n, const double *num, const double *den, double sign, const double *x, double *y,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_axpy_ratio, elem_grid(n), dim3(256), 0, st, n, num, den, sign, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_xpby_ratio(int64_t n, const double *z, const double *num, const double *den, double *p,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_xpby_ratio, elem_grid(n), dim3(256), 0, st, n, z, num, den, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(int64_t n, const double *a, double *b, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_copy_f64, elem_grid(n), dim3(256), 0, st, n, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(int64_t n, double v, double *a, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_fill_f64, elem_grid(n), dim3(256), 0, st, n, v, a);
+    return hipGetLastError();
+}
+
+}  // namespace asi

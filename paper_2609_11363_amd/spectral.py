@@ -16,12 +16,14 @@ import numpy as np
 
 
 def inverse_error_eigenpairs(apply_inv, X_csr, k: int, tol: float = 1e-8, seed: int = 0,
-                             ncv: int | None = None, maxiter: int | None = None):
+                             ncv: int | None = None, maxiter: int | None = None, apply_E=None):
     """k eigenpairs of E = A^-1 - X of largest |lambda| (Section 2.5).
 
-    apply_inv(x) returns A^-1 x (float64, same ordering as X_csr). Returns
-    (lam [k], V [n, k] orthonormal columns, ordered by decreasing |lam|,
-    relative residuals ||E v - lam v|| / |lam|, number of applications of E).
+    apply_inv(x) returns A^-1 x (float64, same ordering as X_csr); or
+    apply_E(x) returns E x directly (then apply_inv and X_csr are not used
+    for products, X_csr only gives n). Returns (lam [k], V [n, k]
+    orthonormal columns, ordered by decreasing |lam|, relative residuals
+    ||E v - lam v|| / |lam|, number of applications of E).
     """
     from scipy.sparse.linalg import LinearOperator, eigsh
     n = X_csr.shape[0]
@@ -30,6 +32,8 @@ def inverse_error_eigenpairs(apply_inv, X_csr, k: int, tol: float = 1e-8, seed: 
     def mv(x):
         count[0] += 1
         x = np.asarray(x, dtype=np.float64).ravel()
+        if apply_E is not None:
+            return apply_E(x)
         return apply_inv(x) - X_csr @ x
 
     op = LinearOperator((n, n), matvec=mv, dtype=np.float64)
@@ -40,6 +44,29 @@ def inverse_error_eigenpairs(apply_inv, X_csr, k: int, tol: float = 1e-8, seed: 
     V = np.ascontiguousarray(V[:, order])
     res = np.array([np.linalg.norm(mv(V[:, m]) - lam[m] * V[:, m]) / abs(lam[m]) for m in range(k)])
     return lam, V, res, count[0]
+
+
+def device_error_operator(solver, A_rowptr, A_col, A_val, perm, X_S, tol: float = 1e-12, maxit: int = 1000):
+    """E x = A^-1 x - X x with both terms on the device (Section 2.5): A^-1 x
+    by conjugate gradients on P^T A P preconditioned with the loaded
+    incomplete factor (asi_pcg; A symmetric positive definite), X x on S
+    (asi_spmv). Returns (apply_E(x) for host float64 vectors, statistics
+    dict with the CG steps taken)."""
+    import torch
+    stats = {"applications": 0, "cg_steps": 0, "max_relres": 0.0}
+    dev = solver.device
+
+    def apply_E(x):
+        xt = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=dev)
+        y, steps, rr = solver.pcg(A_rowptr, A_col, A_val, perm, xt, tol=tol, maxit=maxit)
+        z = solver.spmv(X_S, xt)
+        solver.sync()
+        stats["applications"] += 1
+        stats["cg_steps"] += steps
+        stats["max_relres"] = max(stats["max_relres"], rr)
+        return y.cpu().numpy() - z.cpu().numpy()
+
+    return apply_E, stats
 
 
 def greedy_accept(lam, evaluate):
