@@ -345,6 +345,22 @@ asi_status asi_pcg(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, 
                    const int32_t *perm, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,
                    double *relres);
 
+/*
+ * asi_sqmr: x = Ah^-1 b by the simplified QMR method with the symmetric
+ * preconditioner (L D L^T)^-1 of the loaded factor (Section 2.5: the method
+ * the paper uses for the indefinite case), from x = 0. Arguments, outputs,
+ * synchrony and workspace use as for asi_pcg. The quasi-residual bound
+ * sqrt(k + 1) tau_k decides when the true residual ||b - Ah x||_2 is
+ * computed; the call stops when that is <= tol ||b||_2 or after maxit
+ * steps (*relres is then the last true residual computed). A near-breakdown
+ * (a vanishing rho or sigma, or a quasi-residual that is no longer finite)
+ * restarts the method from the last iterate; ASI_E_NONFINITE after 8
+ * restarts.
+ */
+asi_status asi_sqmr(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                    const int32_t *perm, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,
+                    double *relres);
+
 /* Wait for the handle's stream; return the first device-side error latched
  * since the previous asi_sync (and clear it). */
 asi_status asi_sync(asi_handle h);

@@ -27,7 +27,7 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
            "asi_profile_read", "asi_set_sweep", "asi_mlp_features", "asi_mlp_pack", "asi_mlp_forward",
            "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor", "asi_selinv_ninv", "asi_trace", "asi_ninv_full", "asi_mix_full",
-           "asi_spmv", "asi_ldl_solve", "asi_pcg"]
+           "asi_spmv", "asi_ldl_solve", "asi_pcg", "asi_sqmr"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -87,6 +87,7 @@ def load_library():
         "asi_spmv": [P, P, P, P],
         "asi_ldl_solve": [P, P, P],
         "asi_pcg": [P, P, P, P, P, P, P, f64, i32, P, P],
+        "asi_sqmr": [P, P, P, P, P, P, P, f64, i32, P, P],
         "asi_sync": [P],
         "asi_profile": [P, ctypes.c_int],
         "asi_set_sweep": [P, ctypes.c_int],
@@ -369,15 +370,22 @@ class Solver:
         self._check(self.lib.asi_ldl_solve(self.h, _ptr(x), _ptr(y)))
         return y
 
-    def pcg(self, A_rowptr, A_col, A_val, perm, b, x=None, tol=1e-10, maxit=1000):
-        """x = Ah^-1 b by CG preconditioned with the loaded factor; returns (x, steps, relres)."""
+    def _krylov(self, fn, A_rowptr, A_col, A_val, perm, b, x, tol, maxit):
         x = self.torch.empty_like(b) if x is None else x
         it = ctypes.c_int32(0)
         rr = ctypes.c_double(0.0)
         self._stream()
-        self._check(self.lib.asi_pcg(self.h, _ptr(A_rowptr), _ptr(A_col), _ptr(A_val), _ptr(perm), _ptr(b),
-                                     _ptr(x), float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rr)))
+        self._check(fn(self.h, _ptr(A_rowptr), _ptr(A_col), _ptr(A_val), _ptr(perm), _ptr(b), _ptr(x), float(tol),
+                       int(maxit), ctypes.byref(it), ctypes.byref(rr)))
         return x, it.value, rr.value
+
+    def pcg(self, A_rowptr, A_col, A_val, perm, b, x=None, tol=1e-10, maxit=1000):
+        """x = Ah^-1 b by CG preconditioned with the loaded factor; returns (x, steps, relres)."""
+        return self._krylov(self.lib.asi_pcg, A_rowptr, A_col, A_val, perm, b, x, tol, maxit)
+
+    def sqmr(self, A_rowptr, A_col, A_val, perm, b, x=None, tol=1e-10, maxit=1000):
+        """x = Ah^-1 b by simplified QMR preconditioned with the loaded factor; returns (x, steps, relres)."""
+        return self._krylov(self.lib.asi_sqmr, A_rowptr, A_col, A_val, perm, b, x, tol, maxit)
 
     def trace(self, X, V=None, lam=None, sums=None):
         """Device float64[2]: (sum_i c_i, sum_i |c_i|), c_i = X_ii + sum_m lam_m V_im^2."""

@@ -49,7 +49,7 @@ struct asi_handle_s {
     unsigned long long *nf_cur = nullptr;
     double *nf_dN = nullptr;
     unsigned long long *nf_bsum = nullptr;
-    double *cg = nullptr;  // CG work vectors (4 n), dot partials (1024), scalars (16)
+    double *cg = nullptr;  // Krylov work vectors (5 n), dot partials (1024), scalars (16)
     double *rn = nullptr;         // ||L(i, :)||_2, then ||L(:, i)||_2, of the factor in Lu (set with it)
     int64_t *rowptr_L = nullptr;  // the input L's row pointers
     float *Lf = nullptr;          // float32 copy of the loaded factor's L (mixed precision)
@@ -175,7 +175,7 @@ Layout make_layout(const asi::Analysis &A) {
     L.add((n + 1) * 8);                 // 38   their fill cursors
     L.add(n * 8);                       // 39   diagonal of N
     L.add((n / 1024 + 2) * 8);          // 40   scan block sums
-    L.add((4 * n + 1024 + 16) * 8);     // 41 preconditioned CG: r, z, p, q, dot partials, scalars
+    L.add((5 * n + 1024 + 16) * 8);     // 41 Krylov solves: 5 vectors, dot partials, scalars
     return L;
 }
 
@@ -1126,7 +1126,7 @@ asi_status asi_pcg(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, 
     DeviceGuard g(h->device);
     const int32_t n = h->A.n;
     const int64_t nn = n;
-    double *r = h->cg, *z = r + nn, *p = z + nn, *q = p + nn, *part = q + nn, *sc = part + 1024;
+    double *r = h->cg, *z = r + nn, *p = z + nn, *q = p + nn, *part = q + 2 * nn, *sc = part + 1024;
     double *rz = sc, *rzn = sc + 1, *pq = sc + 2, *rr = sc + 3, *bb = sc + 4;
     const asi::LdlSolveParams L = ldl_params(h);
     hipStream_t st = h->stream;
@@ -1178,6 +1178,129 @@ asi_status asi_pcg(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, 
             if (e == hipSuccess) e = asi::launch_copy_f64(1, rzn, rz, st);
         }
         if (e != hipSuccess) return hip_fail(h, e, "pcg preconditioner");
+    }
+    if (iters) *iters = std::min(it, maxit);
+    if (relres) *relres = res;
+    return asi_sync(h);
+}
+
+asi_status asi_sqmr(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                    const int32_t *perm, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,
+                    double *relres) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!A_rowptr || !A_col || !A_val || !perm || !b || !x) return fail(h, ASI_E_ARG, "null pointer");
+    if (!(tol > 0.0) || maxit < 0) return fail(h, ASI_E_ARG, "tol must be > 0 and maxit >= 0");
+    if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor loaded (asi_load_factor)");
+    if (h->A.s2u.empty() && h->A.nnzS > 0) return fail(h, ASI_E_UNSUPPORTED, "solves need |S| < 2^31");
+    DeviceGuard g(h->device);
+    const int32_t n = h->A.n;
+    const int64_t nn = n;
+    // vectors: r (residual), t (products), q (direction), u (preconditioned), d (step)
+    double *r = h->cg, *t = r + nn, *q = t + nn, *u = q + nn, *d = u + nn, *part = d + nn, *sc = part + 1024;
+    double *rho = sc, *rhon = sc + 1, *sig = sc + 2, *rr = sc + 3, *bb = sc + 4;
+    const asi::LdlSolveParams L = ldl_params(h);
+    hipStream_t st = h->stream;
+    hipError_t e;
+    auto read = [&](double *dst, const double *src, int cnt) {
+        hipError_t e2 = hipMemcpyAsync(dst, src, 8 * (size_t)cnt, hipMemcpyDeviceToHost, st);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+        return e2;
+    };
+    {
+        Trace tr(h, ASI_K_DIAG, 0.0);
+        e = asi::launch_iperm(n, perm, h->iperm, h->status, st);
+        if (e == hipSuccess) e = asi::launch_fill_f64(nn, 0.0, x, st);
+        if (e == hipSuccess) e = asi::launch_dot(nn, b, b, part, bb, st);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "sqmr setup");
+    double bnorm2 = 0.0;
+    e = read(&bnorm2, bb, 1);
+    if (e != hipSuccess) return hip_fail(h, e, "sqmr norm");
+    if (bnorm2 == 0.0) {
+        if (iters) *iters = 0;
+        if (relres) *relres = 0.0;
+        return asi_sync(h);
+    }
+    const double bnorm = std::sqrt(bnorm2);
+    // (re)start from the current x: r = b - Ah x, q = M^-1 r, rho = r^T q,
+    // tau = ||r||, theta = 0, d = 0; a near-breakdown (a vanishing sigma or
+    // rho, or a quasi-residual that is no longer finite) restarts from the
+    // last iterate, at most kRestarts times
+    constexpr int kRestarts = 8;
+    double tau = 0.0, theta = 0.0;
+    auto restart = [&]() -> hipError_t {
+        Trace tr(h, ASI_K_DIAG, 0.0);
+        hipError_t e2 = asi::launch_spmv_ahat(n, A_rowptr, A_col, A_val, perm, h->iperm, x, t, st);
+        if (e2 == hipSuccess) e2 = asi::launch_sub(nn, b, t, r, st);
+        if (e2 == hipSuccess) e2 = asi::launch_fill_f64(nn, 0.0, d, st);
+        if (e2 == hipSuccess) e2 = asi::launch_ldl_solve(L, r, q, st);
+        if (e2 == hipSuccess) e2 = asi::launch_dot(nn, r, q, part, rho, st);
+        if (e2 == hipSuccess) e2 = asi::launch_dot(nn, r, r, part, rr, st);
+        double r2 = 0.0;
+        if (e2 == hipSuccess) e2 = read(&r2, rr, 1);
+        tau = std::sqrt(r2);
+        theta = 0.0;
+        return e2;
+    };
+    e = restart();
+    if (e != hipSuccess) return hip_fail(h, e, "sqmr start");
+    int32_t it = 0, restarts = 0;
+    double res = tau / bnorm;
+    int32_t since = 0;  // steps since the last (re)start
+    for (it = 1; it <= maxit; ++it) {
+        ++since;
+        {
+            Trace tr(h, ASI_K_DIAG, 0.0);
+            e = asi::launch_spmv_ahat(n, A_rowptr, A_col, A_val, perm, h->iperm, q, t, st);
+            if (e == hipSuccess) e = asi::launch_dot(nn, q, t, part, sig, st);
+            if (e == hipSuccess) e = asi::launch_axpy_ratio(nn, rho, sig, -1.0, t, r, st);  // r -= (rho / sigma) t
+            if (e == hipSuccess) e = asi::launch_dot(nn, r, r, part, rr, st);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "sqmr step");
+        double v[4];
+        e = read(v, sc, 4);  // rho, rhon (unused), sigma, ||r||^2
+        if (e != hipSuccess) return hip_fail(h, e, "sqmr scalars");
+        const double alpha = v[0] / v[2];
+        const double theta_n = std::sqrt(v[3]) / tau;
+        const double c = 1.0 / std::sqrt(1.0 + theta_n * theta_n);
+        const double tau_n = tau * theta_n * c;
+        const bool finite = std::isfinite(alpha) && std::isfinite(theta_n) && std::isfinite(tau_n) && c > 0.0;
+        if (!finite || v[0] == 0.0 || v[2] == 0.0) {
+            if (++restarts > kRestarts)
+                return fail(h, ASI_E_NONFINITE, "sqmr breakdown at step " + std::to_string(it) + " after " +
+                                                    std::to_string(kRestarts) + " restarts");
+            e = restart();
+            if (e != hipSuccess) return hip_fail(h, e, "sqmr restart");
+            since = 0;
+            continue;
+        }
+        tau = tau_n;
+        e = asi::launch_qmr_update(nn, c * c * theta * theta, c * c * alpha, q, d, x, st);
+        theta = theta_n;
+        if (e != hipSuccess) return hip_fail(h, e, "sqmr update");
+        // sqrt(k + 1) tau bounds the residual of the iterate; confirm with the true one
+        if (std::sqrt((double)since + 1.0) * tau <= tol * bnorm || it == maxit) {
+            {
+                Trace tr(h, ASI_K_DIAG, 0.0);
+                e = asi::launch_spmv_ahat(n, A_rowptr, A_col, A_val, perm, h->iperm, x, t, st);
+                if (e == hipSuccess) e = asi::launch_sub(nn, b, t, u, st);
+                if (e == hipSuccess) e = asi::launch_dot(nn, u, u, part, rr, st);
+            }
+            double tr2 = 0.0;
+            if (e == hipSuccess) e = read(&tr2, rr, 1);
+            if (e != hipSuccess) return hip_fail(h, e, "sqmr residual");
+            res = std::sqrt(tr2) / bnorm;
+            if (res <= tol) break;
+        }
+        {
+            Trace tr(h, ASI_K_DIAG, 0.0);
+            e = asi::launch_ldl_solve(L, r, u, st);
+            if (e == hipSuccess) e = asi::launch_dot(nn, r, u, part, rhon, st);
+            if (e == hipSuccess) e = asi::launch_xpby_ratio(nn, u, rhon, rho, q, st);  // q = u + (rhon / rho) q
+            if (e == hipSuccess) e = asi::launch_copy_f64(1, rhon, rho, st);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "sqmr preconditioner");
     }
     if (iters) *iters = std::min(it, maxit);
     if (relres) *relres = res;

@@ -211,6 +211,8 @@ hipError_t launch_axpy_ratio(int64_t n, const double *num, const double *den, do
 hipError_t launch_xpby_ratio(int64_t n, const double *z, const double *num, const double *den, double *p,
                              hipStream_t st);
 hipError_t launch_copy_f64(int64_t n, const double *a, double *b, hipStream_t st);
+hipError_t launch_qmr_update(int64_t n, double a, double b, const double *q, double *d, double *x, hipStream_t st);
+hipError_t launch_sub(int64_t n, const double *b, const double *t, double *r, hipStream_t st);
 hipError_t launch_fill_f64(int64_t n, double v, double *a, hipStream_t st);
 
 hipError_t launch_node_feats(const MlpFeatParams &P, hipStream_t st);

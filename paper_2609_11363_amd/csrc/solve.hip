@@ -7,7 +7,7 @@
 //   SelInv sweep: the rows of a level depend only on rows of other levels,
 //   forward substitution runs the levels last to first, backward first to
 //   last, each row a gather over its part of S (its L values in u-space);
-// and the vector kernels of a preconditioned CG on Ah.
+// and the vector kernels of preconditioned CG and simplified QMR on Ah.
 // Every sum has a fixed order (segment lanes, then a fixed shuffle tree, and
 // fixed-order two-stage reductions), so the results repeat bit for bit.
 #include <hip/hip_runtime.h>
@@ -145,6 +145,23 @@ __global__ void k_xpby_ratio(int64_t n, const double *__restrict__ z, const doub
     if (i < n) p[i] = z[i] + (*num / *den) * p[i];
 }
 
+// d = a d + b q, x += d (scalars from the host)
+__global__ void k_qmr_update(int64_t n, double a, double b, const double *__restrict__ q, double *__restrict__ d,
+                             double *__restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double v = a * d[i] + b * q[i];
+        d[i] = v;
+        x[i] += v;
+    }
+}
+
+// r = b - t
+__global__ void k_sub(int64_t n, const double *__restrict__ b, const double *__restrict__ t, double *__restrict__ r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) r[i] = b[i] - t[i];
+}
+
 __global__ void k_copy_f64(int64_t n, const double *__restrict__ a, double *__restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = a[i];
@@ -232,6 +249,16 @@ hipError_t launch_axpy_ratio(int64_t n, const double *num, const double *den, do
 hipError_t launch_xpby_ratio(int64_t n, const double *z, const double *num, const double *den, double *p,
                              hipStream_t st) {
     hipLaunchKernelGGL(dev::k_xpby_ratio, elem_grid(n), dim3(256), 0, st, n, z, num, den, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_qmr_update(int64_t n, double a, double b, const double *q, double *d, double *x, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_qmr_update, elem_grid(n), dim3(256), 0, st, n, a, b, q, d, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub(int64_t n, const double *b, const double *t, double *r, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_sub, elem_grid(n), dim3(256), 0, st, n, b, t, r);
     return hipGetLastError();
 }
 

@@ -46,19 +46,22 @@ def inverse_error_eigenpairs(apply_inv, X_csr, k: int, tol: float = 1e-8, seed: 
     return lam, V, res, count[0]
 
 
-def device_error_operator(solver, A_rowptr, A_col, A_val, perm, X_S, tol: float = 1e-12, maxit: int = 1000):
+def device_error_operator(solver, A_rowptr, A_col, A_val, perm, X_S, tol: float = 1e-12, maxit: int = 1000,
+                          method: str = "cg"):
     """E x = A^-1 x - X x with both terms on the device (Section 2.5): A^-1 x
-    by conjugate gradients on P^T A P preconditioned with the loaded
-    incomplete factor (asi_pcg; A symmetric positive definite), X x on S
-    (asi_spmv). Returns (apply_E(x) for host float64 vectors, statistics
-    dict with the CG steps taken)."""
+    by a Krylov method on P^T A P preconditioned with the loaded incomplete
+    factor, conjugate gradients for positive definite A (asi_pcg) or
+    simplified QMR for indefinite A (asi_sqmr), and X x on S (asi_spmv).
+    Returns (apply_E(x) for host float64 vectors, statistics dict with the
+    Krylov steps taken)."""
+    krylov = solver.pcg if method == "cg" else solver.sqmr
     import torch
     stats = {"applications": 0, "cg_steps": 0, "max_relres": 0.0}
     dev = solver.device
 
     def apply_E(x):
         xt = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=dev)
-        y, steps, rr = solver.pcg(A_rowptr, A_col, A_val, perm, xt, tol=tol, maxit=maxit)
+        y, steps, rr = krylov(A_rowptr, A_col, A_val, perm, xt, tol=tol, maxit=maxit)
         z = solver.spmv(X_S, xt)
         solver.sync()
         stats["applications"] += 1

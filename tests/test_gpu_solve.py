@@ -120,3 +120,36 @@ def test_eigenpairs_with_device_solves_match_host():
     # the spanned subspaces agree (degenerate eigenvalues make single vectors arbitrary)
     sv = np.linalg.svd(V_d.T @ V_h, compute_uv=False)
     assert sv.min() >= 1 - 1e-6
+
+
+@pytest.mark.parametrize("name", ["indef24", "kkt", "cov20"])
+def test_sqmr(name):
+    import torch
+    from paper_2609_11363_amd import Solver, upload_factors
+    from workloads import shifted_laplace2d_indefinite
+    if name == "indef24":
+        A, _ = shifted_laplace2d_indefinite(24, 4)
+        F = ildl_bk(A, nested_multicolor_grid((24, 24)), 1e-2)
+    else:
+        A, F = _case(name)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    Lv, dd, ds = upload_factors(F)
+    s.load_factor(Lv, dd, ds)
+    dev = s.device
+    Ar = torch.as_tensor(A.indptr.astype(np.int64), device=dev)
+    Ac = torch.as_tensor(A.indices.astype(np.int32), device=dev)
+    Av = torch.as_tensor(A.data, device=dev)
+    perm = torch.as_tensor(F.perm.astype(np.int32), device=dev)
+    b = np.random.default_rng(9).standard_normal(F.n)
+    x, it, rr = s.sqmr(Ar, Ac, Av, perm, torch.as_tensor(b, device=dev), tol=1e-11, maxit=2000)
+    s.sync()
+    Ah = oc.permuted(A, F.perm)
+    xo = sp.linalg.spsolve(sp.csc_matrix(Ah), b)
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(Ah @ xg - b) / np.linalg.norm(b)
+    err = np.abs(xg - xo).max() / np.abs(xo).max()
+    print(f"[sqmr] {name}: {it} steps, reported {rr:.1e}, true residual {res:.1e}, error {err:.1e}")
+    assert rr <= 1e-11 and res <= 2e-11
+    cond = np.linalg.cond(Ah.toarray())
+    assert err <= 1e-11 * cond * 10
