@@ -565,7 +565,10 @@ static void launch_small_family(const SelinvParams &P, int group, hipStream_t st
     constexpr int W = 4;
     switch (group) {
         case 64:
-            if (P.nheavy > 0)
+            // the split pays where a level is about one round of wavefronts (its
+            // tail is the longest hit list); on levels of many rounds the tail is
+            // amortised and the split kernel's lower occupancy costs more
+            if (P.nheavy > 0 && P.nblk <= 16384)
                 hipLaunchKernelGGL((dev::k_selinv_split<T>), dim3(P.nheavy + (P.nblk - P.nheavy + W - 1) / W),
                                    dim3(64 * W), 0, st, P);
             else
