@@ -361,6 +361,29 @@ asi_status asi_sqmr(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col,
                     const int32_t *perm, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,
                     double *relres);
 
+/*
+ * Diagnostic (Section 2.1: where the pattern is closed SelInv equals A^-1 on
+ * S, so Z Ah = I on the diagonal): d[i] = (Z Ah)_ii = sum_k Z_ik Ah_ki over
+ * the k in row i of both S and Ah = P^T A P (A: the caller's CSR in its own
+ * ordering, symmetric; perm as for asi_pcg). Z_S: |S| float64; d: n
+ * float64 (factor ordering). Device pointers, asynchronous.
+ */
+asi_status asi_za_diag(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                       const int32_t *perm, const double *Z_S, double *d);
+
+/*
+ * Input check of host arrays (Section 1: the method takes a symmetric A and
+ * its permuted factorization), for debugging: perm (nullable) is a
+ * permutation of 0..n-1; A is a valid CSR (A_rowptr[0] = 0, nondecreasing,
+ * columns sorted, unique and in range, values finite) and symmetric in
+ * pattern and values (|a_ij - a_ji| <= tol max(|a_ij|, |a_ji|); tol = 0 asks
+ * for exact symmetry). ASI_E_PATTERN or ASI_E_NONFINITE with a message
+ * (asi_last_error) otherwise. Host pointers; synchronous; needs only a
+ * handle.
+ */
+asi_status asi_check_matrix(asi_handle h, int32_t n, const int64_t *A_rowptr_h, const int32_t *A_col_h,
+                            const double *A_val_h, const int32_t *perm_h, double tol);
+
 /* Wait for the handle's stream; return the first device-side error latched
  * since the previous asi_sync (and clear it). */
 asi_status asi_sync(asi_handle h);

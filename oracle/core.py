@@ -231,6 +231,12 @@ def spmv(S: Pattern, X: np.ndarray, x: np.ndarray) -> np.ndarray:
     return S.to_csr(X) @ np.asarray(x, dtype=np.float64)
 
 
+def za_diag(S: Pattern, Z: np.ndarray, Ahat) -> np.ndarray:
+    """(Z Ah)_ii = sum_k Z_ik Ah_ki for Z on S (1 where Z is exact on the
+    rows' reach, Section 2.1)."""
+    return np.asarray((S.to_csr(Z) @ sp.csr_matrix(Ahat)).diagonal()).ravel()
+
+
 def unit_lower(F) -> sp.csr_matrix:
     """L with its unit diagonal (the factor stores the strictly lower part)."""
     L = sp.csr_matrix(F.L_csr())

@@ -27,7 +27,7 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
            "asi_profile_read", "asi_set_sweep", "asi_mlp_features", "asi_mlp_pack", "asi_mlp_forward",
            "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor", "asi_selinv_ninv", "asi_trace", "asi_ninv_full", "asi_mix_full",
-           "asi_spmv", "asi_ldl_solve", "asi_pcg", "asi_sqmr"]
+           "asi_spmv", "asi_ldl_solve", "asi_pcg", "asi_sqmr", "asi_za_diag", "asi_check_matrix"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -88,6 +88,8 @@ def load_library():
         "asi_ldl_solve": [P, P, P],
         "asi_pcg": [P, P, P, P, P, P, P, f64, i32, P, P],
         "asi_sqmr": [P, P, P, P, P, P, P, f64, i32, P, P],
+        "asi_za_diag": [P, P, P, P, P, P, P],
+        "asi_check_matrix": [P, i32, P, P, P, P, f64],
         "asi_sync": [P],
         "asi_profile": [P, ctypes.c_int],
         "asi_set_sweep": [P, ctypes.c_int],
@@ -355,6 +357,25 @@ class Solver:
         """Mix on NInv's pattern joined with S_eps: lower triangle as (rowptr, col, val)."""
         rp, cl, vl = N_full
         return self._full_call(self.lib.asi_mix_full, (_ptr(Z), _ptr(rp), _ptr(cl), _ptr(vl), float(eps)))
+
+    def za_diag(self, A_rowptr, A_col, A_val, perm, Z, d=None):
+        """Device float64[n]: (Z Ah)_ii, Ah = P^T A P."""
+        t = self.torch
+        d = t.empty(self.n, dtype=t.float64, device=self.device) if d is None else d
+        self._stream()
+        self._check(self.lib.asi_za_diag(self.h, _ptr(A_rowptr), _ptr(A_col), _ptr(A_val), _ptr(perm), _ptr(Z),
+                                         _ptr(d)))
+        return d
+
+    def check_matrix(self, A, perm=None, tol=0.0):
+        """Host check of a scipy CSR A (and perm): raises AsiError on invalid input."""
+        indptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
+        indices = np.ascontiguousarray(A.indices, dtype=np.int32)
+        data = np.ascontiguousarray(A.data, dtype=np.float64)
+        pp = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+        c = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        self._check(self.lib.asi_check_matrix(self.h, int(A.shape[0]), c(indptr), c(indices), c(data), c(pp),
+                                              float(tol)))
 
     def spmv(self, X, x, y=None):
         """y = X x for X on S."""

@@ -1070,6 +1070,59 @@ asi_status asi_trace(asi_handle h, const double *X_S, int32_t k, const double *V
     return ASI_OK;
 }
 
+asi_status asi_za_diag(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                       const int32_t *perm, const double *Z_S, double *d) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!A_rowptr || !A_col || !A_val || !perm || !Z_S || !d) return fail(h, ASI_E_ARG, "null pointer");
+    DeviceGuard g(h->device);
+    Trace t(h, ASI_K_DIAG, 0.0);
+    hipError_t e = asi::launch_iperm(h->A.n, perm, h->iperm, h->status, h->stream);
+    if (e == hipSuccess)
+        e = asi::launch_za_diag(h->A.n, h->rowptr, h->col, Z_S, A_rowptr, A_col, A_val, perm, h->iperm, d, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "za diag");
+    return ASI_OK;
+}
+
+// Input checks of the host arrays (debug use): perm a permutation, A a
+// valid CSR with sorted unique in-range columns, symmetric in pattern and
+// values (exactly, or within tol relative to the larger entry).
+asi_status asi_check_matrix(asi_handle h, int32_t n, const int64_t *A_rowptr_h, const int32_t *A_col_h,
+                            const double *A_val_h, const int32_t *perm_h, double tol) {
+    if (!h) return ASI_E_ARG;
+    if (n < 0 || !A_rowptr_h || (n > 0 && (!A_col_h || !A_val_h))) return fail(h, ASI_E_ARG, "null pointer");
+    if (perm_h) {
+        std::vector<char> seen(n, 0);
+        for (int32_t i = 0; i < n; ++i) {
+            const int32_t p = perm_h[i];
+            if (p < 0 || p >= n || seen[p]) return fail(h, ASI_E_PATTERN, "perm is not a permutation");
+            seen[p] = 1;
+        }
+    }
+    if (A_rowptr_h[0] != 0) return fail(h, ASI_E_PATTERN, "A_rowptr[0] must be 0");
+    for (int32_t i = 0; i < n; ++i) {
+        if (A_rowptr_h[i + 1] < A_rowptr_h[i]) return fail(h, ASI_E_PATTERN, "A_rowptr must be nondecreasing");
+        for (int64_t q = A_rowptr_h[i]; q < A_rowptr_h[i + 1]; ++q) {
+            const int32_t c = A_col_h[q];
+            if (c < 0 || c >= n) return fail(h, ASI_E_PATTERN, "A column out of range");
+            if (q > A_rowptr_h[i] && c <= A_col_h[q - 1])
+                return fail(h, ASI_E_PATTERN, "A columns must be sorted and unique within each row");
+            if (!std::isfinite(A_val_h[q])) return fail(h, ASI_E_NONFINITE, "A has a non-finite value");
+        }
+    }
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t q = A_rowptr_h[i]; q < A_rowptr_h[i + 1]; ++q) {
+            const int32_t c = A_col_h[q];
+            const int32_t *b = A_col_h + A_rowptr_h[c], *e = A_col_h + A_rowptr_h[c + 1];
+            const int32_t *f = std::lower_bound(b, e, i);
+            if (f == e || *f != i) return fail(h, ASI_E_PATTERN, "A is not structurally symmetric");
+            const double a = A_val_h[q], at = A_val_h[f - A_col_h];
+            if (std::fabs(a - at) > tol * std::max(std::fabs(a), std::fabs(at)))
+                return fail(h, ASI_E_PATTERN, "A is not symmetric in its values");
+        }
+    return ASI_OK;
+}
+
 static asi::LdlSolveParams ldl_params(asi_handle h) {
     const asi::Analysis &A = h->A;
     asi::LdlSolveParams P{};

@@ -203,6 +203,9 @@ hipError_t launch_spmv_s(int32_t n, const int64_t *rowptr, const int32_t *col, c
 hipError_t launch_spmv_ahat(int32_t n, const int64_t *Ap, const int32_t *Aj, const double *Av, const int32_t *perm,
                             const int32_t *iperm, const double *x, double *y, hipStream_t st);
 hipError_t launch_iperm(int32_t n, const int32_t *perm, int32_t *iperm, int32_t *status, hipStream_t st);
+hipError_t launch_za_diag(int32_t n, const int64_t *rowptr, const int32_t *col, const double *Z, const int64_t *Ap,
+                          const int32_t *Aj, const double *Av, const int32_t *perm, const int32_t *iperm, double *d,
+                          hipStream_t st);
 hipError_t launch_ldl_solve(const LdlSolveParams &P, const double *x, double *v, hipStream_t st);
 int dot_blocks(int64_t n);
 hipError_t launch_dot(int64_t n, const double *a, const double *b, double *part, double *out, hipStream_t st);

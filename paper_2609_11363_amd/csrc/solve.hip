@@ -2,7 +2,8 @@
 // (Section 2.5, Algorithm 1: the eigenpairs of A^-1 - X need products with X
 // and solves with A, preconditioned by the incomplete factor):
 //   y = X x for X on S (both triangles),
-//   y = Ah x for Ah = P^T A P (A in its own ordering, perm),
+//   y = Ah x for Ah = P^T A P (A in its own ordering, perm), the diagonal
+//   of Z Ah (a diagnostic of an approximate inverse, 1 where Z is exact),
 //   y = (L D L^T)^-1 x with the loaded factor, by the level schedule of the
 //   SelInv sweep: the rows of a level depend only on rows of other levels,
 //   forward substitution runs the levels last to first, backward first to
@@ -90,6 +91,37 @@ __global__ __launch_bounds__(256) void k_ldl_level(const BlockMeta *__restrict__
         s = seg_sum(s);
         if (sub == 0) v[i] -= s;
     }
+}
+
+// d_i = (Z Ah)_ii = sum_k Z_ik Ah_ki over k in row i of S and of Ah (Ah
+// symmetric, so Ah_ki = Ah_ik): row perm[i] of A is walked, each column
+// mapped to the factor ordering and searched in the sorted row i of S
+__global__ __launch_bounds__(256) void k_za_diag(int32_t n, const int64_t *__restrict__ rowptr,
+                                                 const int32_t *__restrict__ col, const double *__restrict__ Z,
+                                                 const int64_t *__restrict__ Ap, const int32_t *__restrict__ Aj,
+                                                 const double *__restrict__ Av, const int32_t *__restrict__ perm,
+                                                 const int32_t *__restrict__ iperm, double *__restrict__ d) {
+    const int32_t i = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
+    const int sub = threadIdx.x % kSeg;
+    double s = 0.0;
+    if (i < n) {
+        const int32_t r = perm[i];
+        const int64_t b0 = rowptr[i], b1 = rowptr[i + 1];
+        for (int64_t p = Ap[r] + sub; p < Ap[r + 1]; p += kSeg) {
+            const int32_t k = iperm[Aj[p]];
+            int64_t lo = b0, hi = b1;  // first position with col >= k
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (col[mid] < k)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo < b1 && col[lo] == k) s += Z[lo] * Av[p];
+        }
+    }
+    s = seg_sum(s);
+    if (i < n && sub == 0) d[i] = s;
 }
 
 // v = D^-1 v (1x1 and 2x2 blocks, inverses from the D-block kernel)
@@ -200,6 +232,14 @@ hipError_t launch_spmv_ahat(int32_t n, const int64_t *Ap, const int32_t *Aj, con
                             const int32_t *iperm, const double *x, double *y, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(dev::k_spmv_ahat, seg_grid(n), dim3(256), 0, st, n, Ap, Aj, Av, perm, iperm, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_za_diag(int32_t n, const int64_t *rowptr, const int32_t *col, const double *Z, const int64_t *Ap,
+                          const int32_t *Aj, const double *Av, const int32_t *perm, const int32_t *iperm, double *d,
+                          hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::k_za_diag, seg_grid(n), dim3(256), 0, st, n, rowptr, col, Z, Ap, Aj, Av, perm, iperm, d);
     return hipGetLastError();
 }
 

@@ -153,3 +153,21 @@ def test_sqmr(name):
     assert rr <= 1e-11 and res <= 2e-11
     cond = np.linalg.cond(Ah.toarray())
     assert err <= 1e-11 * cond * 10
+
+
+@pytest.mark.parametrize("name", ["cov20", "kkt"])
+def test_za_diag(name):
+    import torch
+    from paper_2609_11363_amd import Solver
+    A, F = _case(name)
+    S = oc.pattern(F)
+    Z = oc.ninv(F, S, 3, 0.1)  # an approximation whose (Z Ah)_ii are not all 1
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    dev = s.device
+    d = s.za_diag(torch.as_tensor(A.indptr.astype(np.int64), device=dev),
+                  torch.as_tensor(A.indices.astype(np.int32), device=dev), torch.as_tensor(A.data, device=dev),
+                  torch.as_tensor(F.perm.astype(np.int32), device=dev), torch.as_tensor(Z, device=dev))
+    s.sync()
+    want = oc.za_diag(S, Z, oc.permuted(A, F.perm))
+    np.testing.assert_allclose(d.cpu().numpy(), want, rtol=1e-12, atol=1e-14)

@@ -128,3 +128,42 @@ def test_host_handle_has_no_device_calls():
     assert rc == 5  # ASI_E_STATE: no workspace on a host-only handle
     rc = h.lib.asi_set_workspace(h.h, ctypes.c_void_p(256), 1 << 20)
     assert rc == 5
+
+
+def test_check_matrix_accepts_valid_and_rejects_invalid_input():
+    import scipy.sparse as sp
+    from workloads import covariance_grid
+    h = HostHandle()
+    A = covariance_grid(6)
+    n = A.shape[0]
+    perm = np.random.default_rng(0).permutation(n).astype(np.int32)
+
+    def check(M, p=perm, tol=0.0, nn=None):
+        ip = np.ascontiguousarray(M.indptr, np.int64)
+        ic = np.ascontiguousarray(M.indices, np.int32)
+        iv = np.ascontiguousarray(M.data, np.float64)
+        pp = None if p is None else np.ascontiguousarray(p, np.int32)
+        return h.lib.asi_check_matrix(h.h, M.shape[0] if nn is None else nn, ip.ctypes.data, ic.ctypes.data,
+                                      iv.ctypes.data, None if pp is None else pp.ctypes.data, ctypes.c_double(tol))
+
+    assert check(A) == 0 and check(A, None) == 0
+    bad = perm.copy()
+    bad[1] = bad[0]
+    assert check(A, bad) == 2 and "permutation" in h.error()
+    B = A.tolil()
+    B[0, 5] = 0.125  # pattern no longer symmetric
+    assert check(sp.csr_matrix(B)) == 2 and "structurally" in h.error()
+    C = A.copy()
+    C.data = C.data.copy()
+    q = C.indptr[1] - 1  # last entry of row 0, an off-diagonal
+    C.data[q] *= 1 + 1e-9
+    assert check(C) == 2 and "values" in h.error()
+    assert check(C, tol=1e-8) == 0
+    D = A.copy()
+    D.indices = D.indices.copy()
+    D.indices[[0, 1]] = D.indices[[1, 0]]  # unsorted row
+    assert check(D) == 2 and "sorted" in h.error()
+    E = A.copy()
+    E.data = E.data.copy()
+    E.data[3] = np.nan
+    assert check(E) == 4  # ASI_E_NONFINITE

@@ -31,3 +31,21 @@ def test_spmv_dense():
     X = np.random.default_rng(2).standard_normal(S.nnz)
     x = np.random.default_rng(3).standard_normal(F.n)
     np.testing.assert_allclose(oc.spmv(S, X, x), S.to_csr(X).toarray() @ x, rtol=1e-13, atol=1e-13)
+
+
+def test_za_diag_is_one_for_the_exact_inverse_on_a_closed_pattern():
+    # tau = 0: pattern(Ah) is inside S and Z = A^-1 on S, so (Z Ah)_ii = 1 (Section 2.1)
+    A = covariance_grid(10)
+    F = ildl_bk(A, nested_multicolor_grid((10, 10)), 0.0)
+    S = oc.pattern(F)
+    Z = oc.selinv(F, S)
+    d = oc.za_diag(S, Z, oc.permuted(A, F.perm))
+    np.testing.assert_allclose(d, 1.0, rtol=0, atol=1e-12)
+    # NInv with drops on an incomplete pattern: equal to a dense product's diagonal, not all ones
+    F2 = ildl_bk(A, nested_multicolor_grid((10, 10)), 1e-2)
+    S2 = oc.pattern(F2)
+    N2 = oc.ninv(F2, S2, 3, 0.1)
+    Ah = oc.permuted(A, F2.perm).toarray()
+    d2 = oc.za_diag(S2, N2, Ah)
+    np.testing.assert_allclose(d2, np.diag(S2.to_csr(N2).toarray() @ Ah), rtol=1e-13)
+    assert np.abs(d2 - 1).max() > 1e-6
