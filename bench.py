@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # scaled by a 256 MiB copy (3.397 GB read + 0.370 GB written per sweep of 140
 # launches). It holds only for the kernel sources it was measured on; any
 # other sources report null.
-SELINV_TRAFFIC = {"sources_sha256": "af41ac0ac4d69d7b8f7295bcf9fafc4453be3f43ebfa81bd3c7a5bd126de9794",
+SELINV_TRAFFIC = {"sources_sha256": "ea108a0f50c10dd45cb20cec4ba6a45a7a83bce8ff336f32efb5c1df9d1bac9b",
                   "bytes_per_launch": (3.406e9 + 0.370e9) / 140,
                   "profile": "profiles/selinv_ninv_mix_learned_diffusion64.md"}
 
