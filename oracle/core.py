@@ -231,6 +231,19 @@ def spmv(S: Pattern, X: np.ndarray, x: np.ndarray) -> np.ndarray:
     return S.to_csr(X) @ np.asarray(x, dtype=np.float64)
 
 
+def error_eigenpairs(Ahat, S: Pattern, X: np.ndarray, k: int):
+    """The k eigenpairs of largest |lambda| of the inverse-error operator
+    E = Ah^-1 - X (Section 2.5, Algorithm 1), by its definition: Ah^-1 as a
+    dense inverse, X as the dense matrix of its values on S, the symmetric
+    eigendecomposition of E. Returns (lambda [k] in decreasing |lambda|, ties
+    by ascending lambda, V [n, k] orthonormal). Dense: small n only."""
+    Ainv = np.linalg.inv(np.asarray(sp.csr_matrix(Ahat).todense(), dtype=np.float64))
+    E = Ainv - np.asarray(S.to_csr(X).todense())
+    lam, V = np.linalg.eigh(0.5 * (E + E.T))
+    order = np.argsort(-np.abs(lam), kind="stable")[:k]
+    return lam[order], np.ascontiguousarray(V[:, order])
+
+
 def za_diag(S: Pattern, Z: np.ndarray, Ahat) -> np.ndarray:
     """(Z Ah)_ii = sum_k Z_ik Ah_ki for Z on S (1 where Z is exact on the
     rows' reach, Section 2.1)."""
