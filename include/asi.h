@@ -362,6 +362,63 @@ asi_status asi_sqmr(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col,
                     double *relres);
 
 /*
+ * The eigen step itself (Section 2.5, Algorithm 1: the k eigenpairs of
+ * largest |lambda| of the symmetric inverse-error operator E = A^-1 - X,
+ * found matrix-free with A^-1 applied by a preconditioned Krylov solve).
+ *
+ * asi_eigs_error: thick-restart Lanczos on E in the factor ordering. Each
+ * application y = E v is a Krylov solve on Ah = P^T A P with the loaded
+ * factor as preconditioner (method 0: asi_pcg, positive definite A;
+ * method 1: asi_sqmr, indefinite A; solve_tol and solve_maxit as there)
+ * minus asi_spmv with X_S. Every new basis vector is orthogonalised against
+ * the whole basis by two passes of classical Gram-Schmidt. After m basis
+ * vectors the host diagonalises the m x m projection T = V^T E V
+ * (asi_dense_symeig) and estimates the residual of each Ritz pair
+ * (theta, u) as |beta_m y_m| (beta_m: norm of the last residual vector,
+ * y_m: last entry of the Ritz vector's coefficients); the call stops when
+ * the k Ritz pairs of largest |theta| all satisfy ||E u - theta u|| <=
+ * tol |theta| or after max_restarts restarts, else it keeps
+ * k + (m - k) / 2 Ritz vectors plus the residual vector and expands again.
+ * A basis vector of norm <= 1e-13 ||T||_max (an invariant subspace) ends
+ * the iteration with exact Ritz pairs (ASI_E_NONFINITE if fewer than k).
+ *
+ * A_rowptr, A_col, A_val, perm: as for asi_pcg (device). X_S: |S| float64
+ * (device). v0: n float64 starting vector, nonzero (device; not modified).
+ * 1 <= k <= 64; k + 2 <= m <= min(256, n - 1); tol > 0; max_restarts >= 0.
+ * work: device buffer of at least asi_eigs_work_bytes(n, m) bytes, 256-byte
+ * aligned, owned by the caller, contents undefined on return.
+ * Outputs: lambda (host, k float64) in decreasing |lambda| (ties by index);
+ * V (device, n x k row-major float64, orthonormal columns, must not overlap
+ * work); resid (host, k float64, nullable): estimated relative residuals
+ * ||E u - theta u|| / |theta|; stats (host, 5 float64, nullable): operator
+ * applications, Krylov steps, restarts, Ritz pairs converged among the k,
+ * largest relative residual of a solve. Synchronous; uses the CG vectors
+ * of the workspace (calls on one handle must not overlap). The result is
+ * repeatable bit for bit. Errors: ASI_E_ARG, ASI_E_STATE (no factor),
+ * ASI_E_WORKSPACE (work too small), the errors of the Krylov solves.
+ */
+asi_status asi_eigs_work_bytes(int32_t n, int32_t m, size_t *bytes);
+asi_status asi_eigs_error(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                          const int32_t *perm, const double *X_S, const double *v0, int32_t k, int32_t m,
+                          double tol, int32_t max_restarts, int32_t method, double solve_tol, int32_t solve_maxit,
+                          void *work, size_t work_bytes, double *lambda, double *V, double *resid, double *stats);
+
+/*
+ * asi_dense_symeig: all eigenpairs of a small dense symmetric matrix on the
+ * host (the projected problem of the Lanczos iteration above) by the cyclic
+ * Jacobi method with Rutishauser's rotation formulas: rotations annihilate
+ * the off-diagonal entries in row order until the off-diagonal Frobenius
+ * norm is <= 1e-15 times the matrix's (or no rotation changes it).
+ * T: m x m row-major float64 (host; symmetrised as (T + T^T) / 2; not
+ * modified); theta: m float64 in ascending order (ties by index of the
+ * diagonal position); Y: m x m row-major float64 whose column t is the unit
+ * eigenvector of theta[t]. 1 <= m <= 4096. Needs no handle. Errors:
+ * ASI_E_ARG, ASI_E_NONFINITE (non-finite entries, or no convergence in 100
+ * sweeps).
+ */
+asi_status asi_dense_symeig(int32_t m, const double *T, double *theta, double *Y);
+
+/*
  * Diagnostic (Section 2.1: where the pattern is closed SelInv equals A^-1 on
  * S, so Z Ah = I on the diagonal): d[i] = (Z Ah)_ii = sum_k Z_ik Ah_ki over
  * the k in row i of both S and Ah = P^T A P (A: the caller's CSR in its own

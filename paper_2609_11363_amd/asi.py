@@ -27,7 +27,8 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_mix", "asi_spai", "asi_lowrank", "asi_diag", "asi_sync", "asi_profile",
            "asi_profile_read", "asi_set_sweep", "asi_mlp_features", "asi_mlp_pack", "asi_mlp_forward",
            "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor", "asi_selinv_ninv", "asi_trace", "asi_ninv_full", "asi_mix_full",
-           "asi_spmv", "asi_ldl_solve", "asi_pcg", "asi_sqmr", "asi_za_diag", "asi_check_matrix"]
+           "asi_spmv", "asi_ldl_solve", "asi_pcg", "asi_sqmr", "asi_za_diag", "asi_check_matrix",
+           "asi_eigs_work_bytes", "asi_eigs_error", "asi_dense_symeig"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -90,6 +91,9 @@ def load_library():
         "asi_sqmr": [P, P, P, P, P, P, P, f64, i32, P, P],
         "asi_za_diag": [P, P, P, P, P, P, P],
         "asi_check_matrix": [P, i32, P, P, P, P, f64],
+        "asi_eigs_work_bytes": [i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "asi_eigs_error": [P, P, P, P, P, P, P, i32, i32, f64, i32, i32, f64, i32, P, ctypes.c_size_t, P, P, P, P],
+        "asi_dense_symeig": [i32, P, P, P],
         "asi_sync": [P],
         "asi_profile": [P, ctypes.c_int],
         "asi_set_sweep": [P, ctypes.c_int],
@@ -408,6 +412,38 @@ class Solver:
         """x = Ah^-1 b by simplified QMR preconditioned with the loaded factor; returns (x, steps, relres)."""
         return self._krylov(self.lib.asi_sqmr, A_rowptr, A_col, A_val, perm, b, x, tol, maxit)
 
+    def eigs_error(self, A_rowptr, A_col, A_val, perm, X, k, m=None, v0=None, seed=0, tol=1e-8, max_restarts=200,
+                   method="cg", solve_tol=1e-12, solve_maxit=1000, work=None):
+        """k eigenpairs of E = A^-1 - X of largest |lambda| by the device
+        Lanczos iteration (A^-1 by PCG, method "cg", or SQMR, "sqmr").
+        m defaults to min(max(2k + 1, 20), n - 1); v0 (device float64[n])
+        defaults to a standard normal vector drawn with numpy from seed.
+        Returns (lam numpy[k], V device [n, k] row-major, estimated relative
+        residuals numpy[k], stats dict)."""
+        t = self.torch
+        n = self.n
+        m = int(m) if m is not None else min(max(2 * k + 1, 20), n - 1)
+        if v0 is None:
+            v0 = t.as_tensor(np.random.default_rng(seed).standard_normal(n), device=self.device)
+        nbytes = ctypes.c_size_t(0)
+        self._check(self.lib.asi_eigs_work_bytes(n, m, ctypes.byref(nbytes)))
+        if work is None or work.numel() * work.element_size() < nbytes.value:
+            work = t.empty((nbytes.value + 7) // 8, dtype=t.float64, device=self.device)
+        lam = np.zeros(k)
+        res = np.zeros(k)
+        stats = np.zeros(5)
+        V = t.empty((n, k), dtype=t.float64, device=self.device)
+        c = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._stream()
+        self._check(self.lib.asi_eigs_error(
+            self.h, _ptr(A_rowptr), _ptr(A_col), _ptr(A_val), _ptr(perm), _ptr(X), _ptr(v0), int(k), m, float(tol),
+            int(max_restarts), {"cg": 0, "sqmr": 1}[method], float(solve_tol), int(solve_maxit), _ptr(work),
+            work.numel() * work.element_size(), c(lam), _ptr(V), c(res), c(stats)))
+        names = ["applications", "krylov_steps", "restarts", "converged", "max_solve_relres"]
+        st = {a: (float(b) if a == "max_solve_relres" else int(b)) for a, b in zip(names, stats)}
+        st["m"] = m
+        return lam, V, res, st
+
     def trace(self, X, V=None, lam=None, sums=None):
         """Device float64[2]: (sum_i c_i, sum_i |c_i|), c_i = X_ii + sum_m lam_m V_im^2."""
         t = self.torch
@@ -442,6 +478,24 @@ class Solver:
                                                   ctypes.byref(b)))
             out[name] = (n.value, ms.value, b.value)
         return out
+
+
+def dense_symeig(T):
+    """All eigenpairs of a small dense symmetric matrix with the library's
+    host Jacobi routine (the Lanczos iteration's projected problem): returns
+    (theta ascending, Y with unit eigenvectors as columns)."""
+    lib = load_library()
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    m = T.shape[0]
+    if T.ndim != 2 or T.shape[1] != m:
+        raise ValueError("T must be square")
+    theta = np.empty(m)
+    Y = np.empty((m, m))
+    c = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    rc = lib.asi_dense_symeig(m, c(T), c(theta), c(Y))
+    if rc != 0:
+        raise AsiError(rc, "asi_dense_symeig failed")
+    return theta, Y
 
 
 def upload_factors(F, device="cuda:0"):

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libasi.so")
 
-SOURCES = ["analyze.cpp", "api.cpp", "kernels.hip", "ninv.hip", "ninv_full.hip", "misc.hip", "mlp.hip", "solve.hip"]
+SOURCES = ["analyze.cpp", "api.cpp", "kernels.hip", "ninv.hip", "ninv_full.hip", "misc.hip", "mlp.hip", "solve.hip",
+           "eig.hip", "symeig.cpp"]
 
 # Packed FP32 instructions are disabled for all device code (the compiler
 # would otherwise form them from ordinary float code); the host pass warns

@@ -6,6 +6,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -1358,6 +1359,194 @@ asi_status asi_sqmr(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col,
     if (iters) *iters = std::min(it, maxit);
     if (relres) *relres = res;
     return asi_sync(h);
+}
+
+// Work buffer of asi_eigs_error, in float64 slots, each region 256-byte aligned:
+// two bases of m + 1 columns (the current one and the one a restart builds),
+// the vector X v, the Gram-Schmidt partials and coefficients, the Ritz
+// coefficients sent for a restart or the result.
+struct EigLayout {
+    size_t v0, v1, y, part, hc, Y, total_bytes;
+};
+
+static EigLayout eig_layout(int64_t n, int32_t m) {
+    auto up = [](size_t x) { return (x + 31) / 32 * 32; };
+    EigLayout E{};
+    const size_t cols = (size_t)m + 1;
+    size_t cur = 0;
+    E.v0 = cur;
+    cur += up(cols * (size_t)n);
+    E.v1 = cur;
+    cur += up(cols * (size_t)n);
+    E.y = cur;
+    cur += up((size_t)n);
+    E.part = cur;
+    cur += up(std::max(cols * (size_t)asi::gs_blocks(n), (size_t)asi::dot_blocks(n)));  // also launch_dot's partials
+    E.hc = cur;
+    cur += up(2 * cols + 1);
+    E.Y = cur;
+    cur += up((size_t)m * m);
+    E.total_bytes = cur * 8;
+    return E;
+}
+
+asi_status asi_eigs_work_bytes(int32_t n, int32_t m, size_t *bytes) {
+    if (n < 2 || m < 1 || m > asi::kEigMaxBasis || !bytes) return ASI_E_ARG;
+    *bytes = eig_layout(n, m).total_bytes;
+    return ASI_OK;
+}
+
+asi_status asi_eigs_error(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                          const int32_t *perm, const double *X_S, const double *v0, int32_t k, int32_t m,
+                          double tol, int32_t max_restarts, int32_t method, double solve_tol, int32_t solve_maxit,
+                          void *work, size_t work_bytes, double *lambda, double *V, double *resid, double *stats) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!A_rowptr || !A_col || !A_val || !perm || !X_S || !v0 || !work || !lambda || !V)
+        return fail(h, ASI_E_ARG, "null pointer");
+    if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor loaded (asi_load_factor)");
+    const int32_t n = h->A.n;
+    if (k < 1 || k > 64) return fail(h, ASI_E_ARG, "k must be in 1..64");
+    if (m < k + 2 || m > asi::kEigMaxBasis || m >= n)
+        return fail(h, ASI_E_ARG, "the basis size m must satisfy k + 2 <= m <= min(256, n - 1)");
+    if (!(tol > 0.0) || max_restarts < 0 || (method != 0 && method != 1) || !(solve_tol > 0.0) || solve_maxit < 0)
+        return fail(h, ASI_E_ARG, "tol > 0, max_restarts >= 0, method 0 or 1, solve_tol > 0, solve_maxit >= 0");
+    if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return fail(h, ASI_E_ARG, "work must be 256-byte aligned");
+    const EigLayout E = eig_layout(n, m);
+    if (work_bytes < E.total_bytes)
+        return fail(h, ASI_E_WORKSPACE, "work smaller than asi_eigs_work_bytes(n, m) = " +
+                                             std::to_string(E.total_bytes));
+    DeviceGuard g(h->device);
+    const int64_t nn = n;
+    double *base = static_cast<double *>(work);
+    double *Vc = base + E.v0, *Vn = base + E.v1, *y = base + E.y, *part = base + E.part, *hc = base + E.hc,
+           *Yd = base + E.Y;
+    const size_t cols = (size_t)m + 1;
+    hipStream_t st = h->stream;
+    auto krylov = method == 0 ? asi_pcg : asi_sqmr;
+    hipError_t e;
+    auto read = [&](double *dst, const double *src, size_t cnt) {
+        hipError_t e2 = hipMemcpyAsync(dst, src, 8 * cnt, hipMemcpyDeviceToHost, st);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+        return e2;
+    };
+    auto send = [&](double *dst, const double *src, size_t cnt) {
+        hipError_t e2 = hipMemcpyAsync(dst, src, 8 * cnt, hipMemcpyHostToDevice, st);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+        return e2;
+    };
+    // v_0 = v0 / ||v0||
+    double nrm2 = 0.0;
+    e = asi::launch_dot(nn, v0, v0, part, hc, st);
+    if (e == hipSuccess) e = read(&nrm2, hc, 1);
+    if (e != hipSuccess) return hip_fail(h, e, "eigs start vector");
+    if (!(nrm2 > 0.0) || !std::isfinite(nrm2)) return fail(h, ASI_E_ARG, "v0 must be nonzero and finite");
+    e = asi::launch_copy_f64(nn, v0, Vc, st);
+    if (e == hipSuccess) e = asi::launch_scale(nn, 1.0 / std::sqrt(nrm2), Vc, st);
+    if (e != hipSuccess) return hip_fail(h, e, "eigs start vector");
+
+    const size_t mm = (size_t)m;
+    std::vector<double> T(mm * mm, 0.0), Tm, theta(mm), Y(mm * mm), coef(2 * cols + 1), Ysel;
+    std::vector<int32_t> order(mm);
+    double applications = 0.0, ksteps = 0.0, maxrel = 0.0, tnorm = 0.0;
+    int32_t restarts = 0, j0 = 0;
+    for (;;) {
+        int32_t meff = m;
+        bool invariant = false;
+        double beta = 0.0;
+        for (int32_t j = j0; j < m; ++j) {
+            double *v = Vc + (size_t)j * nn, *w = Vc + (size_t)(j + 1) * nn;
+            int32_t its = 0;
+            double rr = 0.0;
+            s = krylov(h, A_rowptr, A_col, A_val, perm, v, w, solve_tol, solve_maxit, &its, &rr);
+            if (s != ASI_OK) return s;
+            applications += 1.0;
+            ksteps += its;
+            maxrel = std::max(maxrel, rr);
+            {
+                Trace t(h, ASI_K_DIAG, 0.0);
+                e = asi::launch_spmv_s(n, h->rowptr, h->col, X_S, v, y, st);
+                if (e == hipSuccess) e = asi::launch_sub(nn, w, y, w, st);  // w = A^-1 v - X v
+                // two passes of classical Gram-Schmidt against v_0 .. v_j
+                if (e == hipSuccess) e = asi::launch_gs_dots(nn, j + 1, Vc, w, part, hc, st);
+                if (e == hipSuccess) e = asi::launch_gs_update(nn, j + 1, Vc, hc, w, st);
+                if (e == hipSuccess) e = asi::launch_gs_dots(nn, j + 1, Vc, w, part, hc + cols, st);
+                if (e == hipSuccess) e = asi::launch_gs_update(nn, j + 1, Vc, hc + cols, w, st);
+                if (e == hipSuccess) e = asi::launch_dot(nn, w, w, part, hc + 2 * cols, st);
+            }
+            if (e == hipSuccess) e = read(coef.data(), hc, 2 * cols + 1);
+            if (e != hipSuccess) return hip_fail(h, e, "eigs expansion");
+            for (int32_t c = 0; c <= j; ++c) {
+                const double val = coef[c] + coef[cols + c];
+                if (!std::isfinite(val)) return fail(h, ASI_E_NONFINITE, "eigs: non-finite projection");
+                T[(size_t)c * mm + j] = T[(size_t)j * mm + c] = val;
+                tnorm = std::max(tnorm, std::fabs(val));
+            }
+            beta = std::sqrt(coef[2 * cols]);
+            if (!std::isfinite(beta)) return fail(h, ASI_E_NONFINITE, "eigs: non-finite basis vector");
+            tnorm = std::max(tnorm, beta);
+            if (beta <= 1e-13 * tnorm) {  // E maps the basis into itself: the Ritz pairs are exact
+                meff = j + 1;
+                invariant = true;
+                break;
+            }
+            e = asi::launch_scale(nn, 1.0 / beta, w, st);
+            if (e != hipSuccess) return hip_fail(h, e, "eigs normalisation");
+        }
+        // Rayleigh-Ritz on T(0:meff, 0:meff)
+        Tm.assign((size_t)meff * meff, 0.0);
+        for (int32_t r = 0; r < meff; ++r)
+            for (int32_t c = 0; c < meff; ++c) Tm[(size_t)r * meff + c] = T[(size_t)r * mm + c];
+        s = asi_dense_symeig(meff, Tm.data(), theta.data(), Y.data());
+        if (s != ASI_OK) return fail(h, s, "eigs: projected eigenproblem failed");
+        order.resize(meff);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return std::fabs(theta[a]) > std::fabs(theta[b]); });
+        if (invariant && meff < k)
+            return fail(h, ASI_E_NONFINITE, "eigs: invariant subspace of dimension " + std::to_string(meff) +
+                                                " below k (choose another v0)");
+        auto res_of = [&](int32_t t) {
+            return invariant ? 0.0 : std::fabs(beta * Y[(size_t)(meff - 1) * meff + order[t]]);
+        };
+        int32_t conv = 0;
+        for (int32_t t = 0; t < k; ++t)
+            if (res_of(t) <= tol * std::fabs(theta[order[t]])) ++conv;
+        if (conv == k || restarts >= max_restarts || invariant) {
+            Ysel.assign((size_t)meff * k, 0.0);
+            for (int32_t r = 0; r < meff; ++r)
+                for (int32_t t = 0; t < k; ++t) Ysel[(size_t)r * k + t] = Y[(size_t)r * meff + order[t]];
+            e = send(Yd, Ysel.data(), Ysel.size());
+            if (e == hipSuccess) e = asi::launch_basis_combine(nn, meff, k, Vc, Yd, V, true, st);
+            if (e != hipSuccess) return hip_fail(h, e, "eigs result");
+            for (int32_t t = 0; t < k; ++t) {
+                lambda[t] = theta[order[t]];
+                if (resid) resid[t] = theta[order[t]] != 0.0 ? res_of(t) / std::fabs(theta[order[t]]) : res_of(t);
+            }
+            if (stats) {
+                stats[0] = applications;
+                stats[1] = ksteps;
+                stats[2] = restarts;
+                stats[3] = conv;
+                stats[4] = maxrel;
+            }
+            return asi_sync(h);
+        }
+        // thick restart: keep p Ritz vectors and the residual vector v_m
+        const int32_t p = k + (m - k) / 2;
+        Ysel.assign((size_t)m * p, 0.0);
+        for (int32_t r = 0; r < m; ++r)
+            for (int32_t t = 0; t < p; ++t) Ysel[(size_t)r * p + t] = Y[(size_t)r * mm + order[t]];
+        e = send(Yd, Ysel.data(), Ysel.size());
+        if (e == hipSuccess) e = asi::launch_basis_combine(nn, m, p, Vc, Yd, Vn, false, st);
+        if (e == hipSuccess) e = asi::launch_copy_f64(nn, Vc + (size_t)m * nn, Vn + (size_t)p * nn, st);
+        if (e != hipSuccess) return hip_fail(h, e, "eigs restart");
+        std::swap(Vc, Vn);
+        std::fill(T.begin(), T.end(), 0.0);
+        for (int32_t t = 0; t < p; ++t) T[(size_t)t * mm + t] = theta[order[t]];
+        j0 = p;
+        ++restarts;
+    }
 }
 
 asi_status asi_sync(asi_handle h) {

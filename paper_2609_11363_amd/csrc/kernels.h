@@ -218,6 +218,17 @@ hipError_t launch_qmr_update(int64_t n, double a, double b, const double *q, dou
 hipError_t launch_sub(int64_t n, const double *b, const double *t, double *r, hipStream_t st);
 hipError_t launch_fill_f64(int64_t n, double v, double *a, hipStream_t st);
 
+// Lanczos basis kernels (eig.hip): basis columns at V + c n, at most
+// kEigMaxBasis columns (plus the residual vector) per call
+constexpr int kEigMaxBasis = 256;
+int gs_blocks(int64_t n);  // blocks (and partials per column) of launch_gs_dots
+hipError_t launch_gs_dots(int64_t n, int32_t ncols, const double *V, const double *w, double *part, double *h,
+                          hipStream_t st);
+hipError_t launch_gs_update(int64_t n, int32_t ncols, const double *V, const double *h, double *w, hipStream_t st);
+hipError_t launch_basis_combine(int64_t n, int32_t m, int32_t p, const double *V, const double *Y, double *out,
+                                bool rowmajor, hipStream_t st);
+hipError_t launch_scale(int64_t n, double s, double *x, hipStream_t st);
+
 hipError_t launch_node_feats(const MlpFeatParams &P, hipStream_t st);
 hipError_t launch_factor_norms(int32_t n, const int64_t *Lp, const double *Lval, const int64_t *ustart,
                               const double *Lu, double *rn, hipStream_t st);

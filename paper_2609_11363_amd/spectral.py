@@ -1,9 +1,11 @@
 """Spectral correction of an approximate inverse (Section 2.5, Algorithm 1).
 
 The dominant eigenpairs of the inverse-error operator E = A^-1 - X are found
-on the host, matrix-free (ARPACK's implicitly restarted Lanczos through
-scipy), with A^-1 x supplied by the caller: the paper uses an ILDL
-preconditioned Krylov solve there; any solver more accurate than X serves.
+matrix-free, either on the device by the library's thick-restart Lanczos
+iteration (Solver.eigs_error: A^-1 x by PCG or SQMR preconditioned with the
+incomplete factor, the paper's choice) or here on the host (ARPACK's
+implicitly restarted Lanczos through scipy) with A^-1 x supplied by the
+caller, where any solver more accurate than X serves.
 Everything that touches S runs in libasi's kernels: the rank-k update on S
 (asi_lowrank), the diagonals (asi_diag) and the err_1 sums of the
 acceptance test (asi_diag_err1).
@@ -44,32 +46,6 @@ def inverse_error_eigenpairs(apply_inv, X_csr, k: int, tol: float = 1e-8, seed: 
     V = np.ascontiguousarray(V[:, order])
     res = np.array([np.linalg.norm(mv(V[:, m]) - lam[m] * V[:, m]) / abs(lam[m]) for m in range(k)])
     return lam, V, res, count[0]
-
-
-def device_error_operator(solver, A_rowptr, A_col, A_val, perm, X_S, tol: float = 1e-12, maxit: int = 1000,
-                          method: str = "cg"):
-    """E x = A^-1 x - X x with both terms on the device (Section 2.5): A^-1 x
-    by a Krylov method on P^T A P preconditioned with the loaded incomplete
-    factor, conjugate gradients for positive definite A (asi_pcg) or
-    simplified QMR for indefinite A (asi_sqmr), and X x on S (asi_spmv).
-    Returns (apply_E(x) for host float64 vectors, statistics dict with the
-    Krylov steps taken)."""
-    krylov = solver.pcg if method == "cg" else solver.sqmr
-    import torch
-    stats = {"applications": 0, "cg_steps": 0, "max_relres": 0.0}
-    dev = solver.device
-
-    def apply_E(x):
-        xt = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=dev)
-        y, steps, rr = krylov(A_rowptr, A_col, A_val, perm, xt, tol=tol, maxit=maxit)
-        z = solver.spmv(X_S, xt)
-        solver.sync()
-        stats["applications"] += 1
-        stats["cg_steps"] += steps
-        stats["max_relres"] = max(stats["max_relres"], rr)
-        return y.cpu().numpy() - z.cpu().numpy()
-
-    return apply_E, stats
 
 
 def greedy_accept(lam, evaluate):
