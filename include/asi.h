@@ -110,8 +110,10 @@ asi_status asi_get_pattern(asi_handle h, int64_t *S_rowptr_d, int32_t *S_col_d, 
  * L_val in the order of the L_col array given to asi_analyze, d_diag (n),
  * d_sub (n, the (j+1, j) entry at the first column of each 2x2 block), all
  * device float64. The library inverts the D blocks and gathers L into its
- * column layout once; asi_selinv, asi_ninv, asi_mlp_features and
- * asi_mlp_correct then take NULL for all three factor pointers to use it
+ * column layout once (the first preconditioner solve after a load also
+ * copies L's values into S's order); asi_selinv, asi_ninv,
+ * asi_mlp_features and asi_mlp_correct then take NULL for all three factor
+ * pointers to use it
  * (a call that passes the pointers works on those instead and leaves no
  * factor loaded). The caller may reuse its buffers after the stream has
  * passed this call.
@@ -362,46 +364,71 @@ asi_status asi_sqmr(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col,
                     double *relres);
 
 /*
+ * Several right-hand sides at once (the block form of the solves above, for
+ * the block eigen step): nrhs systems Ah x_v = b_v, 1 <= nrhs <= 8, B and X
+ * n x nrhs column-major float64 device arrays (vector v at B + v n; X must
+ * not overlap B or work), each vector with its own scalars, stopping test
+ * (as for asi_pcg / asi_sqmr, per vector, including SQMR's restarts) and
+ * outputs: iters[v], relres[v] (host, nrhs each). One preconditioner sweep
+ * over the level schedule serves the whole block. work: device buffer of at
+ * least asi_block_solve_work_bytes(n, nrhs) bytes, 256-byte aligned, owned
+ * by the caller (the calls leave the handle's CG vectors alone).
+ * Synchronous. Errors as for asi_pcg / asi_sqmr, and ASI_E_WORKSPACE.
+ */
+asi_status asi_block_solve_work_bytes(int32_t n, int32_t nrhs, size_t *bytes);
+asi_status asi_pcg_block(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                         const int32_t *perm, int32_t nrhs, const double *B, double *X, double tol, int32_t maxit,
+                         void *work, size_t work_bytes, int32_t *iters, double *relres);
+asi_status asi_sqmr_block(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                          const int32_t *perm, int32_t nrhs, const double *B, double *X, double tol, int32_t maxit,
+                          void *work, size_t work_bytes, int32_t *iters, double *relres);
+
+/*
  * The eigen step itself (Section 2.5, Algorithm 1: the k eigenpairs of
  * largest |lambda| of the symmetric inverse-error operator E = A^-1 - X,
  * found matrix-free with A^-1 applied by a preconditioned Krylov solve).
  *
- * asi_eigs_error: thick-restart Lanczos on E in the factor ordering. Each
- * application y = E v is a Krylov solve on Ah = P^T A P with the loaded
- * factor as preconditioner (method 0: asi_pcg, positive definite A;
- * method 1: asi_sqmr, indefinite A; solve_tol and solve_maxit as there)
- * minus asi_spmv with X_S. Every new basis vector is orthogonalised against
- * the whole basis by two passes of classical Gram-Schmidt. After m basis
+ * asi_eigs_error: thick-restart block Lanczos on E in the factor ordering,
+ * block size b = block (b = 1: plain Lanczos). Each step applies E to b
+ * basis vectors at once: a block Krylov solve on Ah = P^T A P with the
+ * loaded factor as preconditioner (method 0: block PCG, positive definite
+ * A; method 1: block SQMR, indefinite A; solve_tol and solve_maxit per
+ * vector as for asi_pcg) minus X V on S; basis vector c + b is the image of
+ * basis vector c, orthogonalised against every earlier basis vector by two
+ * passes of classical Gram-Schmidt and normalised. With m + b basis
  * vectors the host diagonalises the m x m projection T = V^T E V
  * (asi_dense_symeig) and estimates the residual of each Ritz pair
- * (theta, u) as |beta_m y_m| (beta_m: norm of the last residual vector,
- * y_m: last entry of the Ritz vector's coefficients); the call stops when
- * the k Ritz pairs of largest |theta| all satisfy ||E u - theta u|| <=
- * tol |theta| or after max_restarts restarts, else it keeps
- * k + (m - k) / 2 Ritz vectors plus the residual vector and expands again.
- * A basis vector of norm <= 1e-13 ||T||_max (an invariant subspace) ends
- * the iteration with exact Ritz pairs (ASI_E_NONFINITE if fewer than k).
+ * (theta, y) as ||C y|| (C: the b x m coupling of the last b basis vectors
+ * to the first m); the call stops when the k Ritz pairs of largest |theta|
+ * all satisfy ||E u - theta u|| <= tol |theta| or after max_restarts
+ * restarts, else it keeps min(k + (m - k) / 2, m - b) Ritz vectors plus the
+ * last b basis vectors and expands again. For b = 1 a basis vector of norm
+ * <= 1e-13 ||T||_max (an invariant subspace) ends the iteration with exact
+ * Ritz pairs (ASI_E_NONFINITE if fewer than k); for b > 1 it is an error
+ * (ASI_E_NONFINITE: the block became linearly dependent).
  *
  * A_rowptr, A_col, A_val, perm: as for asi_pcg (device). X_S: |S| float64
- * (device). v0: n float64 starting vector, nonzero (device; not modified).
- * 1 <= k <= 64; k + 2 <= m <= min(256, n - 1); tol > 0; max_restarts >= 0.
- * work: device buffer of at least asi_eigs_work_bytes(n, m) bytes, 256-byte
- * aligned, owned by the caller, contents undefined on return.
+ * (device). v0: n x b column-major float64 starting block, linearly
+ * independent columns (device; not modified). 1 <= k <= 64; 1 <= b <= 8;
+ * k + b + 1 <= m <= 256, m + b <= n; tol > 0; max_restarts >= 0.
+ * work: device buffer of at least asi_eigs_work_bytes(n, m, b) bytes,
+ * 256-byte aligned, owned by the caller, contents undefined on return.
  * Outputs: lambda (host, k float64) in decreasing |lambda| (ties by index);
  * V (device, n x k row-major float64, orthonormal columns, must not overlap
  * work); resid (host, k float64, nullable): estimated relative residuals
  * ||E u - theta u|| / |theta|; stats (host, 5 float64, nullable): operator
- * applications, Krylov steps, restarts, Ritz pairs converged among the k,
- * largest relative residual of a solve. Synchronous; uses the CG vectors
- * of the workspace (calls on one handle must not overlap). The result is
- * repeatable bit for bit. Errors: ASI_E_ARG, ASI_E_STATE (no factor),
- * ASI_E_WORKSPACE (work too small), the errors of the Krylov solves.
+ * applications (vectors), block Krylov iterations (each one preconditioner
+ * sweep over a block), restarts, Ritz pairs converged among the k, largest
+ * relative residual of a solve. Synchronous; the result is repeatable bit
+ * for bit. Errors: ASI_E_ARG, ASI_E_STATE (no factor), ASI_E_WORKSPACE (work
+ * too small), the errors of the Krylov solves.
  */
-asi_status asi_eigs_work_bytes(int32_t n, int32_t m, size_t *bytes);
+asi_status asi_eigs_work_bytes(int32_t n, int32_t m, int32_t block, size_t *bytes);
 asi_status asi_eigs_error(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
                           const int32_t *perm, const double *X_S, const double *v0, int32_t k, int32_t m,
-                          double tol, int32_t max_restarts, int32_t method, double solve_tol, int32_t solve_maxit,
-                          void *work, size_t work_bytes, double *lambda, double *V, double *resid, double *stats);
+                          int32_t block, double tol, int32_t max_restarts, int32_t method, double solve_tol,
+                          int32_t solve_maxit, void *work, size_t work_bytes, double *lambda, double *V,
+                          double *resid, double *stats);
 
 /*
  * asi_dense_symeig: all eigenpairs of a small dense symmetric matrix on the

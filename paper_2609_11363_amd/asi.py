@@ -28,7 +28,8 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_profile_read", "asi_set_sweep", "asi_mlp_features", "asi_mlp_pack", "asi_mlp_forward",
            "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor", "asi_selinv_ninv", "asi_trace", "asi_ninv_full", "asi_mix_full",
            "asi_spmv", "asi_ldl_solve", "asi_pcg", "asi_sqmr", "asi_za_diag", "asi_check_matrix",
-           "asi_eigs_work_bytes", "asi_eigs_error", "asi_dense_symeig"]
+           "asi_eigs_work_bytes", "asi_eigs_error", "asi_dense_symeig", "asi_block_solve_work_bytes",
+           "asi_pcg_block", "asi_sqmr_block"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -91,8 +92,12 @@ def load_library():
         "asi_sqmr": [P, P, P, P, P, P, P, f64, i32, P, P],
         "asi_za_diag": [P, P, P, P, P, P, P],
         "asi_check_matrix": [P, i32, P, P, P, P, f64],
-        "asi_eigs_work_bytes": [i32, i32, ctypes.POINTER(ctypes.c_size_t)],
-        "asi_eigs_error": [P, P, P, P, P, P, P, i32, i32, f64, i32, i32, f64, i32, P, ctypes.c_size_t, P, P, P, P],
+        "asi_eigs_work_bytes": [i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "asi_eigs_error": [P, P, P, P, P, P, P, i32, i32, i32, f64, i32, i32, f64, i32, P, ctypes.c_size_t, P, P, P,
+                           P],
+        "asi_block_solve_work_bytes": [i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "asi_pcg_block": [P, P, P, P, P, i32, P, P, f64, i32, P, ctypes.c_size_t, P, P],
+        "asi_sqmr_block": [P, P, P, P, P, i32, P, P, f64, i32, P, ctypes.c_size_t, P, P],
         "asi_dense_symeig": [i32, P, P, P],
         "asi_sync": [P],
         "asi_profile": [P, ctypes.c_int],
@@ -412,21 +417,23 @@ class Solver:
         """x = Ah^-1 b by simplified QMR preconditioned with the loaded factor; returns (x, steps, relres)."""
         return self._krylov(self.lib.asi_sqmr, A_rowptr, A_col, A_val, perm, b, x, tol, maxit)
 
-    def eigs_error(self, A_rowptr, A_col, A_val, perm, X, k, m=None, v0=None, seed=0, tol=1e-8, max_restarts=200,
-                   method="cg", solve_tol=1e-12, solve_maxit=1000, work=None):
+    def eigs_error(self, A_rowptr, A_col, A_val, perm, X, k, m=None, block=1, v0=None, seed=0, tol=1e-8,
+                   max_restarts=200, method="cg", solve_tol=1e-12, solve_maxit=1000, work=None):
         """k eigenpairs of E = A^-1 - X of largest |lambda| by the device
-        Lanczos iteration (A^-1 by PCG, method "cg", or SQMR, "sqmr").
-        m defaults to min(max(2k + 1, 20), n - 1); v0 (device float64[n])
-        defaults to a standard normal vector drawn with numpy from seed.
+        (block) Lanczos iteration (A^-1 by block PCG, method "cg", or block
+        SQMR, "sqmr"). m defaults to min(max(2k + 1, 20) + block - 1, 256,
+        n - block); v0 (device float64 [block, n], row v = start vector v)
+        defaults to standard normal vectors drawn with numpy from seed.
         Returns (lam numpy[k], V device [n, k] row-major, estimated relative
         residuals numpy[k], stats dict)."""
         t = self.torch
         n = self.n
-        m = int(m) if m is not None else min(max(2 * k + 1, 20), n - 1)
+        b = int(block)
+        m = int(m) if m is not None else min(max(2 * k + 1, 20) + b - 1, 256, n - b)
         if v0 is None:
-            v0 = t.as_tensor(np.random.default_rng(seed).standard_normal(n), device=self.device)
+            v0 = t.as_tensor(np.random.default_rng(seed).standard_normal((b, n)), device=self.device)
         nbytes = ctypes.c_size_t(0)
-        self._check(self.lib.asi_eigs_work_bytes(n, m, ctypes.byref(nbytes)))
+        self._check(self.lib.asi_eigs_work_bytes(n, m, b, ctypes.byref(nbytes)))
         if work is None or work.numel() * work.element_size() < nbytes.value:
             work = t.empty((nbytes.value + 7) // 8, dtype=t.float64, device=self.device)
         lam = np.zeros(k)
@@ -436,13 +443,37 @@ class Solver:
         c = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         self._stream()
         self._check(self.lib.asi_eigs_error(
-            self.h, _ptr(A_rowptr), _ptr(A_col), _ptr(A_val), _ptr(perm), _ptr(X), _ptr(v0), int(k), m, float(tol),
-            int(max_restarts), {"cg": 0, "sqmr": 1}[method], float(solve_tol), int(solve_maxit), _ptr(work),
-            work.numel() * work.element_size(), c(lam), _ptr(V), c(res), c(stats)))
+            self.h, _ptr(A_rowptr), _ptr(A_col), _ptr(A_val), _ptr(perm), _ptr(X), _ptr(v0), int(k), m, b,
+            float(tol), int(max_restarts), {"cg": 0, "sqmr": 1}[method], float(solve_tol), int(solve_maxit),
+            _ptr(work), work.numel() * work.element_size(), c(lam), _ptr(V), c(res), c(stats)))
         names = ["applications", "krylov_steps", "restarts", "converged", "max_solve_relres"]
-        st = {a: (float(b) if a == "max_solve_relres" else int(b)) for a, b in zip(names, stats)}
+        st = {a: (float(b_) if a == "max_solve_relres" else int(b_)) for a, b_ in zip(names, stats)}
         st["m"] = m
+        st["block"] = b
         return lam, V, res, st
+
+    def _block_solve(self, fn, A_rowptr, A_col, A_val, perm, B, X, tol, maxit):
+        t = self.torch
+        nrhs = int(B.shape[0])
+        X = t.empty_like(B) if X is None else X
+        nbytes = ctypes.c_size_t(0)
+        self._check(self.lib.asi_block_solve_work_bytes(self.n, nrhs, ctypes.byref(nbytes)))
+        work = t.empty((nbytes.value + 7) // 8, dtype=t.float64, device=self.device)
+        iters = np.zeros(nrhs, dtype=np.int32)
+        rel = np.zeros(nrhs)
+        c = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._stream()
+        self._check(fn(self.h, _ptr(A_rowptr), _ptr(A_col), _ptr(A_val), _ptr(perm), nrhs, _ptr(B), _ptr(X),
+                       float(tol), int(maxit), _ptr(work), work.numel() * 8, c(iters), c(rel)))
+        return X, iters, rel
+
+    def pcg_block(self, A_rowptr, A_col, A_val, perm, B, X=None, tol=1e-10, maxit=1000):
+        """Block PCG: B, X device float64 [nrhs, n] (row v = vector v); returns (X, iters, relres)."""
+        return self._block_solve(self.lib.asi_pcg_block, A_rowptr, A_col, A_val, perm, B, X, tol, maxit)
+
+    def sqmr_block(self, A_rowptr, A_col, A_val, perm, B, X=None, tol=1e-10, maxit=1000):
+        """Block SQMR: B, X device float64 [nrhs, n]; returns (X, iters, relres)."""
+        return self._block_solve(self.lib.asi_sqmr_block, A_rowptr, A_col, A_val, perm, B, X, tol, maxit)
 
     def trace(self, X, V=None, lam=None, sums=None):
         """Device float64[2]: (sum_i c_i, sum_i |c_i|), c_i = X_ii + sum_m lam_m V_im^2."""

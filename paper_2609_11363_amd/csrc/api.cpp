@@ -51,6 +51,8 @@ struct asi_handle_s {
     double *nf_dN = nullptr;
     unsigned long long *nf_bsum = nullptr;
     double *cg = nullptr;  // Krylov work vectors (5 n), dot partials (1024), scalars (16)
+    double *Ls = nullptr;         // L(max(i, j), min(i, j)) at every position of S (0 where L has none)
+    bool ls_loaded = false;       // Ls holds the loaded factor's values
     double *rn = nullptr;         // ||L(i, :)||_2, then ||L(:, i)||_2, of the factor in Lu (set with it)
     int64_t *rowptr_L = nullptr;  // the input L's row pointers
     float *Lf = nullptr;          // float32 copy of the loaded factor's L (mixed precision)
@@ -177,6 +179,7 @@ Layout make_layout(const asi::Analysis &A) {
     L.add(n * 8);                       // 39   diagonal of N
     L.add((n / 1024 + 2) * 8);          // 40   scan block sums
     L.add((5 * n + 1024 + 16) * 8);     // 41 Krylov solves: 5 vectors, dot partials, scalars
+    L.add(A.s2u.size() * 8);            // 42 L values in S's order (preconditioner solves)
     return L;
 }
 
@@ -355,6 +358,8 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->nf_dN = at<double>(b, L.off[39]);
     h->nf_bsum = at<unsigned long long>(b, L.off[40]);
     h->cg = at<double>(b, L.off[41]);
+    h->Ls = at<double>(b, L.off[42]);
+    h->ls_loaded = false;
     h->factor_loaded = false;
     h->lf_loaded = false;
     h->epoch = 0;
@@ -456,6 +461,7 @@ static asi_status prepare_factor(asi_handle h, const double *L_val, const double
             return fail(h, ASI_E_ARG, "null factor pointer (give L_val, d_diag and d_sub, or none of them)");
         h->factor_loaded = false;  // dinv (and Lu or Lf) now hold this call's factor
         h->lf_loaded = false;
+        h->ls_loaded = false;
         {
             Trace t(h, ASI_K_DINV, 0.0);
             e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
@@ -480,6 +486,22 @@ static asi_status prepare_factor(asi_handle h, const double *L_val, const double
         }
     }
     *Lu = fp64 ? h->Lu : (const void *)h->Lf;
+    return ASI_OK;
+}
+
+// L's values in S's order (Ls) for the loaded float64 factor, gathered from
+// the column layout on the first preconditioner solve after a load (a solve
+// runs the whole level schedule twice; the copy lets each row read its L
+// values in sequence instead of through the u-index).
+static asi_status ensure_ls(asi_handle h) {
+    if (h->ls_loaded) return ASI_OK;
+    if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor loaded (asi_load_factor)");
+    if (h->A.s2u.empty() && h->A.nnzS > 0) return fail(h, ASI_E_UNSUPPORTED, "solves need |S| < 2^31");
+    Trace t(h, ASI_K_GATHER, 20.0 * h->A.nnzS);
+    hipError_t e = asi::launch_build_ls(h->A.nnzS, h->s2u, reinterpret_cast<const double *>(h->Lu), h->Ls,
+                                        h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "L in S order");
+    h->ls_loaded = true;
     return ASI_OK;
 }
 
@@ -1136,8 +1158,7 @@ static asi::LdlSolveParams ldl_params(asi_handle h) {
     P.rowptr = h->rowptr;
     P.diagpos = h->diagpos;
     P.col = h->col;
-    P.s2u = h->s2u;
-    P.Lu = reinterpret_cast<const double *>(h->Lu);
+    P.Ls = h->Ls;
     P.piv = h->piv;
     P.dinv = h->dinv;
     return P;
@@ -1162,6 +1183,8 @@ asi_status asi_ldl_solve(asi_handle h, const double *x, double *y) {
     if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor loaded (asi_load_factor)");
     if (h->A.s2u.empty() && h->A.nnzS > 0) return fail(h, ASI_E_UNSUPPORTED, "solves need |S| < 2^31");
     DeviceGuard g(h->device);
+    s = ensure_ls(h);
+    if (s != ASI_OK) return s;
     Trace t(h, ASI_K_DIAG, 24.0 * h->A.nnzS + 40.0 * h->A.n);
     hipError_t e = asi::launch_ldl_solve(ldl_params(h), x, y, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "ldl solve");
@@ -1178,6 +1201,8 @@ asi_status asi_pcg(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, 
     if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor loaded (asi_load_factor)");
     if (h->A.s2u.empty() && h->A.nnzS > 0) return fail(h, ASI_E_UNSUPPORTED, "solves need |S| < 2^31");
     DeviceGuard g(h->device);
+    s = ensure_ls(h);
+    if (s != ASI_OK) return s;
     const int32_t n = h->A.n;
     const int64_t nn = n;
     double *r = h->cg, *z = r + nn, *p = z + nn, *q = p + nn, *part = q + 2 * nn, *sc = part + 1024;
@@ -1248,6 +1273,8 @@ asi_status asi_sqmr(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col,
     if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor loaded (asi_load_factor)");
     if (h->A.s2u.empty() && h->A.nnzS > 0) return fail(h, ASI_E_UNSUPPORTED, "solves need |S| < 2^31");
     DeviceGuard g(h->device);
+    s = ensure_ls(h);
+    if (s != ASI_OK) return s;
     const int32_t n = h->A.n;
     const int64_t nn = n;
     // vectors: r (residual), t (products), q (direction), u (preconditioned), d (step)
@@ -1361,69 +1388,373 @@ asi_status asi_sqmr(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col,
     return asi_sync(h);
 }
 
-// Work buffer of asi_eigs_error, in float64 slots, each region 256-byte aligned:
-// two bases of m + 1 columns (the current one and the one a restart builds),
-// the vector X v, the Gram-Schmidt partials and coefficients, the Ritz
-// coefficients sent for a restart or the result.
-struct EigLayout {
-    size_t v0, v1, y, part, hc, Y, total_bytes;
+// ---- several right-hand sides: block PCG and block SQMR --------------------
+
+// Work of the block solves, in float64 slots, each region 256-byte aligned:
+// five blocks of nv vectors (r, t, q, u, d), the dot partials, the scalars
+// (rho, rhon, sigma, rr, bb, a second rr, per vector), the QMR update
+// coefficients and the active flags.
+struct BlockSolveLayout {
+    size_t r, t, q, u, d, part, sc, coef, act, total;
 };
 
-static EigLayout eig_layout(int64_t n, int32_t m) {
-    auto up = [](size_t x) { return (x + 31) / 32 * 32; };
+static size_t up32(size_t x) { return (x + 31) / 32 * 32; }
+
+static BlockSolveLayout block_layout(int64_t n, int32_t nv) {
+    BlockSolveLayout B{};
+    const size_t blk = up32((size_t)nv * (size_t)n);
+    size_t cur = 0;
+    B.r = cur;
+    cur += blk;
+    B.t = cur;
+    cur += blk;
+    B.q = cur;
+    cur += blk;
+    B.u = cur;
+    cur += blk;
+    B.d = cur;
+    cur += blk;
+    B.part = cur;
+    cur += up32((size_t)nv * asi::dot_blocks(n));
+    B.sc = cur;
+    cur += up32(6 * (size_t)nv);
+    B.coef = cur;
+    cur += up32(2 * (size_t)nv);
+    B.act = cur;
+    cur += up32((size_t)nv);
+    B.total = cur;
+    return B;
+}
+
+asi_status asi_block_solve_work_bytes(int32_t n, int32_t nrhs, size_t *bytes) {
+    if (n < 1 || nrhs < 1 || nrhs > asi::kMaxRhs || !bytes) return ASI_E_ARG;
+    *bytes = block_layout(n, nrhs).total * 8;
+    return ASI_OK;
+}
+
+// nv systems Ah x_v = b_v at once (columns of length n), method 0: PCG, 1:
+// SQMR, each vector with its own scalars and its own stopping test; a
+// stopped vector is left alone by the masked updates. iters[v], relres[v]:
+// host outputs; *sweeps (nullable): block iterations taken.
+static asi_status block_krylov(asi_handle h, int method, const int64_t *A_rowptr, const int32_t *A_col,
+                               const double *A_val, const int32_t *perm, int32_t nv, const double *B, double *X,
+                               double tol, int32_t maxit, double *work, int32_t *iters, double *relres,
+                               int32_t *sweeps) {
+    const int32_t n = h->A.n;
+    const int64_t nn = n, nnv = nn * nv;
+    const BlockSolveLayout W = block_layout(n, nv);
+    double *r = work + W.r, *t = work + W.t, *q = work + W.q, *u = work + W.u, *d = work + W.d,
+           *part = work + W.part, *sc = work + W.sc, *coef_d = work + W.coef;
+    int32_t *act_d = reinterpret_cast<int32_t *>(work + W.act);
+    double *rho = sc, *rhon = sc + nv, *sig = sc + 2 * nv, *rr = sc + 3 * nv, *bb = sc + 4 * nv, *rr2 = sc + 5 * nv;
+    const asi::LdlSolveParams L = ldl_params(h);
+    hipStream_t st = h->stream;
+    hipError_t e;
+    auto read = [&](double *dst, const double *src, size_t cnt) {
+        hipError_t e2 = hipMemcpyAsync(dst, src, 8 * cnt, hipMemcpyDeviceToHost, st);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+        return e2;
+    };
+    std::vector<int32_t> act(nv, 0);
+    std::vector<double> coef(2 * (size_t)nv, 0.0), bn(nv, 0.0), bn2(nv, 0.0), hs(6 * (size_t)nv, 0.0);
+    auto send_act = [&]() {
+        hipError_t e2 = hipMemcpyAsync(act_d, act.data(), 4 * (size_t)nv, hipMemcpyHostToDevice, st);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+        return e2;
+    };
+    auto any_active = [&]() {
+        for (int32_t v = 0; v < nv; ++v)
+            if (act[v]) return true;
+        return false;
+    };
+    for (int32_t v = 0; v < nv; ++v) {
+        iters[v] = 0;
+        relres[v] = 0.0;
+    }
+    if (sweeps) *sweeps = 0;
+    {
+        Trace tr(h, ASI_K_DIAG, 0.0);
+        e = asi::launch_iperm(n, perm, h->iperm, h->status, st);
+        if (e == hipSuccess) e = asi::launch_fill_f64(nnv, 0.0, X, st);
+        if (e == hipSuccess) e = asi::launch_dot_m(nn, nv, B, B, part, bb, st);
+    }
+    if (e == hipSuccess) e = read(bn.data(), bb, nv);
+    if (e != hipSuccess) return hip_fail(h, e, "block solve setup");
+    for (int32_t v = 0; v < nv; ++v) {
+        if (!std::isfinite(bn[v])) return fail(h, ASI_E_NONFINITE, "block solve: non-finite right-hand side");
+        act[v] = bn[v] > 0.0;
+        bn2[v] = bn[v];
+        bn[v] = std::sqrt(bn[v]);
+    }
+    if (!any_active()) return asi_sync(h);
+    e = send_act();
+    if (e != hipSuccess) return hip_fail(h, e, "block solve flags");
+    int32_t it = 0;
+    if (method == 0) {
+        // conjugate gradients: r = b, z = M^-1 r (in u), p = z (in q), rz = r.z (in rho)
+        {
+            Trace tr(h, ASI_K_DIAG, 0.0);
+            e = asi::launch_copy_f64(nnv, B, r, st);
+            if (e == hipSuccess) e = asi::launch_ldl_solve_m(L, nv, r, u, st);
+            if (e == hipSuccess) e = asi::launch_copy_f64(nnv, u, q, st);
+            if (e == hipSuccess) e = asi::launch_dot_m(nn, nv, r, u, part, rho, st);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "block pcg setup");
+        for (it = 1; it <= maxit; ++it) {
+            {
+                Trace tr(h, ASI_K_DIAG, 0.0);
+                e = asi::launch_spmv_ahat_m(n, nv, A_rowptr, A_col, A_val, perm, h->iperm, q, t, st);
+                if (e == hipSuccess) e = asi::launch_dot_m(nn, nv, q, t, part, sig, st);
+                if (e == hipSuccess) e = asi::launch_axpy_ratio_m(nn, nv, rho, sig, act_d, 1.0, q, X, st);
+                if (e == hipSuccess) e = asi::launch_axpy_ratio_m(nn, nv, rho, sig, act_d, -1.0, t, r, st);
+                if (e == hipSuccess) e = asi::launch_dot_m(nn, nv, r, r, part, rr, st);
+            }
+            if (e == hipSuccess) e = read(hs.data(), sc, 4 * (size_t)nv);
+            if (e != hipSuccess) return hip_fail(h, e, "block pcg step");
+            if (sweeps) *sweeps = it;
+            for (int32_t v = 0; v < nv; ++v) {
+                if (!act[v]) continue;
+                const double res = std::sqrt(hs[3 * nv + v] / bn2[v]);
+                if (!(res == res)) return fail(h, ASI_E_NONFINITE, "block pcg breakdown (non-finite residual)");
+                iters[v] = it;
+                relres[v] = res;
+                if (res <= tol) act[v] = 0;
+            }
+            if (!any_active()) break;
+            e = send_act();
+            {
+                Trace tr(h, ASI_K_DIAG, 0.0);
+                if (e == hipSuccess) e = asi::launch_ldl_solve_m(L, nv, r, u, st);
+                if (e == hipSuccess) e = asi::launch_dot_m(nn, nv, r, u, part, rhon, st);
+                if (e == hipSuccess) e = asi::launch_xpby_ratio_m(nn, nv, u, rhon, rho, act_d, q, st);
+                if (e == hipSuccess) e = asi::launch_copy_f64(nv, rhon, rho, st);
+            }
+            if (e != hipSuccess) return hip_fail(h, e, "block pcg preconditioner");
+        }
+        return asi_sync(h);
+    }
+    // simplified QMR, per vector as in asi_sqmr (restart from the last
+    // iterate on a near-breakdown, at most kRestarts times per vector)
+    constexpr int kRestarts = 8;
+    std::vector<double> tau(nv, 0.0), theta(nv, 0.0);
+    std::vector<int32_t> since(nv, 0), restarts(nv, 0);
+    auto restart_one = [&](int32_t v) -> hipError_t {
+        Trace tr(h, ASI_K_DIAG, 0.0);
+        const size_t o = (size_t)v * nn;
+        hipError_t e2 = asi::launch_spmv_ahat(n, A_rowptr, A_col, A_val, perm, h->iperm, X + o, t + o, st);
+        if (e2 == hipSuccess) e2 = asi::launch_sub(nn, B + o, t + o, r + o, st);
+        if (e2 == hipSuccess) e2 = asi::launch_fill_f64(nn, 0.0, d + o, st);
+        if (e2 == hipSuccess) e2 = asi::launch_ldl_solve(L, r + o, q + o, st);
+        if (e2 == hipSuccess) e2 = asi::launch_dot(nn, r + o, q + o, part, rho + v, st);
+        if (e2 == hipSuccess) e2 = asi::launch_dot(nn, r + o, r + o, part, rr + v, st);
+        double r2 = 0.0;
+        if (e2 == hipSuccess) e2 = read(&r2, rr + v, 1);
+        tau[v] = std::sqrt(r2);
+        theta[v] = 0.0;
+        since[v] = 0;
+        return e2;
+    };
+    {
+        Trace tr(h, ASI_K_DIAG, 0.0);
+        e = asi::launch_spmv_ahat_m(n, nv, A_rowptr, A_col, A_val, perm, h->iperm, X, t, st);
+        if (e == hipSuccess) e = asi::launch_sub(nnv, B, t, r, st);
+        if (e == hipSuccess) e = asi::launch_fill_f64(nnv, 0.0, d, st);
+        if (e == hipSuccess) e = asi::launch_ldl_solve_m(L, nv, r, q, st);
+        if (e == hipSuccess) e = asi::launch_dot_m(nn, nv, r, q, part, rho, st);
+        if (e == hipSuccess) e = asi::launch_dot_m(nn, nv, r, r, part, rr, st);
+    }
+    if (e == hipSuccess) e = read(hs.data(), sc, 4 * (size_t)nv);
+    if (e != hipSuccess) return hip_fail(h, e, "block sqmr start");
+    for (int32_t v = 0; v < nv; ++v) {
+        tau[v] = std::sqrt(hs[3 * nv + v]);
+        relres[v] = bn[v] > 0.0 ? tau[v] / bn[v] : 0.0;
+    }
+    std::vector<int32_t> need_true(nv, 0), need_restart(nv, 0);
+    for (it = 1; it <= maxit; ++it) {
+        {
+            Trace tr(h, ASI_K_DIAG, 0.0);
+            e = asi::launch_spmv_ahat_m(n, nv, A_rowptr, A_col, A_val, perm, h->iperm, q, t, st);
+            if (e == hipSuccess) e = asi::launch_dot_m(nn, nv, q, t, part, sig, st);
+            if (e == hipSuccess) e = asi::launch_axpy_ratio_m(nn, nv, rho, sig, act_d, -1.0, t, r, st);
+            if (e == hipSuccess) e = asi::launch_dot_m(nn, nv, r, r, part, rr, st);
+        }
+        if (e == hipSuccess) e = read(hs.data(), sc, 4 * (size_t)nv);
+        if (e != hipSuccess) return hip_fail(h, e, "block sqmr step");
+        if (sweeps) *sweeps = it;
+        bool any_true = false;
+        for (int32_t v = 0; v < nv; ++v) {
+            need_true[v] = need_restart[v] = 0;
+            coef[2 * v] = coef[2 * v + 1] = 0.0;
+            if (!act[v]) continue;
+            iters[v] = it;
+            const double rh = hs[v], sg = hs[2 * nv + v];
+            const double alpha = rh / sg;
+            const double theta_n = std::sqrt(hs[3 * nv + v]) / tau[v];
+            const double c = 1.0 / std::sqrt(1.0 + theta_n * theta_n);
+            const double tau_n = tau[v] * theta_n * c;
+            const bool finite = std::isfinite(alpha) && std::isfinite(theta_n) && std::isfinite(tau_n) && c > 0.0;
+            if (!finite || rh == 0.0 || sg == 0.0) {
+                if (++restarts[v] > kRestarts)
+                    return fail(h, ASI_E_NONFINITE, "block sqmr breakdown of vector " + std::to_string(v) +
+                                                        " at step " + std::to_string(it) + " after " +
+                                                        std::to_string(kRestarts) + " restarts");
+                need_restart[v] = 1;  // coefficients (0, 0): d = 0 and x unchanged
+                continue;
+            }
+            coef[2 * v] = c * c * theta[v] * theta[v];
+            coef[2 * v + 1] = c * c * alpha;
+            tau[v] = tau_n;
+            theta[v] = theta_n;
+            ++since[v];
+            if (std::sqrt((double)since[v] + 1.0) * tau[v] <= tol * bn[v] || it == maxit) {
+                need_true[v] = 1;
+                any_true = true;
+            }
+        }
+        e = hipMemcpyAsync(coef_d, coef.data(), 16 * (size_t)nv, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = asi::launch_qmr_update_m(nn, nv, coef_d, act_d, q, d, X, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // coef (host) may change after this
+        if (e != hipSuccess) return hip_fail(h, e, "block sqmr update");
+        if (any_true) {
+            {
+                Trace tr(h, ASI_K_DIAG, 0.0);
+                e = asi::launch_spmv_ahat_m(n, nv, A_rowptr, A_col, A_val, perm, h->iperm, X, t, st);
+                if (e == hipSuccess) e = asi::launch_sub(nnv, B, t, u, st);
+                if (e == hipSuccess) e = asi::launch_dot_m(nn, nv, u, u, part, rr2, st);
+            }
+            if (e == hipSuccess) e = read(hs.data() + 5 * nv, rr2, nv);
+            if (e != hipSuccess) return hip_fail(h, e, "block sqmr residual");
+            for (int32_t v = 0; v < nv; ++v) {
+                if (!need_true[v]) continue;
+                relres[v] = std::sqrt(hs[5 * nv + v]) / bn[v];
+                if (relres[v] <= tol) act[v] = 0;
+            }
+        }
+        if (!any_active()) break;
+        e = send_act();
+        {
+            Trace tr(h, ASI_K_DIAG, 0.0);
+            if (e == hipSuccess) e = asi::launch_ldl_solve_m(L, nv, r, u, st);
+            if (e == hipSuccess) e = asi::launch_dot_m(nn, nv, r, u, part, rhon, st);
+            if (e == hipSuccess) e = asi::launch_xpby_ratio_m(nn, nv, u, rhon, rho, act_d, q, st);
+            if (e == hipSuccess) e = asi::launch_copy_f64(nv, rhon, rho, st);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "block sqmr preconditioner");
+        for (int32_t v = 0; v < nv; ++v)
+            if (need_restart[v] && act[v]) {
+                e = restart_one(v);
+                if (e != hipSuccess) return hip_fail(h, e, "block sqmr restart");
+            }
+    }
+    return asi_sync(h);
+}
+
+static asi_status block_solve_entry(asi_handle h, int method, const int64_t *A_rowptr, const int32_t *A_col,
+                                    const double *A_val, const int32_t *perm, int32_t nrhs, const double *B,
+                                    double *X, double tol, int32_t maxit, void *work, size_t work_bytes,
+                                    int32_t *iters, double *relres) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!A_rowptr || !A_col || !A_val || !perm || !B || !X || !work || !iters || !relres)
+        return fail(h, ASI_E_ARG, "null pointer");
+    if (nrhs < 1 || nrhs > asi::kMaxRhs) return fail(h, ASI_E_ARG, "nrhs must be in 1..8");
+    if (!(tol > 0.0) || maxit < 0) return fail(h, ASI_E_ARG, "tol must be > 0 and maxit >= 0");
+    if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor loaded (asi_load_factor)");
+    if (h->A.s2u.empty() && h->A.nnzS > 0) return fail(h, ASI_E_UNSUPPORTED, "solves need |S| < 2^31");
+    if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return fail(h, ASI_E_ARG, "work must be 256-byte aligned");
+    if (work_bytes < block_layout(h->A.n, nrhs).total * 8)
+        return fail(h, ASI_E_WORKSPACE, "work smaller than asi_block_solve_work_bytes(n, nrhs)");
+    DeviceGuard g(h->device);
+    s = ensure_ls(h);
+    if (s != ASI_OK) return s;
+    return block_krylov(h, method, A_rowptr, A_col, A_val, perm, nrhs, B, X, tol, maxit, static_cast<double *>(work),
+                        iters, relres, nullptr);
+}
+
+asi_status asi_pcg_block(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                         const int32_t *perm, int32_t nrhs, const double *B, double *X, double tol, int32_t maxit,
+                         void *work, size_t work_bytes, int32_t *iters, double *relres) {
+    return block_solve_entry(h, 0, A_rowptr, A_col, A_val, perm, nrhs, B, X, tol, maxit, work, work_bytes, iters,
+                             relres);
+}
+
+asi_status asi_sqmr_block(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                          const int32_t *perm, int32_t nrhs, const double *B, double *X, double tol, int32_t maxit,
+                          void *work, size_t work_bytes, int32_t *iters, double *relres) {
+    return block_solve_entry(h, 1, A_rowptr, A_col, A_val, perm, nrhs, B, X, tol, maxit, work, work_bytes, iters,
+                             relres);
+}
+
+// ---- the eigen step: thick-restart (block) Lanczos --------------------------
+
+// Work buffer of asi_eigs_error, in float64 slots, each region 256-byte aligned:
+// two bases of m + b columns (the current one and the one a restart builds),
+// the block X V_src, the Gram-Schmidt partials and coefficients, the Ritz
+// coefficients sent for a restart or the result, the block solves' work.
+struct EigLayout {
+    size_t v0, v1, y, part, hc, Y, solve, total_bytes;
+};
+
+static EigLayout eig_layout(int64_t n, int32_t m, int32_t b) {
     EigLayout E{};
-    const size_t cols = (size_t)m + 1;
+    const size_t cols = (size_t)m + b;
     size_t cur = 0;
     E.v0 = cur;
-    cur += up(cols * (size_t)n);
+    cur += up32(cols * (size_t)n);
     E.v1 = cur;
-    cur += up(cols * (size_t)n);
+    cur += up32(cols * (size_t)n);
     E.y = cur;
-    cur += up((size_t)n);
+    cur += up32((size_t)b * n);
     E.part = cur;
-    cur += up(std::max(cols * (size_t)asi::gs_blocks(n), (size_t)asi::dot_blocks(n)));  // also launch_dot's partials
+    cur += up32(std::max(cols * (size_t)asi::gs_blocks(n), (size_t)asi::dot_blocks(n)));  // also launch_dot's partials
     E.hc = cur;
-    cur += up(2 * cols + 1);
+    cur += up32(2 * cols + 1);
     E.Y = cur;
-    cur += up((size_t)m * m);
+    cur += up32((size_t)m * m);
+    E.solve = cur;
+    cur += block_layout(n, b).total;
     E.total_bytes = cur * 8;
     return E;
 }
 
-asi_status asi_eigs_work_bytes(int32_t n, int32_t m, size_t *bytes) {
-    if (n < 2 || m < 1 || m > asi::kEigMaxBasis || !bytes) return ASI_E_ARG;
-    *bytes = eig_layout(n, m).total_bytes;
+asi_status asi_eigs_work_bytes(int32_t n, int32_t m, int32_t block, size_t *bytes) {
+    if (n < 2 || m < 1 || m > 256 || block < 1 || block > asi::kMaxRhs || !bytes) return ASI_E_ARG;
+    *bytes = eig_layout(n, m, block).total_bytes;
     return ASI_OK;
 }
 
 asi_status asi_eigs_error(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
                           const int32_t *perm, const double *X_S, const double *v0, int32_t k, int32_t m,
-                          double tol, int32_t max_restarts, int32_t method, double solve_tol, int32_t solve_maxit,
-                          void *work, size_t work_bytes, double *lambda, double *V, double *resid, double *stats) {
+                          int32_t block, double tol, int32_t max_restarts, int32_t method, double solve_tol,
+                          int32_t solve_maxit, void *work, size_t work_bytes, double *lambda, double *V,
+                          double *resid, double *stats) {
     asi_status s = need_ready(h);
     if (s != ASI_OK) return s;
     if (!A_rowptr || !A_col || !A_val || !perm || !X_S || !v0 || !work || !lambda || !V)
         return fail(h, ASI_E_ARG, "null pointer");
     if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor loaded (asi_load_factor)");
-    const int32_t n = h->A.n;
+    if (h->A.s2u.empty() && h->A.nnzS > 0) return fail(h, ASI_E_UNSUPPORTED, "solves need |S| < 2^31");
+    const int32_t n = h->A.n, b = block;
     if (k < 1 || k > 64) return fail(h, ASI_E_ARG, "k must be in 1..64");
-    if (m < k + 2 || m > asi::kEigMaxBasis || m >= n)
-        return fail(h, ASI_E_ARG, "the basis size m must satisfy k + 2 <= m <= min(256, n - 1)");
+    if (b < 1 || b > asi::kMaxRhs) return fail(h, ASI_E_ARG, "block must be in 1..8");
+    if (m < k + b + 1 || m > 256 || (int64_t)m + b > n)
+        return fail(h, ASI_E_ARG, "the basis size m must satisfy k + block + 1 <= m <= 256 and m + block <= n");
     if (!(tol > 0.0) || max_restarts < 0 || (method != 0 && method != 1) || !(solve_tol > 0.0) || solve_maxit < 0)
         return fail(h, ASI_E_ARG, "tol > 0, max_restarts >= 0, method 0 or 1, solve_tol > 0, solve_maxit >= 0");
     if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return fail(h, ASI_E_ARG, "work must be 256-byte aligned");
-    const EigLayout E = eig_layout(n, m);
+    const EigLayout E = eig_layout(n, m, b);
     if (work_bytes < E.total_bytes)
-        return fail(h, ASI_E_WORKSPACE, "work smaller than asi_eigs_work_bytes(n, m) = " +
+        return fail(h, ASI_E_WORKSPACE, "work smaller than asi_eigs_work_bytes(n, m, block) = " +
                                              std::to_string(E.total_bytes));
     DeviceGuard g(h->device);
+    s = ensure_ls(h);
+    if (s != ASI_OK) return s;
     const int64_t nn = n;
     double *base = static_cast<double *>(work);
     double *Vc = base + E.v0, *Vn = base + E.v1, *y = base + E.y, *part = base + E.part, *hc = base + E.hc,
-           *Yd = base + E.Y;
-    const size_t cols = (size_t)m + 1;
+           *Yd = base + E.Y, *swork = base + E.solve;
+    const int32_t cols = m + b;  // basis slots: m projected vectors, then the residual block
     hipStream_t st = h->stream;
-    auto krylov = method == 0 ? asi_pcg : asi_sqmr;
     hipError_t e;
     auto read = [&](double *dst, const double *src, size_t cnt) {
         hipError_t e2 = hipMemcpyAsync(dst, src, 8 * cnt, hipMemcpyDeviceToHost, st);
@@ -1435,83 +1766,122 @@ asi_status asi_eigs_error(asi_handle h, const int64_t *A_rowptr, const int32_t *
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
         return e2;
     };
-    // v_0 = v0 / ||v0||
-    double nrm2 = 0.0;
-    e = asi::launch_dot(nn, v0, v0, part, hc, st);
-    if (e == hipSuccess) e = read(&nrm2, hc, 1);
-    if (e != hipSuccess) return hip_fail(h, e, "eigs start vector");
-    if (!(nrm2 > 0.0) || !std::isfinite(nrm2)) return fail(h, ASI_E_ARG, "v0 must be nonzero and finite");
-    e = asi::launch_copy_f64(nn, v0, Vc, st);
-    if (e == hipSuccess) e = asi::launch_scale(nn, 1.0 / std::sqrt(nrm2), Vc, st);
-    if (e != hipSuccess) return hip_fail(h, e, "eigs start vector");
+    std::vector<double> coef(2 * (size_t)cols + 1);
+    // orthogonalise column c of Vc against columns 0 .. c-1 (two classical
+    // Gram-Schmidt passes); h receives the summed coefficients, returns ||w||^2
+    auto orthogonalise = [&](int32_t c, double &norm2) -> hipError_t {
+        double *w = Vc + (size_t)c * nn;
+        hipError_t e2 = hipSuccess;
+        {
+            Trace t(h, ASI_K_DIAG, 0.0);
+            if (c > 0) {
+                e2 = asi::launch_gs_dots(nn, c, Vc, w, part, hc, st);
+                if (e2 == hipSuccess) e2 = asi::launch_gs_update(nn, c, Vc, hc, w, st);
+                if (e2 == hipSuccess) e2 = asi::launch_gs_dots(nn, c, Vc, w, part, hc + cols, st);
+                if (e2 == hipSuccess) e2 = asi::launch_gs_update(nn, c, Vc, hc + cols, w, st);
+            }
+            if (e2 == hipSuccess) e2 = asi::launch_dot(nn, w, w, part, hc + 2 * cols, st);
+        }
+        if (e2 == hipSuccess) e2 = read(coef.data(), hc, 2 * (size_t)cols + 1);
+        norm2 = coef[2 * cols];
+        return e2;
+    };
+    // start block: the columns of v0, orthonormalised in order
+    e = asi::launch_copy_f64((int64_t)b * nn, v0, Vc, st);
+    if (e != hipSuccess) return hip_fail(h, e, "eigs start block");
+    for (int32_t c = 0; c < b; ++c) {
+        double nrm2 = 0.0, raw2 = 0.0;
+        e = asi::launch_dot(nn, Vc + (size_t)c * nn, Vc + (size_t)c * nn, part, hc + 2 * cols, st);
+        if (e == hipSuccess) e = read(&raw2, hc + 2 * cols, 1);
+        if (e == hipSuccess) e = orthogonalise(c, nrm2);
+        if (e != hipSuccess) return hip_fail(h, e, "eigs start block");
+        if (!std::isfinite(raw2) || !(nrm2 > 1e-20 * raw2))
+            return fail(h, ASI_E_ARG, "v0 must have finite, linearly independent columns");
+        e = asi::launch_scale(nn, 1.0 / std::sqrt(nrm2), Vc + (size_t)c * nn, st);
+        if (e != hipSuccess) return hip_fail(h, e, "eigs start block");
+    }
 
-    const size_t mm = (size_t)m;
-    std::vector<double> T(mm * mm, 0.0), Tm, theta(mm), Y(mm * mm), coef(2 * cols + 1), Ysel;
-    std::vector<int32_t> order(mm);
+    const size_t ct = (size_t)cols, mm = (size_t)m;
+    std::vector<double> T(ct * ct, 0.0), Tm, theta(mm), Y(mm * mm), Ysel, res(mm);
+    std::vector<int32_t> order(mm), its(b);
+    std::vector<double> rel(b);
     double applications = 0.0, ksteps = 0.0, maxrel = 0.0, tnorm = 0.0;
-    int32_t restarts = 0, j0 = 0;
+    int32_t restarts = 0, q0 = b;
     for (;;) {
         int32_t meff = m;
         bool invariant = false;
-        double beta = 0.0;
-        for (int32_t j = j0; j < m; ++j) {
-            double *v = Vc + (size_t)j * nn, *w = Vc + (size_t)(j + 1) * nn;
-            int32_t its = 0;
-            double rr = 0.0;
-            s = krylov(h, A_rowptr, A_col, A_val, perm, v, w, solve_tol, solve_maxit, &its, &rr);
+        for (int32_t q = q0; q < cols && !invariant; q += b) {
+            const int32_t nb = std::min(b, cols - q), src = q - b;
+            double *Vs = Vc + (size_t)src * nn, *Wq = Vc + (size_t)q * nn;
+            // W = A^-1 V_src - X V_src for the nb sources
+            int32_t sweeps = 0;
+            s = block_krylov(h, method, A_rowptr, A_col, A_val, perm, nb, Vs, Wq, solve_tol, solve_maxit, swork,
+                             its.data(), rel.data(), &sweeps);
             if (s != ASI_OK) return s;
-            applications += 1.0;
-            ksteps += its;
-            maxrel = std::max(maxrel, rr);
+            applications += nb;
+            ksteps += sweeps;
+            for (int32_t v = 0; v < nb; ++v) maxrel = std::max(maxrel, rel[v]);
             {
                 Trace t(h, ASI_K_DIAG, 0.0);
-                e = asi::launch_spmv_s(n, h->rowptr, h->col, X_S, v, y, st);
-                if (e == hipSuccess) e = asi::launch_sub(nn, w, y, w, st);  // w = A^-1 v - X v
-                // two passes of classical Gram-Schmidt against v_0 .. v_j
-                if (e == hipSuccess) e = asi::launch_gs_dots(nn, j + 1, Vc, w, part, hc, st);
-                if (e == hipSuccess) e = asi::launch_gs_update(nn, j + 1, Vc, hc, w, st);
-                if (e == hipSuccess) e = asi::launch_gs_dots(nn, j + 1, Vc, w, part, hc + cols, st);
-                if (e == hipSuccess) e = asi::launch_gs_update(nn, j + 1, Vc, hc + cols, w, st);
-                if (e == hipSuccess) e = asi::launch_dot(nn, w, w, part, hc + 2 * cols, st);
+                e = asi::launch_spmv_s_m(n, nb, h->rowptr, h->col, X_S, Vs, y, st);
+                if (e == hipSuccess) e = asi::launch_sub((int64_t)nb * nn, Wq, y, Wq, st);
             }
-            if (e == hipSuccess) e = read(coef.data(), hc, 2 * cols + 1);
-            if (e != hipSuccess) return hip_fail(h, e, "eigs expansion");
-            for (int32_t c = 0; c <= j; ++c) {
-                const double val = coef[c] + coef[cols + c];
-                if (!std::isfinite(val)) return fail(h, ASI_E_NONFINITE, "eigs: non-finite projection");
-                T[(size_t)c * mm + j] = T[(size_t)j * mm + c] = val;
-                tnorm = std::max(tnorm, std::fabs(val));
+            if (e != hipSuccess) return hip_fail(h, e, "eigs application");
+            for (int32_t v = 0; v < nb; ++v) {
+                const int32_t c = q + v, sv = src + v;
+                double nrm2 = 0.0;
+                e = orthogonalise(c, nrm2);
+                if (e != hipSuccess) return hip_fail(h, e, "eigs expansion");
+                for (int32_t r = 0; r < c; ++r) {
+                    const double val = coef[r] + coef[cols + r];
+                    if (!std::isfinite(val)) return fail(h, ASI_E_NONFINITE, "eigs: non-finite projection");
+                    T[(size_t)r * ct + sv] = T[(size_t)sv * ct + r] = val;
+                    tnorm = std::max(tnorm, std::fabs(val));
+                }
+                const double beta = std::sqrt(nrm2);
+                if (!std::isfinite(beta)) return fail(h, ASI_E_NONFINITE, "eigs: non-finite basis vector");
+                tnorm = std::max(tnorm, beta);
+                T[(size_t)c * ct + sv] = T[(size_t)sv * ct + c] = beta;
+                if (beta <= 1e-13 * tnorm) {
+                    if (b > 1)
+                        return fail(h, ASI_E_NONFINITE, "eigs: the block became linearly dependent (use block 1 "
+                                                        "or another v0)");
+                    meff = c;  // E maps the basis into itself: the Ritz pairs are exact
+                    invariant = true;
+                    break;
+                }
+                e = asi::launch_scale(nn, 1.0 / beta, Vc + (size_t)c * nn, st);
+                if (e != hipSuccess) return hip_fail(h, e, "eigs normalisation");
             }
-            beta = std::sqrt(coef[2 * cols]);
-            if (!std::isfinite(beta)) return fail(h, ASI_E_NONFINITE, "eigs: non-finite basis vector");
-            tnorm = std::max(tnorm, beta);
-            if (beta <= 1e-13 * tnorm) {  // E maps the basis into itself: the Ritz pairs are exact
-                meff = j + 1;
-                invariant = true;
-                break;
-            }
-            e = asi::launch_scale(nn, 1.0 / beta, w, st);
-            if (e != hipSuccess) return hip_fail(h, e, "eigs normalisation");
         }
         // Rayleigh-Ritz on T(0:meff, 0:meff)
         Tm.assign((size_t)meff * meff, 0.0);
         for (int32_t r = 0; r < meff; ++r)
-            for (int32_t c = 0; c < meff; ++c) Tm[(size_t)r * meff + c] = T[(size_t)r * mm + c];
+            for (int32_t c = 0; c < meff; ++c) Tm[(size_t)r * meff + c] = T[(size_t)r * ct + c];
         s = asi_dense_symeig(meff, Tm.data(), theta.data(), Y.data());
         if (s != ASI_OK) return fail(h, s, "eigs: projected eigenproblem failed");
         order.resize(meff);
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t a, int32_t b) { return std::fabs(theta[a]) > std::fabs(theta[b]); });
+                         [&](int32_t a, int32_t c) { return std::fabs(theta[a]) > std::fabs(theta[c]); });
         if (invariant && meff < k)
             return fail(h, ASI_E_NONFINITE, "eigs: invariant subspace of dimension " + std::to_string(meff) +
                                                 " below k (choose another v0)");
-        auto res_of = [&](int32_t t) {
-            return invariant ? 0.0 : std::fabs(beta * Y[(size_t)(meff - 1) * meff + order[t]]);
-        };
+        // residual of Ritz pair t: || C y_t ||, C = T(m : m + b, 0 : m) the
+        // coupling of the residual block (zero for an invariant subspace)
+        for (int32_t t = 0; t < meff; ++t) {
+            double r2 = 0.0;
+            if (!invariant)
+                for (int32_t r = m; r < cols; ++r) {
+                    double z = 0.0;
+                    for (int32_t c = 0; c < m; ++c) z += T[(size_t)r * ct + c] * Y[(size_t)c * meff + order[t]];
+                    r2 += z * z;
+                }
+            res[t] = std::sqrt(r2);
+        }
         int32_t conv = 0;
         for (int32_t t = 0; t < k; ++t)
-            if (res_of(t) <= tol * std::fabs(theta[order[t]])) ++conv;
+            if (res[t] <= tol * std::fabs(theta[order[t]])) ++conv;
         if (conv == k || restarts >= max_restarts || invariant) {
             Ysel.assign((size_t)meff * k, 0.0);
             for (int32_t r = 0; r < meff; ++r)
@@ -1521,7 +1891,7 @@ asi_status asi_eigs_error(asi_handle h, const int64_t *A_rowptr, const int32_t *
             if (e != hipSuccess) return hip_fail(h, e, "eigs result");
             for (int32_t t = 0; t < k; ++t) {
                 lambda[t] = theta[order[t]];
-                if (resid) resid[t] = theta[order[t]] != 0.0 ? res_of(t) / std::fabs(theta[order[t]]) : res_of(t);
+                if (resid) resid[t] = theta[order[t]] != 0.0 ? res[t] / std::fabs(theta[order[t]]) : res[t];
             }
             if (stats) {
                 stats[0] = applications;
@@ -1532,19 +1902,20 @@ asi_status asi_eigs_error(asi_handle h, const int64_t *A_rowptr, const int32_t *
             }
             return asi_sync(h);
         }
-        // thick restart: keep p Ritz vectors and the residual vector v_m
-        const int32_t p = k + (m - k) / 2;
+        // thick restart: keep p Ritz vectors and the residual block
+        const int32_t p = std::min(k + (m - k) / 2, m - b);
         Ysel.assign((size_t)m * p, 0.0);
         for (int32_t r = 0; r < m; ++r)
             for (int32_t t = 0; t < p; ++t) Ysel[(size_t)r * p + t] = Y[(size_t)r * mm + order[t]];
         e = send(Yd, Ysel.data(), Ysel.size());
         if (e == hipSuccess) e = asi::launch_basis_combine(nn, m, p, Vc, Yd, Vn, false, st);
-        if (e == hipSuccess) e = asi::launch_copy_f64(nn, Vc + (size_t)m * nn, Vn + (size_t)p * nn, st);
+        if (e == hipSuccess)
+            e = asi::launch_copy_f64((int64_t)b * nn, Vc + (size_t)m * nn, Vn + (size_t)p * nn, st);
         if (e != hipSuccess) return hip_fail(h, e, "eigs restart");
         std::swap(Vc, Vn);
         std::fill(T.begin(), T.end(), 0.0);
-        for (int32_t t = 0; t < p; ++t) T[(size_t)t * mm + t] = theta[order[t]];
-        j0 = p;
+        for (int32_t t = 0; t < p; ++t) T[(size_t)t * ct + t] = theta[order[t]];
+        q0 = p + b;
         ++restarts;
     }
 }

@@ -193,11 +193,14 @@ struct LdlSolveParams {
     const int32_t *lvl_small, *lvl_big;  // host: per-level offsets into the block records
     const BlockMeta *meta_small, *meta_big;
     const int64_t *rowptr, *diagpos;
-    const int32_t *col, *s2u;
-    const double *Lu;  // float64 L in u-space
+    const int32_t *col;
+    const double *Ls;  // float64 L(max(i, j), min(i, j)) at every position of S
     const int8_t *piv;
     const double *dinv;
 };
+// Ls[p] = L(max(i, j), min(i, j)) for entry p = (i, j) of S (Lu[s2u[p]]),
+// 0 on the diagonal
+hipError_t launch_build_ls(int64_t nnzS, const int32_t *s2u, const double *Lu, double *Ls, hipStream_t st);
 hipError_t launch_spmv_s(int32_t n, const int64_t *rowptr, const int32_t *col, const double *X, const double *x,
                          double *y, hipStream_t st);
 hipError_t launch_spmv_ahat(int32_t n, const int64_t *Ap, const int32_t *Aj, const double *Av, const int32_t *perm,
@@ -218,9 +221,29 @@ hipError_t launch_qmr_update(int64_t n, double a, double b, const double *q, dou
 hipError_t launch_sub(int64_t n, const double *b, const double *t, double *r, hipStream_t st);
 hipError_t launch_fill_f64(int64_t n, double v, double *a, hipStream_t st);
 
+// Several right-hand sides at once (solve.hip): nv <= kMaxRhs vectors stored
+// as columns of length n (vector v at x + v n); dot products give nv results;
+// the masked updates touch the vectors whose act[v] is nonzero; coef holds
+// (a_v, b_v) pairs of the QMR update.
+constexpr int kMaxRhs = 8;
+hipError_t launch_ldl_solve_m(const LdlSolveParams &P, int32_t nv, const double *x, double *V, hipStream_t st);
+hipError_t launch_spmv_s_m(int32_t n, int32_t nv, const int64_t *rowptr, const int32_t *col, const double *X,
+                           const double *x, double *y, hipStream_t st);
+hipError_t launch_spmv_ahat_m(int32_t n, int32_t nv, const int64_t *Ap, const int32_t *Aj, const double *Av,
+                              const int32_t *perm, const int32_t *iperm, const double *x, double *y, hipStream_t st);
+hipError_t launch_dot_m(int64_t n, int32_t nv, const double *a, const double *b, double *part, double *out,
+                        hipStream_t st);
+hipError_t launch_axpy_ratio_m(int64_t n, int32_t nv, const double *num, const double *den, const int32_t *act,
+                               double sign, const double *X, double *Y, hipStream_t st);
+hipError_t launch_xpby_ratio_m(int64_t n, int32_t nv, const double *Z, const double *num, const double *den,
+                               const int32_t *act, double *P, hipStream_t st);
+hipError_t launch_qmr_update_m(int64_t n, int32_t nv, const double *coef, const int32_t *act, const double *Q,
+                               double *D, double *X, hipStream_t st);
+
 // Lanczos basis kernels (eig.hip): basis columns at V + c n, at most
-// kEigMaxBasis columns (plus the residual vector) per call
-constexpr int kEigMaxBasis = 256;
+// kEigMaxBasis columns per call (256 projected vectors and a residual block
+// of up to 8)
+constexpr int kEigMaxBasis = 264;
 int gs_blocks(int64_t n);  // blocks (and partials per column) of launch_gs_dots
 hipError_t launch_gs_dots(int64_t n, int32_t ncols, const double *V, const double *w, double *part, double *h,
                           hipStream_t st);

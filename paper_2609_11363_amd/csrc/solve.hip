@@ -7,7 +7,8 @@
 //   y = (L D L^T)^-1 x with the loaded factor, by the level schedule of the
 //   SelInv sweep: the rows of a level depend only on rows of other levels,
 //   forward substitution runs the levels last to first, backward first to
-//   last, each row a gather over its part of S (its L values in u-space);
+//   last, each row a pass over its part of S with its L values stored in
+//   S's order (so the row reads them in sequence) and a gather of the vector;
 // and the vector kernels of preconditioned CG and simplified QMR on Ah.
 // Every sum has a fixed order (segment lanes, then a fixed shuffle tree, and
 // fixed-order two-stage reductions), so the results repeat bit for bit.
@@ -71,8 +72,8 @@ __global__ __launch_bounds__(256) void k_ldl_level(const BlockMeta *__restrict__
                                                    const BlockMeta *__restrict__ mb, int32_t nb,
                                                    const int64_t *__restrict__ rowptr,
                                                    const int64_t *__restrict__ diagpos,
-                                                   const int32_t *__restrict__ col, const int32_t *__restrict__ s2u,
-                                                   const double *__restrict__ Lu, double *__restrict__ v) {
+                                                   const int32_t *__restrict__ col, const double *__restrict__ Ls,
+                                                   double *__restrict__ v) {
     const int32_t b = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
     const int sub = threadIdx.x % kSeg;
     if (b >= na + nb) return;  // the segment's lanes leave together
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(256) void k_ldl_level(const BlockMeta *__restrict__
         double s = 0.0;
         for (int64_t p = p0 + sub; p < p1; p += kSeg) {
             const int32_t c = col[p];
-            if (c != partner) s += Lu[s2u[p]] * v[c];
+            if (c != partner) s += Ls[p] * v[c];
         }
         s = seg_sum(s);
         if (sub == 0) v[i] -= s;
@@ -216,6 +217,188 @@ __global__ void k_iperm_only(int32_t n, const int32_t *__restrict__ perm, int32_
     iperm[p] = i;
 }
 
+__global__ void k_build_ls(int64_t nnz, const int32_t *__restrict__ s2u, const double *__restrict__ Lu,
+                           double *__restrict__ Ls) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    const int32_t u = s2u[p];
+    Ls[p] = u >= 0 ? Lu[u] : 0.0;
+}
+
+// ---- several right-hand sides at once (columns at V + v ld, v < NV) ---------
+// The same kernels with NV accumulators per row: one walk over a row's
+// entries (column, u-index, L value) serves every vector; lane v of the
+// segment writes vector v.
+
+template <bool FWD, int NV>
+__global__ __launch_bounds__(256) void k_ldl_level_m(const BlockMeta *__restrict__ ma, int32_t na,
+                                                     const BlockMeta *__restrict__ mb, int32_t nb,
+                                                     const int64_t *__restrict__ rowptr,
+                                                     const int64_t *__restrict__ diagpos,
+                                                     const int32_t *__restrict__ col, const double *__restrict__ Ls,
+                                                     int64_t ld, double *__restrict__ V) {
+    const int32_t b = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
+    const int sub = threadIdx.x % kSeg;
+    if (b >= na + nb) return;
+    const BlockMeta &M = b < na ? ma[b] : mb[b - na];
+    const int rows = M.two ? 2 : 1;
+    for (int t = 0; t < rows; ++t) {
+        const int32_t i = M.j + t;
+        const int32_t partner = M.two ? M.j + 1 - t : -1;
+        const int64_t p0 = FWD ? rowptr[i] : diagpos[i] + 1;
+        const int64_t p1 = FWD ? diagpos[i] : rowptr[i + 1];
+        double s[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s[v] = 0.0;
+        for (int64_t p = p0 + sub; p < p1; p += kSeg) {
+            const int32_t c = col[p];
+            if (c != partner) {
+                const double l = Ls[p];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) s[v] += l * V[v * ld + c];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            s[v] = seg_sum(s[v]);
+            if (sub == v) V[v * ld + i] -= s[v];
+        }
+    }
+}
+
+__global__ void k_ldl_diag_m(int32_t n, int32_t nv, int64_t ld, const int8_t *__restrict__ piv,
+                             const double *__restrict__ dinv, double *__restrict__ V) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (int64_t)n * nv) return;
+    const int32_t v = (int32_t)(x / n), j = (int32_t)(x % n);
+    if (piv[j] == 2) return;
+    double *w = V + v * ld;
+    const double *iv = dinv + 3 * (int64_t)j;
+    if (piv[j] == 1) {
+        const double a = w[j], c = w[j + 1];
+        w[j] = iv[0] * a + iv[1] * c;
+        w[j + 1] = iv[1] * a + iv[2] * c;
+    } else {
+        w[j] = iv[0] * w[j];
+    }
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_spmv_s_m(int32_t n, const int64_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ X,
+                                                  int64_t ld, const double *__restrict__ x, double *__restrict__ y) {
+    const int32_t i = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
+    const int sub = threadIdx.x % kSeg;
+    double s[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[v] = 0.0;
+    if (i < n)
+        for (int64_t p = rowptr[i] + sub; p < rowptr[i + 1]; p += kSeg) {
+            const double a = X[p];
+            const int32_t c = col[p];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s[v] += a * x[v * ld + c];
+        }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        s[v] = seg_sum(s[v]);
+        if (i < n && sub == v) y[v * ld + i] = s[v];
+    }
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_spmv_ahat_m(int32_t n, const int64_t *__restrict__ Ap,
+                                                     const int32_t *__restrict__ Aj, const double *__restrict__ Av,
+                                                     const int32_t *__restrict__ perm,
+                                                     const int32_t *__restrict__ iperm, int64_t ld,
+                                                     const double *__restrict__ x, double *__restrict__ y) {
+    const int32_t i = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
+    const int sub = threadIdx.x % kSeg;
+    double s[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[v] = 0.0;
+    if (i < n) {
+        const int32_t r = perm[i];
+        for (int64_t p = Ap[r] + sub; p < Ap[r + 1]; p += kSeg) {
+            const double a = Av[p];
+            const int32_t c = iperm[Aj[p]];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s[v] += a * x[v * ld + c];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        s[v] = seg_sum(s[v]);
+        if (i < n && sub == v) y[v * ld + i] = s[v];
+    }
+}
+
+// part[v nb + b] = partial of a_v . b_v over block b's grid stride (block
+// row blockIdx.y = v); out[v] = the partials of v in index order
+__global__ __launch_bounds__(256) void k_dotm_part(int64_t n, int64_t ld, const double *__restrict__ a,
+                                                   const double *__restrict__ b, double *__restrict__ part) {
+    __shared__ double s[4];
+    const int64_t off = (int64_t)blockIdx.y * ld;
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        v += a[off + i] * b[off + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+__global__ __launch_bounds__(256) void k_dotm_final(int nb, const double *__restrict__ part,
+                                                    double *__restrict__ out) {
+    __shared__ double s[4];
+    double v = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) v += part[(int64_t)blockIdx.x * nb + q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// Y_v += sign (num_v / den_v) X_v for the vectors with act[v] != 0
+__global__ void k_axpy_ratio_m(int64_t n, int32_t nv, int64_t ld, const double *__restrict__ num,
+                               const double *__restrict__ den, const int32_t *__restrict__ act, double sign,
+                               const double *__restrict__ X, double *__restrict__ Y) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n * nv) return;
+    const int32_t v = (int32_t)(x / n);
+    if (!act[v]) return;
+    const int64_t i = v * ld + x % n;
+    Y[i] += sign * (num[v] / den[v]) * X[i];
+}
+
+// P_v = Z_v + (num_v / den_v) P_v for the vectors with act[v] != 0
+__global__ void k_xpby_ratio_m(int64_t n, int32_t nv, int64_t ld, const double *__restrict__ Z,
+                               const double *__restrict__ num, const double *__restrict__ den,
+                               const int32_t *__restrict__ act, double *__restrict__ P) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n * nv) return;
+    const int32_t v = (int32_t)(x / n);
+    if (!act[v]) return;
+    const int64_t i = v * ld + x % n;
+    P[i] = Z[i] + (num[v] / den[v]) * P[i];
+}
+
+// D_v = coef[2v] D_v + coef[2v + 1] Q_v, X_v += D_v for the vectors with act[v] != 0
+__global__ void k_qmr_update_m(int64_t n, int32_t nv, int64_t ld, const double *__restrict__ coef,
+                               const int32_t *__restrict__ act, const double *__restrict__ Q,
+                               double *__restrict__ D, double *__restrict__ X) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n * nv) return;
+    const int32_t v = (int32_t)(x / n);
+    if (!act[v]) return;
+    const int64_t i = v * ld + x % n;
+    const double w = coef[2 * v] * D[i] + coef[2 * v + 1] * Q[i];
+    D[i] = w;
+    X[i] += w;
+}
+
 }  // namespace dev
 
 static dim3 seg_grid(int64_t rows) { return dim3((unsigned)((rows * dev::kSeg + 255) / 256)); }
@@ -258,7 +441,7 @@ hipError_t launch_ldl_solve(const LdlSolveParams &P, const double *x, double *v,
         const int32_t na = P.lvl_small[l + 1] - P.lvl_small[l], nb = P.lvl_big[l + 1] - P.lvl_big[l];
         if (na + nb == 0) continue;
         hipLaunchKernelGGL(dev::k_ldl_level<true>, seg_grid(na + nb), dim3(256), 0, st, P.meta_small + P.lvl_small[l],
-                           na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos, P.col, P.s2u, P.Lu, v);
+                           na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos, P.col, P.Ls, v);
     }
     hipLaunchKernelGGL(dev::k_ldl_diag, elem_grid(n), dim3(256), 0, st, n, P.piv, P.dinv, v);
     for (int32_t l = 0; l < P.n_levels; ++l) {
@@ -266,7 +449,7 @@ hipError_t launch_ldl_solve(const LdlSolveParams &P, const double *x, double *v,
         if (na + nb == 0) continue;
         hipLaunchKernelGGL(dev::k_ldl_level<false>, seg_grid(na + nb), dim3(256), 0, st,
                            P.meta_small + P.lvl_small[l], na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos,
-                           P.col, P.s2u, P.Lu, v);
+                           P.col, P.Ls, v);
     }
     return hipGetLastError();
 }
@@ -309,6 +492,106 @@ hipError_t launch_copy_f64(int64_t n, const double *a, double *b, hipStream_t st
 
 hipError_t launch_fill_f64(int64_t n, double v, double *a, hipStream_t st) {
     hipLaunchKernelGGL(dev::k_fill_f64, elem_grid(n), dim3(256), 0, st, n, v, a);
+    return hipGetLastError();
+}
+
+
+// ---- launchers of the several-right-hand-side kernels ------------------------
+
+#define ASI_NV_SWITCH(nv, CALL)                                                                                       \
+    switch (nv) {                                                                                                     \
+        case 1: CALL(1); break;                                                                                       \
+        case 2: CALL(2); break;                                                                                       \
+        case 3: CALL(3); break;                                                                                       \
+        case 4: CALL(4); break;                                                                                       \
+        case 5: CALL(5); break;                                                                                       \
+        case 6: CALL(6); break;                                                                                       \
+        case 7: CALL(7); break;                                                                                       \
+        case 8: CALL(8); break;                                                                                       \
+        default: return hipErrorInvalidValue;                                                                         \
+    }
+
+hipError_t launch_ldl_solve_m(const LdlSolveParams &P, int32_t nv, const double *x, double *V, hipStream_t st) {
+    const int32_t n = P.n;
+    if (n <= 0) return hipSuccess;
+    if (nv < 1 || nv > kMaxRhs) return hipErrorInvalidValue;
+    const int64_t ld = n;
+    if (x != V) hipLaunchKernelGGL(dev::k_copy_f64, elem_grid((int64_t)n * nv), dim3(256), 0, st, (int64_t)n * nv, x, V);
+    for (int32_t l = P.n_levels - 1; l >= 0; --l) {
+        const int32_t na = P.lvl_small[l + 1] - P.lvl_small[l], nb = P.lvl_big[l + 1] - P.lvl_big[l];
+        if (na + nb == 0) continue;
+#define ASI_FWD(K)                                                                                                    \
+    hipLaunchKernelGGL((dev::k_ldl_level_m<true, K>), seg_grid(na + nb), dim3(256), 0, st,                           \
+                       P.meta_small + P.lvl_small[l], na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos, P.col, \
+                       P.Ls, ld, V)
+        ASI_NV_SWITCH(nv, ASI_FWD)
+#undef ASI_FWD
+    }
+    hipLaunchKernelGGL(dev::k_ldl_diag_m, elem_grid((int64_t)n * nv), dim3(256), 0, st, n, nv, ld, P.piv, P.dinv, V);
+    for (int32_t l = 0; l < P.n_levels; ++l) {
+        const int32_t na = P.lvl_small[l + 1] - P.lvl_small[l], nb = P.lvl_big[l + 1] - P.lvl_big[l];
+        if (na + nb == 0) continue;
+#define ASI_BWD(K)                                                                                                    \
+    hipLaunchKernelGGL((dev::k_ldl_level_m<false, K>), seg_grid(na + nb), dim3(256), 0, st,                          \
+                       P.meta_small + P.lvl_small[l], na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos, P.col, \
+                       P.Ls, ld, V)
+        ASI_NV_SWITCH(nv, ASI_BWD)
+#undef ASI_BWD
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_s_m(int32_t n, int32_t nv, const int64_t *rowptr, const int32_t *col, const double *X,
+                           const double *x, double *y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+#define ASI_SPMV(K) \
+    hipLaunchKernelGGL((dev::k_spmv_s_m<K>), seg_grid(n), dim3(256), 0, st, n, rowptr, col, X, (int64_t)n, x, y)
+    ASI_NV_SWITCH(nv, ASI_SPMV)
+#undef ASI_SPMV
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_ahat_m(int32_t n, int32_t nv, const int64_t *Ap, const int32_t *Aj, const double *Av,
+                              const int32_t *perm, const int32_t *iperm, const double *x, double *y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+#define ASI_SPMVA(K)                                                                                       \
+    hipLaunchKernelGGL((dev::k_spmv_ahat_m<K>), seg_grid(n), dim3(256), 0, st, n, Ap, Aj, Av, perm, iperm, \
+                       (int64_t)n, x, y)
+    ASI_NV_SWITCH(nv, ASI_SPMVA)
+#undef ASI_SPMVA
+    return hipGetLastError();
+}
+
+hipError_t launch_dot_m(int64_t n, int32_t nv, const double *a, const double *b, double *part, double *out,
+                        hipStream_t st) {
+    if (nv < 1 || nv > kMaxRhs) return hipErrorInvalidValue;
+    const int nb = dot_blocks(n);
+    hipLaunchKernelGGL(dev::k_dotm_part, dim3(nb, nv), dim3(256), 0, st, n, n, a, b, part);
+    hipLaunchKernelGGL(dev::k_dotm_final, dim3(nv), dim3(256), 0, st, nb, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_ratio_m(int64_t n, int32_t nv, const double *num, const double *den, const int32_t *act,
+                               double sign, const double *X, double *Y, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_axpy_ratio_m, elem_grid(n * nv), dim3(256), 0, st, n, nv, n, num, den, act, sign, X, Y);
+    return hipGetLastError();
+}
+
+hipError_t launch_xpby_ratio_m(int64_t n, int32_t nv, const double *Z, const double *num, const double *den,
+                               const int32_t *act, double *P, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_xpby_ratio_m, elem_grid(n * nv), dim3(256), 0, st, n, nv, n, Z, num, den, act, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_qmr_update_m(int64_t n, int32_t nv, const double *coef, const int32_t *act, const double *Q,
+                               double *D, double *X, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_qmr_update_m, elem_grid(n * nv), dim3(256), 0, st, n, nv, n, coef, act, Q, D, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_ls(int64_t nnzS, const int32_t *s2u, const double *Lu, double *Ls, hipStream_t st) {
+    if (nnzS <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::k_build_ls, elem_grid(nnzS), dim3(256), 0, st, nnzS, s2u, Lu, Ls);
     return hipGetLastError();
 }
 

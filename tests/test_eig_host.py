@@ -45,15 +45,25 @@ def test_dense_symeig_closed_form_and_degenerate_inputs():
         dense_symeig(np.zeros((0, 0)))
 
 
-def test_eigs_work_bytes_layout():
+def test_eigs_and_block_solve_work_bytes_layout():
     lib = load_library()
     out = ctypes.c_size_t(0)
-    n, m = 100000, 20
-    assert lib.asi_eigs_work_bytes(n, m, ctypes.byref(out)) == 0
     up = lambda x: (x + 31) // 32 * 32
-    nb = max(1, min(1024, (n + 1023) // 1024))
-    part = max((m + 1) * nb, min(1024, (n + 255) // 256))
-    expect = 8 * (2 * up((m + 1) * n) + up(n) + up(part) + up(2 * (m + 1) + 1) + up(m * m))
-    assert out.value == expect
-    assert lib.asi_eigs_work_bytes(n, 257, ctypes.byref(out)) == 1  # m above the basis limit
-    assert lib.asi_eigs_work_bytes(1, 2, ctypes.byref(out)) == 1
+    n = 100000
+    dotb = min(1024, (n + 255) // 256)
+    for nrhs in (1, 3, 8):
+        assert lib.asi_block_solve_work_bytes(n, nrhs, ctypes.byref(out)) == 0
+        solve = 5 * up(nrhs * n) + up(nrhs * dotb) + up(6 * nrhs) + up(2 * nrhs) + up(nrhs)
+        assert out.value == 8 * solve
+    assert lib.asi_block_solve_work_bytes(n, 9, ctypes.byref(out)) == 1
+    for m, b in ((20, 1), (40, 4)):
+        assert lib.asi_eigs_work_bytes(n, m, b, ctypes.byref(out)) == 0
+        nb = max(1, min(1024, (n + 1023) // 1024))
+        cols = m + b
+        part = max(cols * nb, dotb)
+        solve = 5 * up(b * n) + up(b * dotb) + up(6 * b) + up(2 * b) + up(b)
+        expect = 8 * (2 * up(cols * n) + up(b * n) + up(part) + up(2 * cols + 1) + up(m * m) + solve)
+        assert out.value == expect
+    assert lib.asi_eigs_work_bytes(n, 257, 1, ctypes.byref(out)) == 1  # m above the basis limit
+    assert lib.asi_eigs_work_bytes(n, 20, 9, ctypes.byref(out)) == 1   # block above 8
+    assert lib.asi_eigs_work_bytes(1, 2, 1, ctypes.byref(out)) == 1

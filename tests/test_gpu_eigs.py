@@ -62,13 +62,15 @@ def _check(A, F, X, lam, V, k, rtol):
     assert res <= 1e-6
 
 
-@pytest.mark.parametrize("name,method,k,m", [("cov20", "cg", 3, 20), ("cov20", "cg", 6, 14),
-                                             ("indef24", "sqmr", 3, 20), ("kkt", "sqmr", 2, 16)])
-def test_eigs_matches_oracle(name, method, k, m):
+@pytest.mark.parametrize("name,method,k,m,block", [("cov20", "cg", 3, 20, 1), ("cov20", "cg", 6, 14, 1),
+                                                   ("indef24", "sqmr", 3, 20, 1), ("kkt", "sqmr", 2, 16, 1),
+                                                   ("cov20", "cg", 3, 24, 4), ("cov20", "cg", 6, 21, 3),
+                                                   ("indef24", "sqmr", 3, 24, 4), ("kkt", "sqmr", 2, 16, 8)])
+def test_eigs_matches_oracle(name, method, k, m, block):
     A, F, X, s, args = _setup(name)
-    print(f"[eigs] {name} n={F.n} method={method} k={k} m={m}", flush=True)
+    print(f"[eigs] {name} n={F.n} method={method} k={k} m={m} block={block}", flush=True)
     solve_tol = 1e-12 if method == "cg" else 1e-11
-    lam, V, res, st = s.eigs_error(*args, k, m=m, tol=1e-10, method=method, solve_tol=solve_tol,
+    lam, V, res, st = s.eigs_error(*args, k, m=m, block=block, tol=1e-10, method=method, solve_tol=solve_tol,
                                    solve_maxit=3000)
     s.sync()
     print(f"  stats {st}, estimated residuals {res}", flush=True)
@@ -100,6 +102,10 @@ def test_eigs_argument_checks():
     with pytest.raises(AsiError, match="ASI_E_ARG"):
         s.eigs_error(*args, 3, m=4)                      # m < k + 2
     with pytest.raises(AsiError, match="ASI_E_ARG"):
+        s.eigs_error(*args, 3, m=7, block=4)             # m < k + block + 1
+    with pytest.raises(AsiError, match="ASI_E_ARG"):    # dependent start columns
+        s.eigs_error(*args, 2, m=12, block=2, v0=torch.ones((2, F.n), dtype=torch.float64, device=s.device))
+    with pytest.raises(AsiError, match="ASI_E_ARG"):
         s.eigs_error(*args, 65, m=200)                   # k > 64
     with pytest.raises(AsiError, match="ASI_E_ARG"):
         s.eigs_error(*args, 1, v0=torch.zeros(F.n, dtype=torch.float64, device=s.device))
@@ -113,6 +119,6 @@ def test_eigs_argument_checks():
     V = torch.empty((F.n, 2), dtype=torch.float64, device=s.device)
     v0 = torch.ones(F.n, dtype=torch.float64, device=s.device)
     p = lambda x: ctypes.c_void_p(x.data_ptr())
-    rc = s.lib.asi_eigs_error(s.h, *[p(a) for a in args], p(v0), 2, 8, 1e-8, 10, 0, 1e-12, 100, p(small),
+    rc = s.lib.asi_eigs_error(s.h, *[p(a) for a in args], p(v0), 2, 8, 1, 1e-8, 10, 0, 1e-12, 100, p(small),
                               small.numel() * 8, lam.ctypes.data_as(ctypes.c_void_p), p(V), None, None)
     assert rc == 6  # ASI_E_WORKSPACE

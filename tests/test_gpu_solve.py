@@ -171,3 +171,46 @@ def test_za_diag(name):
     s.sync()
     want = oc.za_diag(S, Z, oc.permuted(A, F.perm))
     np.testing.assert_allclose(d.cpu().numpy(), want, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("name,method,nrhs", [("cov20", "cg", 3), ("diff12", "cg", 8), ("indef24", "sqmr", 4),
+                                              ("kkt", "sqmr", 2)])
+def test_block_solves_equal_single_solves(name, method, nrhs):
+    """Several right-hand sides at once: each column equals the one-vector
+    solve bit for bit (same kernels' arithmetic, per-vector scalars and
+    stopping), including a zero column that never starts."""
+    import torch
+    from paper_2609_11363_amd import Solver, upload_factors
+    from workloads import shifted_laplace2d_indefinite
+    if name == "indef24":
+        A, _ = shifted_laplace2d_indefinite(24, 4)
+        F = ildl_bk(A, nested_multicolor_grid((24, 24)), 1e-2)
+    else:
+        A, F = _case(name)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    s.load_factor(*upload_factors(F))
+    dev = s.device
+    Ar = torch.as_tensor(A.indptr.astype(np.int64), device=dev)
+    Ac = torch.as_tensor(A.indices.astype(np.int32), device=dev)
+    Av = torch.as_tensor(A.data, device=dev)
+    perm = torch.as_tensor(F.perm.astype(np.int32), device=dev)
+    B = np.random.default_rng(11).standard_normal((nrhs, F.n))
+    B[nrhs - 1] = 0.0
+    Bt = torch.as_tensor(B, device=dev)
+    tol = 1e-11
+    print(f"[block] {name} {method} nrhs={nrhs} n={F.n}", flush=True)
+    blk = s.pcg_block if method == "cg" else s.sqmr_block
+    one = s.pcg if method == "cg" else s.sqmr
+    X, iters, rel = blk(Ar, Ac, Av, perm, Bt, tol=tol, maxit=3000)
+    s.sync()
+    Ah = oc.permuted(A, F.perm)
+    for v in range(nrhs):
+        x1, it1, rr1 = one(Ar, Ac, Av, perm, Bt[v].contiguous(), tol=tol, maxit=3000)
+        s.sync()
+        print(f"  vector {v}: block {iters[v]} steps {rel[v]:.1e}, single {it1} steps {rr1:.1e}", flush=True)
+        assert torch.equal(X[v], x1) and iters[v] == it1 and rel[v] == rr1
+        if v < nrhs - 1:
+            xg = X[v].cpu().numpy()
+            assert np.linalg.norm(Ah @ xg - B[v]) / np.linalg.norm(B[v]) <= 2 * tol
+    assert not X[nrhs - 1].abs().max().item() and iters[nrhs - 1] == 0
