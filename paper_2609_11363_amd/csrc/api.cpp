@@ -1391,11 +1391,12 @@ asi_status asi_sqmr(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col,
 // ---- several right-hand sides: block PCG and block SQMR --------------------
 
 // Work of the block solves, in float64 slots, each region 256-byte aligned:
-// five blocks of nv vectors (r, t, q, u, d), the dot partials, the scalars
-// (rho, rhon, sigma, rr, bb, a second rr, per vector), the QMR update
-// coefficients and the active flags.
+// seven interleaved blocks of nv vectors (r, t, q, u, d, and the right-hand
+// sides and iterates), the dot partials, the scalars (rho, rhon, sigma, rr,
+// bb, a second rr, per vector), the QMR update coefficients, the active
+// flags and the restart flags.
 struct BlockSolveLayout {
-    size_t r, t, q, u, d, part, sc, coef, act, total;
+    size_t r, t, q, u, d, b, x, part, sc, coef, act, sel, total;
 };
 
 static size_t up32(size_t x) { return (x + 31) / 32 * 32; }
@@ -1414,6 +1415,10 @@ static BlockSolveLayout block_layout(int64_t n, int32_t nv) {
     cur += blk;
     B.d = cur;
     cur += blk;
+    B.b = cur;
+    cur += blk;
+    B.x = cur;
+    cur += blk;
     B.part = cur;
     cur += up32((size_t)nv * asi::dot_blocks(n));
     B.sc = cur;
@@ -1421,6 +1426,8 @@ static BlockSolveLayout block_layout(int64_t n, int32_t nv) {
     B.coef = cur;
     cur += up32(2 * (size_t)nv);
     B.act = cur;
+    cur += up32((size_t)nv);
+    B.sel = cur;
     cur += up32((size_t)nv);
     B.total = cur;
     return B;
@@ -1432,20 +1439,43 @@ asi_status asi_block_solve_work_bytes(int32_t n, int32_t nrhs, size_t *bytes) {
     return ASI_OK;
 }
 
-// nv systems Ah x_v = b_v at once (columns of length n), method 0: PCG, 1:
-// SQMR, each vector with its own scalars and its own stopping test; a
-// stopped vector is left alone by the masked updates. iters[v], relres[v]:
-// host outputs; *sweeps (nullable): block iterations taken.
+static asi_status block_krylov_run(asi_handle h, int method, const int64_t *A_rowptr, const int32_t *A_col,
+                                   const double *A_val, const int32_t *perm, int32_t nv, const double *B, double *X,
+                                   double tol, int32_t maxit, double *work, int32_t *iters, double *relres,
+                                   int32_t *sweeps);
+
+// nv systems Ah x_v = b_v at once (B, X column-major, vector v at B + v n),
+// method 0: PCG, 1: SQMR, each vector with its own scalars and its own
+// stopping test; a stopped vector is left alone by the masked updates. The
+// iteration works on interleaved copies. iters[v], relres[v]: host outputs;
+// *sweeps (nullable): block iterations taken.
 static asi_status block_krylov(asi_handle h, int method, const int64_t *A_rowptr, const int32_t *A_col,
                                const double *A_val, const int32_t *perm, int32_t nv, const double *B, double *X,
                                double tol, int32_t maxit, double *work, int32_t *iters, double *relres,
                                int32_t *sweeps) {
+    const BlockSolveLayout W = block_layout(h->A.n, nv);
+    double *bi = work + W.b, *xi = work + W.x;
+    hipError_t e = asi::launch_interleave(h->A.n, nv, true, B, bi, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "block solve layout");
+    asi_status s = block_krylov_run(h, method, A_rowptr, A_col, A_val, perm, nv, bi, xi, tol, maxit, work, iters,
+                                    relres, sweeps);
+    if (s != ASI_OK) return s;
+    e = asi::launch_interleave(h->A.n, nv, false, xi, X, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "block solve layout");
+    return asi_sync(h);
+}
+
+static asi_status block_krylov_run(asi_handle h, int method, const int64_t *A_rowptr, const int32_t *A_col,
+                                   const double *A_val, const int32_t *perm, int32_t nv, const double *B, double *X,
+                                   double tol, int32_t maxit, double *work, int32_t *iters, double *relres,
+                                   int32_t *sweeps) {
     const int32_t n = h->A.n;
     const int64_t nn = n, nnv = nn * nv;
     const BlockSolveLayout W = block_layout(n, nv);
     double *r = work + W.r, *t = work + W.t, *q = work + W.q, *u = work + W.u, *d = work + W.d,
            *part = work + W.part, *sc = work + W.sc, *coef_d = work + W.coef;
     int32_t *act_d = reinterpret_cast<int32_t *>(work + W.act);
+    int32_t *sel_d = reinterpret_cast<int32_t *>(work + W.sel);
     double *rho = sc, *rhon = sc + nv, *sig = sc + 2 * nv, *rr = sc + 3 * nv, *bb = sc + 4 * nv, *rr2 = sc + 5 * nv;
     const asi::LdlSolveParams L = ldl_params(h);
     hipStream_t st = h->stream;
@@ -1538,20 +1568,30 @@ static asi_status block_krylov(asi_handle h, int method, const int64_t *A_rowptr
     constexpr int kRestarts = 8;
     std::vector<double> tau(nv, 0.0), theta(nv, 0.0);
     std::vector<int32_t> since(nv, 0), restarts(nv, 0);
-    auto restart_one = [&](int32_t v) -> hipError_t {
-        Trace tr(h, ASI_K_DIAG, 0.0);
-        const size_t o = (size_t)v * nn;
-        hipError_t e2 = asi::launch_spmv_ahat(n, A_rowptr, A_col, A_val, perm, h->iperm, X + o, t + o, st);
-        if (e2 == hipSuccess) e2 = asi::launch_sub(nn, B + o, t + o, r + o, st);
-        if (e2 == hipSuccess) e2 = asi::launch_fill_f64(nn, 0.0, d + o, st);
-        if (e2 == hipSuccess) e2 = asi::launch_ldl_solve(L, r + o, q + o, st);
-        if (e2 == hipSuccess) e2 = asi::launch_dot(nn, r + o, q + o, part, rho + v, st);
-        if (e2 == hipSuccess) e2 = asi::launch_dot(nn, r + o, r + o, part, rr + v, st);
-        double r2 = 0.0;
-        if (e2 == hipSuccess) e2 = read(&r2, rr + v, 1);
-        tau[v] = std::sqrt(r2);
-        theta[v] = 0.0;
-        since[v] = 0;
+    // restart the vectors flagged in need: r = b - Ah x, d = 0, q = M^-1 r,
+    // rho = r.q, tau = ||r|| for those only (the others' vectors and scalars
+    // are left as they are; t, u and the second rr slot are scratch)
+    auto restart_flagged = [&](const std::vector<int32_t> &need) -> hipError_t {
+        hipError_t e2 = hipMemcpyAsync(sel_d, need.data(), 4 * (size_t)nv, hipMemcpyHostToDevice, st);
+        {
+            Trace tr(h, ASI_K_DIAG, 0.0);
+            if (e2 == hipSuccess)
+                e2 = asi::launch_spmv_ahat_m(n, nv, A_rowptr, A_col, A_val, perm, h->iperm, X, t, st);
+            if (e2 == hipSuccess) e2 = asi::launch_select_m(nn, nv, sel_d, 1, B, t, r, st);
+            if (e2 == hipSuccess) e2 = asi::launch_select_m(nn, nv, sel_d, 2, nullptr, nullptr, d, st);
+            if (e2 == hipSuccess) e2 = asi::launch_ldl_solve_m(L, nv, r, u, st);
+            if (e2 == hipSuccess) e2 = asi::launch_select_m(nn, nv, sel_d, 0, nullptr, u, q, st);
+            if (e2 == hipSuccess) e2 = asi::launch_dot_m(nn, nv, r, q, part, rr2, st);
+            if (e2 == hipSuccess) e2 = asi::launch_select_m(1, nv, sel_d, 0, nullptr, rr2, rho, st);
+            if (e2 == hipSuccess) e2 = asi::launch_dot_m(nn, nv, r, r, part, rr2, st);
+        }
+        if (e2 == hipSuccess) e2 = read(hs.data() + 5 * nv, rr2, nv);
+        for (int32_t v = 0; v < nv; ++v) {
+            if (!need[v]) continue;
+            tau[v] = std::sqrt(hs[5 * nv + v]);
+            theta[v] = 0.0;
+            since[v] = 0;
+        }
         return e2;
     };
     {
@@ -1640,11 +1680,15 @@ static asi_status block_krylov(asi_handle h, int method, const int64_t *A_rowptr
             if (e == hipSuccess) e = asi::launch_copy_f64(nv, rhon, rho, st);
         }
         if (e != hipSuccess) return hip_fail(h, e, "block sqmr preconditioner");
-        for (int32_t v = 0; v < nv; ++v)
-            if (need_restart[v] && act[v]) {
-                e = restart_one(v);
-                if (e != hipSuccess) return hip_fail(h, e, "block sqmr restart");
-            }
+        bool any_restart = false;
+        for (int32_t v = 0; v < nv; ++v) {
+            need_restart[v] = need_restart[v] && act[v];
+            any_restart = any_restart || need_restart[v];
+        }
+        if (any_restart) {
+            e = restart_flagged(need_restart);
+            if (e != hipSuccess) return hip_fail(h, e, "block sqmr restart");
+        }
     }
     return asi_sync(h);
 }

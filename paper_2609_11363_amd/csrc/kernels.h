@@ -221,10 +221,11 @@ hipError_t launch_qmr_update(int64_t n, double a, double b, const double *q, dou
 hipError_t launch_sub(int64_t n, const double *b, const double *t, double *r, hipStream_t st);
 hipError_t launch_fill_f64(int64_t n, double v, double *a, hipStream_t st);
 
-// Several right-hand sides at once (solve.hip): nv <= kMaxRhs vectors stored
-// as columns of length n (vector v at x + v n); dot products give nv results;
-// the masked updates touch the vectors whose act[v] is nonzero; coef holds
-// (a_v, b_v) pairs of the QMR update.
+// Several right-hand sides at once (solve.hip): nv <= kMaxRhs vectors of
+// length n stored interleaved (entry i of vector v at x[i nv + v]), except
+// launch_spmv_s_m, whose x and y are column-major (vector v at x + v n);
+// dot products give nv results; the masked updates touch the vectors whose
+// act[v] (sel[v]) is nonzero; coef holds (a_v, b_v) pairs of the QMR update.
 constexpr int kMaxRhs = 8;
 hipError_t launch_ldl_solve_m(const LdlSolveParams &P, int32_t nv, const double *x, double *V, hipStream_t st);
 hipError_t launch_spmv_s_m(int32_t n, int32_t nv, const int64_t *rowptr, const int32_t *col, const double *X,
@@ -239,6 +240,11 @@ hipError_t launch_xpby_ratio_m(int64_t n, int32_t nv, const double *Z, const dou
                                const int32_t *act, double *P, hipStream_t st);
 hipError_t launch_qmr_update_m(int64_t n, int32_t nv, const double *coef, const int32_t *act, const double *Q,
                                double *D, double *X, hipStream_t st);
+// masked per-vector copy (mode 0), difference a - src (1) or zero fill (2)
+hipError_t launch_select_m(int64_t n, int32_t nv, const int32_t *sel, int mode, const double *a, const double *src,
+                           double *dst, hipStream_t st);
+// column-major <-> interleaved (to: column-major src to interleaved dst)
+hipError_t launch_interleave(int64_t n, int32_t nv, bool to, const double *src, double *dst, hipStream_t st);
 
 // Lanczos basis kernels (eig.hip): basis columns at V + c n, at most
 // kEigMaxBasis columns per call (256 projected vectors and a residual block

@@ -225,10 +225,28 @@ __global__ void k_build_ls(int64_t nnz, const int32_t *__restrict__ s2u, const d
     Ls[p] = u >= 0 ? Lu[u] : 0.0;
 }
 
-// ---- several right-hand sides at once (columns at V + v ld, v < NV) ---------
-// The same kernels with NV accumulators per row: one walk over a row's
-// entries (column, u-index, L value) serves every vector; lane v of the
-// segment writes vector v.
+// ---- several right-hand sides at once ---------------------------------------
+// The block solves keep their NV vectors interleaved (entry i of vector v at
+// V[i NV + v]): one walk over a row's entries (column, L value) serves every
+// vector, and the NV values a gather needs sit in one 8 NV-byte run. Each
+// vector's arithmetic is that of the one-vector kernels above, in the same
+// order. Lane v of a row's segment writes vector v.
+
+template <int NV>
+__device__ inline void load_run(const double *__restrict__ src, double (&x)[NV]) {
+    if constexpr (NV % 2 == 0) {  // 16-byte aligned: the buffers are, and 8 NV bytes per entry
+        const double2 *s2 = reinterpret_cast<const double2 *>(src);
+#pragma unroll
+        for (int v = 0; v < NV / 2; ++v) {
+            const double2 t = s2[v];
+            x[2 * v] = t.x;
+            x[2 * v + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] = src[v];
+    }
+}
 
 template <bool FWD, int NV>
 __global__ __launch_bounds__(256) void k_ldl_level_m(const BlockMeta *__restrict__ ma, int32_t na,
@@ -236,7 +254,7 @@ __global__ __launch_bounds__(256) void k_ldl_level_m(const BlockMeta *__restrict
                                                      const int64_t *__restrict__ rowptr,
                                                      const int64_t *__restrict__ diagpos,
                                                      const int32_t *__restrict__ col, const double *__restrict__ Ls,
-                                                     int64_t ld, double *__restrict__ V) {
+                                                     double *__restrict__ V) {
     const int32_t b = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
     const int sub = threadIdx.x % kSeg;
     if (b >= na + nb) return;
@@ -254,35 +272,39 @@ __global__ __launch_bounds__(256) void k_ldl_level_m(const BlockMeta *__restrict
             const int32_t c = col[p];
             if (c != partner) {
                 const double l = Ls[p];
+                double x[NV];
+                load_run<NV>(V + (int64_t)c * NV, x);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) s[v] += l * V[v * ld + c];
+                for (int v = 0; v < NV; ++v) s[v] += l * x[v];
             }
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             s[v] = seg_sum(s[v]);
-            if (sub == v) V[v * ld + i] -= s[v];
+            if (sub == v) V[(int64_t)i * NV + v] -= s[v];
         }
     }
 }
 
-__global__ void k_ldl_diag_m(int32_t n, int32_t nv, int64_t ld, const int8_t *__restrict__ piv,
-                             const double *__restrict__ dinv, double *__restrict__ V) {
+__global__ void k_ldl_diag_m(int32_t n, int32_t nv, const int8_t *__restrict__ piv, const double *__restrict__ dinv,
+                             double *__restrict__ V) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (int64_t)n * nv) return;
-    const int32_t v = (int32_t)(x / n), j = (int32_t)(x % n);
+    const int32_t j = (int32_t)(x / nv), v = (int32_t)(x % nv);
     if (piv[j] == 2) return;
-    double *w = V + v * ld;
     const double *iv = dinv + 3 * (int64_t)j;
     if (piv[j] == 1) {
-        const double a = w[j], c = w[j + 1];
-        w[j] = iv[0] * a + iv[1] * c;
-        w[j + 1] = iv[1] * a + iv[2] * c;
+        const double a = V[x], c = V[x + nv];
+        V[x] = iv[0] * a + iv[1] * c;
+        V[x + nv] = iv[1] * a + iv[2] * c;
     } else {
-        w[j] = iv[0] * w[j];
+        V[x] = iv[0] * V[x];
     }
+    (void)v;
 }
 
+// y_v = X x_v on S for column-major x, y (vector v at x + v ld): the
+// Lanczos basis's layout
 template <int NV>
 __global__ __launch_bounds__(256) void k_spmv_s_m(int32_t n, const int64_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ col, const double *__restrict__ X,
@@ -310,7 +332,7 @@ template <int NV>
 __global__ __launch_bounds__(256) void k_spmv_ahat_m(int32_t n, const int64_t *__restrict__ Ap,
                                                      const int32_t *__restrict__ Aj, const double *__restrict__ Av,
                                                      const int32_t *__restrict__ perm,
-                                                     const int32_t *__restrict__ iperm, int64_t ld,
+                                                     const int32_t *__restrict__ iperm,
                                                      const double *__restrict__ x, double *__restrict__ y) {
     const int32_t i = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
     const int sub = threadIdx.x % kSeg;
@@ -321,32 +343,46 @@ __global__ __launch_bounds__(256) void k_spmv_ahat_m(int32_t n, const int64_t *_
         const int32_t r = perm[i];
         for (int64_t p = Ap[r] + sub; p < Ap[r + 1]; p += kSeg) {
             const double a = Av[p];
-            const int32_t c = iperm[Aj[p]];
+            double xv[NV];
+            load_run<NV>(x + (int64_t)iperm[Aj[p]] * NV, xv);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) s[v] += a * x[v * ld + c];
+            for (int v = 0; v < NV; ++v) s[v] += a * xv[v];
         }
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         s[v] = seg_sum(s[v]);
-        if (i < n && sub == v) y[v * ld + i] = s[v];
+        if (i < n && sub == v) y[(int64_t)i * NV + v] = s[v];
     }
 }
 
-// part[v nb + b] = partial of a_v . b_v over block b's grid stride (block
-// row blockIdx.y = v); out[v] = the partials of v in index order
-__global__ __launch_bounds__(256) void k_dotm_part(int64_t n, int64_t ld, const double *__restrict__ a,
+// part[v nb + b] = partial of a_v . b_v over block b's grid stride, the same
+// partition and order as k_dot_part; out[v] = the partials of v in index order
+template <int NV>
+__global__ __launch_bounds__(256) void k_dotm_part(int64_t n, const double *__restrict__ a,
                                                    const double *__restrict__ b, double *__restrict__ part) {
-    __shared__ double s[4];
-    const int64_t off = (int64_t)blockIdx.y * ld;
-    double v = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        v += a[off + i] * b[off + i];
+    __shared__ double sm[4][NV];
+    double acc[NV];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double xa[NV], xb[NV];
+        load_run<NV>(a + i * NV, xa);
+        load_run<NV>(b + i * NV, xb);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += xa[v] * xb[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double w = acc[v];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+        if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6][v] = w;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+    if (threadIdx.x < NV)
+        part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] =
+            (sm[0][threadIdx.x] + sm[1][threadIdx.x]) + (sm[2][threadIdx.x] + sm[3][threadIdx.x]);
 }
 
 __global__ __launch_bounds__(256) void k_dotm_final(int nb, const double *__restrict__ part,
@@ -362,41 +398,59 @@ __global__ __launch_bounds__(256) void k_dotm_final(int nb, const double *__rest
 }
 
 // Y_v += sign (num_v / den_v) X_v for the vectors with act[v] != 0
-__global__ void k_axpy_ratio_m(int64_t n, int32_t nv, int64_t ld, const double *__restrict__ num,
-                               const double *__restrict__ den, const int32_t *__restrict__ act, double sign,
-                               const double *__restrict__ X, double *__restrict__ Y) {
+__global__ void k_axpy_ratio_m(int64_t n, int32_t nv, const double *__restrict__ num, const double *__restrict__ den,
+                               const int32_t *__restrict__ act, double sign, const double *__restrict__ X,
+                               double *__restrict__ Y) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n * nv) return;
-    const int32_t v = (int32_t)(x / n);
+    const int32_t v = (int32_t)(x % nv);
     if (!act[v]) return;
-    const int64_t i = v * ld + x % n;
-    Y[i] += sign * (num[v] / den[v]) * X[i];
+    Y[x] += sign * (num[v] / den[v]) * X[x];
 }
 
 // P_v = Z_v + (num_v / den_v) P_v for the vectors with act[v] != 0
-__global__ void k_xpby_ratio_m(int64_t n, int32_t nv, int64_t ld, const double *__restrict__ Z,
-                               const double *__restrict__ num, const double *__restrict__ den,
-                               const int32_t *__restrict__ act, double *__restrict__ P) {
+__global__ void k_xpby_ratio_m(int64_t n, int32_t nv, const double *__restrict__ Z, const double *__restrict__ num,
+                               const double *__restrict__ den, const int32_t *__restrict__ act,
+                               double *__restrict__ P) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n * nv) return;
-    const int32_t v = (int32_t)(x / n);
+    const int32_t v = (int32_t)(x % nv);
     if (!act[v]) return;
-    const int64_t i = v * ld + x % n;
-    P[i] = Z[i] + (num[v] / den[v]) * P[i];
+    P[x] = Z[x] + (num[v] / den[v]) * P[x];
 }
 
 // D_v = coef[2v] D_v + coef[2v + 1] Q_v, X_v += D_v for the vectors with act[v] != 0
-__global__ void k_qmr_update_m(int64_t n, int32_t nv, int64_t ld, const double *__restrict__ coef,
-                               const int32_t *__restrict__ act, const double *__restrict__ Q,
-                               double *__restrict__ D, double *__restrict__ X) {
+__global__ void k_qmr_update_m(int64_t n, int32_t nv, const double *__restrict__ coef,
+                               const int32_t *__restrict__ act, const double *__restrict__ Q, double *__restrict__ D,
+                               double *__restrict__ X) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n * nv) return;
-    const int32_t v = (int32_t)(x / n);
+    const int32_t v = (int32_t)(x % nv);
     if (!act[v]) return;
-    const int64_t i = v * ld + x % n;
-    const double w = coef[2 * v] * D[i] + coef[2 * v + 1] * Q[i];
-    D[i] = w;
-    X[i] += w;
+    const double w = coef[2 * v] * D[x] + coef[2 * v + 1] * Q[x];
+    D[x] = w;
+    X[x] += w;
+}
+
+// for the vectors with sel[v] != 0: mode 0 dst = src, mode 1 dst = a - src,
+// mode 2 dst = 0 (entries i v of n x nv interleaved arrays)
+__global__ void k_select_m(int64_t n, int32_t nv, const int32_t *__restrict__ sel, int mode,
+                           const double *__restrict__ a, const double *__restrict__ src, double *__restrict__ dst) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n * nv) return;
+    if (!sel[x % nv]) return;
+    dst[x] = mode == 0 ? src[x] : (mode == 1 ? a[x] - src[x] : 0.0);
+}
+
+// interleave (to != 0: dst[i nv + v] = src[v n + i]) or back (dst[v n + i] = src[i nv + v])
+__global__ void k_interleave(int64_t n, int32_t nv, int to, const double *__restrict__ src, double *__restrict__ dst) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n * nv) return;
+    const int64_t i = x / nv, v = x % nv;
+    if (to)
+        dst[x] = src[v * n + i];
+    else
+        dst[v * n + i] = src[x];
 }
 
 }  // namespace dev
@@ -515,7 +569,6 @@ hipError_t launch_ldl_solve_m(const LdlSolveParams &P, int32_t nv, const double 
     const int32_t n = P.n;
     if (n <= 0) return hipSuccess;
     if (nv < 1 || nv > kMaxRhs) return hipErrorInvalidValue;
-    const int64_t ld = n;
     if (x != V) hipLaunchKernelGGL(dev::k_copy_f64, elem_grid((int64_t)n * nv), dim3(256), 0, st, (int64_t)n * nv, x, V);
     for (int32_t l = P.n_levels - 1; l >= 0; --l) {
         const int32_t na = P.lvl_small[l + 1] - P.lvl_small[l], nb = P.lvl_big[l + 1] - P.lvl_big[l];
@@ -523,18 +576,18 @@ hipError_t launch_ldl_solve_m(const LdlSolveParams &P, int32_t nv, const double 
 #define ASI_FWD(K)                                                                                                    \
     hipLaunchKernelGGL((dev::k_ldl_level_m<true, K>), seg_grid(na + nb), dim3(256), 0, st,                           \
                        P.meta_small + P.lvl_small[l], na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos, P.col, \
-                       P.Ls, ld, V)
+                       P.Ls, V)
         ASI_NV_SWITCH(nv, ASI_FWD)
 #undef ASI_FWD
     }
-    hipLaunchKernelGGL(dev::k_ldl_diag_m, elem_grid((int64_t)n * nv), dim3(256), 0, st, n, nv, ld, P.piv, P.dinv, V);
+    hipLaunchKernelGGL(dev::k_ldl_diag_m, elem_grid((int64_t)n * nv), dim3(256), 0, st, n, nv, P.piv, P.dinv, V);
     for (int32_t l = 0; l < P.n_levels; ++l) {
         const int32_t na = P.lvl_small[l + 1] - P.lvl_small[l], nb = P.lvl_big[l + 1] - P.lvl_big[l];
         if (na + nb == 0) continue;
 #define ASI_BWD(K)                                                                                                    \
     hipLaunchKernelGGL((dev::k_ldl_level_m<false, K>), seg_grid(na + nb), dim3(256), 0, st,                          \
                        P.meta_small + P.lvl_small[l], na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos, P.col, \
-                       P.Ls, ld, V)
+                       P.Ls, V)
         ASI_NV_SWITCH(nv, ASI_BWD)
 #undef ASI_BWD
     }
@@ -554,9 +607,8 @@ hipError_t launch_spmv_s_m(int32_t n, int32_t nv, const int64_t *rowptr, const i
 hipError_t launch_spmv_ahat_m(int32_t n, int32_t nv, const int64_t *Ap, const int32_t *Aj, const double *Av,
                               const int32_t *perm, const int32_t *iperm, const double *x, double *y, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-#define ASI_SPMVA(K)                                                                                       \
-    hipLaunchKernelGGL((dev::k_spmv_ahat_m<K>), seg_grid(n), dim3(256), 0, st, n, Ap, Aj, Av, perm, iperm, \
-                       (int64_t)n, x, y)
+#define ASI_SPMVA(K) \
+    hipLaunchKernelGGL((dev::k_spmv_ahat_m<K>), seg_grid(n), dim3(256), 0, st, n, Ap, Aj, Av, perm, iperm, x, y)
     ASI_NV_SWITCH(nv, ASI_SPMVA)
 #undef ASI_SPMVA
     return hipGetLastError();
@@ -564,28 +616,41 @@ hipError_t launch_spmv_ahat_m(int32_t n, int32_t nv, const int64_t *Ap, const in
 
 hipError_t launch_dot_m(int64_t n, int32_t nv, const double *a, const double *b, double *part, double *out,
                         hipStream_t st) {
-    if (nv < 1 || nv > kMaxRhs) return hipErrorInvalidValue;
     const int nb = dot_blocks(n);
-    hipLaunchKernelGGL(dev::k_dotm_part, dim3(nb, nv), dim3(256), 0, st, n, n, a, b, part);
+#define ASI_DOTM(K) hipLaunchKernelGGL((dev::k_dotm_part<K>), dim3(nb), dim3(256), 0, st, n, a, b, part)
+    ASI_NV_SWITCH(nv, ASI_DOTM)
+#undef ASI_DOTM
     hipLaunchKernelGGL(dev::k_dotm_final, dim3(nv), dim3(256), 0, st, nb, part, out);
     return hipGetLastError();
 }
 
 hipError_t launch_axpy_ratio_m(int64_t n, int32_t nv, const double *num, const double *den, const int32_t *act,
                                double sign, const double *X, double *Y, hipStream_t st) {
-    hipLaunchKernelGGL(dev::k_axpy_ratio_m, elem_grid(n * nv), dim3(256), 0, st, n, nv, n, num, den, act, sign, X, Y);
+    hipLaunchKernelGGL(dev::k_axpy_ratio_m, elem_grid(n * nv), dim3(256), 0, st, n, nv, num, den, act, sign, X, Y);
     return hipGetLastError();
 }
 
 hipError_t launch_xpby_ratio_m(int64_t n, int32_t nv, const double *Z, const double *num, const double *den,
                                const int32_t *act, double *P, hipStream_t st) {
-    hipLaunchKernelGGL(dev::k_xpby_ratio_m, elem_grid(n * nv), dim3(256), 0, st, n, nv, n, Z, num, den, act, P);
+    hipLaunchKernelGGL(dev::k_xpby_ratio_m, elem_grid(n * nv), dim3(256), 0, st, n, nv, Z, num, den, act, P);
     return hipGetLastError();
 }
 
 hipError_t launch_qmr_update_m(int64_t n, int32_t nv, const double *coef, const int32_t *act, const double *Q,
                                double *D, double *X, hipStream_t st) {
-    hipLaunchKernelGGL(dev::k_qmr_update_m, elem_grid(n * nv), dim3(256), 0, st, n, nv, n, coef, act, Q, D, X);
+    hipLaunchKernelGGL(dev::k_qmr_update_m, elem_grid(n * nv), dim3(256), 0, st, n, nv, coef, act, Q, D, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_m(int64_t n, int32_t nv, const int32_t *sel, int mode, const double *a, const double *src,
+                           double *dst, hipStream_t st) {
+    hipLaunchKernelGGL(dev::k_select_m, elem_grid(n * nv), dim3(256), 0, st, n, nv, sel, mode, a, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_interleave(int64_t n, int32_t nv, bool to, const double *src, double *dst, hipStream_t st) {
+    if (n * nv <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::k_interleave, elem_grid(n * nv), dim3(256), 0, st, n, nv, to ? 1 : 0, src, dst);
     return hipGetLastError();
 }
 

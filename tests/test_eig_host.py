@@ -53,7 +53,7 @@ def test_eigs_and_block_solve_work_bytes_layout():
     dotb = min(1024, (n + 255) // 256)
     for nrhs in (1, 3, 8):
         assert lib.asi_block_solve_work_bytes(n, nrhs, ctypes.byref(out)) == 0
-        solve = 5 * up(nrhs * n) + up(nrhs * dotb) + up(6 * nrhs) + up(2 * nrhs) + up(nrhs)
+        solve = 7 * up(nrhs * n) + up(nrhs * dotb) + up(6 * nrhs) + up(2 * nrhs) + 2 * up(nrhs)
         assert out.value == 8 * solve
     assert lib.asi_block_solve_work_bytes(n, 9, ctypes.byref(out)) == 1
     for m, b in ((20, 1), (40, 4)):
@@ -61,7 +61,7 @@ def test_eigs_and_block_solve_work_bytes_layout():
         nb = max(1, min(1024, (n + 1023) // 1024))
         cols = m + b
         part = max(cols * nb, dotb)
-        solve = 5 * up(b * n) + up(b * dotb) + up(6 * b) + up(2 * b) + up(b)
+        solve = 7 * up(b * n) + up(b * dotb) + up(6 * b) + up(2 * b) + 2 * up(b)
         expect = 8 * (2 * up(cols * n) + up(b * n) + up(part) + up(2 * cols + 1) + up(m * m) + solve)
         assert out.value == expect
     assert lib.asi_eigs_work_bytes(n, 257, 1, ctypes.byref(out)) == 1  # m above the basis limit
