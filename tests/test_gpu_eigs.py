@@ -122,3 +122,35 @@ def test_eigs_argument_checks():
     rc = s.lib.asi_eigs_error(s.h, *[p(a) for a in args], p(v0), 2, 8, 1, 1e-8, 10, 0, 1e-12, 100, p(small),
                               small.numel() * 8, lam.ctypes.data_as(ctypes.c_void_p), p(V), None, None)
     assert rc == 6  # ASI_E_WORKSPACE
+
+
+def test_eigs_edge_cases():
+    """The smallest basis a block allows (m = k + b + 1), a run stopped by
+    max_restarts = 0 before convergence (it returns its best Ritz pairs with
+    honest residual estimates), and k = 1 with b = 1."""
+    A, F, X, s, args = _setup("cov20")
+    print(f"[eigs] edge cases n={F.n}", flush=True)
+    # minimal basis for k = 1, b = 2
+    lam, V, res, st = s.eigs_error(*args, 1, m=4, block=2, tol=1e-9, max_restarts=500)
+    s.sync()
+    print(f"  m=4 b=2: {lam} {st}", flush=True)
+    assert st["converged"] == 1
+    _check(A, F, X, lam, V, 1, 1e-7)
+    # stopped early: the estimates say so
+    lam0, V0, res0, st0 = s.eigs_error(*args, 3, m=8, block=1, tol=1e-14, max_restarts=0)
+    s.sync()
+    print(f"  max_restarts=0: {lam0} residual estimates {res0} {st0}", flush=True)
+    assert st0["restarts"] == 0 and st0["applications"] == 8
+    assert np.all(np.isfinite(lam0)) and np.all(res0 >= 0)
+    assert st0["converged"] == int((res0 <= 1e-14).sum())
+    Vd = V0.cpu().numpy()
+    assert np.abs(Vd.T @ Vd - np.eye(3)).max() <= 1e-10
+    S = oc.pattern(F)
+    E = np.linalg.inv(oc.permuted(A, F.perm).toarray()) - S.to_csr(X).toarray()
+    true = [np.linalg.norm(E @ Vd[:, t] - lam0[t] * Vd[:, t]) / abs(lam0[t]) for t in range(3)]
+    np.testing.assert_allclose(true, res0, rtol=1e-3, atol=1e-9)  # the estimates are the true residuals
+    # k = 1, b = 1
+    lam1, V1, _, st1 = s.eigs_error(*args, 1, m=6, tol=1e-10)
+    s.sync()
+    assert st1["converged"] == 1
+    _check(A, F, X, lam1, V1, 1, 1e-8)

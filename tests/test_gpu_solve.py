@@ -214,3 +214,40 @@ def test_block_solves_equal_single_solves(name, method, nrhs):
             xg = X[v].cpu().numpy()
             assert np.linalg.norm(Ah @ xg - B[v]) / np.linalg.norm(B[v]) <= 2 * tol
     assert not X[nrhs - 1].abs().max().item() and iters[nrhs - 1] == 0
+
+
+def test_block_solve_edge_cases():
+    """One right-hand side (equal to asi_pcg bit for bit), maxit = 0 (X = 0,
+    no steps), and the argument checks (nrhs above 8, work too small)."""
+    import ctypes
+
+    import torch
+    from paper_2609_11363_amd import AsiError, Solver, upload_factors
+    A, F = _case("cov20")
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    s.load_factor(*upload_factors(F))
+    dev = s.device
+    Ar = torch.as_tensor(A.indptr.astype(np.int64), device=dev)
+    Ac = torch.as_tensor(A.indices.astype(np.int32), device=dev)
+    Av = torch.as_tensor(A.data, device=dev)
+    perm = torch.as_tensor(F.perm.astype(np.int32), device=dev)
+    B = torch.as_tensor(np.random.default_rng(13).standard_normal((1, F.n)), device=dev)
+    print(f"[block] edge cases n={F.n}", flush=True)
+    X, iters, rel = s.pcg_block(Ar, Ac, Av, perm, B, tol=1e-12, maxit=500)
+    x1, it1, rr1 = s.pcg(Ar, Ac, Av, perm, B[0].contiguous(), tol=1e-12, maxit=500)
+    s.sync()
+    assert torch.equal(X[0], x1) and iters[0] == it1 and rel[0] == rr1
+    X0, it0, _ = s.sqmr_block(Ar, Ac, Av, perm, B, tol=1e-12, maxit=0)
+    s.sync()
+    assert it0[0] == 0 and not X0.abs().max().item()
+    with pytest.raises(AsiError, match="ASI_E_ARG"):
+        s.pcg_block(Ar, Ac, Av, perm, torch.zeros((9, F.n), dtype=torch.float64, device=dev))
+    small = torch.empty(64, dtype=torch.float64, device=dev)
+    Xs = torch.empty((1, F.n), dtype=torch.float64, device=dev)
+    it = np.zeros(1, dtype=np.int32)
+    rr = np.zeros(1)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    rc = s.lib.asi_pcg_block(s.h, p(Ar), p(Ac), p(Av), p(perm), 1, p(B), p(Xs), 1e-10, 10, p(small), 512,
+                             it.ctypes.data_as(ctypes.c_void_p), rr.ctypes.data_as(ctypes.c_void_p))
+    assert rc == 6  # ASI_E_WORKSPACE
