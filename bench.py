@@ -50,6 +50,35 @@ def selinv_sources_sha256():
         return hashlib.sha256(fh.read()).hexdigest()
 
 
+def host_cpu():
+    """The host CPU model (the oracle baseline's machine), from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def copy_bandwidth_gbs(torch, dev, nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth of a plain device copy (read + write bytes per
+    second), timed with events on torch's current stream."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -227,6 +256,8 @@ def run_diffusion(args):
         torch.cuda.synchronize()
         del src, dst
 
+    copy_gbs = copy_bandwidth_gbs(torch, dev)
+    log(f"plain 1 GiB device copy: {copy_gbs:.0f} GB/s (read + write)")
     # live per-launch timing of the dominant kernel (HIP events on the stream)
     s.profile(True)
     for _ in range(3):
@@ -285,7 +316,8 @@ def run_diffusion(args):
                      "traffic_source": SELINV_TRAFFIC["profile"] if traffic else None,
                      "launches_per_step": launches // 3, "avg_launch_ms": avg_ms,
                      "alg_bytes_per_launch": tot_bytes / max(launches, 1),
-                     "dominant_class_by_time": dom},
+                     "dominant_class_by_time": dom,
+                     "copy_achievable_gbs": copy_gbs},
         "host": {"ildl_s": t_fact, "analysis_s": t_sym},
     }
 
@@ -300,7 +332,8 @@ def run_diffusion(args):
         result["cpu_baseline"] = {"value": nnzS / t_cpu, "unit": "entries/s", "cores": 1,
                                   "kind": "oracle",
                                   "sample": f"the whole workload ({N}^3, |S|={nnzS}): single-threaded "
-                                            f"float64 oracle SelInv + NInv + Mix, {t_cpu:.1f} s"}
+                                            f"float64 oracle SelInv + NInv + Mix, {t_cpu:.1f} s on one core of "
+                                            f"{host_cpu()}"}
         e64 = oc.entry_error(S, Z64, Zo)
         e32 = oc.entry_error(S, Z32, Zo)
         em = oc.entry_error(S, M64, Mo)
@@ -479,7 +512,8 @@ def run_stencil27(args):
             f"float64 {e_sel.max():.2e}, mixed {e_sel_m.max():.2e}; NInv {e_ninv.max():.2e}; Mix {e_mix.max():.2e}")
         result["cpu_baseline"] = {"value": nnzS / t_ninv, "unit": "entries/s", "cores": 1, "kind": "oracle",
                                   "sample": f"oracle NInv (p=3, delta=0.1) on the whole {N}^3 workload, "
-                                            f"{t_ninv:.1f} s (the oracle SelInv is not run at this size)"}
+                                            f"{t_ninv:.1f} s on one core of {host_cpu()} (the oracle SelInv is not "
+                                            f"run at this size)"}
         result["rel_error_vs_oracle"] = {
             "ninv_fp64_max_all_entries": float(e_ninv.max()),
             "mix_fp64_max_selection_rule": float(e_mix.max()),
@@ -864,7 +898,8 @@ def run_indefinite(args):
         s.sync()
         result["cpu_baseline"] = {"value": nnzS / t_cpu, "unit": "entries/s", "cores": 1, "kind": "oracle",
                                   "sample": f"the whole workload ({N}^2, |S|={nnzS}): single-threaded float64 "
-                                            f"oracle SelInv + NInv + Mix + SPAI + rank-{k} update, {t_cpu:.1f} s"}
+                                            f"oracle SelInv + NInv + Mix + SPAI + rank-{k} update, {t_cpu:.1f} s on one "
+                                            f"core of {host_cpu()}"}
         result["rel_error_vs_oracle"] = {
             "selinv_fp64_max": float(oc.entry_error(S, Z.cpu().numpy(), Zo).max()),
             "mix_fp64_max": float(oc.entry_error(S, M.cpu().numpy(), Mo).max()),
@@ -1079,7 +1114,8 @@ def run_covariance(args):
         t_cpu = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": nnzS / t_cpu, "unit": "entries/s", "cores": 1, "kind": "oracle",
                                   "sample": f"the whole workload ({N}^2, |S|={nnzS}): single-threaded float64 "
-                                            f"oracle SelInv + NInv + Mix + SPAI + trace, {t_cpu:.1f} s"}
+                                            f"oracle SelInv + NInv + Mix + SPAI + trace, {t_cpu:.1f} s on one core of "
+                                            f"{host_cpu()}"}
         result["rel_error_vs_oracle"] = {
             "selinv_fp64_max": float(oc.entry_error(S, Z.cpu().numpy(), Zo).max()),
             "ninv_fp64_max": float(oc.entry_error(S, Nn.cpu().numpy(), No).max()),
