@@ -170,12 +170,16 @@ def run_diffusion(args):
     ML = torch.empty_like(Z)
 
     def correct():
-        s.mlp_correct(packed, Z, Nn, M, eps, out=ML)
+        # Mix and the learned correction in one pass over S: M and M + y s
+        s.mlp_correct_mix(packed, Z, Nn, eps, M=M, out=ML)
 
     def full_step(prec="fp64"):
-        step(prec)
+        s.load_factor(Lv, dd, ds)
+        s.selinv_ninv(p=p, delta=delta, precision=prec, Z=Z, N=Nn)
         if packed is not None:
             correct()
+        else:
+            s.mix(Z, Nn, eps, out=M)
 
     for _ in range(args.warmup):
         full_step()
@@ -188,8 +192,8 @@ def run_diffusion(args):
     s.sync()
     ms_correct = timed(correct, args.steps) * 1e3 if packed is not None else 0.0
     s.sync()
-    log(f"fp64 step {ms_full:.3f} ms (SelInv + NInv + Mix {ms_step:.3f} ms, learned correction "
-        f"{ms_correct:.3f} ms)")
+    log(f"fp64 step {ms_full:.3f} ms (SelInv + NInv + Mix {ms_step:.3f} ms; Mix and the learned correction "
+        f"in one pass {ms_correct:.3f} ms)")
     ms_selinv = timed(lambda: s.selinv(Lv, dd, ds, out=Z), args.steps) * 1e3
     ms_ninv = timed(lambda: s.ninv(Lv, dd, ds, p=p, delta=delta, out=Nn), args.steps) * 1e3
     ms_mix = timed(lambda: s.mix(Z, Nn, eps, out=M), args.steps) * 1e3
@@ -288,9 +292,10 @@ def run_diffusion(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"3D 7-point lognormal(0,1) diffusion {N}^3, nested multicolor order, "
-                               f"ILDL tau={tau}; step = SelInv + NInv(p=3, delta=0.1) + Mix(eps=1e-2)"
-                               + (" + learned correction (fused features, bf16 MLP, apply)" if packed is not None
-                                  else " (learned correction fell back to plain Mix)"),
+                               f"ILDL tau={tau}; step = SelInv + NInv(p=3, delta=0.1), then "
+                               + ("Mix(eps=1e-2) and the learned correction in one pass (features, bf16 MLP, "
+                                  "apply; M and M + y s written)" if packed is not None
+                                  else "Mix(eps=1e-2) (learned correction fell back to plain Mix)"),
                    "n": F.n, "nnz_A": int(A.nnz), "nnz_L": F.nnzL, "nnz_S": nnzS,
                    "levels": info["n_levels"], "max_cols": info["max_cols"],
                    "parallelism": "single GPU"},
@@ -301,7 +306,7 @@ def run_diffusion(args):
             "mix_pipeline_fp64": {"ms": ms_step, "entries_per_s": nnzS / (ms_step * 1e-3)},
             "selinv_mixed": {"ms": ms_selinv_mixed, "entries_per_s": nnzS / (ms_selinv_mixed * 1e-3)},
             "mix_pipeline_mixed": {"ms": ms_step_mixed, "entries_per_s": nnzS / (ms_step_mixed * 1e-3)},
-            "learned_correction": {"ms": ms_correct},
+            "mix_and_learned_correction_one_pass": {"ms": ms_correct},
             "mix_learned_pipeline_fp64": {"ms": ms_full, "entries_per_s": nnzS / (ms_full * 1e-3)},
             "mix_learned_pipeline_mixed": {"ms": ms_full_mixed, "entries_per_s": nnzS / (ms_full_mixed * 1e-3)},
         },
@@ -433,9 +438,12 @@ def run_stencil27(args):
         s.mix(Z, Nn, eps, out=M)
 
     def learned_pipeline(prec):
-        mix_pipeline(prec)
-        if packed is not None:
-            s.mlp_correct(packed, Z, Nn, M, eps, Lv, dd, ds, out=ML)
+        if packed is None:
+            mix_pipeline(prec)
+            return
+        s.selinv(Lv, dd, ds, precision=prec, out=Z)
+        s.ninv(Lv, dd, ds, p=p, delta=delta, precision=prec, out=Nn)
+        s.mlp_correct_mix(packed, Z, Nn, eps, Lv, dd, ds, M=M, out=ML)
 
     for _ in range(args.warmup):
         learned_pipeline("mixed")
@@ -647,9 +655,12 @@ def run_equal_error(args):
                 s.mix(Z, Nn, eps, out=M)
 
             def mix_learned_mixed():
-                mix_mixed()
-                if packed is not None:
-                    s.mlp_correct(packed, Z, Nn, M, eps, out=ML)
+                if packed is None:
+                    mix_mixed()
+                    return
+                s.load_factor(Lv, dd, ds)
+                s.selinv_ninv(p=p, delta=delta, precision="mixed", Z=Z, N=Nn)
+                s.mlp_correct_mix(packed, Z, Nn, eps, M=M, out=ML)
 
             for _ in range(args.warmup):
                 mix_learned_mixed()

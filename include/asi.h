@@ -275,6 +275,18 @@ asi_status asi_mlp_apply(asi_handle h, const double *M_S, const float *y, const 
 asi_status asi_mlp_correct(asi_handle h, const void *W, const double *Z_S, const double *N_S, const double *M_S,
                            double eps, const double *L_val, const double *d_diag, const double *d_sub,
                            double *out_S);
+/*
+ * asi_mlp_correct_mix: Mix (Section 2.3, as asi_mix with eps) and the
+ * correction in one pass: M = Mix(Z, N) is formed entry by entry (its test
+ * is the feature the network already reads) and written to M_S when M_S is
+ * not NULL, out = M + y s as asi_mlp_correct; both equal asi_mix followed by
+ * asi_mlp_correct bit for bit, without the separate pass over S. Arguments
+ * as for asi_mlp_correct; M_S and out_S must be different arrays (either may
+ * alias Z_S or N_S).
+ */
+asi_status asi_mlp_correct_mix(asi_handle h, const void *W, const double *Z_S, const double *N_S, double eps,
+                               const double *L_val, const double *d_diag, const double *d_sub, double *M_S,
+                               double *out_S);
 
 /* Diagonal of a matrix on S: d[i] = X(i, i). */
 asi_status asi_diag(asi_handle h, const double *X_S, double *d);

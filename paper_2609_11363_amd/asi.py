@@ -29,7 +29,7 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor", "asi_selinv_ninv", "asi_trace", "asi_ninv_full", "asi_mix_full",
            "asi_spmv", "asi_ldl_solve", "asi_pcg", "asi_sqmr", "asi_za_diag", "asi_check_matrix",
            "asi_eigs_work_bytes", "asi_eigs_error", "asi_dense_symeig", "asi_block_solve_work_bytes",
-           "asi_pcg_block", "asi_sqmr_block"]
+           "asi_pcg_block", "asi_sqmr_block", "asi_mlp_correct_mix"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -110,6 +110,7 @@ def load_library():
         "asi_mlp_adam": [P, P, P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, i64],
         "asi_mlp_apply": [P, P, P, P, P],
         "asi_mlp_correct": [P, P, P, P, P, f64, P, P, P, P],
+        "asi_mlp_correct_mix": [P, P, P, P, f64, P, P, P, P, P],
         "asi_profile_read": [P, i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(f64)],
     }
     for name, args in sig.items():
@@ -322,6 +323,15 @@ class Solver:
         self._stream()
         self._check(self.lib.asi_mlp_correct(self.h, _ptr(packed), _ptr(Z), _ptr(N), _ptr(M), float(eps),
                                              _ptr(L_val), _ptr(d_diag), _ptr(d_sub), _ptr(out)))
+        return out
+
+    def mlp_correct_mix(self, packed, Z, N, eps, L_val=None, d_diag=None, d_sub=None, M=None, out=None):
+        """Mix and the learned correction in one pass: returns out = M + y s
+        (and writes M = Mix(Z, N) into M when given)."""
+        out = self._out(out)
+        self._stream()
+        self._check(self.lib.asi_mlp_correct_mix(self.h, _ptr(packed), _ptr(Z), _ptr(N), float(eps), _ptr(L_val),
+                                                 _ptr(d_diag), _ptr(d_sub), _ptr(M), _ptr(out)))
         return out
 
     def diag(self, X, out=None):

@@ -915,7 +915,8 @@ asi_status asi_lowrank(asi_handle h, int32_t k, const double *V, const double *l
 // Common set-up of the learned-correction calls: D-block inverses, L in its
 // column layout, the per-node records; fills P.
 static asi_status mlp_setup(asi_handle h, const double *Z_S, const double *N_S, const double *M_S, double eps,
-                            const double *L_val, const double *d_diag, const double *d_sub, asi::MlpFeatParams &P) {
+                            const double *L_val, const double *d_diag, const double *d_sub, asi::MlpFeatParams &P,
+                            bool fuse_mix = false, double *M_out = nullptr) {
     const asi::Analysis &A = h->A;
     if (A.nnzS > (int64_t)INT32_MAX) return fail(h, ASI_E_UNSUPPORTED, "the learned correction needs |S| < 2^31");
     const void *Lu = nullptr;
@@ -941,6 +942,8 @@ static asi_status mlp_setup(asi_handle h, const double *Z_S, const double *N_S, 
     P.N = N_S;
     P.M = M_S;
     P.eps = eps;
+    P.fuse_mix = fuse_mix ? 1 : 0;
+    P.Mout = M_out;
     {
         Trace t(h, ASI_K_MLP_FEATURES, 0.0);
         e = asi::launch_node_feats(P, h->stream);
@@ -982,6 +985,24 @@ asi_status asi_mlp_correct(asi_handle h, const void *W, const double *Z_S, const
     Trace t(h, ASI_K_MLP_FORWARD, 40.0 * h->A.nnzS + 32.0 * h->A.n);
     hipError_t e = asi::launch_mlp_correct(P, W, out_S, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "mlp correct");
+    return ASI_OK;
+}
+
+asi_status asi_mlp_correct_mix(asi_handle h, const void *W, const double *Z_S, const double *N_S, double eps,
+                               const double *L_val, const double *d_diag, const double *d_sub, double *M_S,
+                               double *out_S) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!W || !Z_S || !N_S || !out_S) return fail(h, ASI_E_ARG, "null pointer");
+    if (M_S && M_S == out_S) return fail(h, ASI_E_ARG, "M_S and out_S must be different arrays");
+    DeviceGuard g(h->device);
+    asi::MlpFeatParams P;
+    s = mlp_setup(h, Z_S, N_S, nullptr, eps, L_val, d_diag, d_sub, P, true, M_S);
+    if (s != ASI_OK) return s;
+    // algorithmic bytes: row and column index, Z, N in and the result (and M) out per entry
+    Trace t(h, ASI_K_MLP_FORWARD, (M_S ? 40.0 : 32.0) * h->A.nnzS + 32.0 * h->A.n);
+    hipError_t e = asi::launch_mlp_correct(P, W, out_S, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "mlp correct (with Mix)");
     return ASI_OK;
 }
 

@@ -137,6 +137,8 @@ struct MlpFeatParams {
     double eps;
     uint16_t *F;  // nnz x 16 bfloat16
     float *scale; // nnz
+    int fuse_mix;  // the correction forms M = Mix(Z, N) itself (M unused) and writes it to Mout if not null
+    double *Mout;
 };
 
 // NInv and Mix on their own pattern (lower triangle, CSR)

@@ -90,8 +90,13 @@ __global__ void k_node_feats(MlpFeatParams P) {
     if (i >= P.n) return;
     const double maxlev = P.maxlevel > 0 ? (double)P.maxlevel : 1.0;
     NodeRec r;
-    r.m = P.M[P.diagpos[i]];
     r.z = P.Z[P.diagpos[i]];
+    if (P.fuse_mix) {
+        const double nv = P.N[P.diagpos[i]];
+        r.m = fabs(r.z) > P.eps * sqrt(fabs(r.z * r.z)) ? r.z : nv;  // Mix on the diagonal
+    } else {
+        r.m = P.M[P.diagpos[i]];
+    }
     r.f[0] = feat_bf16(log(fabs(dinv_diag(P.dinv, P.piv, i)) + 1e-30));
     r.f[1] = feat_bf16(log(P.rn[i] + 1e-30));
     r.f[2] = feat_bf16(log(P.rn[P.n + i] + 1e-30));
@@ -377,12 +382,16 @@ __global__ __launch_bounds__(64 * kFwdWaves, 4) void k_mlp_forward(const uint8_t
 // indices of the next tile (row, column, u-index) are loaded while the
 // current tile's gathers and network run, so a tile waits for one round of
 // memory accesses (node records, L value, Z, N, M) instead of two.
+// FUSE: M = Mix(Z, N) is formed here (the test is the one the features
+// already make, on the same values) and written to Mout when given.
+template <bool FUSE>
 __global__ __launch_bounds__(64 * kFwdWaves, 4) void k_mlp_correct(MlpFeatParams P, const uint8_t *__restrict__ W,
                                                                    double *out) {
     __shared__ __align__(16) uint16_t sF[kFwdWaves][64 * NF];
     __shared__ float sy[kFwdWaves][64];
     __shared__ __align__(16) float sb[2 * NH];
     __shared__ __align__(16) uint8_t sw[kMlpFragBytes];
+    __shared__ double sM[FUSE ? kFwdWaves : 1][64];  // FUSE: the formed M value, kept across the network
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
     MlpRegs R;
@@ -411,7 +420,10 @@ __global__ __launch_bounds__(64 * kFwdWaves, 4) void k_mlp_correct(MlpFeatParams
             lv = lval_at(P, cu);
             z = P.Z[p];
             nv = P.N[p];
-            m = P.M[p];
+            if constexpr (FUSE)
+                m = fabs(z) > P.eps * sqrt(fabs(ni.z * nj.z)) ? z : nv;
+            else
+                m = P.M[p];
         }
         const int32_t i = ci, j = cj;
         const int64_t pn = p + stride * 64;
@@ -429,9 +441,18 @@ __global__ __launch_bounds__(64 * kFwdWaves, 4) void k_mlp_correct(MlpFeatParams
             for (int k = 0; k < NF; ++k) f[k] = 0;
         }
         store_features(sF[w] + lane * NF, f);
+        if constexpr (FUSE) sM[w][lane] = m;
         wave_sync();
         mlp_tile(R, sb, sw, sF[w], sy[w], col, g);
-        if (valid) out[p] = m + (double)sy[w][lane] * (double)(float)sc;
+        if (valid) {
+            if constexpr (FUSE) {
+                const double mm = sM[w][lane];
+                out[p] = mm + (double)sy[w][lane] * (double)(float)sc;
+                if (P.Mout) P.Mout[p] = mm;
+            } else {
+                out[p] = m + (double)sy[w][lane] * (double)(float)sc;
+            }
+        }
     }
 }
 
@@ -590,8 +611,12 @@ hipError_t launch_mlp_correct(const MlpFeatParams &P, const void *W, double *out
     if (P.nnz <= 0) return hipSuccess;
     const int64_t tiles = (P.nnz + 63) / 64;
     const int64_t grid = std::min<int64_t>((tiles + dev::kFwdWaves - 1) / dev::kFwdWaves, 8192);
-    hipLaunchKernelGGL(dev::k_mlp_correct, dim3((unsigned)grid), dim3(64 * dev::kFwdWaves), 0, st, P,
-                       reinterpret_cast<const uint8_t *>(W), out);
+    if (P.fuse_mix)
+        hipLaunchKernelGGL(dev::k_mlp_correct<true>, dim3((unsigned)grid), dim3(64 * dev::kFwdWaves), 0, st, P,
+                           reinterpret_cast<const uint8_t *>(W), out);
+    else
+        hipLaunchKernelGGL(dev::k_mlp_correct<false>, dim3((unsigned)grid), dim3(64 * dev::kFwdWaves), 0, st, P,
+                           reinterpret_cast<const uint8_t *>(W), out);
     return hipGetLastError();
 }
 

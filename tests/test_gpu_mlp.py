@@ -215,3 +215,47 @@ def test_fused_correction_matches_three_calls_and_oracle(case):
     assert np.median(rel) <= 1e-5
     assert err.max() <= 2e-2 * scale
     assert (rel > 1e-4).mean() <= 0.01
+
+
+@pytest.mark.parametrize("case", ["rand2500", "kkt", "diff12_mixed"])
+def test_mix_and_correction_in_one_pass(case):
+    """asi_mlp_correct_mix writes M = Mix(Z, N) and M + y s equal to asi_mix
+    followed by asi_mlp_correct bit for bit (1x1 and 2x2 pivots, float64 and
+    mixed-precision SelInv; factor loaded or passed; M not requested); M and
+    out must differ."""
+    import torch
+    from paper_2609_11363_amd import AsiError, Solver, upload_factors
+    from workloads import diffusion3d_7pt, kkt_matrix, nested_multicolor_grid
+    print(f"[mix+mlp] case={case}", flush=True)
+    prec = "fp64"
+    if case == "rand2500":
+        A = random_dd_symmetric(6, n=2500)
+        F = ildl_bk(A, rcm(A), 1e-2)
+    elif case == "kkt":
+        A = kkt_matrix(60, 40, 3)
+        F = ildl_bk(A, None, 1e-2)
+    else:
+        A = diffusion3d_7pt(12, 1.0, 2)
+        F = ildl_bk(A, nested_multicolor_grid((12, 12, 12)), 1e-3)
+        prec = "mixed"
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    Lv, dd, ds = upload_factors(F)
+    eps = 1e-2
+    Z = s.selinv(Lv, dd, ds, precision=prec)
+    N = s.ninv(Lv, dd, ds, p=3, delta=0.1)
+    theta_h = om.init_params(13)
+    theta_h[5248:5313] *= 0.01
+    packed = s.mlp_pack(torch.as_tensor(theta_h, device=s.device))
+    M1 = s.mix(Z, N, eps)
+    out1 = s.mlp_correct(packed, Z, N, M1, eps, Lv, dd, ds)
+    M2 = torch.full_like(Z, float("nan"))
+    out2 = s.mlp_correct_mix(packed, Z, N, eps, Lv, dd, ds, M=M2)
+    s.load_factor(Lv, dd, ds)
+    out3 = s.mlp_correct_mix(packed, Z, N, eps)  # loaded factor, M not written
+    s.sync()
+    print(f"  |S|={Z.numel()} M differs at {int((M1 != M2).sum())}, out at {int((out1 != out2).sum())}",
+          flush=True)
+    assert torch.equal(M1, M2) and torch.equal(out1, out2) and torch.equal(out1, out3)
+    with pytest.raises(AsiError, match="ASI_E_ARG"):
+        s.mlp_correct_mix(packed, Z, N, eps, M=M2, out=M2)
