@@ -5,16 +5,35 @@ Default workload (--workload diffusion64): 3D 7-point variable-coefficient
 diffusion on a 64^3 grid (n = 262,144, lognormal(0, 1) face coefficients,
 seed 2), nested multicolor ordering, threshold ILDL with drop tolerance 1e-3
 (host, untimed). One step is one pass of the hot path on the resident
-factors: SelInv (float64) -> NInv (p = 3, delta = 0.1) -> Mix (eps = 1e-2),
-all through libasi's C ABI. value = |S| / step time (entries of the Mix
-result per second; the step also produces the SelInv result).
+factors, all through libasi's C ABI: load the factor, SelInv (float64) with
+NInv (p = 3, delta = 0.1) beside it, then Mix (eps = 1e-2) and the learned
+correction (trained before the timed region on small grids of the same
+family) in one pass. value = |S| / step time (entries of the Mix+learned
+result per second; the step also produces the SelInv and Mix results).
 
 --workload indefinite512: the 5-point Laplacian on 512^2 minus sigma I with
 20 negative eigenvalues, Bunch-Kaufman ILDL at 1e-3; one step is SelInv ->
 NInv -> Mix -> SPAI (10 CG steps) -> rank-16 update on S -> diagonal. The
 16 eigenpairs of A^-1 - X come from a host Lanczos run before the timed
-region (exact A^-1 products in closed form), and the acceptance test of the
-spectral correction runs on the device against the exact diag(A^-1).
+region (exact A^-1 products in closed form) and, measured beside it, from
+the device eigen step (block Lanczos with block SQMR solves); the acceptance
+test of the spectral correction runs on the device against the exact
+diag(A^-1).
+
+--workload covariance200: the covariance-type matrix on a 200^2 grid (SPD),
+one step SelInv with NInv beside it -> Mix -> SPAI -> diagonal -> trace; the
+spectral check with the device eigen step (block Lanczos, block PCG).
+
+--workload stencil27_128 / stencil27_equal_error: the 27-point stencil at
+128^3, and the equal-error comparison of SelInv at tighter drop tolerances
+against Mix + learned at 64^3.
+
+--workload randdd: random sparse diagonally dominant matrices (the 48 of
+smallest n among seeds 0-255, n 2,034-5,701): the learned correction trained
+on 32, validated on 8, and its gain on the other 8 measured against SelInv
+at drop tolerance 1e-4 and against the exact (dense) inverse; value = the
+device pipeline's rate over those 8 (SelInv, NInv, then Mix and the
+correction in one pass).
 
 Prints one JSON line. Extra fields: per-method times, the mixed-precision
 step, the roofline of the dominant kernel measured live with HIP events on
@@ -90,7 +109,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="diffusion64",
                     choices=["diffusion64", "indefinite512", "stencil27_128", "stencil27_equal_error",
-                             "covariance200"])
+                             "covariance200", "randdd"])
     ap.add_argument("--grid", type=int, default=None, help="grid size (default 64, 512, 128 per workload)")
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -116,6 +135,9 @@ def main():
         return
     if args.workload == "covariance200":
         run_covariance(args)
+        return
+    if args.workload == "randdd":
+        run_randdd(args)
         return
     run_diffusion(args)
 
@@ -1144,6 +1166,138 @@ def run_covariance(args):
             result["rel_error_vs_oracle"]["ninv_full_fp64_max"] = float(
                 (np.abs(v_g - Nfo[2]) / np.sqrt(np.abs(dN[rr] * dN[c_g]))).max())
         log(f"oracle {t_cpu:.1f}s; {result['rel_error_vs_oracle']}")
+    print(json.dumps(result), flush=True)
+
+
+
+def run_randdd(args):
+    """The random diagonally dominant set (strictly dominant, about 10
+    off-diagonals per row, RCM order): of seeds 0-255 the 48 with the
+    smallest n (their tight factors stay within minutes of host ILDL), by
+    seed: 32 train, 8 validation, 8 test. Loose factor ILDL tau = 1e-2 (Mix
+    as the network's input), tight tau = 1e-4 (SelInv as its target). The
+    test gain is reported against the tight SelInv and against the dense
+    inverse of each test matrix on its pattern S; value = entries of S per
+    second of the device pipeline (SelInv, NInv, then Mix and the learned
+    correction in one pass) summed over the test matrices."""
+    import numpy as np
+    import torch
+
+    from oracle import core as oc
+    from paper_2609_11363_amd import Solver, learned, upload_factors
+    from workloads import ildl_bk, random_dd_symmetric, rcm
+
+    tau_l, tau_t, p, delta, eps = 1e-2, 1e-4, 3, 0.1, 1e-2
+    sizes = sorted((int(np.random.default_rng(sd).integers(2000, 20001)), sd) for sd in range(256))
+    seeds = sorted(sd for _, sd in sizes[:48])
+    groups = {"train": seeds[:32], "val": seeds[32:40], "test": seeds[40:]}
+    t0 = time.time()
+    samples = {}
+    for name, ss in groups.items():
+        samples[name] = []
+        for sd in ss:
+            A = random_dd_symmetric(sd)
+            samples[name].append(learned.build_sample(A, rcm(A), tau_loose=tau_l, tau_tight=tau_t, p=p,
+                                                      delta=delta, eps=eps))
+            log(f"{name} seed {sd}: {samples[name][-1].meta} ({time.time() - t0:.0f}s)")
+    t_data = time.time() - t0
+    t0 = time.time()
+    packed, _, hist = learned.train(samples["train"], samples["val"], epochs=args.learned_epochs, lr=1e-3,
+                                    seed=0, log=lambda m: log("train " + m))
+    t_train = time.time() - t0
+    test = samples["test"]
+    base = learned.mean_error(test)
+    got = learned.mean_error(test, packed) if packed is not None else base
+    log(f"held-out vs SelInv(tau={tau_t:g}): Mix {base[0]:.3e} -> Mix+learned {got[0]:.3e} "
+        f"(gain {base[0] / got[0]:.2f}x)")
+
+    # against the dense inverse, on every entry of each test matrix's S, and
+    # the device pipeline's time
+    dev = torch.device("cuda", 0)
+    err_mix, err_ml, tot_entries, tot_ms = [], [], 0, 0.0
+    for sd, smp in zip(groups["test"], test):
+        A = random_dd_symmetric(sd)
+        F = ildl_bk(A, rcm(A), tau_l)
+        s = Solver(0)
+        s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+        Lv, dd, ds = upload_factors(F)
+        nnzS = s.nnz_S
+        Z = torch.empty(nnzS, dtype=torch.float64, device=dev)
+        Nn, M, ML = (torch.empty_like(Z) for _ in range(3))
+
+        def pipeline():
+            s.load_factor(Lv, dd, ds)
+            s.selinv_ninv(p=p, delta=delta, Z=Z, N=Nn)
+            if packed is not None:
+                s.mlp_correct_mix(packed, Z, Nn, eps, M=M, out=ML)
+            else:
+                s.mix(Z, Nn, eps, out=M)
+
+        for _ in range(args.warmup):
+            pipeline()
+        ms = timed(pipeline, args.steps) * 1e3
+        s.sync()
+        tot_entries += nnzS
+        tot_ms += ms
+        S = oc.pattern(F)
+        Ainv = np.linalg.inv(oc.permuted(A, F.perm).toarray())
+        exact = Ainv[S.rows(), S.col]
+        scale = smp.scale.cpu().numpy().astype(np.float64)
+        mix = M.cpu().numpy()
+        ml = ML.cpu().numpy() if packed is not None else mix
+        err_mix.append(np.abs(mix - exact) / scale)
+        err_ml.append(np.abs(ml - exact) / scale)
+        log(f"test seed {sd}: n={F.n} |S|={nnzS} pipeline {ms:.3f} ms; vs dense inverse: Mix "
+            f"{err_mix[-1].mean():.3e} -> Mix+learned {err_ml[-1].mean():.3e}")
+    em, eml = np.concatenate(err_mix), np.concatenate(err_ml)
+    value = tot_entries / (tot_ms * 1e-3)
+    result = {
+        "metric": "selected entries of A^-1 per sec (SelInv, Mix, Mix+learned) at stated rel error",
+        "value": value,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": tot_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "random sparse strictly diagonally dominant set (about 10 off-diagonals per "
+                               "row, RCM): of seeds 0-255 the 48 with the smallest n, by seed 32 train / 8 "
+                               f"validation / 8 test; ILDL tau={tau_l:g} (Mix, the network's input) and "
+                               f"{tau_t:g} (SelInv, its target); a step runs the device pipeline on each test "
+                               "matrix once (SelInv with NInv beside it, then Mix and the learned correction "
+                               "in one pass)",
+                   "n_test": [int(x.meta["n"]) for x in test], "nnz_S_test": tot_entries,
+                   "parallelism": "single GPU"},
+        "learned": {"train_seeds": groups["train"], "val_seeds": groups["val"], "test_seeds": groups["test"],
+                    "train_rows": int(sum(len(x.target) for x in samples["train"])), "data_s": t_data,
+                    "train_s": t_train, "epochs": args.learned_epochs, "fallback_to_mix": packed is None,
+                    "test_mean_entry_error_vs_tight_selinv": {"mix": base[0], "mix_learned": got[0],
+                                                              "gain": base[0] / got[0]},
+                    "test_p99_entry_error_vs_tight_selinv": {"mix": base[1], "mix_learned": got[1]},
+                    "test_mean_entry_error_vs_dense_inverse": {"mix": float(em.mean()),
+                                                               "mix_learned": float(eml.mean()),
+                                                               "gain": float(em.mean() / eml.mean())},
+                    "test_p99_entry_error_vs_dense_inverse": {"mix": float(np.quantile(em, 0.99)),
+                                                              "mix_learned": float(np.quantile(eml, 0.99))}},
+    }
+    if not args.no_cpu_baseline:
+        sd = groups["test"][0]
+        A = random_dd_symmetric(sd)
+        F = ildl_bk(A, rcm(A), tau_l)
+        S = oc.pattern(F)
+        t0 = time.perf_counter()
+        Zo = oc.selinv(F, S)
+        No = oc.ninv(F, S, p, delta)
+        oc.mix(S, Zo, No, eps)
+        t_cpu = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": S.nnz / t_cpu, "unit": "entries/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"test matrix seed {sd} (n={F.n}, |S|={S.nnz}): single-threaded "
+                                            f"float64 oracle SelInv + NInv + Mix, {t_cpu:.2f} s on one core of "
+                                            f"{host_cpu()}"}
     print(json.dumps(result), flush=True)
 
 
