@@ -454,18 +454,21 @@ def run_stencil27(args):
     Z = torch.empty(nnzS, dtype=torch.float64, device=dev)
     Nn, M, ML = (torch.empty_like(Z) for _ in range(3))
 
+    # the default step's structure: the factor loaded once, NInv beside the
+    # SelInv sweep on the handle's second stream, then Mix (and the learned
+    # correction in the same pass)
     def mix_pipeline(prec):
-        s.selinv(Lv, dd, ds, precision=prec, out=Z)
-        s.ninv(Lv, dd, ds, p=p, delta=delta, precision=prec, out=Nn)
+        s.load_factor(Lv, dd, ds)
+        s.selinv_ninv(p=p, delta=delta, precision=prec, Z=Z, N=Nn)
         s.mix(Z, Nn, eps, out=M)
 
     def learned_pipeline(prec):
         if packed is None:
             mix_pipeline(prec)
             return
-        s.selinv(Lv, dd, ds, precision=prec, out=Z)
-        s.ninv(Lv, dd, ds, p=p, delta=delta, precision=prec, out=Nn)
-        s.mlp_correct_mix(packed, Z, Nn, eps, Lv, dd, ds, M=M, out=ML)
+        s.load_factor(Lv, dd, ds)
+        s.selinv_ninv(p=p, delta=delta, precision=prec, Z=Z, N=Nn)
+        s.mlp_correct_mix(packed, Z, Nn, eps, M=M, out=ML)
 
     for _ in range(args.warmup):
         learned_pipeline("mixed")
@@ -474,6 +477,7 @@ def run_stencil27(args):
           "selinv_mixed": timed(lambda: s.selinv(Lv, dd, ds, precision="mixed", out=Z), args.steps) * 1e3,
           "mix_pipeline_fp64": timed(lambda: mix_pipeline("fp64"), args.steps) * 1e3,
           "mix_pipeline_mixed": timed(lambda: mix_pipeline("mixed"), args.steps) * 1e3,
+          "mix_learned_pipeline_fp64": timed(lambda: learned_pipeline("fp64"), args.steps) * 1e3,
           "mix_learned_pipeline_mixed": timed(lambda: learned_pipeline("mixed"), args.steps) * 1e3}
     s.sync()
     log("times: " + ", ".join(f"{k} {v:.2f} ms" for k, v in ms.items()))
@@ -492,7 +496,10 @@ def run_stencil27(args):
     avg_ms = tot_ms / max(launches, 1)
     achieved = (tot_bytes / launches) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
 
-    step_ms = ms["mix_learned_pipeline_mixed"]
+    # the line reports the faster precision of the Mix + learned step (float64
+    # is at least as accurate, so it qualifies whenever it is faster)
+    fast64 = ms["mix_learned_pipeline_fp64"] <= ms["mix_learned_pipeline_mixed"]
+    step_ms = ms["mix_learned_pipeline_fp64" if fast64 else "mix_learned_pipeline_mixed"]
     result = {
         "metric": "selected entries of A^-1 per sec (SelInv, Mix, Mix+learned) at stated rel error",
         "value": nnzS / (step_ms * 1e-3),
@@ -504,11 +511,13 @@ def run_stencil27(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (mixed: float32 off-diagonal bulk, float64 D blocks and diagonals)",
+        "dtype": "f64" if fast64 else "f32 (mixed: float32 off-diagonal bulk, float64 D blocks and diagonals)",
         "data": "synthetic",
         "config": {"workload": f"3D 27-point lognormal(0,0.5) stencil {N}^3, nested multicolor order, ILDL "
-                               f"tau={tau}; step = mixed-precision SelInv + NInv(p=3, delta=0.1) + Mix(eps=1e-2)"
-                               + (" + learned correction" if packed is not None else " (learned fell back to Mix)"),
+                               f"tau={tau}; step = load the factor, {'float64' if fast64 else 'mixed-precision'} "
+                               f"SelInv with NInv(p=3, delta=0.1) beside it, then Mix(eps=1e-2)"
+                               + (" and the learned correction in one pass" if packed is not None
+                                  else " (learned fell back to Mix)"),
                    "n": F.n, "nnz_A": int(A.nnz), "nnz_L": F.nnzL, "nnz_S": nnzS,
                    "levels": info["n_levels"], "max_cols": info["max_cols"], "parallelism": "single GPU"},
         "methods": {k: {"ms": v, "entries_per_s": nnzS / (v * 1e-3)} for k, v in ms.items()},
