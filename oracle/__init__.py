@@ -11,7 +11,9 @@ Modules:
               SPAI, rank-k correction on S; diagonal and err_1 helpers
   dense       dense numpy references for tiny inputs (masked Takahashi
               recursion, Neumann series, SPAI) and a dense threshold ILDL with
-              Bunch-Kaufman pivots that pins the host factorization
+              Bunch-Kaufman pivots that pins the host factorization; the
+              numeric phase of the factorization on a given pattern and
+              pivot sequence (masked Crout recurrence)
   spectral    dominant eigenpairs of E_inv = A^-1 - A^inv and the acceptance
               test of Algorithm 1
   mlp         float64 forward/backward of the learned per-entry correction

@@ -218,3 +218,42 @@ def dense_ildl_bk(A, tau=0.0, pivoting=True):
         if piv[j] == 1:
             d_sub[j] = ds[j] / (sq[j] * sq[j + 1])
     return order, L, Lpat, d_diag, d_sub, piv
+
+
+def fixed_pattern_ldl(Ah, Lpat, piv):
+    """Numeric phase of the incomplete factorization P^T A P ~ L D L^T
+    (Section 2.1) on a given strictly lower pattern and 1x1/2x2 partition.
+
+    The pivot sequence and the kept entries are the symbolic result of a
+    threshold factorization; given them, each block B = {j} or {j, j+1} of D
+    and each kept entry of L follow from the Crout recurrence, in block order:
+        W(:, B) = Ah(:, B) - L(:, <j) D(<j, <j) L(B, <j)^T,
+        D_B = W(B, B),
+        L(i, B) = W(i, B) D_B^-1 where (i, B) is kept, 0 elsewhere.
+    Dense matrices, library matrix products, no reordering. Returns
+    (L with unit diagonal, d_diag, d_sub) with d_sub[j] = D(j+1, j) at the
+    first index of each 2x2 block.
+    """
+    Ah = np.asarray(Ah, dtype=np.float64)
+    n = Ah.shape[0]
+    L = np.eye(n)
+    D = np.zeros((n, n))
+    d_diag = np.zeros(n)
+    d_sub = np.zeros(n)
+    for j in block_starts(piv):
+        B = [j, j + 1] if piv[j] == 1 else [j]
+        e = j + len(B)
+        W = Ah[:, B] - L[:, :j] @ (D[:j, :j] @ L[B, :j].T)
+        if len(B) == 1:
+            d = W[j, 0]
+            D[j, j] = d_diag[j] = d
+            L[e:, j] = np.where(Lpat[e:, j], W[e:, 0] / d, 0.0)
+        else:
+            d0, d1, s = W[j, 0], W[j + 1, 1], W[j + 1, 0]
+            D[j, j], D[j + 1, j + 1] = d0, d1
+            D[j + 1, j] = D[j, j + 1] = s
+            d_diag[j], d_diag[j + 1], d_sub[j] = d0, d1, s
+            det = d0 * d1 - s * s
+            inv = np.array([[d1, -s], [-s, d0]]) / det
+            L[e:, B] = np.where(Lpat[e:, B], W[e:, :] @ inv, 0.0)
+    return L, d_diag, d_sub
