@@ -337,6 +337,36 @@ asi_status asi_trace(asi_handle h, const double *X_S, int32_t k, const double *V
 asi_status asi_spmv(asi_handle h, const double *X_S, const double *x, double *y);
 
 /*
+ * asi_ildl_numeric: the numeric phase of the incomplete factorization
+ * Ah = P^T A P ~ L D L^T (Section 2.1) on the analysed pattern of L and its
+ * pivot partition piv (asi_analyze), on the device. The threshold
+ * factorization decides which pivots (1x1 or 2x2) and which entries of L are
+ * kept; given those decisions, L and D follow from the Crout recurrence over
+ * the kept entries, block B = {j} or {j, j+1} in order:
+ *     w(i, B) = Ah(i, B) - sum_{C < B} L(i, C) D_C L(B, C)^T,
+ *     D_B = w(B, B),   L(i, B) = w(i, B) D_B^-1 for every kept (i, B),
+ * so that (L D L^T)_ij = Ah_ij on every kept entry and every D block. Run
+ * again with new values of A on the same pattern, or with the pattern and
+ * pivots of a host threshold factorization, it reproduces that factor up to
+ * rounding (no pivot perturbation is applied: a zero D block is an error).
+ * A: the caller's CSR in its own ordering (int64 row pointers, int32
+ * columns, unique within a row, float64 values), perm: n int32 with
+ * Ah(i, j) = A(perm[i], perm[j]); entries of Ah outside the kept pattern are
+ * ignored. Outputs (device, caller-owned): L_val in the layout of the L_col
+ * array given to asi_analyze, d_diag[n], d_sub[n] (D(j+1, j) at the first
+ * index of each 2x2 block, 0 elsewhere), ready for asi_load_factor (this call
+ * loads nothing). Blocks run level by level of the SelInv schedule, last
+ * level first. Errors: ASI_E_ARG; ASI_E_UNSUPPORTED when a row of L holds
+ * only one column of a 2x2 block or a block's rows of L hold more than 3200
+ * entries together (checked on the first call after asi_analyze); at
+ * asi_sync, ASI_E_SINGULAR_D (a zero 1x1 pivot or a singular 2x2 block),
+ * ASI_E_NONFINITE, or ASI_E_ARG for an invalid perm. Asynchronous on the
+ * handle's stream.
+ */
+asi_status asi_ildl_numeric(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                            const int32_t *perm, double *L_val, double *d_diag, double *d_sub);
+
+/*
  * asi_ldl_solve: y = (L D L^T)^-1 x with the factor of asi_load_factor
  * (ASI_E_STATE if none is loaded): forward substitution with the unit lower
  * L, the D-block inverses, backward substitution with L^T, level by level of
@@ -506,7 +536,8 @@ typedef enum {
     ASI_K_MLP_FORWARD = 10,  /* MLP inference */
     ASI_K_MLP_TRAIN = 11,    /* MLP backward, loss and Adam */
     ASI_K_DIAG = 12,         /* diagonal error reductions */
-    ASI_K_COUNT = 13
+    ASI_K_ILDL = 13,         /* numeric phase of the incomplete factorization */
+    ASI_K_COUNT = 14
 } asi_kernel_class;
 asi_status asi_profile(asi_handle h, int enable);
 asi_status asi_profile_read(asi_handle h, int32_t kernel_class, int64_t *launches, double *total_ms,

@@ -29,13 +29,13 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor", "asi_selinv_ninv", "asi_trace", "asi_ninv_full", "asi_mix_full",
            "asi_spmv", "asi_ldl_solve", "asi_pcg", "asi_sqmr", "asi_za_diag", "asi_check_matrix",
            "asi_eigs_work_bytes", "asi_eigs_error", "asi_dense_symeig", "asi_block_solve_work_bytes",
-           "asi_pcg_block", "asi_sqmr_block", "asi_mlp_correct_mix"]
+           "asi_pcg_block", "asi_sqmr_block", "asi_mlp_correct_mix", "asi_ildl_numeric"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
 KERNEL_CLASSES = {"dinv": 0, "selinv": 1, "selinv_big": 2, "ninv": 3, "mix": 4, "spai": 5,
                   "lowrank": 6, "gather_l": 7, "selinv_flow": 8, "mlp_features": 9, "mlp_forward": 10,
-                  "mlp_train": 11, "diag": 12}
+                  "mlp_train": 11, "diag": 12, "ildl": 13}
 
 
 class AsiError(RuntimeError):
@@ -91,6 +91,7 @@ def load_library():
         "asi_pcg": [P, P, P, P, P, P, P, f64, i32, P, P],
         "asi_sqmr": [P, P, P, P, P, P, P, f64, i32, P, P],
         "asi_za_diag": [P, P, P, P, P, P, P],
+        "asi_ildl_numeric": [P, P, P, P, P, P, P, P],
         "asi_check_matrix": [P, i32, P, P, P, P, f64],
         "asi_eigs_work_bytes": [i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
         "asi_eigs_error": [P, P, P, P, P, P, P, i32, i32, i32, f64, i32, i32, f64, i32, P, ctypes.c_size_t, P, P, P,
@@ -139,6 +140,7 @@ class Solver:
         self._check(self.lib.asi_create(ctypes.byref(self.h), device, None))
         self.ws = None
         self.n = 0
+        self.nnzL = 0
         self.nnz_S = 0
 
     def __del__(self):
@@ -181,6 +183,7 @@ class Solver:
         self._check(self.lib.asi_analyze(self.h, int(n), rp.ctypes.data, cl.ctypes.data, pv.ctypes.data,
                                          ctypes.byref(nnz), ctypes.byref(wsb)))
         self.n = int(n)
+        self.nnzL = int(rp[-1])
         self.nnz_S = int(nnz.value)
         if workspace_bytes is None and pool_entries is not None:
             workspace_bytes = self.info()["workspace_min"] + 20 * int(pool_entries) + 1024
@@ -376,6 +379,18 @@ class Solver:
         """Mix on NInv's pattern joined with S_eps: lower triangle as (rowptr, col, val)."""
         rp, cl, vl = N_full
         return self._full_call(self.lib.asi_mix_full, (_ptr(Z), _ptr(rp), _ptr(cl), _ptr(vl), float(eps)))
+
+    def ildl_numeric(self, A_rowptr, A_col, A_val, perm, L_val=None, d_diag=None, d_sub=None):
+        """Numeric phase of the incomplete factorization on the analysed
+        pattern and pivots (device): returns (L_val, d_diag, d_sub), ready for
+        load_factor. A is the device CSR of A in its own ordering."""
+        t = self.torch
+        f = lambda x, m: t.empty(m, dtype=t.float64, device=self.device) if x is None else x
+        L_val, d_diag, d_sub = f(L_val, max(self.nnzL, 1)), f(d_diag, self.n), f(d_sub, self.n)
+        self._stream()
+        self._check(self.lib.asi_ildl_numeric(self.h, _ptr(A_rowptr), _ptr(A_col), _ptr(A_val), _ptr(perm),
+                                              _ptr(L_val), _ptr(d_diag), _ptr(d_sub)))
+        return L_val, d_diag, d_sub
 
     def za_diag(self, A_rowptr, A_col, A_val, perm, Z, d=None):
         """Device float64[n]: (Z Ah)_ii, Ah = P^T A P."""

@@ -82,6 +82,10 @@ struct asi_handle_s {
     void *plinv = nullptr;
     void *pw = nullptr;
     int64_t pool_cap = 0;  // entries (sized for float64 values)
+    // numeric factorization: per-level LDS entries and algorithmic bytes (set on its first call)
+    bool ildl_ready = false;
+    std::vector<int32_t> ildl_lvl_entries;
+    double ildl_bytes = 0.0;
     // tracing
     bool prof = false;
     struct Rec {
@@ -295,6 +299,7 @@ asi_status asi_analyze(asi_handle h, int32_t n, const int64_t *L_rowptr_h, const
     int64_t pool = 8 * (int64_t)n + 2 * h->A.nnzL + 4096;
     h->ws_default = L.cur + (size_t)pool * kPoolEntryBytes + 3 * 256;
     h->analyzed = true;
+    h->ildl_ready = false;
     if (nnzS_out) *nnzS_out = h->A.nnzS;
     if (workspace_bytes_out) *workspace_bytes_out = h->ws_default;
     return ASI_OK;
@@ -1111,6 +1116,85 @@ asi_status asi_trace(asi_handle h, const double *X_S, int32_t k, const double *V
     Trace t(h, ASI_K_DIAG, 16.0 * h->A.n + 8.0 * h->A.n * k);
     hipError_t e = asi::launch_trace(h->A.n, h->diagpos, X_S, k, V, lambda, h->red, sums, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "trace");
+    return ASI_OK;
+}
+
+// First call after an analysis: every row of L must hold both columns of
+// each 2x2 block it touches (then the first Lp[i+1] - Lp[i] lower entries of
+// row i of S are exactly row i of L), and the LDS of each level's launch is
+// sized by its largest block (sum of its L row lengths). The algorithmic
+// bytes count, per row i, A's row (12 B an entry, 4 B of iperm), row i of L
+// written (8 B), and for each column k of row i the index and value of row k
+// of L read (12 B an entry).
+static asi_status ildl_prepare(asi_handle h) {
+    if (h->ildl_ready) return ASI_OK;
+    const asi::Analysis &A = h->A;
+    auto len = [&](int32_t i) { return A.L_rowptr[i + 1] - A.L_rowptr[i]; };
+    double bytes = 0.0;
+    for (int32_t i = 0; i < A.n; ++i) {
+        const int64_t lower = A.diagpos[i] - A.rowptr[i] - (A.piv[i] == 2 ? 1 : 0);
+        if (lower != len(i))
+            return fail(h, ASI_E_UNSUPPORTED,
+                        "the numeric factorization needs both columns of a 2x2 block in every row of L holding one");
+        bytes += 8.0 * len(i);
+        for (int64_t p = A.rowptr[i]; p < A.rowptr[i] + len(i); ++p) bytes += 12.0 * len(A.col[p]);
+    }
+    std::vector<int32_t> ent(A.n_levels, 0);
+    for (int32_t l = 0; l < A.n_levels; ++l) {
+        int64_t mx = 0;
+        auto scan = [&](const std::vector<asi::BlockMeta> &meta, const std::vector<int32_t> &lvl) {
+            for (int32_t s = lvl[l]; s < lvl[l + 1]; ++s) {
+                const asi::BlockMeta &M = meta[s];
+                mx = std::max<int64_t>(mx, len(M.j) + (M.two ? len(M.j + 1) : 0));
+            }
+        };
+        scan(A.meta_small, A.lvl_small);
+        scan(A.meta_big, A.lvl_big);
+        if (mx > asi::kIldlMaxEntries)
+            return fail(h, ASI_E_UNSUPPORTED, "a block's rows of L hold more than 3200 entries together");
+        ent[l] = (int32_t)mx;
+    }
+    h->ildl_lvl_entries.swap(ent);
+    h->ildl_bytes = bytes;
+    h->ildl_ready = true;
+    return ASI_OK;
+}
+
+asi_status asi_ildl_numeric(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
+                            const int32_t *perm, double *L_val, double *d_diag, double *d_sub) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!A_rowptr || !A_col || !A_val || !perm || (!L_val && h->A.nnzL > 0) || !d_diag || !d_sub)
+        return fail(h, ASI_E_ARG, "null pointer");
+    s = ildl_prepare(h);
+    if (s != ASI_OK) return s;
+    DeviceGuard g(h->device);
+    const asi::Analysis &A = h->A;
+    asi::IldlParams P{};
+    P.n = A.n;
+    P.rowptr = h->rowptr;
+    P.col = h->col;
+    P.Lp = h->rowptr_L;
+    P.piv = h->piv;
+    P.Ap = A_rowptr;
+    P.Aj = A_col;
+    P.Av = A_val;
+    P.perm = perm;
+    P.iperm = h->iperm;
+    P.L = L_val;
+    P.dd = d_diag;
+    P.ds = d_sub;
+    P.status = h->status;
+    hipError_t e;
+    {
+        Trace t(h, ASI_K_ILDL, h->ildl_bytes);
+        e = asi::launch_iperm(A.n, perm, h->iperm, h->status, h->stream);
+        for (int32_t l = A.n_levels - 1; l >= 0 && e == hipSuccess; --l)
+            e = asi::launch_ildl_level(h->meta_small + A.lvl_small[l], A.lvl_small[l + 1] - A.lvl_small[l],
+                                       h->meta_big + A.lvl_big[l], A.lvl_big[l + 1] - A.lvl_big[l],
+                                       h->ildl_lvl_entries[l], P, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "numeric factorization");
     return ASI_OK;
 }
 

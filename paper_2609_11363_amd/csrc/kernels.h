@@ -190,6 +190,29 @@ hipError_t launch_mixfull(const MixFullParams &P, bool fill, hipStream_t st);
 hipError_t set_nfull_lds_limits();
 
 // Operator applications of the eigen step (y = X x on S, y = Ah x, LDL^T solves)
+// Numeric phase of the incomplete factorization on the analysed pattern:
+// L values at the offsets of the input L's CSR (Lp), columns read from S's
+// CSR (the first Lp[i+1] - Lp[i] entries of row i of S are row i of L),
+// Ah(i, j) = A(perm[i], perm[j]) from the caller's CSR of A.
+struct IldlParams {
+    int32_t n;
+    const int64_t *rowptr;  // S
+    const int32_t *col;
+    const int64_t *Lp;      // input L's row pointers
+    const int8_t *piv;
+    const int64_t *Ap;
+    const int32_t *Aj;
+    const double *Av;
+    const int32_t *perm, *iperm;
+    double *L;               // out: L values (input L's CSR order)
+    double *dd, *ds;         // out: D diagonal and D(j+1, j) at the first index of each 2x2 block
+    int32_t *status;
+};
+// one level of blocks; max_entries = largest sum of the L row lengths of a block
+hipError_t launch_ildl_level(const BlockMeta *ma, int32_t na, const BlockMeta *mb, int32_t nb, int32_t max_entries,
+                             const IldlParams &P, hipStream_t st);
+constexpr int kIldlMaxEntries = 3200;  // 20 B of LDS each: 64000 B per block
+
 struct LdlSolveParams {
     int32_t n, n_levels;
     const int32_t *lvl_small, *lvl_big;  // host: per-level offsets into the block records
