@@ -1123,9 +1123,9 @@ asi_status asi_trace(asi_handle h, const double *X_S, int32_t k, const double *V
 // each 2x2 block it touches (then the first Lp[i+1] - Lp[i] lower entries of
 // row i of S are exactly row i of L), and the LDS of each level's launch is
 // sized by its largest block (sum of its L row lengths). The algorithmic
-// bytes count, per row i, A's row (12 B an entry, 4 B of iperm), row i of L
-// written (8 B), and for each column k of row i the index and value of row k
-// of L read (12 B an entry).
+// bytes count, per row i, row i of L written (8 B an entry) and, for each
+// column k of row i, the index and value of row k of L read (12 B an entry);
+// A's rows are not counted (their size is not known here).
 static asi_status ildl_prepare(asi_handle h) {
     if (h->ildl_ready) return ASI_OK;
     const asi::Analysis &A = h->A;

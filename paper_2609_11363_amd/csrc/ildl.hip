@@ -38,6 +38,16 @@ __device__ inline double wave_sum64(double x) {
     return x;
 }
 
+// Orders lane 0's LDS writes before the other lanes' next reads. A block is
+// one wavefront and LDS accesses of a wavefront are performed in order, so
+// wavefront-scope fences suffice; unlike a workgroup barrier they do not wait
+// for the global loads still in flight (the next column block's prefetch).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // first position p in [0, hi) with c[p] >= key (hi if none)
 __device__ inline int lower_pos(const int32_t *c, int hi, int32_t key) {
     int lo = 0;
@@ -184,7 +194,7 @@ __global__ __launch_bounds__(64) void k_ildl_level(const BlockMeta *__restrict__
             } else {
                 l0 = w0 / cur.d0;
             }
-            __syncthreads();  // every lane has read w[a] (and w[a + 1])
+            wave_sync();  // every lane has read w[a] (and w[a + 1])
             if (lane == 0) {
                 w[a] = w0;
                 l[a] = l0;
@@ -196,7 +206,7 @@ __global__ __launch_bounds__(64) void k_ildl_level(const BlockMeta *__restrict__
                 }
                 if (!isfinite(l0) || !isfinite(l1)) latch_ildl(P.status, 4);
             }
-            __syncthreads();
+            wave_sync();
             a += step;
             cur = nxt;
         }
