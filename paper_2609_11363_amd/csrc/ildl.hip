@@ -32,10 +32,33 @@ namespace {
 
 __device__ inline void latch_ildl(int32_t *status, int32_t code) { atomicCAS(status, 0, code); }
 
+// x of another lane of the same 16-lane row, moved by the DPP pattern CTRL
+template <int CTRL>
+__device__ inline double dpp_move(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double lane_value(double x, int lane) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)v, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes, the same in every lane, in a fixed order: within
+// each 16-lane row by DPP moves (swap neighbours, swap pairs, mirror the
+// halves of 8, mirror the row: each lane then holds its row's sum), then the
+// four row sums read out of lanes 0, 16, 32 and 48. The all-lane moves stay
+// in the vector ALU instead of going through the LDS crossbar.
 __device__ inline double wave_sum64(double x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+    x += dpp_move<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+    x += dpp_move<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+    x += dpp_move<0x141>(x);  // row_half_mirror
+    x += dpp_move<0x140>(x);  // row_mirror
+    return (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
 }
 
 // Orders lane 0's LDS writes before the other lanes' next reads. A block is
