@@ -147,6 +147,25 @@ typedef enum { ASI_SWEEP_AUTO = 0, ASI_SWEEP_LEVELS = 1, ASI_SWEEP_DATAFLOW = 2 
 asi_status asi_set_sweep(asi_handle h, asi_sweep mode);
 
 /*
+ * The level launches asi_selinv makes with ASI_SWEEP_LEVELS (Section 2.1:
+ * one launch per level of the dependency DAG), by kernel variant. Each level
+ * runs its blocks with |R_J| <= 128 in one launch of a wavefront-per-block
+ * variant (levels of more than 3,072 blocks: ASI_SV_SMALL, or ASI_SV_SPLIT
+ * when the level has blocks of more than 512 hits and at most 16,384 blocks)
+ * or a workgroup-per-block variant (levels of 1,537-3,072 / 769-1,536 /
+ * at most 768 blocks: 128 / 256 / 512 threads per block), and its blocks
+ * with |R_J| > 128 in one launch of 1,024 threads per block (at most 1,024
+ * such blocks) or 256. counts_h: host array of ASI_SV_COUNT int64, the
+ * number of launches of each variant per sweep. Host-only; needs
+ * asi_analyze. Errors: ASI_E_ARG, ASI_E_STATE.
+ */
+typedef enum {
+    ASI_SV_SMALL = 0, ASI_SV_SPLIT = 1, ASI_SV_GROUP128 = 2, ASI_SV_GROUP256 = 3,
+    ASI_SV_GROUP512 = 4, ASI_SV_BIG256 = 5, ASI_SV_BIG1024 = 6, ASI_SV_COUNT = 7
+} asi_sweep_variant;
+asi_status asi_sweep_plan(asi_handle h, int64_t *counts_h);
+
+/*
  * NInv (Section 2.2): L^inv = sum_{m=0}^{p} T_m with T_0 = I and
  * T_m = drop_delta(E T_{m-1}), E = I - L, dropping |t| < delta in each new
  * term; N = (L^inv)^T D^-1 L^inv evaluated on S. Columns of L^inv are kept in
@@ -496,6 +515,26 @@ asi_status asi_dense_symeig(int32_t m, const double *T, double *theta, double *Y
  */
 asi_status asi_za_diag(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,
                        const int32_t *perm, const double *Z_S, double *d);
+
+/*
+ * Values on S in A's own ordering. Section 1 asks for entries of A^-1 and
+ * Section 2.1 factors the permuted matrix P^T A P, so entry (i, j) of a
+ * result in the factor ordering approximates (A^-1)(perm[i], perm[j]).
+ * X_S: |S| float64 values in S's CSR layout (factor ordering); perm: n int32,
+ * the factor ordering (P^T A P = A[perm][:, perm], as returned with the
+ * factor). Outputs, the same |S| entries as a CSR matrix in A's ordering:
+ * rowptr_out (n + 1 int64), col_out (|S| int32, sorted and unique within
+ * each row), val_out (|S| float64); row perm[i] holds row i of S with every
+ * column j renamed perm[j]. The values are copied, not recomputed. All
+ * device pointers, owned by the caller; the outputs must not overlap X_S.
+ * Asynchronous on the handle's stream (uses the workspace's inverse
+ * permutation and scan areas, so calls on one handle must not overlap).
+ * Errors: ASI_E_ARG (null pointer, overlap), ASI_E_STATE; at asi_sync,
+ * ASI_E_ARG if perm is not a permutation of 0..n-1 (rows that no index maps
+ * to are then left empty).
+ */
+asi_status asi_unpermute(asi_handle h, const int32_t *perm, const double *X_S, int64_t *rowptr_out,
+                         int32_t *col_out, double *val_out);
 
 /*
  * Input check of host arrays (Section 1: the method takes a symmetric A and

@@ -29,10 +29,12 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_mlp_backward", "asi_mlp_loss", "asi_mlp_adam", "asi_mlp_apply", "asi_diag_err1", "asi_mlp_correct", "asi_load_factor", "asi_selinv_ninv", "asi_trace", "asi_ninv_full", "asi_mix_full",
            "asi_spmv", "asi_ldl_solve", "asi_pcg", "asi_sqmr", "asi_za_diag", "asi_check_matrix",
            "asi_eigs_work_bytes", "asi_eigs_error", "asi_dense_symeig", "asi_block_solve_work_bytes",
-           "asi_pcg_block", "asi_sqmr_block", "asi_mlp_correct_mix", "asi_ildl_numeric"]
+           "asi_pcg_block", "asi_sqmr_block", "asi_mlp_correct_mix", "asi_ildl_numeric",
+           "asi_sweep_plan", "asi_unpermute"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
+SWEEP_VARIANTS = ["small", "split", "group128", "group256", "group512", "big256", "big1024"]
 KERNEL_CLASSES = {"dinv": 0, "selinv": 1, "selinv_big": 2, "ninv": 3, "mix": 4, "spai": 5,
                   "lowrank": 6, "gather_l": 7, "selinv_flow": 8, "mlp_features": 9, "mlp_forward": 10,
                   "mlp_train": 11, "diag": 12, "ildl": 13}
@@ -103,6 +105,8 @@ def load_library():
         "asi_sync": [P],
         "asi_profile": [P, ctypes.c_int],
         "asi_set_sweep": [P, ctypes.c_int],
+        "asi_sweep_plan": [P, P],
+        "asi_unpermute": [P, P, P, P, P, P],
         "asi_mlp_features": [P, P, P, P, f64, P, P, P, P, P],
         "asi_mlp_pack": [P, P, P],
         "asi_mlp_forward": [P, P, P, i64, P],
@@ -392,6 +396,19 @@ class Solver:
                                               _ptr(L_val), _ptr(d_diag), _ptr(d_sub)))
         return L_val, d_diag, d_sub
 
+    def unpermute(self, perm, X):
+        """Values X on S (factor ordering) as a CSR matrix in A's ordering:
+        (rowptr int64, col int32, val float64) device tensors, row perm[i]
+        holding row i of S with columns renamed by perm and sorted."""
+        t = self.torch
+        perm = t.as_tensor(perm, dtype=t.int32, device=self.device).contiguous()
+        rp = t.empty(self.n + 1, dtype=t.int64, device=self.device)
+        cl = t.empty(self.nnz_S, dtype=t.int32, device=self.device)
+        vl = t.empty(self.nnz_S, dtype=t.float64, device=self.device)
+        self._stream()
+        self._check(self.lib.asi_unpermute(self.h, _ptr(perm), _ptr(X), _ptr(rp), _ptr(cl), _ptr(vl)))
+        return rp, cl, vl
+
     def za_diag(self, A_rowptr, A_col, A_val, perm, Z, d=None):
         """Device float64[n]: (Z Ah)_ii, Ah = P^T A P."""
         t = self.torch
@@ -518,6 +535,12 @@ class Solver:
     def set_sweep(self, mode="auto"):
         """SelInv schedule: "auto", "levels" (one launch per DAG level) or "dataflow"."""
         self._check(self.lib.asi_set_sweep(self.h, SWEEP[mode]))
+
+    def sweep_plan(self):
+        """{variant: level launches per SelInv sweep} of the level schedule."""
+        counts = np.zeros(len(SWEEP_VARIANTS), np.int64)
+        self._check(self.lib.asi_sweep_plan(self.h, counts.ctypes.data))
+        return dict(zip(SWEEP_VARIANTS, (int(c) for c in counts)))
 
     def profile(self, enable=True):
         self._stream()

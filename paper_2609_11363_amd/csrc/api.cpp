@@ -566,7 +566,7 @@ static asi_status selinv_launch(asi_handle h, const void *Lu, bool fp64, double 
         P.nheavy = A.lvl_heavy[l];
         if (P.nblk > 0) {
             Trace t(h, ASI_K_SELINV, A.lvl_bytes_small[m][l], st);
-            e = asi::launch_selinv_level(P, false, fp64, st, asi::small_group_size(P.nblk));
+            e = asi::launch_selinv_level(P, asi::small_level_variant(P.nblk, P.nheavy), fp64, st, 0);
             if (e != hipSuccess) return hip_fail(h, e, "selinv level");
         }
         P.meta = h->meta_big + A.lvl_big[l];
@@ -574,7 +574,7 @@ static asi_status selinv_launch(asi_handle h, const void *Lu, bool fp64, double 
         P.nheavy = 0;
         if (P.nblk > 0) {
             Trace t(h, ASI_K_SELINV_BIG, A.lvl_bytes_big[m][l], st);
-            e = asi::launch_selinv_level(P, true, fp64, st, A.lvl_maxc_big[l]);
+            e = asi::launch_selinv_level(P, asi::big_level_variant(P.nblk), fp64, st, A.lvl_maxc_big[l]);
             if (e != hipSuccess) return hip_fail(h, e, "selinv level (large blocks)");
         }
     }
@@ -600,6 +600,21 @@ asi_status asi_set_sweep(asi_handle h, asi_sweep mode) {
     if (mode != ASI_SWEEP_AUTO && mode != ASI_SWEEP_LEVELS && mode != ASI_SWEEP_DATAFLOW)
         return fail(h, ASI_E_ARG, "unknown sweep mode");
     h->sweep = mode;
+    return ASI_OK;
+}
+
+asi_status asi_sweep_plan(asi_handle h, int64_t *counts_h) {
+    if (!h || !counts_h) return h ? fail(h, ASI_E_ARG, "null pointer") : ASI_E_ARG;
+    if (!h->analyzed) return fail(h, ASI_E_STATE, "asi_analyze has not run");
+    static_assert((int)asi::SV_COUNT == (int)ASI_SV_COUNT, "variant numbering");
+    const asi::Analysis &A = h->A;
+    for (int v = 0; v < asi::SV_COUNT; ++v) counts_h[v] = 0;
+    for (int32_t l = 0; l < A.n_levels; ++l) {
+        const int64_t ns = A.lvl_small[l + 1] - A.lvl_small[l];
+        const int64_t nb = A.lvl_big[l + 1] - A.lvl_big[l];
+        if (ns > 0) counts_h[asi::small_level_variant(ns, A.lvl_heavy[l])]++;
+        if (nb > 0) counts_h[asi::big_level_variant(nb)]++;
+    }
     return ASI_OK;
 }
 
@@ -1209,6 +1224,24 @@ asi_status asi_za_diag(asi_handle h, const int64_t *A_rowptr, const int32_t *A_c
     if (e == hipSuccess)
         e = asi::launch_za_diag(h->A.n, h->rowptr, h->col, Z_S, A_rowptr, A_col, A_val, perm, h->iperm, d, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "za diag");
+    return ASI_OK;
+}
+
+asi_status asi_unpermute(asi_handle h, const int32_t *perm, const double *X_S, int64_t *rowptr_out,
+                         int32_t *col_out, double *val_out) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!perm || !X_S || !rowptr_out || !col_out || !val_out) return fail(h, ASI_E_ARG, "null pointer");
+    const int64_t nnz = h->A.nnzS;
+    const char *x0 = reinterpret_cast<const char *>(X_S), *x1 = x0 + nnz * 8;
+    const char *v0 = reinterpret_cast<const char *>(val_out), *v1 = v0 + nnz * 8;
+    const char *c0 = reinterpret_cast<const char *>(col_out), *c1 = c0 + nnz * 4;
+    if ((v0 < x1 && x0 < v1) || (c0 < x1 && x0 < c1)) return fail(h, ASI_E_ARG, "the outputs overlap X_S");
+    DeviceGuard g(h->device);
+    Trace t(h, ASI_K_DIAG, 0.0);
+    hipError_t e = asi::launch_unpermute(h->A.n, h->rowptr, h->col, perm, X_S, h->iperm, h->nf_bsum, rowptr_out,
+                                         col_out, val_out, h->status, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "unpermute");
     return ASI_OK;
 }
 
@@ -2083,7 +2116,8 @@ asi_status asi_sync(asi_handle h) {
         e = asi::launch_fill_i32(h->status, 1, 0, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "clear status");
-        const char *what = st == asi::ST_SINGULAR   ? "singular D block"
+        const char *what = st == asi::ST_PERM        ? "perm is not a permutation of 0..n-1"
+                           : st == asi::ST_SINGULAR ? "singular D block"
                            : st == asi::ST_NONFINITE ? "non-finite value produced"
                            : st == asi::ST_POOL      ? "NInv pool exhausted: enlarge the workspace"
                            : st == asi::ST_TIMEOUT   ? "dataflow wait exceeded its poll limit"

@@ -92,22 +92,43 @@ inline double selinv_block_bytes(int64_t c, int ncols, int64_t hits, bool fp64) 
     return 12.0 * c * ncols + (4.0 + w) * hits + (fp64 ? 16.0 : 20.0) * c * ncols + 8.0 * ncols * ncols;
 }
 
-// Threads per block for a level of nblk blocks with |R_J| <= kSmallCols:
-// enough lanes per block that the level keeps about 6144 wavefronts (256 CUs,
-// 24 resident wavefronts each) busy, from one wavefront up to a 512-thread
-// workgroup per block.
 // A small block with more hits than this takes more than two passes of a
 // wavefront (4 hits per lane per pass); in a level run one wavefront per
 // block such blocks get a whole 256-thread workgroup instead.
 constexpr int32_t kHeavyHits = 512;
 
-inline int small_group_size(int64_t nblk) {
+// The kernel variants of one level launch of the SelInv sweep (the same
+// numbering as asi_sweep_variant in asi.h).
+enum SweepVariant {
+    SV_SMALL = 0,     // one wavefront per block, four per workgroup
+    SV_SPLIT = 1,     // the same, the level's heavy blocks on 256-thread workgroups
+    SV_GROUP128 = 2,  // one workgroup of 128 / 256 / 512 threads per block
+    SV_GROUP256 = 3,
+    SV_GROUP512 = 4,
+    SV_BIG256 = 5,    // |R_J| > kSmallCols: 256 / 1024 threads per block
+    SV_BIG1024 = 6,
+    SV_COUNT = 7
+};
+
+// Variant for a level of nblk blocks with |R_J| <= kSmallCols, nheavy of them
+// with more than kHeavyHits hits: enough lanes per block that the level keeps
+// about 6144 wavefronts (256 CUs, 24 resident wavefronts each) busy, from one
+// wavefront up to a 512-thread workgroup per block. The heavy-block split pays
+// where a level is about one round of wavefronts (its tail is the longest hit
+// list); on levels of many rounds the tail is amortised and the split
+// kernel's lower occupancy costs more.
+inline int small_level_variant(int64_t nblk, int64_t nheavy) {
     const int64_t waves = 6144;
-    if (nblk * 2 > waves) return 64;
-    if (nblk * 4 > waves) return 128;
-    if (nblk * 8 > waves) return 256;
-    return 512;
+    if (nblk * 2 > waves) return (nheavy > 0 && nblk <= 16384) ? SV_SPLIT : SV_SMALL;
+    if (nblk * 4 > waves) return SV_GROUP128;
+    if (nblk * 8 > waves) return SV_GROUP256;
+    return SV_GROUP512;
 }
+
+// Variant for a level of nblk blocks with |R_J| > kSmallCols: few blocks get
+// 1024 threads each (fewer passes over each block's hits), many get 256 (more
+// blocks per compute unit).
+inline int big_level_variant(int64_t nblk) { return nblk <= 1024 ? SV_BIG1024 : SV_BIG256; }
 
 // Builds the analysis; returns 0 or an asi_status code with a message.
 int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, Analysis &out,

@@ -10,7 +10,7 @@
 namespace asi {
 
 // Device-side status codes latched into the workspace status word.
-enum : int32_t { ST_SINGULAR = 3, ST_NONFINITE = 4, ST_POOL = 6, ST_LIMIT = 8, ST_TIMEOUT = 9 };
+enum : int32_t { ST_PERM = 1, ST_SINGULAR = 3, ST_NONFINITE = 4, ST_POOL = 6, ST_LIMIT = 8, ST_TIMEOUT = 9 };
 
 struct SelinvParams {
     const BlockMeta *meta;  // records of this launch's blocks
@@ -34,11 +34,9 @@ struct SelinvParams {
 
 hipError_t launch_dinv(int32_t n, const int8_t *piv, const double *dd, const double *ds, double *dinv,
                        int32_t *status, hipStream_t st);
-// group: threads per block for |R_J| <= kSmallCols (64 = one wavefront per
-// block, four blocks per workgroup; 128, 256 or 512 = one workgroup per block)
-// group: for |R_J| <= kSmallCols, threads per block; for the large blocks,
-// the launch's largest |R_J| (sizes the dynamic LDS)
-hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipStream_t st, int group);
+// one level launch in the given SweepVariant; maxc = the level's largest
+// |R_J| (the LDS size of the large-block variants)
+hipError_t launch_selinv_level(const SelinvParams &P, int variant, bool fp64, hipStream_t st, int32_t maxc);
 // Dataflow sweep over all blocks in one cooperative launch (|R_J| <= kSmallCols).
 int flow_grid(bool fp64);
 hipError_t launch_selinv_flow(const SelinvParams &P, int32_t nblocks, int32_t *done, int32_t epoch,
@@ -94,6 +92,16 @@ hipError_t launch_trace(int32_t n, const int64_t *diagpos, const double *X, int3
 hipError_t launch_lowrank(int64_t nnz, int32_t k, const int32_t *srow, const int32_t *col, const double *V,
                           const double *lam, const double *in, double *out, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st);
+
+// Values on S in A's ordering (perm.hip): row perm[i] of the output holds row
+// i of S with columns renamed by perm and sorted; iperm is work (n int32),
+// bsum the scan's block sums (n / 1024 + 2 uint64). A perm that is not a
+// permutation latches ST_PERM and leaves the rows without a preimage empty.
+hipError_t launch_unpermute(int32_t n, const int64_t *rowptr, const int32_t *col, const int32_t *perm,
+                            const double *X, int32_t *iperm, unsigned long long *bsum, int64_t *rowptr_out,
+                            int32_t *col_out, double *val_out, int32_t *status, hipStream_t st);
+// inclusive scan of a[1..n] in place (a[0] untouched); bsum: n / 1024 + 2 entries
+hipError_t launch_scan_counts(int64_t n, unsigned long long *a, unsigned long long *bsum, hipStream_t st);
 
 struct SpaiParams {
     int32_t n;

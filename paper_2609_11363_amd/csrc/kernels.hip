@@ -561,57 +561,46 @@ hipError_t launch_dinv(int32_t n, const int8_t *piv, const double *dd, const dou
 }
 
 template <typename T>
-static void launch_small_family(const SelinvParams &P, int group, hipStream_t st) {
+static void launch_variant(const SelinvParams &P, int variant, int32_t maxc, hipStream_t st) {
     constexpr int W = 4;
-    switch (group) {
-        case 64:
-            // the split pays where a level is about one round of wavefronts (its
-            // tail is the longest hit list); on levels of many rounds the tail is
-            // amortised and the split kernel's lower occupancy costs more
-            if (P.nheavy > 0 && P.nblk <= 16384)
-                hipLaunchKernelGGL((dev::k_selinv_split<T>), dim3(P.nheavy + (P.nblk - P.nheavy + W - 1) / W),
-                                   dim3(64 * W), 0, st, P);
-            else
-                hipLaunchKernelGGL((dev::k_selinv_small<T, W>), dim3((P.nblk + W - 1) / W), dim3(64 * W), 0, st,
-                                   P);
+    switch (variant) {
+        case SV_SPLIT:
+            hipLaunchKernelGGL((dev::k_selinv_split<T>), dim3(P.nheavy + (P.nblk - P.nheavy + W - 1) / W),
+                               dim3(64 * W), 0, st, P);
             break;
-        case 128:
+        case SV_GROUP128:
             hipLaunchKernelGGL((dev::k_selinv_group<T, 128>), dim3(P.nblk), dim3(128), 0, st, P);
             break;
-        case 256:
+        case SV_GROUP256:
             hipLaunchKernelGGL((dev::k_selinv_group<T, 256>), dim3(P.nblk), dim3(256), 0, st, P);
             break;
-        default:
+        case SV_GROUP512:
             hipLaunchKernelGGL((dev::k_selinv_group<T, 512>), dim3(P.nblk), dim3(512), 0, st, P);
+            break;
+        case SV_BIG256:
+        case SV_BIG1024: {
+            const int32_t C = std::min<int32_t>(kBigCols, (maxc + 63) & ~63);
+            const bool wide = variant == SV_BIG1024;
+            const size_t lds = selinv_big_lds_bytes(sizeof(T) == 8, wide ? 1024 : 256, C);
+            if (wide)
+                hipLaunchKernelGGL((dev::k_selinv_big<T, 1024>), dim3(P.nblk), dim3(1024), lds, st, P, C);
+            else
+                hipLaunchKernelGGL((dev::k_selinv_big<T, 256>), dim3(P.nblk), dim3(256), lds, st, P, C);
+            break;
+        }
+        default:
+            hipLaunchKernelGGL((dev::k_selinv_small<T, W>), dim3((P.nblk + W - 1) / W), dim3(64 * W), 0, st, P);
             break;
     }
 }
 
-hipError_t launch_selinv_level(const SelinvParams &P, bool big, bool fp64, hipStream_t st, int group) {
+hipError_t launch_selinv_level(const SelinvParams &P, int variant, bool fp64, hipStream_t st, int32_t maxc) {
     if (P.nblk <= 0) return hipSuccess;
-    if (!big) {
-        if (fp64)
-            launch_small_family<double>(P, group, st);
-        else
-            launch_small_family<float>(P, group, st);
-    } else {
-        // group = the level's largest |R_J|; few blocks: 1024 threads per block
-        // (fewer passes over each block's hits), many: 256 (more blocks per CU)
-        const int32_t C = std::min<int32_t>(kBigCols, (group + 63) & ~63);
-        const bool wide = P.nblk <= 1024;
-        const size_t lds = selinv_big_lds_bytes(fp64, wide ? 1024 : 256, C);
-        if (fp64) {
-            if (wide)
-                hipLaunchKernelGGL((dev::k_selinv_big<double, 1024>), dim3(P.nblk), dim3(1024), lds, st, P, C);
-            else
-                hipLaunchKernelGGL((dev::k_selinv_big<double, 256>), dim3(P.nblk), dim3(256), lds, st, P, C);
-        } else {
-            if (wide)
-                hipLaunchKernelGGL((dev::k_selinv_big<float, 1024>), dim3(P.nblk), dim3(1024), lds, st, P, C);
-            else
-                hipLaunchKernelGGL((dev::k_selinv_big<float, 256>), dim3(P.nblk), dim3(256), lds, st, P, C);
-        }
-    }
+    if (variant < 0 || variant >= SV_COUNT) return hipErrorInvalidValue;
+    if (fp64)
+        launch_variant<double>(P, variant, maxc, st);
+    else
+        launch_variant<float>(P, variant, maxc, st);
     return hipGetLastError();
 }
 

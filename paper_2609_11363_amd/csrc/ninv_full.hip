@@ -378,7 +378,7 @@ hipError_t set_nfull_lds_limits() {
     return e;
 }
 
-static hipError_t scan_counts(int64_t n, unsigned long long *a, unsigned long long *bsum, hipStream_t st) {
+hipError_t launch_scan_counts(int64_t n, unsigned long long *a, unsigned long long *bsum, hipStream_t st) {
     const int64_t nb = (n + dev::kScanB - 1) / dev::kScanB;
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(dev::k_scan_block, dim3((unsigned)nb), dim3(dev::kScanB), 0, st, n, a, bsum);
@@ -396,7 +396,7 @@ hipError_t launch_nfull_count_w(const NfullParams &P, hipStream_t st) {
     hipLaunchKernelGGL(dev::k_zero_u64, g1, b, 0, st, (int64_t)n + 1, reinterpret_cast<unsigned long long *>(P.rpT));
     hipLaunchKernelGGL(dev::k_wt_count, g, b, 0, st, n, P.cstart, P.clen, P.prow,
                        reinterpret_cast<unsigned long long *>(P.rpT));
-    hipError_t e = scan_counts(n, reinterpret_cast<unsigned long long *>(P.rpT), P.bsum, st);
+    hipError_t e = launch_scan_counts(n, reinterpret_cast<unsigned long long *>(P.rpT), P.bsum, st);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -428,7 +428,7 @@ hipError_t launch_nfull_rows(const NfullParams &P, bool fill, hipStream_t st) {
     } else {
         hipLaunchKernelGGL(dev::k_nfull_small<false>, g, b, 0, st, P);
         hipLaunchKernelGGL(dev::k_nfull_big<false>, dim3(256), b, lds, st, P);
-        hipError_t e = scan_counts(n, P.cnt, P.bsum, st);
+        hipError_t e = launch_scan_counts(n, P.cnt, P.bsum, st);
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();
@@ -442,7 +442,7 @@ hipError_t launch_mixfull(const MixFullParams &P, bool fill, hipStream_t st) {
     } else {
         hipLaunchKernelGGL(dev::k_zero_u64, dim3((unsigned)((n + 1 + 255) / 256)), b, 0, st, (int64_t)n + 1, P.cnt);
         hipLaunchKernelGGL(dev::k_mixfull<false>, g, b, 0, st, P);
-        hipError_t e = scan_counts(n, P.cnt, P.bsum, st);
+        hipError_t e = launch_scan_counts(n, P.cnt, P.bsum, st);
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();

@@ -102,7 +102,7 @@ def test_numeric_factorization_matches_oracle(name):
 
 def test_new_values_on_the_same_pattern_and_selinv_round_trip():
     import torch
-    from paper_2609_11363_amd import Solver, upload_factors
+    from paper_2609_11363_amd import Solver
     A, F = _case("diff12")
     A2 = sp.csr_matrix(A) * 1.5 + sp.identity(F.n, format="csr") * 0.3  # new values, same pattern of L
     s = Solver(0)
@@ -112,15 +112,16 @@ def test_new_values_on_the_same_pattern_and_selinv_round_trip():
     Lo, ddo, _ = _oracle(A2, F)
     _close("L (new values)", Lv.cpu().numpy()[:F.nnzL], Lo, max(1.0, np.abs(Lo).max()))
     _close("D (new values)", dd.cpu().numpy(), ddo, np.abs(ddo).max())
-    # the device factor of A itself, loaded, gives the SelInv of the host factor
+    # the device factor of A itself, loaded, gives the oracle's SelInv of the
+    # host factor (the two factors agree to rounding)
     Lv, dd, ds = s.ildl_numeric(*_dev(A, F, s.device))
     Zg = s.selinv(Lv, dd, ds)
-    Zh = s.selinv(*upload_factors(F))
     s.sync()
-    err = (Zg - Zh).abs().max().item() / Zh.abs().max().item()
-    print(f"  SelInv from the device factor vs the host factor: {err:.1e}")
+    S = oc.pattern(F)
+    Zo = oc.selinv(F, S)
+    err = oc.entry_error(S, Zg.cpu().numpy(), Zo).max()
+    print(f"  SelInv from the device factor vs the oracle on the host factor: {err:.1e}")
     assert err <= 1e-9
-    assert np.isfinite(oc.selinv(F, oc.pattern(F))).all()
 
 
 def test_full_size_identity_and_host_factor():

@@ -167,3 +167,32 @@ def test_check_matrix_accepts_valid_and_rejects_invalid_input():
     E.data = E.data.copy()
     E.data[3] = np.nan
     assert check(E) == 4  # ASI_E_NONFINITE
+
+
+def test_sweep_plan_reaches_every_variant():
+    """asi_sweep_plan on the layered factor (host-only handle): every level
+    launch variant occurs, and the counts add up to one small-block launch per
+    level with small blocks plus one large-block launch per level with large
+    blocks."""
+    from workloads.layered import layered_factor
+    F = layered_factor(seed=1)
+    h = HostHandle()
+    rc, nnz, _ = h.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    assert rc == 0, h.error()
+    counts = np.zeros(7, np.int64)
+    assert h.lib.asi_sweep_plan(h.h, counts.ctypes.data) == 0
+    plan = dict(zip(asi.SWEEP_VARIANTS, counts.tolist()))
+    assert all(v > 0 for v in plan.values()), plan
+    # levels computed by the oracle's definition: per level, whether it has
+    # blocks with |R_J| <= 128 and with |R_J| > 128
+    S = oc.pattern(F)
+    lev = oc.dag_levels(F, S)
+    firsts = np.nonzero(F.piv != 2)[0]
+    last = np.where(F.piv[firsts] == 1, firsts + 1, firsts)
+    diagpos = S.diag_positions()
+    c = S.rowptr[last + 1] - diagpos[last] - 1
+    small = {int(lev[j]) for j, cj in zip(firsts, c) if cj <= 128}
+    big = {int(lev[j]) for j, cj in zip(firsts, c) if cj > 128}
+    assert sum(plan.values()) == len(small) + len(big)
+    assert plan["big256"] + plan["big1024"] == len(big)
+    assert h.info()["n_levels"] == int(lev.max()) + 1
