@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libasi.so")
 
 SOURCES = ["analyze.cpp", "api.cpp", "kernels.hip", "ninv.hip", "ninv_full.hip", "misc.hip", "mlp.hip", "solve.hip",
-           "eig.hip", "symeig.cpp", "ildl.hip"]
+           "eig.hip", "symeig.cpp", "ildl.hip", "perm.hip"]
 
 # Packed FP32 instructions are disabled for all device code (the compiler
 # would otherwise form them from ordinary float code); the host pass warns
@@ -21,16 +21,24 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-munsafe-fp-atomics"]
 
 
+def _compile(src: str, build_dir: str) -> tuple:
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    lang = ["-x", "hip"] if src.endswith(".hip") or src == "api.cpp" else []
+    cmd = ["hipcc", *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    return src, obj, r
+
+
 def build(verbose: bool = False) -> str:
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") or src == "api.cpp" else []
-        cmd = ["hipcc", *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-               *lang, "-c", os.path.join(CSRC, src), "-o", obj]
-        r = subprocess.run(cmd, capture_output=True, text=True)
+    jobs = max(1, min(8, os.cpu_count() or 1, len(SOURCES)))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
+    objs = []
+    for src, obj, r in results:
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)
             raise RuntimeError(f"hipcc failed on {src}")

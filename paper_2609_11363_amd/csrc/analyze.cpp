@@ -10,6 +10,7 @@
 #include <climits>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "asi_internal.h"
 
@@ -17,6 +18,30 @@ namespace asi {
 
 namespace {
 enum { OK = 0, E_ARG = 1, E_PATTERN = 2, E_UNSUPPORTED = 8 };
+
+// Runs fn(begin, end, worker) over [0, count) split into contiguous chunks,
+// one per worker thread (the analysis' independent per-row and per-block
+// loops; each worker gets its own scratch through its index).
+template <typename Fn>
+void parallel_chunks(int64_t count, int workers, Fn fn) {
+    if (workers <= 1 || count < 4096) {
+        fn((int64_t)0, count, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t step = (count + workers - 1) / workers;
+    for (int w = 0; w < workers; ++w) {
+        const int64_t b = w * step, e = std::min(count, b + step);
+        if (b >= e) break;
+        th.emplace_back(fn, b, e, w);
+    }
+    for (auto &t : th) t.join();
+}
+
+int analysis_workers() {
+    const unsigned hc = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(16u, hc));
+}
 }
 
 int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, Analysis &A,
@@ -151,7 +176,9 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
     A.lsrc_u.assign(A.nnzU, -1);
     A.mirror_u.resize(A.nnzU);
     A.useg_u.resize(A.nnzU);
-    for (int32_t j = 0; j < n; ++j) {
+    const int workers = analysis_workers();
+    parallel_chunks(n, workers, [&](int64_t jb, int64_t je, int) {
+    for (int32_t j = (int32_t)jb; j < (int32_t)je; ++j) {
         const int64_t p0 = A.diagpos[j] + 1, u0 = A.ustart[j];
         for (int64_t u = u0; u < A.ustart[j + 1]; ++u) {
             int64_t p = p0 + (u - u0);
@@ -172,17 +199,22 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
             }
         }
     }
-    for (int64_t u = 0; u < A.nnzU; ++u) A.useg_u[u] = A.ustart[A.ucol[u]];
+    });
+    parallel_chunks(A.nnzU, workers, [&](int64_t b, int64_t e, int) {
+        for (int64_t u = b; u < e; ++u) A.useg_u[u] = A.ustart[A.ucol[u]];
+    });
     // S position -> u-index of the entry's L value (int32; the learned
     // correction, which reads it, needs |S| < 2^31)
     A.s2u.assign(A.nnzS <= (int64_t)INT32_MAX ? A.nnzS : 0, -1);
     if (!A.s2u.empty())
-        for (int32_t i = 0; i < n; ++i)
-            for (int64_t p = A.diagpos[i] + 1; p < A.rowptr[i + 1]; ++p) {
-                const int32_t u = (int32_t)(A.ustart[i] + (p - A.diagpos[i] - 1));
-                A.s2u[p] = u;
-                A.s2u[A.mirror[p]] = u;
-            }
+        parallel_chunks(n, workers, [&](int64_t ib, int64_t ie, int) {
+            for (int32_t i = (int32_t)ib; i < (int32_t)ie; ++i)
+                for (int64_t p = A.diagpos[i] + 1; p < A.rowptr[i + 1]; ++p) {
+                    const int32_t u = (int32_t)(A.ustart[i] + (p - A.diagpos[i] - 1));
+                    A.s2u[p] = u;
+                    A.s2u[A.mirror[p]] = u;
+                }
+        });
 
     // blocks, levels and work counts
     A.level.assign(n, 0);
@@ -191,32 +223,50 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
     A.n_blocks = (int32_t)blocks.size();
     std::vector<int32_t> bcols(n, 0);
     std::vector<int64_t> bhits(n, 0);
-    std::vector<int32_t> mark(n, -1);
     int32_t maxlev = -1;
     for (auto it = blocks.rbegin(); it != blocks.rend(); ++it) {
         int32_t j = *it;
         int32_t last = piv[j] == 1 ? j + 1 : j;
         int64_t u0 = A.diagpos[last] + 1, u1 = A.rowptr[last + 1];
         int32_t lev = 0;
-        for (int64_t p = u0; p < u1; ++p) {
-            lev = std::max(lev, A.level[A.col[p]] + 1);
-            mark[A.col[p]] = j;
-        }
+        for (int64_t p = u0; p < u1; ++p) lev = std::max(lev, A.level[A.col[p]] + 1);
         A.level[j] = lev;
         if (last != j) A.level[last] = lev;
         maxlev = std::max(maxlev, lev);
         int32_t c = (int32_t)(u1 - u0);
         bcols[j] = c;
         A.max_cols = std::max(A.max_cols, c);
-        for (int64_t p = u0; p < u1; ++p) {
-            int32_t l = A.col[p];
-            int64_t s0 = A.diagpos[l] + 1, s1 = A.rowptr[l + 1];
-            A.gather_pairs += s1 - s0;
-            for (int64_t s = s0; s < s1; ++s) bhits[j] += (mark[A.col[s]] == j);
-        }
-        A.gather_hits += bhits[j];
     }
     A.n_levels = maxlev + 1;
+    // hits of every block (independent per block: per-worker marks)
+    {
+        std::vector<int64_t> wpairs(workers, 0), whits(workers, 0);
+        parallel_chunks((int64_t)blocks.size(), workers, [&](int64_t bb, int64_t be, int w) {
+            std::vector<int32_t> mark(n, -1);
+            int64_t pairs = 0, hits = 0;
+            for (int64_t bi = bb; bi < be; ++bi) {
+                const int32_t j = blocks[bi];
+                const int32_t last = piv[j] == 1 ? j + 1 : j;
+                const int64_t u0 = A.diagpos[last] + 1, u1 = A.rowptr[last + 1];
+                for (int64_t p = u0; p < u1; ++p) mark[A.col[p]] = j;
+                int64_t h = 0;
+                for (int64_t p = u0; p < u1; ++p) {
+                    const int32_t l = A.col[p];
+                    const int64_t s0 = A.diagpos[l] + 1, s1 = A.rowptr[l + 1];
+                    pairs += s1 - s0;
+                    for (int64_t q = s0; q < s1; ++q) h += (mark[A.col[q]] == j);
+                }
+                bhits[j] = h;
+                hits += h;
+            }
+            wpairs[w] = pairs;
+            whits[w] = hits;
+        });
+        for (int w = 0; w < workers; ++w) {
+            A.gather_pairs += wpairs[w];
+            A.gather_hits += whits[w];
+        }
+    }
     if (A.max_cols > kBigCols) {
         msg = "a block has more than 2048 rows below it (|R_J| limit)";
         return E_UNSUPPORTED;
@@ -227,14 +277,25 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
         for (int32_t j : blocks) words += bhits[j] * (bcols[j] <= kSmallCols ? 1 : 2);
         A.hits.resize(words);
         A.hit_ptr.assign(n + 1, 0);
+        {
+            int64_t w = 0;
+            for (int32_t j : blocks) {
+                const int32_t last = piv[j] == 1 ? j + 1 : j;
+                A.hit_ptr[j] = w;
+                w += bhits[j] * (bcols[j] <= kSmallCols ? 1 : 2);
+                A.hit_ptr[j + 1] = w;
+                if (last != j) A.hit_ptr[last + 1] = w;
+            }
+        }
+        parallel_chunks((int64_t)blocks.size(), workers, [&](int64_t bb, int64_t be, int) {
         std::vector<int32_t> pos(n, -1);
-        int64_t w = 0;
-        for (int32_t j : blocks) {
+        for (int64_t bi = bb; bi < be; ++bi) {
+            const int32_t j = blocks[bi];
             const int32_t last = piv[j] == 1 ? j + 1 : j;
             const int64_t ub = A.ustart[last], ue = A.ustart[last + 1];
             const int32_t c = (int32_t)(ue - ub);
             const bool small = c <= kSmallCols;
-            A.hit_ptr[j] = w;
+            int64_t w = A.hit_ptr[j];
             for (int32_t t = 0; t < c; ++t) pos[A.ucol[ub + t]] = t;
             for (int32_t b = 0; b < c; ++b) {
                 const int32_t l = A.ucol[ub + b];
@@ -252,9 +313,8 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
                 }
             }
             for (int32_t t = 0; t < c; ++t) pos[A.ucol[ub + t]] = -1;
-            A.hit_ptr[j + 1] = w;
-            if (last != j) A.hit_ptr[last + 1] = w;
         }
+        });
     }
     // level-major schedules (blocks in increasing start index within a level)
     std::vector<int32_t> cs(A.n_levels + 1, 0), cb(A.n_levels + 1, 0);
