@@ -537,6 +537,21 @@ asi_status asi_unpermute(asi_handle h, const int32_t *perm, const double *X_S, i
                          int32_t *col_out, double *val_out);
 
 /*
+ * asi_unpermute for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments, outputs and errors, but its work arrays
+ * (the inverse permutation and the row-pointer scan's block sums) live in a
+ * static device array of the library (about 8 MB per device, held until the
+ * process ends) instead of the handle's workspace, and the call allocates
+ * nothing. n <= 2,097,152 (ASI_E_ARG with a message otherwise). Every call on
+ * one device shares that array: calls that overlap on a device (two streams
+ * or two handles) race and must not be issued. The array keeps the previous
+ * call's contents; nothing in it needs to start at zero.
+ */
+asi_status asi_unpermute_noalloc(asi_handle h, const int32_t *perm, const double *X_S, int64_t *rowptr_out,
+                                 int32_t *col_out, double *val_out);
+
+/*
  * Input check of host arrays (Section 1: the method takes a symmetric A and
  * its permuted factorization), for debugging: perm (nullable) is a
  * permutation of 0..n-1; A is a valid CSR (A_rowptr[0] = 0, nondecreasing,

@@ -30,7 +30,7 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_spmv", "asi_ldl_solve", "asi_pcg", "asi_sqmr", "asi_za_diag", "asi_check_matrix",
            "asi_eigs_work_bytes", "asi_eigs_error", "asi_dense_symeig", "asi_block_solve_work_bytes",
            "asi_pcg_block", "asi_sqmr_block", "asi_mlp_correct_mix", "asi_ildl_numeric",
-           "asi_sweep_plan", "asi_unpermute"]
+           "asi_sweep_plan", "asi_unpermute", "asi_unpermute_noalloc"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -107,6 +107,7 @@ def load_library():
         "asi_set_sweep": [P, ctypes.c_int],
         "asi_sweep_plan": [P, P],
         "asi_unpermute": [P, P, P, P, P, P],
+        "asi_unpermute_noalloc": [P, P, P, P, P, P],
         "asi_mlp_features": [P, P, P, P, f64, P, P, P, P, P],
         "asi_mlp_pack": [P, P, P],
         "asi_mlp_forward": [P, P, P, i64, P],

@@ -250,6 +250,12 @@ asi_status asi_create(asi_handle *h, int device, void *stream) {
     auto *p = new asi_handle_s();
     p->device = device;
     p->stream = reinterpret_cast<hipStream_t>(stream);
+    if (device >= 0) {
+        // resolve the no-allocation scratch of asi_unpermute_noalloc on this
+        // device once per process (its result is checked by that call)
+        DeviceGuard g(device);
+        (void)asi::unpermute_scratch_init(device);
+    }
     *h = p;
     return ASI_OK;
 }
@@ -1242,6 +1248,26 @@ asi_status asi_unpermute(asi_handle h, const int32_t *perm, const double *X_S, i
     hipError_t e = asi::launch_unpermute(h->A.n, h->rowptr, h->col, perm, X_S, h->iperm, h->nf_bsum, rowptr_out,
                                          col_out, val_out, h->status, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "unpermute");
+    return ASI_OK;
+}
+
+asi_status asi_unpermute_noalloc(asi_handle h, const int32_t *perm, const double *X_S, int64_t *rowptr_out,
+                                 int32_t *col_out, double *val_out) {
+    asi_status s = need_ready(h);
+    if (s != ASI_OK) return s;
+    if (!perm || !X_S || !rowptr_out || !col_out || !val_out) return fail(h, ASI_E_ARG, "null pointer");
+    if (h->A.n > asi::kUnpermStaticMaxN)
+        return fail(h, ASI_E_ARG, "n exceeds the static scratch of asi_unpermute_noalloc (at most 2,097,152 "
+                                  "unknowns); use asi_unpermute");
+    const int64_t nnz = h->A.nnzS;
+    const char *x0 = reinterpret_cast<const char *>(X_S), *x1 = x0 + nnz * 8;
+    const char *v0 = reinterpret_cast<const char *>(val_out), *v1 = v0 + nnz * 8;
+    const char *c0 = reinterpret_cast<const char *>(col_out), *c1 = c0 + nnz * 4;
+    if ((v0 < x1 && x0 < v1) || (c0 < x1 && x0 < c1)) return fail(h, ASI_E_ARG, "the outputs overlap X_S");
+    DeviceGuard g(h->device);
+    hipError_t e = asi::launch_unpermute_static(h->device, h->A.n, h->rowptr, h->col, perm, X_S, rowptr_out,
+                                                col_out, val_out, h->status, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "unpermute (static scratch)");
     return ASI_OK;
 }
 

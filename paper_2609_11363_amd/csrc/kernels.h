@@ -100,6 +100,16 @@ hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st)
 hipError_t launch_unpermute(int32_t n, const int64_t *rowptr, const int32_t *col, const int32_t *perm,
                             const double *X, int32_t *iperm, unsigned long long *bsum, int64_t *rowptr_out,
                             int32_t *col_out, double *val_out, int32_t *status, hipStream_t st);
+// The same with the iperm and scan work in the library's static device
+// scratch (no workspace, nothing allocated): n <= kUnpermStaticMaxN
+// (hipErrorInvalidValue otherwise). unpermute_scratch_init resolves the
+// scratch's address on `device` (current) once per process; later calls
+// reuse it. Calls that overlap on one device race on the scratch.
+constexpr int32_t kUnpermStaticMaxN = 1 << 21;
+hipError_t unpermute_scratch_init(int device);
+hipError_t launch_unpermute_static(int device, int32_t n, const int64_t *rowptr, const int32_t *col,
+                                   const int32_t *perm, const double *X, int64_t *rowptr_out, int32_t *col_out,
+                                   double *val_out, int32_t *status, hipStream_t st);
 // inclusive scan of a[1..n] in place (a[0] untouched); bsum: n / 1024 + 2 entries
 hipError_t launch_scan_counts(int64_t n, unsigned long long *a, unsigned long long *bsum, hipStream_t st);
 

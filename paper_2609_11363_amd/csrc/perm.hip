@@ -9,6 +9,8 @@
 // and no scratch beyond the inverse permutation are needed.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "kernels.h"
 
 namespace asi {
@@ -86,7 +88,54 @@ __global__ __launch_bounds__(64 * kUnpermWaves) void k_unperm_fill(
     }
 }
 
+// Scratch of the no-allocation variant: the inverse permutation (n int32)
+// and the row-pointer scan's block sums (n / 1024 + 2 uint64) for n up to
+// kUnpermStaticMaxN, one copy per device for the life of the process. Host
+// code never uses this name as an address (on the host it is a stand-in, not
+// device memory): it takes each device's address from hipGetSymbolAddress.
+constexpr size_t kUnpermIpermBytes = (size_t)kUnpermStaticMaxN * 4;
+constexpr size_t kUnpermBsumBytes = ((size_t)kUnpermStaticMaxN / 1024 + 2) * 8;
+static __device__ __align__(256) unsigned char scratch[kUnpermIpermBytes + kUnpermBsumBytes];
+
 }  // namespace dev
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+}  // namespace
+
+hipError_t unpermute_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        // the caller has made `device` current
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(dev::scratch));
+        g_scratch_err[device] = e;
+        g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+        g_scratch_done[device] = true;
+    }
+    return g_scratch_err[device];
+}
+
+hipError_t launch_unpermute_static(int device, int32_t n, const int64_t *rowptr, const int32_t *col,
+                                   const int32_t *perm, const double *X, int64_t *rowptr_out, int32_t *col_out,
+                                   double *val_out, int32_t *status, hipStream_t st) {
+    if (n < 0 || n > kUnpermStaticMaxN) return hipErrorInvalidValue;
+    hipError_t e = unpermute_scratch_init(device);
+    if (e != hipSuccess) return e;
+    unsigned char *base;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = static_cast<unsigned char *>(g_scratch_ptr[device]);
+    }
+    int32_t *iperm = reinterpret_cast<int32_t *>(base);
+    unsigned long long *bsum = reinterpret_cast<unsigned long long *>(base + dev::kUnpermIpermBytes);
+    return launch_unpermute(n, rowptr, col, perm, X, iperm, bsum, rowptr_out, col_out, val_out, status, st);
+}
 
 hipError_t launch_unpermute(int32_t n, const int64_t *rowptr, const int32_t *col, const int32_t *perm,
                             const double *X, int32_t *iperm, unsigned long long *bsum, int64_t *rowptr_out,
