@@ -1,15 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark: selected entries of A^-1 per second on one MI355X.
 
-Default workload (--workload diffusion64): 3D 7-point variable-coefficient
-diffusion on a 64^3 grid (n = 262,144, lognormal(0, 1) face coefficients,
-seed 2), nested multicolor ordering, threshold ILDL with drop tolerance 1e-3
-(host, untimed). One step is one pass of the hot path on the resident
-factors, all through libasi's C ABI: load the factor, SelInv (float64) with
+Default workload (--workload stencil27_128): the 3D 27-point stencil on a
+128^3 grid (n = 2,097,152, nnz(A) = 55,742,968, lognormal(0, 0.5)
+coefficients, seed 5), nested multicolor ordering, threshold ILDL with drop
+tolerance 1e-3 (host, untimed). One step is one pass of the hot path on the
+resident factors, all through libasi's C ABI: load the factor, SelInv with
 NInv (p = 3, delta = 0.1) beside it, then Mix (eps = 1e-2) and the learned
 correction (trained before the timed region on small grids of the same
 family) in one pass. value = |S| / step time (entries of the Mix+learned
-result per second; the step also produces the SelInv and Mix results).
+result per second; the step also produces the SelInv and Mix results), in
+the faster of float64 and mixed precision. The CPU baseline is the oracle's
+SelInv + NInv + Mix on a trailing sub-factor of the same workload (an exact
+sub-problem), whose result is also compared entry by entry with the
+trailing block of the device's.
+
+--workload diffusion64: 3D 7-point variable-coefficient diffusion on a 64^3
+grid (n = 262,144, lognormal(0, 1) face coefficients, seed 2), the same step.
 
 --workload indefinite512: the 5-point Laplacian on 512^2 minus sigma I with
 20 negative eigenvalues, Bunch-Kaufman ILDL at 1e-3; one step is SelInv ->
@@ -24,9 +31,8 @@ diag(A^-1).
 one step SelInv with NInv beside it -> Mix -> SPAI -> diagonal -> trace; the
 spectral check with the device eigen step (block Lanczos, block PCG).
 
---workload stencil27_128 / stencil27_equal_error: the 27-point stencil at
-128^3, and the equal-error comparison of SelInv at tighter drop tolerances
-against Mix + learned at 64^3.
+--workload stencil27_equal_error: the equal-error comparison of SelInv at
+tighter drop tolerances against Mix + learned on the 27-point stencil.
 
 --workload randdd: random sparse diagonally dominant matrices (the 48 of
 smallest n among seeds 0-255, n 2,034-5,701): the learned correction trained
@@ -61,6 +67,12 @@ HBM_PEAK_GBS = 8000.0
 SELINV_TRAFFIC = {"sources_sha256": "ea108a0f50c10dd45cb20cec4ba6a45a7a83bce8ff336f32efb5c1df9d1bac9b",
                   "bytes_per_launch": (3.406e9 + 0.370e9) / 140,
                   "profile": "profiles/selinv_ninv_mix_learned_diffusion64.md"}
+
+
+# The same for the 27-point 128^3 stencil (the default workload); filled from
+# its profile once the counters have been taken on the current sources.
+STENCIL_TRAFFIC = {"sources_sha256": None, "bytes_per_launch": None,
+                   "profile": "profiles/selinv_ninv_mix_learned_stencil128.md"}
 
 
 def selinv_sources_sha256():
@@ -107,12 +119,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="diffusion64",
+    ap.add_argument("--workload", default="stencil27_128",
                     choices=["diffusion64", "indefinite512", "stencil27_128", "stencil27_equal_error",
                              "covariance200", "randdd"])
     ap.add_argument("--grid", type=int, default=None, help="grid size (default 64, 512, 128 per workload)")
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target time of the CPU oracle baseline's sample (stencil27_128)")
     ap.add_argument("--learned-epochs", type=int, default=30)
     ap.add_argument("--sweeps", default="levels,dataflow",
                     help="SelInv schedules to time separately (comma list of levels, dataflow)")
@@ -180,12 +194,15 @@ def ildl_device(s, A, F, dev, t_host):
     err_L = float((Lg[:F.nnzL].cpu() - torch.as_tensor(F.L_val)).abs().max() / np.abs(F.L_val).max())
     err_D = float((dg.cpu() - torch.as_tensor(F.d_diag)).abs().max() / np.abs(F.d_diag).max())
     alg = prof[2] / max(prof[0], 1)
-    log(f"numeric factorization on the device {ms:.2f} ms (host threshold ILDL {t_host:.1f} s); "
+    log(f"numeric phase of the factorization on the device {ms:.2f} ms (host threshold ILDL with its pivot and "
+        f"drop decisions {t_host:.1f} s); "
         f"vs host factor L {err_L:.1e}, D {err_D:.1e}; {alg / (prof[1] * 1e-3) / 1e9:.0f} GB/s algorithmic")
-    return {"ms": ms, "host_threshold_ildl_s": t_host, "speedup_vs_host": t_host * 1e3 / ms,
+    return {"ms": ms, "host_threshold_ildl_s": t_host,
             "alg_bytes": alg, "achieved_gbs": alg / (prof[1] * 1e-3) / 1e9,
             "max_rel_diff_vs_host_factor": {"L": err_L, "D": err_D},
-            "note": "pattern and pivots from the host threshold factorization; values recomputed on the device"}
+            "note": ("numeric phase only: pattern and pivots from the host threshold factorization, values "
+                     "recomputed on the device; the host time also includes the pivot choice and the drop "
+                     "decisions, which this call does not make, so the two times are not a like-for-like pair")}
 
 
 def run_diffusion(args):
@@ -524,15 +541,34 @@ def run_stencil27(args):
     s.sync()
     Z64, N64, M64 = Z.cpu().numpy(), Nn.cpu().numpy(), M.cpu().numpy()
 
+    if args.copy_calibration:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE read for it give
+        # the counters' scale (256 MiB read + 256 MiB written per launch)
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    copy_gbs = copy_bandwidth_gbs(torch, dev)
+    log(f"plain 1 GiB device copy: {copy_gbs:.0f} GB/s (read + write)")
+
+    # live per-launch timing of the SelInv level kernels (HIP events that the
+    # library records around every launch on its stream), in the step itself
     s.profile(True)
-    s.selinv(Lv, dd, ds, out=Z)
+    for _ in range(3):
+        learned_pipeline("fp64")
     prof = s.profile_read()
     s.profile(False)
     s.sync()
+    log("profile: " + ", ".join(f"{k}: {v[0]} launches {v[1]:.3f} ms" for k, v in prof.items() if v[0]))
     launches, tot_ms, tot_bytes = prof["selinv"]
     avg_ms = tot_ms / max(launches, 1)
     achieved = (tot_bytes / launches) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
 
+    traffic = None
+    if N == 128 and tau == 1e-3 and selinv_sources_sha256() == STENCIL_TRAFFIC["sources_sha256"]:
+        traffic = STENCIL_TRAFFIC["bytes_per_launch"]
     # the line reports the faster precision of the Mix + learned step (float64
     # is at least as accurate, so it qualifies whenever it is faster)
     fast64 = ms["mix_learned_pipeline_fp64"] <= ms["mix_learned_pipeline_mixed"]
@@ -559,49 +595,115 @@ def run_stencil27(args):
                    "levels": info["n_levels"], "max_cols": info["max_cols"], "parallelism": "single GPU"},
         "methods": {k: {"ms": v, "entries_per_s": nnzS / (v * 1e-3)} for k, v in ms.items()},
         "learned": learned_info,
-        "roofline": {"kernel": "SelInv level kernels, float64 (k_selinv_small / k_selinv_group)",
+        "roofline": {"kernel": "SelInv level kernels, float64 (k_selinv_small / _split / _group)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches_per_step": launches,
-                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": tot_bytes / max(launches, 1)},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (L2 <-> memory, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                     "traffic_source": STENCIL_TRAFFIC["profile"] if traffic else None,
+                     "launches_per_step": launches // 3, "avg_launch_ms": avg_ms,
+                     "alg_bytes_per_launch": tot_bytes / max(launches, 1),
+                     "copy_achievable_gbs": copy_gbs},
+        "profile_ms_per_step": {k: v[1] / 3 for k, v in prof.items() if v[0]},
+        "sweep_plan": s.sweep_plan(),
         "host": {"ildl_s": t_fact, "analysis_s": t_sym},
         "ildl_numeric_device": ildl_device(s, A, F, dev, t_fact),
     }
     if not args.no_cpu_baseline:
         from oracle import core as oc
-        t0 = time.time()
         S = oc.pattern(F)
-        log(f"oracle pattern {time.time() - t0:.1f}s; oracle NInv on the whole workload starts")
-        t0 = time.perf_counter()
-        No = oc.ninv(F, S, p, delta)
-        t_ninv = time.perf_counter() - t0
-        log(f"oracle NInv {t_ninv:.1f}s")
-        e_ninv = oc.entry_error(S, N64, No)
-        # Mix: the selection rule applied to the device's SelInv and the oracle's NInv
-        e_mix = oc.entry_error(S, M64, oc.mix(S, Z64, No, eps))
-        # SelInv: the defining recursion on sampled blocks (float64 and mixed results)
+        result["cpu_baseline"], result["rel_error_vs_oracle"] = oracle_trailing_sample(
+            F, S, Z64, N64, M64, Zm, p, delta, eps, target_s=args.cpu_seconds)
+        # SelInv on blocks drawn over the whole range: the defining recursion
+        # evaluated from the result's own entries (float64 and mixed results)
         rng = np.random.default_rng(11)
         firsts = np.nonzero(F.piv != 2)[0]
         blocks = np.sort(rng.choice(firsts, size=min(256, len(firsts)), replace=False))
-        t0 = time.perf_counter()
         e_sel = oc.selinv_block_check(F, S, Z64, blocks)
         e_sel_m = oc.selinv_block_check(F, S, Zm, blocks)
-        log(f"SelInv recursion on {len(blocks)} sampled blocks {time.perf_counter() - t0:.1f}s: "
-            f"float64 {e_sel.max():.2e}, mixed {e_sel_m.max():.2e}; NInv {e_ninv.max():.2e}; Mix {e_mix.max():.2e}")
-        result["cpu_baseline"] = {"value": nnzS / t_ninv, "unit": "entries/s", "cores": 1, "kind": "oracle",
-                                  "sample": f"oracle NInv (p=3, delta=0.1) on the whole {N}^3 workload, "
-                                            f"{t_ninv:.1f} s on one core of {host_cpu()} (the oracle SelInv is not "
-                                            f"run at this size)"}
-        result["rel_error_vs_oracle"] = {
-            "ninv_fp64_max_all_entries": float(e_ninv.max()),
-            "mix_fp64_max_selection_rule": float(e_mix.max()),
+        log(f"SelInv recursion on {len(blocks)} sampled blocks: float64 {e_sel.max():.2e}, mixed {e_sel_m.max():.2e}")
+        result["rel_error_vs_oracle"].update({
             "selinv_fp64_max_recursion_256_blocks": float(e_sel.max()),
             "selinv_mixed_max_recursion_256_blocks": float(e_sel_m.max()),
             "mixed_vs_fp64_selinv_max": float(oc.entry_error(S, Zm, Z64).max()),
-            "mixed_vs_fp64_mix_max": float(oc.entry_error(S, Mm, M64).max())}
+            "mixed_vs_fp64_mix_max": float(oc.entry_error(S, Mm, M64).max())})
         if MLm is not None:
             result["rel_error_vs_oracle"]["learned_correction_vs_mix_mean"] = float(
                 oc.entry_error(S, MLm, Mm).mean())
     print(json.dumps(result), flush=True)
+
+
+def oracle_trailing_sample(F, S, Z64, N64, M64, Zm, p, delta, eps, target_s=15.0):
+    """CPU baseline and full-size parity on a trailing sub-factor.
+
+    The unknowns k..n-1 form a sub-problem (L is lower triangular: SelInv,
+    NInv and Mix on them read nothing before k), so the oracle's SelInv +
+    NInv + Mix on that sub-factor is a bounded sample of the same workload,
+    and its result must equal the trailing block of the device's whole
+    result. k is chosen so that the sample holds a share of sum_J |R_J|^2
+    (the oracle's SelInv does a dense |R_J| x |R_J| loop per block) that a
+    probe on a smaller slice predicts to take about target_s seconds. The
+    rate is entries of the sample per second of the oracle on it; the
+    whole-workload time is estimated by scaling SelInv with that share and
+    NInv + Mix with the share of |S|."""
+    import numpy as np
+
+    from oracle import core as oc
+
+    cnt = np.bincount(F.L_col, minlength=F.n).astype(np.float64)
+    w = cnt * cnt
+    tail = np.cumsum(w[::-1])[::-1]  # tail[k] = share of the work from k on
+    total = tail[0]
+
+    def start_for(share):
+        k = int(np.searchsorted(-tail, -share * total))  # first k with tail[k] <= share * total
+        k = min(max(k, 0), F.n - 1)
+        while k > 0 and F.piv[k] == 2:
+            k -= 1
+        return k
+
+    def run(k):
+        G = F.trailing(k)
+        t0 = time.perf_counter()
+        S2 = oc.pattern(G)
+        t1 = time.perf_counter()
+        Zo = oc.selinv(G, S2)
+        t2 = time.perf_counter()
+        No = oc.ninv(G, S2, p, delta)
+        Mo = oc.mix(S2, Zo, No, eps)
+        t3 = time.perf_counter()
+        return G, S2, (Zo, No, Mo), (t2 - t1, t3 - t2, t1 - t0)
+
+    probe_share = 0.002
+    _, _, _, tp = run(start_for(probe_share))
+    share = min(0.5, probe_share * target_s / max(sum(tp[:2]), 1e-3))
+    k = start_for(share)
+    G, S2, (Zo, No, Mo), (t_sel, t_nm, t_pat) = run(k)
+    t_cpu = t_sel + t_nm
+    share = tail[k] / total
+    nnzS = S.nnz
+    S_share = S2.nnz / nnzS
+    est = t_sel / share + t_nm / S_share
+    log(f"oracle on the trailing {F.n - k} unknowns ({S2.nnz} entries, {100 * S_share:.1f} % of |S|, "
+        f"{100 * share:.1f} % of sum |R_J|^2): SelInv {t_sel:.1f} s, NInv + Mix {t_nm:.1f} s")
+    # full-size parity on the trailing block
+    errs = {}
+    for name, X, Y in (("selinv_fp64", Z64, Zo), ("ninv_fp64", N64, No), ("mix_fp64", M64, Mo),
+                       ("selinv_mixed", Zm, Zo)):
+        B = S.to_csr(X)[k:, k:]
+        B.sort_indices()
+        errs[name + "_max_trailing_block"] = float(oc.entry_error(S2, np.asarray(B.data), Y).max())
+    log("trailing-block parity: " + ", ".join(f"{a} {b:.2e}" for a, b in errs.items()))
+    est = float(est)
+    baseline = {"value": nnzS / est, "unit": "entries/s", "cores": 1, "kind": "oracle",
+                "sample": (f"single-threaded float64 oracle SelInv + NInv(p={p}, delta={delta}) + Mix(eps={eps}) on "
+                           f"the trailing sub-factor of the same workload (unknowns {k}..{F.n - 1}: {S2.nnz} entries, "
+                           f"{100 * S_share:.1f} % of |S| and {100 * share:.1f} % of the oracle SelInv's sum "
+                           f"|R_J|^2), {t_cpu:.1f} s on one core of {host_cpu()}; value = |S| / the whole-workload "
+                           f"time estimated from it ({est:.0f} s: SelInv scaled by its share of sum |R_J|^2, NInv + "
+                           f"Mix by the share of |S|)"),
+                "sample_s": t_cpu, "sample_entries": int(S2.nnz), "sample_entries_per_s": S2.nnz / t_cpu,
+                "selinv_s": t_sel, "ninv_mix_s": t_nm, "whole_workload_estimate_s": est}
+    return baseline, errs
 
 
 def reference_columns(A, cols, tol=1e-12, max_iter=20000, diag_only=False):

@@ -94,6 +94,24 @@ class IldlFactors:
         """nnz(L + D + L^T) counted over both triangles (2x2 blocks add 2)."""
         return 2 * self.nnzL + self.n + 2 * int(np.count_nonzero(self.piv == 1))
 
+    def trailing(self, k: int) -> "IldlFactors":
+        """The factor of the trailing unknowns k..n-1 (rows and columns of L,
+        D and piv from k on, renumbered from 0; k must not split a 2x2 block).
+        L is lower triangular, so every result of the method on the trailing
+        unknowns depends on this part only: it is a sub-problem whose result
+        is the trailing block of the whole result."""
+        if not 0 <= k < self.n or self.piv[k] == 2:
+            raise ValueError("k must start a block")
+        rows = np.repeat(np.arange(self.n), np.diff(self.L_rowptr))
+        keep = (rows >= k) & (self.L_col >= k)
+        n2 = self.n - k
+        rp = np.zeros(n2 + 1, np.int64)
+        np.add.at(rp, rows[keep] - k + 1, 1)
+        return IldlFactors(n=n2, perm=np.arange(n2, dtype=np.int32), L_rowptr=np.cumsum(rp),
+                           L_col=(self.L_col[keep] - k).astype(np.int32), L_val=self.L_val[keep].copy(),
+                           d_diag=self.d_diag[k:].copy(), d_sub=self.d_sub[k:].copy(), piv=self.piv[k:].copy(),
+                           tau=self.tau, n_2x2=int(np.count_nonzero(self.piv[k:] == 1)))
+
     def L_csr(self):
         return sp.csr_matrix((self.L_val, self.L_col, self.L_rowptr), shape=(self.n, self.n))
 
