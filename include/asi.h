@@ -517,6 +517,51 @@ asi_status asi_za_diag(asi_handle h, const int64_t *A_rowptr, const int32_t *A_c
                        const int32_t *perm, const double *Z_S, double *d);
 
 /*
+ * asi_ildl_threshold: the whole threshold incomplete factorization on the
+ * device, pivot and drop decisions included (Section 2.1 takes the factor
+ * P^T A P ~ L D L^T as given; the paper's own factorization is sequential
+ * and a parallel one is named as future work in its concluding remarks).
+ * It computes, bit for bit, the right-looking threshold ILDL of the
+ * scaled matrix Ah = S A(q, q) S (s_i = 1/sqrt(max_j |a_ij|)) with 1x1
+ * pivots in the given order: the Schur column of pivot p is summed over the
+ * earlier pivots in increasing order, a pivot below 1e-14 max|Ah| is replaced
+ * by +-1e-8 max|Ah| and counted, l_ip = w(i)/d_p is kept when |l_ip| >= tau,
+ * and L <- S^-1 L S, D <- S^-1 D S^-1 at the end. Pivots are taken as they
+ * come: with pivoting != 0 the Bunch-Kaufman 1x1 test (alpha =
+ * (1 + sqrt 17)/8) is applied to every pivot and a pivot that fails it (a
+ * swap or a 2x2 block would be needed) ends the call with
+ * ASI_E_UNSUPPORTED; with pivoting = 0 no test is made. Columns are
+ * eliminated in rounds: every column with no uneliminated smaller neighbour
+ * in the current Schur graph at once.
+ * Inputs (device): A in its own ordering, CSR with int64 row pointers and
+ * int32 columns, structurally symmetric (every stored (i, j) has a stored
+ * (j, i)), unique columns per row; q: n int32, the ordering (Ah = A(q, q)),
+ * a permutation. Work: a caller-owned device buffer of at least
+ * asi_ildl_threshold_work_bytes(n, row_cap, pool_cap) bytes, 256-byte
+ * aligned, that must stay alive until asi_ildl_threshold_extract has run:
+ * row_cap bounds the entries of one row of L, pool_cap the entries of L.
+ * Synchronous (one host read per round). Outputs (host): *nnzL_h = nnz(L);
+ * stats_h (nullable, 2 int64): rounds, replaced pivots. Errors: ASI_E_ARG
+ * (null pointer, q not a permutation, a column out of range),
+ * ASI_E_WORKSPACE (work too small, or a row of L above row_cap or L above
+ * pool_cap: retry with larger ones), ASI_E_UNSUPPORTED (a pivot that needs
+ * Bunch-Kaufman pivoting, a Schur column above 3,072 entries, a row of L
+ * above 2,048 entries).
+ * asi_ildl_threshold_extract writes the factor of the last successful call
+ * on this handle from its work buffer, in the layout asi_analyze and
+ * asi_load_factor take: L_rowptr (n + 1 int64), L_col (nnzL int32, sorted
+ * per row), L_val (nnzL float64), d_diag, d_sub (n float64; d_sub all 0) and
+ * piv (n int8, all 0), device, caller-owned; the ordering is q.
+ * Asynchronous.
+ */
+asi_status asi_ildl_threshold_work_bytes(int32_t n, int32_t row_cap, int64_t pool_cap, size_t *bytes);
+asi_status asi_ildl_threshold(asi_handle h, int32_t n, const int64_t *A_rowptr, const int32_t *A_col,
+                              const double *A_val, const int32_t *q, double tau, int32_t pivoting, int32_t row_cap,
+                              int64_t pool_cap, void *work, size_t work_bytes, int64_t *nnzL_h, int64_t *stats_h);
+asi_status asi_ildl_threshold_extract(asi_handle h, int64_t *L_rowptr, int32_t *L_col, double *L_val,
+                                      double *d_diag, double *d_sub, int8_t *piv);
+
+/*
  * Values on S in A's own ordering. Section 1 asks for entries of A^-1 and
  * Section 2.1 factors the permuted matrix P^T A P, so entry (i, j) of a
  * result in the factor ordering approximates (A^-1)(perm[i], perm[j]).

@@ -30,7 +30,8 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_spmv", "asi_ldl_solve", "asi_pcg", "asi_sqmr", "asi_za_diag", "asi_check_matrix",
            "asi_eigs_work_bytes", "asi_eigs_error", "asi_dense_symeig", "asi_block_solve_work_bytes",
            "asi_pcg_block", "asi_sqmr_block", "asi_mlp_correct_mix", "asi_ildl_numeric",
-           "asi_sweep_plan", "asi_unpermute", "asi_unpermute_noalloc"]
+           "asi_sweep_plan", "asi_unpermute", "asi_unpermute_noalloc", "asi_ildl_threshold_work_bytes",
+           "asi_ildl_threshold", "asi_ildl_threshold_extract"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -108,6 +109,10 @@ def load_library():
         "asi_sweep_plan": [P, P],
         "asi_unpermute": [P, P, P, P, P, P],
         "asi_unpermute_noalloc": [P, P, P, P, P, P],
+        "asi_ildl_threshold_work_bytes": [i32, i32, i64, ctypes.POINTER(ctypes.c_size_t)],
+        "asi_ildl_threshold": [P, i32, P, P, P, P, f64, i32, i32, i64, P, ctypes.c_size_t, ctypes.POINTER(i64),
+                               P],
+        "asi_ildl_threshold_extract": [P, P, P, P, P, P, P],
         "asi_mlp_features": [P, P, P, P, f64, P, P, P, P, P],
         "asi_mlp_pack": [P, P, P],
         "asi_mlp_forward": [P, P, P, i64, P],
@@ -396,6 +401,51 @@ class Solver:
         self._check(self.lib.asi_ildl_numeric(self.h, _ptr(A_rowptr), _ptr(A_col), _ptr(A_val), _ptr(perm),
                                               _ptr(L_val), _ptr(d_diag), _ptr(d_sub)))
         return L_val, d_diag, d_sub
+
+    def ildl_threshold(self, A_rowptr, A_col, A_val, q, tau, pivoting=True, row_cap=512, pool_cap=None,
+                       max_retries=6):
+        """The threshold incomplete factorization on the device (asi_ildl_threshold
+        and _extract). A: device CSR in its own ordering; q: the ordering.
+        Returns (L_rowptr, L_col, L_val, d_diag, d_sub, piv) device tensors and
+        stats {rounds, replaced_pivots, row_cap, pool_cap}. row_cap and
+        pool_cap (default 64 n) are doubled and the call repeated when the
+        library reports them too small."""
+        t = self.torch
+        n = int(A_rowptr.numel()) - 1
+        q = t.as_tensor(q, dtype=t.int32, device=self.device).contiguous()
+        pool_cap = int(pool_cap) if pool_cap is not None else 64 * n
+        for attempt in range(max_retries + 1):
+            nbytes = ctypes.c_size_t(0)
+            self._check(self.lib.asi_ildl_threshold_work_bytes(n, int(row_cap), int(pool_cap),
+                                                               ctypes.byref(nbytes)))
+            work = t.empty(nbytes.value + 256, dtype=t.uint8, device=self.device)
+            base = (work.data_ptr() + 255) & ~255
+            nnz = ctypes.c_int64(0)
+            stats = np.zeros(2, np.int64)
+            self._stream()
+            rc = self.lib.asi_ildl_threshold(self.h, n, _ptr(A_rowptr), _ptr(A_col), _ptr(A_val), _ptr(q),
+                                             float(tau), 1 if pivoting else 0, int(row_cap), int(pool_cap),
+                                             ctypes.c_void_p(base), nbytes.value, ctypes.byref(nnz),
+                                             stats.ctypes.data)
+            if rc == 6 and attempt < max_retries:  # ASI_E_WORKSPACE: a cap was too small
+                del work
+                row_cap, pool_cap = 2 * int(row_cap), 2 * int(pool_cap)
+                continue
+            self._check(rc)
+            break
+        m = int(nnz.value)
+        Lp = t.empty(n + 1, dtype=t.int64, device=self.device)
+        Lc = t.empty(max(m, 1), dtype=t.int32, device=self.device)
+        Lv = t.empty(max(m, 1), dtype=t.float64, device=self.device)
+        dd = t.empty(n, dtype=t.float64, device=self.device)
+        ds = t.empty(n, dtype=t.float64, device=self.device)
+        pv = t.empty(n, dtype=t.int8, device=self.device)
+        self._check(self.lib.asi_ildl_threshold_extract(self.h, _ptr(Lp), _ptr(Lc), _ptr(Lv), _ptr(dd), _ptr(ds),
+                                                        _ptr(pv)))
+        self.sync()
+        del work
+        return (Lp, Lc[:m], Lv[:m], dd, ds, pv), {"rounds": int(stats[0]), "replaced_pivots": int(stats[1]),
+                                                  "row_cap": int(row_cap), "pool_cap": int(pool_cap)}
 
     def unpermute(self, perm, X):
         """Values X on S (factor ordering) as a CSR matrix in A's ordering:

@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libasi.so")
 
 SOURCES = ["analyze.cpp", "api.cpp", "kernels.hip", "ninv.hip", "ninv_full.hip", "misc.hip", "mlp.hip", "solve.hip",
-           "eig.hip", "symeig.cpp", "ildl.hip", "perm.hip"]
+           "eig.hip", "symeig.cpp", "ildl.hip", "perm.hip",
+           "ildl_threshold.hip"]
 
 # Packed FP32 instructions are disabled for all device code (the compiler
 # would otherwise form them from ordinary float code); the host pass warns

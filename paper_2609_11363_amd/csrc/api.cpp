@@ -86,6 +86,10 @@ struct asi_handle_s {
     bool ildl_ready = false;
     std::vector<int32_t> ildl_lvl_entries;
     double ildl_bytes = 0.0;
+    // device threshold factorization: the last call's work buffer and sizes
+    asi::IldlTParams ildlt{};
+    bool ildlt_done = false;
+    int64_t ildlt_nnz = 0;
     // tracing
     bool prof = false;
     struct Rec {
@@ -1216,6 +1220,151 @@ asi_status asi_ildl_numeric(asi_handle h, const int64_t *A_rowptr, const int32_t
                                        h->ildl_lvl_entries[l], P, h->stream);
     }
     if (e != hipSuccess) return hip_fail(h, e, "numeric factorization");
+    return ASI_OK;
+}
+
+// Work buffer of asi_ildl_threshold: offsets of its regions (256-byte
+// aligned), filled into P when base is not null; returns the total size.
+static size_t ildlt_layout(int32_t n, int32_t row_cap, int64_t pool_cap, unsigned char *base, asi::IldlTParams *P) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const size_t nn = (size_t)n, rc = nn * (size_t)row_cap, pc = (size_t)pool_cap;
+    const size_t o_scale = take(nn * 8), o_dpiv = take(nn * 8), o_elim = take(nn * 4), o_watch = take(nn * 4),
+                 o_iq = take(nn * 4), o_rowcnt = take(nn * 4), o_colptr = take(nn * 8), o_collen = take(nn * 4),
+                 o_lc = take(nn * 4), o_lr = take(nn * 4), o_lb = take(nn * 4), o_counts = take(8 * 4),
+                 o_top = take(16), o_bsum = take((nn / 1024 + 2) * 8), o_rk = take(rc * 4), o_rv = take(rc * 8),
+                 o_pr = take(pc * 4), o_pv = take(pc * 8);
+    if (base && P) {
+        P->scale = at<double>(base, o_scale);
+        P->dpiv = at<double>(base, o_dpiv);
+        P->elim = at<int32_t>(base, o_elim);
+        P->watch = at<int32_t>(base, o_watch);
+        P->iq = at<int32_t>(base, o_iq);
+        P->rowcnt = at<int32_t>(base, o_rowcnt);
+        P->colptr = at<int64_t>(base, o_colptr);
+        P->collen = at<int32_t>(base, o_collen);
+        P->list_check = at<int32_t>(base, o_lc);
+        P->list_ready = at<int32_t>(base, o_lr);
+        P->list_big = at<int32_t>(base, o_lb);
+        P->counts = at<int32_t>(base, o_counts);
+        P->status = P->counts + 5;
+        P->pool_top = at<unsigned long long>(base, o_top);
+        P->amax_bits = P->pool_top + 1;
+        P->rk = at<int32_t>(base, o_rk);
+        P->rv = at<double>(base, o_rv);
+        P->pr = at<int32_t>(base, o_pr);
+        P->pv = at<double>(base, o_pv);
+        P->bsum = at<unsigned long long>(base, o_bsum);
+    }
+    return off;
+}
+
+asi_status asi_ildl_threshold_work_bytes(int32_t n, int32_t row_cap, int64_t pool_cap, size_t *bytes) {
+    if (n <= 0 || row_cap <= 0 || pool_cap < 0 || !bytes) return ASI_E_ARG;
+    *bytes = ildlt_layout(n, row_cap, pool_cap, nullptr, nullptr);
+    return ASI_OK;
+}
+
+asi_status asi_ildl_threshold(asi_handle h, int32_t n, const int64_t *A_rowptr, const int32_t *A_col,
+                              const double *A_val, const int32_t *q, double tau, int32_t pivoting, int32_t row_cap,
+                              int64_t pool_cap, void *work, size_t work_bytes, int64_t *nnzL_h, int64_t *stats_h) {
+    asi_status s = need_device(h);
+    if (s != ASI_OK) return s;
+    h->ildlt_done = false;
+    if (n <= 0 || !A_rowptr || !A_col || !A_val || !q || !work || !nnzL_h) return fail(h, ASI_E_ARG, "null pointer");
+    if (!(tau >= 0.0)) return fail(h, ASI_E_ARG, "tau must be >= 0");
+    if (row_cap <= 0 || row_cap > (1 << 20) || pool_cap < 0) return fail(h, ASI_E_ARG, "bad row_cap or pool_cap");
+    if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return fail(h, ASI_E_ARG, "work must be 256-byte aligned");
+    const size_t need = ildlt_layout(n, row_cap, pool_cap, nullptr, nullptr);
+    if (work_bytes < need) return fail(h, ASI_E_WORKSPACE, "work buffer smaller than asi_ildl_threshold_work_bytes");
+    DeviceGuard g(h->device);
+    static bool limits = false;
+    hipError_t e = hipSuccess;
+    if (!limits) {
+        e = asi::ildlt_set_limits();
+        if (e != hipSuccess) return hip_fail(h, e, "threshold factorization LDS limit");
+        limits = true;
+    }
+    asi::IldlTParams P{};
+    ildlt_layout(n, row_cap, pool_cap, static_cast<unsigned char *>(work), &P);
+    P.n = n;
+    P.Ap = A_rowptr;
+    P.Aj = A_col;
+    P.Av = A_val;
+    P.q = q;
+    P.row_cap = row_cap;
+    P.pool_cap = pool_cap;
+    P.tau = tau;
+    P.alpha = (1.0 + std::sqrt(17.0)) / 8.0;
+    P.pivoting = pivoting ? 1 : 0;
+    hipStream_t st = h->stream;
+    e = hipMemsetAsync(P.counts, 0, 8 * 4, st);
+    if (e == hipSuccess) e = hipMemsetAsync(P.pool_top, 0, 16, st);
+    if (e == hipSuccess) e = asi::ildlt_setup(P, st);
+    unsigned long long amax_bits = 0;
+    int32_t cnt[8] = {};
+    if (e == hipSuccess) e = hipMemcpyAsync(&amax_bits, P.amax_bits, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(cnt, P.counts, 8 * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(h, e, "threshold factorization set-up");
+    if (cnt[5] != 0) return fail(h, ASI_E_ARG, "q is not a permutation of 0..n-1 or A has a column out of range");
+    double amax;
+    std::memcpy(&amax, &amax_bits, 8);
+    P.tiny = 1e-14 * amax;
+    P.repl = 1e-8 * amax;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
+        cus = 256;
+    int32_t done = 0, round = 0;
+    for (;; ++round) {
+        P.round = round;
+        e = asi::ildlt_round(P, 4 * cus, 3 * cus, cus, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(cnt, P.counts, 8 * 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(h, e, "threshold factorization round");
+        if (cnt[5] != 0) {
+            const int32_t code = cnt[5];
+            if (code == asi::ST_POOL)
+                return fail(h, ASI_E_WORKSPACE, "a row of L exceeds row_cap or the columns exceed pool_cap");
+            if (code == asi::ST_PIVOT)
+                return fail(h, ASI_E_UNSUPPORTED,
+                            "a pivot fails the Bunch-Kaufman 1x1 test (a swap or a 2x2 block would be needed); "
+                            "the device factorization takes 1x1 pivots in order only");
+            return fail(h, ASI_E_UNSUPPORTED, "a Schur column exceeds 3,072 entries or a row of L 2,048");
+        }
+        if (cnt[3] == n) break;
+        if (cnt[3] <= done) return fail(h, ASI_E_HIP, "threshold factorization made no progress");
+        done = cnt[3];
+    }
+    unsigned long long top = 0;
+    e = hipMemcpy(&top, P.pool_top, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "threshold factorization size");
+    *nnzL_h = (int64_t)top;
+    if (stats_h) {
+        stats_h[0] = round + 1;
+        stats_h[1] = cnt[4];
+    }
+    h->ildlt = P;
+    h->ildlt_done = true;
+    h->ildlt_nnz = (int64_t)top;
+    return ASI_OK;
+}
+
+asi_status asi_ildl_threshold_extract(asi_handle h, int64_t *L_rowptr, int32_t *L_col, double *L_val,
+                                      double *d_diag, double *d_sub, int8_t *piv) {
+    asi_status s = need_device(h);
+    if (s != ASI_OK) return s;
+    if (!h->ildlt_done) return fail(h, ASI_E_STATE, "asi_ildl_threshold has not completed on this handle");
+    if (!L_rowptr || (h->ildlt_nnz > 0 && (!L_col || !L_val)) || !d_diag || !d_sub || !piv)
+        return fail(h, ASI_E_ARG, "null pointer");
+    DeviceGuard g(h->device);
+    const asi::IldlTParams &P = h->ildlt;
+    hipError_t e = asi::ildlt_extract(P, L_rowptr, L_col, L_val, d_diag, d_sub, piv, P.bsum, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "threshold factorization extract");
     return ASI_OK;
 }
 

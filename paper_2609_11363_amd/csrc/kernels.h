@@ -10,7 +10,10 @@
 namespace asi {
 
 // Device-side status codes latched into the workspace status word.
-enum : int32_t { ST_PERM = 1, ST_SINGULAR = 3, ST_NONFINITE = 4, ST_POOL = 6, ST_LIMIT = 8, ST_TIMEOUT = 9 };
+enum : int32_t {
+    ST_PERM = 1, ST_SINGULAR = 3, ST_NONFINITE = 4, ST_POOL = 6, ST_LIMIT = 8, ST_TIMEOUT = 9,
+    ST_PIVOT = 10  // the device threshold factorization met a pivot that needs a swap or a 2x2 block
+};
 
 struct SelinvParams {
     const BlockMeta *meta;  // records of this launch's blocks
@@ -230,6 +233,44 @@ struct IldlParams {
 hipError_t launch_ildl_level(const BlockMeta *ma, int32_t na, const BlockMeta *mb, int32_t nb, int32_t max_entries,
                              const IldlParams &P, hipStream_t st);
 constexpr int kIldlMaxEntries = 3200;  // 20 B of LDS each: 64000 B per block
+
+// Threshold factorization on the device (ildl_threshold.hip): inputs, the
+// work arrays of the round schedule and the factor as it grows (scaled).
+struct IldlTParams {
+    int32_t n;
+    const int64_t *Ap;       // A in its own ordering (symmetric pattern)
+    const int32_t *Aj;
+    const double *Av;
+    const int32_t *q;        // Ah = A(q, q)
+    int32_t *iq;             // n
+    double *scale;           // n: s_i
+    double *dpiv;            // n: scaled pivots (after a tiny-pivot replacement)
+    int32_t *elim;           // n: round of elimination, INT32_MAX while remaining
+    int32_t *watch;          // n: the blocker a column waits for (-1: none yet)
+    int32_t *rowcnt;         // n: entries of row i's list
+    int32_t *rk;             // n x row_cap: row lists (column m, scaled l_im)
+    double *rv;
+    int32_t row_cap;
+    int64_t *colptr;         // n: kept rows of column m in the pool
+    int32_t *collen;
+    int32_t *pr;             // pool_cap: rows (sorted per column) and scaled values
+    double *pv;
+    int64_t pool_cap;
+    unsigned long long *pool_top;
+    unsigned long long *amax_bits;
+    int32_t *list_check, *list_ready, *list_big;  // n each
+    int32_t *counts;         // [0] listed, [1] ready, [2] large, [3] eliminated, [4] replaced pivots
+    int32_t *status;         // counts + 5
+    unsigned long long *bsum;  // n / 1024 + 2: scan sums of the extraction
+    double tau, alpha, tiny, repl;
+    int32_t pivoting;
+    int32_t round;
+};
+hipError_t ildlt_setup(const IldlTParams &P, hipStream_t st);
+hipError_t ildlt_round(const IldlTParams &P, int check_groups, int factor_groups, int big_groups, hipStream_t st);
+hipError_t ildlt_extract(const IldlTParams &P, int64_t *Lp, int32_t *Lc, double *Lv, double *dd, double *ds,
+                         int8_t *piv, unsigned long long *bsum, hipStream_t st);
+hipError_t ildlt_set_limits();
 
 struct LdlSolveParams {
     int32_t n, n_levels;
