@@ -70,8 +70,8 @@ struct asi_handle_s {
     int64_t *cstart = nullptr;
     int32_t *clen = nullptr;
     int32_t *ovf = nullptr;
-    int32_t *ovf2 = nullptr;
-    int32_t *counters = nullptr;  // [0] ovf count, [1] ovf2 count, [2], [3] SPAI list lengths
+    int32_t *clast = nullptr;      // NInv: largest row of each stored series column
+    int32_t *counters = nullptr;  // [0] ovf count, [1] unused, [2], [3] SPAI list lengths
     unsigned long long *pool_top = nullptr;
     int32_t *iperm = nullptr;
     double *cn2 = nullptr;
@@ -162,7 +162,7 @@ Layout make_layout(const asi::Analysis &A) {
     L.add(n * 8);                       // 14 cstart
     L.add(n * 4);                       // 15 clen
     L.add(n * 4);                       // 16 ovf
-    L.add(n * 4);                       // 17 ovf2
+    L.add(n * 4);                       // 17 clast
     L.add(n * 4);                       // 18 iperm
     L.add(n * 8);                       // 19 cn2
     L.add(s * 8);                       // 20 X
@@ -348,7 +348,7 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->cstart = at<int64_t>(b, L.off[14]);
     h->clen = at<int32_t>(b, L.off[15]);
     h->ovf = at<int32_t>(b, L.off[16]);
-    h->ovf2 = at<int32_t>(b, L.off[17]);
+    h->clast = at<int32_t>(b, L.off[17]);
     h->iperm = at<int32_t>(b, L.off[18]);
     h->cn2 = at<double>(b, L.off[19]);
     h->X = at<double>(b, L.off[20]);
@@ -637,6 +637,8 @@ static asi_status ninv_launch(asi_handle h, const void *Lu, bool fp64, int32_t p
     P.n = A.n;
     P.rowptr = h->rowptr;
     P.col = h->col;
+    P.srow = h->srow;
+    P.rowptr_n = A.nnzS;
     P.diagpos = h->diagpos;
     P.mirror = h->mirror;
     P.ustart = h->ustart;
@@ -655,8 +657,7 @@ static asi_status ninv_launch(asi_handle h, const void *Lu, bool fp64, int32_t p
     P.clen = h->clen;
     P.ovf_list = h->ovf;
     P.ovf_count = h->counters;
-    P.ovf2_list = h->ovf2;
-    P.ovf2_count = h->counters + 1;
+    P.clast = h->clast;
     P.out = N_S;
     P.status = h->status;
     hipError_t e;
@@ -730,8 +731,7 @@ asi_status asi_ninv_full(asi_handle h, const double *L_val, const double *d_diag
     Q.clen = h->clen;
     Q.ovf_list = h->ovf;
     Q.ovf_count = h->counters;
-    Q.ovf2_list = h->ovf2;
-    Q.ovf2_count = h->counters + 1;
+    Q.clast = h->clast;
     Q.status = h->status;
     hipError_t e;
     {

@@ -55,6 +55,8 @@ struct NinvParams {
     int32_t n;
     const int64_t *rowptr;
     const int32_t *col;
+    const int32_t *srow;     // |S|: row of every entry of S
+    int64_t rowptr_n;        // |S|
     const int64_t *diagpos;
     const int64_t *mirror;
     const int64_t *ustart;
@@ -72,10 +74,9 @@ struct NinvParams {
     unsigned long long *pool_top;  // allocation counter
     int64_t *cstart;               // n
     int32_t *clen;                 // n (-1: pending in the large-column pass)
+    int32_t *clast;                // n: largest row of the stored column (-1: empty)
     int32_t *ovf_list;             // n
     int32_t *ovf_count;            // 1
-    int32_t *ovf2_list;            // n (product pass overflow)
-    int32_t *ovf2_count;           // 1
     double *out;                   // N on S (float64)
     int32_t *status;
 };

@@ -7,9 +7,10 @@
 // gathered through lsrc. Columns that outgrow the wavefront table are
 // redone by a 256-thread workgroup with a larger table.
 //
-// N = (L^inv)^T D^-1 L^inv on S: for every (i, j) with i >= j in S,
-// N_ij = sum_k L^inv(k, i) w_j(k), w_j = D^-1 L^inv(:, j). One wavefront per
-// column j holds w_j in an LDS hash and streams the columns i of its row.
+// N = (L^inv)^T D^-1 L^inv on S: for every (i, j) in S (i >= j by symmetry),
+// N_ij = sum_k L^inv(k, i) w_j(k), w_j = D^-1 L^inv(:, j). The series columns
+// are stored sorted by row with w beside L^inv, so one thread per entry of S
+// merges the two (short) columns.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -105,6 +106,27 @@ __device__ inline int32_t group_excl_scan(int32_t v, int32_t *scratch, int32_t *
     }
 }
 
+// group-wide maximum (LDS scratch of G/64 ints)
+template <int G>
+__device__ inline int32_t group_max_i(int32_t v, int32_t *scratch) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t t = __shfl_xor(v, o, 64);
+        v = t > v ? t : v;
+    }
+    if constexpr (G == 64) {
+        return v;
+    } else {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        __syncthreads();
+        if (lane == 0) scratch[w] = v;
+        __syncthreads();
+        int32_t m = scratch[0];
+        for (int q = 1; q < G / 64; ++q) m = scratch[q] > m ? scratch[q] : m;
+        __syncthreads();
+        return m;
+    }
+}
+
 template <typename T>
 struct LinvLds {
     int32_t *key;  // H
@@ -188,7 +210,48 @@ __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S,
     }
     gsync<G>();
     const T delta = (T)P.delta;
-    for (int m = 1; m <= P.p; ++m) {
+    int m0 = 1;
+    if (P.p >= 1) {
+        // t^1 = drop_delta(E e_j) = drop_delta(-L(:, j)): the rows of column j
+        // are distinct, so the first term is a filter of the column (the
+        // values -(1 * l) and the test of the general step below, without its
+        // accumulation table)
+        const int64_t u0 = P.ustart[j], u1 = P.ustart[j + 1];
+        int32_t nn = 0;
+        for (int64_t b0 = u0; b0 < u1; b0 += G) {
+            const int64_t q = b0 + tid;
+            int32_t key = -1;
+            T v = T(0);
+            if (q < u1) {
+                const T l = Lu[q];
+                v = -(T(1) * l);
+                if (l != T(0) && !(fabs(v) < delta)) key = P.ucol[q];
+            }
+            int32_t cnt;
+            const int32_t p0 = group_excl_scan<G>(key >= 0 ? 1 : 0, S.scr, &cnt);
+            if (key >= 0) {
+                const int s = hinsert_t(S.key, H, key, S.tl, &S.flag[3]);
+                if (s < 0)
+                    S.flag[0] = 1;
+                else
+                    S.ser[s] += v;
+                if (nn + p0 < TC) {
+                    S.lk[nn + p0] = key;
+                    S.lv[nn + p0] = v;
+                }
+            }
+            nn += cnt;
+        }
+        gsync<G>();
+        if (tid == 0) {
+            S.flag[1] = nn;
+            if (nn > TC) S.flag[0] = 1;
+        }
+        gsync<G>();
+        if (S.flag[0]) return false;
+        m0 = 2;
+    }
+    for (int m = m0; m <= P.p; ++m) {
         const int32_t nl = S.flag[1];
         if (nl == 0) break;
         // columns of L (u-ranges) to scatter: E t = -sum_k t_k L(:, k)
@@ -306,7 +369,7 @@ __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S,
 }
 
 // writes the finished column to the pool
-template <typename T, int G, int H>
+template <typename T, int G, int H, int TC>
 __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, int tid) {
     auto wanted = [&](int s) -> bool {
         int32_t r = S.key[s];
@@ -316,11 +379,27 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
         int ps = hfind(S.key, H, pv == 1 ? r + 1 : r - 1);
         return ps >= 0 && S.ser[ps] != T(0);
     };
+    // which touched slots the column keeps, once per slot (held in nxt, which
+    // is zero between terms and reset with the column); the kept rows are
+    // also listed compactly in lk (free once the series is built) when they
+    // fit, so that each entry's rank in the row order is counted over the
+    // kept rows only
     const int32_t nt = S.flag[3];
     int32_t mine = 0;
-    for (int i = tid; i < nt; i += G) mine += wanted(S.tl[i]);
+    for (int i = tid; i < nt; i += G) {
+        const int s = S.tl[i];
+        const bool keep = wanted(s);
+        S.nxt[s] = keep ? T(1) : T(0);
+        mine += keep;
+    }
     int32_t cnt;
     int32_t pos = group_excl_scan<G>(mine, S.scr, &cnt);
+    const bool compact = cnt <= TC;
+    if (compact)
+        for (int i = tid; i < nt; i += G) {
+            const int s = S.tl[i];
+            if (S.nxt[s] != T(0)) S.lk[pos++] = S.key[s];
+        }
     if (tid == 0) {
         int64_t base = S.base[1];
         if (base + cnt > S.base[2]) {
@@ -342,13 +421,26 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
     gsync<G>();
     const bool fits = S.flag[2] != 0;
     const int64_t base = S.base[0];
+    int32_t last = -1;  // the column's largest row (quick test of the product)
     if (fits) {
         T *plinv = reinterpret_cast<T *>(P.plinv);
         T *pw = reinterpret_cast<T *>(P.pw);
         for (int i = tid; i < nt; i += G) {
             const int s = S.tl[i];
-            if (!wanted(s)) continue;
+            if (S.nxt[s] == T(0)) continue;
             int32_t r = S.key[s];
+            // the column is stored sorted by row: the entry's rank among the
+            // column's kept rows (rows are distinct)
+            int32_t rank = 0;
+            if (compact) {
+                for (int i2 = 0; i2 < cnt; ++i2) rank += S.lk[i2] < r ? 1 : 0;
+            } else {
+                for (int i2 = 0; i2 < nt; ++i2) {
+                    const int s2 = S.tl[i2];
+                    rank += (S.key[s2] < r && S.nxt[s2] != T(0)) ? 1 : 0;
+                }
+            }
+            last = r > last ? r : last;
             T lv = S.ser[s];
             int8_t pv = P.piv[r];
             T w;
@@ -364,15 +456,17 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
                 else
                     w = (T)iv[1] * other + (T)iv[2] * lv;
             }
-            int64_t d = base + pos++;
+            const int64_t d = base + rank;
             P.prow[d] = r;
             plinv[d] = lv;
             pw[d] = w;
         }
     }
+    last = group_max_i<G>(last, S.scr);
     if (tid == 0) {
         P.cstart[j] = base;
         P.clen[j] = fits ? cnt : 0;
+        P.clast[j] = fits ? last : -1;
     }
     gsync<G>();
 }
@@ -400,7 +494,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_linv_small(NinvParams P) {
     const int32_t stride = gridDim.x * WAVES;
     for (int32_t j = blockIdx.x * WAVES + w; j < P.n; j += stride) {
         if (linv_column<T, 64, kLinvH, kLinvTerm>(P, j, S, lane)) {
-            linv_emit<T, 64, kLinvH>(P, j, S, lane);
+            linv_emit<T, 64, kLinvH, kLinvTerm>(P, j, S, lane);
         } else if (lane == 0) {
             P.clen[j] = -1;
             int32_t slot = atomicAdd(P.ovf_count, 1);
@@ -432,7 +526,7 @@ __global__ __launch_bounds__(256) void k_linv_big(NinvParams P) {
     for (int32_t idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
         int32_t j = P.ovf_list[idx];
         if (linv_column<T, 256, H, H>(P, j, S, threadIdx.x)) {
-            linv_emit<T, 256, H>(P, j, S, threadIdx.x);
+            linv_emit<T, 256, H, H>(P, j, S, threadIdx.x);
         } else if (threadIdx.x == 0) {
             P.clen[j] = 0;
             latch2(P.status, ST_LIMIT);
@@ -443,148 +537,52 @@ __global__ __launch_bounds__(256) void k_linv_big(NinvParams P) {
 
 // ---- product N on S --------------------------------------------------------
 
+// N on S entry by entry: for (r, c) in S with i = max(r, c), j = min(r, c),
+// N_ij = sum_k L^inv(k, i) w_j(k) over the rows k the two stored columns
+// share (both sorted by row: a two-pointer merge), in increasing k; a row of
+// column i absent from column j has w_j(k) = 0 and adds nothing. Both
+// triangles are written directly.
 template <typename T>
-struct ProdLds {
-    int32_t *key;
-    T *w;
-    T *acc;
-    int32_t *off;
-    int64_t *start;
-};
-
-template <typename T, int G>
-__device__ void nprod_column(const NinvParams &P, int32_t j, const ProdLds<T> &S, int H, int tid) {
-    const T *plinv = reinterpret_cast<const T *>(P.plinv);
-    const T *pw = reinterpret_cast<const T *>(P.pw);
-    const int64_t p0 = P.diagpos[j];
-    const int32_t ct = (int32_t)(P.rowptr[j + 1] - p0);  // targets i = col[p0 + t], i >= j
-    for (int s = tid; s < H; s += G) S.key[s] = -1;
-    gsync<G>();
-    const int64_t cs = P.cstart[j];
-    const int32_t cl = P.clen[j];
-    for (int t = tid; t < cl; t += G) {
-        int s = hinsert(S.key, H, P.prow[cs + t]);
-        S.w[s] = pw[cs + t];
-    }
-    for (int t = tid; t < ct; t += G) {
-        int32_t i = P.col[p0 + t];
-        S.acc[t] = T(0);
-        S.start[t] = P.cstart[i];
-        S.off[t + 1] = P.clen[i];
-    }
-    gsync<G>();
-    if (tid < 64) {
-        int32_t carry = 0;
-        for (int base = 0; base < ct; base += 64) {
-            int t = base + tid;
-            int32_t v = t < ct ? S.off[t + 1] : 0;
-            int32_t s = v;
-            for (int o = 1; o < 64; o <<= 1) {
-                int32_t u = __shfl_up(s, o, 64);
-                if (tid >= o) s += u;
-            }
-            s += carry;
-            if (t < ct) S.off[t + 1] = s;
-            carry = __shfl(s, 63, 64);
-        }
-        if (tid == 0) S.off[0] = 0;
-    }
-    gsync<G>();
-    const int32_t total = S.off[ct];
-    // uniform trip count: every lane joins the segmented sums
-    for (int32_t t0 = 0; t0 < total; t0 += G) {
-        const int32_t t = t0 + tid;
-        int lo = -1;
-        T v = T(0);
-        if (t < total) {
-            lo = 0;
-            int hi = ct - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (S.off[mid] <= t)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            int64_t q = S.start[lo] + (t - S.off[lo]);
-            int32_t row = P.prow[q];
-            T lvv = plinv[q];
-            int s = hfind(S.key, H, row);
-            if (s >= 0) v = lvv * S.w[s];
-        }
-        // one target per segment: sum the run within the wavefront first
-        const int lane = threadIdx.x & 63;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            T vo = __shfl_down(v, o, 64);
-            int ko = __shfl_down(lo, o, 64);
-            if (lane + o < 64 && ko == lo) v += vo;
-        }
-        int kp = __shfl_up(lo, 1, 64);
-        if (lo >= 0 && (lane == 0 || kp != lo)) atomicAdd(&S.acc[lo], v);
-    }
-    gsync<G>();
-    for (int t = tid; t < ct; t += G) {
-        double v = (double)S.acc[t];
-        P.out[p0 + t] = v;
-        if (t > 0) P.out[P.mirror[p0 + t]] = v;
-    }
-}
-
-constexpr int kProdH = 64;
-constexpr int kProdCt = 160;
-constexpr int kProdHBig = 4096;
-constexpr int kProdCtBig = kBigCols + 2;
-
-template <typename T, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_nprod_small(NinvParams P) {
-    __shared__ int32_t key[WAVES][kProdH];
-    __shared__ T wv[WAVES][kProdH];
-    __shared__ T acc[WAVES][kProdCt];
-    __shared__ int32_t off[WAVES][kProdCt + 1];
-    __shared__ int64_t start[WAVES][kProdCt];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int32_t j = blockIdx.x * WAVES + w;
-    if (j >= P.n) return;
-    const int32_t ct = (int32_t)(P.rowptr[j + 1] - P.diagpos[j]);
-    if (P.clen[j] > kProdH / 2 || ct > kProdCt) {
-        if (lane == 0) {
-            int32_t slot = atomicAdd(P.ovf2_count, 1);
-            P.ovf2_list[slot] = j;
-        }
+__global__ __launch_bounds__(256) void k_nprod_entry(NinvParams P, int64_t nnz, const int32_t *__restrict__ srow) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    const int32_t r = srow[p], c = P.col[p];
+    const int32_t i = r > c ? r : c, j = r > c ? c : r;
+    // the rows of column i are >= i: without a row >= i in column j the two
+    // columns share none and N_ij = 0
+    if (P.clast[j] < i) {
+        P.out[p] = 0.0;
         return;
     }
-    ProdLds<T> S{key[w], wv[w], acc[w], off[w], start[w]};
-    nprod_column<T, 64>(P, j, S, kProdH, lane);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_nprod_big(NinvParams P) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int H = kProdHBig;
-    int64_t *start = reinterpret_cast<int64_t *>(smem);
-    T *wv = reinterpret_cast<T *>(start + kProdCtBig);
-    T *acc = wv + H;
-    int32_t *key = reinterpret_cast<int32_t *>(acc + kProdCtBig);
-    int32_t *off = key + H;
-    ProdLds<T> S{key, wv, acc, off, start};
-    const int32_t cnt = *P.ovf2_count;
-    for (int32_t idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
-        int32_t j = P.ovf2_list[idx];
-        if (P.clen[j] > H / 2) {
-            if (threadIdx.x == 0) latch2(P.status, ST_LIMIT);
+    const T *plinv = reinterpret_cast<const T *>(P.plinv);
+    const T *pw = reinterpret_cast<const T *>(P.pw);
+    const int64_t ci = P.cstart[i], cj = P.cstart[j];
+    const int32_t li = P.clen[i], lj = P.clen[j];
+    T sum = T(0);
+    int32_t a = 0, b = 0;
+    int32_t ra = a < li ? P.prow[ci] : INT32_MAX, rb = b < lj ? P.prow[cj] : INT32_MAX;
+    while (a < li && b < lj) {
+        if (ra == rb) {
+            sum += plinv[ci + a] * pw[cj + b];
+            ++a;
+            ++b;
+            ra = a < li ? P.prow[ci + a] : INT32_MAX;
+            rb = b < lj ? P.prow[cj + b] : INT32_MAX;
+        } else if (ra < rb) {
+            ++a;
+            ra = a < li ? P.prow[ci + a] : INT32_MAX;
         } else {
-            nprod_column<T, 256>(P, j, S, H, threadIdx.x);
+            ++b;
+            rb = b < lj ? P.prow[cj + b] : INT32_MAX;
         }
-        __syncthreads();
     }
+    P.out[p] = (double)sum;
 }
 
 __global__ void k_ninv_reset(NinvParams P) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         *P.pool_top = 0ull;
         *P.ovf_count = 0;
-        *P.ovf2_count = 0;
     }
 }
 
@@ -593,12 +591,6 @@ size_t linv_big_lds() {
     return 32 + 8 * (size_t)kLinvHBig + 3 * (size_t)kLinvHBig * sizeof(T) +
            (4 * (size_t)kLinvHBig + 1 + 8 + 8) * 4 + 64;
 }
-template <typename T>
-size_t nprod_big_lds() {
-    return (size_t)kProdCtBig * 8 + (size_t)kProdHBig * sizeof(T) + (size_t)kProdCtBig * sizeof(T) +
-           (size_t)kProdHBig * 4 + ((size_t)kProdCtBig + 1) * 4 + 64;
-}
-
 // Workgroups of the persistent column kernel: as many as can be resident at
 // once (so the grid-stride loop ends evenly), at most kLinvGrid.
 template <typename T, int W>
@@ -628,21 +620,18 @@ hipError_t run_ninv(const NinvParams &P, hipStream_t st, int cap) {
     hipLaunchKernelGGL((k_linv_small<T, W>), dim3(grid), dim3(64 * W), 0, st, P);
     size_t l1 = linv_big_lds<T>();
     hipLaunchKernelGGL((k_linv_big<T>), dim3(256), dim3(256), l1, st, P);
-    constexpr int W2 = 8;
-    hipLaunchKernelGGL((k_nprod_small<T, W2>), dim3((P.n + W2 - 1) / W2), dim3(64 * W2), 0, st, P);
-    size_t l2 = nprod_big_lds<T>();
-    hipLaunchKernelGGL((k_nprod_big<T>), dim3(256), dim3(256), l2, st, P);
+    const int64_t nnz = P.rowptr_n;
+    if (nnz > 0)
+        hipLaunchKernelGGL((k_nprod_entry<T>), dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, P, nnz, P.srow);
     return hipGetLastError();
 }
 
 }  // namespace dev
 
 hipError_t set_ninv_lds_limits() {
-    const void *fns[] = {(const void *)dev::k_linv_big<double>, (const void *)dev::k_linv_big<float>,
-                         (const void *)dev::k_nprod_big<double>, (const void *)dev::k_nprod_big<float>};
-    const size_t bytes[] = {dev::linv_big_lds<double>(), dev::linv_big_lds<float>(),
-                            dev::nprod_big_lds<double>(), dev::nprod_big_lds<float>()};
-    for (int i = 0; i < 4; ++i) {
+    const void *fns[] = {(const void *)dev::k_linv_big<double>, (const void *)dev::k_linv_big<float>};
+    const size_t bytes[] = {dev::linv_big_lds<double>(), dev::linv_big_lds<float>()};
+    for (int i = 0; i < 2; ++i) {
         hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes[i]);
         if (e != hipSuccess) return e;
     }
