@@ -71,7 +71,8 @@ SELINV_TRAFFIC = {"sources_sha256": "ea108a0f50c10dd45cb20cec4ba6a45a7a83bce8ff3
 
 # The same for the 27-point 128^3 stencil (the default workload); filled from
 # its profile once the counters have been taken on the current sources.
-STENCIL_TRAFFIC = {"sources_sha256": None, "bytes_per_launch": None,
+STENCIL_TRAFFIC = {"sources_sha256": "27803528bdbffa740c2ac1fe5417b895b72c74ee95fc7ff812a6384487bc0dd7",
+                   "bytes_per_launch": (87.464e9 + 5.726e9) / 127,
                    "profile": "profiles/selinv_ninv_mix_learned_stencil128.md"}
 
 
