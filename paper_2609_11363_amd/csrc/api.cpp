@@ -52,6 +52,8 @@ struct asi_handle_s {
     unsigned long long *nf_bsum = nullptr;
     double *cg = nullptr;  // Krylov work vectors (5 n), dot partials (1024), scalars (16)
     double *Ls = nullptr;         // L(max(i, j), min(i, j)) at every position of S (0 where L has none)
+    double *Lcsr = nullptr;       // the loaded factor's L values in the input's row order
+    bool rows_aligned = false;    // row i of L is the lower part of row i of S (the 2x2 (i, i-1) entry aside)
     bool ls_loaded = false;       // Ls holds the loaded factor's values
     double *rn = nullptr;         // ||L(i, :)||_2, then ||L(:, i)||_2, of the factor in Lu (set with it)
     int64_t *rowptr_L = nullptr;  // the input L's row pointers
@@ -188,6 +190,7 @@ Layout make_layout(const asi::Analysis &A) {
     L.add((n / 1024 + 2) * 8);          // 40   scan block sums
     L.add((5 * n + 1024 + 16) * 8);     // 41 Krylov solves: 5 vectors, dot partials, scalars
     L.add(A.s2u.size() * 8);            // 42 L values in S's order (preconditioner solves)
+    L.add(A.nnzL * 8);                  // 43 L values in the input's row order (copied with the factor)
     return L;
 }
 
@@ -310,6 +313,16 @@ asi_status asi_analyze(asi_handle h, int32_t n, const int64_t *L_rowptr_h, const
     h->ws_default = L.cur + (size_t)pool * kPoolEntryBytes + 3 * 256;
     h->analyzed = true;
     h->ildl_ready = false;
+    {
+        // row i of L equals the lower part of row i of S (but for the (i, i-1)
+        // entry of a 2x2 block, which L does not store): then the learned
+        // correction reads L(i, j) for j < i in row order from the copy of L
+        const asi::Analysis &A = h->A;
+        bool al = true;
+        for (int32_t i = 0; i < n && al; ++i)
+            al = A.diagpos[i] - A.rowptr[i] - (A.piv[i] == 2 ? 1 : 0) == A.L_rowptr[i + 1] - A.L_rowptr[i];
+        h->rows_aligned = al;
+    }
     if (nnzS_out) *nnzS_out = h->A.nnzS;
     if (workspace_bytes_out) *workspace_bytes_out = h->ws_default;
     return ASI_OK;
@@ -375,6 +388,7 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->cg = at<double>(b, L.off[41]);
     h->Ls = at<double>(b, L.off[42]);
     h->ls_loaded = false;
+    h->Lcsr = at<double>(b, L.off[43]);
     h->factor_loaded = false;
     h->lf_loaded = false;
     h->epoch = 0;
@@ -488,7 +502,7 @@ static asi_status prepare_factor(asi_handle h, const double *L_val, const double
             // the row and column norms of L (learned-correction features) come with the float64 copy
             if (e == hipSuccess && fp64)
                 e = asi::launch_factor_norms(A.n, h->rowptr_L, L_val, h->ustart, reinterpret_cast<const double *>(h->Lu),
-                                             h->rn, h->stream);
+                                             h->rn, h->Lcsr, h->stream);
         }
         if (e != hipSuccess) return hip_fail(h, e, "gather L");
     } else {
@@ -965,6 +979,9 @@ static asi_status mlp_setup(asi_handle h, const double *Z_S, const double *N_S, 
     P.level = h->level;
     P.maxlevel = A.n_levels - 1;
     P.Lu = reinterpret_cast<const double *>(Lu);
+    P.Lcsr = h->rows_aligned ? h->Lcsr : nullptr;
+    P.Lp = h->rowptr_L;
+    P.rowptr = h->rowptr;
     P.dinv = h->dinv;
     P.node = h->node;
     P.rn = h->rn;

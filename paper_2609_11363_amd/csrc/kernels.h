@@ -152,6 +152,9 @@ struct MlpFeatParams {
     const int32_t *level;
     int32_t maxlevel;
     const double *Lu;    // u-space L values (float64)
+    const double *Lcsr;  // L values in the input's row order (null: take every L value from Lu)
+    const int64_t *Lp;   // n + 1: the input L's row pointers
+    const int64_t *rowptr;  // n + 1: S's row pointers
     const double *dinv;  // 3 per block start
     void *node;          // n per-node feature records of 32 bytes (workspace)
     const double *rn;    // 2n: ||L(i, :)||_2, then ||L(:, i)||_2
@@ -345,7 +348,7 @@ hipError_t launch_scale(int64_t n, double s, double *x, hipStream_t st);
 
 hipError_t launch_node_feats(const MlpFeatParams &P, hipStream_t st);
 hipError_t launch_factor_norms(int32_t n, const int64_t *Lp, const double *Lval, const int64_t *ustart,
-                              const double *Lu, double *rn, hipStream_t st);
+                              const double *Lu, double *rn, double *Lcopy, hipStream_t st);
 hipError_t launch_mlp_features(const MlpFeatParams &P, hipStream_t st);
 hipError_t launch_mlp_correct(const MlpFeatParams &P, const void *W, double *out, hipStream_t st);
 hipError_t launch_mlp_pack(const float *theta, void *W, hipStream_t st);

@@ -62,16 +62,23 @@ __device__ inline double dinv_diag(const double *dinv, const int8_t *piv, int32_
 
 // ||L(i, :)||_2 from the caller's CSR values (row order) into rn[i] and
 // ||L(:, i)||_2 from the column layout (u-range of column i, padding is 0)
-// into rn[n + i]; 16 lanes per unknown, strided over its entries
+// into rn[n + i]; 16 lanes per unknown, strided over its entries. The row
+// values read here are also copied to Lcopy (the loaded factor's row-order
+// copy, read by the learned correction).
 __global__ __launch_bounds__(256) void k_factor_norms(int32_t n, const int64_t *__restrict__ Lp,
                                                       const double *__restrict__ Lval,
                                                       const int64_t *__restrict__ ustart,
-                                                      const double *__restrict__ Lu, double *__restrict__ rn) {
+                                                      const double *__restrict__ Lu, double *__restrict__ rn,
+                                                      double *__restrict__ Lcopy) {
     const int32_t i = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 4);
     const int sub = threadIdx.x & 15;
     double r = 0.0, c = 0.0;
     if (i < n) {
-        for (int64_t q = Lp[i] + sub; q < Lp[i + 1]; q += 16) r += Lval[q] * Lval[q];
+        for (int64_t q = Lp[i] + sub; q < Lp[i + 1]; q += 16) {
+            const double v = Lval[q];
+            r += v * v;
+            Lcopy[q] = v;
+        }
         for (int64_t u = ustart[i] + sub; u < ustart[i + 1]; u += 16) c += Lu[u] * Lu[u];
     }
 #pragma unroll
@@ -174,6 +181,19 @@ __device__ inline void features_of(const MlpFeatParams &P, int32_t i, int32_t j,
 // |L(max(i, j), min(i, j))| at u-index u (-1: diagonal, 0)
 __device__ inline double lval_at(const MlpFeatParams &P, int32_t u) { return u >= 0 ? fabs(P.Lu[u]) : 0.0; }
 
+// The same for entry p = (i, j) of S: below the diagonal, where the column
+// layout would be a scattered gather, from the row-order copy of L when row i
+// of L is the lower part of row i of S (position p - rowptr[i] in the row;
+// past the row's end only the (i, i-1) entry of a 2x2 block, whose L value is
+// 0); above it, from the column layout, which runs along the row.
+__device__ inline double lval_of(const MlpFeatParams &P, int64_t p, int32_t i, int32_t j, int32_t u) {
+    if (P.Lcsr && j < i) {
+        const int64_t t = p - P.rowptr[i], l0 = P.Lp[i];
+        return t < P.Lp[i + 1] - l0 ? fabs(P.Lcsr[l0 + t]) : 0.0;
+    }
+    return lval_at(P, u);
+}
+
 __device__ inline void store_features(uint16_t *dst16, const uint16_t (&f)[NF]) {
     uint4 *dst = reinterpret_cast<uint4 *>(dst16);
     dst[0] = make_uint4(f[0] | (uint32_t)f[1] << 16, f[2] | (uint32_t)f[3] << 16, f[4] | (uint32_t)f[5] << 16,
@@ -189,7 +209,7 @@ __global__ void k_features(MlpFeatParams P) {
     const int32_t i = P.srow[p], j = P.col[p];
     uint16_t f[NF];
     double sc;
-    features_of(P, i, j, node[i], node[j], P.Z[p], P.N[p], P.M[p], lval_at(P, P.s2u[p]), f, sc);
+    features_of(P, i, j, node[i], node[j], P.Z[p], P.N[p], P.M[p], lval_of(P, p, i, j, P.s2u[p]), f, sc);
     store_features(P.F + p * NF, f);
     P.scale[p] = (float)sc;
 }
@@ -417,7 +437,7 @@ __global__ __launch_bounds__(64 * kFwdWaves, 4) void k_mlp_correct(MlpFeatParams
         if (valid) {
             ni = node[ci];
             nj = node[cj];
-            lv = lval_at(P, cu);
+            lv = lval_of(P, p, ci, cj, cu);
             z = P.Z[p];
             nv = P.N[p];
             if constexpr (FUSE)
@@ -589,10 +609,10 @@ __global__ void k_mlp_apply(int64_t nnz, const double *__restrict__ M, const flo
 }  // namespace dev
 
 hipError_t launch_factor_norms(int32_t n, const int64_t *Lp, const double *Lval, const int64_t *ustart,
-                              const double *Lu, double *rn, hipStream_t st) {
+                              const double *Lu, double *rn, double *Lcopy, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(dev::k_factor_norms, dim3((unsigned)(((int64_t)n * 16 + 255) / 256)), dim3(256), 0, st, n, Lp,
-                       Lval, ustart, Lu, rn);
+                       Lval, ustart, Lu, rn, Lcopy);
     return hipGetLastError();
 }
 
