@@ -128,8 +128,9 @@ asi_status asi_load_factor(asi_handle h, const double *L_val, const double *d_di
  * L_col array given to asi_analyze (or L_val, d_diag and d_sub all NULL:
  * the factor of asi_load_factor; ASI_E_STATE if none is loaded).
  * Z_S: |S| float64 outputs.
- * ASI_MIXED keeps the off-diagonal working values, the gathers and their
- * accumulation in float32, and the D-block inverses and Z(J, J) in float64.
+ * ASI_MIXED keeps the off-diagonal working values (their storage, the
+ * gathers and the products) in float32 and sums the products of each block
+ * in float64, with the D-block inverses and Z(J, J) in float64.
  */
 asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
                       asi_precision prec, double *Z_S);

@@ -140,13 +140,16 @@ __global__ void k_dinv(int32_t n, const int8_t *__restrict__ piv, const double *
 // y_a += z L(l, J) (scatter half, LDS atomics on distinct targets) and
 // y_b += z L(r, J) (dot half: hits are sorted by b, so a segmented wavefront
 // sum leaves one atomic per run). Each lane keeps kUnroll hits in flight.
-// T is the working precision of the off-diagonal values and their
-// accumulation; D^-1 and Z(J, J) stay in float64.
+// T is the working precision of the off-diagonal values (storage, gathers
+// and products); the sums y run in float64 LDS accumulators in both modes
+// (float32 LDS atomic adds stall the sweep on gfx950); D^-1 and Z(J, J) stay
+// in float64.
 constexpr int kUnroll = 4;
 
 template <typename T>
 struct SelinvLds {
-    T *l0, *l1, *y0, *y1;
+    T *l0, *l1;
+    double *y0, *y1;
     int64_t *seg;  // c: u-range start of R_J[b]
 };
 
@@ -282,8 +285,8 @@ __device__ void selinv_block(const SelinvParams &P, const BlockMeta &M, const Se
         zrr[k] = T(0);
         if (t < c) {
             zrr[k] = (T)co_load<CO>(&P.zdiag[rr[k]]);
-            S.y0[t] = T(0);
-            if (two) S.y1[t] = T(0);
+            S.y0[t] = 0.0;
+            if (two) S.y1[t] = 0.0;
         }
     }
     group_sync<G>();
@@ -313,13 +316,15 @@ __device__ void selinv_block(const SelinvParams &P, const BlockMeta &M, const Se
         if (base0 + kStep < total) load_hit_words<WIDE, G>(H, base0 + kStep + tid, total, w0, w1);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            T dot0 = T(0), dot1 = T(0);
+            // products in the working precision T, sums in float64 (LDS
+            // accumulators: the float32 LDS atomic add stalls the sweep)
+            double dot0 = 0.0, dot1 = 0.0;
             if (b[u] >= 0) {
-                atomicAdd(&S.y0[a[u]], -z[u] * S.l0[b[u]]);
-                dot0 = -z[u] * S.l0[a[u]];
+                atomicAdd(&S.y0[a[u]], (double)(-z[u] * S.l0[b[u]]));
+                dot0 = (double)(-z[u] * S.l0[a[u]]);
                 if (two) {
-                    atomicAdd(&S.y1[a[u]], -z[u] * S.l1[b[u]]);
-                    dot1 = -z[u] * S.l1[a[u]];
+                    atomicAdd(&S.y1[a[u]], (double)(-z[u] * S.l1[b[u]]));
+                    dot1 = (double)(-z[u] * S.l1[a[u]]);
                 }
             }
             dot0 = seg_suffix_sum(dot0, b[u]);
@@ -337,7 +342,7 @@ __device__ void selinv_block(const SelinvParams &P, const BlockMeta &M, const Se
         const int t = tid + k * G;
         if (t >= c) continue;
         const T l0t = S.l0[t];
-        const T y0 = S.y0[t] - zrr[k] * l0t;
+        const T y0 = (T)(S.y0[t] - (double)(zrr[k] * l0t));
         co_store<CO>(&Zu[ubj + t], y0);
         P.out[M.pdj + t] = (double)y0;
         P.out[mir0[k]] = (double)y0;
@@ -345,7 +350,7 @@ __device__ void selinv_block(const SelinvParams &P, const BlockMeta &M, const Se
         d00 += l0 * (double)y0;
         if (two) {
             const T l1t = S.l1[t];
-            const T y1 = S.y1[t] - zrr[k] * l1t;
+            const T y1 = (T)(S.y1[t] - (double)(zrr[k] * l1t));
             co_store<CO>(&Zu[ub + t], y1);
             P.out[M.pdl + t] = (double)y1;
             P.out[mir1[k]] = (double)y1;
@@ -402,7 +407,7 @@ __device__ void selinv_block(const SelinvParams &P, const BlockMeta &M, const Se
 template <typename T, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_selinv_small(SelinvParams P) {
     __shared__ T sL0[WAVES][kSmallCols], sL1[WAVES][kSmallCols];
-    __shared__ T sY0[WAVES][kSmallCols], sY1[WAVES][kSmallCols];
+    __shared__ double sY0[WAVES][kSmallCols], sY1[WAVES][kSmallCols];
     __shared__ int64_t sSeg[WAVES][kSmallCols];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t bi = blockIdx.x * WAVES + w;
@@ -420,7 +425,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_selinv_split(SelinvParams P) {
     constexpr int W = 4;
     __shared__ T sL0[W][kSmallCols], sL1[W][kSmallCols];
-    __shared__ T sY0[W][kSmallCols], sY1[W][kSmallCols];
+    __shared__ double sY0[W][kSmallCols], sY1[W][kSmallCols];
     __shared__ int64_t sSeg[W][kSmallCols];
     __shared__ double red[4 * W];
     const int32_t b = blockIdx.x;
@@ -443,7 +448,7 @@ __global__ __launch_bounds__(256) void k_selinv_split(SelinvParams P) {
 template <typename T, int G>
 __global__ __launch_bounds__(G) void k_selinv_group(SelinvParams P) {
     __shared__ T sL0[kSmallCols], sL1[kSmallCols];
-    __shared__ T sY0[kSmallCols], sY1[kSmallCols];
+    __shared__ double sY0[kSmallCols], sY1[kSmallCols];
     __shared__ int64_t sSeg[kSmallCols];
     __shared__ double red[4 * (G / 64)];
     const int32_t bi = blockIdx.x;
@@ -461,10 +466,10 @@ __global__ __launch_bounds__(G) void k_selinv_big(SelinvParams P, int32_t C) {
     extern __shared__ __align__(16) unsigned char smem[];
     double *red = reinterpret_cast<double *>(smem);
     int64_t *seg = reinterpret_cast<int64_t *>(red + 4 * (G / 64));
-    T *l0 = reinterpret_cast<T *>(seg + C);
+    double *y0 = reinterpret_cast<double *>(seg + C);
+    double *y1 = y0 + C;
+    T *l0 = reinterpret_cast<T *>(y1 + C);
     T *l1 = l0 + C;
-    T *y0 = l1 + C;
-    T *y1 = y0 + C;
     const int32_t bi = blockIdx.x;
     if (bi >= P.nblk) return;
     SelinvLds<T> S{l0, l1, y0, y1, seg};
@@ -488,7 +493,7 @@ template <typename T, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_selinv_flow(SelinvParams P, int32_t nblocks, int32_t *done,
                                                             int32_t epoch, int32_t spin_limit) {
     __shared__ T sL0[WAVES][kSmallCols], sL1[WAVES][kSmallCols];
-    __shared__ T sY0[WAVES][kSmallCols], sY1[WAVES][kSmallCols];
+    __shared__ double sY0[WAVES][kSmallCols], sY1[WAVES][kSmallCols];
     __shared__ int64_t sSeg[WAVES][kSmallCols];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
     SelinvLds<T> S{sL0[w], sL1[w], sY0[w], sY1[w], sSeg[w]};
@@ -550,7 +555,7 @@ hipError_t launch_lu_to_float(int64_t nnzU, const double *Lu, float *Lf, hipStre
 
 size_t selinv_big_lds_bytes(bool fp64, int G, int32_t C) {
     const size_t w = fp64 ? 8 : 4;
-    return (size_t)4 * (G / 64) * 8 + (size_t)C * 8 + 4 * (size_t)C * w;
+    return (size_t)4 * (G / 64) * 8 + (size_t)C * 8 + 2 * (size_t)C * 8 + 2 * (size_t)C * w;
 }
 
 hipError_t launch_dinv(int32_t n, const int8_t *piv, const double *dd, const double *ds, double *dinv,
