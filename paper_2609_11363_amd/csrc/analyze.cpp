@@ -203,6 +203,14 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
     parallel_chunks(A.nnzU, workers, [&](int64_t b, int64_t e, int) {
         for (int64_t u = b; u < e; ++u) A.useg_u[u] = A.ustart[A.ucol[u]];
     });
+    // every L entry sits at exactly one u-index (the padding of 2x2 unions has none)
+    if (A.nnzU > (int64_t)INT32_MAX) {
+        msg = "more than 2^31 - 1 entries above the diagonal of S";
+        return E_UNSUPPORTED;
+    }
+    A.q2u.assign(A.nnzL, -1);
+    for (int64_t u = 0; u < A.nnzU; ++u)
+        if (A.lsrc_u[u] >= 0) A.q2u[A.lsrc_u[u]] = (int32_t)u;
     // S position -> u-index of the entry's L value (int32; the learned
     // correction, which reads it, needs |S| < 2^31)
     A.s2u.assign(A.nnzS <= (int64_t)INT32_MAX ? A.nnzS : 0, -1);

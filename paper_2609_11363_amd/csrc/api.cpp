@@ -35,7 +35,7 @@ struct asi_handle_s {
     int64_t *mirror = nullptr;
     int64_t *ustart = nullptr;
     int32_t *ucol = nullptr;
-    int64_t *lsrc_u = nullptr;
+    int32_t *q2u = nullptr;        // u-index of each input L entry (the factor load's scatter)
     int64_t *mirror_u = nullptr;
     int64_t *useg = nullptr;
     int64_t *hit_ptr = nullptr;
@@ -168,7 +168,7 @@ Layout make_layout(const asi::Analysis &A) {
     L.add(n * 4);                       // 18 iperm
     L.add(n * 8);                       // 19 cn2
     L.add(s * 8);                       // 20 X
-    L.add(u * 8);                       // 21 lsrc_u
+    L.add(A.nnzL * 4);                  // 21 q2u: u-index of each input L entry
     L.add(u * 8);                       // 22 mirror_u
     L.add(u * 8);                       // 23 useg
     L.add((n + 1) * 8);                 // 24 hit_ptr
@@ -365,7 +365,7 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->iperm = at<int32_t>(b, L.off[18]);
     h->cn2 = at<double>(b, L.off[19]);
     h->X = at<double>(b, L.off[20]);
-    h->lsrc_u = at<int64_t>(b, L.off[21]);
+    h->q2u = at<int32_t>(b, L.off[21]);
     h->mirror_u = at<int64_t>(b, L.off[22]);
     h->useg = at<int64_t>(b, L.off[23]);
     h->hit_ptr = at<int64_t>(b, L.off[24]);
@@ -415,7 +415,7 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
         {h->mirror, A.mirror.data(), A.mirror.size() * 8},
         {h->ustart, A.ustart.data(), A.ustart.size() * 8},
         {h->ucol, A.ucol.data(), A.ucol.size() * 4},
-        {h->lsrc_u, A.lsrc_u.data(), A.lsrc_u.size() * 8},
+        {h->q2u, A.q2u.data(), A.q2u.size() * 4},
         {h->mirror_u, A.mirror_u.data(), A.mirror_u.size() * 8},
         {h->useg, A.useg_u.data(), A.useg_u.size() * 8},
         {h->hit_ptr, A.hit_ptr.data(), A.hit_ptr.size() * 8},
@@ -434,6 +434,10 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     }
     hipError_t e = asi::launch_fill_i32(h->status, 64, 0, h->stream);
     if (e == hipSuccess) e = asi::launch_fill_i32(h->done, A.n, 0, h->stream);
+    // the factor load scatters L's entries into the column layout; the
+    // padding of 2x2 unions (no L entry) keeps these zeros
+    if (e == hipSuccess && A.nnzU > 0) e = hipMemsetAsync(h->Lu, 0, A.nnzU * 8, h->stream);
+    if (e == hipSuccess && A.nnzU > 0) e = hipMemsetAsync(h->Lf, 0, A.nnzU * 4, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "clear status");
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "upload analysis");
@@ -497,8 +501,8 @@ static asi_status prepare_factor(asi_handle h, const double *L_val, const double
         }
         if (e != hipSuccess) return hip_fail(h, e, "dinv");
         {
-            Trace t(h, ASI_K_GATHER, 24.0 * A.nnzU);
-            e = asi::launch_gather_lu(A.nnzU, h->lsrc_u, L_val, fp64 ? h->Lu : (void *)h->Lf, fp64, h->stream);
+            Trace t(h, ASI_K_GATHER, 20.0 * A.nnzL);
+            e = asi::launch_scatter_lu(A.nnzL, h->q2u, L_val, fp64 ? h->Lu : (void *)h->Lf, fp64, h->stream);
             // the row and column norms of L (learned-correction features) come with the float64 copy
             if (e == hipSuccess && fp64)
                 e = asi::launch_factor_norms(A.n, h->rowptr_L, L_val, h->ustart, reinterpret_cast<const double *>(h->Lu),
@@ -674,6 +678,10 @@ static asi_status ninv_launch(asi_handle h, const void *Lu, bool fp64, int32_t p
     P.clast = h->clast;
     P.out = N_S;
     P.status = h->status;
+    P.tr_ptr = reinterpret_cast<unsigned long long *>(h->nf_rpT);
+    P.tr_cur = h->nf_cur;
+    P.tr_bsum = h->nf_bsum;
+    P.tr_flag = h->status + 12;
     hipError_t e;
     {
         Trace t(h, ASI_K_NINV, 0.0, st);

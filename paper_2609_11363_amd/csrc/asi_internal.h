@@ -56,6 +56,7 @@ struct Analysis {
     std::vector<int64_t> ustart;   // n+1
     std::vector<int32_t> ucol;     // nnzU: column r of the upper entry (j, r)
     std::vector<int64_t> lsrc_u;   // nnzU: index of L(r, j) in the input L arrays, -1 if absent
+    std::vector<int32_t> q2u;      // nnzL: u-index of each input L entry (the inverse of lsrc_u)
     std::vector<int64_t> mirror_u; // nnzU: S position of the lower entry (r, j)
     std::vector<int64_t> useg_u;   // nnzU: ustart[r], start of row r's u-range (gather segment)
     // Hit lists of the SelInv gathers: for block J, every pair (r, l) in

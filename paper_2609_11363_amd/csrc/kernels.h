@@ -45,8 +45,10 @@ int flow_grid(bool fp64);
 hipError_t launch_selinv_flow(const SelinvParams &P, int32_t nblocks, int32_t *done, int32_t epoch,
                               int32_t spin_limit, bool fp64, int grid, hipStream_t st);
 hipError_t launch_lu_to_float(int64_t nnzU, const double *Lu, float *Lf, hipStream_t st);
-hipError_t launch_gather_lu(int64_t nnzU, const int64_t *lsrc_u, const double *Lval, void *Lu, bool fp64,
-                            hipStream_t st);
+// L's values from the input's row order into the column layout: Lu[q2u[q]] =
+// Lval[q] (read in order, written scattered)
+hipError_t launch_scatter_lu(int64_t nnzL, const int32_t *q2u, const double *Lval, void *Lu, bool fp64,
+                             hipStream_t st);
 hipError_t set_big_lds_limits();
 size_t selinv_big_lds_bytes(bool fp64, int G, int32_t C);
 
@@ -79,6 +81,13 @@ struct NinvParams {
     int32_t *ovf_count;            // 1
     double *out;                   // N on S (float64)
     int32_t *status;
+    // product through the transposed series pattern (rows of L^inv): column
+    // counts / row pointers (n + 1), fill cursors (n), scan sums, and a flag:
+    // 1 while that path applies, 0 to use the entry-by-entry kernel
+    unsigned long long *tr_ptr;
+    unsigned long long *tr_cur;
+    unsigned long long *tr_bsum;
+    int32_t *tr_flag;
 };
 
 // linv_grid: 0 = as many workgroups of the series kernel as are resident,

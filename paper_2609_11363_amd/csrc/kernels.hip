@@ -532,12 +532,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_selinv_flow(SelinvParams P, int3
 }
 
 template <typename T>
-__global__ void k_gather_lu(int64_t nnzU, const int64_t *__restrict__ lsrc_u, const double *__restrict__ Lval,
-                            T *__restrict__ Lu) {
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= nnzU) return;
-    int64_t s = lsrc_u[u];
-    Lu[u] = s >= 0 ? (T)Lval[s] : T(0);
+__global__ void k_scatter_lu(int64_t nnzL, const int32_t *__restrict__ q2u, const double *__restrict__ Lval,
+                             T *__restrict__ Lu) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nnzL) return;
+    Lu[q2u[q]] = (T)Lval[q];
 }
 
 __global__ void k_lu_to_float(int64_t nnzU, const double *__restrict__ Lu, float *__restrict__ Lf) {
@@ -609,15 +608,15 @@ hipError_t launch_selinv_level(const SelinvParams &P, int variant, bool fp64, hi
     return hipGetLastError();
 }
 
-hipError_t launch_gather_lu(int64_t nnzU, const int64_t *lsrc_u, const double *Lval, void *Lu, bool fp64,
-                            hipStream_t st) {
-    if (nnzU <= 0) return hipSuccess;
-    dim3 g((unsigned)((nnzU + 255) / 256));
+hipError_t launch_scatter_lu(int64_t nnzL, const int32_t *q2u, const double *Lval, void *Lu, bool fp64,
+                             hipStream_t st) {
+    if (nnzL <= 0) return hipSuccess;
+    dim3 g((unsigned)((nnzL + 255) / 256));
     if (fp64)
-        hipLaunchKernelGGL(dev::k_gather_lu<double>, g, dim3(256), 0, st, nnzU, lsrc_u, Lval,
+        hipLaunchKernelGGL(dev::k_scatter_lu<double>, g, dim3(256), 0, st, nnzL, q2u, Lval,
                            reinterpret_cast<double *>(Lu));
     else
-        hipLaunchKernelGGL(dev::k_gather_lu<float>, g, dim3(256), 0, st, nnzU, lsrc_u, Lval,
+        hipLaunchKernelGGL(dev::k_scatter_lu<float>, g, dim3(256), 0, st, nnzL, q2u, Lval,
                            reinterpret_cast<float *>(Lu));
     return hipGetLastError();
 }

@@ -471,6 +471,133 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
     gsync<G>();
 }
 
+// ---- N on S through the transposed series pattern ---------------------------
+// Row k of L^inv lists the columns whose series reaches row k. N_ij can be
+// nonzero only where columns i and j share a row, so: count the columns of
+// every row, scan, list them (in the pool's free tail), then for every row k
+// and every pair i >= j of its columns with (i, j) in S evaluate N_ij by the
+// merge of the two columns (the value of the entry-by-entry kernel, bit for
+// bit) and write it at (i, j) and (j, i); every other entry of S is zero.
+// A pair met through several rows is written with the same value each time.
+// This path applies when the lists fit the pool's free tail and every row
+// holds at most kPairMax columns; otherwise the entry-by-entry kernel runs
+// (each kernel reads the flag and returns early when it does not apply).
+constexpr int32_t kPairMax = 64;
+
+__global__ void k_tr_init(NinvParams P) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= P.n) P.tr_ptr[i] = 0ull;
+    if (i == 0) *P.tr_flag = 1;
+}
+
+__global__ void k_tr_count(NinvParams P) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P.n) return;
+    const int64_t b = P.cstart[j];
+    const int32_t len = P.clen[j];
+    for (int32_t a = 0; a < len; ++a) atomicAdd(&P.tr_ptr[P.prow[b + a] + 1], 1ull);
+}
+
+// the lists go to the pool's rows array after its last reserved entry
+__global__ void k_tr_start(NinvParams P) {
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long top = *P.pool_top, total = P.tr_ptr[P.n];
+    if (k == 0 && top + total > (unsigned long long)P.pool_cap) *P.tr_flag = 0;
+    if (k < P.n) P.tr_cur[k] = P.tr_ptr[k];
+}
+
+__global__ void k_tr_fill(NinvParams P) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P.n || *P.tr_flag == 0) return;
+    int32_t *colT = P.prow + *P.pool_top;
+    const int64_t b = P.cstart[j];
+    const int32_t len = P.clen[j];
+    for (int32_t a = 0; a < len; ++a) {
+        const int32_t k = P.prow[b + a];
+        const unsigned long long pos = atomicAdd(&P.tr_cur[k], 1ull);
+        colT[pos] = j;
+        if (pos - P.tr_ptr[k] >= (unsigned long long)kPairMax) *P.tr_flag = 0;
+    }
+}
+
+// zeros of N on S: 16-byte stores (out is 16-byte aligned when its first
+// entry is; otherwise one entry at a time)
+__global__ void k_nzero(NinvParams P, int64_t nnz) {
+    if (*P.tr_flag == 0) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0) {
+        double2 *o2 = reinterpret_cast<double2 *>(P.out);
+        for (int64_t q = t; q < nnz / 2; q += stride) o2[q] = make_double2(0.0, 0.0);
+        if (t == 0 && (nnz & 1)) P.out[nnz - 1] = 0.0;
+    } else {
+        for (int64_t q = t; q < nnz; q += stride) P.out[q] = 0.0;
+    }
+}
+
+// position of column j in the sorted row i of S, or -1
+__device__ inline int64_t s_pos(const NinvParams &P, int32_t i, int32_t j) {
+    int64_t lo = P.rowptr[i], hi = P.rowptr[i + 1] - 1;
+    while (lo <= hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const int32_t c = P.col[mid];
+        if (c == j) return mid;
+        if (c < j)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
+    }
+    return -1;
+}
+
+// N_ij (i >= j) by the merge of the stored columns i and j of the series
+template <typename T>
+__device__ inline double n_entry(const NinvParams &P, int32_t i, int32_t j) {
+    const T *plinv = reinterpret_cast<const T *>(P.plinv);
+    const T *pw = reinterpret_cast<const T *>(P.pw);
+    const int64_t ci = P.cstart[i], cj = P.cstart[j];
+    const int32_t li = P.clen[i], lj = P.clen[j];
+    T sum = T(0);
+    int32_t a = 0, b = 0;
+    int32_t ra = a < li ? P.prow[ci] : INT32_MAX, rb = b < lj ? P.prow[cj] : INT32_MAX;
+    while (a < li && b < lj) {
+        if (ra == rb) {
+            sum += plinv[ci + a] * pw[cj + b];
+            ++a;
+            ++b;
+            ra = a < li ? P.prow[ci + a] : INT32_MAX;
+            rb = b < lj ? P.prow[cj + b] : INT32_MAX;
+        } else if (ra < rb) {
+            ++a;
+            ra = a < li ? P.prow[ci + a] : INT32_MAX;
+        } else {
+            ++b;
+            rb = b < lj ? P.prow[cj + b] : INT32_MAX;
+        }
+    }
+    return (double)sum;
+}
+
+template <typename T>
+__global__ void k_npairs(NinvParams P) {
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P.n || *P.tr_flag == 0) return;
+    const int32_t *colT = P.prow + *P.pool_top;
+    const int64_t c0 = (int64_t)P.tr_ptr[k], c1 = (int64_t)P.tr_ptr[k + 1];
+    for (int64_t a = c0; a < c1; ++a) {
+        const int32_t i = colT[a];
+        for (int64_t b = c0; b < c1; ++b) {
+            const int32_t j = colT[b];
+            if (j > i) continue;
+            const int64_t p = s_pos(P, i, j);
+            if (p < 0) continue;
+            const double v = n_entry<T>(P, i, j);
+            P.out[p] = v;
+            if (i != j) P.out[P.mirror[p]] = v;
+        }
+    }
+}
+
 constexpr int kLinvH = 256;
 constexpr int kLinvTerm = 64;    // kept entries of one term (the series columns are short)
 constexpr int kLinvHBig = 2048;
@@ -543,40 +670,20 @@ __global__ __launch_bounds__(256) void k_linv_big(NinvParams P) {
 // column i absent from column j has w_j(k) = 0 and adds nothing. Both
 // triangles are written directly.
 template <typename T>
-__global__ __launch_bounds__(256) void k_nprod_entry(NinvParams P, int64_t nnz, const int32_t *__restrict__ srow) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nnz) return;
+__device__ inline void nprod_one(const NinvParams &P, int64_t p, const int32_t *__restrict__ srow) {
     const int32_t r = srow[p], c = P.col[p];
     const int32_t i = r > c ? r : c, j = r > c ? c : r;
     // the rows of column i are >= i: without a row >= i in column j the two
     // columns share none and N_ij = 0
-    if (P.clast[j] < i) {
-        P.out[p] = 0.0;
-        return;
-    }
-    const T *plinv = reinterpret_cast<const T *>(P.plinv);
-    const T *pw = reinterpret_cast<const T *>(P.pw);
-    const int64_t ci = P.cstart[i], cj = P.cstart[j];
-    const int32_t li = P.clen[i], lj = P.clen[j];
-    T sum = T(0);
-    int32_t a = 0, b = 0;
-    int32_t ra = a < li ? P.prow[ci] : INT32_MAX, rb = b < lj ? P.prow[cj] : INT32_MAX;
-    while (a < li && b < lj) {
-        if (ra == rb) {
-            sum += plinv[ci + a] * pw[cj + b];
-            ++a;
-            ++b;
-            ra = a < li ? P.prow[ci + a] : INT32_MAX;
-            rb = b < lj ? P.prow[cj + b] : INT32_MAX;
-        } else if (ra < rb) {
-            ++a;
-            ra = a < li ? P.prow[ci + a] : INT32_MAX;
-        } else {
-            ++b;
-            rb = b < lj ? P.prow[cj + b] : INT32_MAX;
-        }
-    }
-    P.out[p] = (double)sum;
+    P.out[p] = P.clast[j] < i ? 0.0 : n_entry<T>(P, i, j);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nprod_entry(NinvParams P, int64_t nnz, const int32_t *__restrict__ srow) {
+    if (*P.tr_flag != 0) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += stride)
+        nprod_one<T>(P, p, srow);
 }
 
 __global__ void k_ninv_reset(NinvParams P) {
@@ -621,8 +728,21 @@ hipError_t run_ninv(const NinvParams &P, hipStream_t st, int cap) {
     size_t l1 = linv_big_lds<T>();
     hipLaunchKernelGGL((k_linv_big<T>), dim3(256), dim3(256), l1, st, P);
     const int64_t nnz = P.rowptr_n;
-    if (nnz > 0)
-        hipLaunchKernelGGL((k_nprod_entry<T>), dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, P, nnz, P.srow);
+    if (nnz > 0) {
+        // the grids of the two alternatives are bounded (grid-stride loops):
+        // the one that does not apply exits at once
+        const dim3 gn((unsigned)((P.n + 256) / 256)), b(256);
+        const dim3 gs((unsigned)std::min<int64_t>((nnz + 255) / 256, 16384));
+        hipLaunchKernelGGL(k_tr_init, gn, b, 0, st, P);
+        hipLaunchKernelGGL(k_tr_count, gn, b, 0, st, P);
+        hipError_t e = launch_scan_counts(P.n, P.tr_ptr, P.tr_bsum, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tr_start, gn, b, 0, st, P);
+        hipLaunchKernelGGL(k_tr_fill, gn, b, 0, st, P);
+        hipLaunchKernelGGL(k_nzero, gs, b, 0, st, P, nnz);
+        hipLaunchKernelGGL((k_npairs<T>), gn, b, 0, st, P);
+        hipLaunchKernelGGL((k_nprod_entry<T>), gs, b, 0, st, P, nnz, P.srow);
+    }
     return hipGetLastError();
 }
 
