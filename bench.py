@@ -4,7 +4,8 @@
 Default workload (--workload stencil27_128): the 3D 27-point stencil on a
 128^3 grid (n = 2,097,152, nnz(A) = 55,742,968, lognormal(0, 0.5)
 coefficients, seed 5), nested multicolor ordering, threshold ILDL with drop
-tolerance 1e-3 (host, untimed). One step is one pass of the hot path on the
+tolerance 1e-3 (on the device, untimed: asi_ildl_threshold; --factor host
+runs the host factorization instead). One step is one pass of the hot path on the
 resident factors, all through libasi's C ABI: load the factor, SelInv with
 NInv (p = 3, delta = 0.1) beside it, then Mix (eps = 1e-2) and the learned
 correction (trained before the timed region on small grids of the same
@@ -31,8 +32,10 @@ diag(A^-1).
 one step SelInv with NInv beside it -> Mix -> SPAI -> diagonal -> trace; the
 spectral check with the device eigen step (block Lanczos, block PCG).
 
---workload stencil27_equal_error: the equal-error comparison of SelInv at
-tighter drop tolerances against Mix + learned on the 27-point stencil.
+--workload stencil27_equal_error: the equal-error comparison on the same
+128^3 stencil: float64 SelInv at drop tolerances 1e-3, 3e-4 and 1e-4
+(--taus) against Mix and Mix + learned at 1e-3, every factor computed on the
+device; errors against 256 columns of A^-1 computed by CG.
 
 --workload randdd: random sparse diagonally dominant matrices (the 48 of
 smallest n among seeds 0-255, n 2,034-5,701): the learned correction trained
@@ -125,6 +128,8 @@ def main():
                              "covariance200", "randdd"])
     ap.add_argument("--grid", type=int, default=None, help="grid size (default 64, 512, 128 per workload)")
     ap.add_argument("--tau", type=float, default=1e-3)
+    ap.add_argument("--taus", default="1e-3,3e-4,1e-4",
+                    help="drop tolerances of the equal-error comparison (the loosest is Mix's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target time of the CPU oracle baseline's sample (stencil27_128)")
@@ -758,8 +763,9 @@ def reference_columns(A, cols, tol=1e-12, max_iter=20000, diag_only=False):
     """Columns `cols` of A^-1 (original ordering) by Jacobi-preconditioned CG in
     float64 on the GPU, to a relative residual of tol per column (the accuracy
     reference of the equal-error comparison; torch's sparse product is used
-    here as measurement plumbing, outside the method's path)."""
-    import numpy as np
+    here as measurement plumbing, outside the method's path). Returns a device
+    tensor (n x len(cols)), or the diagonal entries (A^-1)_jj as a host array
+    with diag_only."""
     import torch
     dev = torch.device("cuda", 0)
     At = torch.sparse_csr_tensor(torch.as_tensor(A.indptr, dtype=torch.int64),
@@ -775,97 +781,126 @@ def reference_columns(A, cols, tol=1e-12, max_iter=20000, diag_only=False):
     P = Zp.clone()
     rz = (R * Zp).sum(0)
     bn = B.norm(dim=0)
+    del B
     it = 0
+    t0 = time.time()
     for it in range(1, max_iter + 1):
         AP = At @ P
         alpha = rz / (P * AP).sum(0)
-        X += alpha * P
-        R -= alpha * AP
-        if it % 25 == 0 and bool(((R.norm(dim=0) / bn) <= tol).all()):
-            break
-        Zp = dinv * R
+        X.add_(alpha * P)
+        R.sub_(alpha * AP)
+        del AP
+        if it % 25 == 0:
+            rel = float((R.norm(dim=0) / bn).max())
+            if it % 500 == 0:
+                log(f"reference CG: iteration {it}, max relative residual {rel:.2e}, {time.time() - t0:.0f}s")
+            if rel <= tol:
+                break
+        torch.mul(dinv, R, out=Zp)
         rz_new = (R * Zp).sum(0)
-        P = Zp + (rz_new / rz) * P
+        P.mul_(rz_new / rz).add_(Zp)
         rz = rz_new
     res = float((R.norm(dim=0) / bn).max())
+    del R, Zp, P
     if diag_only:  # (A^-1)_jj for j in cols
         return X[torch.as_tensor(cols, device=dev), torch.arange(k, device=dev)].cpu().numpy(), it, res
-    return X.cpu().numpy(), it, res
+    return X, it, res
 
 
 def run_equal_error(args):
-    """Equal-error comparison on the 27-point lognormal(0, 0.5) stencil (64^3
-    by default): float64 SelInv at tau = 1e-3, 3e-4, 1e-4 against Mix and
-    Mix + learned (mixed precision) at tau = 1e-3. Accuracy against 256
-    sampled columns of A^-1: err_1 on their diagonals (Section 2.6) and the
-    column-relative error |x_ij - y_ij| / |y_jj| on the entries of the
-    tau = 1e-3 pattern in those columns."""
+    """Equal-error comparison on the 27-point lognormal(0, 0.5) stencil (128^3
+    by default): float64 SelInv at tau = 1e-3, 3e-4, 1e-4 (--taus) against Mix
+    and Mix + learned (float64 and mixed) at the loosest tau. Every factor is
+    computed on the device (threshold ILDL). Accuracy against 256 seeded
+    columns of A^-1: err_1 on their diagonals (Section 2.6) and the
+    column-relative error |x_ij - y_ij| / |y_jj| on the entries of the loosest
+    pattern in those columns."""
     import numpy as np
     import torch
 
     from paper_2609_11363_amd import Solver, upload_factors
-    from workloads import ildl_bk, nested_multicolor_grid, stencil27_3d
+    from workloads import nested_multicolor_grid, stencil27_3d
 
-    N = args.grid or 64
-    taus = [1e-3, 3e-4, 1e-4]
+    N = args.grid or 128
+    taus = sorted((float(t) for t in args.taus.split(",")), reverse=True)
     p, delta, eps = 3, 0.1, 1e-2
     A = stencil27_3d(N, 0.5, 5)
     n = A.shape[0]
     q = nested_multicolor_grid((N, N, N))
     rng = np.random.default_rng(3)
     cols = np.sort(rng.choice(n, size=256, replace=False))
+    ncol = len(cols)
     learned_info, packed = train_learned(args, taus[0], p, delta, eps, family="stencil27")
     t0 = time.time()
     Xref, iters, res = reference_columns(A, cols)
-    log(f"reference: 256 columns of A^-1 by CG, {iters} iterations, residual {res:.1e}, {time.time() - t0:.1f}s")
-    yjj = Xref[cols, np.arange(len(cols))]
+    t_ref = time.time() - t0
+    log(f"reference: {ncol} columns of A^-1 by CG, {iters} iterations, residual {res:.1e}, {t_ref:.1f}s")
     dev = torch.device("cuda", 0)
+    cols_d = torch.as_tensor(cols, device=dev)
+    yjj = Xref[cols_d, torch.arange(ncol, device=dev)].cpu().numpy()
     methods = {}
-    loose_entries = None  # (factor rows, sample index) of the tau = 1e-3 pattern in the sampled columns
+    loose = None  # keys (original row * ncol + sample) of the loosest pattern in the sampled columns
+    loose_ref = None
 
-    def sample_values(s, perm, values):
-        """values on S at (i, cols[k]) for every entry of S in the sampled columns."""
-        rp, cl = (x.cpu().numpy() for x in s.pattern())
+    def sample_positions(s, perm):
+        """Positions in S of every entry of the sampled columns (row f of S is
+        column f), with their keys: original row * ncol + sample index."""
+        rp, cl = s.pattern()
+        rp_h = rp.cpu().numpy()
         iperm = np.empty(n, np.int64)
         iperm[perm] = np.arange(n)
         fc = iperm[cols]
-        out = {}
-        v = values.cpu().numpy()
-        for k, f in enumerate(fc):
-            lo, hi = rp[f], rp[f + 1]
-            for fi, x in zip(cl[lo:hi], v[lo:hi]):  # row f of S = column f (symmetric)
-                out[(int(perm[fi]), k)] = x
-        return out
+        cnt = rp_h[fc + 1] - rp_h[fc]
+        pos = np.concatenate([np.arange(rp_h[f], rp_h[f + 1]) for f in fc])
+        pos_d = torch.as_tensor(pos, device=dev)
+        rows = perm[cl[pos_d].cpu().numpy()].astype(np.int64)
+        keys = rows * ncol + np.repeat(np.arange(ncol), cnt)
+        order = np.argsort(keys)
+        del rp, cl
+        return pos_d[torch.as_tensor(order, device=dev)], keys[order]
 
-    def errors(vals):
-        keys = loose_entries
-        d = np.array([vals.get((int(cols[k]), k), 0.0) for k in range(len(cols))])
+    def errors(samp, values):
+        pos_d, keys = samp
+        v = values[pos_d].cpu().numpy()
+
+        def lookup(k):
+            i = np.minimum(np.searchsorted(keys, k), len(keys) - 1)
+            return np.where(keys[i] == k, v[i], 0.0)
+        d = lookup(cols.astype(np.int64) * ncol + np.arange(ncol))
         err1 = float(np.abs(d - yjj).sum() / np.abs(yjj).sum())
-        e = np.array([abs(vals.get(key, 0.0) - Xref[key[0], key[1]]) / abs(yjj[key[1]]) for key in keys])
+        e = np.abs(lookup(loose) - loose_ref) / np.abs(yjj[loose % ncol])
         return err1, float(e.mean()), float(np.quantile(e, 0.99))
 
-    for tau in taus:
-        t0 = time.time()
-        F = ildl_bk(A, q, tau, progress=True)
-        t_fact = time.time() - t0
+    for ti, tau in enumerate(taus):
+        log(f"tau={tau:g}: {args.factor} threshold ILDL starts")
+        F, fact_info, dev_factor = factorize(A, q, tau, args.factor)
         s = Solver(0)
+        t0 = time.time()
         s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
-        Lv, dd, ds = upload_factors(F)
+        t_sym = time.time() - t0
+        info = s.info()
+        log(f"tau={tau:g}: nnz(L)={F.nnzL} |S|={s.nnz_S} analysis {t_sym:.1f}s levels={info['n_levels']} "
+            f"max|R_J|={info['max_cols']} workspace {s.ws.numel() / 1e9:.1f} GB")
+        Lv, dd, ds = dev_factor if dev_factor is not None else upload_factors(F)
+        samp = sample_positions(s, F.perm)
+        if loose is None:
+            loose = samp[1]
+            loose_ref = Xref[torch.as_tensor(loose // ncol, device=dev),
+                             torch.as_tensor(loose % ncol, device=dev)].cpu().numpy()
         Z = torch.empty(s.nnz_S, dtype=torch.float64, device=dev)
         s.load_factor(Lv, dd, ds)
         for _ in range(args.warmup):
             s.selinv(Lv, dd, ds, out=Z)
         ms_sel = timed(lambda: s.selinv(Lv, dd, ds, out=Z), args.steps) * 1e3
         s.sync()
-        zv = sample_values(s, F.perm, Z)
-        if loose_entries is None:
-            loose_entries = sorted(zv.keys())
-        e1, em, e99 = errors(zv)
-        methods[f"selinv_fp64_tau{tau:g}"] = {"tau": tau, "nnz_S": s.nnz_S, "ms": ms_sel,
-                                             "entries_per_s": s.nnz_S / (ms_sel * 1e-3), "err1_diag": e1,
-                                             "mean_entry_err": em, "p99_entry_err": e99, "ildl_s": t_fact}
+        e1, em, e99 = errors(samp, Z)
+        common = {"tau": tau, "nnz_L": F.nnzL, "nnz_S": s.nnz_S, "levels": info["n_levels"],
+                  "max_cols": info["max_cols"], "ildl_s": fact_info["seconds"], "ildl_where": args.factor,
+                  "analysis_s": t_sym}
+        methods[f"selinv_fp64_tau{tau:g}"] = {**common, "ms": ms_sel, "entries_per_s": s.nnz_S / (ms_sel * 1e-3),
+                                             "err1_diag": e1, "mean_entry_err": em, "p99_entry_err": e99}
         log(f"SelInv fp64 tau={tau:g}: |S|={s.nnz_S} {ms_sel:.2f} ms err_1 {e1:.3e} mean entry {em:.3e}")
-        if tau == taus[0]:
+        if ti == 0:
             Nn, M, ML = (torch.empty_like(Z) for _ in range(3))
 
             def mix_only(prec):
@@ -888,25 +923,27 @@ def run_equal_error(args):
                     mix_learned(prec)
                 ms_mix = timed(lambda: mix_only(prec), args.steps) * 1e3
                 s.sync()
-                e_mix = errors(sample_values(s, F.perm, M))
+                e_mix = errors(samp, M)
                 ms_ml = timed(lambda: mix_learned(prec), args.steps) * 1e3
                 s.sync()
-                e_ml = errors(sample_values(s, F.perm, ML if packed is not None else M))
+                e_ml = errors(samp, ML if packed is not None else M)
                 for name, ms, (e1, em, e99) in ((f"mix_{tag}", ms_mix, e_mix), (f"mix_learned_{tag}", ms_ml, e_ml)):
-                    methods[f"{name}_tau{tau:g}"] = {"tau": tau, "nnz_S": s.nnz_S, "ms": ms,
-                                                     "entries_per_s": s.nnz_S / (ms * 1e-3), "err1_diag": e1,
-                                                     "mean_entry_err": em, "p99_entry_err": e99}
+                    methods[f"{name}_tau{tau:g}"] = {**common, "ms": ms, "entries_per_s": s.nnz_S / (ms * 1e-3),
+                                                     "err1_diag": e1, "mean_entry_err": em, "p99_entry_err": e99}
                     log(f"{name} tau={tau:g}: {ms:.2f} ms err_1 {e1:.3e} mean entry {em:.3e}")
-        del s, Lv, dd, ds, Z
+            del Nn, M, ML
+        del s, Lv, dd, ds, Z, samp, F, dev_factor
         torch.cuda.empty_cache()
+    del Xref
+    torch.cuda.empty_cache()
 
     # the faster precision of the learned form (float64 is at least as accurate)
     lm, l64 = methods[f"mix_learned_mixed_tau{taus[0]:g}"], methods[f"mix_learned_fp64_tau{taus[0]:g}"]
     ml_key = f"mix_learned_{'fp64' if l64['ms'] <= lm['ms'] else 'mixed'}_tau{taus[0]:g}"
 
-    # float64 SelInv time at the learned form's error (log-log interpolation in tau's sweep)
-    def at_equal(metric):
-        target = methods[ml_key][metric]
+    # float64 SelInv time at a method's error (log-log interpolation in tau's sweep)
+    def at_equal(key, metric):
+        target = methods[key][metric]
         sel = [methods[f"selinv_fp64_tau{t:g}"] for t in taus]
         for a, b in zip(sel, sel[1:]):
             if (a[metric] - target) * (b[metric] - target) <= 0 and a[metric] != b[metric]:
@@ -915,7 +952,9 @@ def run_equal_error(args):
         return None
 
     ml = methods[ml_key]
-    eq = {m: at_equal(m) for m in ("err1_diag", "mean_entry_err")}
+    eq = {m: at_equal(ml_key, m) for m in ("err1_diag", "mean_entry_err")}
+    eq_all = {k: {m: at_equal(k, m) for m in ("err1_diag", "mean_entry_err")}
+              for k in methods if not k.startswith("selinv_fp64")}
     result = {
         "metric": "selected entries of A^-1 per sec (SelInv, Mix, Mix+learned) at stated rel error",
         "value": ml["entries_per_s"],
@@ -931,15 +970,17 @@ def run_equal_error(args):
                                                                     "SelInv sweep",
         "data": "synthetic",
         "config": {"workload": f"equal-error comparison, 3D 27-point lognormal(0,0.5) stencil {N}^3, nested "
-                               f"multicolor order: float64 SelInv at tau in {taus} vs Mix and Mix+learned (float64 "
-                               f"and mixed; the faster is the value: {ml_key}) at tau={taus[0]}; errors against "
-                               "256 CG columns of A^-1", "n": n,
+                               f"multicolor order, {args.factor} threshold ILDL: float64 SelInv at tau in {taus} "
+                               f"vs Mix and Mix+learned (float64 and mixed; the faster is the value: {ml_key}) at "
+                               f"tau={taus[0]}; errors against {ncol} CG columns of A^-1", "n": n,
                    "parallelism": "single GPU"},
         "methods": methods,
         "learned": learned_info,
-        "reference": {"columns": 256, "cg_iterations": iters, "max_rel_residual": res},
+        "reference": {"columns": ncol, "cg_iterations": iters, "max_rel_residual": res, "seconds": t_ref},
         "selinv_fp64_ms_at_mix_learned_error": eq,
         "speedup_at_equal_error": {m: (v / ml["ms"] if v else None) for m, v in eq.items()},
+        "speedup_at_equal_error_all": {k: {m: (v / methods[k]["ms"] if v else None) for m, v in d.items()}
+                                       for k, d in eq_all.items()},
     }
     print(json.dumps(result), flush=True)
 
