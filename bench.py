@@ -72,11 +72,14 @@ SELINV_TRAFFIC = {"sources_sha256": "ea108a0f50c10dd45cb20cec4ba6a45a7a83bce8ff3
                   "profile": "profiles/selinv_ninv_mix_learned_diffusion64.md"}
 
 
-# The same for the 27-point 128^3 stencil (the default workload); filled from
-# its profile once the counters have been taken on the current sources.
-# Per precision of the reported step; an entry holds while kernels.hip has the
-# SHA-256 the counters were taken on.
-STENCIL_TRAFFIC = {"profile": "profiles/selinv_ninv_mix_learned_stencil128.md"}
+# The same for the 27-point 128^3 stencil (the default workload), per
+# precision of the reported step: FETCH_SIZE x 2 + WRITE_SIZE per sweep of 127
+# launches (mixed: 60.580 + 5.262 GB; float64: 87.466 + 5.726 GB). An entry
+# holds while kernels.hip has the SHA-256 the counters were taken on.
+_STENCIL_SHA = "4312359c4b30e3a809213204bf72623848c0a3053751c55f3c9db6f913e25656"
+STENCIL_TRAFFIC = {"profile": "profiles/selinv_ninv_mix_learned_stencil128.md",
+                   "mixed": {"sources_sha256": _STENCIL_SHA, "bytes_per_launch": (60.580e9 + 5.262e9) / 127},
+                   "fp64": {"sources_sha256": _STENCIL_SHA, "bytes_per_launch": (87.466e9 + 5.726e9) / 127}}
 
 
 def selinv_sources_sha256():
@@ -702,6 +705,7 @@ def oracle_trailing_sample(F, S, Z64, N64, M64, Zm, p, delta, eps, target_s=15.0
 
     from oracle import core as oc
 
+    build = oc.use_host_tuned()
     cnt = np.bincount(F.L_col, minlength=F.n).astype(np.float64)
     w = cnt * cnt
     tail = np.cumsum(w[::-1])[::-1]  # tail[k] = share of the work from k on
@@ -751,7 +755,7 @@ def oracle_trailing_sample(F, S, Z64, N64, M64, Zm, p, delta, eps, target_s=15.0
                 "sample": (f"single-threaded float64 oracle SelInv + NInv(p={p}, delta={delta}) + Mix(eps={eps}) on "
                            f"the trailing sub-factor of the same workload (unknowns {k}..{F.n - 1}: {S2.nnz} entries, "
                            f"{100 * S_share:.1f} % of |S| and {100 * share:.1f} % of the oracle SelInv's sum "
-                           f"|R_J|^2), {t_cpu:.1f} s on one core of {host_cpu()}; value = |S| / the whole-workload "
+                           f"|R_J|^2), {t_cpu:.1f} s on one core of {host_cpu()} (oracle built with {build}); value = |S| / the whole-workload "
                            f"time estimated from it ({est:.0f} s: SelInv scaled by its share of sum |R_J|^2, NInv + "
                            f"Mix by the share of |S|)"),
                 "sample_s": t_cpu, "sample_entries": int(S2.nnz), "sample_entries_per_s": S2.nnz / t_cpu,

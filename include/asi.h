@@ -160,6 +160,18 @@ asi_status asi_set_sweep(asi_handle h, asi_sweep mode);
  * number of launches of each variant per sweep. Host-only; needs
  * asi_analyze. Errors: ASI_E_ARG, ASI_E_STATE.
  */
+/*
+ * Schedule check (debug): with on != 0, every SelInv sweep of the handle
+ * first fills its working copy of Z (the column layout of the strictly lower
+ * part, and the diagonal) with NaN. Section 2.1 computes block J from entries
+ * of Zhat that earlier blocks have already written; an entry read before its
+ * block writes it then turns the result non-finite instead of silently using
+ * a stale value of an earlier call. Costs one extra pass over that working
+ * copy per sweep (4 or 8 bytes per entry of L plus 8 per unknown); results
+ * are otherwise unchanged. Default off. Errors: ASI_E_ARG (null handle).
+ */
+asi_status asi_set_sentinel(asi_handle h, int on);
+
 typedef enum {
     ASI_SV_SMALL = 0, ASI_SV_SPLIT = 1, ASI_SV_GROUP128 = 2, ASI_SV_GROUP256 = 3,
     ASI_SV_GROUP512 = 4, ASI_SV_BIG256 = 5, ASI_SV_BIG1024 = 6, ASI_SV_COUNT = 7
@@ -273,7 +285,12 @@ asi_status asi_mlp_pack(asi_handle h, const float *theta, void *packed);
 /* y[r] for rows feature rows (bfloat16 MFMA, float32 accumulation). */
 asi_status asi_mlp_forward(asi_handle h, const void *packed, const uint16_t *F, int64_t rows, float *y);
 /* grad += d(sum_r dy[r] y[r]) / d theta for the packed weights' network
- * (bfloat16 roundings treated as identity); float32, ASI_MLP_PARAMS entries. */
+ * (bfloat16 roundings treated as identity); float32, ASI_MLP_PARAMS entries.
+ * The products run on bfloat16 MFMA with float32 sums: activations, features
+ * and weights are bfloat16 already, and each float32 back-propagated value
+ * enters as a bfloat16 head and tail (relative 2^-17). grad receives one
+ * atomic addition per parameter and workgroup, so the summation order (and
+ * the last bits) can vary between runs. */
 asi_status asi_mlp_backward(asi_handle h, const void *packed, const uint16_t *F, const float *dy, int64_t rows,
                             float *grad);
 /* Mean squared error: dy[r] = 2 (y[r] - t[r]) / rows and *loss += mean((y - t)^2)

@@ -21,29 +21,54 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 ORC_ERRORS = {1: "pattern", 2: "singular D block", 3: "allocation"}
 
 
+_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+
+# Single-threaded, no fast-math: no reassociation, and no contraction of a
+# product and a sum into one rounding (-ffp-contract=off), so every build
+# gives the same bits. The shipped copy targets x86-64-v3 (it may run on a
+# host other than the one that built it); the timed CPU baseline rebuilds for
+# the CPU it runs on (use_host_tuned).
+_FLAGS = ["-O3", "-ffp-contract=off", "-std=c11", "-fPIC", "-shared"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc, single-threaded, -O2, no fast-math."""
+    """Compile the oracle with gcc (-O3 -march=x86-64-v3)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"],
-                       check=True)
+        subprocess.run(["gcc", *_FLAGS, "-march=x86-64-v3", "-o", tmp, _SRC, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
 
 _lib = None
+_lib_path = None
 _P = ctypes.c_void_p
 
 
-def _load():
+def use_host_tuned() -> str:
+    """Rebuild the oracle for this host's CPU (-O3 -march=native) and load that
+    copy instead: for timing it as the CPU baseline on the machine that runs
+    it. Same source and floating-point flags, so the same results."""
     global _lib
+    tmp = f"{_NATIVE}.{os.getpid()}.tmp"
+    subprocess.run(["gcc", *_FLAGS, "-march=native", "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, _NATIVE)
+    _lib = None
+    _load(_NATIVE)
+    return "gcc -O3 -march=native -ffp-contract=off"
+
+
+def _load(path=None):
+    global _lib, _lib_path
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = path or _LIB
+        if path == _LIB and not os.path.exists(_LIB):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        _lib_path = path
+        lib = ctypes.CDLL(path)
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         lib.orc_pattern.argtypes = [i32, _P, _P, _P, _P, _P, ctypes.POINTER(i64)]
-        lib.orc_selinv.argtypes = [i32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        lib.orc_selinv.argtypes = [i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, i32]
         lib.orc_linv.argtypes = [i32, _P, _P, _P, i32, f64, i64, _P, _P, _P, ctypes.POINTER(i64)]
         lib.orc_ninv_product.argtypes = [i32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
         lib.orc_mix.argtypes = [i32, _P, _P, _P, _P, f64, _P]
@@ -111,13 +136,17 @@ def pattern(F) -> Pattern:
     return Pattern(n, rowptr, col[:nnz.value])
 
 
-def selinv(F, S: Pattern) -> np.ndarray:
-    """Takahashi/SelInv recursion on S (Section 2.1)."""
+def selinv(F, S: Pattern, sentinel: bool = False, wrong_order: bool = False) -> np.ndarray:
+    """Takahashi/SelInv recursion on S (Section 2.1). sentinel: start from NaN
+    on S, so a read before a write shows as a non-finite result.
+    wrong_order: visit the blocks first to last (a planted mistake, only for
+    the test that shows the sentinel catches it)."""
     lib = _load()
     Z = np.zeros(max(1, S.nnz))
+    flags = (1 if sentinel else 0) | (2 if wrong_order else 0)
     _check(lib.orc_selinv(F.n, _p(_f(F, "L_rowptr")), _p(_f(F, "L_col")), _p(_f(F, "L_val")),
                           _p(_f(F, "d_diag")), _p(_f(F, "d_sub")), _p(_f(F, "piv")),
-                          _p(S.rowptr), _p(S.col), _p(Z)))
+                          _p(S.rowptr), _p(S.col), _p(Z), flags))
     return Z[:S.nnz]
 
 

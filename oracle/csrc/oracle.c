@@ -192,10 +192,18 @@ static int d_block_inverse(const double *dd, const double *ds, const int8_t *piv
  *     Z(R_J, J) = -Zhat(R_J, R_J) L(R_J, J)
  *     Z(J, J)   = D_J^-1 - L(R_J, J)^T Z(R_J, J).
  * Z_S receives all of Z on S in S's CSR layout.
+ *
+ * flags: ORC_SEL_SENTINEL starts from NaN instead of zero on S, so an entry
+ * of Zhat read before its block has written it makes the result non-finite
+ * (the recursion only ever reads entries of later blocks). ORC_SEL_FORWARD
+ * visits the blocks from the first to the last: a deliberately wrong order,
+ * used only by the tests to show that the sentinel detects such a mistake.
  */
+#define ORC_SEL_SENTINEL 1
+#define ORC_SEL_FORWARD 2
 int orc_selinv(int32_t n, const int64_t *Lp, const int32_t *Li, const double *Lx, const double *dd,
                const double *ds, const int8_t *piv, const int64_t *Sp, const int32_t *Sj,
-               double *Z_S) {
+               double *Z_S, int32_t flags) {
     int rc = ORC_OK;
     int32_t *R = (int32_t *)malloc(sizeof(int32_t) * (n + 1));
     double *l0 = (double *)malloc(sizeof(double) * (n + 1));
@@ -206,9 +214,11 @@ int orc_selinv(int32_t n, const int64_t *Lp, const int32_t *Li, const double *Lx
         rc = ORC_E_ALLOC;
         goto out;
     }
-    for (int64_t q = 0; q < Sp[n]; ++q) Z_S[q] = 0.0;
-    int32_t j = n - 1;
-    while (j >= 0) {
+    const int forward = (flags & ORC_SEL_FORWARD) != 0;
+    const double start = (flags & ORC_SEL_SENTINEL) ? NAN : 0.0;
+    for (int64_t q = 0; q < Sp[n]; ++q) Z_S[q] = start;
+    int32_t j = forward ? 0 : n - 1;
+    while (forward ? j < n : j >= 0) {
         int32_t J = block_start(piv, j);
         int two = piv[J] == 1;
         int32_t last = two ? J + 1 : J;
@@ -256,7 +266,7 @@ int orc_selinv(int32_t n, const int64_t *Lp, const int32_t *Li, const double *Lx
             Z_S[s_find(Sp, Sj, J + 1, J)] = off;
             Z_S[s_find(Sp, Sj, J, J + 1)] = off;
         }
-        j = J - 1;
+        j = forward ? last + 1 : J - 1;
     }
 out:
     free(R);

@@ -31,7 +31,7 @@ EXPORTS = ["asi_create", "asi_destroy", "asi_set_stream", "asi_last_error", "asi
            "asi_eigs_work_bytes", "asi_eigs_error", "asi_dense_symeig", "asi_block_solve_work_bytes",
            "asi_pcg_block", "asi_sqmr_block", "asi_mlp_correct_mix", "asi_ildl_numeric",
            "asi_sweep_plan", "asi_unpermute", "asi_unpermute_noalloc", "asi_ildl_threshold_work_bytes",
-           "asi_ildl_threshold", "asi_ildl_threshold_extract"]
+           "asi_ildl_threshold", "asi_ildl_threshold_extract", "asi_set_sentinel"]
 MLP_FEATURES = 16
 MLP_PARAMS = 5313
 MLP_PACKED_BYTES = 12944
@@ -106,6 +106,7 @@ def load_library():
         "asi_sync": [P],
         "asi_profile": [P, ctypes.c_int],
         "asi_set_sweep": [P, ctypes.c_int],
+        "asi_set_sentinel": [P, ctypes.c_int],
         "asi_sweep_plan": [P, P],
         "asi_unpermute": [P, P, P, P, P, P],
         "asi_unpermute_noalloc": [P, P, P, P, P, P],
@@ -586,6 +587,12 @@ class Solver:
     def set_sweep(self, mode="auto"):
         """SelInv schedule: "auto", "levels" (one launch per DAG level) or "dataflow"."""
         self._check(self.lib.asi_set_sweep(self.h, SWEEP[mode]))
+
+    def set_sentinel(self, on=True):
+        """Schedule check: SelInv sweeps start from a NaN-filled working Z, so
+        a read of an entry before its block writes it shows up as a
+        non-finite result."""
+        self._check(self.lib.asi_set_sentinel(self.h, 1 if on else 0))
 
     def sweep_plan(self):
         """{variant: level launches per SelInv sweep} of the level schedule."""

@@ -62,6 +62,7 @@ struct asi_handle_s {
     bool lf_loaded = false;       // Lf holds the float32 copy of that factor's L
     int32_t epoch = 0;
     int sweep = ASI_SWEEP_AUTO;
+    bool sentinel = false;        // SelInv sweeps start from a NaN-filled working Z (schedule check)
     int8_t *piv = nullptr;
     int32_t *level = nullptr;
     asi::BlockMeta *meta_small = nullptr;
@@ -570,6 +571,14 @@ static asi_status selinv_launch(asi_handle h, const void *Lu, bool fp64, double 
     P.zdiag = h->zd;
     P.out = Z_S;
     P.status = h->status;
+    if (h->sentinel) {
+        // every entry a block reads must have been written by an earlier
+        // block of this sweep: NaN (all-ones words, in float32 and float64)
+        // makes any other read visible in the result
+        e = asi::launch_fill_i32(reinterpret_cast<int32_t *>(h->Zu), (int64_t)A.nnzU * (fp64 ? 2 : 1), -1, st);
+        if (e == hipSuccess) e = asi::launch_fill_i32(reinterpret_cast<int32_t *>(h->zd), (int64_t)A.n * 2, -1, st);
+        if (e != hipSuccess) return hip_fail(h, e, "sentinel fill");
+    }
     const bool flow_ok = A.sched_big.empty() && A.n_blocks > 0;
     int grid = 0;
     // AUTO runs the level schedule: on MI355X it measured faster than the
@@ -621,6 +630,12 @@ asi_status asi_selinv(asi_handle h, const double *L_val, const double *d_diag, c
     s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu);
     if (s != ASI_OK) return s;
     return selinv_launch(h, Lu, fp64, Z_S, h->stream);
+}
+
+asi_status asi_set_sentinel(asi_handle h, int on) {
+    if (!h) return ASI_E_ARG;
+    h->sentinel = on != 0;
+    return ASI_OK;
 }
 
 asi_status asi_set_sweep(asi_handle h, asi_sweep mode) {

@@ -11,8 +11,8 @@ namespace asi {
 namespace dev {
 
 __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = v;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
 }
 
 __global__ void k_zdiag(int32_t n, const int64_t *__restrict__ diagpos, const double *__restrict__ X,
@@ -604,7 +604,8 @@ hipError_t launch_trace(int32_t n, const int64_t *diagpos, const double *X, int3
 
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dev::k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, v);
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+    hipLaunchKernelGGL(dev::k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, st, p, count, v);
     return hipGetLastError();
 }
 

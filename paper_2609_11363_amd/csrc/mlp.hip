@@ -476,100 +476,260 @@ __global__ __launch_bounds__(64 * kFwdWaves, 4) void k_mlp_correct(MlpFeatParams
     }
 }
 
-// ---- backward (float32) -------------------------------------------------------
-// Phase A, lane = entry: recompute the forward pass in float32 with the same
-// bfloat16 quantisation, then dz2 = dy w3 [z2 > 0], dz1 = (W2^T dz2) [z1 > 0]
-// into LDS. Phase B, lane = unit n: accumulate the weight gradients over the
-// 64 entries of the tile. Each wavefront adds its totals to grad at the end.
+// ---- backward (bfloat16 MFMA, float32 accumulation) ------------------------------
+// A wavefront takes 16 entries at a time and recomputes their forward pass in
+// both orientations: transposed (units x entries, as the forward kernel does),
+// whose results are the k operands of the next product over units, and direct
+// (entries x units: the same MFMAs with A and B swapped), whose results hold
+// for one unit the values of four consecutive entries, the operand layout of
+// the gradient products, which contract over entries. So
+//   dz2 = dy w3 [z2 > 0]                        (both layouts, elementwise)
+//   dz1 = (dz2 W2) [z1 > 0]                     (direct; dz2 transposed as A)
+//   gW2 += dz2^T h1, gW1 += dz1^T x             (K = the 16 entries)
+//   gb2 += sum dz2, gb1 += sum dz1, gw3 += sum dy h2, gb3 += sum dy
+// with no transpose through LDS. The activations and weights are bfloat16
+// already, as in the forward pass; a float32 dz enters an MFMA as a bfloat16
+// head and tail (dz = hi + lo to 2^-17 relative), two products each, so only
+// the float32 sums round. The bfloat16 roundings of the forward pass count as
+// identity in the derivative. At the end the workgroup adds its four
+// wavefronts' sums in LDS (in wavefront order) and adds them to grad with one
+// atomic per parameter.
 
-constexpr int kBwdTile = 32;   // entries per pass
-constexpr int kLd = NH + 1;    // padded row stride of the per-entry LDS arrays
+constexpr int kBwdWaves = 4;
+constexpr int kBwdBlocksPerWave = 4;   // at least this many 16-entry blocks per wavefront (amortises the final reduction)
+constexpr int kBwdMaxGrid = 256;       // workgroups: one per compute unit
 
-__global__ __launch_bounds__(64) void k_mlp_backward(const uint8_t *__restrict__ W, const uint16_t *__restrict__ F,
-                                                     const float *__restrict__ dy, int64_t rows,
-                                                     float *__restrict__ grad) {
-    __shared__ float sW1[NH * NF];
-    __shared__ float sW2[NH * NH];
-    __shared__ float sw3[NH], sb1[NH], sb2[NH];
-    __shared__ float sX[kBwdTile * (NF + 1)];
-    __shared__ float sH1[kBwdTile * kLd], sH2[kBwdTile * kLd], sD1[kBwdTile * kLd], sD2[kBwdTile * kLd];
-    __shared__ float sDY[kBwdTile];
-    const int lane = threadIdx.x;
-    for (int t = lane; t < NH * NF; t += 64) {
-        int n = t / NF, k = t % NF;
-        sW1[t] = from_bf16(reinterpret_cast<const uint16_t *>(W + OFF_W1)[n * 32 + k]);
+// W2 fragments of dz1 = dz2 W2 (B operand: k = output unit in slot order
+// sigma, column = input unit 16 it + col), fragment f = 2 it + kb at
+// (f * 64 + lane) * 16.
+constexpr int kW2tFragBytes = 8 * 64 * 16;
+
+__device__ inline void load_w2t_frags(const uint8_t *W, uint8_t *swt) {
+    const uint16_t *w2 = reinterpret_cast<const uint16_t *>(W + OFF_W2);
+    for (int t = threadIdx.x; t < 8 * 64; t += blockDim.x) {
+        const int f = t >> 6, l = t & 63, it = f >> 1, kb = f & 1, c = l & 15, g = l >> 4;
+        uint32_t h[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) h[s] = w2[(16 * (2 * kb + s / 4) + 4 * g + s % 4) * NH + 16 * it + c];
+        *reinterpret_cast<uint4 *>(swt + t * 16) =
+            make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16, h[6] | h[7] << 16);
     }
-    for (int t = lane; t < NH * NH; t += 64) sW2[t] = from_bf16(reinterpret_cast<const uint16_t *>(W + OFF_W2)[t]);
-    sw3[lane] = from_bf16(reinterpret_cast<const uint16_t *>(W + OFF_W3)[lane]);
-    sb1[lane] = reinterpret_cast<const float *>(W + OFF_B1)[lane];
-    sb2[lane] = reinterpret_cast<const float *>(W + OFF_B2)[lane];
-    __syncthreads();
-    float gW2[NH], gW1[NF];
+}
+
+// x = hi + lo, both bfloat16 (the difference x - hi is exact in float32)
+__device__ inline void split2(float x, uint32_t &hi, uint32_t &lo) {
+    const uint16_t h = to_bf16(x);
+    hi = h;
+    lo = to_bf16(x - from_bf16(h));
+}
+
+// two 16 x 16 blocks (slots 0..3 from a, 4..7 from b) as bfloat16 head and tail
+__device__ inline void split_pack8(const f32x4 &a, const f32x4 &b, bf16x8 &hi, bf16x8 &lo) {
+    uint32_t h[8], l[8];
 #pragma unroll
-    for (int k = 0; k < NH; ++k) gW2[k] = 0.f;
+    for (int r = 0; r < 4; ++r) {
+        split2(a[r], h[r], l[r]);
+        split2(b[r], h[4 + r], l[4 + r]);
+    }
+    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16,
+                                               h[6] | h[7] << 16));
+    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0] | l[1] << 16, l[2] | l[3] << 16, l[4] | l[5] << 16,
+                                               l[6] | l[7] << 16));
+}
+
+__device__ inline void split_pack4(const f32x4 &a, s16x4 &hi, s16x4 &lo) {
+    uint32_t h[4], l[4];
 #pragma unroll
-    for (int k = 0; k < NF; ++k) gW1[k] = 0.f;
-    float gb1 = 0.f, gb2 = 0.f, gw3 = 0.f, gb3 = 0.f;
-    const int64_t ntiles = (rows + kBwdTile - 1) / kBwdTile;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        // phase A: lanes 0..31 take one entry each
-        if (lane < kBwdTile) {
-            const int64_t e = tile * kBwdTile + lane;
-            const bool valid = e < rows;
-            float x[NF];
+    for (int r = 0; r < 4; ++r) split2(a[r], h[r], l[r]);
+    hi = __builtin_bit_cast(s16x4, make_uint2(h[0] | h[1] << 16, h[2] | h[3] << 16));
+    lo = __builtin_bit_cast(s16x4, make_uint2(l[0] | l[1] << 16, l[2] | l[3] << 16));
+}
+
+__device__ inline s16x4 relu_pack4(const f32x4 &a) {
+    uint32_t h[4];
 #pragma unroll
-            for (int k = 0; k < NF; ++k) x[k] = valid ? from_bf16(F[e * NF + k]) : 0.f;
-            const float d = valid ? dy[e] : 0.f;
-            float *h1 = sH1 + lane * kLd, *h2 = sH2 + lane * kLd, *d1 = sD1 + lane * kLd, *d2 = sD2 + lane * kLd;
-            uint64_t m1 = 0, m2 = 0;
-            for (int n = 0; n < NH; ++n) {
-                float z = sb1[n];
+    for (int r = 0; r < 4; ++r) h[r] = to_bf16(relu(a[r]));
+    return __builtin_bit_cast(s16x4, make_uint2(h[0] | h[1] << 16, h[2] | h[3] << 16));
+}
+
+__device__ inline float sum_groups(float v) {  // over the four lane groups g (lanes col + 16 g)
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(64 * kBwdWaves, 2) void k_mlp_backward(const uint8_t *__restrict__ W,
+                                                                    const uint16_t *__restrict__ F,
+                                                                    const float *__restrict__ dy, int64_t rows,
+                                                                    float *__restrict__ grad) {
+    __shared__ __align__(16) float sb[2 * NH];
+    __shared__ __align__(16) uint8_t sw[kMlpFragBytes];
+    __shared__ __align__(16) uint8_t swt[kW2tFragBytes];
+    __shared__ float sw3[NH];
+    __shared__ __align__(16) uint16_t sX[kBwdWaves][16 * NF];
+    __shared__ float sred[kMlpParams];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, g = lane >> 4;
+    MlpRegs R;
+    for (int t = threadIdx.x; t < kMlpParams; t += blockDim.x) sred[t] = 0.f;
+    for (int t = threadIdx.x; t < NH; t += blockDim.x)
+        sw3[t] = from_bf16(reinterpret_cast<const uint16_t *>(W + OFF_W3)[t]);
+    load_w2t_frags(W, swt);
+    load_mlp_regs(W, col, g, R, sb, sw);  // ends with a workgroup barrier
+
+    f32x4 gW2[4][4], gW1[4];
 #pragma unroll
-                for (int k = 0; k < NF; ++k) z += sW1[n * NF + k] * x[k];
-                m1 |= (uint64_t)(z > 0.f) << n;
-                h1[n] = round_bf16(z > 0.f ? z : 0.f);
+    for (int a = 0; a < 4; ++a) {
+        gW1[a] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gW2[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    float gb1[4] = {0.f, 0.f, 0.f, 0.f}, gb2[4] = {0.f, 0.f, 0.f, 0.f}, gw3[4] = {0.f, 0.f, 0.f, 0.f};
+    float gb3 = 0.f;
+    float w3c[4];  // w3 of the lane's direct-layout units 16 nt + col
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) w3c[nt] = sw3[16 * nt + col];
+
+    const int64_t nblk = (rows + 15) / 16;
+    uint16_t *xs = sX[w];
+    for (int64_t blk = (int64_t)blockIdx.x * kBwdWaves + w; blk < nblk; blk += (int64_t)gridDim.x * kBwdWaves) {
+        const int64_t e0 = blk * 16;
+        // the block's 16 feature rows (32 bytes each) into LDS; rows past the end are 0
+        if (lane < 32) {
+            const int64_t e = e0 + (lane >> 1);
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (e < rows) v = reinterpret_cast<const uint4 *>(F + e * NF)[lane & 1];
+            reinterpret_cast<uint4 *>(xs)[lane] = v;
+        }
+        wave_sync();
+        // dy of entry col (transposed layout) and of entries 4 g + r (direct); 0 past the end
+        const float dyt = e0 + col < rows ? dy[e0 + col] : 0.f;
+        float dyn[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dyn[r] = e0 + 4 * g + r < rows ? dy[e0 + 4 * g + r] : 0.f;
+        const s16x4 x = *reinterpret_cast<const s16x4 *>(xs + col * NF + 4 * g);
+
+        // layer 1, both orientations
+        f32x4 z1t[4], z1n[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 b1t = *reinterpret_cast<const f32x4 *>(sb + 16 * nt + 4 * g);
+            const float b1c = sb[16 * nt + col];
+            z1t[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w1[nt], x, b1t, 0, 0, 0);
+            z1n[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, R.w1[nt], f32x4{b1c, b1c, b1c, b1c}, 0, 0, 0);
+        }
+        const bf16x8 h1t[2] = {relu_pack(z1t[0], z1t[1]), relu_pack(z1t[2], z1t[3])};
+        s16x4 h1n[4];
+        uint32_t m1 = 0;  // bit 4 it + r: z1 > 0 at entry 4 g + r, unit 16 it + col
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            h1n[it] = relu_pack4(z1n[it]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) m1 |= (uint32_t)(z1n[it][r] > 0.f) << (4 * it + r);
+        }
+
+        // layer 2, both orientations, and dz2
+        f32x4 d2t[4], d2n[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 b2t = *reinterpret_cast<const f32x4 *>(sb + NH + 16 * nt + 4 * g);
+            const float b2c = sb[NH + 16 * nt + col];
+            const int ln = col + 16 * g;
+            const bf16x8 wa = *reinterpret_cast<const bf16x8 *>(sw + ((nt * 2 + 0) * 64 + ln) * 16);
+            const bf16x8 wb = *reinterpret_cast<const bf16x8 *>(sw + ((nt * 2 + 1) * 64 + ln) * 16);
+            f32x4 zt = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, h1t[0], b2t, 0, 0, 0);
+            zt = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb, h1t[1], zt, 0, 0, 0);
+            f32x4 zn = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h1t[0], wa, f32x4{b2c, b2c, b2c, b2c}, 0, 0, 0);
+            zn = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h1t[1], wb, zn, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                d2t[nt][r] = zt[r] > 0.f ? dyt * sw3[16 * nt + 4 * g + r] : 0.f;
+                d2n[nt][r] = zn[r] > 0.f ? dyn[r] * w3c[nt] : 0.f;
+                gw3[nt] += dyn[r] * round_bf16(relu(zn[r]));
+                gb2[nt] += d2n[nt][r];
             }
-            for (int n = 0; n < NH; ++n) {
-                float z = sb2[n];
-                for (int k = 0; k < NH; ++k) z += sW2[n * NH + k] * h1[k];
-                m2 |= (uint64_t)(z > 0.f) << n;
-                h2[n] = round_bf16(z > 0.f ? z : 0.f);
-                d2[n] = ((m2 >> n) & 1) ? d * sw3[n] : 0.f;
-            }
-            for (int k = 0; k < NH; ++k) {
-                float s = 0.f;
-                for (int n = 0; n < NH; ++n) s += d2[n] * sW2[n * NH + k];
-                d1[k] = ((m1 >> k) & 1) ? s : 0.f;
-            }
+        }
+        if (col == 0) gb3 += (dyn[0] + dyn[1]) + (dyn[2] + dyn[3]);
+
+        // gW2 += dz2^T h1 (K = the block's 16 entries)
 #pragma unroll
-            for (int k = 0; k < NF; ++k) sX[lane * (NF + 1) + k] = x[k];
-            sDY[lane] = d;
+        for (int ob = 0; ob < 4; ++ob) {
+            s16x4 dh, dl;
+            split_pack4(d2n[ob], dh, dl);
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) {
+                gW2[ob][ib] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dh, h1n[ib], gW2[ob][ib], 0, 0, 0);
+                gW2[ob][ib] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dl, h1n[ib], gW2[ob][ib], 0, 0, 0);
+            }
+        }
+
+        // dz1 = (dz2 W2) [z1 > 0], direct layout: entries 4 g + r, input unit 16 it + col
+        bf16x8 d2h[2], d2l[2];
+        split_pack8(d2t[0], d2t[1], d2h[0], d2l[0]);
+        split_pack8(d2t[2], d2t[3], d2h[1], d2l[1]);
+        // x as the B operand of gW1: feature col of entries 4 g + r
+        uint32_t xv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xv[r] = xs[(4 * g + r) * NF + col];
+        const s16x4 xn = __builtin_bit_cast(s16x4, make_uint2(xv[0] | xv[1] << 16, xv[2] | xv[3] << 16));
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int ln = col + 16 * g;
+            const bf16x8 ta = *reinterpret_cast<const bf16x8 *>(swt + ((it * 2 + 0) * 64 + ln) * 16);
+            const bf16x8 tb = *reinterpret_cast<const bf16x8 *>(swt + ((it * 2 + 1) * 64 + ln) * 16);
+            f32x4 d1 = {0.f, 0.f, 0.f, 0.f};
+            d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(d2h[0], ta, d1, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(d2h[1], tb, d1, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(d2l[0], ta, d1, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(d2l[1], tb, d1, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                d1[r] = (m1 >> (4 * it + r)) & 1u ? d1[r] : 0.f;
+                gb1[it] += d1[r];
+            }
+            // gW1 += dz1^T x
+            s16x4 dh, dl;
+            split_pack4(d1, dh, dl);
+            gW1[it] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dh, xn, gW1[it], 0, 0, 0);
+            gW1[it] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dl, xn, gW1[it], 0, 0, 0);
+        }
+        wave_sync();  // xs is rewritten by the next block
+    }
+
+    // sums over the lane groups, then the workgroup's wavefronts in order into LDS
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        gb1[k] = sum_groups(gb1[k]);
+        gb2[k] = sum_groups(gb2[k]);
+        gw3[k] = sum_groups(gw3[k]);
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) gb3 += __shfl_xor(gb3, o, 64);
+    for (int turn = 0; turn < kBwdWaves; ++turn) {
+        if (w == turn) {
+#pragma unroll
+            for (int ob = 0; ob < 4; ++ob) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int n = 16 * ob + 4 * g + r;
+#pragma unroll
+                    for (int ib = 0; ib < 4; ++ib) sred[M_W2 + n * NH + 16 * ib + col] += gW2[ob][ib][r];
+                    sred[M_W1 + n * NF + col] += gW1[ob][r];
+                }
+            }
+            if (g == 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    sred[M_B1 + 16 * k + col] += gb1[k];
+                    sred[M_B2 + 16 * k + col] += gb2[k];
+                    sred[M_W3 + 16 * k + col] += gw3[k];
+                }
+            }
+            if (lane == 0) sred[M_B3] += gb3;
         }
         __syncthreads();
-        // phase B: lane = unit n
-        const int n = lane;
-        for (int ee = 0; ee < kBwdTile; ++ee) {
-            const float d2 = sD2[ee * kLd + n], d1 = sD1[ee * kLd + n];
-#pragma unroll
-            for (int k = 0; k < NH; ++k) gW2[k] += d2 * sH1[ee * kLd + k];
-#pragma unroll
-            for (int k = 0; k < NF; ++k) gW1[k] += d1 * sX[ee * (NF + 1) + k];
-            gb1 += d1;
-            gb2 += d2;
-            gw3 += sDY[ee] * sH2[ee * kLd + n];
-            if (n == 0) gb3 += sDY[ee];
-        }
-        __syncthreads();
     }
-    const int n = lane;
-#pragma unroll
-    for (int k = 0; k < NH; ++k) atomicAdd(&grad[M_W2 + n * NH + k], gW2[k]);
-#pragma unroll
-    for (int k = 0; k < NF; ++k) atomicAdd(&grad[M_W1 + n * NF + k], gW1[k]);
-    atomicAdd(&grad[M_B1 + n], gb1);
-    atomicAdd(&grad[M_B2 + n], gb2);
-    atomicAdd(&grad[M_W3 + n], gw3);
-    if (n == 0) atomicAdd(&grad[M_B3], gb3);
+    for (int t = threadIdx.x; t < kMlpParams; t += blockDim.x) atomicAdd(&grad[t], sred[t]);
 }
 
 // ---- loss, Adam, apply ------------------------------------------------------
@@ -657,9 +817,10 @@ hipError_t launch_mlp_forward(const void *W, const uint16_t *F, int64_t rows, fl
 hipError_t launch_mlp_backward(const void *W, const uint16_t *F, const float *dy, int64_t rows, float *grad,
                                hipStream_t st) {
     if (rows <= 0) return hipSuccess;
-    const int64_t tiles = (rows + dev::kBwdTile - 1) / dev::kBwdTile;
-    const int64_t grid = std::min<int64_t>(tiles, 512);
-    hipLaunchKernelGGL(dev::k_mlp_backward, dim3((unsigned)grid), dim3(64), 0, st,
+    const int64_t blocks = (rows + 15) / 16;
+    const int64_t per_wg = (int64_t)dev::kBwdWaves * dev::kBwdBlocksPerWave;
+    const int64_t grid = std::min<int64_t>((blocks + per_wg - 1) / per_wg, dev::kBwdMaxGrid);
+    hipLaunchKernelGGL(dev::k_mlp_backward, dim3((unsigned)grid), dim3(64 * dev::kBwdWaves), 0, st,
                        reinterpret_cast<const uint8_t *>(W), F, dy, rows, grad);
     return hipGetLastError();
 }

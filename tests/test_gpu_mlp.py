@@ -97,6 +97,36 @@ def test_backward_loss_adam_parity(solver):
     np.testing.assert_allclose(th.cpu().numpy()[big], t1[big], rtol=1e-6, atol=1e-7)
 
 
+@pytest.mark.parametrize("rows", [1, 17, 1000, 70001])
+def test_backward_sizes_and_accumulation(solver, rows):
+    """The backward pass (bfloat16 MFMA products, float32 sums) against the
+    oracle's float64 backward at ragged sizes (a single entry; one block and
+    one entry; many workgroups with a partial last block), and grad += on a
+    second call."""
+    import torch
+    X, theta = _random_inputs(rows, 11)
+    dyo = np.random.default_rng(12).standard_normal(rows).astype(np.float32) / max(rows, 1)
+    dev = solver.device
+    packed = solver.mlp_pack(torch.as_tensor(theta, device=dev))
+    Xd = torch.as_tensor(_bf16_words(X), device=dev)
+    dy = torch.as_tensor(dyo, device=dev)
+    grad = torch.zeros(om.NPARAMS, dtype=torch.float32, device=dev)
+    solver.mlp_backward(packed, Xd, dy, grad)
+    solver.sync()
+    g1 = grad.cpu().numpy().astype(np.float64)
+    solver.mlp_backward(packed, Xd, dy, grad)
+    solver.sync()
+    g2 = grad.cpu().numpy().astype(np.float64)
+    go = om.unpack(om.backward(theta, X, dyo.astype(np.float64)))
+    for tag, g, f in (("one call", g1, 1.0), ("two calls", g2, 2.0)):
+        gg = om.unpack(g)
+        for k in go:
+            ref = f * go[k]
+            e = np.linalg.norm(gg[k] - ref) / max(np.linalg.norm(ref), 1e-30)
+            print(f"  rows={rows} {tag} grad {k}: rel {e:.2e}")
+            assert e <= 1e-3, (tag, k)
+
+
 def test_features_parity_and_zero_layer_identity():
     import torch
     from paper_2609_11363_amd import Solver, upload_factors

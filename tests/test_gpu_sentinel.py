@@ -1,0 +1,84 @@
+"""NaN-sentinel runs of the device SelInv sweep (schedule check).
+
+Section 2.1 computes block J from entries of Zhat that blocks later in the
+ordering have already written. With asi_set_sentinel the library fills its
+working copy of Z with NaN before every sweep, so an entry read before its
+block writes it (a schedule or dependency mistake) would turn the result
+non-finite instead of silently reusing a value left by an earlier call. The
+output array is NaN-filled by the test as well, so an entry the sweep never
+writes shows too. Every level-kernel variant (the layered factor), 2x2 pivots
+(KKT), both precisions and the dataflow sweep are covered; each result must
+be finite, match the oracle, and match the ordinary run of the same handle.
+"""
+import numpy as np
+import pytest
+
+from oracle import core as oc
+from workloads import diffusion3d_7pt, ildl_bk, kkt_matrix, nested_multicolor_grid
+from workloads.layered import layered_factor
+
+pytestmark = pytest.mark.gpu
+
+# against the oracle, and against the ordinary run of the same handle (repeat
+# runs may differ in the last bits where several wavefronts add into one
+# block's accumulators: up to about 1e-12 on the ill-conditioned KKT case)
+TOL = {"fp64": 1e-10, "mixed": 1e-4}
+
+
+def _factor(name):
+    if name == "layered":
+        return layered_factor(seed=2)
+    if name == "kkt":
+        return ildl_bk(kkt_matrix(300, 180, 5), None, 1e-2)
+    if name == "diff16":
+        return ildl_bk(diffusion3d_7pt(16, 1.0, 9), nested_multicolor_grid((16, 16, 16)), 1e-3)
+    raise KeyError(name)
+
+
+@pytest.fixture(scope="module")
+def cases():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            F = _factor(name)
+            S = oc.pattern(F)
+            cache[name] = (F, S, oc.selinv(F, S))
+        return cache[name]
+    return get
+
+
+@pytest.mark.parametrize("sweep", ["levels", "dataflow"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["layered", "kkt", "diff16"])
+def test_sentinel_sweep_is_finite_and_matches(cases, name, precision, sweep):
+    import torch
+    from paper_2609_11363_amd import Solver, upload_factors
+    F, S, Zo = cases(name)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    if sweep == "dataflow" and s.info()["max_cols"] > 128:
+        pytest.skip("the dataflow sweep takes |R_J| <= 128 only")
+    print(f"[sentinel] case={name} precision={precision} sweep={sweep} n={F.n} |S|={S.nnz} "
+          f"2x2={int((F.piv == 1).sum())}", flush=True)
+    s.set_sweep(sweep)
+    Lv, dd, ds = upload_factors(F)
+    dev = torch.device("cuda", 0)
+    s.set_sentinel(True)
+    outs = []
+    for _ in range(2):  # the second sweep starts from NaN again, not from the first's values
+        Z = torch.full((S.nnz,), float("nan"), dtype=torch.float64, device=dev)
+        s.selinv(Lv, dd, ds, precision=precision, out=Z)
+        s.sync()
+        outs.append(Z.cpu().numpy())
+    s.set_sentinel(False)
+    Zp = s.selinv(Lv, dd, ds, precision=precision)
+    s.sync()
+    Zp = Zp.cpu().numpy()
+    for Zs in outs:
+        assert np.isfinite(Zs).all(), f"{int((~np.isfinite(Zs)).sum())} non-finite entries"
+        e = oc.entry_error(S, Zs, Zo).max()
+        r = oc.entry_error(S, Zs, Zp).max()
+        print(f"  vs oracle {e:.2e}, vs the ordinary run {r:.2e}", flush=True)
+        assert e <= TOL[precision]
+        assert r <= TOL[precision]

@@ -366,3 +366,26 @@ def test_selinv_block_check_accepts_selinv_and_flags_a_planted_error():
         p = S.rowptr[10] + 1  # an off-diagonal entry of row 10
         Zb[p] *= 1.0 + 1e-6
         assert oc.selinv_block_check(F, S, Zb, blocks).max() >= 1e-8
+
+
+def test_selinv_nan_sentinel_run_is_finite_and_catches_a_planted_order_mistake():
+    """NaN-sentinel run (Section 2.1 reads only entries of Zhat that later
+    blocks have written): starting from NaN on S instead of zero gives a
+    finite result, bit for bit the ordinary one, on 1x1 and 2x2 incomplete
+    factors. The same run with the blocks visited in the wrong order (first
+    to last, a mistake planted in the oracle) turns non-finite, while the
+    zero-started run with that mistake stays finite: the sentinel is what
+    exposes it."""
+    cases = [ildl_bk(laplace2d(12, 12, 0.05), rcm(laplace2d(12, 12, 0.05)), 1e-2),
+             ildl_bk(kkt_matrix(30, 18, 3), None, 1e-2),
+             ildl_bk(diffusion3d_7pt(6, 1.0, 4), nested_multicolor_grid((6, 6, 6)), 1e-3)]
+    assert cases[1].n_2x2 > 0
+    for F in cases:
+        S = oc.pattern(F)
+        Z = oc.selinv(F, S)
+        Zs = oc.selinv(F, S, sentinel=True)
+        assert np.isfinite(Zs).all()
+        assert np.array_equal(Zs, Z)
+        wrong = oc.selinv(F, S, wrong_order=True)
+        assert np.isfinite(wrong).all()
+        assert not np.isfinite(oc.selinv(F, S, sentinel=True, wrong_order=True)).all()
