@@ -474,15 +474,18 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
 // ---- N on S through the transposed series pattern ---------------------------
 // Row k of L^inv lists the columns whose series reaches row k. N_ij can be
 // nonzero only where columns i and j share a row, so: count the columns of
-// every row, scan, list them (in the pool's free tail), then for every row k
-// and every pair i >= j of its columns with (i, j) in S evaluate N_ij by the
-// merge of the two columns (the value of the entry-by-entry kernel, bit for
-// bit) and write it at (i, j) and (j, i); every other entry of S is zero.
-// A pair met through several rows is written with the same value each time.
+// every row, scan, list them with their row (in the pool's free tail), then,
+// one thread per listed (k, i), go over the columns j <= i of row k with
+// (i, j) in S and evaluate N_ij by the merge of the two columns (the value of
+// the entry-by-entry kernel, bit for bit), writing it at (i, j) and (j, i);
+// every other entry of S is zero. A pair is evaluated by the first row the two
+// columns share: the merge runs in increasing row order and gives up at a
+// first shared row other than k, so each N_ij is summed once.
 // This path applies when the lists fit the pool's free tail and every row
-// holds at most kPairMax columns; otherwise the entry-by-entry kernel runs
-// (each kernel reads the flag and returns early when it does not apply).
-constexpr int32_t kPairMax = 64;
+// holds at most kPairMax columns (a thread walks its row's list); otherwise
+// the entry-by-entry kernel runs (each kernel reads the flag and returns
+// early when it does not apply).
+constexpr int32_t kPairMax = 4096;
 
 __global__ void k_tr_init(NinvParams P) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -502,7 +505,7 @@ __global__ void k_tr_count(NinvParams P) {
 __global__ void k_tr_start(NinvParams P) {
     const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned long long top = *P.pool_top, total = P.tr_ptr[P.n];
-    if (k == 0 && top + total > (unsigned long long)P.pool_cap) *P.tr_flag = 0;
+    if (k == 0 && top + 2 * total > (unsigned long long)P.pool_cap) *P.tr_flag = 0;
     if (k < P.n) P.tr_cur[k] = P.tr_ptr[k];
 }
 
@@ -510,12 +513,14 @@ __global__ void k_tr_fill(NinvParams P) {
     const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= P.n || *P.tr_flag == 0) return;
     int32_t *colT = P.prow + *P.pool_top;
+    int32_t *rowT = colT + P.tr_ptr[P.n];
     const int64_t b = P.cstart[j];
     const int32_t len = P.clen[j];
     for (int32_t a = 0; a < len; ++a) {
         const int32_t k = P.prow[b + a];
         const unsigned long long pos = atomicAdd(&P.tr_cur[k], 1ull);
         colT[pos] = j;
+        rowT[pos] = k;
         if (pos - P.tr_ptr[k] >= (unsigned long long)kPairMax) *P.tr_flag = 0;
     }
 }
@@ -578,20 +583,59 @@ __device__ inline double n_entry(const NinvParams &P, int32_t i, int32_t j) {
     return (double)sum;
 }
 
+// N_ij (i >= j) as n_entry, for the pair met through row k (which both
+// columns hold): false, without the sum, when the first row the two columns
+// share is not k (that row evaluates the pair)
 template <typename T>
-__global__ void k_npairs(NinvParams P) {
-    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= P.n || *P.tr_flag == 0) return;
+__device__ inline bool n_entry_at(const NinvParams &P, int32_t i, int32_t j, int32_t k, double &v) {
+    const T *plinv = reinterpret_cast<const T *>(P.plinv);
+    const T *pw = reinterpret_cast<const T *>(P.pw);
+    const int64_t ci = P.cstart[i], cj = P.cstart[j];
+    const int32_t li = P.clen[i], lj = P.clen[j];
+    T sum = T(0);
+    bool first = true;
+    int32_t a = 0, b = 0;
+    int32_t ra = a < li ? P.prow[ci] : INT32_MAX, rb = b < lj ? P.prow[cj] : INT32_MAX;
+    while (a < li && b < lj) {
+        if (ra == rb) {
+            if (first) {
+                if (ra != k) return false;
+                first = false;
+            }
+            sum += plinv[ci + a] * pw[cj + b];
+            ++a;
+            ++b;
+            ra = a < li ? P.prow[ci + a] : INT32_MAX;
+            rb = b < lj ? P.prow[cj + b] : INT32_MAX;
+        } else if (ra < rb) {
+            ++a;
+            ra = a < li ? P.prow[ci + a] : INT32_MAX;
+        } else {
+            ++b;
+            rb = b < lj ? P.prow[cj + b] : INT32_MAX;
+        }
+    }
+    v = (double)sum;
+    return true;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_npairs(NinvParams P) {
+    if (*P.tr_flag == 0) return;
+    const int64_t total = (int64_t)P.tr_ptr[P.n];
     const int32_t *colT = P.prow + *P.pool_top;
-    const int64_t c0 = (int64_t)P.tr_ptr[k], c1 = (int64_t)P.tr_ptr[k + 1];
-    for (int64_t a = c0; a < c1; ++a) {
-        const int32_t i = colT[a];
+    const int32_t *rowT = colT + total;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int32_t k = rowT[t], i = colT[t];
+        const int64_t c0 = (int64_t)P.tr_ptr[k], c1 = (int64_t)P.tr_ptr[k + 1];
         for (int64_t b = c0; b < c1; ++b) {
             const int32_t j = colT[b];
             if (j > i) continue;
             const int64_t p = s_pos(P, i, j);
             if (p < 0) continue;
-            const double v = n_entry<T>(P, i, j);
+            double v;
+            if (!n_entry_at<T>(P, i, j, k, v)) continue;
             P.out[p] = v;
             if (i != j) P.out[P.mirror[p]] = v;
         }
@@ -740,7 +784,7 @@ hipError_t run_ninv(const NinvParams &P, hipStream_t st, int cap) {
         hipLaunchKernelGGL(k_tr_start, gn, b, 0, st, P);
         hipLaunchKernelGGL(k_tr_fill, gn, b, 0, st, P);
         hipLaunchKernelGGL(k_nzero, gs, b, 0, st, P, nnz);
-        hipLaunchKernelGGL((k_npairs<T>), gn, b, 0, st, P);
+        hipLaunchKernelGGL((k_npairs<T>), gs, b, 0, st, P);
         hipLaunchKernelGGL((k_nprod_entry<T>), gs, b, 0, st, P, nnz, P.srow);
     }
     return hipGetLastError();
