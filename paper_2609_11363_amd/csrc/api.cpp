@@ -493,7 +493,7 @@ static asi_status prepare_factor(asi_handle h, const double *L_val, const double
     if (L_val || d_diag || d_sub) {
         if ((!L_val && A.nnzL > 0) || !d_diag || !d_sub)
             return fail(h, ASI_E_ARG, "null factor pointer (give L_val, d_diag and d_sub, or none of them)");
-        h->factor_loaded = false;  // dinv (and Lu or Lf) now hold this call's factor
+        h->factor_loaded = false;  // dinv and Lu (and Lf for a mixed call) now hold this call's factor
         h->lf_loaded = false;
         h->ls_loaded = false;
         {
@@ -502,22 +502,24 @@ static asi_status prepare_factor(asi_handle h, const double *L_val, const double
         }
         if (e != hipSuccess) return hip_fail(h, e, "dinv");
         {
+            // the float64 copy in the column layout always (NInv's series
+            // reads it in both precisions), with the row and column norms of
+            // L (learned-correction features)
             Trace t(h, ASI_K_GATHER, 20.0 * A.nnzL);
-            e = asi::launch_scatter_lu(A.nnzL, h->q2u, L_val, fp64 ? h->Lu : (void *)h->Lf, fp64, h->stream);
-            // the row and column norms of L (learned-correction features) come with the float64 copy
-            if (e == hipSuccess && fp64)
+            e = asi::launch_scatter_lu(A.nnzL, h->q2u, L_val, h->Lu, true, h->stream);
+            if (e == hipSuccess)
                 e = asi::launch_factor_norms(A.n, h->rowptr_L, L_val, h->ustart, reinterpret_cast<const double *>(h->Lu),
                                              h->rn, h->Lcsr, h->stream);
         }
         if (e != hipSuccess) return hip_fail(h, e, "gather L");
-    } else {
-        if (!h->factor_loaded) return fail(h, ASI_E_STATE, "no factor given and none loaded (asi_load_factor)");
-        if (!fp64 && !h->lf_loaded) {
-            Trace t(h, ASI_K_GATHER, 12.0 * A.nnzU);
-            e = asi::launch_lu_to_float(A.nnzU, reinterpret_cast<const double *>(h->Lu), h->Lf, h->stream);
-            if (e != hipSuccess) return hip_fail(h, e, "L to float32");
-            h->lf_loaded = true;
-        }
+    } else if (!h->factor_loaded) {
+        return fail(h, ASI_E_STATE, "no factor given and none loaded (asi_load_factor)");
+    }
+    if (!fp64 && !h->lf_loaded) {
+        Trace t(h, ASI_K_GATHER, 12.0 * A.nnzU);
+        e = asi::launch_lu_to_float(A.nnzU, reinterpret_cast<const double *>(h->Lu), h->Lf, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "L to float32");
+        h->lf_loaded = true;
     }
     *Lu = fp64 ? h->Lu : (const void *)h->Lf;
     return ASI_OK;
@@ -661,10 +663,12 @@ asi_status asi_sweep_plan(asi_handle h, int64_t *counts_h) {
     return ASI_OK;
 }
 
-// NInv on stream st, reading L in u-space from Lu; linv_grid > 0 caps the
-// workgroups of the persistent series kernel (0: as many as are resident).
-static asi_status ninv_launch(asi_handle h, const void *Lu, bool fp64, int32_t p, double delta, double *N_S,
-                              hipStream_t st, int linv_grid) {
+// NInv on stream st. The series reads the float64 copy of L (Lu) in both
+// precisions; fp64 selects the storage of its columns and the precision of
+// the product. linv_grid > 0 caps the workgroups of the persistent series
+// kernel (0: as many as are resident; < 0: that fraction of them).
+static asi_status ninv_launch(asi_handle h, bool fp64, int32_t p, double delta, double *N_S, hipStream_t st,
+                              int linv_grid) {
     const asi::Analysis &A = h->A;
     asi::NinvParams P{};
     P.n = A.n;
@@ -677,7 +681,7 @@ static asi_status ninv_launch(asi_handle h, const void *Lu, bool fp64, int32_t p
     P.ustart = h->ustart;
     P.ucol = h->ucol;
     P.piv = h->piv;
-    P.Lu = Lu;
+    P.Lu = h->Lu;
     P.dinv = h->dinv;
     P.p = p;
     P.delta = delta;
@@ -719,7 +723,7 @@ asi_status asi_ninv(asi_handle h, const double *L_val, const double *d_diag, con
     const void *Lu = nullptr;
     s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu);
     if (s != ASI_OK) return s;
-    return ninv_launch(h, Lu, fp64, p, delta, N_S, h->stream, 0);
+    return ninv_launch(h, fp64, p, delta, N_S, h->stream, 0);
 }
 
 // Result sizes of the full-pattern calls: the count pass leaves the row
@@ -890,7 +894,7 @@ asi_status asi_selinv_ninv(asi_handle h, const double *L_val, const double *d_di
     if (s != ASI_OK) return s;
     // the dataflow sweep needs every workgroup resident: no concurrent work beside it
     if (h->sweep == ASI_SWEEP_DATAFLOW) {
-        s = ninv_launch(h, Lu, fp64, p, delta, N_S, h->stream, 0);
+        s = ninv_launch(h, fp64, p, delta, N_S, h->stream, 0);
         if (s != ASI_OK) return s;
         return selinv_launch(h, Lu, fp64, Z_S, h->stream);
     }
@@ -906,7 +910,7 @@ asi_status asi_selinv_ninv(asi_handle h, const double *L_val, const double *d_di
     if (e != hipSuccess) return hip_fail(h, e, "fork");
     // NInv's persistent kernel takes half the resident workgroups, leaving
     // compute units to the latency-bound SelInv levels running beside it
-    s = ninv_launch(h, Lu, fp64, p, delta, N_S, h->aux, -2);
+    s = ninv_launch(h, fp64, p, delta, N_S, h->aux, -2);
     if (s == ASI_OK) s = selinv_launch(h, Lu, fp64, Z_S, h->stream);
     e = hipEventRecord(h->ev_join, h->aux);
     if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->ev_join, 0);

@@ -2,15 +2,21 @@
 //
 // Column j of L^inv: t^0 = e_j, t^m = drop_delta(E t^{m-1}) with E = I - L,
 // L^inv(:, j) = sum_m t^m (Section 2.2). One wavefront builds one column in an
-// LDS hash table keyed by row; the column of L that E t^{m-1} needs for a
-// row k is the upper segment of row k of S (contiguous), with its values
-// gathered through lsrc. Columns that outgrow the wavefront table are
-// redone by a 256-thread workgroup with a larger table.
+// LDS hash table keyed by row; E t^{m-1} scatters the columns of L of the
+// current term's rows (their u-ranges of the column layout). Columns that
+// outgrow the wavefront table are redone by a 256-thread workgroup with a
+// larger table. The series is computed in float64 in both precisions, from
+// the float64 copy of L: its drop tests are discontinuous in the values, so a
+// float32 series would keep or drop different entries near delta than the
+// float64 method; the mixed-precision form stores the finished columns (and
+// w = D^-1 L^inv) in float32 for the product.
 //
 // N = (L^inv)^T D^-1 L^inv on S: for every (i, j) in S (i >= j by symmetry),
 // N_ij = sum_k L^inv(k, i) w_j(k), w_j = D^-1 L^inv(:, j). The series columns
-// are stored sorted by row with w beside L^inv, so one thread per entry of S
-// merges the two (short) columns.
+// are stored sorted by row with w beside L^inv; the product goes through the
+// transposed pattern of L^inv (below), with an entry-by-entry merge of the two
+// columns as the fallback. Products are in the pool's precision, their sums in
+// float64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -130,7 +136,7 @@ __device__ inline int32_t group_max_i(int32_t v, int32_t *scratch) {
 template <typename T>
 struct LinvLds {
     int32_t *key;  // H
-    T *nxt, *ser;  // H: the term being accumulated, the series
+    double *nxt, *ser;  // H: the term being accumulated, the series (float64 sums in both precisions)
     int32_t *tl;   // H: slots touched by the current column
     int32_t *lk;   // H: rows of the current term (compact)
     T *lv;         // H: values of the current term
@@ -209,7 +215,7 @@ __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S,
         S.flag[1] = 1;
     }
     gsync<G>();
-    const T delta = (T)P.delta;
+    const double delta = P.delta;
     int m0 = 1;
     if (P.p >= 1) {
         // t^1 = drop_delta(E e_j) = drop_delta(-L(:, j)): the rows of column j
@@ -225,7 +231,7 @@ __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S,
             if (q < u1) {
                 const T l = Lu[q];
                 v = -(T(1) * l);
-                if (l != T(0) && !(fabs(v) < delta)) key = P.ucol[q];
+                if (l != T(0) && !(fabs((double)v) < delta)) key = P.ucol[q];
             }
             int32_t cnt;
             const int32_t p0 = group_excl_scan<G>(key >= 0 ? 1 : 0, S.scr, &cnt);
@@ -308,7 +314,7 @@ __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S,
                     S.flag[0] = 1;
                     continue;
                 }
-                atomicAdd(&S.nxt[s], -S.lv[b[u]] * l[u]);
+                atomicAdd(&S.nxt[s], (double)(-S.lv[b[u]] * l[u]));
             }
         }
         gsync<G>();
@@ -320,13 +326,13 @@ __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S,
         for (int i0 = 0; i0 < nt; i0 += G) {
             const int i = i0 + tid;
             int32_t key = -1;
-            T v = T(0);
+            double v = 0.0;
             if (i < nt) {
                 int s = S.tl[i];
                 v = S.nxt[s];
-                S.nxt[s] = T(0);
+                S.nxt[s] = 0.0;
                 key = S.key[s];
-                bool keep = v != T(0) && !(fabs(v) < delta);
+                bool keep = v != 0.0 && !(fabs(v) < delta);
                 if (keep)
                     S.ser[s] += v;
                 else
@@ -336,7 +342,7 @@ __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S,
             int32_t p0 = group_excl_scan<G>(key >= 0 ? 1 : 0, S.scr, &cnt);
             if (key >= 0 && nn + p0 < TC) {
                 S.lk[nn + p0] = key;
-                S.lv[nn + p0] = v;
+                S.lv[nn + p0] = (T)v;
             }
             nn += cnt;
         }
@@ -369,15 +375,15 @@ __device__ bool linv_column(const NinvParams &P, int32_t j, const LinvLds<T> &S,
 }
 
 // writes the finished column to the pool
-template <typename T, int G, int H, int TC>
-__device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, int tid) {
+template <typename TP, int G, int H, int TC>
+__device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<double> &S, int tid) {
     auto wanted = [&](int s) -> bool {
         int32_t r = S.key[s];
-        if (S.ser[s] != T(0)) return true;
+        if (S.ser[s] != 0.0) return true;
         int8_t pv = P.piv[r];
         if (pv == 0) return false;
         int ps = hfind(S.key, H, pv == 1 ? r + 1 : r - 1);
-        return ps >= 0 && S.ser[ps] != T(0);
+        return ps >= 0 && S.ser[ps] != 0.0;
     };
     // which touched slots the column keeps, once per slot (held in nxt, which
     // is zero between terms and reset with the column); the kept rows are
@@ -389,7 +395,7 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
     for (int i = tid; i < nt; i += G) {
         const int s = S.tl[i];
         const bool keep = wanted(s);
-        S.nxt[s] = keep ? T(1) : T(0);
+        S.nxt[s] = keep ? 1.0 : 0.0;
         mine += keep;
     }
     int32_t cnt;
@@ -398,7 +404,7 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
     if (compact)
         for (int i = tid; i < nt; i += G) {
             const int s = S.tl[i];
-            if (S.nxt[s] != T(0)) S.lk[pos++] = S.key[s];
+            if (S.nxt[s] != 0.0) S.lk[pos++] = S.key[s];
         }
     if (tid == 0) {
         int64_t base = S.base[1];
@@ -423,11 +429,11 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
     const int64_t base = S.base[0];
     int32_t last = -1;  // the column's largest row (quick test of the product)
     if (fits) {
-        T *plinv = reinterpret_cast<T *>(P.plinv);
-        T *pw = reinterpret_cast<T *>(P.pw);
+        TP *plinv = reinterpret_cast<TP *>(P.plinv);
+        TP *pw = reinterpret_cast<TP *>(P.pw);
         for (int i = tid; i < nt; i += G) {
             const int s = S.tl[i];
-            if (S.nxt[s] == T(0)) continue;
+            if (S.nxt[s] == 0.0) continue;
             int32_t r = S.key[s];
             // the column is stored sorted by row: the entry's rank among the
             // column's kept rows (rows are distinct)
@@ -437,29 +443,31 @@ __device__ void linv_emit(const NinvParams &P, int32_t j, const LinvLds<T> &S, i
             } else {
                 for (int i2 = 0; i2 < nt; ++i2) {
                     const int s2 = S.tl[i2];
-                    rank += (S.key[s2] < r && S.nxt[s2] != T(0)) ? 1 : 0;
+                    rank += (S.key[s2] < r && S.nxt[s2] != 0.0) ? 1 : 0;
                 }
             }
             last = r > last ? r : last;
-            T lv = S.ser[s];
+            // the series is float64 in both precisions; the pool stores it
+            // (and w = D^-1 L^inv) in the call's precision
+            const double lv = S.ser[s];
             int8_t pv = P.piv[r];
-            T w;
+            double w;
             if (pv == 0) {
-                w = (T)P.dinv[3 * (int64_t)r] * lv;
+                w = P.dinv[3 * (int64_t)r] * lv;
             } else {
                 int32_t K = pv == 1 ? r : r - 1;
                 int ps = hfind(S.key, H, pv == 1 ? r + 1 : r - 1);
-                T other = ps >= 0 ? S.ser[ps] : T(0);
+                const double other = ps >= 0 ? S.ser[ps] : 0.0;
                 const double *iv = P.dinv + 3 * (int64_t)K;
                 if (pv == 1)
-                    w = (T)iv[0] * lv + (T)iv[1] * other;
+                    w = iv[0] * lv + iv[1] * other;
                 else
-                    w = (T)iv[1] * other + (T)iv[2] * lv;
+                    w = iv[1] * other + iv[2] * lv;
             }
             const int64_t d = base + rank;
             P.prow[d] = r;
-            plinv[d] = lv;
-            pw[d] = w;
+            plinv[d] = (TP)lv;
+            pw[d] = (TP)w;
         }
     }
     last = group_max_i<G>(last, S.scr);
@@ -562,12 +570,12 @@ __device__ inline double n_entry(const NinvParams &P, int32_t i, int32_t j) {
     const T *pw = reinterpret_cast<const T *>(P.pw);
     const int64_t ci = P.cstart[i], cj = P.cstart[j];
     const int32_t li = P.clen[i], lj = P.clen[j];
-    T sum = T(0);
+    double sum = 0.0;  // float64 sums also in mixed precision (float32 products)
     int32_t a = 0, b = 0;
     int32_t ra = a < li ? P.prow[ci] : INT32_MAX, rb = b < lj ? P.prow[cj] : INT32_MAX;
     while (a < li && b < lj) {
         if (ra == rb) {
-            sum += plinv[ci + a] * pw[cj + b];
+            sum += (double)(plinv[ci + a] * pw[cj + b]);
             ++a;
             ++b;
             ra = a < li ? P.prow[ci + a] : INT32_MAX;
@@ -580,7 +588,7 @@ __device__ inline double n_entry(const NinvParams &P, int32_t i, int32_t j) {
             rb = b < lj ? P.prow[cj + b] : INT32_MAX;
         }
     }
-    return (double)sum;
+    return sum;
 }
 
 // N_ij (i >= j) as n_entry, for the pair met through row k (which both
@@ -592,7 +600,7 @@ __device__ inline bool n_entry_at(const NinvParams &P, int32_t i, int32_t j, int
     const T *pw = reinterpret_cast<const T *>(P.pw);
     const int64_t ci = P.cstart[i], cj = P.cstart[j];
     const int32_t li = P.clen[i], lj = P.clen[j];
-    T sum = T(0);
+    double sum = 0.0;  // float64 sums also in mixed precision (float32 products)
     bool first = true;
     int32_t a = 0, b = 0;
     int32_t ra = a < li ? P.prow[ci] : INT32_MAX, rb = b < lj ? P.prow[cj] : INT32_MAX;
@@ -602,7 +610,7 @@ __device__ inline bool n_entry_at(const NinvParams &P, int32_t i, int32_t j, int
                 if (ra != k) return false;
                 first = false;
             }
-            sum += plinv[ci + a] * pw[cj + b];
+            sum += (double)(plinv[ci + a] * pw[cj + b]);
             ++a;
             ++b;
             ra = a < li ? P.prow[ci + a] : INT32_MAX;
@@ -615,7 +623,7 @@ __device__ inline bool n_entry_at(const NinvParams &P, int32_t i, int32_t j, int
             rb = b < lj ? P.prow[cj + b] : INT32_MAX;
         }
     }
-    v = (double)sum;
+    v = sum;
     return true;
 }
 
@@ -647,62 +655,63 @@ constexpr int kLinvTerm = 64;    // kept entries of one term (the series columns
 constexpr int kLinvHBig = 2048;
 constexpr int kLinvGrid = 2048;  // workgroups of the persistent column kernel
 
-template <typename T, int WAVES>
+// TP: the storage type of the pool (the series itself is float64)
+template <typename TP, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_linv_small(NinvParams P) {
     __shared__ int32_t key[WAVES][kLinvH];
-    __shared__ T nxt[WAVES][kLinvH], ser[WAVES][kLinvH];
+    __shared__ double nxt[WAVES][kLinvH], ser[WAVES][kLinvH];
     __shared__ int32_t tl[WAVES][kLinvH];
     __shared__ int32_t lk[WAVES][kLinvTerm];
-    __shared__ T lv[WAVES][kLinvTerm];
+    __shared__ double lv[WAVES][kLinvTerm];
     __shared__ int32_t off[WAVES][kLinvTerm + 1];
     __shared__ int64_t seg[WAVES][kLinvTerm];
     __shared__ int32_t scr[WAVES][8];
     __shared__ int32_t flag[WAVES][8];
     __shared__ int64_t basev[WAVES][3];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    LinvLds<T> S{key[w], nxt[w], ser[w], tl[w], lk[w], lv[w], off[w], seg[w], scr[w], flag[w], basev[w]};
-    linv_init<T, 64, kLinvH>(S, lane);
+    LinvLds<double> S{key[w], nxt[w], ser[w], tl[w], lk[w], lv[w], off[w], seg[w], scr[w], flag[w], basev[w]};
+    linv_init<double, 64, kLinvH>(S, lane);
     const int32_t stride = gridDim.x * WAVES;
     for (int32_t j = blockIdx.x * WAVES + w; j < P.n; j += stride) {
-        if (linv_column<T, 64, kLinvH, kLinvTerm>(P, j, S, lane)) {
-            linv_emit<T, 64, kLinvH, kLinvTerm>(P, j, S, lane);
+        if (linv_column<double, 64, kLinvH, kLinvTerm>(P, j, S, lane)) {
+            linv_emit<TP, 64, kLinvH, kLinvTerm>(P, j, S, lane);
         } else if (lane == 0) {
             P.clen[j] = -1;
             int32_t slot = atomicAdd(P.ovf_count, 1);
             P.ovf_list[slot] = j;
         }
-        linv_reset<T, 64, kLinvH>(S, lane);
+        linv_reset<double, 64, kLinvH>(S, lane);
     }
 }
 
-template <typename T>
+template <typename TP>
 __global__ __launch_bounds__(256) void k_linv_big(NinvParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int H = kLinvHBig;
     int64_t *basev = reinterpret_cast<int64_t *>(smem);
     int64_t *seg = basev + 4;
-    T *nxt = reinterpret_cast<T *>(seg + H);
-    T *ser = nxt + H;
-    T *lv = ser + H;
+    double *nxt = reinterpret_cast<double *>(seg + H);
+    double *ser = nxt + H;
+    double *lv = ser + H;
     int32_t *key = reinterpret_cast<int32_t *>(lv + H);
     int32_t *tl = key + H;
     int32_t *lk = tl + H;
     int32_t *off = lk + H;
     int32_t *scr = off + H + 1;
     int32_t *flag = scr + 8;
-    LinvLds<T> S{key, nxt, ser, tl, lk, lv, off, seg, scr, flag, basev};
+    LinvLds<double> S{key, nxt, ser, tl, lk, lv, off, seg, scr, flag, basev};
     const int32_t cnt = *P.ovf_count;
     if (cnt == 0) return;
-    linv_init<T, 256, H>(S, threadIdx.x);
+    linv_init<double, 256, H>(S, threadIdx.x);
     for (int32_t idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
         int32_t j = P.ovf_list[idx];
-        if (linv_column<T, 256, H, H>(P, j, S, threadIdx.x)) {
-            linv_emit<T, 256, H, H>(P, j, S, threadIdx.x);
+        if (linv_column<double, 256, H, H>(P, j, S, threadIdx.x)) {
+            linv_emit<TP, 256, H, H>(P, j, S, threadIdx.x);
         } else if (threadIdx.x == 0) {
             P.clen[j] = 0;
             latch2(P.status, ST_LIMIT);
         }
-        linv_reset<T, 256, H>(S, threadIdx.x);
+        linv_reset<double, 256, H>(S, threadIdx.x);
     }
 }
 
@@ -739,7 +748,7 @@ __global__ void k_ninv_reset(NinvParams P) {
 
 template <typename T>
 size_t linv_big_lds() {
-    return 32 + 8 * (size_t)kLinvHBig + 3 * (size_t)kLinvHBig * sizeof(T) +
+    return 32 + 8 * (size_t)kLinvHBig + 3 * (size_t)kLinvHBig * 8 +
            (4 * (size_t)kLinvHBig + 1 + 8 + 8) * 4 + 64;
 }
 // Workgroups of the persistent column kernel: as many as can be resident at

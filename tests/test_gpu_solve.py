@@ -83,6 +83,14 @@ def test_pcg(name):
     res = np.linalg.norm(Ah @ x.cpu().numpy() - b) / np.linalg.norm(b)
     print(f"[pcg] {name}: {it} steps, reported {rr:.1e}, true residual {res:.1e}, error {err:.1e}")
     assert rr <= 1e-12 and res <= 1e-11 and err <= 1e-9
+    # with other work on the stream between calls, a second call repeats the
+    # first bit for bit
+    bd = torch.as_tensor(b, device=dev)
+    ze = s.ldl_solve(bd)
+    x2, it2, rr2 = s.pcg(Ar, Ac, Av, perm, bd, tol=1e-12, maxit=500)
+    ze2 = s.ldl_solve(bd)
+    s.sync()
+    assert torch.equal(x, x2) and it2 == it and rr2 == rr and torch.equal(ze, ze2)
     # zero right-hand side: zero steps, zero solution
     x0, it0, _ = s.pcg(Ar, Ac, Av, perm, torch.zeros(F.n, dtype=torch.float64, device=dev))
     s.sync()

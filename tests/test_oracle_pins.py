@@ -389,3 +389,38 @@ def test_selinv_nan_sentinel_run_is_finite_and_catches_a_planted_order_mistake()
         wrong = oc.selinv(F, S, wrong_order=True)
         assert np.isfinite(wrong).all()
         assert not np.isfinite(oc.selinv(F, S, sentinel=True, wrong_order=True)).all()
+
+
+def test_saddle2d_generator_and_its_2x2_pivots():
+    """The saddle-point input: symmetric, the Laplacian block and one
+    constraint per 2 x 2 cell coupling exactly the cell's four grid unknowns,
+    a zero constraint block, q a permutation that puts each constraint before
+    its cell's unknowns; the host factorization then takes 2x2 pivots (and a
+    dense LDL^T of the same matrix confirms its inertia: N^2 positive and N^2/4
+    negative eigenvalues)."""
+    from workloads import saddle2d
+    N = 12
+    K, q = saddle2d(N)
+    n, nu = N * N + N * N // 4, N * N
+    assert K.shape == (n, n) and abs(K - K.T).max() == 0
+    Kd = K.toarray()
+    np.testing.assert_array_equal(Kd[:nu, :nu], laplace2d(N, N, 0.0).toarray())
+    assert not Kd[nu:, nu:].any()
+    for c in range(N * N // 4):
+        x, y = c % (N // 2), c // (N // 2)
+        cells = sorted((2 * x + dx) + N * (2 * y + dy) for dx in (0, 1) for dy in (0, 1))
+        assert sorted(np.nonzero(Kd[nu + c, :nu])[0].tolist()) == cells
+    assert sorted(q.tolist()) == list(range(n))
+    pos = np.empty(n, np.int64)
+    pos[q] = np.arange(n)
+    for c in range(N * N // 4):
+        assert all(pos[nu + c] < pos[u] for u in np.nonzero(Kd[nu + c, :nu])[0])
+    F = ildl_bk(K, q, 1e-3)
+    assert F.n_2x2 > 0
+    ev = np.linalg.eigvalsh(Kd)
+    assert (ev > 0).sum() == nu and (ev < 0).sum() == N * N // 4
+    # the inertia of D equals that of K (Sylvester) for the complete factor
+    G = ildl_bk(K, q, 0.0)
+    D = od.dense_D(G.d_diag, G.d_sub, G.piv)
+    evd = np.linalg.eigvalsh(D)
+    assert (evd > 0).sum() == nu and (evd < 0).sum() == N * N // 4

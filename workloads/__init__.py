@@ -14,14 +14,15 @@ also gives the exact A^-1 products and diag(A^-1) in closed form: the
 reference quantities that the paper obtains from a direct solver.
 """
 from .matrices import (laplace2d, diffusion3d_7pt, shifted_laplace2d_indefinite,
-                       random_dd_symmetric, stencil27_3d, kkt_matrix, dodd, covariance_grid)
+                       random_dd_symmetric, stencil27_3d, kkt_matrix, dodd, covariance_grid,
+                       saddle2d)
 from .ordering import rcm, nested_dissection_grid, nested_multicolor_grid, apply_symmetric_perm
 from .ildl import ildl_bk, IldlFactors
 from .exact import ShiftedLaplace2DExact
 
 __all__ = [
     "laplace2d", "diffusion3d_7pt", "shifted_laplace2d_indefinite",
-    "random_dd_symmetric", "stencil27_3d", "kkt_matrix", "dodd", "covariance_grid",
+    "random_dd_symmetric", "stencil27_3d", "kkt_matrix", "dodd", "covariance_grid", "saddle2d",
     "rcm", "nested_dissection_grid", "nested_multicolor_grid", "apply_symmetric_perm",
     "ildl_bk", "IldlFactors", "ShiftedLaplace2DExact",
 ]

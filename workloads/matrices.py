@@ -226,6 +226,62 @@ def kkt_matrix(m: int, k: int, seed: int, density: float = 0.3):
     return _csr(m + k, r, c, K[r, c])
 
 
+def saddle2d(N: int = 160, seed: int = 7, scale: float = 8.0):
+    """Sparse saddle-point matrix [[A, B^T], [B, 0]] and an ordering for it.
+
+    A: the 5-point Dirichlet Laplacian on an N x N grid (diagonal 4, N even),
+    unknowns 0 .. N^2 - 1 lexicographic (x fastest). B: one constraint per
+    2 x 2 cell (N^2 / 4 of them, unknowns N^2 + cell index, cells
+    lexicographic) coupling the cell's four grid unknowns with weights
+    s scale (0.5 + U(0, 1)), s a random sign; drawn from
+    numpy.random.default_rng(seed), cell by cell, the four corners in the order
+    (0,0), (1,0), (0,1), (1,1), the magnitude before the sign. The zero
+    diagonal of the constraints makes a symmetric indefinite matrix; with
+    couplings larger than the Laplacian's diagonal (the default scale) the
+    grid unknown a constraint meets fails the Bunch-Kaufman 1x1 test as well,
+    and the threshold factorization takes (constraint, grid unknown) 2x2
+    pivots.
+
+    Returns (K, q): q orders the cells by the nested multicolor ordering of the
+    (N/2 x N/2) cell grid, each cell's constraint first and its four grid
+    unknowns after it, so the factorization meets every constraint's zero
+    pivot beside the unknowns it couples.
+    """
+    from .ordering import nested_multicolor_grid
+    if N % 2:
+        raise ValueError("N must be even")
+    rng = np.random.default_rng(seed)
+    L2 = laplace2d(N, N, 0.0)
+    A_row = np.repeat(np.arange(N * N), np.diff(L2.indptr))
+    nu, M = N * N, N // 2
+    nc = M * M
+    cx, cy = np.meshgrid(np.arange(M), np.arange(M), indexing="xy")
+    cx, cy = cx.ravel(), cy.ravel()  # cell c = cx + M cy
+    corners = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    rows, cols, vals = [], [], []
+    draws = rng.random((nc, 4, 2))
+    for k, (dx, dy) in enumerate(corners):
+        u = (2 * cx + dx) + N * (2 * cy + dy)
+        w = scale * (0.5 + draws[:, k, 0]) * np.where(draws[:, k, 1] < 0.5, -1.0, 1.0)
+        rows += [nu + np.arange(nc), u]
+        cols += [u, nu + np.arange(nc)]
+        vals += [w, w]
+    r = np.concatenate([A_row] + rows)
+    c = np.concatenate([L2.indices.astype(np.int64)] + cols)
+    v = np.concatenate([L2.data] + vals)
+    K = _csr(nu + nc, r, c, v)
+    cell_order = nested_multicolor_grid((M, M))
+    q = np.empty(nu + nc, np.int64)
+    pos = 0
+    for c0 in cell_order:
+        x, y = c0 % M, c0 // M
+        q[pos] = nu + c0
+        for dx, dy in corners:
+            q[pos + 1 + (dx + 2 * dy)] = (2 * x + dx) + N * (2 * y + dy)
+        pos += 5
+    return K, q
+
+
 def dodd(A) -> float:
     """Degree of diagonal dominance min_i |a_ii| / sum_{j != i} |a_ij| (Section 3.2)."""
     A = sp.csr_matrix(A)
