@@ -131,6 +131,8 @@ def main():
                              "covariance200", "randdd"])
     ap.add_argument("--grid", type=int, default=None, help="grid size (default 64, 512, 128 per workload)")
     ap.add_argument("--tau", type=float, default=1e-3)
+    ap.add_argument("--randdd-set", default="full", choices=["full", "small"],
+                    help="random dominant set: all 256 seeds (192/32/32) or the 48 smallest (32/8/8)")
     ap.add_argument("--taus", default="1e-3,3e-4,1e-4",
                     help="drop tolerances of the equal-error comparison (the loosest is Mix's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1425,34 +1427,50 @@ def run_covariance(args):
 
 def run_randdd(args):
     """The random diagonally dominant set (strictly dominant, about 10
-    off-diagonals per row, RCM order): of seeds 0-255 the 48 with the
-    smallest n (their tight factors stay within minutes of host ILDL), by
-    seed: 32 train, 8 validation, 8 test. Loose factor ILDL tau = 1e-2 (Mix
-    as the network's input), tight tau = 1e-4 (SelInv as its target). The
-    test gain is reported against the tight SelInv and against the dense
-    inverse of each test matrix on its pattern S; value = entries of S per
-    second of the device pipeline (SelInv, NInv, then Mix and the learned
-    correction in one pass) summed over the test matrices."""
+    off-diagonals per row, RCM order), seeds 0-255 with n drawn from
+    [2,000, 20,000]: seeds 0-191 train, 192-223 validate, 224-255 test
+    (--randdd-set small: the 48 with the smallest n, by seed 32 / 8 / 8).
+    Loose factor ILDL tau = 1e-2 (Mix as the network's input), tight tau =
+    1e-4 (SelInv as its target), both by the host threshold ILDL-BK in a pool
+    of worker processes while the device builds the samples. The test gain is
+    reported against the tight SelInv on every test matrix and against the
+    dense inverse of the 8 smallest test matrices on their pattern S; value =
+    entries of S per second of the device pipeline (SelInv, NInv, then Mix
+    and the learned correction in one pass) summed over those 8."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor, as_completed
+
     import numpy as np
     import torch
 
     from oracle import core as oc
     from paper_2609_11363_amd import Solver, learned, upload_factors
     from workloads import ildl_bk, random_dd_symmetric, rcm
+    from workloads.ildl import random_dd_factors
 
     tau_l, tau_t, p, delta, eps = 1e-2, 1e-4, 3, 0.1, 1e-2
-    sizes = sorted((int(np.random.default_rng(sd).integers(2000, 20001)), sd) for sd in range(256))
-    seeds = sorted(sd for _, sd in sizes[:48])
-    groups = {"train": seeds[:32], "val": seeds[32:40], "test": seeds[40:]}
+    size = {sd: int(np.random.default_rng(sd).integers(2000, 20001)) for sd in range(256)}
+    if args.randdd_set == "small":
+        seeds = sorted(sorted(size, key=lambda sd: (size[sd], sd))[:48])
+        groups = {"train": seeds[:32], "val": seeds[32:40], "test": seeds[40:]}
+    else:
+        groups = {"train": list(range(192)), "val": list(range(192, 224)), "test": list(range(224, 256))}
+    order = sorted((sd for ss in groups.values() for sd in ss), key=lambda sd: -size[sd])  # largest first
+    workers = max(1, min(16, os.cpu_count() or 1))
     t0 = time.time()
-    samples = {}
-    for name, ss in groups.items():
-        samples[name] = []
-        for sd in ss:
-            A = random_dd_symmetric(sd)
-            samples[name].append(learned.build_sample(A, rcm(A), tau_loose=tau_l, tau_tight=tau_t, p=p,
-                                                      delta=delta, eps=eps))
-            log(f"{name} seed {sd}: {samples[name][-1].meta} ({time.time() - t0:.0f}s)")
+    by_seed = {}
+    # the worker processes are started (spawned, not forked) before this
+    # process touches the GPU; they only run the host factorization
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        futs = [ex.submit(random_dd_factors, sd, (tau_l, tau_t)) for sd in order]
+        for k, fut in enumerate(as_completed(futs)):
+            sd, A, q, (Fl, Ft) = fut.result()
+            smp = learned.build_sample(A, q, tau_loose=tau_l, tau_tight=tau_t, p=p, delta=delta, eps=eps,
+                                       ildl=lambda A_, q_, tau, Fl=Fl, Ft=Ft: Fl if tau == tau_l else Ft)
+            smp.meta["seed"] = sd
+            by_seed[sd] = smp
+            log(f"sample {k + 1}/{len(order)} seed {sd}: {smp.meta} ({time.time() - t0:.0f}s)")
+    samples = {name: [by_seed[sd] for sd in ss] for name, ss in groups.items()}
     t_data = time.time() - t0
     t0 = time.time()
     packed, _, hist = learned.train(samples["train"], samples["val"], epochs=args.learned_epochs, lr=1e-3,
@@ -1463,12 +1481,16 @@ def run_randdd(args):
     got = learned.mean_error(test, packed) if packed is not None else base
     log(f"held-out vs SelInv(tau={tau_t:g}): Mix {base[0]:.3e} -> Mix+learned {got[0]:.3e} "
         f"(gain {base[0] / got[0]:.2f}x)")
+    dense_seeds = sorted(sorted(groups["test"], key=lambda sd: (size[sd], sd))[:8])
+    for smp in samples["train"] + samples["val"]:
+        del smp.solver
 
     # against the dense inverse, on every entry of each test matrix's S, and
     # the device pipeline's time
     dev = torch.device("cuda", 0)
     err_mix, err_ml, tot_entries, tot_ms = [], [], 0, 0.0
-    for sd, smp in zip(groups["test"], test):
+    for sd in dense_seeds:
+        smp = by_seed[sd]
         A = random_dd_symmetric(sd)
         F = ildl_bk(A, rcm(A), tau_l)
         s = Solver(0)
@@ -1518,14 +1540,19 @@ def run_randdd(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "random sparse strictly diagonally dominant set (about 10 off-diagonals per "
-                               "row, RCM): of seeds 0-255 the 48 with the smallest n, by seed 32 train / 8 "
-                               f"validation / 8 test; ILDL tau={tau_l:g} (Mix, the network's input) and "
-                               f"{tau_t:g} (SelInv, its target); a step runs the device pipeline on each test "
-                               "matrix once (SelInv with NInv beside it, then Mix and the learned correction "
-                               "in one pass)",
-                   "n_test": [int(x.meta["n"]) for x in test], "nnz_S_test": tot_entries,
-                   "parallelism": "single GPU"},
+                               "row, RCM), " + ("seeds 0-255 (n in [2,000, 20,000]): 192 train / 32 validation / "
+                                                 "32 test" if args.randdd_set == "full" else
+                                                 "of seeds 0-255 the 48 with the smallest n, by seed 32 train / "
+                                                 "8 validation / 8 test") +
+                               f"; host ILDL-BK tau={tau_l:g} (Mix, the network's input) and {tau_t:g} (SelInv, "
+                               "its target); a step runs the device pipeline once on each of the 8 smallest test "
+                               "matrices (SelInv with NInv beside it, then Mix and the learned correction in one "
+                               "pass)",
+                   "n_test": [int(x.meta["n"]) for x in test], "n_timed": [size[sd] for sd in dense_seeds],
+                   "nnz_S_timed": tot_entries, "parallelism": "single GPU"},
         "learned": {"train_seeds": groups["train"], "val_seeds": groups["val"], "test_seeds": groups["test"],
+                    "dense_inverse_seeds": dense_seeds, "factor_workers": workers,
+                    "nnz_S_tight_max": int(max(x.meta["nnz_S_tight"] for x in test)),
                     "train_rows": int(sum(len(x.target) for x in samples["train"])), "data_s": t_data,
                     "train_s": t_train, "epochs": args.learned_epochs, "fallback_to_mix": packed is None,
                     "test_mean_entry_error_vs_tight_selinv": {"mix": base[0], "mix_learned": got[0],
@@ -1538,7 +1565,7 @@ def run_randdd(args):
                                                               "mix_learned": float(np.quantile(eml, 0.99))}},
     }
     if not args.no_cpu_baseline:
-        sd = groups["test"][0]
+        sd = dense_seeds[0]
         A = random_dd_symmetric(sd)
         F = ildl_bk(A, rcm(A), tau_l)
         S = oc.pattern(F)

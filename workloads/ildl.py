@@ -170,3 +170,15 @@ def ildl_bk(A, q=None, tau: float = 1e-3, pivoting: bool = True, progress: bool 
     return IldlFactors(n=n, perm=perm, L_rowptr=L_rowptr, L_col=L_col, L_val=L_val,
                        d_diag=d_diag, d_sub=d_sub, piv=piv, tau=float(tau),
                        n_perturbed=npert, n_2x2=n2)
+
+
+def random_dd_factors(seed: int, taus):
+    """The random dominant matrix of `seed` (`random_dd_symmetric`), its RCM
+    ordering and its threshold ILDL-BK at each tau in `taus`: a module-level
+    function, so that process pools can produce a set of matrices in
+    parallel. Returns (seed, A, q, [factors])."""
+    from .matrices import random_dd_symmetric
+    from .ordering import rcm
+    A = random_dd_symmetric(seed)
+    q = rcm(A)
+    return seed, A, q, [ildl_bk(A, q, t) for t in taus]
