@@ -418,24 +418,10 @@ __global__ __launch_bounds__(64 * kFwdWaves, 4) void k_mlp_correct(MlpFeatParams
     load_mlp_regs(W, col, g, R, sb, sw);
     const NodeRec *node = reinterpret_cast<const NodeRec *>(P.node);
     const int64_t ntiles = (P.nnz + 63) / 64;
-    // Tiles in XCD-major order: workgroup b runs on XCD b % 8 (workgroups are
-    // handed to the 8 XCDs in turn); the workgroups of one XCD take a
-    // contiguous eighth of the tiles and stride over it, so the rows an XCD
-    // works on at any time are neighbours whose columns share node records
-    // (and the lines of that XCD's L2). With fewer than 8 workgroups, one range.
-    int64_t tile, t_end, stride;
-    if (gridDim.x >= 8) {
-        const int32_t x = blockIdx.x & 7, nx = ((int32_t)gridDim.x - x + 7) / 8;
-        t_end = ntiles * (x + 1) / 8;
-        stride = (int64_t)nx * kFwdWaves;
-        tile = ntiles * x / 8 + (int64_t)(blockIdx.x >> 3) * kFwdWaves + w;
-    } else {
-        t_end = ntiles;
-        stride = (int64_t)gridDim.x * kFwdWaves;
-        tile = (int64_t)blockIdx.x * kFwdWaves + w;
-    }
+    const int64_t stride = (int64_t)gridDim.x * kFwdWaves;
+    int64_t tile = (int64_t)blockIdx.x * kFwdWaves + w;
     int32_t ci = 0, cj = 0, cu = -1;
-    if (tile < t_end) {
+    {
         const int64_t p = tile * 64 + lane;
         if (p < P.nnz) {
             ci = P.srow[p];
@@ -443,7 +429,7 @@ __global__ __launch_bounds__(64 * kFwdWaves, 4) void k_mlp_correct(MlpFeatParams
             cu = P.s2u[p];
         }
     }
-    for (; tile < t_end; tile += stride) {
+    for (; tile < ntiles; tile += stride) {
         const int64_t p = tile * 64 + lane;
         const bool valid = p < P.nnz;
         NodeRec ni{}, nj{};
@@ -461,7 +447,7 @@ __global__ __launch_bounds__(64 * kFwdWaves, 4) void k_mlp_correct(MlpFeatParams
         }
         const int32_t i = ci, j = cj;
         const int64_t pn = p + stride * 64;
-        if (tile + stride < t_end && pn < P.nnz) {
+        if (pn < P.nnz) {
             ci = P.srow[pn];
             cj = P.col[pn];
             cu = P.s2u[pn];
