@@ -656,6 +656,8 @@ def run_stencil27(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (L2 <-> memory, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "traffic_source": STENCIL_TRAFFIC["profile"] if traffic else None,
+                     "traffic_gbs": (traffic / (avg_ms * 1e-3) / 1e9) if traffic else None,
+                     "traffic_frac_of_copy": (traffic / (avg_ms * 1e-3) / 1e9 / copy_gbs) if traffic else None,
                      "precision": prec,
                      "launches_per_step": launches // 3, "avg_launch_ms": avg_ms,
                      "alg_bytes_per_launch": tot_bytes / max(launches, 1),
