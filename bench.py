@@ -131,6 +131,8 @@ def main():
                              "covariance200", "randdd"])
     ap.add_argument("--grid", type=int, default=None, help="grid size (default 64, 512, 128 per workload)")
     ap.add_argument("--tau", type=float, default=1e-3)
+    ap.add_argument("--learned-grids", default="large", choices=["large", "small"],
+                    help="27-point training grids: 16^3-28^3 (held-out 32^3) or 12^3-18^3 (held-out 20^3)")
     ap.add_argument("--randdd-set", default="full", choices=["full", "small"],
                     help="random dominant set: all 256 seeds (192/32/32) or the 48 smallest (32/8/8)")
     ap.add_argument("--taus", default="1e-3,3e-4,1e-4",
@@ -451,16 +453,26 @@ def train_learned(args, tau, p, delta, eps, family="diffusion7"):
         val_spec, test_spec = (20, 16), (24, 17)
         desc = ("3D 7-point lognormal(0,1) diffusion: 16^3 x2, 20^3 x2, 24^3 (seeds 11-15); validation "
                 "20^3 (seed 16); held-out test 24^3 (seed 17)")
-    else:
+    elif args.learned_grids == "small":
         gen = lambda Ng, sd: stencil27_3d(Ng, 0.5, sd)  # noqa: E731
         specs = [(12, 21), (14, 22), (14, 23), (16, 24), (18, 25)]
         val_spec, test_spec = (16, 26), (20, 27)
         desc = ("3D 27-point lognormal(0,0.5) stencil: 12^3, 14^3 x2, 16^3, 18^3 (seeds 21-25); "
                 "validation 16^3 (seed 26); held-out test 20^3 (seed 27)")
+    else:
+        gen = lambda Ng, sd: stencil27_3d(Ng, 0.5, sd)  # noqa: E731
+        specs = [(16, 21), (20, 22), (24, 23), (24, 24), (28, 25)]
+        val_spec, test_spec = (24, 26), (32, 27)
+        desc = ("3D 27-point lognormal(0,0.5) stencil: 16^3, 20^3, 24^3 x2, 28^3 (seeds 21-25); "
+                "validation 24^3 (seed 26); held-out test 32^3 (seed 27); factors on the device")
+
+    # the 27-point family's factors come from the device factorization (the
+    # host one for the 7-point family, whose grids are small)
+    ildl = (lambda A, q, t: factorize(A, q, t, "device")[0]) if family != "diffusion7" else None
 
     def sample(Ng, seed):
         return learned.build_sample(gen(Ng, seed), nested_multicolor_grid((Ng, Ng, Ng)), tau_loose=tau,
-                                    tau_tight=tau / 10, p=p, delta=delta, eps=eps)
+                                    tau_tight=tau / 10, p=p, delta=delta, eps=eps, ildl=ildl)
 
     t0 = time.time()
     train = [sample(Ng, sd) for Ng, sd in specs]
