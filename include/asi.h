@@ -433,9 +433,13 @@ asi_status asi_pcg(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, 
  * synchrony and workspace use as for asi_pcg. The quasi-residual bound
  * sqrt(k + 1) tau_k decides when the true residual ||b - Ah x||_2 is
  * computed; the call stops when that is <= tol ||b||_2 or after maxit
- * steps (*relres is then the last true residual computed). A near-breakdown
- * (a vanishing rho or sigma, or a quasi-residual that is no longer finite)
- * restarts the method from the last iterate; ASI_E_NONFINITE after 8
+ * steps (*relres is then the last true residual computed). When that true
+ * residual is still above tol ||b||_2 (the recursion's residual has drifted
+ * from it, as happens near the attainable accuracy of an ill-conditioned
+ * Ah) the method restarts from the iterate on the true residual, and again
+ * whenever the same happens, within the maxit steps. A near-breakdown (a
+ * vanishing rho or sigma, or a quasi-residual that is no longer finite)
+ * restarts it from the last iterate too; ASI_E_NONFINITE after 8 such
  * restarts.
  */
 asi_status asi_sqmr(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col, const double *A_val,

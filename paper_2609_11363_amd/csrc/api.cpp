@@ -1730,6 +1730,16 @@ asi_status asi_sqmr(asi_handle h, const int64_t *A_rowptr, const int32_t *A_col,
             if (e != hipSuccess) return hip_fail(h, e, "sqmr residual");
             res = std::sqrt(tr2) / bnorm;
             if (res <= tol) break;
+            if (it < maxit) {
+                // the recursion's residual has drifted from the true one (it
+                // stalls near the attainable accuracy, eps times the condition
+                // of Ah): start a fresh recursion from the iterate, on the true
+                // residual; this is no breakdown and is not counted as one
+                e = restart();
+                if (e != hipSuccess) return hip_fail(h, e, "sqmr restart");
+                since = 0;
+                continue;
+            }
         }
         {
             Trace tr(h, ASI_K_DIAG, 0.0);
@@ -2024,7 +2034,10 @@ static asi_status block_krylov_run(asi_handle h, int method, const int64_t *A_ro
             for (int32_t v = 0; v < nv; ++v) {
                 if (!need_true[v]) continue;
                 relres[v] = std::sqrt(hs[5 * nv + v]) / bn[v];
-                if (relres[v] <= tol) act[v] = 0;
+                if (relres[v] <= tol)
+                    act[v] = 0;
+                else if (it < maxit)
+                    need_restart[v] = 1;  // stalled recursion: a fresh one from the iterate, as in asi_sqmr
             }
         }
         if (!any_active()) break;
