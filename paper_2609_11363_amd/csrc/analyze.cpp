@@ -382,6 +382,37 @@ int analyze(int32_t n, const int64_t *Lp, const int32_t *Li, const int8_t *piv, 
             meta[s] = m;
         }
     }
+    // the preconditioner solves' rows, level by level
+    A.solve_fwd.clear();
+    A.solve_bwd.clear();
+    A.lvl_rows.assign(A.n_levels + 1, 0);
+    if (!A.s2u.empty()) {
+        A.solve_fwd.reserve(n);
+        A.solve_bwd.reserve(n);
+        for (int32_t l = 0; l < A.n_levels; ++l) {
+            for (int k = 0; k < 2; ++k) {
+                const std::vector<int32_t> &sched = k == 0 ? A.sched_small : A.sched_big;
+                const std::vector<int32_t> &off = k == 0 ? A.lvl_small : A.lvl_big;
+                for (int32_t s = off[l]; s < off[l + 1]; ++s) {
+                    const int32_t j = sched[s];
+                    const bool two = piv[j] == 1;
+                    for (int t = 0; t < (two ? 2 : 1); ++t) {
+                        const int32_t i = j + t;
+                        const int64_t dp = A.diagpos[i];
+                        // the partner (j + 1 - t) sits next to the diagonal: last of
+                        // the lower part for the second row, first of the upper
+                        // part for the first
+                        int64_t skf = -1, skb = -1;
+                        if (two && t == 1 && dp > A.rowptr[i] && A.col[dp - 1] == j) skf = dp - 1;
+                        if (two && t == 0 && dp + 1 < A.rowptr[i + 1] && A.col[dp + 1] == j + 1) skb = dp + 1;
+                        A.solve_fwd.push_back({i, (int32_t)A.rowptr[i], (int32_t)dp, (int32_t)skf});
+                        A.solve_bwd.push_back({i, (int32_t)(dp + 1), (int32_t)A.rowptr[i + 1], (int32_t)skb});
+                    }
+                }
+            }
+            A.lvl_rows[l + 1] = (int32_t)A.solve_fwd.size();
+        }
+    }
     return OK;
 }
 

@@ -53,6 +53,7 @@ struct asi_handle_s {
     double *cg = nullptr;  // Krylov work vectors (5 n), dot partials (1024), scalars (16)
     double *Ls = nullptr;         // L(max(i, j), min(i, j)) at every position of S (0 where L has none)
     double *Lcsr = nullptr;       // the loaded factor's L values in the input's row order
+    asi::SolveRow *solve_fwd = nullptr, *solve_bwd = nullptr;  // preconditioner solve rows, level order
     bool rows_aligned = false;    // row i of L is the lower part of row i of S (the 2x2 (i, i-1) entry aside)
     bool ls_loaded = false;       // Ls holds the loaded factor's values
     double *rn = nullptr;         // ||L(i, :)||_2, then ||L(:, i)||_2, of the factor in Lu (set with it)
@@ -192,6 +193,8 @@ Layout make_layout(const asi::Analysis &A) {
     L.add((5 * n + 1024 + 16) * 8);     // 41 Krylov solves: 5 vectors, dot partials, scalars
     L.add(A.s2u.size() * 8);            // 42 L values in S's order (preconditioner solves)
     L.add(A.nnzL * 8);                  // 43 L values in the input's row order (copied with the factor)
+    L.add(A.solve_fwd.size() * 16);     // 44 preconditioner solve rows, forward
+    L.add(A.solve_bwd.size() * 16);     // 45   backward
     return L;
 }
 
@@ -390,6 +393,8 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
     h->Ls = at<double>(b, L.off[42]);
     h->ls_loaded = false;
     h->Lcsr = at<double>(b, L.off[43]);
+    h->solve_fwd = at<asi::SolveRow>(b, L.off[44]);
+    h->solve_bwd = at<asi::SolveRow>(b, L.off[45]);
     h->factor_loaded = false;
     h->lf_loaded = false;
     h->epoch = 0;
@@ -427,6 +432,8 @@ asi_status asi_set_workspace(asi_handle h, void *dev_ws, size_t bytes) {
         {h->meta_big, A.meta_big.data(), A.meta_big.size() * 64},
         {h->rowptr_L, A.L_rowptr.data(), A.L_rowptr.size() * 8},
         {h->s2u, A.s2u.data(), A.s2u.size() * 4},
+        {h->solve_fwd, A.solve_fwd.data(), A.solve_fwd.size() * 16},
+        {h->solve_bwd, A.solve_bwd.data(), A.solve_bwd.size() * 16},
     };
     for (auto &u : ups) {
         if (u.bytes == 0) continue;
@@ -1508,12 +1515,9 @@ static asi::LdlSolveParams ldl_params(asi_handle h) {
     asi::LdlSolveParams P{};
     P.n = A.n;
     P.n_levels = A.n_levels;
-    P.lvl_small = A.lvl_small.data();
-    P.lvl_big = A.lvl_big.data();
-    P.meta_small = h->meta_small;
-    P.meta_big = h->meta_big;
-    P.rowptr = h->rowptr;
-    P.diagpos = h->diagpos;
+    P.lvl_rows = A.lvl_rows.data();
+    P.rows_fwd = h->solve_fwd;
+    P.rows_bwd = h->solve_bwd;
     P.col = h->col;
     P.Ls = h->Ls;
     P.piv = h->piv;

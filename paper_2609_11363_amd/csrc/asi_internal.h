@@ -25,6 +25,15 @@ struct BlockMeta {
 };
 static_assert(sizeof(BlockMeta) == 64, "block records are 64 bytes");
 
+// One row of a level of the preconditioner solves (forward: the lower part
+// of row i of S, backward: its upper part): v_i -= sum of L v over the S
+// positions [p0, p1), but for position skip (the other row of a 2x2 block,
+// an explicit zero of L; -1 if none).
+struct SolveRow {
+    int32_t i, p0, p1, skip;
+};
+static_assert(sizeof(SolveRow) == 16, "solve rows are 16 bytes");
+
 // Kernel limits (the analysis refuses patterns above them).
 constexpr int kSmallCols = 128;   // |R_J| handled by one wavefront per block
 constexpr int kBigCols = 2048;    // |R_J| handled by one 256-thread workgroup per block
@@ -78,6 +87,11 @@ struct Analysis {
     std::vector<int32_t> lvl_maxc_big;        // per level: largest |R_J| of its large blocks
     std::vector<int32_t> lvl_heavy;           // per level: small blocks with more than kHeavyHits hits
                                               // (placed first in the level's small schedule)
+    // rows of the preconditioner solves in level order (each level's blocks
+    // as in the two schedules, both rows of a 2x2 block); empty when
+    // |S| >= 2^31, where the solves are not offered
+    std::vector<SolveRow> solve_fwd, solve_bwd;
+    std::vector<int32_t> lvl_rows;            // n_levels+1 offsets into them
     int64_t gather_pairs = 0;
     int64_t gather_hits = 0;
     // algorithmic bytes of each level's launches, [0] float64 mode, [1] mixed

@@ -287,9 +287,8 @@ hipError_t ildlt_set_limits();
 
 struct LdlSolveParams {
     int32_t n, n_levels;
-    const int32_t *lvl_small, *lvl_big;  // host: per-level offsets into the block records
-    const BlockMeta *meta_small, *meta_big;
-    const int64_t *rowptr, *diagpos;
+    const int32_t *lvl_rows;             // host: per-level offsets into the row records
+    const SolveRow *rows_fwd, *rows_bwd;  // the rows of each level, forward and backward substitution
     const int32_t *col;
     const double *Ls;  // float64 L(max(i, j), min(i, j)) at every position of S
     const int8_t *piv;

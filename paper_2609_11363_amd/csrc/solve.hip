@@ -62,38 +62,6 @@ __global__ __launch_bounds__(256) void k_spmv_ahat(int32_t n, const int64_t *__r
     if (i < n && sub == 0) y[i] = s;
 }
 
-// One level of the forward (FWD) or backward substitution, in place on v,
-// kSeg lanes per block (both rows of a 2x2 block in turn). Forward: row i
-// subtracts L(i, c) v_c over the lower part of row i of S; backward: row k
-// subtracts L(r, k) v_r over its upper part. The 2x2 partner entry (an
-// explicit zero of L, in the same level) is skipped.
-template <bool FWD>
-__global__ __launch_bounds__(256) void k_ldl_level(const BlockMeta *__restrict__ ma, int32_t na,
-                                                   const BlockMeta *__restrict__ mb, int32_t nb,
-                                                   const int64_t *__restrict__ rowptr,
-                                                   const int64_t *__restrict__ diagpos,
-                                                   const int32_t *__restrict__ col, const double *__restrict__ Ls,
-                                                   double *__restrict__ v) {
-    const int32_t b = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
-    const int sub = threadIdx.x % kSeg;
-    if (b >= na + nb) return;  // the segment's lanes leave together
-    const BlockMeta &M = b < na ? ma[b] : mb[b - na];
-    const int rows = M.two ? 2 : 1;
-    for (int t = 0; t < rows; ++t) {
-        const int32_t i = M.j + t;
-        const int32_t partner = M.two ? M.j + 1 - t : -1;
-        const int64_t p0 = FWD ? rowptr[i] : diagpos[i] + 1;
-        const int64_t p1 = FWD ? diagpos[i] : rowptr[i + 1];
-        double s = 0.0;
-        for (int64_t p = p0 + sub; p < p1; p += kSeg) {
-            const int32_t c = col[p];
-            if (c != partner) s += Ls[p] * v[c];
-        }
-        s = seg_sum(s);
-        if (sub == 0) v[i] -= s;
-    }
-}
-
 // d_i = (Z Ah)_ii = sum_k Z_ik Ah_ki over k in row i of S and of Ah (Ah
 // symmetric, so Ah_ki = Ah_ik): row perm[i] of A is walked, each column
 // mapped to the factor ordering and searched in the sorted row i of S
@@ -248,42 +216,42 @@ __device__ inline void load_run(const double *__restrict__ src, double (&x)[NV])
     }
 }
 
-template <bool FWD, int NV>
-__global__ __launch_bounds__(256) void k_ldl_level_m(const BlockMeta *__restrict__ ma, int32_t na,
-                                                     const BlockMeta *__restrict__ mb, int32_t nb,
-                                                     const int64_t *__restrict__ rowptr,
-                                                     const int64_t *__restrict__ diagpos,
-                                                     const int32_t *__restrict__ col, const double *__restrict__ Ls,
-                                                     double *__restrict__ V) {
+// One level of the forward or backward substitution, in place on V: kSeg
+// lanes per row record (the level's rows are consecutive records, so a
+// segment starts from one 16-byte load). Row i subtracts L v over its range
+// of S positions (forward: the lower part of row i, L(i, c) v_c; backward:
+// the upper part, L(r, i) v_r), the 2x2 partner's position skipped. v_i is
+// read beside the gathers: no other row of the level writes it, and the
+// rows gathered were finished by earlier levels. NV = 1 is the one-vector
+// solve.
+template <int NV>
+__global__ __launch_bounds__(256) void k_ldl_rows(const SolveRow *__restrict__ rows, int32_t nr,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ Ls,
+                                                  double *__restrict__ V) {
     const int32_t b = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg);
     const int sub = threadIdx.x % kSeg;
-    if (b >= na + nb) return;
-    const BlockMeta &M = b < na ? ma[b] : mb[b - na];
-    const int rows = M.two ? 2 : 1;
-    for (int t = 0; t < rows; ++t) {
-        const int32_t i = M.j + t;
-        const int32_t partner = M.two ? M.j + 1 - t : -1;
-        const int64_t p0 = FWD ? rowptr[i] : diagpos[i] + 1;
-        const int64_t p1 = FWD ? diagpos[i] : rowptr[i + 1];
-        double s[NV];
+    if (b >= nr) return;  // the segment's lanes leave together
+    const SolveRow R = rows[b];
+    const int64_t vi = (int64_t)R.i * NV;
+    const double own = sub < NV ? V[vi + sub] : 0.0;
+    double s[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) s[v] = 0.0;
-        for (int64_t p = p0 + sub; p < p1; p += kSeg) {
-            const int32_t c = col[p];
-            if (c != partner) {
-                const double l = Ls[p];
-                double x[NV];
-                load_run<NV>(V + (int64_t)c * NV, x);
+    for (int v = 0; v < NV; ++v) s[v] = 0.0;
+    for (int32_t p = R.p0 + sub; p < R.p1; p += kSeg) {
+        if (p == R.skip) continue;
+        const double l = Ls[p];
+        double x[NV];
+        load_run<NV>(V + (int64_t)col[p] * NV, x);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) s[v] += l * x[v];
-            }
-        }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            s[v] = seg_sum(s[v]);
-            if (sub == v) V[(int64_t)i * NV + v] -= s[v];
-        }
+        for (int v = 0; v < NV; ++v) s[v] += l * x[v];
     }
+    double mine = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        s[v] = seg_sum(s[v]);
+        if (sub == v) mine = s[v];
+    }
+    if (sub < NV) V[vi + sub] = own - mine;
 }
 
 __global__ void k_ldl_diag_m(int32_t n, int32_t nv, const int8_t *__restrict__ piv, const double *__restrict__ dinv,
@@ -492,18 +460,17 @@ hipError_t launch_ldl_solve(const LdlSolveParams &P, const double *x, double *v,
     if (x != v) hipLaunchKernelGGL(dev::k_copy_f64, elem_grid(n), dim3(256), 0, st, (int64_t)n, x, v);
     // forward: levels last to first (a row's lower entries belong to blocks of higher levels)
     for (int32_t l = P.n_levels - 1; l >= 0; --l) {
-        const int32_t na = P.lvl_small[l + 1] - P.lvl_small[l], nb = P.lvl_big[l + 1] - P.lvl_big[l];
-        if (na + nb == 0) continue;
-        hipLaunchKernelGGL(dev::k_ldl_level<true>, seg_grid(na + nb), dim3(256), 0, st, P.meta_small + P.lvl_small[l],
-                           na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos, P.col, P.Ls, v);
+        const int32_t nr = P.lvl_rows[l + 1] - P.lvl_rows[l];
+        if (nr == 0) continue;
+        hipLaunchKernelGGL(dev::k_ldl_rows<1>, seg_grid(nr), dim3(256), 0, st, P.rows_fwd + P.lvl_rows[l], nr, P.col,
+                           P.Ls, v);
     }
     hipLaunchKernelGGL(dev::k_ldl_diag, elem_grid(n), dim3(256), 0, st, n, P.piv, P.dinv, v);
     for (int32_t l = 0; l < P.n_levels; ++l) {
-        const int32_t na = P.lvl_small[l + 1] - P.lvl_small[l], nb = P.lvl_big[l + 1] - P.lvl_big[l];
-        if (na + nb == 0) continue;
-        hipLaunchKernelGGL(dev::k_ldl_level<false>, seg_grid(na + nb), dim3(256), 0, st,
-                           P.meta_small + P.lvl_small[l], na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos,
-                           P.col, P.Ls, v);
+        const int32_t nr = P.lvl_rows[l + 1] - P.lvl_rows[l];
+        if (nr == 0) continue;
+        hipLaunchKernelGGL(dev::k_ldl_rows<1>, seg_grid(nr), dim3(256), 0, st, P.rows_bwd + P.lvl_rows[l], nr, P.col,
+                           P.Ls, v);
     }
     return hipGetLastError();
 }
@@ -571,22 +538,20 @@ hipError_t launch_ldl_solve_m(const LdlSolveParams &P, int32_t nv, const double 
     if (nv < 1 || nv > kMaxRhs) return hipErrorInvalidValue;
     if (x != V) hipLaunchKernelGGL(dev::k_copy_f64, elem_grid((int64_t)n * nv), dim3(256), 0, st, (int64_t)n * nv, x, V);
     for (int32_t l = P.n_levels - 1; l >= 0; --l) {
-        const int32_t na = P.lvl_small[l + 1] - P.lvl_small[l], nb = P.lvl_big[l + 1] - P.lvl_big[l];
-        if (na + nb == 0) continue;
+        const int32_t nr = P.lvl_rows[l + 1] - P.lvl_rows[l];
+        if (nr == 0) continue;
 #define ASI_FWD(K)                                                                                                    \
-    hipLaunchKernelGGL((dev::k_ldl_level_m<true, K>), seg_grid(na + nb), dim3(256), 0, st,                           \
-                       P.meta_small + P.lvl_small[l], na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos, P.col, \
+    hipLaunchKernelGGL((dev::k_ldl_rows<K>), seg_grid(nr), dim3(256), 0, st, P.rows_fwd + P.lvl_rows[l], nr, P.col,  \
                        P.Ls, V)
         ASI_NV_SWITCH(nv, ASI_FWD)
 #undef ASI_FWD
     }
     hipLaunchKernelGGL(dev::k_ldl_diag_m, elem_grid((int64_t)n * nv), dim3(256), 0, st, n, nv, P.piv, P.dinv, V);
     for (int32_t l = 0; l < P.n_levels; ++l) {
-        const int32_t na = P.lvl_small[l + 1] - P.lvl_small[l], nb = P.lvl_big[l + 1] - P.lvl_big[l];
-        if (na + nb == 0) continue;
+        const int32_t nr = P.lvl_rows[l + 1] - P.lvl_rows[l];
+        if (nr == 0) continue;
 #define ASI_BWD(K)                                                                                                    \
-    hipLaunchKernelGGL((dev::k_ldl_level_m<false, K>), seg_grid(na + nb), dim3(256), 0, st,                          \
-                       P.meta_small + P.lvl_small[l], na, P.meta_big + P.lvl_big[l], nb, P.rowptr, P.diagpos, P.col, \
+    hipLaunchKernelGGL((dev::k_ldl_rows<K>), seg_grid(nr), dim3(256), 0, st, P.rows_bwd + P.lvl_rows[l], nr, P.col,  \
                        P.Ls, V)
         ASI_NV_SWITCH(nv, ASI_BWD)
 #undef ASI_BWD

@@ -163,6 +163,47 @@ def test_sqmr(name):
     assert err <= 1e-11 * cond * 10
 
 
+def test_sqmr_restarts_when_the_true_residual_stalls():
+    """A right-hand side made of the eigenvectors of Ah nearest zero (an
+    indefinite 48 x 48 shifted Laplacian, condition ~2e3) and a tolerance
+    close to the attainable accuracy: the recursion's quasi-residual keeps
+    falling while the true residual stalls just above 1e-12, so without a
+    fresh recursion from the iterate SQMR never meets the tolerance (a
+    float64 host run of the same steps stalls for 2,000 steps; with the
+    restart it stops after 150). The block form takes the same restarts:
+    each of its columns equals the one-vector solve bit for bit."""
+    import torch
+    from paper_2609_11363_amd import Solver, upload_factors
+    from workloads import shifted_laplace2d_indefinite
+    A, _ = shifted_laplace2d_indefinite(48, 20)
+    F = ildl_bk(A, nested_multicolor_grid((48, 48)), 1e-2)
+    Ah = oc.permuted(A, F.perm)
+    w, V = np.linalg.eigh(Ah.toarray())
+    near = np.argsort(np.abs(w))[:8]
+    rng = np.random.default_rng(3)
+    B = np.stack([V[:, near] @ rng.standard_normal(8) + 1e-3 * rng.standard_normal(F.n) for _ in range(3)])
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    s.load_factor(*upload_factors(F))
+    dev = s.device
+    Ar = torch.as_tensor(A.indptr.astype(np.int64), device=dev)
+    Ac = torch.as_tensor(A.indices.astype(np.int32), device=dev)
+    Av = torch.as_tensor(A.data, device=dev)
+    perm = torch.as_tensor(F.perm.astype(np.int32), device=dev)
+    Bt = torch.as_tensor(B, device=dev)
+    tol, maxit = 1e-12, 600
+    print(f"[sqmr stall] n={F.n} cond={np.abs(w).max() / np.abs(w).min():.0f} tol={tol:g}", flush=True)
+    X, iters, rel = s.sqmr_block(Ar, Ac, Av, perm, Bt, tol=tol, maxit=maxit)
+    s.sync()
+    for v in range(3):
+        x1, it1, rr1 = s.sqmr(Ar, Ac, Av, perm, Bt[v].contiguous(), tol=tol, maxit=maxit)
+        s.sync()
+        res = np.linalg.norm(Ah @ x1.cpu().numpy() - B[v]) / np.linalg.norm(B[v])
+        print(f"  vector {v}: {it1} steps, reported {rr1:.1e}, true {res:.1e}", flush=True)
+        assert rr1 <= tol and it1 < maxit and res <= 2 * tol
+        assert torch.equal(X[v], x1) and iters[v] == it1 and rel[v] == rr1
+
+
 @pytest.mark.parametrize("name", ["cov20", "kkt"])
 def test_za_diag(name):
     import torch
