@@ -249,8 +249,7 @@ def run_diffusion(args):
     M = torch.empty_like(Z)
 
     def step(prec="fp64"):
-        s.load_factor(Lv, dd, ds)
-        s.selinv_ninv(p=p, delta=delta, precision=prec, Z=Z, N=Nn)
+        s.selinv_ninv(Lv, dd, ds, p=p, delta=delta, precision=prec, Z=Z, N=Nn)
         s.mix(Z, Nn, eps, out=M)
 
     # learned correction: trained on small grids of the same family before the
@@ -263,8 +262,7 @@ def run_diffusion(args):
         s.mlp_correct_mix(packed, Z, Nn, eps, M=M, out=ML)
 
     def full_step(prec="fp64"):
-        s.load_factor(Lv, dd, ds)
-        s.selinv_ninv(p=p, delta=delta, precision=prec, Z=Z, N=Nn)
+        s.selinv_ninv(Lv, dd, ds, p=p, delta=delta, precision=prec, Z=Z, N=Nn)
         if packed is not None:
             correct()
         else:
@@ -570,20 +568,19 @@ def run_stencil27(args):
     Z = torch.empty(nnzS, dtype=torch.float64, device=dev)
     Nn, M, ML = (torch.empty_like(Z) for _ in range(3))
 
-    # the default step's structure: the factor loaded once, NInv beside the
-    # SelInv sweep on the handle's second stream, then Mix (and the learned
-    # correction in the same pass)
+    # the default step's structure: the factor passed with the SelInv call
+    # (the sweep's copy of L made on the calling stream; the rest of the load
+    # and NInv on the handle's second stream, beside the sweep), then Mix (and
+    # the learned correction in the same pass, on the factor that call loaded)
     def mix_pipeline(prec):
-        s.load_factor(Lv, dd, ds)
-        s.selinv_ninv(p=p, delta=delta, precision=prec, Z=Z, N=Nn)
+        s.selinv_ninv(Lv, dd, ds, p=p, delta=delta, precision=prec, Z=Z, N=Nn)
         s.mix(Z, Nn, eps, out=M)
 
     def learned_pipeline(prec):
         if packed is None:
             mix_pipeline(prec)
             return
-        s.load_factor(Lv, dd, ds)
-        s.selinv_ninv(p=p, delta=delta, precision=prec, Z=Z, N=Nn)
+        s.selinv_ninv(Lv, dd, ds, p=p, delta=delta, precision=prec, Z=Z, N=Nn)
         s.mlp_correct_mix(packed, Z, Nn, eps, M=M, out=ML)
 
     for _ in range(args.warmup):
@@ -924,16 +921,14 @@ def run_equal_error(args):
             Nn, M, ML = (torch.empty_like(Z) for _ in range(3))
 
             def mix_only(prec):
-                s.load_factor(Lv, dd, ds)
-                s.selinv_ninv(p=p, delta=delta, precision=prec, Z=Z, N=Nn)
+                s.selinv_ninv(Lv, dd, ds, p=p, delta=delta, precision=prec, Z=Z, N=Nn)
                 s.mix(Z, Nn, eps, out=M)
 
             def mix_learned(prec):
                 if packed is None:
                     mix_only(prec)
                     return
-                s.load_factor(Lv, dd, ds)
-                s.selinv_ninv(p=p, delta=delta, precision=prec, Z=Z, N=Nn)
+                s.selinv_ninv(Lv, dd, ds, p=p, delta=delta, precision=prec, Z=Z, N=Nn)
                 s.mlp_correct_mix(packed, Z, Nn, eps, M=M, out=ML)
 
             # Mix and Mix + learned in both precisions (each timed, then its own
@@ -1042,9 +1037,9 @@ def run_indefinite(args):
     dC = torch.empty(F.n, dtype=torch.float64, device=dev)
 
     def base():
-        # the factor loaded once, NInv beside the SelInv sweep (second stream)
-        s.load_factor(Lv, dd, ds)
-        s.selinv_ninv(p=p, delta=delta, Z=Z, N=Nn)
+        # the factor passed with the call: the sweep's copy of L on the
+        # calling stream, the rest of the load and NInv beside the sweep
+        s.selinv_ninv(Lv, dd, ds, p=p, delta=delta, Z=Z, N=Nn)
         s.mix(Z, Nn, eps, out=M)
         s.spai(Ar, Ac, Av, perm, M, cg_iters=cg, out=R)
 
@@ -1254,8 +1249,7 @@ def run_covariance(args):
     tr = torch.empty(2, dtype=torch.float64, device=dev)
 
     def step():
-        s.load_factor(Lv, dd, ds)
-        s.selinv_ninv(p=p, delta=delta, Z=Z, N=Nn)
+        s.selinv_ninv(Lv, dd, ds, p=p, delta=delta, Z=Z, N=Nn)
         s.mix(Z, Nn, eps, out=M)
         s.spai(Ar, Ac, Av, perm, M, cg_iters=cg, out=R)
         s.diag(R, out=dR)
@@ -1515,8 +1509,7 @@ def run_randdd(args):
         Nn, M, ML = (torch.empty_like(Z) for _ in range(3))
 
         def pipeline():
-            s.load_factor(Lv, dd, ds)
-            s.selinv_ninv(p=p, delta=delta, Z=Z, N=Nn)
+            s.selinv_ninv(Lv, dd, ds, p=p, delta=delta, Z=Z, N=Nn)
             if packed is not None:
                 s.mlp_correct_mix(packed, Z, Nn, eps, M=M, out=ML)
             else:

@@ -113,10 +113,10 @@ asi_status asi_get_pattern(asi_handle h, int64_t *S_rowptr_d, int32_t *S_col_d, 
  * column layout once (the first preconditioner solve after a load also
  * copies L's values into S's order); asi_selinv, asi_ninv,
  * asi_mlp_features and asi_mlp_correct then take NULL for all three factor
- * pointers to use it
- * (a call that passes the pointers works on those instead and leaves no
- * factor loaded). The caller may reuse its buffers after the stream has
- * passed this call.
+ * pointers to use it. A call that passes the pointers loads the factor it
+ * is given the same way (replacing the loaded one), so later calls may pass
+ * NULL for it. The caller may reuse its buffers after the stream has passed
+ * this call (or that call).
  */
 asi_status asi_load_factor(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub);
 

@@ -59,7 +59,7 @@ struct asi_handle_s {
     double *rn = nullptr;         // ||L(i, :)||_2, then ||L(:, i)||_2, of the factor in Lu (set with it)
     int64_t *rowptr_L = nullptr;  // the input L's row pointers
     float *Lf = nullptr;          // float32 copy of the loaded factor's L (mixed precision)
-    bool factor_loaded = false;   // Lu (float64) and dinv hold the factor of asi_load_factor
+    bool factor_loaded = false;   // Lu (float64), dinv, the norms and the row copy hold the last factor given
     bool lf_loaded = false;       // Lf holds the float32 copy of that factor's L
     int32_t epoch = 0;
     int sweep = ASI_SWEEP_AUTO;
@@ -493,14 +493,26 @@ asi_status asi_get_pattern(asi_handle h, int64_t *S_rowptr_d, int32_t *S_col_d, 
 // u-space in the call's precision (Lu float64, Lf float32), from the given
 // arrays, or (all three NULL) from the factor of asi_load_factor. Sets *Lu to
 // the u-space values the call's kernels read.
+// With side given the call also forks side off the calling stream: a new
+// factor's column layouts (float64, and float32 for a mixed call) are made on
+// the calling stream, and the norms and the row-order copy of L, which only
+// the learned correction reads, are left to the caller (factor_norms_on, on
+// side after NInv), which joins side back before anything else reads them.
 static asi_status prepare_factor(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
-                                 bool fp64, const void **Lu) {
+                                 bool fp64, const void **Lu, hipStream_t side = nullptr) {
     const asi::Analysis &A = h->A;
     hipError_t e;
+    bool forked = false;
+    auto fork = [&]() -> hipError_t {
+        hipError_t e2 = hipEventRecord(h->ev_fork, h->stream);
+        if (e2 == hipSuccess) e2 = hipStreamWaitEvent(side, h->ev_fork, 0);
+        forked = true;
+        return e2;
+    };
     if (L_val || d_diag || d_sub) {
         if ((!L_val && A.nnzL > 0) || !d_diag || !d_sub)
             return fail(h, ASI_E_ARG, "null factor pointer (give L_val, d_diag and d_sub, or none of them)");
-        h->factor_loaded = false;  // dinv and Lu (and Lf for a mixed call) now hold this call's factor
+        h->factor_loaded = false;  // until dinv and Lu (and Lf for a mixed call) hold this call's factor
         h->lf_loaded = false;
         h->ls_loaded = false;
         {
@@ -508,17 +520,30 @@ static asi_status prepare_factor(asi_handle h, const double *L_val, const double
             e = asi::launch_dinv(A.n, h->piv, d_diag, d_sub, h->dinv, h->status, h->stream);
         }
         if (e != hipSuccess) return hip_fail(h, e, "dinv");
-        {
+        if (side) {
+            {
+                Trace t(h, ASI_K_GATHER, 20.0 * A.nnzL);
+                e = asi::launch_scatter_lu(A.nnzL, h->q2u, L_val, h->Lu, true, h->stream);
+            }
+            if (e == hipSuccess && !fp64) {
+                Trace t(h, ASI_K_GATHER, 12.0 * A.nnzU);
+                e = asi::launch_lu_to_float(A.nnzU, reinterpret_cast<const double *>(h->Lu), h->Lf, h->stream);
+                h->lf_loaded = true;
+            }
+            if (e == hipSuccess) e = fork();
+            if (e != hipSuccess) return hip_fail(h, e, "gather L");
+        } else {
             // the float64 copy in the column layout always (NInv's series
             // reads it in both precisions), with the row and column norms of
             // L (learned-correction features)
             Trace t(h, ASI_K_GATHER, 20.0 * A.nnzL);
             e = asi::launch_scatter_lu(A.nnzL, h->q2u, L_val, h->Lu, true, h->stream);
             if (e == hipSuccess)
-                e = asi::launch_factor_norms(A.n, h->rowptr_L, L_val, h->ustart, reinterpret_cast<const double *>(h->Lu),
-                                             h->rn, h->Lcsr, h->stream);
+                e = asi::launch_factor_norms(A.n, h->rowptr_L, L_val, h->ustart,
+                                             reinterpret_cast<const double *>(h->Lu), h->rn, h->Lcsr, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "gather L");
         }
-        if (e != hipSuccess) return hip_fail(h, e, "gather L");
+        h->factor_loaded = true;  // the call's factor stays loaded for later calls without factor pointers
     } else if (!h->factor_loaded) {
         return fail(h, ASI_E_STATE, "no factor given and none loaded (asi_load_factor)");
     }
@@ -528,7 +553,21 @@ static asi_status prepare_factor(asi_handle h, const double *L_val, const double
         if (e != hipSuccess) return hip_fail(h, e, "L to float32");
         h->lf_loaded = true;
     }
+    if (side && !forked) {
+        e = fork();
+        if (e != hipSuccess) return hip_fail(h, e, "fork");
+    }
     *Lu = fp64 ? h->Lu : (const void *)h->Lf;
+    return ASI_OK;
+}
+
+// The row and column norms of L and its row-order copy (learned-correction
+// features), from the caller's L_val and the float64 column layout, on st.
+static asi_status factor_norms_on(asi_handle h, const double *L_val, hipStream_t st) {
+    Trace t(h, ASI_K_GATHER, 0.0, st);
+    hipError_t e = asi::launch_factor_norms(h->A.n, h->rowptr_L, L_val, h->ustart,
+                                            reinterpret_cast<const double *>(h->Lu), h->rn, h->Lcsr, st);
+    if (e != hipSuccess) return hip_fail(h, e, "factor norms");
     return ASI_OK;
 }
 
@@ -897,10 +936,10 @@ asi_status asi_selinv_ninv(asi_handle h, const double *L_val, const double *d_di
     DeviceGuard g(h->device);
     const bool fp64 = prec == ASI_FP64;
     const void *Lu = nullptr;
-    s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu);
-    if (s != ASI_OK) return s;
     // the dataflow sweep needs every workgroup resident: no concurrent work beside it
     if (h->sweep == ASI_SWEEP_DATAFLOW) {
+        s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu);
+        if (s != ASI_OK) return s;
         s = ninv_launch(h, fp64, p, delta, N_S, h->stream, 0);
         if (s != ASI_OK) return s;
         return selinv_launch(h, Lu, fp64, Z_S, h->stream);
@@ -912,12 +951,14 @@ asi_status asi_selinv_ninv(asi_handle h, const double *L_val, const double *d_di
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(h, e, "second stream");
     }
-    e = hipEventRecord(h->ev_fork, h->stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(h->aux, h->ev_fork, 0);
-    if (e != hipSuccess) return hip_fail(h, e, "fork");
+    // forks the second stream: NInv, then the rest of a new factor's load
+    // (only the learned correction reads it), run there, beside the sweep
+    s = prepare_factor(h, L_val, d_diag, d_sub, fp64, &Lu, h->aux);
+    if (s != ASI_OK) return s;
     // NInv's persistent kernel takes half the resident workgroups, leaving
     // compute units to the latency-bound SelInv levels running beside it
     s = ninv_launch(h, fp64, p, delta, N_S, h->aux, -2);
+    if (s == ASI_OK && (L_val || d_diag || d_sub)) s = factor_norms_on(h, L_val, h->aux);
     if (s == ASI_OK) s = selinv_launch(h, Lu, fp64, Z_S, h->stream);
     e = hipEventRecord(h->ev_join, h->aux);
     if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->ev_join, 0);

@@ -1,6 +1,6 @@
 """asi_load_factor: the calls that reuse the loaded factor agree with the
 calls that pass the factor arrays, in float64 and mixed precision, with and
-without 2x2 pivots; a call with explicit arrays leaves no factor loaded.
+without 2x2 pivots; a call with explicit arrays loads the factor it is given.
 
 SelInv and NInv are compared at rounding level: blocks handled by several
 wavefronts add into shared LDS accumulators in run-dependent order. The
@@ -56,11 +56,18 @@ def test_loaded_factor_matches_explicit_arrays(name):
         print(f"  {prec}: loaded vs explicit SelInv {ez:.1e}, NInv {en:.1e}")
         assert ez <= tol[prec] and en <= tol[prec]
         assert torch.equal(Fe, Fl) and torch.equal(sce, scl) and torch.equal(Ce, Cl)
-    # an explicit call replaces the loaded factor's D-block inverses: nothing is loaded afterwards
-    s.selinv(Lv, dd, ds)
+    # an explicit call loads the factor it is given: a later call without
+    # factor arrays uses it (here the same factor, so the same NInv)
+    s2 = Solver(0)
+    s2.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
     with pytest.raises(AsiError):
-        s.ninv()
+        s2.ninv()  # nothing given yet
+    s2.selinv(Lv, dd, ds)
+    N2 = s2.ninv(p=3, delta=0.1)
+    Nref = s.ninv(Lv, dd, ds, p=3, delta=0.1)
+    s2.sync()
     s.sync()
+    assert oc.entry_error(S, N2.cpu().numpy(), Nref.cpu().numpy()).max() <= tol["fp64"]
     assert np.isfinite(Ze.cpu().numpy()).all()
 
 
