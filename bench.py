@@ -709,8 +709,8 @@ def oracle_trailing_sample(F, S, Z64, N64, M64, Zm, p, delta, eps, target_s=15.0
     NInv + Mix on that sub-factor is a bounded sample of the same workload,
     and its result must equal the trailing block of the device's whole
     result. k is chosen so that the sample holds a share of sum_J |R_J|^2
-    (the oracle's SelInv does a dense |R_J| x |R_J| loop per block) that a
-    probe on a smaller slice predicts to take about target_s seconds. The
+    (the oracle's SelInv does a dense |R_J| x |R_J| loop per block) that
+    probes on smaller slices predict to take about target_s seconds. The
     rate is entries of the sample per second of the oracle on it; the
     whole-workload time is estimated by scaling SelInv with that share and
     NInv + Mix with the share of |S|."""
@@ -743,11 +743,19 @@ def oracle_trailing_sample(F, S, Z64, N64, M64, Zm, p, delta, eps, target_s=15.0
         t3 = time.perf_counter()
         return G, S2, (Zo, No, Mo), (t2 - t1, t3 - t2, t1 - t0)
 
+    # the time per unit of work grows with the sample (larger blocks, caches
+    # outgrown), so a small probe under-predicts: a second, mid-sized probe
+    # aimed at a third of the target is the sample when it took at least half
+    # the target, and otherwise predicts the sample
     probe_share = 0.002
     _, _, _, tp = run(start_for(probe_share))
-    share = min(0.5, probe_share * target_s / max(sum(tp[:2]), 1e-3))
+    share = min(0.5, probe_share * target_s / 3 / max(sum(tp[:2]), 1e-3))
     k = start_for(share)
     G, S2, (Zo, No, Mo), (t_sel, t_nm, t_pat) = run(k)
+    if t_sel + t_nm < 0.5 * target_s and share < 0.5:
+        share = min(0.5, (tail[k] / total) * target_s / max(t_sel + t_nm, 1e-3))
+        k = start_for(share)
+        G, S2, (Zo, No, Mo), (t_sel, t_nm, t_pat) = run(k)
     t_cpu = t_sel + t_nm
     share = tail[k] / total
     nnzS = S.nnz

@@ -321,14 +321,20 @@ __global__ __launch_bounds__(64) void k_spai_general(SpaiParams P, const int32_t
 }
 
 // ---- SPAI, staged variant --------------------------------------------------
-// One wavefront per column j of S. Lane l owns the entries a = l + 64 k
-// (k < E) of the column (J_a) with their CG scalars, and stages column J_a of
-// Ah (its rows as slots of a per-wavefront LDS hash, its values) once; each
-// application of G = Ah_J^T Ah_J is then an LDS scatter of Ah_J p into the
-// slots and a per-lane gather back, with no global traffic. The E = 1 kernel
-// runs over every column and lists those it cannot hold (more than 64
-// entries, or more than 384 entries in Ah(:, J)); the E = 2 kernel takes that
-// list and passes what it cannot hold on to the general kernel.
+// One wavefront per column j of S. The column's entries J_a are spread over
+// the lanes with lpc lanes per entry, lpc the largest power of two with
+// c lpc <= 64 (c = |J|; lpc = 1 from c > 32 on, and then lane l owns the
+// entries a = l + 64 k, k < E): lane l serves entry a = l mod (64 / lpc) as
+// its sub-lane h = l div (64 / lpc). Every lane of an entry keeps that
+// entry's CG scalars (the same arithmetic in each); sub-lane h stages and
+// walks the entries h, h + lpc, ... of column J_a of Ah (its rows as slots of
+// a per-wavefront LDS hash, its values), so each application of
+// G = Ah_J^T Ah_J is an LDS scatter of Ah_J p into the slots and a strided
+// gather back, whose lpc partial sums are added across the sub-lanes, with
+// no global traffic. The E = 1 kernel runs over every column and lists those
+// it cannot hold (more than 64 entries, or more than 384 entries in
+// Ah(:, J)); the E = 2 kernel takes that list and passes what it cannot hold
+// on to the general kernel.
 template <int E>
 struct SpaiStaged {
     static constexpr int C = 64 * E;    // entries of the column of S
@@ -361,6 +367,12 @@ __device__ inline int sp_insert(int32_t *key, int32_t r) {
     return -1;
 }
 
+// v summed over the lanes l, l + cw, l + 2 cw, ... (cw a power of two <= 64)
+__device__ inline double sublane_sum(double v, int cw) {
+    for (int o = cw; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 template <int E, int W>
 __global__ __launch_bounds__(64 * W) void k_spai_staged(SpaiParams P, const int32_t *__restrict__ in_list,
                                                         const int32_t *__restrict__ in_count,
@@ -379,18 +391,25 @@ __global__ __launch_bounds__(64 * W) void k_spai_staged(SpaiParams P, const int3
             if (lane == 0) out_list[atomicAdd(out_count, 1)] = j;
             continue;
         }
+        int lpc = 1;
+        while (lpc < 64 && 2 * lpc * c <= 64) lpc <<= 1;
+        const int cw = 64 / lpc;          // entries per pass of the wavefront (k = 0)
+        const int h = lane / cw;          // sub-lane of the lane's entry
         double xa[E], cna[E];
         int64_t qa[E];
         int32_t dega[E], e0[E];
+        bool own[E];                      // the lane answers for entry a (sub-lane 0 of a valid entry)
         int32_t carry = 0;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-            const int a = lane + 64 * k;
+            const int a = k == 0 ? lane % cw : lane + 64 * k;
+            const bool valid = a < c && (k == 0 || lpc == 1);
+            own[k] = valid && h == 0;
             xa[k] = 0.0;
             cna[k] = 1.0;
             qa[k] = 0;
             dega[k] = 0;
-            if (a < c) {
+            if (valid) {
                 const int32_t ja = P.col[s0 + a];
                 xa[k] = P.M[s0 + a];
                 cna[k] = P.colnorm2[ja];
@@ -398,13 +417,17 @@ __global__ __launch_bounds__(64 * W) void k_spai_staged(SpaiParams P, const int3
                 qa[k] = P.A_rowptr[ra];
                 dega[k] = (int32_t)(P.A_rowptr[ra + 1] - qa[k]);
             }
-            int32_t incl = dega[k];
+            // offsets of the entries' Ah columns: a scan over the owning lanes
+            // (lanes 0..cw-1 for k = 0), then each sub-lane takes its entry's
+            const int32_t d = own[k] ? dega[k] : 0;
+            int32_t incl = d;
             for (int o = 1; o < 64; o <<= 1) {
                 int32_t u = __shfl_up(incl, o, 64);
                 if (lane >= o) incl += u;
             }
             incl += carry;
-            e0[k] = incl - dega[k];
+            e0[k] = incl - d;
+            if (k == 0) e0[k] = __shfl(e0[k], lane % cw, 64);
             carry = __shfl(incl, 63, 64);
         }
         if (carry > Lds::T) {
@@ -421,7 +444,7 @@ __global__ __launch_bounds__(64 * W) void k_spai_staged(SpaiParams P, const int3
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             ba[k] = 0.0;
-            for (int32_t e = 0; e < dega[k]; ++e) {
+            for (int32_t e = h; e < dega[k]; e += lpc) {
                 const int32_t r = P.A_col[qa[k] + e];
                 const double v = P.A_val[qa[k] + e];
                 const int sl = sp_insert<Lds::HB>(L.key, r);
@@ -431,38 +454,42 @@ __global__ __launch_bounds__(64 * W) void k_spai_staged(SpaiParams P, const int3
                 if (r == rj) ba[k] = v;
             }
         }
+        ba[0] = sublane_sum(ba[0], cw);  // one sub-lane found it (or none): exact
         wsync();
         if (L.flag) {
             if (lane == 0) out_list[atomicAdd(out_count, 1)] = j;
             continue;
         }
-        // g = G v for the lane-owned vector entries v
+        // g = G v for the lane's vector entries v
         auto apply = [&](const double(&va)[E], double(&ga)[E]) {
             wsync();
             for (int s = lane; s < Lds::H; s += 64) L.y[s] = 0.0;
             wsync();
 #pragma unroll
             for (int k = 0; k < E; ++k)
-                for (int32_t e = e0[k]; e < e0[k] + dega[k]; ++e) atomicAdd(&L.y[L.slot[e]], L.val[e] * va[k]);
+                for (int32_t e = e0[k] + h; e < e0[k] + dega[k]; e += lpc)
+                    atomicAdd(&L.y[L.slot[e]], L.val[e] * va[k]);
             wsync();
 #pragma unroll
             for (int k = 0; k < E; ++k) {
                 double g = 0.0;
-                for (int32_t e = e0[k]; e < e0[k] + dega[k]; ++e) g += L.val[e] * L.y[L.slot[e]];
+                for (int32_t e = e0[k] + h; e < e0[k] + dega[k]; e += lpc) g += L.val[e] * L.y[L.slot[e]];
                 ga[k] = g;
             }
+            ga[0] = sublane_sum(ga[0], cw);
         };
-        // r = b - G x, z = r / diag, p = z
+        // r = b - G x, z = r / diag, p = z (every lane of an entry alike; the
+        // dot products count each entry once, from its sub-lane 0)
         double ga[E], ra[E], za[E], pa[E];
         apply(xa, ga);
         double rz = 0.0;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-            const bool own = lane + 64 * k < c;
-            ra[k] = own ? ba[k] - ga[k] : 0.0;
-            za[k] = own ? ra[k] / cna[k] : 0.0;
+            const bool valid = own[k] || (k == 0 && (lane % cw) < c);
+            ra[k] = valid ? ba[k] - ga[k] : 0.0;
+            za[k] = valid ? ra[k] / cna[k] : 0.0;
             pa[k] = za[k];
-            rz += ra[k] * za[k];
+            if (own[k]) rz += ra[k] * za[k];
         }
         rz = wsum(rz);
         for (int it = 0; it < P.iters; ++it) {
@@ -470,18 +497,19 @@ __global__ __launch_bounds__(64 * W) void k_spai_staged(SpaiParams P, const int3
             apply(pa, ga);
             double pgp = 0.0;
 #pragma unroll
-            for (int k = 0; k < E; ++k) pgp += pa[k] * ga[k];
+            for (int k = 0; k < E; ++k)
+                if (own[k]) pgp += pa[k] * ga[k];
             pgp = wsum(pgp);
             if (pgp == 0.0) break;
             const double al = rz / pgp;
             double rzn = 0.0;
 #pragma unroll
             for (int k = 0; k < E; ++k) {
-                const bool own = lane + 64 * k < c;
+                const bool valid = own[k] || (k == 0 && (lane % cw) < c);
                 xa[k] += al * pa[k];
                 ra[k] -= al * ga[k];
-                za[k] = own ? ra[k] / cna[k] : 0.0;
-                rzn += ra[k] * za[k];
+                za[k] = valid ? ra[k] / cna[k] : 0.0;
+                if (own[k]) rzn += ra[k] * za[k];
             }
             rzn = wsum(rzn);
             const double be = rzn / rz;
@@ -491,7 +519,7 @@ __global__ __launch_bounds__(64 * W) void k_spai_staged(SpaiParams P, const int3
         }
 #pragma unroll
         for (int k = 0; k < E; ++k)
-            if (lane + 64 * k < c) P.X[s0 + lane + 64 * k] = xa[k];
+            if (own[k]) P.X[s0 + (k == 0 ? lane : lane + 64 * k)] = xa[k];
     }
 }
 
