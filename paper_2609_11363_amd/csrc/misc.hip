@@ -351,10 +351,10 @@ struct SpaiStaged {
     int32_t flag;
 };
 
-template <int HB>
-__device__ inline int sp_insert(int32_t *key, int32_t r) {
-    constexpr int H = 1 << HB;
-    uint32_t s = ((uint32_t)r * 2654435761u) >> (32 - HB);
+// slot of row r in a table of 2^hb slots (linear probing; -1 if full)
+__device__ inline int sp_insert(int32_t *key, int32_t r, int hb) {
+    const int H = 1 << hb;
+    uint32_t s = ((uint32_t)r * 2654435761u) >> (32 - hb);
     for (int probe = 0; probe < H; ++probe) {
         int32_t k = key[s];
         if (k == r) return (int)s;
@@ -434,8 +434,13 @@ __global__ __launch_bounds__(64 * W) void k_spai_staged(SpaiParams P, const int3
             if (lane == 0) out_list[atomicAdd(out_count, 1)] = j;
             continue;
         }
+        // hash slots in use: at least twice the column's rows of Ah (fewer
+        // slots to clear per application), at most the table
+        int hb = 6;
+        while (hb < Lds::HB && (1 << hb) < 2 * carry) ++hb;
+        const int hs = 1 << hb;
         wsync();  // the previous column's readers of L are done
-        for (int s = lane; s < Lds::H; s += 64) L.key[s] = -1;
+        for (int s = lane; s < hs; s += 64) L.key[s] = -1;
         if (lane == 0) L.flag = 0;
         wsync();
         // b_a = Ah(j, J_a) = entry of column J_a of Ah in row j (Ah symmetric)
@@ -447,7 +452,7 @@ __global__ __launch_bounds__(64 * W) void k_spai_staged(SpaiParams P, const int3
             for (int32_t e = h; e < dega[k]; e += lpc) {
                 const int32_t r = P.A_col[qa[k] + e];
                 const double v = P.A_val[qa[k] + e];
-                const int sl = sp_insert<Lds::HB>(L.key, r);
+                const int sl = sp_insert(L.key, r, hb);
                 if (sl < 0) L.flag = 1;
                 L.slot[e0[k] + e] = (uint16_t)(sl < 0 ? 0 : sl);
                 L.val[e0[k] + e] = v;
@@ -463,7 +468,7 @@ __global__ __launch_bounds__(64 * W) void k_spai_staged(SpaiParams P, const int3
         // g = G v for the lane's vector entries v
         auto apply = [&](const double(&va)[E], double(&ga)[E]) {
             wsync();
-            for (int s = lane; s < Lds::H; s += 64) L.y[s] = 0.0;
+            for (int s = lane; s < hs; s += 64) L.y[s] = 0.0;
             wsync();
 #pragma unroll
             for (int k = 0; k < E; ++k)
