@@ -131,8 +131,9 @@ def main():
                              "covariance200", "randdd"])
     ap.add_argument("--grid", type=int, default=None, help="grid size (default 64, 512, 128 per workload)")
     ap.add_argument("--tau", type=float, default=1e-3)
-    ap.add_argument("--learned-grids", default="large", choices=["large", "small"],
-                    help="27-point training grids: 16^3-28^3 (held-out 32^3) or 12^3-18^3 (held-out 20^3)")
+    ap.add_argument("--learned-grids", default="larger", choices=["larger", "large", "small"],
+                    help="27-point training grids: 24^3-36^3 (held-out 40^3), 16^3-28^3 (held-out 32^3) or "
+                         "12^3-18^3 (held-out 20^3)")
     ap.add_argument("--randdd-set", default="full", choices=["full", "small"],
                     help="random dominant set: all 256 seeds (192/32/32) or the 48 smallest (32/8/8)")
     ap.add_argument("--taus", default="1e-3,3e-4,1e-4",
@@ -140,7 +141,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target time of the CPU oracle baseline's sample (stencil27_128)")
-    ap.add_argument("--learned-epochs", type=int, default=30)
+    ap.add_argument("--learned-epochs", type=int, default=60)
     ap.add_argument("--sweeps", default="levels,dataflow",
                     help="SelInv schedules to time separately (comma list of levels, dataflow)")
     ap.add_argument("--factor", default="device", choices=["device", "host"],
@@ -457,12 +458,18 @@ def train_learned(args, tau, p, delta, eps, family="diffusion7"):
         val_spec, test_spec = (16, 26), (20, 27)
         desc = ("3D 27-point lognormal(0,0.5) stencil: 12^3, 14^3 x2, 16^3, 18^3 (seeds 21-25); "
                 "validation 16^3 (seed 26); held-out test 20^3 (seed 27)")
-    else:
+    elif args.learned_grids == "large":
         gen = lambda Ng, sd: stencil27_3d(Ng, 0.5, sd)  # noqa: E731
         specs = [(16, 21), (20, 22), (24, 23), (24, 24), (28, 25)]
         val_spec, test_spec = (24, 26), (32, 27)
         desc = ("3D 27-point lognormal(0,0.5) stencil: 16^3, 20^3, 24^3 x2, 28^3 (seeds 21-25); "
                 "validation 24^3 (seed 26); held-out test 32^3 (seed 27); factors on the device")
+    else:
+        gen = lambda Ng, sd: stencil27_3d(Ng, 0.5, sd)  # noqa: E731
+        specs = [(24, 31), (28, 32), (32, 33), (32, 34), (36, 35)]
+        val_spec, test_spec = (28, 36), (40, 37)
+        desc = ("3D 27-point lognormal(0,0.5) stencil: 24^3, 28^3, 32^3 x2, 36^3 (seeds 31-35); "
+                "validation 28^3 (seed 36); held-out test 40^3 (seed 37); factors on the device")
 
     # the 27-point family's factors come from the device factorization (the
     # host one for the 7-point family, whose grids are small)
