@@ -226,9 +226,13 @@ asi_status asi_mix_full(asi_handle h, const double *Z_S, const int64_t *N_rowptr
  * inputs of Mix, Section 2.3): NInv runs on a second stream of the handle
  * (created on first use, default priority) concurrently with the SelInv
  * sweep on the handle's stream, and the handle's stream waits for it before
- * its next work, so later calls and asi_sync see both results. Arguments and
- * results as for asi_selinv and asi_ninv. With ASI_SWEEP_DATAFLOW the two
- * run one after the other (that sweep needs every workgroup resident).
+ * its next work, so later calls and asi_sync see both results. Given the
+ * factor arrays, the call makes the column layouts the sweep reads on the
+ * handle's stream and the row and column norms of L and its row-order copy
+ * (read only by asi_mlp_features / asi_mlp_correct) on the second stream
+ * after NInv. Arguments and results as for asi_selinv and asi_ninv. With
+ * ASI_SWEEP_DATAFLOW the two run one after the other (that sweep needs every
+ * workgroup resident).
  */
 asi_status asi_selinv_ninv(asi_handle h, const double *L_val, const double *d_diag, const double *d_sub,
                            int32_t p, double delta, asi_precision prec, double *Z_S, double *N_S);
