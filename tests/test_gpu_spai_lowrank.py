@@ -64,6 +64,43 @@ def test_spai_parity(name, iters):
     assert abs(Rm - Rm.T).max() == 0.0
 
 
+@pytest.mark.parametrize("iters", [1, 10])
+def test_spai_column_lengths(iters):
+    """Columns of S of every length class of the staged kernel's lane split:
+    isolated unknowns (one entry: 64 lanes per entry), a 1D chain (two or
+    three entries: 16-32 lanes), a 2D Laplacian (4-8 lanes) and a denser
+    random block (one lane per entry), in one matrix, against the oracle."""
+    import scipy.sparse as sp
+    import torch
+    from paper_2609_11363_amd import Solver
+    rng = np.random.default_rng(4)
+    n1 = 40
+    chain = sp.diags([-np.ones(n1 - 1), 2.5 * np.ones(n1), -np.ones(n1 - 1)], [-1, 0, 1])
+    blocks = [sp.diags(rng.uniform(1.0, 3.0, 5)), chain, laplace2d(12, 12, 0.05), random_dd_symmetric(3, n=200)]
+    blocks = [sp.coo_matrix(sp.csr_matrix(b).toarray()) for b in blocks]
+    A = sp.csr_matrix(sp.block_diag(blocks))
+    A.sort_indices()
+    F = ildl_bk(A, rcm(A), 1e-3)
+    S = oc.pattern(F)
+    clen = np.diff(S.rowptr)
+    print(f"[spai lengths] n={F.n} column lengths {clen.min()}..{clen.max()}", flush=True)
+    assert clen.min() == 1 and (clen <= 3).sum() > n1 // 2 and clen.max() > 32
+    Mo = oc.mix(S, oc.selinv(F, S), oc.ninv(F, S, 3, 0.1), 1e-2)
+    s = Solver(0)
+    s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
+    dev = torch.device("cuda", 0)
+    R = s.spai(torch.as_tensor(A.indptr.astype(np.int64), device=dev),
+               torch.as_tensor(A.indices.astype(np.int32), device=dev),
+               torch.as_tensor(A.data.astype(np.float64), device=dev),
+               torch.as_tensor(F.perm.astype(np.int32), device=dev), torch.as_tensor(Mo, device=dev),
+               cg_iters=iters)
+    s.sync()
+    Ro = oc.spai(oc.permuted(A, F.perm), S, Mo, iters)
+    e = oc.entry_error(S, R.cpu().numpy(), Ro)
+    print(f"  iters={iters} e_R max={e.max():.2e}", flush=True)
+    assert e.max() <= FP64_TOL
+
+
 @pytest.mark.parametrize("k", [1, 5, 16, 33, 64])
 def test_lowrank_parity(k):
     import torch
