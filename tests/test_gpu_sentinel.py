@@ -58,7 +58,16 @@ def test_sentinel_sweep_is_finite_and_matches(cases, name, precision, sweep):
     s = Solver(0)
     s.analyze(F.n, F.L_rowptr, F.L_col, F.piv)
     if sweep == "dataflow" and s.info()["max_cols"] > 128:
-        pytest.skip("the dataflow sweep takes |R_J| <= 128 only")
+        # the dataflow sweep takes |R_J| <= 128 only: the call refuses the
+        # pattern (ASI_E_UNSUPPORTED) and the level schedule still serves it
+        from paper_2609_11363_amd import AsiError, upload_factors
+        s.set_sweep("dataflow")
+        with pytest.raises(AsiError) as ei:
+            s.selinv(*upload_factors(F), precision=precision)
+        assert ei.value.code == 8
+        print(f"[sentinel] case={name} precision={precision}: dataflow refused (max |R_J| "
+              f"{s.info()['max_cols']})", flush=True)
+        return
     print(f"[sentinel] case={name} precision={precision} sweep={sweep} n={F.n} |S|={S.nnz} "
           f"2x2={int((F.piv == 1).sum())}", flush=True)
     s.set_sweep(sweep)
